@@ -1,0 +1,423 @@
+"""Plain FP64 CPU oracle for canonical density-matrix perturbation theory.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import or call
+this module: only the tests, the smoke check and the CPU-baseline leg of the
+benchmark use it.  It shares no code with the GPU library.
+
+What it computes (Niklasson, Rubensson, Rudberg, Cawkwell, "Canonical density
+matrix perturbation theory"):
+
+* Sec. II, Eq. (Rec_F_2): the recursive Fermi-operator expansion
+  X0 = I/2 - 2^-(M+2) beta (H - mu I),  X_n = X^2 / (X^2 + (I - X)^2).
+  Every step is a rational function of the previous iterate, so X_M is an
+  exact matrix function of H: on an eigenvalue e = eps - mu it equals the
+  Pade function f_{2^M}(x) = x^n / (x^n + (1-x)^n) at x = 1/2 - beta e / (4n),
+  n = 2^M (Appendix A, recursive Fermi operator expansion).  Writing
+  x = 1/2 - d, the one-step map d -> 2d / (1 + 4 d^2) is tanh doubling, so
+  phi_M(e) = 1/2 - tanh(2^M artanh(s e)) / 2  with  s = 2^-(M+1) beta.
+  ``phi`` evaluates this closed form; ``phi_pade`` evaluates the Pade power
+  form of Appendix A in log space, an independent second closed form.
+* Sec. II, Eqs. (P_resp), (H_prt) and the mu expansion: P(lambda) is the same
+  matrix function of K(lambda) = H(lambda) - mu(lambda) I, so P^(1) and P^(2)
+  are the first and second Frechet (Daleckii-Krein) derivatives in the
+  eigenbasis of H0, and the canonical mu^(k) are fixed by Tr P^(k) = 0
+  (Tr P^(0) = Ne).  Algorithm 1's Newton loop converges to exactly this fixed
+  point; the oracle computes the fixed point directly.
+* Sec. III, Eq. (Resp_0): free-energy response traces Tr[H^(k) P^(m-k)].
+* The adjoint d Tr(A P0)/d H0 of the canonical map, which by the symmetry of
+  the first-order kernel equals the canonical first-order response to sym(A).
+
+All arithmetic is FP64 (numpy / LAPACK).  Eigenvalue-space divided
+differences are evaluated in forms that avoid cancellation (see ``dd1`` and
+``dd2``); near-coincident eigenvalues use short Taylor expansions.
+"""
+import math
+import numpy as np
+
+__all__ = [
+    "phi", "phi_pade", "phi_derivs", "fermi_dirac", "dd1", "dd2",
+    "mu_canonical", "eig", "density", "response", "canonical_response",
+    "adjoint_grad", "entropy", "omega", "range_ok",
+]
+
+
+# ----------------------------------------------------------------------------
+# scalar functions of an eigenvalue e = eps - mu
+# ----------------------------------------------------------------------------
+
+def _s(beta, M):
+    """Scale s = 2^-(M+1) beta of the closed form; also returns K = 2^M."""
+    return math.ldexp(beta, -(M + 1)), math.ldexp(1.0, M)
+
+
+def range_ok(e, beta, M):
+    """True when every |s e| < 1, i.e. x = 1/2 - beta e/2^(M+2) lies in (0, 1)."""
+    s, _ = _s(beta, M)
+    return bool(np.all(np.abs(s * np.asarray(e)) < 1.0))
+
+
+def _u(e, beta, M):
+    s, K = _s(beta, M)
+    z = s * np.asarray(e, dtype=np.float64)
+    if np.any(np.abs(z) >= 1.0):
+        raise ValueError("spectrum outside the recursion's range: need 2^(M+1) > beta*|eps-mu|")
+    return K * np.arctanh(z)
+
+
+def phi(e, beta, M):
+    """Occupation computed by M recursion steps: 1/2 - tanh(2^M artanh(s e))/2."""
+    return 0.5 - 0.5 * np.tanh(_u(e, beta, M))
+
+
+def phi_pade(e, beta, M):
+    """Appendix A's Pade form f_n(x) = x^n/(x^n+(1-x)^n), n = 2^M, x = 1/2 - beta e/(4n).
+
+    Evaluated as 1/(1 + exp(n (log(1-x) - log x))) so n = 2^30 does not
+    overflow; valid for x in (0, 1).
+    """
+    n = math.ldexp(1.0, M)
+    e = np.asarray(e, dtype=np.float64)
+    x = 0.5 - beta * e / (4.0 * n)
+    if np.any((x <= 0) | (x >= 1)):
+        raise ValueError("x outside (0, 1)")
+    # log(1-x) - log(x) = log1p(-2x + 1 ...) computed as log((1-x)/x) with the
+    # small quantity y = beta e/(4n):  (1/2 + y)/(1/2 - y)
+    y = beta * e / (4.0 * n)
+    t = n * (np.log1p(2.0 * y) - np.log1p(-2.0 * y))
+    return 0.5 * (1.0 - np.tanh(0.5 * t))
+
+
+def fermi_dirac(e, beta):
+    """Fermi-Dirac occupation 1/(1 + exp(beta e)), the M -> infinity limit (Eq. Rec_F_1)."""
+    return 0.5 * (1.0 - np.tanh(0.5 * beta * np.asarray(e, dtype=np.float64)))
+
+
+def phi_derivs(e, beta, M):
+    """Analytic derivatives (phi', phi'', phi'''') of the closed form at e.
+
+    phi = h(u(e)) with h(u) = 1/2 - tanh(u)/2 and u = 2^M artanh(s e);
+    chain rule (Faa di Bruno) with t = tanh u:
+      h'  = -(1-t^2)/2, h'' = t(1-t^2), h''' = (1-t^2)(1-3t^2),
+      h'''' = -4t(1-t^2)(2-3t^2);
+      w = artanh(z), z = s e:  w' = s/(1-z^2), w'' = 2 s^2 z/(1-z^2)^2,
+      w''' = 2 s^3 (1+3z^2)/(1-z^2)^3, w'''' = 24 s^4 z (1+z^2)/(1-z^2)^4.
+    """
+    s, K = _s(beta, M)
+    e = np.asarray(e, dtype=np.float64)
+    z = s * e
+    q = 1.0 - z * z
+    t = np.tanh(_u(e, beta, M))
+    c = 1.0 - t * t
+    h1, h2, h3, h4 = -0.5 * c, t * c, c * (1.0 - 3.0 * t * t), -4.0 * t * c * (2.0 - 3.0 * t * t)
+    u1 = K * s / q
+    u2 = K * 2.0 * s * s * z / q**2
+    u3 = K * 2.0 * s**3 * (1.0 + 3.0 * z * z) / q**3
+    u4 = K * 24.0 * s**4 * z * (1.0 + z * z) / q**4
+    p1 = h1 * u1
+    p2 = h2 * u1**2 + h1 * u2
+    p4 = h4 * u1**4 + 6.0 * h3 * u1**2 * u2 + h2 * (3.0 * u2**2 + 4.0 * u1 * u3) + h1 * u4
+    return p1, p2, p4
+
+
+def _sinhc(x):
+    """sinh(x)/x, accurate near 0."""
+    x = np.asarray(x, dtype=np.float64)
+    out = np.ones_like(x)
+    big = np.abs(x) > 1e-4
+    out[big] = np.sinh(x[big]) / x[big]
+    sm = ~big
+    out[sm] = 1.0 + x[sm] ** 2 / 6.0
+    return out
+
+
+def _artanhc(z):
+    """artanh(z)/z, accurate near 0."""
+    z = np.asarray(z, dtype=np.float64)
+    out = np.ones_like(z)
+    big = np.abs(z) > 1e-4
+    out[big] = np.arctanh(z[big]) / z[big]
+    sm = ~big
+    out[sm] = 1.0 + z[sm] ** 2 / 3.0
+    return out
+
+
+def dd1(a, b, beta, M):
+    """First divided difference phi[a, b] (= phi'(a) when a == b), broadcasting.
+
+    phi(a) - phi(b) = -(tanh u_a - tanh u_b)/2 with
+    tanh u_a - tanh u_b = sinh(du)/(cosh u_a cosh u_b) and
+    du = 2^M artanh(s(a-b)/(1 - s^2 ab)); the factor (a - b) is divided out
+    analytically through sinh(du)/du and artanh(z)/z, so there is no
+    cancellation for a close to b.  The cosh product is formed in log space.
+    """
+    s, K = _s(beta, M)
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    a, b = np.broadcast_arrays(a, b)
+    ua = _u(a, beta, M)
+    ub = _u(b, beta, M)
+    den = 1.0 - s * s * a * b
+    z = s * (a - b) / den
+    du = K * np.arctanh(z)
+    r = K * s / den * _artanhc(z)          # du / (a - b)
+    # 1/(cosh ua cosh ub) = 4 exp(-|ua|-|ub|) / ((1+exp(-2|ua|))(1+exp(-2|ub|)))
+    aa, ab = np.abs(ua), np.abs(ub)
+    inv_cc = 4.0 / ((1.0 + np.exp(-2.0 * aa)) * (1.0 + np.exp(-2.0 * ab)))
+    # sinh(du) exp(-|ua|-|ub|) without overflow: |du| <= |ua| + |ub|
+    lg = -(aa + ab)
+    small = np.abs(du) < 1.0
+    sh = np.empty_like(du)
+    # small |du|: sinh(du)/(a-b) = sinhc(du) * r, times exp(lg)
+    sh[small] = (_sinhc(du[small]) * r[small]) * np.exp(lg[small])
+    big = ~small
+    if np.any(big):
+        d = du[big]
+        val = 0.5 * (np.exp(d + lg[big]) - np.exp(-d + lg[big]))
+        sh[big] = val / (a[big] - b[big])
+    return -0.5 * sh * inv_cc
+
+
+def dd2(x, y, z, beta, M, delta):
+    """Second divided difference phi[x, y, z] (symmetric in its arguments), broadcasting.
+
+    If the largest pairwise gap |p - q| is at least ``delta`` the recurrence
+    phi[p, r, q] = (phi[p, r] - phi[r, q]) / (p - q) is used with that pair,
+    so the division is by the largest gap.  Otherwise all three points lie in
+    a cluster of width < delta and the expansion about their mean m,
+    phi''(m)/2 + phi''''(m) * sum((x_i - m)^2) / 48, is used (the linear term
+    vanishes at the mean; the first neglected term is O(delta^3 phi^(5))).
+    """
+    x, y, z = np.broadcast_arrays(*(np.asarray(v, dtype=np.float64) for v in (x, y, z)))
+    gxy, gyz, gxz = np.abs(x - y), np.abs(y - z), np.abs(x - z)
+    # pick the pair with the largest gap: (p, q) and the third point r
+    use_xz = (gxz >= gxy) & (gxz >= gyz)
+    use_xy = ~use_xz & (gxy >= gyz)
+    p = np.where(use_xz, x, np.where(use_xy, x, y))
+    q = np.where(use_xz, z, np.where(use_xy, y, z))
+    r = np.where(use_xz, y, np.where(use_xy, z, x))
+    gap = np.abs(p - q)
+    out = np.empty(x.shape)
+    far = gap >= delta
+    if np.any(far):
+        pf, qf, rf = p[far], q[far], r[far]
+        out[far] = (dd1(pf, rf, beta, M) - dd1(rf, qf, beta, M)) / (pf - qf)
+    near = ~far
+    if np.any(near):
+        m = (x[near] + y[near] + z[near]) / 3.0
+        ss = (x[near] - m) ** 2 + (y[near] - m) ** 2 + (z[near] - m) ** 2
+        _, p2, p4 = phi_derivs(m, beta, M)
+        out[near] = 0.5 * p2 + p4 * ss / 48.0
+    return out
+
+
+# ----------------------------------------------------------------------------
+# chemical potential and matrices
+# ----------------------------------------------------------------------------
+
+def mu_canonical(eps, beta, M, Ne):
+    """Unique mu with sum_i phi_M(eps_i - mu) = Ne (Sec. II, canonical ensemble).
+
+    The occupation sum is strictly increasing in mu, so bracketed bisection
+    converges; it is finished with safeguarded Newton steps using the exact
+    slope -sum phi'(eps_i - mu).
+    """
+    eps = np.asarray(eps, dtype=np.float64)
+    n = eps.size
+    if not (0.0 < Ne < n):
+        raise ValueError("Ne must lie strictly between 0 and N")
+    s, _ = _s(beta, M)
+    lim = 1.0 / s  # |eps - mu| must stay below this
+    lo = max(eps.max() - lim * (1 - 1e-12), eps.min() - 50.0 / beta - 1.0)
+    hi = min(eps.min() + lim * (1 - 1e-12), eps.max() + 50.0 / beta + 1.0)
+
+    def occ(mu):
+        return float(np.sum(phi(eps - mu, beta, M)))
+
+    if not (lo < hi and occ(lo) <= Ne <= occ(hi)):
+        raise ValueError("cannot bracket the chemical potential")
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if mid == lo or mid == hi:
+            break
+        if occ(mid) < Ne:
+            lo = mid
+        else:
+            hi = mid
+    mu = 0.5 * (lo + hi)
+    # one Newton step with the exact slope, kept only if it lowers the residual
+    f = occ(mu) - Ne
+    d1, _, _ = phi_derivs(eps - mu, beta, M)
+    slope = -float(np.sum(d1))
+    if slope > 0:
+        cand = mu - f / slope
+        if abs(occ(cand) - Ne) < abs(f):
+            mu = cand
+    return mu
+
+
+def eig(h0):
+    """Eigen-decomposition of sym(H0) with LAPACK dsyevd."""
+    h = 0.5 * (h0 + h0.T)
+    w, v = np.linalg.eigh(h)
+    return w, v
+
+
+def density(h0, beta, M, mu, eigh=None):
+    """Grand-canonical P0 = phi_M(H0 - mu I) (Eq. Rec_F_2 after M steps)."""
+    w, v = eigh if eigh is not None else eig(h0)
+    f = phi(w - mu, beta, M)
+    return (v * f) @ v.T
+
+
+def _rot(v, h):
+    """V^T sym(H) V; a diagonal H (given as a vector) is applied by scaling."""
+    if h is None:
+        return np.zeros((v.shape[1], v.shape[1]))
+    if h.ndim == 1:
+        return v.T @ (h[:, None] * v)
+    hs = 0.5 * (h + h.T)
+    return v.T @ hs @ v
+
+
+def _second_order_kernel(e, F1, E, beta, M, delta):
+    """Q_ij = sum_k phi[e_i, e_k, e_j] E_ik E_kj (second-order Daleckii-Krein term).
+
+    Pairs with |e_i - e_j| >= delta use the identity
+    phi[e_i, e_k, e_j] = (phi[e_i, e_k] - phi[e_k, e_j]) / (e_i - e_j), i.e.
+    Q = ((F1 o E) E - E (F1 o E)) / (e_i - e_j); the remaining (nearly
+    coincident) pairs, including the diagonal, are summed directly over k.
+    """
+    n = e.size
+    G = F1 * E
+    num = G @ E - E @ G
+    de = e[:, None] - e[None, :]
+    close = np.abs(de) < delta
+    with np.errstate(divide="ignore", invalid="ignore"):
+        Q = np.where(close, 0.0, num / np.where(close, 1.0, de))
+    ii, jj = np.nonzero(close)
+    # only the upper triangle (Q is symmetric), in chunks of pairs
+    keep = ii <= jj
+    ii, jj = ii[keep], jj[keep]
+    chunk = max(1, (1 << 22) // max(n, 1))
+    for c0 in range(0, ii.size, chunk):
+        i = ii[c0:c0 + chunk]
+        j = jj[c0:c0 + chunk]
+        w2 = dd2(e[i][:, None], e[None, :], e[j][:, None], beta, M, delta)
+        val = np.sum(w2 * E[i, :] * E[:, j].T, axis=1)
+        Q[i, j] = val
+        Q[j, i] = val
+    return Q
+
+
+def _delta(e):
+    width = float(e.max() - e.min()) if e.size > 1 else 1.0
+    return 1e-5 * max(width, 1e-3)
+
+
+def response(h0, h1s, h2s, beta, M, mu, order=2, eigh=None):
+    """P0, P1[d], P2[d] at a fixed mu jet (grand canonical; one pass of Algorithm 1).
+
+    mu = (mu0, [mu1_d], [mu2_d]).  H1s, H2s are lists of N x N matrices or
+    length-N vectors (diagonal); an entry of H2s may be None (zero).
+    Returns a dict with P0, P1, P2 (lists) in the original basis.
+    """
+    w, v = eigh if eigh is not None else eig(h0)
+    mu0 = mu[0]
+    e = w - mu0
+    F = phi(e, beta, M)
+    P0 = (v * F) @ v.T
+    out = dict(P0=P0, P1=[], P2=[], eigh=(w, v))
+    if order == 0:
+        return out
+    F1 = dd1(e[:, None], e[None, :], beta, M)
+    delta = _delta(e)
+    for d, h1 in enumerate(h1s):
+        E1 = _rot(v, h1) - mu[1][d] * np.eye(e.size)
+        out["P1"].append(v @ (F1 * E1) @ v.T)
+        if order >= 2:
+            h2 = h2s[d] if h2s is not None else None
+            E2 = _rot(v, h2) - mu[2][d] * np.eye(e.size)
+            Q = _second_order_kernel(e, F1, E1, beta, M, delta)
+            out["P2"].append(v @ (Q + F1 * E2) @ v.T)
+    return out
+
+
+def canonical_response(h0, h1s, h2s, beta, Ne, M, order=2, eigh=None):
+    """Canonical P0, P1, P2 and the mu jet (the fixed point of Algorithm 1).
+
+    mu0 solves Tr P0 = Ne; mu1 = sum_i phi'(e_i) E_ii / sum_i phi'(e_i) makes
+    Tr P1 = 0; mu2 = (Tr Q + sum_i phi'(e_i) (V^T H2 V)_ii) / sum_i phi'(e_i)
+    makes Tr P2 = 0 (P1, P2 are affine in mu1 resp. mu2 with slope -phi'(K)).
+    Returns a dict with P0, P1, P2, mu0, mu1, mu2, and the response traces
+    tr_h1p1[d] = Tr(H1 P1), tr_h1p2[d] = Tr(H1 P2), tr_h2p0[d] = Tr(H2 P0).
+    """
+    w, v = eigh if eigh is not None else eig(h0)
+    n = w.size
+    mu0 = mu_canonical(w, beta, M, Ne)
+    e = w - mu0
+    F = phi(e, beta, M)
+    P0 = (v * F) @ v.T
+    res = dict(P0=P0, P1=[], P2=[], mu0=mu0, mu1=[], mu2=[], tr_h1p1=[], tr_h1p2=[],
+               tr_h2p0=[], eigh=(w, v), occ=F)
+    if order == 0:
+        return res
+    F1 = dd1(e[:, None], e[None, :], beta, M)
+    fd = np.diag(F1).copy()
+    sfd = float(np.sum(fd))
+    delta = _delta(e)
+    eye = np.eye(n)
+    for d, h1 in enumerate(h1s):
+        H1t = _rot(v, h1)
+        mu1 = float(np.sum(fd * np.diag(H1t)) / sfd)
+        E1 = H1t - mu1 * eye
+        Pt1 = F1 * E1
+        P1 = v @ Pt1 @ v.T
+        res["P1"].append(P1)
+        res["mu1"].append(mu1)
+        h1m = np.diag(h1) if h1.ndim == 1 else h1
+        res["tr_h1p1"].append(float(np.sum(0.5 * (h1m + h1m.T) * P1)))
+        if order >= 2:
+            h2 = h2s[d] if h2s is not None else None
+            H2t = _rot(v, h2)
+            Q = _second_order_kernel(e, F1, E1, beta, M, delta)
+            mu2 = float((np.trace(Q) + np.sum(fd * np.diag(H2t))) / sfd)
+            P2 = v @ (Q + F1 * (H2t - mu2 * eye)) @ v.T
+            res["P2"].append(P2)
+            res["mu2"].append(mu2)
+            res["tr_h1p2"].append(float(np.sum(0.5 * (h1m + h1m.T) * P2)))
+            if h2 is None:
+                res["tr_h2p0"].append(0.0)
+            else:
+                h2m = np.diag(h2) if h2.ndim == 1 else h2
+                res["tr_h2p0"].append(float(np.sum(0.5 * (h2m + h2m.T) * P0)))
+    return res
+
+
+def adjoint_grad(h0, beta, Ne, M, A, eigh=None):
+    """G = d Tr(A P0)/d H0 for the canonical map (mu0 follows H0 through Tr P0 = Ne).
+
+    For symmetric dH, d Tr(A P0) = Tr(A P1[dH]) with P1 the canonical first
+    response, and the Daleckii-Krein kernel with the mu-projection is
+    self-adjoint, so G is the canonical first-order response to sym(A).
+    """
+    r = canonical_response(h0, [np.asarray(A)], None, beta, Ne, M, order=1, eigh=eigh)
+    return r["P1"][0]
+
+
+# ----------------------------------------------------------------------------
+# free energy (Sec. III) -- used only by tests of the n+1 rule
+# ----------------------------------------------------------------------------
+
+def entropy(occ):
+    """S/k_B = -sum_i [f ln f + (1-f) ln(1-f)] over occupations f (Eq. SED)."""
+    f = np.clip(np.asarray(occ, dtype=np.float64), 1e-300, 1 - 1e-16)
+    g = 1.0 - f
+    return float(-np.sum(np.where(f > 0, f * np.log(f), 0.0) + np.where(g > 0, g * np.log(g), 0.0)))
+
+
+def omega(h, beta, Ne, M):
+    """Canonical free energy Tr[P H] - T_e S[P] with k_B T_e = 1/beta (Eq. FreeE)."""
+    w, v = eig(h)
+    mu = mu_canonical(w, beta, M, Ne)
+    f = phi(w - mu, beta, M)
+    return float(np.sum(f * w)) - entropy(f) / beta

@@ -1,0 +1,392 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: the
+closed forms of Appendix A evaluated independently, the scalar recursions of
+Eq. (Rec_F_2), the Fermi-Dirac limit of Eq. (Rec_F_1), the literal
+Algorithm 1 (dense solves, X-form), canonical finite differences in lambda,
+special cases with known answers, brute-force sums and the free-energy
+identities of Sec. III.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as o
+import workloads as w
+import alg1_literal
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+def _sym(rng, n, scale=1.0):
+    a = rng.standard_normal((n, n)) * scale
+    return 0.5 * (a + a.T)
+
+
+# ---------------------------------------------------------------- scalar map
+
+@pytest.mark.parametrize("M", [1, 2, 5, 10, 20, 30])
+def test_phi_matches_scalar_recursions(M):
+    """Closed form == M steps of the paper's map x -> x^2/(x^2+(1-x)^2) (Eq. Rec_F_2).
+
+    The X-form is iterated in extended precision for small M; the shifted
+    d-form d -> 2d/(1+4d^2) (x = 1/2 - d) in FP64 for every M.
+    """
+    beta = 10.0
+    lim = min(3.0, 0.95 / math.ldexp(beta, -(M + 1)))   # stay inside the range |s e| < 1
+    e = np.linspace(-lim, lim, 241)
+    ref = o.phi(e, beta, M)
+    # d-form in fp64
+    d = math.ldexp(beta, -(M + 2)) * e
+    for _ in range(M):
+        d = 2.0 * d / (1.0 + 4.0 * d * d)
+    assert np.max(np.abs((0.5 - d) - ref)) < 2e-15
+    if M <= 10:
+        x = np.longdouble(0.5) - np.longdouble(math.ldexp(beta, -(M + 2))) * e.astype(np.longdouble)
+        for _ in range(M):
+            x = x * x / (x * x + (1 - x) * (1 - x))
+        assert np.max(np.abs(x.astype(np.float64) - ref)) < 1e-15 * 2 ** M
+
+
+@pytest.mark.parametrize("M", [1, 3, 8, 16, 30])
+def test_phi_matches_pade_power_form(M):
+    """Appendix A: phi_M(e) = f_{2^M}(x), f_n(x) = x^n/(x^n+(1-x)^n), x = 1/2 - beta e/(4n)."""
+    beta = 40.0
+    lim = min(4.0, 0.95 / math.ldexp(beta, -(M + 1)))
+    e = np.linspace(-lim, lim, 161)
+    assert np.max(np.abs(o.phi_pade(e, beta, M) - o.phi(e, beta, M))) < 5e-15
+    if M <= 4:
+        n = 2 ** M
+        x = 0.5 - beta * e / (4 * n)
+        if np.all((x > 0) & (x < 1)):
+            direct = x ** n / (x ** n + (1 - x) ** n)
+            assert np.max(np.abs(direct - o.phi(e, beta, M))) < 1e-14
+
+
+def test_pade_composition():
+    """Appendix A: f_{m n} = f_m o f_n for the Pade polynomial."""
+    x = np.linspace(0.01, 0.99, 99)
+
+    def f(n, t):
+        return t ** n / (t ** n + (1 - t) ** n)
+
+    for m, n in ((2, 2), (2, 4), (4, 2), (2, 8)):
+        assert np.max(np.abs(f(m, f(n, x)) - f(m * n, x))) < 1e-14
+
+
+def test_phi_tends_to_fermi_dirac():
+    """Eq. (Rec_F_1): the expansion approaches [exp(beta(e)) + 1]^-1 as M grows."""
+    beta = 10.0
+    e = np.linspace(-3.0, 3.0, 601)
+    fd = o.fermi_dirac(e, beta)
+    errs = [np.max(np.abs(o.phi(e, beta, M) - fd)) for M in (4, 8, 12, 16, 20, 25)]
+    assert all(b < a for a, b in zip(errs, errs[1:]) if a > 1e-15)
+    assert errs[0] > 1e-4           # a short expansion is visibly different
+    assert errs[-1] < 1e-14
+
+
+def test_phi_derivatives_vs_finite_differences():
+    beta, M = 20.0, 12
+    e = np.linspace(-1.0, 1.0, 41)
+    p1, p2, p4 = o.phi_derivs(e, beta, M)
+    h = 1e-4
+    f = lambda x: o.phi(x, beta, M)
+    d1 = (f(e - 2 * h) - 8 * f(e - h) + 8 * f(e + h) - f(e + 2 * h)) / (12 * h)
+    d2 = (-f(e - 2 * h) + 16 * f(e - h) - 30 * f(e) + 16 * f(e + h) - f(e + 2 * h)) / (12 * h * h)
+    assert np.max(np.abs(d1 - p1)) < 1e-8 * beta
+    assert np.max(np.abs(d2 - p2)) < 1e-4 * beta ** 2
+    # fourth derivative from the analytic second derivative, differenced twice
+    h = 1e-3
+    g = lambda x: o.phi_derivs(x, beta, M)[1]
+    d4 = (g(e - h) - 2 * g(e) + g(e + h)) / (h * h)
+    assert np.max(np.abs(d4 - p4)) < 2e-3 * beta ** 4
+
+
+def test_divided_differences_vs_extended_precision():
+    """dd1/dd2 against plain quotients of phi evaluated in 80-bit long double."""
+    beta, M = 40.0, 30
+    s = np.longdouble(math.ldexp(beta, -(M + 1)))
+    K = np.longdouble(2.0) ** M
+
+    def phil(e):
+        e = np.asarray(e, dtype=np.longdouble)
+        return np.longdouble(0.5) - np.tanh(K * np.arctanh(s * e)) / 2
+
+    rng = np.random.default_rng(3)
+    a = rng.uniform(-0.3, 0.3, 200)
+    b = a + rng.uniform(1e-3, 0.2, 200) * rng.choice([-1, 1], 200)
+    ref1 = (phil(a) - phil(b)) / (a.astype(np.longdouble) - b.astype(np.longdouble))
+    assert np.max(np.abs(o.dd1(a, b, beta, M) - ref1.astype(np.float64))) < 1e-12
+    c = b + rng.uniform(1e-3, 0.2, 200)
+    ref2 = (ref1 - (phil(b) - phil(c)) / (b.astype(np.longdouble) - c.astype(np.longdouble))) / (
+        a.astype(np.longdouble) - c.astype(np.longdouble))
+    got2 = o.dd2(a, b, c, beta, M, 1e-5)
+    assert np.max(np.abs(got2 - ref2.astype(np.float64))) < 1e-9
+    # coincident points reduce to derivatives
+    p1, p2, _ = o.phi_derivs(a, beta, M)
+    assert np.max(np.abs(o.dd1(a, a, beta, M) - p1)) < 1e-12 * beta
+    assert np.max(np.abs(o.dd2(a, a, a, beta, M, 1e-5) - 0.5 * p2)) < 1e-12 * beta ** 2
+    # a nearly coincident pair next to a far point: continuity across delta
+    near = o.dd2(a, a + 2e-5, c, beta, M, 1e-5)
+    ref_near = (o.dd1(a, c, beta, M) - o.dd1(a + 2e-5, c, beta, M)) / (-2e-5)
+    assert np.max(np.abs(near - ref_near)) < 1e-6 * beta ** 2
+
+
+# ---------------------------------------------------------------- P0
+
+@pytest.mark.parametrize("name", ["chain128"])
+def test_p0_invariants(name):
+    """Tr P0 = Ne, [H0, P0] = 0, symmetric, spectrum in (0, 1) (Sec. II)."""
+    c = w.config(name)
+    r = o.canonical_response(c["H0"], c["H1"], None, c["beta"], c["Ne"], c["n"], order=0)
+    P0, H0 = r["P0"], c["H0"]
+    assert abs(np.trace(P0) - c["Ne"]) < 1e-11
+    assert np.max(np.abs(H0 @ P0 - P0 @ H0)) < 1e-12
+    assert np.max(np.abs(P0 - P0.T)) < 1e-14
+    ev = np.linalg.eigvalsh(P0)
+    assert ev.min() > 0 and ev.max() < 1
+
+
+def test_mu_root_is_unique_and_tight():
+    c = w.config("chain128")
+    ev = np.linalg.eigvalsh(c["H0"])
+    mu = o.mu_canonical(ev, c["beta"], c["n"], c["Ne"])
+    occ = np.sum(o.phi(ev - mu, c["beta"], c["n"]))
+    assert abs(occ - c["Ne"]) < 1e-12
+    # strictly increasing occupation
+    assert np.sum(o.phi(ev - (mu - 1e-6), c["beta"], c["n"])) < occ < np.sum(o.phi(ev - (mu + 1e-6), c["beta"], c["n"]))
+
+
+# ---------------------------------------------------------------- Algorithm 1
+
+@pytest.mark.parametrize("M,beta", [(6, 4.0), (10, 8.0), (12, 3.0)])
+def test_literal_algorithm1_agrees(M, beta):
+    """The paper's Algorithm 1 (X-form, dense solves, its Newton loop) reaches the oracle's fixed point."""
+    n = 14
+    rng = np.random.default_rng(M)
+    h0 = w.chain_1d(n, M)
+    h1 = np.diag(np.arange(n) - n / 2.0)
+    h2 = _sym(rng, n, 0.05)
+    Ne = 6.0
+    P, mu, _ = alg1_literal.canonical([h0, h1, h2], beta, Ne, M, 2)
+    r = o.canonical_response(h0, [h1], [h2], beta, Ne, M, order=2)
+    tol = 1e-15 * 2 ** M * 10
+    assert np.max(np.abs(P[0] - r["P0"])) < tol
+    assert np.max(np.abs(P[1] - r["P1"][0])) < tol * np.max(np.abs(r["P1"][0])) * 10
+    assert np.max(np.abs(P[2] - r["P2"][0])) < tol * np.max(np.abs(r["P2"][0])) * 20
+    assert abs(mu[0] - r["mu0"]) < tol
+    assert abs(mu[1] - r["mu1"][0]) < tol * 10
+    assert abs(mu[2] - r["mu2"][0]) < tol * 100
+
+
+def test_grand_canonical_response_agrees_with_literal_pass():
+    """One pass at a fixed mu jet (no Newton) against the literal recursion."""
+    n, M, beta = 10, 8, 5.0
+    rng = np.random.default_rng(11)
+    h0 = _sym(rng, n)
+    h1 = _sym(rng, n, 0.3)
+    h2 = _sym(rng, n, 0.2)
+    mu = [0.1, 0.25, -0.4]
+    X = alg1_literal.recursion([h0, h1, h2], beta, M, mu, 2)
+    r = o.response(h0, [h1], [h2], beta, M, (mu[0], [mu[1]], [mu[2]]), order=2)
+    assert np.max(np.abs(X[0] - r["P0"])) < 1e-12
+    assert np.max(np.abs(X[1] - r["P1"][0])) < 1e-12
+    assert np.max(np.abs(X[2] - r["P2"][0])) < 1e-11
+
+
+# ---------------------------------------------------------------- perturbations
+
+def _p_of_lambda(h0, h1, h2, lam, beta, Ne, M):
+    h = h0 + lam * h1 + (lam * lam) * h2
+    wv = o.eig(h)
+    mu = o.mu_canonical(wv[0], beta, M, Ne)
+    return o.density(h, beta, M, mu, eigh=wv), mu
+
+
+def test_canonical_finite_differences_in_lambda():
+    """P1 = dP/dlambda and P2 = (1/2) d^2P/dlambda^2 with mu(lambda) re-solved (Eqs. P_resp, H_prt)."""
+    n, M, beta, Ne = 24, 20, 10.0, 11.0
+    rng = np.random.default_rng(5)
+    h0 = w.chain_1d(n, 5)
+    h1 = np.diag(np.arange(n) - n / 2.0) / n
+    h2 = _sym(rng, n, 0.05)
+    r = o.canonical_response(h0, [h1], [h2], beta, Ne, M, order=2)
+
+    def d1(h):
+        pp, mp = _p_of_lambda(h0, h1, h2, h, beta, Ne, M)
+        pm, mm = _p_of_lambda(h0, h1, h2, -h, beta, Ne, M)
+        return (pp - pm) / (2 * h), (mp - mm) / (2 * h)
+
+    def d2(h):
+        pp, mp = _p_of_lambda(h0, h1, h2, h, beta, Ne, M)
+        pm, mm = _p_of_lambda(h0, h1, h2, -h, beta, Ne, M)
+        p0, m0 = _p_of_lambda(h0, h1, h2, 0.0, beta, Ne, M)
+        return (pp - 2 * p0 + pm) / (2 * h * h), (mp - 2 * m0 + mm) / (2 * h * h)
+
+    h = 1e-3
+    a1, b1 = d1(h)
+    a2, b2 = d1(2 * h)
+    P1_fd = (4 * a1 - a2) / 3
+    mu1_fd = (4 * b1 - b2) / 3
+    s1 = np.max(np.abs(r["P1"][0]))
+    assert np.max(np.abs(P1_fd - r["P1"][0])) < 1e-9 * max(s1, 1)
+    assert abs(mu1_fd - r["mu1"][0]) < 1e-9
+    h = 4e-3
+    a1, b1 = d2(h)
+    a2, b2 = d2(2 * h)
+    P2_fd = (4 * a1 - a2) / 3
+    mu2_fd = (4 * b1 - b2) / 3
+    s2 = np.max(np.abs(r["P2"][0]))
+    assert np.max(np.abs(P2_fd - r["P2"][0])) < 2e-6 * max(s2, 1)
+    assert abs(mu2_fd - r["mu2"][0]) < 2e-6 * max(abs(r["mu2"][0]), 1)
+    assert abs(np.trace(r["P1"][0])) < 1e-12 and abs(np.trace(r["P2"][0])) < 1e-11
+
+
+def test_identity_perturbation_only_shifts_mu():
+    """H1 = I moves mu1 by exactly 1 and leaves P1 = 0; H2 = I (H1 = 0) gives mu2 = 1, P2 = 0."""
+    c = w.config("chain128")
+    n = c["N"]
+    r = o.canonical_response(c["H0"], [np.eye(n)], None, c["beta"], c["Ne"], c["n"], order=2)
+    assert abs(r["mu1"][0] - 1.0) < 1e-13
+    assert np.max(np.abs(r["P1"][0])) < 1e-12
+    assert np.max(np.abs(r["P2"][0])) < 1e-10
+    r = o.canonical_response(c["H0"], [np.zeros((n, n))], [np.eye(n)], c["beta"], c["Ne"], c["n"], order=2)
+    assert abs(r["mu2"][0] - 1.0) < 1e-13
+    assert np.max(np.abs(r["P2"][0])) < 1e-12
+
+
+def test_two_level_analytic():
+    """2x2: H0 = diag(a, b), off-diagonal H1 = v: P1_12 = v (phi(a) - phi(b))/(a - b), mu1 = 0."""
+    beta, M = 7.0, 15
+    a, b, v = -0.3, 0.45, 0.2
+    h0 = np.diag([a, b])
+    h1 = np.array([[0.0, v], [v, 0.0]])
+    mu = 0.1
+    r = o.response(h0, [h1], None, beta, M, (mu, [0.0], [0.0]), order=1)
+    expect = v * (o.phi(a - mu, beta, M) - o.phi(b - mu, beta, M)) / (a - b)
+    assert abs(r["P1"][0][0, 1] - expect) < 1e-15
+    assert abs(r["P1"][0][0, 0]) < 1e-16 and abs(r["P1"][0][1, 1]) < 1e-16
+    # canonical: mu1 = 0 because the diagonal of H1 in the eigenbasis vanishes
+    rc = o.canonical_response(h0, [h1], None, beta, 1.0, M, order=1)
+    assert abs(rc["mu1"][0]) < 1e-15
+
+
+def test_second_order_kernel_bruteforce():
+    """Q_ij = sum_k phi[e_i,e_k,e_j] E_ik E_kj by a plain triple loop with a plain quotient rule."""
+    n, M, beta = 9, 14, 6.0
+    rng = np.random.default_rng(2)
+    e = np.sort(rng.uniform(-1, 1, n))
+    e[4] = e[3] + 3e-7            # a near-degenerate pair goes through the direct path
+    E = _sym(rng, n)
+    F1 = o.dd1(e[:, None], e[None, :], beta, M)
+    got = o.dmpt_oracle._second_order_kernel(e, F1, E, beta, M, 1e-5)
+    ref = np.zeros((n, n))
+    for i in range(n):
+        for j in range(n):
+            acc = 0.0
+            for k in range(n):
+                pts = sorted([e[i], e[k], e[j]])
+                if pts[2] - pts[0] > 1e-3:
+                    lo, mid, hi = pts
+                    f01 = (o.phi(lo, beta, M) - o.phi(mid, beta, M)) / (lo - mid) if mid - lo > 1e-3 else o.dd1(lo, mid, beta, M)
+                    f12 = (o.phi(mid, beta, M) - o.phi(hi, beta, M)) / (mid - hi) if hi - mid > 1e-3 else o.dd1(mid, hi, beta, M)
+                    dd = (f01 - f12) / (lo - hi)
+                else:
+                    dd = 0.5 * o.phi_derivs(np.mean(pts), beta, M)[1]
+                acc += dd * E[i, k] * E[k, j]
+            ref[i, j] = acc
+    assert np.max(np.abs(got - ref)) < 1e-9 * np.max(np.abs(ref))
+
+
+def test_reciprocity_of_first_order_response():
+    """Tr(A P1[B]) = Tr(B P1[A]) for the canonical first-order kernel."""
+    n, M, beta, Ne = 30, 18, 8.0, 13.0
+    rng = np.random.default_rng(9)
+    h0 = _sym(rng, n)
+    A, B = _sym(rng, n), _sym(rng, n)
+    pa = o.canonical_response(h0, [A], None, beta, Ne, M, order=1)["P1"][0]
+    pb = o.canonical_response(h0, [B], None, beta, Ne, M, order=1)["P1"][0]
+    assert abs(np.sum(A * pb) - np.sum(B * pa)) < 1e-12 * max(1.0, abs(np.sum(A * pb)))
+
+
+def test_adjoint_matches_directional_derivatives():
+    """G = d Tr(A P0)/dH0 (canonical) against central differences along symmetric directions."""
+    n, M, beta, Ne = 20, 16, 9.0, 9.0
+    rng = np.random.default_rng(21)
+    h0 = w.chain_1d(n, 21)
+    A = np.diag(np.arange(n) - n / 2.0)
+    G = o.adjoint_grad(h0, beta, Ne, M, A)
+    assert np.max(np.abs(G - G.T)) < 1e-13
+    for t in range(4):
+        E = _sym(rng, n)
+        E /= np.linalg.norm(E)
+        f = lambda h: float(np.sum(A * _p_of_lambda(h0, E, np.zeros_like(E), h, beta, Ne, M)[0]))
+        hh = 1e-4
+        fd1 = (f(hh) - f(-hh)) / (2 * hh)
+        fd2 = (f(2 * hh) - f(-2 * hh)) / (4 * hh)
+        fd = (4 * fd1 - fd2) / 3
+        assert abs(fd - np.sum(G * E)) < 1e-8 * max(1.0, abs(fd))
+
+
+# ---------------------------------------------------------------- free energy
+
+def test_n_plus_one_rule_second_order():
+    """Eq. (Resp_0): Omega^(2) = (1/2) Tr[H1 P1] + Tr[H2 P0] equals the lambda^2 coefficient of Omega."""
+    n, beta, Ne, M = 24, 6.0, 10.0, 40  # M large: the expansion equals Fermi-Dirac to rounding
+    rng = np.random.default_rng(4)
+    h0 = w.chain_1d(n, 4)
+    h1 = np.diag(np.arange(n) - n / 2.0) / n
+    h2 = _sym(rng, n, 0.05)
+    r = o.canonical_response(h0, [h1], [h2], beta, Ne, M, order=2)
+    om2 = 0.5 * r["tr_h1p1"][0] + r["tr_h2p0"][0]
+    om3 = (r["tr_h1p2"][0] + 2 * float(np.sum(h2 * r["P1"][0]))) / 3.0
+    f = lambda lam: o.omega(h0 + lam * h1 + lam * lam * h2, beta, Ne, M)
+    h = 2e-3
+    f0, fp, fm, fp2, fm2 = f(0), f(h), f(-h), f(2 * h), f(-2 * h)
+    c2 = (-fp2 + 16 * fp - 30 * f0 + 16 * fm - fm2) / (12 * h * h) / 2.0
+    c3 = (fp2 - 2 * fp + 2 * fm - fm2) / (2 * h ** 3) / 6.0
+    assert abs(c2 - om2) < 1e-6 * max(1.0, abs(om2))
+    assert abs(c3 - om3) < 1e-3 * max(1.0, abs(om3))
+    # first order: Omega^(1) = Tr[H1 P0]
+    c1 = (fp - fm) / (2 * h)
+    assert abs(c1 - float(np.sum(h1 * r["P0"]))) < 1e-5
+
+
+def test_entropy_derivative_identity():
+    """Eq. (EntDer): dS/dlambda = k_B beta Tr[H P^(1)] for a canonical perturbation (Fermi-Dirac limit)."""
+    n, beta, Ne, M = 16, 5.0, 7.0, 40
+    rng = np.random.default_rng(8)
+    h0 = _sym(rng, n)
+    h1 = _sym(rng, n, 0.2)
+    r = o.canonical_response(h0, [h1], None, beta, Ne, M, order=1)
+
+    def S(lam):
+        wv = o.eig(h0 + lam * h1)
+        mu = o.mu_canonical(wv[0], beta, M, Ne)
+        return o.entropy(o.phi(wv[0] - mu, beta, M))
+
+    h = 1e-4
+    dS = (S(h) - S(-h)) / (2 * h)
+    assert abs(dS - beta * float(np.sum(h0 * r["P1"][0]))) < 1e-6
+
+
+# ---------------------------------------------------------------- planted mistakes
+
+def test_planted_mistakes_are_caught(monkeypatch):
+    """A wrong sign in the canonical mu1 shift, or a dropped second-order term, fails a pin."""
+    n, M, beta, Ne = 12, 10, 5.0, 5.0
+    h0 = w.chain_1d(n, 3)
+    h1 = np.diag(np.arange(n) - n / 2.0) / n
+    P, mu, _ = alg1_literal.canonical([h0, h1, np.zeros((n, n))], beta, Ne, M, 2)
+    good = o.canonical_response(h0, [h1], None, beta, Ne, M, order=2)
+    assert np.max(np.abs(good["P2"][0] - P[2])) < 1e-10
+    orig = o.dmpt_oracle._second_order_kernel
+    monkeypatch.setattr(o.dmpt_oracle, "_second_order_kernel", lambda *a: 0.0 * orig(*a))
+    bad = o.canonical_response(h0, [h1], None, beta, Ne, M, order=2)
+    assert np.max(np.abs(bad["P2"][0] - P[2])) > 1e-3
+    monkeypatch.setattr(o.dmpt_oracle, "_second_order_kernel", orig)
+    orig_dd1 = o.dmpt_oracle.dd1
+    monkeypatch.setattr(o.dmpt_oracle, "dd1", lambda a, b, be, m: orig_dd1(b, a, be, m) * 1.01)
+    bad = o.canonical_response(h0, [h1], None, beta, Ne, M, order=1)
+    assert np.max(np.abs(bad["P1"][0] - P[1])) > 1e-4
