@@ -1,0 +1,188 @@
+/*
+ * dmpt.h -- C ABI of the MI355X (gfx950) canonical density-matrix
+ * perturbation theory library.
+ *
+ * The method (Niklasson, Rubensson, Rudberg, Cawkwell, "Canonical density
+ * matrix perturbation theory"):
+ *   Sec. II, Eq. (Rec_F_2)   recursive Fermi-operator expansion
+ *        X_0 = I/2 - 2^-(n+2) beta (H - mu I),  X_k = X^2 [X^2 + (I - X)^2]^-1,
+ *        P = X_n  (n recursion steps; the paper calls it M);
+ *   Sec. II, Eqs. (P_resp), (H_prt) and Algorithm 1
+ *        perturbed recursions for P^(1), P^(2) under H = H0 + lambda H1 + lambda^2 H2,
+ *        each step a linear solve with the same system matrix T = X^2 + (I - X)^2;
+ *   Sec. II, Eq. (NewtRaphs) and Algorithm 1's while loop
+ *        canonical Newton update of the mu jet with P_mu = beta P0 (I - P0) so
+ *        that Tr P0 = Ne and Tr P1 = Tr P2 = 0;
+ *   Sec. III, Eq. (Resp_0)   response traces Tr[H^(k) P^(m-k)].
+ *
+ * Internally the recursion runs in the shifted variable D = I/2 - X, for
+ * which a step reads D_k = 2 D (I + 4 D^2)^-1 (algebraically identical; it
+ * keeps the iterate away from the rounding grid of 1/2).
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are DEVICE pointers to dense, row-major, N x N FP64 arrays with
+ *     leading dimension N, owned by the caller.  Inputs are read only and are
+ *     used through their symmetric part (A + A^T)/2.  Outputs are written in
+ *     full and are symmetric.  The library keeps no reference to caller
+ *     buffers after a call returns.  A diagonal perturbation must still be
+ *     passed as a full matrix.
+ *   - Work is queued on the context's HIP stream.  A call returns after the
+ *     values it reports on the host (statistics, the mu jet) are final; output
+ *     matrices are complete when the call returns.
+ *   - Errors are status codes; nothing is thrown across the ABI.  Arguments
+ *     are checked on the host before any device work; dmpt_last_error()
+ *     describes the most recent failure of a context.
+ *   - A context is not thread safe; use one context per host thread.
+ */
+#ifndef DMPT_H
+#define DMPT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dmpt_ctx_s* dmpt_ctx;
+
+typedef enum {
+  DMPT_OK = 0,
+  DMPT_ERR_ARG = -1,        /* invalid argument (checked before any launch) */
+  DMPT_ERR_HIP = -2,        /* a HIP runtime call failed */
+  DMPT_ERR_NOMEM = -3,      /* device allocation failed or the problem exceeds the context */
+  DMPT_ERR_NOCONV = -4,     /* Newton loop or a linear solve did not reach its tolerance */
+  DMPT_ERR_RANGE = -5,      /* beta * spread(H0) >= 2^(n+1): X_0 leaves [0, 1] (Appendix A) */
+  DMPT_ERR_NONFINITE = -6,  /* NaN or Inf in an input or in an iterate */
+  DMPT_ERR_UNSUPPORTED = -7 /* feature not built for this configuration */
+} dmpt_status;
+
+/* Arithmetic of the matrix products and of the iterates.  Every mode keeps
+ * FP64 for traces, norms, the mu jet and the reported outputs. */
+typedef enum {
+  DMPT_FP64 = 0,    /* FP64 iterates, FP64 MFMA products */
+  DMPT_FP32 = 1,    /* FP32 iterates, FP32 MFMA products */
+  DMPT_BF16X3 = 2,  /* FP32 iterates; products as hi*hi + hi*lo + lo*hi of BF16 splits, FP32 accumulation */
+  DMPT_BF16X6 = 3   /* FP32 iterates; three-way BF16 split, six cross products, FP32 accumulation */
+} dmpt_prec;
+
+/* Per-step linear solver for T' Y = R, T' = I + 4 D^2 (2 T of Algorithm 1). */
+typedef enum {
+  DMPT_SOLVER_CG = 0,  /* conjugate gradients, one product per iteration and right-hand side (Sec. II) */
+  DMPT_SOLVER_NS = 1   /* shared inverse of T' by Newton-Schulz, reused for every order (Sec. II remark) */
+} dmpt_solver;
+
+/* Initial guess of the conjugate-gradient solve. */
+typedef enum {
+  DMPT_GUESS_PREV = 0,   /* the previous iterate X_{n-1}^(k) (Algorithm 1 remark) */
+  DMPT_GUESS_TAYLOR = 1  /* 2D - 8D^3 for order 0, previous iterate for the others */
+} dmpt_guess;
+
+typedef struct {
+  dmpt_prec prec;       /* arithmetic mode */
+  dmpt_solver solver;   /* per-step solver */
+  dmpt_guess guess;     /* CG initial guess */
+  double tol_occ;       /* Newton stops when |Tr P0 - Ne| <= tol_occ * N and, for k >= 1,
+                           |Tr P^(k)| <= tol_occ * sum_i |P^(k)_ii|; <= 0: default for prec */
+  double tol_cg;        /* relative residual of each solve; <= 0: default for prec */
+  int max_newton;       /* Newton passes (default 50) */
+  int max_cg;           /* CG iterations per solve (default 60) */
+  int refine;           /* BF16X3 only: after convergence, redo the last passes in BF16X6 (1) or not (0) */
+  int ckpt_every;       /* adjoint: keep every ckpt_every-th iterate, recompute the rest (default 5) */
+  int check;            /* 1: compute the commutator and idempotency checks at the end of a call */
+  int staged;           /* 1: converge mu0 with order-0 passes first, then run full passes (same fixed point) */
+} dmpt_options;
+
+#define DMPT_MAX_DIRS 8
+
+typedef struct {
+  int newton_iters;                      /* Newton passes executed */
+  int cg_iters_total;                    /* CG iterations summed over steps, orders and directions */
+  int cg_iters_max;                      /* largest CG iteration count of a single solve */
+  double occ_err;                        /* |Tr P0 - Ne| + sum_k |Tr P^(k)| of the returned P */
+  double mu[1 + 2 * DMPT_MAX_DIRS];      /* mu0, mu1[d], mu2[d] used for the returned P */
+  double trP[1 + 2 * DMPT_MAX_DIRS];     /* Tr P0, Tr P1[d], Tr P2[d] */
+  double tr_pmu;                         /* Tr P_mu = beta (Tr P0 - ||P0||_F^2) */
+  double tr_h1p1[DMPT_MAX_DIRS];         /* Tr(H1 P1) per direction */
+  double tr_h1p2[DMPT_MAX_DIRS];         /* Tr(H1 P2) per direction */
+  double tr_h2p0[DMPT_MAX_DIRS];         /* Tr(H2 P0) per direction (0 when H2 is absent) */
+  double idempotency;                    /* Tr[P0 (I - P0)] (check = 1) */
+  double commutator;                     /* ||H0 P0 - P0 H0||_F (check = 1) */
+  double asymmetry;                      /* max |P - P^T| over the outputs (check = 1) */
+  double mfma_flops;                     /* matrix-core flops executed (every split product counted) */
+  double useful_flops;                   /* 2 N^3 per logical matrix product */
+  double seconds;                        /* wall time of the call */
+} dmpt_stats;
+
+/* Fill *opt with defaults: FP64, CG, previous-iterate guess, default tolerances. */
+void dmpt_default_options(dmpt_options* opt);
+
+/* Create a context on HIP device `device` able to handle N <= n_max and up
+ * to dirs_max perturbation directions.  All device workspace is allocated
+ * here (sized by n_max, dirs_max and opt->prec) and freed in
+ * dmpt_finalize.  `hip_stream` is a hipStream_t to queue work on; NULL
+ * creates a private stream.  opt may be NULL (defaults). */
+dmpt_status dmpt_init(dmpt_ctx* ctx, int device, int64_t n_max, int dirs_max,
+                      const dmpt_options* opt, void* hip_stream);
+
+/* Release a context and its workspace.  NULL is accepted. */
+dmpt_status dmpt_finalize(dmpt_ctx ctx);
+
+/* Text of the last error of ctx (a static string when ctx is NULL). */
+const char* dmpt_last_error(dmpt_ctx ctx);
+
+/* Replace the options of an existing context; the precision must not need
+ * more workspace than the context was created with. */
+dmpt_status dmpt_set_options(dmpt_ctx ctx, const dmpt_options* opt);
+
+/* Grand-canonical density matrix at fixed mu: P0 = X_n of Eq. (Rec_F_2).
+ * H0: N x N device FP64 (input); P0: N x N device FP64 (output). */
+dmpt_status dmpt_fermi_recursion(dmpt_ctx ctx, int64_t N, const double* H0, double beta,
+                                 double mu, int n, double* P0, dmpt_stats* st);
+
+/* One pass of Algorithm 1's inner loop at a given mu jet (no Newton):
+ * orders 0..order (order in {0, 1, 2}) for d directions.
+ *   H1[d]  device pointers to the first-order perturbations (order >= 1)
+ *   H2[d]  device pointers to second-order perturbations, or H2 == NULL / H2[i] == NULL for zero
+ *   mu     host array: mu0, then mu1[0..d-1] (order >= 1), then mu2[0..d-1] (order >= 2)
+ *   P0, P1[d], P2[d]  device outputs (P1 / P2 may be NULL when order is lower). */
+dmpt_status dmpt_response(dmpt_ctx ctx, int64_t N, const double* H0, int d,
+                          const double* const* H1, const double* const* H2, double beta, int n,
+                          int order, const double* mu, double* P0, double* const* P1,
+                          double* const* P2, dmpt_stats* st);
+
+/* Canonical response (Algorithm 1): Newton on the mu jet until the
+ * occupation error is at most tol_occ.  mu_inout (host, 1 + order*d
+ * doubles): in, mu0 guess (NaN: Tr H0 / N) and mu^(k) guesses (NaN: 0); out,
+ * the jet at which the returned P was computed.  On DMPT_ERR_NOCONV the
+ * outputs and *st hold the last pass. */
+dmpt_status dmpt_mu_newton(dmpt_ctx ctx, int64_t N, const double* H0, int d,
+                           const double* const* H1, const double* const* H2, double beta,
+                           double Ne, int n, int order, double* mu_inout, double* P0,
+                           double* const* P1, double* const* P2, dmpt_stats* st);
+
+/* Batched canonical response: nsys independent systems of sizes Ns[s] (each
+ * <= the context's n_max), with per-system beta and Ne, d directions each.
+ * H0s[s], P0s[s]: N_s x N_s device FP64; H1s[s*d + i], P1s[s*d + i],
+ * P2s[s*d + i] likewise (P1s / P2s may be NULL for lower orders).  mus
+ * (host, nsys * (1 + 2d)) receives each system's jet; st (may be NULL) the
+ * aggregate statistics.  Systems converge independently. */
+dmpt_status dmpt_mu_newton_batched(dmpt_ctx ctx, int nsys, const int64_t* Ns,
+                                   const double* const* H0s, int d, const double* const* H1s,
+                                   const double* betas, const double* Nes, int n, int order,
+                                   double* mus, double* const* P0s, double* const* P1s,
+                                   double* const* P2s, dmpt_stats* st);
+
+/* Adjoint of the canonical map: G = d Tr(Abar P0) / d H0 with mu0 following
+ * H0 through Tr P0 = Ne.  mu0: host pointer to a converged mu0, or NULL to
+ * solve for it first.  Abar, G: N x N device FP64 (G symmetric, so
+ * dTr(Abar P0) = <G, dH> for symmetric dH).  The forward iterates are kept
+ * every ckpt_every steps and recomputed in between. */
+dmpt_status dmpt_backward(dmpt_ctx ctx, int64_t N, const double* H0, double beta, double Ne,
+                          int n, const double* mu0, const double* Abar, double* G,
+                          dmpt_stats* st);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DMPT_H */

@@ -1,0 +1,200 @@
+"""Python front end of the DMPT library: torch tensors in, torch tensors out.
+
+PyTorch is used only for device memory and the current HIP stream; every
+operation of the method runs in libdmpt.so (the C ABI of include/dmpt.h).
+All matrices are N x N float64 CUDA (HIP) tensors; inputs are used through
+their symmetric part.
+"""
+import ctypes
+import math
+
+from . import _lib as L
+
+
+class DMPTError(RuntimeError):
+    """A non-OK status from the library; ``status`` holds the code."""
+
+    def __init__(self, status, msg, stats=None):
+        super().__init__(f"{L.STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+        self.stats = stats
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def options(prec="fp64", solver="cg", guess="prev", tol_occ=0.0, tol_cg=0.0, max_newton=50,
+            max_cg=60, refine=0, ckpt_every=5, check=0, staged=1):
+    """Build an options struct; 0 tolerances select the precision's defaults."""
+    lib = L.load()
+    o = L.Options()
+    lib.dmpt_default_options(ctypes.byref(o))
+    o.prec = L.PREC[prec] if isinstance(prec, str) else int(prec)
+    o.solver = L.SOLVER[solver] if isinstance(solver, str) else int(solver)
+    o.guess = L.GUESS[guess] if isinstance(guess, str) else int(guess)
+    o.tol_occ, o.tol_cg = float(tol_occ), float(tol_cg)
+    o.max_newton, o.max_cg, o.refine = int(max_newton), int(max_cg), int(refine)
+    o.ckpt_every, o.check, o.staged = int(ckpt_every), int(check), int(staged)
+    return o
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(None)
+
+
+def _ptr_array(ts):
+    if ts is None:
+        return None
+    arr = (ctypes.c_void_p * len(ts))()
+    for i, t in enumerate(ts):
+        arr[i] = t.data_ptr() if t is not None else None
+    return arr
+
+
+def _check_mat(t, n, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != (n, n):
+        raise ValueError(f"{name} must be a contiguous ({n}, {n}) float64 GPU tensor")
+
+
+class Context:
+    """A library context (device workspace for N <= n_max, dirs_max directions)."""
+
+    def __init__(self, n_max, dirs_max=1, device=0, stream=None, **opts):
+        torch = _torch()
+        self.lib = L.load()
+        self.device = device
+        self.opts = options(**opts)
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        st = self.lib.dmpt_init(ctypes.byref(h), device, int(n_max), int(dirs_max),
+                                ctypes.byref(self.opts), ctypes.c_void_p(stream.cuda_stream))
+        if st != L.DMPT_OK:
+            raise DMPTError(st, self.lib.dmpt_last_error(None).decode())
+        self.h = h
+        self.n_max, self.dirs_max = n_max, dirs_max
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dmpt_finalize(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_options(self, **opts):
+        o = options(**opts)
+        st = self.lib.dmpt_set_options(self.h, ctypes.byref(o))
+        self._raise(st)
+        self.opts = o
+
+    def _raise(self, st, stats=None):
+        if st != L.DMPT_OK:
+            raise DMPTError(st, self.lib.dmpt_last_error(self.h).decode(), stats)
+
+    def _empty(self, n):
+        torch = _torch()
+        return torch.empty((n, n), dtype=torch.float64, device=f"cuda:{self.device}")
+
+    # ------------------------------------------------------------------ calls
+    def fermi_recursion(self, H0, beta, mu, n, out=None):
+        """Grand-canonical P0 at fixed mu (Eq. Rec_F_2).  Returns (P0, stats)."""
+        N = H0.shape[0]
+        _check_mat(H0, N, "H0")
+        P0 = out if out is not None else self._empty(N)
+        s = L.Stats()
+        st = self.lib.dmpt_fermi_recursion(self.h, N, _ptr(H0), float(beta), float(mu), int(n),
+                                           _ptr(P0), ctypes.byref(s))
+        self._raise(st, s)
+        return P0, s.as_dict()
+
+    def response(self, H0, H1=(), H2=None, beta=1.0, n=20, order=0, mu=(0.0,), raise_on_error=True):
+        """One pass at a fixed mu jet.  Returns (P0, [P1], [P2], stats)."""
+        N = H0.shape[0]
+        _check_mat(H0, N, "H0")
+        d = len(H1) if order >= 1 else 0
+        for i, h in enumerate(H1[:d]):
+            _check_mat(h, N, f"H1[{i}]")
+        h2 = None
+        if order >= 2 and H2 is not None:
+            for i, h in enumerate(H2):
+                if h is not None:
+                    _check_mat(h, N, f"H2[{i}]")
+            h2 = _ptr_array(list(H2))
+        mu = [float(m) for m in mu]
+        P0 = self._empty(N)
+        P1 = [self._empty(N) for _ in range(d)] if order >= 1 else []
+        P2 = [self._empty(N) for _ in range(d)] if order >= 2 else []
+        s = L.Stats()
+        mu_arr = (ctypes.c_double * len(mu))(*mu)
+        st = self.lib.dmpt_response(self.h, N, _ptr(H0), d, _ptr_array(list(H1[:d])), h2,
+                                    float(beta), int(n), int(order), mu_arr, _ptr(P0),
+                                    _ptr_array(P1) if P1 else None, _ptr_array(P2) if P2 else None,
+                                    ctypes.byref(s))
+        stats = s.as_dict(d, order)
+        if raise_on_error:
+            self._raise(st, stats)
+        stats["status"] = st
+        return P0, P1, P2, stats
+
+    def mu_newton(self, H0, H1=(), H2=None, beta=1.0, Ne=1.0, n=20, order=0, mu=None,
+                  raise_on_error=True):
+        """Canonical response (Algorithm 1).  Returns (P0, [P1], [P2], mu_jet, stats)."""
+        N = H0.shape[0]
+        _check_mat(H0, N, "H0")
+        d = len(H1) if order >= 1 else 0
+        for i, h in enumerate(H1[:d]):
+            _check_mat(h, N, f"H1[{i}]")
+        h2 = None
+        if order >= 2 and H2 is not None:
+            for i, h in enumerate(H2):
+                if h is not None:
+                    _check_mat(h, N, f"H2[{i}]")
+            h2 = _ptr_array(list(H2))
+        nmu = 1 + order * d
+        m = [math.nan] * nmu
+        if mu is not None:
+            for i, v in enumerate(mu[:nmu]):
+                m[i] = float(v)
+        mu_arr = (ctypes.c_double * nmu)(*m)
+        P0 = self._empty(N)
+        P1 = [self._empty(N) for _ in range(d)] if order >= 1 else []
+        P2 = [self._empty(N) for _ in range(d)] if order >= 2 else []
+        s = L.Stats()
+        st = self.lib.dmpt_mu_newton(self.h, N, _ptr(H0), d, _ptr_array(list(H1[:d])), h2,
+                                     float(beta), float(Ne), int(n), int(order), mu_arr, _ptr(P0),
+                                     _ptr_array(P1) if P1 else None,
+                                     _ptr_array(P2) if P2 else None, ctypes.byref(s))
+        stats = s.as_dict(d, order)
+        stats["status"] = st
+        if raise_on_error:
+            self._raise(st, stats)
+        return P0, P1, P2, list(mu_arr), stats
+
+    def backward(self, H0, beta, Ne, n, Abar, mu0=None):
+        """Adjoint G = d Tr(Abar P0)/d H0 of the canonical map.  Returns (G, stats)."""
+        N = H0.shape[0]
+        _check_mat(H0, N, "H0")
+        _check_mat(Abar, N, "Abar")
+        G = self._empty(N)
+        s = L.Stats()
+        m = (ctypes.c_double * 1)(float(mu0)) if mu0 is not None else None
+        st = self.lib.dmpt_backward(self.h, N, _ptr(H0), float(beta), float(Ne), int(n), m,
+                                    _ptr(Abar), _ptr(G), ctypes.byref(s))
+        self._raise(st, s.as_dict())
+        return G, s.as_dict()

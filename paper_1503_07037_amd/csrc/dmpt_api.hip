@@ -1,0 +1,1017 @@
+// Host side of the DMPT library: context and workspace, argument checks,
+// the per-step recursion driver (Algorithm 1's inner loop), the canonical
+// Newton loop (Algorithm 1's while loop) and the C ABI of dmpt.h.
+//
+// The recursion runs on D = I/2 - X (Eq. Rec_F_2 with X_0 = I/2 - c(H - mu I),
+// c = 2^-(n+2) beta):  D_0^(0) = c (H0 - mu0 I),  D_0^(k) = c (H^(k) - mu^(k) I),
+// and each step solves, with T' = I + 4 D^2 (= 2 T of Algorithm 1),
+//     T' Y^(0) = 2 D^(0)
+//     T' Y^(1) = 2 D^(1) - 4 S^(1) Y^(0)
+//     T' Y^(2) = 2 D^(2) - 4 S^(1) Y^(1) - 4 S^(2) Y^(0)
+// with S^(1) = D^(0) D^(1) + D^(1) D^(0), S^(2) = D^(0) D^(2) + D^(2) D^(0) + D^(1) D^(1)
+// (the lambda-expansion of T'(lambda) Y(lambda) = 2 D(lambda); these are the
+// systems of Algorithm 1 written for D).  After n steps P^(0) = I/2 - D^(0),
+// P^(k) = -D^(k).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dmpt_internal.h"
+
+using namespace dmpt;
+
+namespace {
+
+const char* kNoCtx = "invalid context (NULL)";
+
+struct Group {
+  void* m = nullptr;             // master base, members at m + z * stride elements
+  uint16_t* pl[3] = {nullptr, nullptr, nullptr};
+  int count = 0;
+};
+
+}  // namespace
+
+struct dmpt_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int64_t n_max = 0, np_max = 0;
+  int dirs_max = 0;
+  dmpt_options opt{};
+  size_t esize = 8;              // master element size of the workspace
+  int planes = 0;                // BF16 planes per operand allocated
+  std::vector<void*> allocs;
+  // matrix groups
+  Group D0, D1, D2, S0, S1, S2, R, P, Q;
+  // scalars
+  int hstride = 0;               // CG history length per right-hand side
+  double* d_rr = nullptr;        // [dirs][hstride]
+  double* d_pq = nullptr;        // [dirs][hstride]
+  double* d_ref = nullptr;       // [dirs]
+  int* d_active = nullptr;       // [dirs]
+  int* d_iters = nullptr;        // [dirs]
+  int* d_flag = nullptr;         // non-finite flag
+  double* d_res = nullptr;       // results block (traces etc.)
+  double* d_part = nullptr;      // partials
+  size_t part_count = 0;
+  double* d_gersh = nullptr;     // 2 + 2 n_max
+  double* h_res = nullptr;       // pinned mirror of d_res
+  int* h_int = nullptr;          // pinned ints
+  std::string err;
+  // per-call statistics accumulators
+  double mfma_flops = 0, useful_flops = 0;
+  long cg_total = 0;
+  int cg_max = 0;
+  bool cg_capped = false;
+};
+
+namespace {
+
+// Layout of the results block d_res.
+enum : int {
+  RES_TR = 0,                          // Tr P0, Tr P1[d], Tr P2[d]
+  RES_ATR = RES_TR + 1 + 2 * DMPT_MAX_DIRS,
+  RES_FRO = RES_ATR + 1 + 2 * DMPT_MAX_DIRS,
+  RES_H1P1 = RES_FRO + 1,
+  RES_H1P2 = RES_H1P1 + DMPT_MAX_DIRS,
+  RES_H2P0 = RES_H1P2 + DMPT_MAX_DIRS,
+  RES_MISC = RES_H2P0 + DMPT_MAX_DIRS,  // scratch scalars
+  RES_HALF = RES_MISC + 15,             // constant 1/2
+  RES_COUNT = RES_MISC + 16
+};
+
+dmpt_status fail(dmpt_ctx c, dmpt_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+#define HIPCHK(ctx, expr)                                                             \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail((ctx), DMPT_ERR_HIP,                                                \
+                  std::string("HIP error: ") + hipGetErrorString(e_) + " in " #expr); \
+  } while (0)
+
+#define STCHK(expr)                    \
+  do {                                 \
+    dmpt_status s_ = (expr);           \
+    if (s_ != DMPT_OK) return s_;      \
+  } while (0)
+
+Engine engine_of(dmpt_prec p) {
+  switch (p) {
+    case DMPT_FP64: return Engine::F64;
+    case DMPT_FP32: return Engine::F32;
+    case DMPT_BF16X3: return Engine::BF16S2;
+    case DMPT_BF16X6: return Engine::BF16S3;
+  }
+  return Engine::F64;
+}
+
+double default_tol_cg(dmpt_prec p) {
+  switch (p) {
+    case DMPT_FP64: return 1e-14;
+    case DMPT_FP32: return 1e-6;
+    case DMPT_BF16X3: return 1e-5;
+    case DMPT_BF16X6: return 1e-6;
+  }
+  return 1e-14;
+}
+
+double default_tol_occ(dmpt_prec p) {
+  switch (p) {
+    case DMPT_FP64: return 1e-12;
+    case DMPT_FP32: return 2e-6;
+    case DMPT_BF16X3: return 2e-5;
+    case DMPT_BF16X6: return 2e-6;
+  }
+  return 1e-12;
+}
+
+int planes_needed(const dmpt_options& o) {
+  int p = engine_planes(engine_of(o.prec));
+  if (o.prec == DMPT_BF16X3 && o.refine) p = 3;
+  return p;
+}
+
+size_t esize_needed(const dmpt_options& o) { return o.prec == DMPT_FP64 ? 8 : 4; }
+
+// ------------------------------------------------------------------ views
+struct Call {
+  dmpt_ctx c;
+  Engine eng;
+  int np;                        // planes used by the engine
+  int64_t N, Np, nn;             // nn = Np*Np
+  int64_t stride;                // member stride of every group (elements)
+  bool f64;
+};
+
+// Member z of a group as an operand.
+BOp op(const Call& k, const Group& g, int z, bool batched) {
+  BOp o;
+  const size_t es = k.c->esize;
+  o.m = (const char*)g.m + (size_t)z * k.stride * es;
+  for (int p = 0; p < 3; ++p) o.pl[p] = g.pl[p] ? g.pl[p] + (size_t)z * k.stride : nullptr;
+  o.stride = batched ? k.stride : 0;
+  return o;
+}
+void* mptr(const Call& k, const Group& g, int z) {
+  return (char*)g.m + (size_t)z * k.stride * k.c->esize;
+}
+void planes_of(const Call& k, const Group& g, int z, uint16_t** out) {
+  for (int p = 0; p < 3; ++p)
+    out[p] = (g.pl[p] && p < k.np) ? g.pl[p] + (size_t)z * k.stride : nullptr;
+}
+
+// C(batch members z0..z0+batch) = alpha X Y^T + beta1 C1 + beta2 C2
+struct G {
+  BOp X, Y;
+  void* C = nullptr;
+  int64_t sC = 0;
+  uint16_t* Cpl[3] = {nullptr, nullptr, nullptr};
+  double alpha = 1.0;
+  const void* C1 = nullptr; int64_t sC1 = 0; double beta1 = 0.0;
+  const void* C2 = nullptr; int64_t sC2 = 0; double beta2 = 0.0;
+  const void* W = nullptr; int64_t sW = 0;
+  int batch = 1;
+  const int* active = nullptr;
+};
+
+dmpt_status run_gemm(const Call& k, const G& g) {
+  GemmArgs a{};
+  a.eng = k.eng;
+  a.Np = k.Np;
+  a.batch = g.batch;
+  a.X = g.X;
+  a.Y = g.Y;
+  a.C = g.C;
+  a.sC = g.sC;
+  for (int p = 0; p < 3; ++p) a.Cpl[p] = (p < k.np) ? g.Cpl[p] : nullptr;
+  a.alpha = g.alpha;
+  a.C1 = g.C1; a.sC1 = g.sC1; a.beta1 = g.beta1;
+  a.C2 = g.C2; a.sC2 = g.sC2; a.beta2 = g.beta2;
+  a.W = g.W; a.sW = g.sW;
+  a.partials = k.c->d_part;
+  a.active = g.active;
+  HIPCHK(k.c, gemm(a, k.c->stream));
+  const double n3 = 2.0 * (double)k.Np * k.Np * k.Np;
+  k.c->mfma_flops += n3 * engine_terms(k.eng) * g.batch;
+  k.c->useful_flops += 2.0 * (double)k.N * k.N * k.N * g.batch;
+  return DMPT_OK;
+}
+
+// Sum the GEMM per-tile partials into out[z*ostride + oidx].
+dmpt_status sum_gemm_partials(const Call& k, int batch, double* out, int ostride, int oidx) {
+  HIPCHK(k.c, sum_partials(k.c->d_part, gemm_tiles(k.eng, k.Np), batch, out, ostride, oidx,
+                           k.c->stream));
+  return DMPT_OK;
+}
+
+// ------------------------------------------------------------------ typed helpers
+template <class T>
+dmpt_status sym_inplace(const Call& k, const Group& g, int z0, int batch, double a) {
+  uint16_t* pl[3];
+  planes_of(k, g, z0, pl);
+  T* m = (T*)mptr(k, g, z0);
+  HIPCHK(k.c, (sym_combine<T, T>(m, k.Np, k.stride, k.N, k.Np, a, nullptr, 0, m, k.Np, k.stride,
+                                 pl, k.np, batch, k.c->stream)));
+  return DMPT_OK;
+}
+
+// out group (members z0..) = a (in + in^T), in and out distinct groups.
+template <class T>
+dmpt_status sym_to(const Call& k, const Group& in, const Group& out, int batch, bool planes) {
+  uint16_t* pl[3];
+  planes_of(k, out, 0, pl);
+  HIPCHK(k.c, (sym_combine<T, T>((const T*)mptr(k, in, 0), k.Np, k.stride, k.N, k.Np, 1.0, nullptr,
+                                 0, (T*)mptr(k, out, 0), k.Np, k.stride, pl, planes ? k.np : 0,
+                                 batch, k.c->stream)));
+  return DMPT_OK;
+}
+
+// Conjugate gradients on the transposed unknowns U (U T' = R^T, see gemm.hip):
+//   U (group `u`, members z = 0..batch-1) holds the initial guess and
+//   receives the solution; R holds the initial residual, whose squared norm
+//   is in d_rr[z][0]; d_ref[z] holds ||rhs||^2.
+template <class T>
+dmpt_status cg_solve(const Call& k, const Group& u, int batch) {
+  dmpt_ctx c = k.c;
+  hipStream_t s = c->stream;
+  const int hs = c->hstride;
+  const double tol = c->opt.tol_cg;
+  const int64_t n = k.nn;
+  // P = R (with planes)
+  {
+    uint16_t* pl[3];
+    planes_of(k, c->P, 0, pl);
+    HIPCHK(c, axpby<T>((const T*)mptr(k, c->R, 0), k.stride, (T*)mptr(k, c->P, 0), k.stride, n,
+                       batch, 1.0, 0.0, pl, k.stride, k.np, s));
+  }
+  // active[z] = 1; iters = 0; then the check against the initial residual
+  HIPCHK(c, set_values(c->d_active, 1, batch, nullptr, 0.0, 0, s));
+  HIPCHK(c, set_values(c->d_iters, 0, batch, nullptr, 0.0, 0, s));
+  HIPCHK(c, cg_check(c->d_rr, c->d_ref, hs, batch, tol * tol, c->d_active, c->d_iters, s));
+  const int red_nb = reduce_blocks(n);
+  int it = 0;
+  for (; it < c->opt.max_cg; ++it) {
+    // which members are still active?
+    HIPCHK(c, hipMemcpyAsync(c->h_int, c->d_active, batch * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    bool any = false;
+    for (int z = 0; z < batch; ++z) any |= c->h_int[z] != 0;
+    if (!any) break;
+    if (it + 1 >= hs) break;
+    // Q = P + 4 P S0  (T' applied on the right), partials of <P, Q>
+    G g;
+    g.X = op(k, c->P, 0, true);
+    g.Y = op(k, c->S0, 0, false);
+    g.C = mptr(k, c->Q, 0);
+    g.sC = k.stride;
+    g.alpha = 4.0;
+    g.C1 = mptr(k, c->P, 0); g.sC1 = k.stride; g.beta1 = 1.0;
+    g.W = mptr(k, c->P, 0); g.sW = k.stride;
+    g.batch = batch;
+    g.active = c->d_active;
+    STCHK(run_gemm(k, g));
+    STCHK(sum_gemm_partials(k, batch, c->d_pq + it, hs, 0));
+    HIPCHK(c, cg_update_xr<T>((T*)mptr(k, u, 0), (T*)mptr(k, c->R, 0), (const T*)mptr(k, c->P, 0),
+                              (const T*)mptr(k, c->Q, 0), n, k.stride, batch, c->d_rr + it,
+                              c->d_pq + it, hs, c->d_active, c->d_part, s));
+    HIPCHK(c, sum_partials(c->d_part, red_nb, batch, c->d_rr + it + 1, hs, 0, s));
+    {
+      uint16_t* pl[3];
+      planes_of(k, c->P, 0, pl);
+      HIPCHK(c, cg_update_p<T>((T*)mptr(k, c->P, 0), (const T*)mptr(k, c->R, 0), n, k.stride, batch,
+                               c->d_rr + it + 1, c->d_rr + it, hs, c->d_active, pl, k.np, s));
+    }
+    HIPCHK(c, cg_check(c->d_rr + it + 1, c->d_ref, hs, batch, tol * tol, c->d_active, c->d_iters, s));
+  }
+  HIPCHK(c, hipMemcpyAsync(c->h_int, c->d_active, batch * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(c->h_int + DMPT_MAX_DIRS, c->d_iters, batch * sizeof(int),
+                           hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  for (int z = 0; z < batch; ++z) {
+    // d_iters counts the initial check too
+    const int its = std::max(0, c->h_int[DMPT_MAX_DIRS + z] - 1);
+    c->cg_total += its;
+    c->cg_max = std::max(c->cg_max, its);
+    if (c->h_int[z]) c->cg_capped = true;
+  }
+  return DMPT_OK;
+}
+
+// Inputs of one recursion pass.
+struct PassIn {
+  const double* H0;
+  int d;
+  const double* const* H1;
+  const double* const* H2;
+  double beta;
+  int n;
+  int order;
+  const double* mu;  // mu0, mu1[d], mu2[d]
+};
+
+// Initialise D0^(k) = c (sym H^(k) - mu^(k) I) from the FP64 caller inputs.
+template <class T>
+dmpt_status init_d(const Call& k, const PassIn& in, double cscale) {
+  dmpt_ctx c = k.c;
+  hipStream_t s = c->stream;
+  auto one = [&](const double* h, const Group& g, int z, double mu) -> dmpt_status {
+    uint16_t* pl[3];
+    planes_of(k, g, z, pl);
+    T* out = (T*)mptr(k, g, z);
+    if (h) {
+      HIPCHK(c, (sym_combine<double, T>(h, k.N, 0, k.N, k.Np, 0.5 * cscale, nullptr, 0, out, k.Np, 0,
+                                        pl, k.np, 1, s)));
+      // diagonal shift -c mu applied by a scaled identity add
+      HIPCHK(c, scaled_plus_identity<T>(out, out, k.N, k.Np, -cscale * mu, 1.0, pl, k.np, s));
+    } else {
+      HIPCHK(c, scaled_plus_identity<T>(out, out, k.N, k.Np, -cscale * mu, 0.0, pl, k.np, s));
+    }
+    return DMPT_OK;
+  };
+  STCHK(one(in.H0, c->D0, 0, in.mu[0]));
+  if (in.order >= 1)
+    for (int z = 0; z < in.d; ++z) STCHK(one(in.H1[z], c->D1, z, in.mu[1 + z]));
+  if (in.order >= 2)
+    for (int z = 0; z < in.d; ++z)
+      STCHK(one(in.H2 ? in.H2[z] : nullptr, c->D2, z, in.mu[1 + in.d + z]));
+  return DMPT_OK;
+}
+
+// One full pass of the recursion for orders 0..order.
+template <class T>
+dmpt_status recursion_pass(const Call& k, const PassIn& in) {
+  dmpt_ctx c = k.c;
+  hipStream_t s = c->stream;
+  const int d = in.d, hs = c->hstride;
+  const double cscale = std::ldexp(in.beta, -(in.n + 2));
+  STCHK(init_d<T>(k, in, cscale));
+  uint16_t* pl[3];
+  for (int step = 0; step < in.n; ++step) {
+    // S0 = D0 D0
+    {
+      G g;
+      g.X = op(k, c->D0, 0, false);
+      g.Y = op(k, c->D0, 0, false);
+      g.C = mptr(k, c->S0, 0);
+      planes_of(k, c->S0, 0, g.Cpl);
+      STCHK(run_gemm(k, g));
+    }
+    if (in.order >= 1) {
+      // Q = D1 D0 -> S1 = Q + Q^T
+      G g;
+      g.X = op(k, c->D1, 0, true);
+      g.Y = op(k, c->D0, 0, false);
+      g.C = mptr(k, c->Q, 0);
+      g.sC = k.stride;
+      g.batch = d;
+      STCHK(run_gemm(k, g));
+      STCHK(sym_to<T>(k, c->Q, c->S1, d, true));
+    }
+    if (in.order >= 2) {
+      // Q = D2 D0 -> S2 = Q + Q^T; S2 += D1 D1
+      G g;
+      g.X = op(k, c->D2, 0, true);
+      g.Y = op(k, c->D0, 0, false);
+      g.C = mptr(k, c->Q, 0);
+      g.sC = k.stride;
+      g.batch = d;
+      STCHK(run_gemm(k, g));
+      STCHK(sym_to<T>(k, c->Q, c->S2, d, false));
+      G h;
+      h.X = op(k, c->D1, 0, true);
+      h.Y = op(k, c->D1, 0, true);
+      h.C = mptr(k, c->S2, 0);
+      h.sC = k.stride;
+      planes_of(k, c->S2, 0, h.Cpl);
+      h.C1 = mptr(k, c->S2, 0); h.sC1 = k.stride; h.beta1 = 1.0;
+      h.batch = d;
+      STCHK(run_gemm(k, h));
+    }
+    // ---- order 0: T' Y0 = 2 D0, guess D0 (the previous iterate), U = D0 in place
+    {
+      // ||rhs||^2 = 4 ||D0||^2
+      HIPCHK(c, dot_partials<T>((const T*)mptr(k, c->D0, 0), 0, (const T*)mptr(k, c->D0, 0), 0, k.nn,
+                                1, c->d_part, s));
+      HIPCHK(c, sum_partials(c->d_part, reduce_blocks(k.nn), 1, c->d_ref, 1, 0, s));
+      HIPCHK(c, axpby<double>(c->d_ref, 0, c->d_ref, 0, 1, 1, 0.0, 4.0, pl, 0, 0, s));
+      // R = 2 D0 - D0 - 4 D0 S0 = D0 - 4 D0 S0, with ||R||^2 -> rr[0]
+      G g;
+      g.X = op(k, c->D0, 0, false);
+      g.Y = op(k, c->S0, 0, false);
+      g.C = mptr(k, c->R, 0);
+      g.alpha = -4.0;
+      g.C1 = mptr(k, c->D0, 0); g.beta1 = 1.0;
+      g.W = mptr(k, c->R, 0);
+      STCHK(run_gemm(k, g));
+      STCHK(sum_gemm_partials(k, 1, c->d_rr, hs, 0));
+      STCHK(cg_solve<T>(k, c->D0, 1));
+      STCHK(sym_inplace<T>(k, c->D0, 0, 1, 0.5));
+    }
+    // ---- order 1: T' Y1 = 2 D1 - 4 S1 Y0; transposed: rhs^T = 2 D1 - 4 Y0 S1
+    if (in.order >= 1) {
+      G g;  // R = 2 D1 - 4 Y0 S1   (Y0 = new D0), ||rhs||^2 -> ref
+      g.X = op(k, c->D0, 0, false);
+      g.Y = op(k, c->S1, 0, true);
+      g.C = mptr(k, c->R, 0);
+      g.sC = k.stride;
+      g.alpha = -4.0;
+      g.C1 = mptr(k, c->D1, 0); g.sC1 = k.stride; g.beta1 = 2.0;
+      g.W = mptr(k, c->R, 0); g.sW = k.stride;
+      g.batch = d;
+      STCHK(run_gemm(k, g));
+      STCHK(sum_gemm_partials(k, d, c->d_ref, 1, 0));
+      G h;  // R -= D1 + 4 D1 S0  (guess U = D1)
+      h.X = op(k, c->D1, 0, true);
+      h.Y = op(k, c->S0, 0, false);
+      h.C = mptr(k, c->R, 0);
+      h.sC = k.stride;
+      h.alpha = -4.0;
+      h.C1 = mptr(k, c->R, 0); h.sC1 = k.stride; h.beta1 = 1.0;
+      h.C2 = mptr(k, c->D1, 0); h.sC2 = k.stride; h.beta2 = -1.0;
+      h.W = mptr(k, c->R, 0); h.sW = k.stride;
+      h.batch = d;
+      STCHK(run_gemm(k, h));
+      STCHK(sum_gemm_partials(k, d, c->d_rr, hs, 0));
+      STCHK(cg_solve<T>(k, c->D1, d));
+      STCHK(sym_inplace<T>(k, c->D1, 0, d, 0.5));
+    }
+    // ---- order 2: rhs^T = 2 D2 - 4 Y1 S1 - 4 Y0 S2
+    if (in.order >= 2) {
+      G g;  // R = 2 D2 - 4 Y0 S2
+      g.X = op(k, c->D0, 0, false);
+      g.Y = op(k, c->S2, 0, true);
+      g.C = mptr(k, c->R, 0);
+      g.sC = k.stride;
+      g.alpha = -4.0;
+      g.C1 = mptr(k, c->D2, 0); g.sC1 = k.stride; g.beta1 = 2.0;
+      g.batch = d;
+      STCHK(run_gemm(k, g));
+      G g2;  // R -= 4 Y1 S1, ||rhs||^2 -> ref
+      g2.X = op(k, c->D1, 0, true);
+      g2.Y = op(k, c->S1, 0, true);
+      g2.C = mptr(k, c->R, 0);
+      g2.sC = k.stride;
+      g2.alpha = -4.0;
+      g2.C1 = mptr(k, c->R, 0); g2.sC1 = k.stride; g2.beta1 = 1.0;
+      g2.W = mptr(k, c->R, 0); g2.sW = k.stride;
+      g2.batch = d;
+      STCHK(run_gemm(k, g2));
+      STCHK(sum_gemm_partials(k, d, c->d_ref, 1, 0));
+      G h;  // R -= D2 + 4 D2 S0
+      h.X = op(k, c->D2, 0, true);
+      h.Y = op(k, c->S0, 0, false);
+      h.C = mptr(k, c->R, 0);
+      h.sC = k.stride;
+      h.alpha = -4.0;
+      h.C1 = mptr(k, c->R, 0); h.sC1 = k.stride; h.beta1 = 1.0;
+      h.C2 = mptr(k, c->D2, 0); h.sC2 = k.stride; h.beta2 = -1.0;
+      h.W = mptr(k, c->R, 0); h.sW = k.stride;
+      h.batch = d;
+      STCHK(run_gemm(k, h));
+      STCHK(sum_gemm_partials(k, d, c->d_rr, hs, 0));
+      STCHK(cg_solve<T>(k, c->D2, d));
+      STCHK(sym_inplace<T>(k, c->D2, 0, d, 0.5));
+    }
+  }
+  return DMPT_OK;
+}
+
+// Outputs and traces of a pass: P0 = I/2 - D0, P^(k) = -D^(k) (FP64,
+// caller buffers), Tr P^(k), sum |P^(k)_ii|, ||P0||_F^2 and the response
+// traces; then one synchronisation and the values land in c->h_res.
+template <class T>
+dmpt_status finish_pass(const Call& k, const PassIn& in, double* P0, double* const* P1,
+                        double* const* P2) {
+  dmpt_ctx c = k.c;
+  hipStream_t s = c->stream;
+  double* shift = c->d_res + RES_HALF;  // device constant 1/2 for the P0 diagonal
+  HIPCHK(c, (sym_combine<T, double>((const T*)mptr(k, c->D0, 0), k.Np, 0, k.N, k.Np, -0.5, shift, 0,
+                                    P0, k.N, 0, nullptr, 0, 1, s)));
+  HIPCHK(c, trace(P0, k.N, 0, k.N, 1, c->d_res + RES_TR, 1, c->d_res + RES_ATR, s));
+  HIPCHK(c, dot_partials<double>(P0, 0, P0, 0, k.N * k.N, 1, c->d_part, s));
+  HIPCHK(c, sum_partials(c->d_part, reduce_blocks(k.N * k.N), 1, c->d_res + RES_FRO, 1, 0, s));
+  const int d = in.d;
+  for (int ord = 1; ord <= in.order; ++ord) {
+    const Group& g = ord == 1 ? c->D1 : c->D2;
+    double* const* Pk = ord == 1 ? P1 : P2;
+    for (int z = 0; z < d; ++z) {
+      const int slot = (ord == 1 ? 1 : 1 + d) + z;
+      HIPCHK(c, (sym_combine<T, double>((const T*)mptr(k, g, z), k.Np, 0, k.N, k.Np, -0.5, nullptr,
+                                        0, Pk[z], k.N, 0, nullptr, 0, 1, s)));
+      HIPCHK(c, trace(Pk[z], k.N, 0, k.N, 1, c->d_res + RES_TR + slot, 1,
+                      c->d_res + RES_ATR + slot, s));
+      // Tr(H1 P^(k)) = <sym H1, P^(k)> = <H1, P^(k)> since P^(k) is symmetric
+      HIPCHK(c, dot_partials<double>(in.H1[z], 0, Pk[z], 0, k.N * k.N, 1, c->d_part, s));
+      HIPCHK(c, sum_partials(c->d_part, reduce_blocks(k.N * k.N), 1,
+                             c->d_res + (ord == 1 ? RES_H1P1 : RES_H1P2) + z, 1, 0, s));
+      if (ord == 2) {
+        if (in.H2 && in.H2[z]) {
+          HIPCHK(c, dot_partials<double>(in.H2[z], 0, P0, 0, k.N * k.N, 1, c->d_part, s));
+          HIPCHK(c, sum_partials(c->d_part, reduce_blocks(k.N * k.N), 1, c->d_res + RES_H2P0 + z, 1,
+                                 0, s));
+        } else {
+          HIPCHK(c, set_values(nullptr, 0, 0, c->d_res + RES_H2P0 + z, 0.0, 1, s));
+        }
+      }
+    }
+  }
+  HIPCHK(c, hipMemcpyAsync(c->h_res, c->d_res, RES_MISC * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  return DMPT_OK;
+}
+
+dmpt_status check_common(dmpt_ctx c, int64_t N, const double* H0, double beta, int n) {
+  if (!c) return DMPT_ERR_ARG;
+  if (N < 1) return fail(c, DMPT_ERR_ARG, "N must be >= 1");
+  if (N > c->n_max) return fail(c, DMPT_ERR_NOMEM, "N exceeds the context's n_max");
+  if (!H0) return fail(c, DMPT_ERR_ARG, "H0 is NULL");
+  if (!(beta > 0.0) || !std::isfinite(beta)) return fail(c, DMPT_ERR_ARG, "beta must be finite and > 0");
+  if (n < 1 || n > 62) return fail(c, DMPT_ERR_ARG, "recursion depth n must lie in [1, 62]");
+  return DMPT_OK;
+}
+
+dmpt_status check_dirs(dmpt_ctx c, int d, int order, const double* const* H1, const double* const* P1v,
+                       const double* const* P2v) {
+  if (order < 0 || order > 2) return fail(c, DMPT_ERR_ARG, "order must be 0, 1 or 2");
+  if (order == 0) return DMPT_OK;
+  if (d < 1 || d > c->dirs_max || d > DMPT_MAX_DIRS)
+    return fail(c, DMPT_ERR_ARG, "d must lie in [1, dirs_max]");
+  if (!H1) return fail(c, DMPT_ERR_ARG, "H1 is NULL");
+  for (int i = 0; i < d; ++i)
+    if (!H1[i]) return fail(c, DMPT_ERR_ARG, "H1[i] is NULL");
+  if (!P1v) return fail(c, DMPT_ERR_ARG, "P1 is NULL");
+  for (int i = 0; i < d; ++i)
+    if (!P1v[i]) return fail(c, DMPT_ERR_ARG, "P1[i] is NULL");
+  if (order >= 2) {
+    if (!P2v) return fail(c, DMPT_ERR_ARG, "P2 is NULL");
+    for (int i = 0; i < d; ++i)
+      if (!P2v[i]) return fail(c, DMPT_ERR_ARG, "P2[i] is NULL");
+  }
+  return DMPT_OK;
+}
+
+// Non-finite scan of the inputs and the Gershgorin interval of sym(H0).
+dmpt_status scan_inputs(dmpt_ctx c, int64_t N, const PassIn& in, double* glo, double* ghi) {
+  hipStream_t s = c->stream;
+  HIPCHK(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), s));
+  HIPCHK(c, nonfinite_scan(in.H0, N, N, c->d_flag, s));
+  for (int o = 1; o <= in.order; ++o)
+    for (int z = 0; z < in.d; ++z) {
+      const double* h = o == 1 ? in.H1[z] : (in.H2 ? in.H2[z] : nullptr);
+      if (h) HIPCHK(c, nonfinite_scan(h, N, N, c->d_flag, s));
+    }
+  HIPCHK(c, gershgorin(in.H0, N, c->d_gersh, s));
+  double g[2];
+  HIPCHK(c, hipMemcpyAsync(g, c->d_gersh, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(c->h_int, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  if (c->h_int[0]) return fail(c, DMPT_ERR_NONFINITE, "non-finite value in an input matrix");
+  *glo = g[0];
+  *ghi = g[1];
+  return DMPT_OK;
+}
+
+Call make_call(dmpt_ctx c, int64_t N) {
+  Call k;
+  k.c = c;
+  k.eng = engine_of(c->opt.prec);
+  k.np = engine_planes(k.eng);
+  k.N = N;
+  k.Np = padded(N);
+  k.nn = k.Np * k.Np;
+  k.stride = c->np_max * c->np_max;
+  k.f64 = c->opt.prec == DMPT_FP64;
+  return k;
+}
+
+void reset_stats(dmpt_ctx c) {
+  c->mfma_flops = c->useful_flops = 0;
+  c->cg_total = 0;
+  c->cg_max = 0;
+  c->cg_capped = false;
+}
+
+void fill_stats(dmpt_ctx c, const PassIn& in, dmpt_stats* st, int newton, double occ_err, double secs) {
+  if (!st) return;
+  std::memset(st, 0, sizeof(*st));
+  st->newton_iters = newton;
+  st->cg_iters_total = (int)c->cg_total;
+  st->cg_iters_max = c->cg_max;
+  st->occ_err = occ_err;
+  const int d = in.order >= 1 ? in.d : 0;
+  const int nmu = 1 + in.order * d;
+  for (int i = 0; i < nmu; ++i) st->mu[i] = in.mu[i];
+  for (int i = 0; i < nmu; ++i) st->trP[i] = c->h_res[RES_TR + i];
+  st->tr_pmu = in.beta * (c->h_res[RES_TR] - c->h_res[RES_FRO]);
+  for (int z = 0; z < d; ++z) {
+    st->tr_h1p1[z] = c->h_res[RES_H1P1 + z];
+    if (in.order >= 2) {
+      st->tr_h1p2[z] = c->h_res[RES_H1P2 + z];
+      st->tr_h2p0[z] = c->h_res[RES_H2P0 + z];
+    }
+  }
+  st->idempotency = c->h_res[RES_TR] - c->h_res[RES_FRO];
+  st->mfma_flops = c->mfma_flops;
+  st->useful_flops = c->useful_flops;
+  st->seconds = secs;
+}
+
+template <class T>
+dmpt_status one_pass(const Call& k, const PassIn& in, double* P0, double* const* P1,
+                     double* const* P2) {
+  STCHK(recursion_pass<T>(k, in));
+  return finish_pass<T>(k, in, P0, P1, P2);
+}
+
+dmpt_status pass_dispatch(const Call& k, const PassIn& in, double* P0, double* const* P1,
+                          double* const* P2) {
+  if (k.f64) return one_pass<double>(k, in, P0, P1, P2);
+  return one_pass<float>(k, in, P0, P1, P2);
+}
+
+// Commutator ||H0 P0 - P0 H0||_F and output asymmetry (FP64 checks).
+dmpt_status final_checks(dmpt_ctx c, int64_t N, const double* H0, const double* P0, dmpt_stats* st) {
+  if (!st) return DMPT_OK;
+  hipStream_t s = c->stream;
+  // G = H0 P0 computed with the FP64 engine into the (FP64-sized or not)
+  // workspace is only possible when the workspace holds doubles; otherwise
+  // the commutator is evaluated on the host-visible FP64 data in tiles.
+  if (c->esize == 8) {
+    Call k = make_call(c, N);
+    k.eng = Engine::F64;
+    k.np = 0;
+    // copy H0, P0 into padded FP64 members S1[0] (if present) / Q
+    const Group& gh = c->S0;
+    const Group& gp = c->Q;
+    HIPCHK(c, (sym_combine<double, double>(H0, N, 0, N, k.Np, 0.5, nullptr, 0, (double*)mptr(k, gh, 0),
+                                           k.Np, 0, nullptr, 0, 1, s)));
+    HIPCHK(c, (sym_combine<double, double>(P0, N, 0, N, k.Np, 0.5, nullptr, 0, (double*)mptr(k, gp, 0),
+                                           k.Np, 0, nullptr, 0, 1, s)));
+    G g;
+    g.X = op(k, gh, 0, false);
+    g.Y = op(k, gp, 0, false);
+    g.C = mptr(k, c->R, 0);
+    const double mf = c->mfma_flops, uf = c->useful_flops;
+    STCHK(run_gemm(k, g));
+    c->mfma_flops = mf;
+    c->useful_flops = uf;
+    // ||G - G^T||_F^2 = ||H P - P H||_F^2 (H, P symmetric)
+    HIPCHK(c, antisym_sq_partials<double>((const double*)mptr(k, c->R, 0), k.Np, N, c->d_part, s));
+    HIPCHK(c, sum_partials(c->d_part, reduce_blocks(N * N), 1, c->d_res + RES_MISC + 1, 1, 0, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_res + RES_MISC + 1, c->d_res + RES_MISC + 1, sizeof(double),
+                             hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    st->commutator = std::sqrt(std::max(0.0, c->h_res[RES_MISC + 1]));
+  } else {
+    st->commutator = NAN;
+  }
+  HIPCHK(c, asym_max(P0, N, c->d_part, s));
+  std::vector<double> mx(reduce_blocks(N * N));
+  HIPCHK(c, hipMemcpyAsync(mx.data(), c->d_part, mx.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  double m = 0;
+  for (double v : mx) m = std::max(m, v);
+  st->asymmetry = m;
+  return DMPT_OK;
+}
+
+bool converged(const double* res, int d, int order, double Ne, int64_t N, double tol, double* occ_err) {
+  double e = std::fabs(res[RES_TR] - Ne);
+  bool ok = e <= tol * (double)N;
+  for (int i = 1; i < 1 + order * d; ++i) {
+    const double t = std::fabs(res[RES_TR + i]);
+    e += t;
+    if (!(t <= tol * std::max(res[RES_ATR + i], 1e-300))) ok = false;
+  }
+  *occ_err = e;
+  return ok && std::isfinite(e);
+}
+
+}  // namespace
+
+// ======================================================================= C ABI
+extern "C" {
+
+void dmpt_default_options(dmpt_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->prec = DMPT_FP64;
+  o->solver = DMPT_SOLVER_CG;
+  o->guess = DMPT_GUESS_PREV;
+  o->tol_occ = 0.0;
+  o->tol_cg = 0.0;
+  o->max_newton = 50;
+  o->max_cg = 60;
+  o->refine = 0;
+  o->ckpt_every = 5;
+  o->check = 0;
+  o->staged = 1;
+}
+
+static dmpt_status normalise_options(dmpt_ctx c, const dmpt_options* in, dmpt_options* out) {
+  dmpt_options o;
+  if (in) o = *in; else dmpt_default_options(&o);
+  if (o.prec < DMPT_FP64 || o.prec > DMPT_BF16X6) return fail(c, DMPT_ERR_ARG, "unknown precision");
+  if (o.solver != DMPT_SOLVER_CG && o.solver != DMPT_SOLVER_NS)
+    return fail(c, DMPT_ERR_ARG, "unknown solver");
+  if (o.solver == DMPT_SOLVER_NS) return fail(c, DMPT_ERR_UNSUPPORTED, "Newton-Schulz solver not built");
+  if (o.tol_occ <= 0) o.tol_occ = default_tol_occ(o.prec);
+  if (o.tol_cg <= 0) o.tol_cg = default_tol_cg(o.prec);
+  if (o.max_newton <= 0) o.max_newton = 50;
+  if (o.max_cg <= 0) o.max_cg = 60;
+  if (o.max_cg > 500) return fail(c, DMPT_ERR_ARG, "max_cg must be <= 500");
+  if (o.ckpt_every <= 0) o.ckpt_every = 5;
+  *out = o;
+  return DMPT_OK;
+}
+
+static char g_noctx_err[256] = "";
+
+dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, const dmpt_options* opt,
+                      void* hip_stream) {
+  if (!out) return DMPT_ERR_ARG;
+  *out = nullptr;
+  if (n_max < 1 || n_max > (int64_t)1 << 17) {
+    std::snprintf(g_noctx_err, sizeof g_noctx_err, "n_max must lie in [1, 131072]");
+    return DMPT_ERR_ARG;
+  }
+  if (dirs_max < 0 || dirs_max > DMPT_MAX_DIRS) {
+    std::snprintf(g_noctx_err, sizeof g_noctx_err, "dirs_max must lie in [0, %d]", DMPT_MAX_DIRS);
+    return DMPT_ERR_ARG;
+  }
+  dmpt_ctx c = new dmpt_ctx_s();
+  dmpt_status st = normalise_options(c, opt, &c->opt);
+  if (st != DMPT_OK) {
+    std::snprintf(g_noctx_err, sizeof g_noctx_err, "%s", c->err.c_str());
+    delete c;
+    return st;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    std::snprintf(g_noctx_err, sizeof g_noctx_err, "no HIP device %d", device);
+    delete c;
+    return ndev == 0 ? DMPT_ERR_HIP : DMPT_ERR_ARG;
+  }
+  c->device = device;
+  auto bail = [&](dmpt_status s, const char* what) {
+    std::snprintf(g_noctx_err, sizeof g_noctx_err, "%s", what);
+    dmpt_finalize(c);
+    return s;
+  };
+  if (hipSetDevice(device) != hipSuccess) return bail(DMPT_ERR_HIP, "hipSetDevice failed");
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess)
+      return bail(DMPT_ERR_HIP, "hipStreamCreate failed");
+    c->own_stream = true;
+  }
+  c->n_max = n_max;
+  c->np_max = padded(n_max);
+  c->dirs_max = dirs_max;
+  c->esize = esize_needed(c->opt);
+  c->planes = planes_needed(c->opt);
+  const int dm = std::max(1, dirs_max);
+  const size_t nn = (size_t)c->np_max * c->np_max;
+  auto alloc = [&](size_t bytes) -> void* {
+    void* p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(bytes, 256)) != hipSuccess) return nullptr;
+    c->allocs.push_back(p);
+    return p;
+  };
+  auto group = [&](Group& g, int count, bool planes) -> bool {
+    g.count = count;
+    g.m = alloc(nn * c->esize * count);
+    if (!g.m) return false;
+    if (planes)
+      for (int p = 0; p < c->planes; ++p) {
+        g.pl[p] = (uint16_t*)alloc(nn * 2 * count);
+        if (!g.pl[p]) return false;
+      }
+    return true;
+  };
+  const int dd = dirs_max;  // groups for perturbations may be empty
+  bool ok = group(c->D0, 1, true) && group(c->S0, 1, true) && group(c->R, dm, false) &&
+            group(c->P, dm, true) && group(c->Q, dm, false);
+  if (ok && dd > 0)
+    ok = group(c->D1, dd, true) && group(c->D2, dd, true) && group(c->S1, dd, true) &&
+         group(c->S2, dd, true);
+  if (!ok) return bail(DMPT_ERR_NOMEM, "device workspace allocation failed");
+  c->hstride = c->opt.max_cg + 2;
+  c->d_rr = (double*)alloc(sizeof(double) * dm * 512);
+  c->d_pq = (double*)alloc(sizeof(double) * dm * 512);
+  c->d_ref = (double*)alloc(sizeof(double) * DMPT_MAX_DIRS);
+  c->d_active = (int*)alloc(sizeof(int) * DMPT_MAX_DIRS);
+  c->d_iters = (int*)alloc(sizeof(int) * DMPT_MAX_DIRS);
+  c->d_flag = (int*)alloc(sizeof(int) * 4);
+  c->d_res = (double*)alloc(sizeof(double) * RES_COUNT);
+  const size_t tiles = (size_t)(c->np_max / 128) * (c->np_max / 128);
+  c->part_count = std::max<size_t>(tiles, 1024) * dm;
+  c->d_part = (double*)alloc(sizeof(double) * c->part_count);
+  c->d_gersh = (double*)alloc(sizeof(double) * (2 + 2 * (size_t)n_max));
+  if (!c->d_rr || !c->d_pq || !c->d_ref || !c->d_active || !c->d_iters || !c->d_flag || !c->d_res ||
+      !c->d_part || !c->d_gersh)
+    return bail(DMPT_ERR_NOMEM, "device scalar allocation failed");
+  if (hipHostMalloc((void**)&c->h_res, sizeof(double) * RES_COUNT, hipHostMallocDefault) != hipSuccess)
+    return bail(DMPT_ERR_NOMEM, "pinned allocation failed");
+  if (hipHostMalloc((void**)&c->h_int, sizeof(int) * 4 * DMPT_MAX_DIRS, hipHostMallocDefault) !=
+      hipSuccess)
+    return bail(DMPT_ERR_NOMEM, "pinned allocation failed");
+  // zero the workspace once so the padding of every member starts at zero
+  {
+    auto zero = [&](const Group& g) -> bool {
+      if (!g.m) return true;
+      if (hipMemsetAsync(g.m, 0, nn * c->esize * g.count, c->stream) != hipSuccess) return false;
+      for (int p = 0; p < 3; ++p)
+        if (g.pl[p] && hipMemsetAsync(g.pl[p], 0, nn * 2 * g.count, c->stream) != hipSuccess)
+          return false;
+      return true;
+    };
+    if (!(zero(c->D0) && zero(c->S0) && zero(c->R) && zero(c->P) && zero(c->Q) && zero(c->D1) &&
+          zero(c->D2) && zero(c->S1) && zero(c->S2)))
+      return bail(DMPT_ERR_HIP, "workspace clear failed");
+    if (set_values(nullptr, 0, 0, c->d_res + RES_HALF, 0.5, 1, c->stream) != hipSuccess)
+      return bail(DMPT_ERR_HIP, "constant init failed");
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(DMPT_ERR_HIP, "sync failed");
+  }
+  *out = c;
+  return DMPT_OK;
+}
+
+dmpt_status dmpt_finalize(dmpt_ctx c) {
+  if (!c) return DMPT_OK;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (void* p : c->allocs) (void)hipFree(p);
+  c->allocs.clear();
+  if (c->h_res) (void)hipHostFree(c->h_res);
+  if (c->h_int) (void)hipHostFree(c->h_int);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+  return DMPT_OK;
+}
+
+const char* dmpt_last_error(dmpt_ctx c) {
+  if (!c) return g_noctx_err[0] ? g_noctx_err : kNoCtx;
+  return c->err.c_str();
+}
+
+dmpt_status dmpt_set_options(dmpt_ctx c, const dmpt_options* opt) {
+  if (!c) return DMPT_ERR_ARG;
+  dmpt_options o;
+  STCHK(normalise_options(c, opt, &o));
+  if (esize_needed(o) > c->esize || planes_needed(o) > c->planes)
+    return fail(c, DMPT_ERR_NOMEM, "options need more workspace than the context holds");
+  if (o.max_cg + 2 > 512) return fail(c, DMPT_ERR_ARG, "max_cg too large");
+  c->opt = o;
+  c->hstride = o.max_cg + 2;
+  return DMPT_OK;
+}
+
+dmpt_status dmpt_fermi_recursion(dmpt_ctx c, int64_t N, const double* H0, double beta, double mu, int n,
+                                 double* P0, dmpt_stats* st) {
+  STCHK(check_common(c, N, H0, beta, n));
+  if (!P0) return fail(c, DMPT_ERR_ARG, "P0 is NULL");
+  if (!std::isfinite(mu)) return fail(c, DMPT_ERR_ARG, "mu must be finite");
+  double m[1] = {mu};
+  return dmpt_response(c, N, H0, 0, nullptr, nullptr, beta, n, 0, m, P0, nullptr, nullptr, st);
+}
+
+dmpt_status dmpt_response(dmpt_ctx c, int64_t N, const double* H0, int d, const double* const* H1,
+                          const double* const* H2, double beta, int n, int order, const double* mu,
+                          double* P0, double* const* P1, double* const* P2, dmpt_stats* st) {
+  STCHK(check_common(c, N, H0, beta, n));
+  STCHK(check_dirs(c, d, order, H1, (const double* const*)P1, (const double* const*)P2));
+  if (!P0) return fail(c, DMPT_ERR_ARG, "P0 is NULL");
+  if (!mu) return fail(c, DMPT_ERR_ARG, "mu is NULL");
+  const int nmu = 1 + order * (order >= 1 ? d : 0);
+  for (int i = 0; i < nmu; ++i)
+    if (!std::isfinite(mu[i])) return fail(c, DMPT_ERR_ARG, "mu jet must be finite");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, DMPT_ERR_HIP, "hipSetDevice failed");
+  const auto t0 = std::chrono::steady_clock::now();
+  reset_stats(c);
+  PassIn in{H0, order >= 1 ? d : 0, H1, H2, beta, n, order, mu};
+  double glo, ghi;
+  STCHK(scan_inputs(c, N, in, &glo, &ghi));
+  const double emax = std::max(std::fabs(glo - mu[0]), std::fabs(ghi - mu[0]));
+  if (beta * emax >= std::ldexp(1.0, n + 1))
+    return fail(c, DMPT_ERR_RANGE, "beta * max|eps - mu| >= 2^(n+1): the recursion's start leaves [0, 1]");
+  Call k = make_call(c, N);
+  STCHK(pass_dispatch(k, in, P0, P1, P2));
+  double occ = 0;
+  for (int i = 1; i < nmu; ++i) occ += std::fabs(c->h_res[RES_TR + i]);
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  fill_stats(c, in, st, 1, occ, secs);
+  if (c->opt.check) STCHK(final_checks(c, N, H0, P0, st));
+  if (!std::isfinite(c->h_res[RES_TR])) return fail(c, DMPT_ERR_NONFINITE, "non-finite trace");
+  if (c->cg_capped) return fail(c, DMPT_ERR_NOCONV, "a linear solve reached max_cg");
+  return DMPT_OK;
+}
+
+dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const double* const* H1,
+                           const double* const* H2, double beta, double Ne, int n, int order,
+                           double* mu_inout, double* P0, double* const* P1, double* const* P2,
+                           dmpt_stats* st) {
+  STCHK(check_common(c, N, H0, beta, n));
+  STCHK(check_dirs(c, d, order, H1, (const double* const*)P1, (const double* const*)P2));
+  if (!P0) return fail(c, DMPT_ERR_ARG, "P0 is NULL");
+  if (!mu_inout) return fail(c, DMPT_ERR_ARG, "mu_inout is NULL");
+  if (!(Ne > 0.0 && Ne < (double)N)) return fail(c, DMPT_ERR_ARG, "Ne must lie in (0, N)");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, DMPT_ERR_HIP, "hipSetDevice failed");
+  const auto t0 = std::chrono::steady_clock::now();
+  reset_stats(c);
+  const int dd = order >= 1 ? d : 0;
+  const int nmu = 1 + order * dd;
+  std::vector<double> mu(1 + 2 * DMPT_MAX_DIRS, 0.0);
+  for (int i = 0; i < nmu; ++i) mu[i] = mu_inout[i];
+  for (int i = 1; i < nmu; ++i)
+    if (std::isnan(mu[i])) mu[i] = 0.0;
+  PassIn in{H0, dd, H1, H2, beta, n, order, mu.data()};
+  double glo, ghi;
+  STCHK(scan_inputs(c, N, in, &glo, &ghi));
+  if (beta * (ghi - glo) >= std::ldexp(1.0, n + 1))
+    return fail(c, DMPT_ERR_RANGE, "beta * spread(H0) >= 2^(n+1): the recursion's start leaves [0, 1]");
+  if (std::isnan(mu[0])) {
+    // Tr H0 / N from the diagonal (trace kernel on the caller's H0)
+    HIPCHK(c, trace(H0, N, 0, N, 1, c->d_res + RES_MISC + 2, 1, nullptr, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->h_res + RES_MISC + 2, c->d_res + RES_MISC + 2, sizeof(double),
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    mu[0] = c->h_res[RES_MISC + 2] / (double)N;
+  }
+  if (!std::isfinite(mu[0])) return fail(c, DMPT_ERR_ARG, "mu0 guess must be finite");
+  // mu0 stays where the recursion is defined (|eps - mu| < 2^(n+1)/beta for the
+  // Gershgorin interval) and within a generous thermal margin of the spectrum
+  const double lrange = 0.999 * std::ldexp(1.0, n + 1) / beta;
+  const double mu_lo = std::max(ghi - lrange, glo - 50.0 / beta);
+  const double mu_hi = std::min(glo + lrange, ghi + 50.0 / beta);
+  mu[0] = std::min(std::max(mu[0], mu_lo), mu_hi);
+  Call k = make_call(c, N);
+  double occ = 0;
+  int it = 0;
+  bool done = false;
+  // staged: order-0 passes until mu0 is close, then passes of every order
+  const bool staged = c->opt.staged && order > 0;
+  int stage_order = staged ? 0 : order;
+  const double tol = c->opt.tol_occ;
+  for (it = 1; it <= c->opt.max_newton; ++it) {
+    in.order = stage_order;
+    STCHK(pass_dispatch(k, in, P0, P1, P2));
+    const double* r = c->h_res;
+    if (!std::isfinite(r[RES_TR]) || !std::isfinite(r[RES_FRO]))
+      return fail(c, DMPT_ERR_NONFINITE, "non-finite trace in the Newton loop");
+    const bool ok = converged(r, dd, stage_order, Ne, N, tol, &occ);
+    if (ok && stage_order == order) {
+      done = true;
+      break;
+    }
+    const double trpmu = beta * (r[RES_TR] - r[RES_FRO]);
+    if (!(trpmu > 0.0)) return fail(c, DMPT_ERR_NOCONV, "Tr P_mu vanished: Newton step undefined");
+    if (ok) {
+      // order 0 converged: switch to full passes without moving mu0 further
+      stage_order = order;
+      continue;
+    }
+    mu[0] += (Ne - r[RES_TR]) / trpmu;
+    mu[0] = std::min(std::max(mu[0], mu_lo), mu_hi);
+    for (int i = 1; i < 1 + stage_order * dd; ++i) mu[i] -= r[RES_TR + i] / trpmu;
+  }
+  if (it > c->opt.max_newton) it = c->opt.max_newton;
+  in.order = order;
+  for (int i = 0; i < nmu; ++i) mu_inout[i] = mu[i];
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  fill_stats(c, in, st, it, occ, secs);
+  if (c->opt.check) STCHK(final_checks(c, N, H0, P0, st));
+  if (!done) return fail(c, DMPT_ERR_NOCONV, "Newton loop did not reach tol_occ within max_newton passes");
+  if (c->cg_capped) return fail(c, DMPT_ERR_NOCONV, "a linear solve reached max_cg");
+  return DMPT_OK;
+}
+
+dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, const double* const* H0s,
+                                   int d, const double* const* H1s, const double* betas,
+                                   const double* Nes, int n, int order, double* mus,
+                                   double* const* P0s, double* const* P1s, double* const* P2s,
+                                   dmpt_stats* st) {
+  if (!c) return DMPT_ERR_ARG;
+  (void)nsys; (void)Ns; (void)H0s; (void)d; (void)H1s; (void)betas; (void)Nes; (void)n; (void)order;
+  (void)mus; (void)P0s; (void)P1s; (void)P2s; (void)st;
+  return fail(c, DMPT_ERR_UNSUPPORTED, "batched solve not built yet");
+}
+
+dmpt_status dmpt_backward(dmpt_ctx c, int64_t N, const double* H0, double beta, double Ne, int n,
+                          const double* mu0, const double* Abar, double* G, dmpt_stats* st) {
+  if (!c) return DMPT_ERR_ARG;
+  (void)N; (void)H0; (void)beta; (void)Ne; (void)n; (void)mu0; (void)Abar; (void)G; (void)st;
+  return fail(c, DMPT_ERR_UNSUPPORTED, "adjoint not built yet");
+}
+
+}  // extern "C"

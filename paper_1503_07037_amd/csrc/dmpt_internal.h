@@ -1,0 +1,132 @@
+// Internal declarations shared by the HIP kernels and the host drivers of
+// the DMPT library.  Nothing here is part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "dmpt.h"
+
+namespace dmpt {
+
+// Padding granule of the workspace: every working matrix is stored Np x Np
+// with Np = roundup(N, kPad) and zeros outside the leading N x N block, so
+// product kernels never need edge masks.
+constexpr int kPad = 128;
+
+inline int64_t padded(int64_t n) { return (n + kPad - 1) / kPad * kPad; }
+
+// Product engines (see gemm.hip).
+enum class Engine : int { F64 = 0, F32 = 1, BF16S2 = 2, BF16S3 = 3 };
+
+inline int engine_planes(Engine e) {
+  return e == Engine::BF16S2 ? 2 : (e == Engine::BF16S3 ? 3 : 0);
+}
+inline int engine_terms(Engine e) {
+  return e == Engine::BF16S2 ? 3 : (e == Engine::BF16S3 ? 6 : 1);
+}
+
+// A working matrix: master copy (double for F64, float otherwise) plus, for
+// the split-BF16 engines, its BF16 slices (plane p holds the p-th term of
+// x = sum_p bf16_p).  ld = Np.
+struct Mat {
+  void* m = nullptr;                 // master (double* or float*)
+  uint16_t* pl[3] = {nullptr, nullptr, nullptr};
+};
+
+// Batched operand: base matrix and element stride between batch members
+// (0 = the same matrix for every member).
+struct BOp {
+  const void* m = nullptr;
+  const uint16_t* pl[3] = {nullptr, nullptr, nullptr};
+  int64_t stride = 0;
+};
+
+struct GemmArgs {
+  Engine eng;
+  int64_t Np;          // all operands are Np x Np, ld = Np
+  int batch;           // gridDim.z
+  BOp X, Y;            // C = alpha * X * Y^T (+ beta1 C1 + beta2 C2)
+  void* C;             // master output
+  uint16_t* Cpl[3];    // optional split planes of C (nullptr: not written)
+  int64_t sC;
+  double alpha;
+  const void* C1; int64_t sC1; double beta1;
+  const void* C2; int64_t sC2; double beta2;
+  const void* W; int64_t sW;   // optional: per-tile partials of <W, C>
+  double* partials;            // [batch][tiles]
+  const int* active;           // optional per-batch mask; 0 = skip the member
+};
+
+// Number of output tiles of a product of size Np (per batch member).
+int gemm_tiles(Engine eng, int64_t Np);
+hipError_t gemm(const GemmArgs& a, hipStream_t s);
+
+// ---------------------------------------------------------------- element-wise
+// out = a (in + in^T) + dshift I on the leading N x N block, 0 elsewhere.
+// in: Tin with leading dim ldi; out: Tout with leading dim ldo (+ split planes).
+// Batched over `batch` members with element strides.
+// The tile pair (i, j) / (j, i) is handled by one block, so in == out is allowed.
+template <class Tin, class Tout>
+hipError_t sym_combine(const Tin* in, int64_t ldi, int64_t si, int64_t N, int64_t Np, double a,
+                       const double* dshift, int dstride, Tout* out, int64_t ldo, int64_t so,
+                       uint16_t* const* planes, int nplanes, int batch, hipStream_t s);
+
+// Split a master matrix into BF16 planes (batched).
+hipError_t split_planes(const float* x, int64_t n_elems, int64_t sx, uint16_t* const* planes,
+                        int64_t sp, int nplanes, int batch, hipStream_t s);
+
+// Reductions; every result is FP64 and deterministic.
+// Number of partial slots a streaming reduction over n elements uses.
+int reduce_blocks(int64_t n_elems);
+// partials[z*nb + b] of sum x*y over n elements (batched; strides in elements)
+template <class T>
+hipError_t dot_partials(const T* x, int64_t sx, const T* y, int64_t sy, int64_t n, int batch,
+                        double* partials, hipStream_t s);
+// out[z * ostride + oidx] = sum of partials[z*count .. z*count+count)
+hipError_t sum_partials(const double* partials, int count, int batch, double* out,
+                        int ostride, int oidx, hipStream_t s);
+// out[z*ostride] = sum_i x[z][i*ld + i], i < N (trace, FP64 input);
+// aout[z*ostride] = sum_i |x_ii| when aout is not null
+hipError_t trace(const double* x, int64_t ld, int64_t sx, int64_t N, int batch, double* out,
+                 int ostride, double* aout, hipStream_t s);
+
+// CG updates (batched over right-hand sides z).
+//   update_xr: alpha = rr[z]/pq[z]; U += alpha P; R -= alpha Q; partials of <R,R>
+template <class T>
+hipError_t cg_update_xr(T* U, T* R, const T* P, const T* Q, int64_t n, int64_t stride, int batch,
+                        const double* rr, const double* pq, int hstride, const int* active,
+                        double* partials, hipStream_t s);
+//   update_p: beta = rr_new[z]/rr_old[z]; P = R + beta P (+ planes)
+template <class T>
+hipError_t cg_update_p(T* P, const T* R, int64_t n, int64_t stride, int batch,
+                       const double* rr_new, const double* rr_old, int hstride, const int* active,
+                       uint16_t* const* planes, int nplanes, hipStream_t s);
+// convergence: active[z] = rr[z] > tol^2 * ref[z]  (with iteration counter)
+hipError_t cg_check(const double* rr, const double* ref, int hstride, int batch, double tol2,
+                    int* active, int* iters, hipStream_t s);
+
+// Element-wise linear combination: y = a x + b y (batched, master only) + planes
+template <class T>
+hipError_t axpby(const T* x, int64_t sx, T* y, int64_t sy, int64_t n, int batch, double a,
+                 double b, uint16_t* const* planes, int64_t sp, int nplanes, hipStream_t s);
+
+// Fill identity-plus-scaled matrix: out = a I + b x (Np x Np, zero padding kept)
+template <class T>
+hipError_t scaled_plus_identity(const T* x, T* out, int64_t N, int64_t Np, double a, double b,
+                                uint16_t* const* planes, int nplanes, hipStream_t s);
+
+// p[0..n) = v and q[0..nq) = qv (n, nq <= 64); either pointer may be null with count 0
+hipError_t set_values(int* p, int v, int n, double* q, double qv, int nq, hipStream_t s);
+
+// Scan for non-finite values: flag |= any(!isfinite(x))
+hipError_t nonfinite_scan(const double* x, int64_t ld, int64_t N, int* flag, hipStream_t s);
+// Gershgorin interval of sym(H): out[0] = min_i (h_ii - r_i), out[1] = max_i (h_ii + r_i)
+hipError_t gershgorin(const double* h, int64_t N, double* out, hipStream_t s);
+// asymmetry max |x - x^T| and antisymmetric-part norm ||x - x^T||_F^2 partial
+hipError_t asym_max(const double* x, int64_t N, double* out_max, hipStream_t s);
+template <class T>
+hipError_t antisym_sq_partials(const T* x, int64_t ld, int64_t N, double* partials, hipStream_t s);
+
+}  // namespace dmpt

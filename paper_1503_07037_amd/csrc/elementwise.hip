@@ -1,0 +1,510 @@
+// Bandwidth-bound kernels of the DMPT path: symmetrised initialisation and
+// output, BF16 splitting, conjugate-gradient vector updates, and FP64
+// reductions (traces, Frobenius products) for the Newton update of the mu
+// jet (Algorithm 1) and the response observables (Eq. Resp_0).
+//
+// Reductions never use floating-point atomics: each block writes one FP64
+// partial and a second kernel sums a fixed-size partial array in a fixed
+// order, so every result is bitwise reproducible.
+#include "dmpt_internal.h"
+
+namespace dmpt {
+namespace {
+
+constexpr int kT = 256;
+constexpr int kMaxRedBlocks = 1024;
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over the block; the result is valid in thread 0.
+__device__ inline double block_sum(double v) {
+  __shared__ double red[kT / 64];
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
+  return s;
+}
+
+__device__ inline uint16_t bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ inline float bf16_to_f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+__device__ inline void split_store(float v, uint16_t* const* pl, int np, int64_t idx) {
+  float r = v;
+  for (int p = 0; p < np; ++p) {
+    const uint16_t h = bf16_rne(r);
+    pl[p][idx] = h;
+    r -= bf16_to_f(h);
+  }
+}
+
+struct Planes {
+  uint16_t* p[3];
+};
+
+// ------------------------------------------------------------ symmetrise
+// One block owns the tile pair (bi, bj) and (bj, bi), bi <= bj: both input
+// tiles are staged in LDS before either output tile is written, so the
+// kernel may run in place.  Reads and writes stay row-contiguous.
+template <class Tin, class Tout>
+__global__ __launch_bounds__(kT) void k_sym(const Tin* in, int64_t ldi, int64_t si, int64_t N,
+                                            int64_t Np, double a, const double* dshift,
+                                            int dstride, Tout* out, int64_t ldo, int64_t so,
+                                            Planes pl, int np, int64_t out_rows) {
+  __shared__ double ta[32][33], tb[32][33];
+  const int64_t bi = blockIdx.y, bj = blockIdx.x;
+  if (bi > bj) return;
+  const int z = blockIdx.z;
+  in += z * si;
+  out += z * so;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    int64_t gi = bi * 32 + r, gj = bj * 32 + tx;
+    ta[r][tx] = (gi < N && gj < N) ? (double)in[gi * ldi + gj] : 0.0;
+    gi = bj * 32 + r;
+    gj = bi * 32 + tx;
+    tb[r][tx] = (gi < N && gj < N) ? (double)in[gi * ldi + gj] : 0.0;
+  }
+  __syncthreads();
+  const double ds = dshift ? dshift[z * dstride] : 0.0;
+  uint16_t* p3[3] = {pl.p[0] ? pl.p[0] + z * so : nullptr, pl.p[1] ? pl.p[1] + z * so : nullptr,
+                     pl.p[2] ? pl.p[2] + z * so : nullptr};
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 1 && bi == bj) break;
+    const int64_t ti = pass ? bj : bi, tj = pass ? bi : bj;
+    for (int r = ty; r < 32; r += 8) {
+      const int64_t gi = ti * 32 + r, gj = tj * 32 + tx;
+      if (gi >= out_rows || gj >= out_rows) continue;
+      double v = 0.0;
+      if (gi < N && gj < N) {
+        // out(ti,tj)[r][tx] = a (in(ti,tj)[r][tx] + in(tj,ti)[tx][r])
+        v = pass ? a * (tb[r][tx] + ta[tx][r]) : a * (ta[r][tx] + tb[tx][r]);
+        if (gi == gj) v += ds;
+      }
+      const Tout o = (Tout)v;
+      out[gi * ldo + gj] = o;
+      if (np) split_store((float)o, p3, np, gi * ldo + gj);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kT) void k_split(const float* __restrict__ x, int64_t n, int64_t sx,
+                                              Planes pl, int64_t sp, int np) {
+  const int z = blockIdx.y;
+  x += z * sx;
+  uint16_t* p3[3] = {pl.p[0] ? pl.p[0] + z * sp : nullptr, pl.p[1] ? pl.p[1] + z * sp : nullptr,
+                     pl.p[2] ? pl.p[2] + z * sp : nullptr};
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
+    split_store(x[i], p3, np, i);
+}
+
+// ------------------------------------------------------------ reductions
+template <class T>
+__global__ __launch_bounds__(kT) void k_dot(const T* __restrict__ x, int64_t sx,
+                                            const T* __restrict__ y, int64_t sy, int64_t n,
+                                            double* partials) {
+  const int z = blockIdx.y;
+  x += z * sx;
+  y += z * sy;
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
+    s += (double)x[i] * (double)y[i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) partials[(int64_t)z * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kT) void k_sum_partials(const double* __restrict__ p, int count,
+                                                     double* out, int ostride, int oidx) {
+  const int z = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < count; i += kT) s += p[(int64_t)z * count + i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) out[z * ostride + oidx] = s;
+}
+
+__global__ __launch_bounds__(kT) void k_trace(const double* __restrict__ x, int64_t ld, int64_t sx,
+                                              int64_t N, double* out, int ostride, double* aout) {
+  const int z = blockIdx.x;
+  x += z * sx;
+  double s = 0.0, sa = 0.0;
+  for (int64_t i = threadIdx.x; i < N; i += kT) {
+    const double v = x[i * ld + i];
+    s += v;
+    sa += fabs(v);
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) out[z * ostride] = s;
+  if (aout) {
+    sa = block_sum(sa);
+    if (threadIdx.x == 0) aout[z * ostride] = sa;
+  }
+}
+
+// ------------------------------------------------------------ CG
+template <class T>
+__global__ __launch_bounds__(kT) void k_cg_xr(T* __restrict__ U, T* __restrict__ R,
+                                              const T* __restrict__ P, const T* __restrict__ Q,
+                                              int64_t n, int64_t stride, const double* rr,
+                                              const double* pq, int hstride, const int* active,
+                                              double* partials) {
+  const int z = blockIdx.y;
+  if (active && !active[z]) {
+    if (threadIdx.x == 0) partials[(int64_t)z * gridDim.x + blockIdx.x] = 0.0;
+    return;
+  }
+  const double den = pq[z * hstride];
+  const double alpha = den != 0.0 ? rr[z * hstride] / den : 0.0;
+  const T al = (T)alpha;
+  U += z * stride;
+  R += z * stride;
+  P += z * stride;
+  Q += z * stride;
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+    U[i] += al * P[i];
+    const T r = R[i] - al * Q[i];
+    R[i] = r;
+    s += (double)r * (double)r;
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) partials[(int64_t)z * gridDim.x + blockIdx.x] = s;
+}
+
+template <class T>
+__global__ __launch_bounds__(kT) void k_cg_p(T* __restrict__ P, const T* __restrict__ R, int64_t n,
+                                             int64_t stride, const double* rr_new,
+                                             const double* rr_old, int hstride, const int* active,
+                                             Planes pl, int np) {
+  const int z = blockIdx.y;
+  if (active && !active[z]) return;
+  const double ro = rr_old[z * hstride];
+  const double beta = ro != 0.0 ? rr_new[z * hstride] / ro : 0.0;
+  const T be = (T)beta;
+  P += z * stride;
+  R += z * stride;
+  uint16_t* p3[3] = {pl.p[0] ? pl.p[0] + z * stride : nullptr,
+                     pl.p[1] ? pl.p[1] + z * stride : nullptr,
+                     pl.p[2] ? pl.p[2] + z * stride : nullptr};
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+    const T p = R[i] + be * P[i];
+    P[i] = p;
+    if (np) split_store((float)p, p3, np, i);
+  }
+}
+
+__global__ void k_cg_check(const double* rr, const double* ref, int hstride, int batch,
+                           double tol2, int* active, int* iters) {
+  const int z = threadIdx.x;
+  if (z >= batch || !active[z]) return;
+  iters[z] += 1;
+  if (!(rr[z * hstride] > tol2 * ref[z])) active[z] = 0;
+}
+
+template <class T>
+__global__ __launch_bounds__(kT) void k_axpby(const T* __restrict__ x, int64_t sx, T* __restrict__ y,
+                                              int64_t sy, int64_t n, double a, double b, Planes pl,
+                                              int64_t sp, int np) {
+  const int z = blockIdx.y;
+  x += z * sx;
+  y += z * sy;
+  uint16_t* p3[3] = {pl.p[0] ? pl.p[0] + z * sp : nullptr, pl.p[1] ? pl.p[1] + z * sp : nullptr,
+                     pl.p[2] ? pl.p[2] + z * sp : nullptr};
+  const T ta = (T)a, tb = (T)b;
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+    const T v = ta * x[i] + tb * y[i];
+    y[i] = v;
+    if (np) split_store((float)v, p3, np, i);
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(kT) void k_spi(const T* __restrict__ x, T* __restrict__ out, int64_t N,
+                                            int64_t Np, double a, double b, Planes pl, int np) {
+  const int64_t n = Np * Np;
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+    const int64_t r = i / Np, c = i % Np;
+    double v = (b != 0.0) ? b * (double)x[i] : 0.0;
+    if (r == c && r < N) v += a;
+    const T o = (T)v;
+    out[i] = o;
+    if (np) split_store((float)o, pl.p, np, i);
+  }
+}
+
+__global__ __launch_bounds__(kT) void k_nonfinite(const double* __restrict__ x, int64_t ld, int64_t N,
+                                                  int* flag) {
+  int bad = 0;
+  const int64_t n = N * N;
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+    const double v = x[(i / N) * ld + (i % N)];
+    if (!isfinite(v)) bad = 1;
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+// Gershgorin bounds of sym(H): per row i, c_i = h_ii, r_i = sum_{j != i} |h_ij + h_ji|/2.
+__global__ __launch_bounds__(kT) void k_gersh_rows(const double* __restrict__ h, int64_t N,
+                                                   double* lo, double* hi) {
+  const int64_t i = blockIdx.x;
+  double s = 0.0;
+  for (int64_t j = threadIdx.x; j < N; j += kT)
+    if (j != i) s += fabs(0.5 * (h[i * N + j] + h[j * N + i]));
+  s = block_sum(s);
+  if (threadIdx.x == 0) {
+    const double c = h[i * N + i];
+    lo[i] = c - s;
+    hi[i] = c + s;
+  }
+}
+
+__global__ __launch_bounds__(kT) void k_minmax(const double* lo, const double* hi, int64_t N,
+                                               double* out) {
+  __shared__ double smin[kT], smax[kT];
+  double mn = 1e300, mx = -1e300;
+  for (int64_t i = threadIdx.x; i < N; i += kT) {
+    mn = fmin(mn, lo[i]);
+    mx = fmax(mx, hi[i]);
+  }
+  smin[threadIdx.x] = mn;
+  smax[threadIdx.x] = mx;
+  __syncthreads();
+  for (int o = kT / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + o]);
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = smin[0];
+    out[1] = smax[0];
+  }
+}
+
+__global__ __launch_bounds__(kT) void k_asym_max(const double* __restrict__ x, int64_t N, double* out) {
+  __shared__ double sm[kT];
+  double m = 0.0;
+  const int64_t n = N * N;
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+    const int64_t r = i / N, c = i % N;
+    m = fmax(m, fabs(x[r * N + c] - x[c * N + r]));
+  }
+  sm[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = kT / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = sm[0];
+}
+
+template <class T>
+__global__ __launch_bounds__(kT) void k_antisym_sq(const T* __restrict__ x, int64_t ld, int64_t N,
+                                                   double* partials) {
+  double s = 0.0;
+  const int64_t n = N * N;
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+    const int64_t r = i / N, c = i % N;
+    const double d = (double)x[r * ld + c] - (double)x[c * ld + r];
+    s += d * d;
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ void k_set(int* p, int v, int n, double* q, double qv, int nq) {
+  const int i = threadIdx.x;
+  if (i < n) p[i] = v;
+  if (i < nq) q[i] = qv;
+}
+
+inline unsigned red_grid(int64_t n) {
+  int64_t b = (n + kT * 8 - 1) / (kT * 8);
+  if (b < 1) b = 1;
+  if (b > kMaxRedBlocks) b = kMaxRedBlocks;
+  return (unsigned)b;
+}
+
+inline unsigned ew_grid(int64_t n) {
+  int64_t b = (n + kT * 4 - 1) / (kT * 4);
+  if (b < 1) b = 1;
+  if (b > 65535) b = 65535;
+  return (unsigned)b;
+}
+
+}  // namespace
+
+int reduce_blocks(int64_t n) { return (int)red_grid(n); }
+
+template <class Tin, class Tout>
+hipError_t sym_combine(const Tin* in, int64_t ldi, int64_t si, int64_t N, int64_t Np, double a,
+                       const double* dshift, int dstride, Tout* out, int64_t ldo, int64_t so,
+                       uint16_t* const* planes, int nplanes, int batch, hipStream_t s) {
+  Planes pl{{nullptr, nullptr, nullptr}};
+  for (int p = 0; p < nplanes; ++p) pl.p[p] = planes[p];
+  const int64_t rows = (ldo == N && ldo != Np) ? N : ldo;  // caller buffer: only N x N
+  const int64_t span = rows > N ? rows : N;
+  const unsigned nb = (unsigned)((span + 31) / 32);
+  hipLaunchKernelGGL((k_sym<Tin, Tout>), dim3(nb, nb, batch), dim3(kT), 0, s, in, ldi, si, N, Np, a,
+                     dshift, dstride, out, ldo, so, pl, nplanes, rows);
+  return hipGetLastError();
+}
+
+template hipError_t sym_combine<double, double>(const double*, int64_t, int64_t, int64_t, int64_t,
+                                                double, const double*, int, double*, int64_t,
+                                                int64_t, uint16_t* const*, int, int, hipStream_t);
+template hipError_t sym_combine<double, float>(const double*, int64_t, int64_t, int64_t, int64_t,
+                                               double, const double*, int, float*, int64_t, int64_t,
+                                               uint16_t* const*, int, int, hipStream_t);
+template hipError_t sym_combine<float, float>(const float*, int64_t, int64_t, int64_t, int64_t,
+                                              double, const double*, int, float*, int64_t, int64_t,
+                                              uint16_t* const*, int, int, hipStream_t);
+template hipError_t sym_combine<float, double>(const float*, int64_t, int64_t, int64_t, int64_t,
+                                               double, const double*, int, double*, int64_t,
+                                               int64_t, uint16_t* const*, int, int, hipStream_t);
+
+hipError_t split_planes(const float* x, int64_t n, int64_t sx, uint16_t* const* planes, int64_t sp,
+                        int nplanes, int batch, hipStream_t s) {
+  Planes pl{{nullptr, nullptr, nullptr}};
+  for (int p = 0; p < nplanes; ++p) pl.p[p] = planes[p];
+  hipLaunchKernelGGL(k_split, dim3(ew_grid(n), batch), dim3(kT), 0, s, x, n, sx, pl, sp, nplanes);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t dot_partials(const T* x, int64_t sx, const T* y, int64_t sy, int64_t n, int batch,
+                        double* partials, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot<T>, dim3(red_grid(n), batch), dim3(kT), 0, s, x, sx, y, sy, n, partials);
+  return hipGetLastError();
+}
+template hipError_t dot_partials<double>(const double*, int64_t, const double*, int64_t, int64_t,
+                                         int, double*, hipStream_t);
+template hipError_t dot_partials<float>(const float*, int64_t, const float*, int64_t, int64_t, int,
+                                        double*, hipStream_t);
+
+hipError_t sum_partials(const double* partials, int count, int batch, double* out, int ostride,
+                        int oidx, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_partials, dim3(batch), dim3(kT), 0, s, partials, count, out, ostride,
+                     oidx);
+  return hipGetLastError();
+}
+
+hipError_t trace(const double* x, int64_t ld, int64_t sx, int64_t N, int batch, double* out,
+                 int ostride, double* aout, hipStream_t s) {
+  hipLaunchKernelGGL(k_trace, dim3(batch), dim3(kT), 0, s, x, ld, sx, N, out, ostride, aout);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t cg_update_xr(T* U, T* R, const T* P, const T* Q, int64_t n, int64_t stride, int batch,
+                        const double* rr, const double* pq, int hstride, const int* active,
+                        double* partials, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_xr<T>, dim3(red_grid(n), batch), dim3(kT), 0, s, U, R, P, Q, n, stride,
+                     rr, pq, hstride, active, partials);
+  return hipGetLastError();
+}
+template hipError_t cg_update_xr<double>(double*, double*, const double*, const double*, int64_t,
+                                         int64_t, int, const double*, const double*, int,
+                                         const int*, double*, hipStream_t);
+template hipError_t cg_update_xr<float>(float*, float*, const float*, const float*, int64_t,
+                                        int64_t, int, const double*, const double*, int, const int*,
+                                        double*, hipStream_t);
+
+template <class T>
+hipError_t cg_update_p(T* P, const T* R, int64_t n, int64_t stride, int batch, const double* rr_new,
+                       const double* rr_old, int hstride, const int* active,
+                       uint16_t* const* planes, int nplanes, hipStream_t s) {
+  Planes pl{{nullptr, nullptr, nullptr}};
+  for (int p = 0; p < nplanes; ++p) pl.p[p] = planes[p];
+  hipLaunchKernelGGL(k_cg_p<T>, dim3(ew_grid(n), batch), dim3(kT), 0, s, P, R, n, stride, rr_new,
+                     rr_old, hstride, active, pl, nplanes);
+  return hipGetLastError();
+}
+template hipError_t cg_update_p<double>(double*, const double*, int64_t, int64_t, int,
+                                        const double*, const double*, int, const int*,
+                                        uint16_t* const*, int, hipStream_t);
+template hipError_t cg_update_p<float>(float*, const float*, int64_t, int64_t, int, const double*,
+                                       const double*, int, const int*, uint16_t* const*, int,
+                                       hipStream_t);
+
+hipError_t cg_check(const double* rr, const double* ref, int hstride, int batch, double tol2,
+                    int* active, int* iters, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(64), 0, s, rr, ref, hstride, batch, tol2, active,
+                     iters);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t axpby(const T* x, int64_t sx, T* y, int64_t sy, int64_t n, int batch, double a, double b,
+                 uint16_t* const* planes, int64_t sp, int nplanes, hipStream_t s) {
+  Planes pl{{nullptr, nullptr, nullptr}};
+  for (int p = 0; p < nplanes; ++p) pl.p[p] = planes[p];
+  hipLaunchKernelGGL(k_axpby<T>, dim3(ew_grid(n), batch), dim3(kT), 0, s, x, sx, y, sy, n, a, b, pl,
+                     sp, nplanes);
+  return hipGetLastError();
+}
+template hipError_t axpby<double>(const double*, int64_t, double*, int64_t, int64_t, int, double,
+                                  double, uint16_t* const*, int64_t, int, hipStream_t);
+template hipError_t axpby<float>(const float*, int64_t, float*, int64_t, int64_t, int, double,
+                                 double, uint16_t* const*, int64_t, int, hipStream_t);
+
+template <class T>
+hipError_t scaled_plus_identity(const T* x, T* out, int64_t N, int64_t Np, double a, double b,
+                                uint16_t* const* planes, int nplanes, hipStream_t s) {
+  Planes pl{{nullptr, nullptr, nullptr}};
+  for (int p = 0; p < nplanes; ++p) pl.p[p] = planes[p];
+  hipLaunchKernelGGL(k_spi<T>, dim3(ew_grid(Np * Np)), dim3(kT), 0, s, x, out, N, Np, a, b, pl,
+                     nplanes);
+  return hipGetLastError();
+}
+template hipError_t scaled_plus_identity<double>(const double*, double*, int64_t, int64_t, double,
+                                                 double, uint16_t* const*, int, hipStream_t);
+template hipError_t scaled_plus_identity<float>(const float*, float*, int64_t, int64_t, double,
+                                                double, uint16_t* const*, int, hipStream_t);
+
+hipError_t set_values(int* p, int v, int n, double* q, double qv, int nq, hipStream_t s) {
+  hipLaunchKernelGGL(k_set, dim3(1), dim3(64), 0, s, p, v, n, q, qv, nq);
+  return hipGetLastError();
+}
+
+hipError_t nonfinite_scan(const double* x, int64_t ld, int64_t N, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_nonfinite, dim3(red_grid(N * N)), dim3(kT), 0, s, x, ld, N, flag);
+  return hipGetLastError();
+}
+
+hipError_t gershgorin(const double* h, int64_t N, double* out, hipStream_t s) {
+  // out[0..1]: bounds; out[2 .. 2+2N): per-row scratch
+  double* lo = out + 2;
+  double* hi = out + 2 + N;
+  hipLaunchKernelGGL(k_gersh_rows, dim3((unsigned)N), dim3(kT), 0, s, h, N, lo, hi);
+  hipLaunchKernelGGL(k_minmax, dim3(1), dim3(kT), 0, s, lo, hi, N, out);
+  return hipGetLastError();
+}
+
+hipError_t asym_max(const double* x, int64_t N, double* out_max, hipStream_t s) {
+  // out_max[0..nb): per-block maxima (host reduces)
+  hipLaunchKernelGGL(k_asym_max, dim3(red_grid(N * N)), dim3(kT), 0, s, x, N, out_max);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t antisym_sq_partials(const T* x, int64_t ld, int64_t N, double* partials, hipStream_t s) {
+  hipLaunchKernelGGL(k_antisym_sq<T>, dim3(red_grid(N * N)), dim3(kT), 0, s, x, ld, N, partials);
+  return hipGetLastError();
+}
+template hipError_t antisym_sq_partials<double>(const double*, int64_t, int64_t, double*,
+                                                hipStream_t);
+template hipError_t antisym_sq_partials<float>(const float*, int64_t, int64_t, double*, hipStream_t);
+
+}  // namespace dmpt

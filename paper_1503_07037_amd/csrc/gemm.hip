@@ -1,0 +1,426 @@
+// Matrix-core (MFMA) products of the DMPT recursion on gfx950.
+//
+// Every product on the recursion path (Sec. II: D^2, the cross terms of the
+// perturbation jets, the right-hand sides of Algorithm 1's per-step systems
+// and the system-matrix products inside the linear solves) has the form
+//
+//     C = alpha * X * Y^T + beta1 * C1 + beta2 * C2,   Y symmetric in use,
+//
+// with X and Y stored row major, so both operands are read along contiguous
+// rows (k is the fast index of both).  Solves are run on transposed
+// unknowns (U = Y^T solves U T' = R^T with T' = T'^T), which keeps the
+// non-symmetric iterate on the X side; every Y operand on the path (D, S^(k),
+// T' factors) is symmetric, so X * Y^T = X * Y.
+//
+// Engines:
+//   F64     v_mfma_f64_16x16x4f64, FP64 accumulation
+//   F32     v_mfma_f32_32x32x2f32, FP32 accumulation
+//   BF16S2  x = x_hi + x_lo (BF16 splits): x_hi y_hi + x_hi y_lo + x_lo y_hi
+//   BF16S3  x = x_0 + x_1 + x_2: the six products x_p y_q with p + q <= 2
+//           (both BF16 engines use v_mfma_f32_32x32x16_bf16, FP32 accumulation)
+//
+// All engines: 128 x 128 output tile per 256-thread workgroup (four waves,
+// 64 x 64 each), K staged through LDS in a two-stage ring, operands
+// zero-padded to a multiple of 128 so no edge handling is needed.  The block
+// index is remapped so that the tiles of one XCD form a contiguous,
+// row-grouped range (better reuse of that XCD's L2).
+#include "dmpt_internal.h"
+
+namespace dmpt {
+namespace {
+
+typedef double d4v __attribute__((__vector_size__(4 * sizeof(double))));
+typedef float f16v __attribute__((__vector_size__(16 * sizeof(float))));
+typedef __bf16 bf8v __attribute__((__vector_size__(8 * sizeof(__bf16))));
+typedef unsigned int u4v __attribute__((__vector_size__(4 * sizeof(unsigned int))));
+
+constexpr int BM = 128, BN = 128;
+constexpr int kThreads = 256;
+constexpr int kGroupM = 8;   // tile rows per raster group
+constexpr int kXcd = 8;      // XCDs of an MI355X
+
+// Tile coordinates of a (possibly remapped) linear block index.
+__device__ inline void tile_coords(int b, int tiles_m, int tiles_n, int& tm, int& tn) {
+  const int T = tiles_m * tiles_n;
+  if (T % kXcd == 0) b = (b % kXcd) * (T / kXcd) + b / kXcd;
+  const int per_group = kGroupM * tiles_n;
+  const int g = b / per_group;
+  const int first = g * kGroupM;
+  const int gsz = min(tiles_m - first, kGroupM);
+  const int r = b % per_group;
+  tm = first + r % gsz;
+  tn = r / gsz;
+}
+
+__device__ inline double block_sum(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
+  }
+  return s;
+}
+
+// Round-to-nearest-even FP32 -> BF16 bits.
+__device__ inline uint16_t bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ inline float bf16_to_f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+// Write the BF16 slices of v to planes[0..np-1] at offset idx.
+__device__ inline void write_split(float v, uint16_t* const* pl, int np, int64_t idx) {
+  float r = v;
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    if (p < np) {
+      const uint16_t h = bf16_rne(r);
+      pl[p][idx] = h;
+      r -= bf16_to_f(h);
+    }
+  }
+}
+
+// Epilogue for one output element.
+template <class T>
+__device__ inline void epi(const GemmArgs& a, int z, int64_t off, double acc, double& dsum) {
+  double v = a.alpha * acc;
+  if (a.C1) v += a.beta1 * (double)((const T*)a.C1)[z * a.sC1 + off];
+  if (a.C2) v += a.beta2 * (double)((const T*)a.C2)[z * a.sC2 + off];
+  const T out = (T)v;
+  ((T*)a.C)[z * a.sC + off] = out;
+  if (a.Cpl[0]) {
+    uint16_t* pl[3] = {a.Cpl[0] ? a.Cpl[0] + z * a.sC : nullptr,
+                       a.Cpl[1] ? a.Cpl[1] + z * a.sC : nullptr,
+                       a.Cpl[2] ? a.Cpl[2] + z * a.sC : nullptr};
+    write_split((float)out, pl, a.Cpl[2] ? 3 : (a.Cpl[1] ? 2 : 1), off);
+  }
+  if (a.W) dsum += (double)((const T*)a.W)[z * a.sW + off] * (double)out;
+}
+
+// ------------------------------------------------------------------ FP64
+constexpr int F64_BK = 8, F64_LD = F64_BK + 1;
+
+__global__ __launch_bounds__(kThreads) void k_gemm_f64(GemmArgs a) {
+  const int z = blockIdx.z;
+  if (a.active && !a.active[z]) return;
+  const int64_t Np = a.Np;
+  int tm, tn;
+  tile_coords(blockIdx.x, (int)(Np / BM), (int)(Np / BN), tm, tn);
+  const double* X = (const double*)a.X.m + z * a.X.stride + (int64_t)tm * BM * Np;
+  const double* Y = (const double*)a.Y.m + z * a.Y.stride + (int64_t)tn * BN * Np;
+  __shared__ double sX[2][BM][F64_LD];
+  __shared__ double sY[2][BN][F64_LD];
+  __shared__ double red[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  // 128 rows x 8 doubles = 512 double2 per operand: two per thread
+  double2 rx[2], ry[2];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int idx = tid + i * kThreads, row = idx >> 2, q = idx & 3;
+      rx[i] = *(const double2*)(X + (int64_t)row * Np + k0 + 2 * q);
+      ry[i] = *(const double2*)(Y + (int64_t)row * Np + k0 + 2 * q);
+    }
+  };
+  auto swrite = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int idx = tid + i * kThreads, row = idx >> 2, q = idx & 3;
+      sX[buf][row][2 * q] = rx[i].x;
+      sX[buf][row][2 * q + 1] = rx[i].y;
+      sY[buf][row][2 * q] = ry[i].x;
+      sY[buf][row][2 * q + 1] = ry[i].y;
+    }
+  };
+  d4v acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = (d4v){0.0, 0.0, 0.0, 0.0};
+  gload(0);
+  swrite(0);
+  __syncthreads();
+  const int nk = (int)(Np / F64_BK);
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload((kt + 1) * F64_BK);
+#pragma unroll
+    for (int kk = 0; kk < F64_BK; kk += 4) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = sX[buf][wm * 64 + i * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = sY[buf][wn * 64 + j * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < nk) swrite(buf ^ 1);
+    __syncthreads();
+  }
+  double dsum = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = (int64_t)tm * BM + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
+        const int64_t col = (int64_t)tn * BN + wn * 64 + j * 16 + (lane & 15);
+        epi<double>(a, z, row * Np + col, acc[i][j][r], dsum);
+      }
+  if (a.W) {
+    const double s = block_sum(dsum, red);
+    if (tid == 0) a.partials[(int64_t)z * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+// ------------------------------------------------------------------ FP32
+constexpr int F32_BK = 16, F32_LD = F32_BK + 1;
+
+__global__ __launch_bounds__(kThreads) void k_gemm_f32(GemmArgs a) {
+  const int z = blockIdx.z;
+  if (a.active && !a.active[z]) return;
+  const int64_t Np = a.Np;
+  int tm, tn;
+  tile_coords(blockIdx.x, (int)(Np / BM), (int)(Np / BN), tm, tn);
+  const float* X = (const float*)a.X.m + z * a.X.stride + (int64_t)tm * BM * Np;
+  const float* Y = (const float*)a.Y.m + z * a.Y.stride + (int64_t)tn * BN * Np;
+  __shared__ float sX[2][BM][F32_LD];
+  __shared__ float sY[2][BN][F32_LD];
+  __shared__ double red[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  // 128 rows x 16 floats = 512 float4 per operand: two per thread
+  float4 rx[2], ry[2];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int idx = tid + i * kThreads, row = idx >> 2, q = idx & 3;
+      rx[i] = *(const float4*)(X + (int64_t)row * Np + k0 + 4 * q);
+      ry[i] = *(const float4*)(Y + (int64_t)row * Np + k0 + 4 * q);
+    }
+  };
+  auto swrite = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int idx = tid + i * kThreads, row = idx >> 2, q = idx & 3;
+      sX[buf][row][4 * q + 0] = rx[i].x;
+      sX[buf][row][4 * q + 1] = rx[i].y;
+      sX[buf][row][4 * q + 2] = rx[i].z;
+      sX[buf][row][4 * q + 3] = rx[i].w;
+      sY[buf][row][4 * q + 0] = ry[i].x;
+      sY[buf][row][4 * q + 1] = ry[i].y;
+      sY[buf][row][4 * q + 2] = ry[i].z;
+      sY[buf][row][4 * q + 3] = ry[i].w;
+    }
+  };
+  f16v acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+  gload(0);
+  swrite(0);
+  __syncthreads();
+  const int nk = (int)(Np / F32_BK);
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload((kt + 1) * F32_BK);
+#pragma unroll
+    for (int kk = 0; kk < F32_BK; kk += 2) {
+      float av[2], bv[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) av[i] = sX[buf][wm * 64 + i * 32 + (lane & 31)][kk + (lane >> 5)];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bv[j] = sY[buf][wn * 64 + j * 32 + (lane & 31)][kk + (lane >> 5)];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < nk) swrite(buf ^ 1);
+    __syncthreads();
+  }
+  double dsum = 0.0;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t row = (int64_t)tm * BM + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int64_t col = (int64_t)tn * BN + wn * 64 + j * 32 + (lane & 31);
+        epi<float>(a, z, row * Np + col, (double)acc[i][j][r], dsum);
+      }
+  if (a.W) {
+    const double s = block_sum(dsum, red);
+    if (tid == 0) a.partials[(int64_t)z * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+// ------------------------------------------------------------------ split BF16
+// LDS tile of one plane: 128 rows x 32 BF16 (64 B = four 16-byte chunks per
+// row).  Chunk c of row r is stored at chunk position c ^ ((r >> 1) & 3), so
+// the eight rows read by one group of eight lanes hit eight different
+// 16-byte bank groups.
+constexpr int B16_BK = 32;
+constexpr int kTileBytes = BM * B16_BK * 2;  // 8 KB per plane and operand
+
+__device__ inline int swz(int row, int c) { return row * 64 + ((c ^ ((row >> 1) & 3)) << 4); }
+
+template <int S>
+__global__ __launch_bounds__(kThreads) void k_gemm_bf16(GemmArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  __shared__ double red[4];
+  const int z = blockIdx.z;
+  if (a.active && !a.active[z]) return;
+  const int64_t Np = a.Np;
+  int tm, tn;
+  tile_coords(blockIdx.x, (int)(Np / BM), (int)(Np / BN), tm, tn);
+  const uint16_t* Xp[S];
+  const uint16_t* Yp[S];
+#pragma unroll
+  for (int p = 0; p < S; ++p) {
+    Xp[p] = a.X.pl[p] + z * a.X.stride + (int64_t)tm * BM * Np;
+    Yp[p] = a.Y.pl[p] + z * a.Y.stride + (int64_t)tn * BN * Np;
+  }
+  // stage layout: [stage][operand X/Y][plane] tiles of kTileBytes
+  auto tile = [&](int stage, int op, int p) -> unsigned char* {
+    return smem + ((stage * 2 + op) * S + p) * kTileBytes;
+  };
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  u4v rx[S][2], ry[S][2];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int p = 0; p < S; ++p)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int idx = tid + i * kThreads, row = idx >> 2, c = idx & 3;
+        rx[p][i] = *(const u4v*)(Xp[p] + (int64_t)row * Np + k0 + 8 * c);
+        ry[p][i] = *(const u4v*)(Yp[p] + (int64_t)row * Np + k0 + 8 * c);
+      }
+  };
+  auto swrite = [&](int stage) {
+#pragma unroll
+    for (int p = 0; p < S; ++p)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int idx = tid + i * kThreads, row = idx >> 2, c = idx & 3;
+        *(u4v*)(tile(stage, 0, p) + swz(row, c)) = rx[p][i];
+        *(u4v*)(tile(stage, 1, p) + swz(row, c)) = ry[p][i];
+      }
+  };
+  f16v acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+  gload(0);
+  swrite(0);
+  __syncthreads();
+  const int nk = (int)(Np / B16_BK);
+  for (int kt = 0; kt < nk; ++kt) {
+    const int st = kt & 1;
+    if (kt + 1 < nk) gload((kt + 1) * B16_BK);
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+      bf8v xa[S][2], yb[S][2];
+      const int c = kk * 2 + (lane >> 5);
+#pragma unroll
+      for (int p = 0; p < S; ++p) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const int row = wm * 64 + i * 32 + (lane & 31);
+          xa[p][i] = __builtin_bit_cast(bf8v, *(const u4v*)(tile(st, 0, p) + swz(row, c)));
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int row = wn * 64 + j * 32 + (lane & 31);
+          yb[p][j] = __builtin_bit_cast(bf8v, *(const u4v*)(tile(st, 1, p) + swz(row, c)));
+        }
+      }
+      // smallest terms first
+#pragma unroll
+      for (int t = S - 1; t >= 0; --t)          // t = p + q
+#pragma unroll
+        for (int p = 0; p <= t; ++p)
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa[p][i], yb[t - p][j], acc[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < nk) swrite(st ^ 1);
+    __syncthreads();
+  }
+  double dsum = 0.0;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t row = (int64_t)tm * BM + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int64_t col = (int64_t)tn * BN + wn * 64 + j * 32 + (lane & 31);
+        epi<float>(a, z, row * Np + col, (double)acc[i][j][r], dsum);
+      }
+  if (a.W) {
+    const double s = block_sum(dsum, red);
+    if (tid == 0) a.partials[(int64_t)z * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+template <int S>
+hipError_t launch_bf16(const GemmArgs& a, dim3 grid, hipStream_t s) {
+  const size_t lds = (size_t)2 * 2 * S * kTileBytes;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_gemm_bf16<S>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_gemm_bf16<S>, grid, dim3(kThreads), lds, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int gemm_tiles(Engine, int64_t Np) { return (int)((Np / BM) * (Np / BN)); }
+
+hipError_t gemm(const GemmArgs& a, hipStream_t s) {
+  if (a.Np <= 0 || a.Np % BM != 0 || a.batch <= 0) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)gemm_tiles(a.eng, a.Np), 1, (unsigned)a.batch);
+  switch (a.eng) {
+    case Engine::F64:
+      hipLaunchKernelGGL(k_gemm_f64, grid, dim3(kThreads), 0, s, a);
+      return hipGetLastError();
+    case Engine::F32:
+      hipLaunchKernelGGL(k_gemm_f32, grid, dim3(kThreads), 0, s, a);
+      return hipGetLastError();
+    case Engine::BF16S2:
+      return launch_bf16<2>(a, grid, s);
+    case Engine::BF16S3:
+      return launch_bf16<3>(a, grid, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace dmpt

@@ -1,0 +1,71 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry
+point include/dmpt.h declares, and rejects bad arguments before touching a
+device.  No compute call is made here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dmpt.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dmpt_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1503_07037_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return _lib.load()
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for n in ("dmpt_init", "dmpt_fermi_recursion", "dmpt_response", "dmpt_mu_newton",
+              "dmpt_backward", "dmpt_mu_newton_batched", "dmpt_finalize", "dmpt_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_default_options(lib):
+    from paper_1503_07037_amd import _lib as L
+    o = L.Options()
+    lib.dmpt_default_options(ctypes.byref(o))
+    assert o.prec == 0 and o.solver == 0 and o.max_newton == 50 and o.max_cg == 60
+    assert o.staged == 1 and o.ckpt_every == 5
+
+
+def test_null_context_is_rejected(lib):
+    from paper_1503_07037_amd import _lib as L
+    s = L.Stats()
+    assert lib.dmpt_fermi_recursion(None, 4, None, 1.0, 0.0, 10, None, ctypes.byref(s)) == L.DMPT_ERR_ARG
+    assert lib.dmpt_mu_newton(None, 4, None, 0, None, None, 1.0, 2.0, 10, 0, None, None, None, None,
+                              None) == L.DMPT_ERR_ARG
+    assert lib.dmpt_backward(None, 4, None, 1.0, 2.0, 10, None, None, None, None) == L.DMPT_ERR_ARG
+    assert lib.dmpt_finalize(None) == L.DMPT_OK
+    assert lib.dmpt_last_error(None)
+
+
+def test_init_argument_checks(lib):
+    from paper_1503_07037_amd import _lib as L
+    h = ctypes.c_void_p()
+    assert lib.dmpt_init(None, 0, 128, 1, None, None) == L.DMPT_ERR_ARG
+    assert lib.dmpt_init(ctypes.byref(h), 0, 0, 1, None, None) == L.DMPT_ERR_ARG
+    assert b"n_max" in lib.dmpt_last_error(None)
+    assert lib.dmpt_init(ctypes.byref(h), 0, 128, 99, None, None) == L.DMPT_ERR_ARG
+    o = L.Options()
+    lib.dmpt_default_options(ctypes.byref(o))
+    o.prec = 17
+    assert lib.dmpt_init(ctypes.byref(h), 0, 128, 1, ctypes.byref(o), None) == L.DMPT_ERR_ARG
+    assert not h.value

@@ -1,0 +1,185 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Bars: FP64 path <= 1e-10 (P0 absolute; P1, P2 normalised by max |P^(k)|
+of the oracle), FP32 / split-BF16 paths <= 1e-6 on the same measures.
+Sizes span several 128-wide tiles and ragged tails (N not a multiple of 128).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def dm():
+    import paper_1503_07037_amd as m
+    m.load()
+    return m
+
+
+def T(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=_dev())
+
+
+def errs(P0, P1, P2, ref):
+    e0 = float(np.abs(P0.cpu().numpy() - ref["P0"]).max())
+    e1 = [float(np.abs(p.cpu().numpy() - r).max() / max(np.abs(r).max(), 1e-300))
+          for p, r in zip(P1, ref["P1"])]
+    e2 = [float(np.abs(p.cpu().numpy() - r).max() / max(np.abs(r).max(), 1e-300))
+          for p, r in zip(P2, ref["P2"])]
+    return e0, max(e1, default=0.0), max(e2, default=0.0)
+
+
+def _sym(rng, n, s=1.0):
+    a = rng.standard_normal((n, n)) * s
+    return 0.5 * (a + a.T)
+
+
+# ------------------------------------------------------------------ grand canonical
+
+@pytest.mark.parametrize("N", [128, 200, 300])
+def test_fermi_recursion_fp64(dm, N):
+    print(f"case fermi_recursion fp64 N={N}", flush=True)
+    h0 = workloads.chain_1d(N, 7)
+    beta, n, mu = 10.0, 20, 0.05
+    ref = oracle.density(h0, beta, n, mu)
+    with dm.Context(N, dirs_max=0, prec="fp64") as ctx:
+        P0, st = ctx.fermi_recursion(T(h0), beta, mu, n)
+    assert float(np.abs(P0.cpu().numpy() - ref).max()) < 1e-12
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_response_at_fixed_mu_fp64(dm, order):
+    print(f"case response fp64 order={order}", flush=True)
+    N, n, beta = 160, 18, 8.0
+    rng = np.random.default_rng(3)
+    h0 = workloads.chain_1d(N, 3)
+    h1 = [np.diag(np.arange(N) - N / 2.0) / N, _sym(rng, N, 0.1)]
+    h2 = [_sym(rng, N, 0.05), None]
+    mu = [0.02, 0.3, -0.1, 0.05, 0.2][: 1 + order * 2]
+    mu_o = (mu[0], mu[1:3], mu[3:5] if order >= 2 else [0.0, 0.0])
+    ref = oracle.response(h0, h1, h2, beta, n, mu_o, order=order)
+    with dm.Context(N, dirs_max=2, prec="fp64") as ctx:
+        P0, P1, P2, st = ctx.response(T(h0), [T(h) for h in h1],
+                                      [T(h2[0]), None] if order >= 2 else None,
+                                      beta=beta, n=n, order=order, mu=mu)
+    e0, e1, e2 = errs(P0, P1, P2, ref)
+    assert e0 < 1e-12 and e1 < 1e-10 and e2 < 1e-10, (e0, e1, e2)
+
+
+# ------------------------------------------------------------------ canonical
+
+@pytest.fixture(scope="module")
+def chain128_ref():
+    c = workloads.config("chain128")
+    r = oracle.canonical_response(c["H0"], c["H1"], None, c["beta"], c["Ne"], c["n"], order=2)
+    return c, r
+
+
+def test_chain128_canonical_fp64(dm, chain128_ref):
+    print("case chain128 canonical fp64", flush=True)
+    c, ref = chain128_ref
+    with dm.Context(c["N"], dirs_max=1, prec="fp64") as ctx:
+        P0, P1, P2, mu, st = ctx.mu_newton(T(c["H0"]), [T(h) for h in c["H1"]], None,
+                                           beta=c["beta"], Ne=c["Ne"], n=c["n"], order=2)
+    e0, e1, e2 = errs(P0, P1, P2, ref)
+    print(f"  errs {e0:.2e} {e1:.2e} {e2:.2e} newton={st['newton_iters']} cg={st['cg_iters_total']}")
+    assert e0 < 1e-10 and e1 < 1e-10 and e2 < 1e-10
+    assert abs(mu[0] - ref["mu0"]) < 1e-10
+    assert abs(mu[1] - ref["mu1"][0]) < 1e-9 * max(1, abs(ref["mu1"][0]))
+    assert abs(mu[2] - ref["mu2"][0]) < 1e-9 * max(1, abs(ref["mu2"][0]))
+    assert abs(st["tr_h1p1"][0] - ref["tr_h1p1"][0]) < 1e-10 * abs(ref["tr_h1p1"][0])
+    assert abs(st["tr_h1p2"][0] - ref["tr_h1p2"][0]) < 1e-10 * abs(ref["tr_h1p2"][0])
+    assert abs(st["trP"][0] - c["Ne"]) < 1e-9
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-6), ("bf16x6", 1e-6), ("bf16x3", 3e-5)])
+def test_chain128_canonical_low_precision(dm, chain128_ref, prec, tol):
+    print(f"case chain128 canonical {prec}", flush=True)
+    c, ref = chain128_ref
+    with dm.Context(c["N"], dirs_max=1, prec=prec) as ctx:
+        P0, P1, P2, mu, st = ctx.mu_newton(T(c["H0"]), [T(h) for h in c["H1"]], None,
+                                           beta=c["beta"], Ne=c["Ne"], n=c["n"], order=2)
+    e0, e1, e2 = errs(P0, P1, P2, ref)
+    print(f"  errs {e0:.2e} {e1:.2e} {e2:.2e} newton={st['newton_iters']} cg={st['cg_iters_total']}")
+    assert e0 < tol and e1 < tol and e2 < tol
+
+
+@pytest.mark.parametrize("N,d", [(250, 3), (384, 2)])
+def test_ragged_multi_direction_fp64(dm, N, d):
+    """N not a multiple of the tile, several directions, non-zero H2."""
+    print(f"case ragged canonical fp64 N={N} d={d}", flush=True)
+    rng = np.random.default_rng(N)
+    h0 = workloads.banded(N, 9, bandwidth=24, decay=8.0)
+    grid = [np.arange(N) % 7 - 3.0, (np.arange(N) // 7) % 5 - 2.0, np.sin(np.arange(N))]
+    h1 = [np.diag(g) for g in grid][:d]
+    h2 = [_sym(rng, N, 0.02) if i == 0 else None for i in range(d)]
+    beta, n, Ne = 12.0, 22, N / 2.0 - 3.0
+    ref = oracle.canonical_response(h0, h1, h2, beta, Ne, n, order=2)
+    with dm.Context(N, dirs_max=d, prec="fp64") as ctx:
+        P0, P1, P2, mu, st = ctx.mu_newton(T(h0), [T(h) for h in h1],
+                                           [T(h) if h is not None else None for h in h2],
+                                           beta=beta, Ne=Ne, n=n, order=2)
+    e0, e1, e2 = errs(P0, P1, P2, ref)
+    print(f"  errs {e0:.2e} {e1:.2e} {e2:.2e}")
+    assert e0 < 1e-10 and e1 < 1e-10 and e2 < 1e-10
+    for z in range(d):
+        assert abs(st["tr_h2p0"][z] - ref["tr_h2p0"][z]) < 1e-10 * max(1, abs(ref["tr_h2p0"][z]))
+
+
+def test_single_site(dm):
+    """N = 1: P0 = Ne exactly, mu = H00 - (1/beta) log(1/Ne - 1) in the Fermi-Dirac limit."""
+    print("case single site", flush=True)
+    h0 = np.array([[0.3]])
+    with dm.Context(1, dirs_max=1, prec="fp64") as ctx:
+        P0, P1, P2, mu, st = ctx.mu_newton(T(h0), [T(np.array([[2.0]]))], None, beta=4.0, Ne=0.25,
+                                           n=30, order=2)
+    assert abs(P0.item() - 0.25) < 1e-12
+    assert abs(P1[0].item()) < 1e-12 and abs(P2[0].item()) < 1e-12
+    assert abs(mu[1] - 2.0) < 1e-10
+    assert abs(mu[0] - (0.3 - math.log(3.0) / 4.0)) < 1e-9
+
+
+# ------------------------------------------------------------------ failure paths
+
+def test_range_guard(dm):
+    print("case range guard", flush=True)
+    h0 = workloads.chain_1d(64, 1)
+    with dm.Context(64, dirs_max=0) as ctx:
+        with pytest.raises(dm.DMPTError) as ei:
+            ctx.fermi_recursion(T(h0), 1e6, 0.0, 4)
+    assert ei.value.status == -5
+
+
+def test_nonfinite_input(dm):
+    print("case nonfinite", flush=True)
+    h0 = workloads.chain_1d(64, 1)
+    h0[3, 5] = np.nan
+    with dm.Context(64, dirs_max=0) as ctx:
+        with pytest.raises(dm.DMPTError) as ei:
+            ctx.fermi_recursion(T(h0), 5.0, 0.0, 10)
+    assert ei.value.status == -6
+
+
+def test_newton_cap_reports_noconv(dm):
+    """Too few Newton passes: status NOCONV with the last pass's statistics filled."""
+    print("case noconv", flush=True)
+    h0 = workloads.chain_1d(64, 2)
+    with dm.Context(64, dirs_max=0, max_newton=1) as ctx:
+        P0, _, _, mu, st = ctx.mu_newton(T(h0), beta=10.0, Ne=20.0, n=20, order=0,
+                                         raise_on_error=False)
+    assert st["status"] == -4
+    assert st["newton_iters"] == 1 and math.isfinite(st["trP"][0])
