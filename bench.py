@@ -1,0 +1,167 @@
+#!/usr/bin/env python3
+"""Benchmark of the canonical DMPT hot path on one MI355X.
+
+Workload (default): the dense random-banded Hamiltonian, N = 8192 (bandwidth
+256, entries 0.3 g exp(-|i-j|/32), diagonal U(-2, 2)), Ne = 4096, beta = 40,
+n = 30 recursion steps, three diagonal dipole perturbations (x, y, z of a
+32 x 16 x 16 grid), orders 0-2 (polarisability and hyperpolarisability), the
+canonical Newton loop of Algorithm 1, split-BF16 (3-product) matrix products
+with FP32 accumulation.  Inputs are synthetic, seeded, already resident in
+HBM when the timed region starts.
+
+One step = one complete canonical solve (dmpt_mu_newton): every Newton pass,
+every recursion step, every order and direction.  value = response solves
+per second = directions / seconds per step.
+
+Printed: one JSON line with the metric, the roofline of the dominant kernel
+(the split-BF16 MFMA product kernel, timed with HIP events on the library's
+stream over the timed region), accuracy on the oracle's sampled entries, and
+the FP64 CPU oracle timed on a bounded sample on this host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAKS_TFLOPS = {"bf16x3": 2500.0, "bf16x6": 2500.0, "fp32": 157.3, "fp64": 78.6}
+DTYPE = {"bf16x3": "bf16", "bf16x6": "bf16", "fp32": "f32", "fp64": "f64"}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="banded8192", choices=["banded8192", "cubic2048", "chain128"])
+    ap.add_argument("--prec", default="bf16x3", choices=list(PEAKS_TFLOPS))
+    ap.add_argument("--n", type=int, default=0, help="shrink the banded workload to this N (testing)")
+    ap.add_argument("--cpu-sample-n", type=int, default=2048)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tol-cg", type=float, default=0.0)
+    ap.add_argument("--tol-occ", type=float, default=0.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(n_sample, n_full, dirs):
+    """The FP64 oracle on the same recipe at N = n_sample, scaled by (n_full/n_sample)^3."""
+    import numpy as np
+    import oracle
+    import workloads
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        threads = len(os.sched_getaffinity(0))
+    c = workloads.config("banded8192", n_override=n_sample)
+    h1v = [np.diag(h).copy() for h in c["H1"]]
+    t0 = time.perf_counter()
+    oracle.canonical_response(c["H0"], h1v, None, c["beta"], c["Ne"], c["n"], order=2)
+    t = time.perf_counter() - t0
+    scale = (n_full / n_sample) ** 3
+    return {
+        "value": dirs / (t * scale), "unit": "responses/s", "cores": threads, "kind": "oracle",
+        "sample": (f"FP64 oracle (eigh + Daleckii-Krein, orders 0-2, {dirs} directions) on the banded "
+                   f"recipe at N={n_sample}: {t:.2f} s, scaled by (N/{n_sample})^3 = {scale:.0f} to "
+                   f"N={n_full}"),
+    }
+
+
+def accuracy(name, P0, P1, P2, mu):
+    """Max errors on the oracle's stored samples (tests/golden/<name>_samples.npz)."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", f"{name}_samples.npz")
+    if not os.path.exists(path):
+        return None
+    g = np.load(path)
+    i = g["i"]
+    j = g["j"]
+    import torch
+    ii = torch.as_tensor(i, device=P0.device)
+    jj = torch.as_tensor(j, device=P0.device)
+    e0 = float(np.abs(P0[ii, jj].cpu().numpy() - g["P0"]).max())
+    e1 = max(float(np.abs(p[ii, jj].cpu().numpy() - g["P1"][z]).max() / g["max_P1"][z])
+             for z, p in enumerate(P1))
+    e2 = max(float(np.abs(p[ii, jj].cpu().numpy() - g["P2"][z]).max() / g["max_P2"][z])
+             for z, p in enumerate(P2))
+    return {"P0_maxabs": e0, "P1_maxabs_rel": e1, "P2_maxabs_rel": e2,
+            "mu0_err": abs(mu[0] - float(g["mu0"])), "samples": int(i.size)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sharded "
+              f"design is described in DESIGN.md and not built.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import workloads
+    import paper_1503_07037_amd as dm
+
+    dev = torch.device("cuda:0")
+    c = workloads.config(args.workload, n_override=args.n or None)
+    N, d = c["N"], len(c["H1"])
+    order = c["order"]
+    H0 = torch.tensor(c["H0"], device=dev)
+    H1 = [torch.tensor(h, device=dev) for h in c["H1"]]
+    torch.cuda.synchronize()
+    ctx = dm.Context(N, dirs_max=d, prec=args.prec, tol_cg=args.tol_cg, tol_occ=args.tol_occ)
+
+    def step():
+        return ctx.mu_newton(H0, H1, None, beta=c["beta"], Ne=c["Ne"], n=c["n"], order=order)
+
+    for w in range(args.warmup):
+        t0 = time.perf_counter()
+        out = step()
+        torch.cuda.synchronize()
+        print(f"warmup {w}: {time.perf_counter() - t0:.2f} s newton={out[4]['newton_iters']} "
+              f"cg={out[4]['cg_iters_total']}", file=sys.stderr, flush=True)
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        out = step()
+        print(f"step {s}: {time.perf_counter() - t0:.2f} s cumulative", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    prof = ctx.profile_get()
+    ctx.profile(False)
+    P0, P1, P2, mu, st = out
+    ms_step = 1e3 * secs / args.steps
+    value = d * args.steps / secs
+    avg_ms = prof["ms"] / max(prof["launches"], 1)
+    achieved = prof["mfma_flops"] / max(prof["ms"], 1e-12) / 1e9   # TFLOP/s
+    peak = PEAKS_TFLOPS[args.prec]
+    name = args.workload if not args.n else None
+    acc = accuracy(name, P0, P1, P2, mu) if name else None
+    res = {
+        "metric": "response solves/sec (P0+P1+P2) and MFMA TFLOP/s at N=8192, err <=1e-6 vs FP64",
+        "value": value, "unit": "responses/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[args.prec], "data": "synthetic",
+        "config": {"workload": f"{args.workload}: banded N={N}, d={d}, orders 0-{order}, "
+                               f"beta={c['beta']}, n={c['n']}, Ne={c['Ne']}" if args.workload == "banded8192"
+                   else args.workload,
+                   "N": N, "dirs": d, "order": order, "beta": c["beta"], "n": c["n"],
+                   "precision": args.prec, "parallelism": "single GPU"},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": f"split product kernel ({args.prec})", "launches": prof["launches"],
+                     "avg_launch_ms": avg_ms},
+        "mfma_tflops_whole_step": st["mfma_flops"] / (ms_step / 1e3) / 1e12,
+        "useful_tflops_whole_step": st["useful_flops"] / (ms_step / 1e3) / 1e12,
+        "newton_iters": st["newton_iters"], "cg_iters_total": st["cg_iters_total"],
+        "accuracy": acc,
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(min(args.cpu_sample_n, N), N, d)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -181,6 +181,23 @@ dmpt_status dmpt_backward(dmpt_ctx ctx, int64_t N, const double* H0, double beta
                           int n, const double* mu0, const double* Abar, double* G,
                           dmpt_stats* st);
 
+/* Device-time accounting of the matrix-product kernels (the MFMA engine of
+ * the context's precision).  dmpt_profile(ctx, 1) resets the totals and
+ * starts recording a pair of HIP events on the context stream around every
+ * product launch; dmpt_profile(ctx, 0) stops.  dmpt_profile_get
+ * synchronises the context stream, resolves the pending events and reports
+ * the totals since the last reset.  Intended for measurement; the events
+ * add a few microseconds per launch. */
+typedef struct {
+  int64_t launches;      /* product kernel launches timed */
+  double ms;             /* summed device time of those launches (ms) */
+  double mfma_flops;     /* matrix-core flops of those launches (every split product counted) */
+  double useful_flops;   /* 2 N^3 per logical product and batch member */
+} dmpt_profile_data;
+
+dmpt_status dmpt_profile(dmpt_ctx ctx, int enable);
+dmpt_status dmpt_profile_get(dmpt_ctx ctx, dmpt_profile_data* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -64,10 +64,15 @@ class Stats(ctypes.Structure):
             useful_flops=self.useful_flops, seconds=self.seconds)
 
 
+class ProfileData(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("mfma_flops", ctypes.c_double), ("useful_flops", ctypes.c_double)]
+
+
 EXPORTS = [
     "dmpt_default_options", "dmpt_init", "dmpt_finalize", "dmpt_last_error", "dmpt_set_options",
     "dmpt_fermi_recursion", "dmpt_response", "dmpt_mu_newton", "dmpt_mu_newton_batched",
-    "dmpt_backward",
+    "dmpt_backward", "dmpt_profile", "dmpt_profile_get",
 ]
 
 _lib = None
@@ -102,6 +107,8 @@ def load(path=None):
     lib.dmpt_mu_newton_batched.argtypes = [P, I, ctypes.POINTER(I64), PP, I, PP, DP, DP, I, I, DP,
                                            PP, PP, PP, ctypes.POINTER(Stats)]
     lib.dmpt_backward.argtypes = [P, I64, P, D, D, I, DP, P, P, ctypes.POINTER(Stats)]
+    lib.dmpt_profile.argtypes = [P, I]
+    lib.dmpt_profile_get.argtypes = [P, ctypes.POINTER(ProfileData)]
     for name in EXPORTS:
         if name not in ("dmpt_default_options", "dmpt_last_error"):
             getattr(lib, name).restype = ctypes.c_int

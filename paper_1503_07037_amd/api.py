@@ -111,6 +111,17 @@ class Context:
         torch = _torch()
         return torch.empty((n, n), dtype=torch.float64, device=f"cuda:{self.device}")
 
+    def profile(self, enable=True):
+        """Start (resetting the totals) or stop device timing of every product launch."""
+        self._raise(self.lib.dmpt_profile(self.h, 1 if enable else 0))
+
+    def profile_get(self):
+        """Totals since the last reset: launches, ms, mfma_flops, useful_flops."""
+        d = L.ProfileData()
+        self._raise(self.lib.dmpt_profile_get(self.h, ctypes.byref(d)))
+        return dict(launches=d.launches, ms=d.ms, mfma_flops=d.mfma_flops,
+                    useful_flops=d.useful_flops)
+
     # ------------------------------------------------------------------ calls
     def fermi_recursion(self, H0, beta, mu, n, out=None):
         """Grand-canonical P0 at fixed mu (Eq. Rec_F_2).  Returns (P0, stats)."""
@@ -137,6 +148,8 @@ class Context:
                     _check_mat(h, N, f"H2[{i}]")
             h2 = _ptr_array(list(H2))
         mu = [float(m) for m in mu]
+        if len(mu) < 1 + order * d:
+            raise ValueError(f"mu must hold 1 + order*d = {1 + order * d} values")
         P0 = self._empty(N)
         P1 = [self._empty(N) for _ in range(d)] if order >= 1 else []
         P2 = [self._empty(N) for _ in range(d)] if order >= 2 else []

@@ -27,9 +27,9 @@ inline int engine_terms(Engine e) {
   return e == Engine::BF16S2 ? 3 : (e == Engine::BF16S3 ? 6 : 1);
 }
 
-// A working matrix: master copy (double for F64, float otherwise) plus, for
-// the split-BF16 engines, its BF16 slices (plane p holds the p-th term of
-// x = sum_p bf16_p).  ld = Np.
+// A working matrix: master copy (float for the F32 engine, double for the
+// others) plus, for the split-BF16 engines, its BF16 slices (plane p holds
+// the p-th term of x ~ sum_p bf16_p).  ld = Np.
 struct Mat {
   void* m = nullptr;                 // master (double* or float*)
   uint16_t* pl[3] = {nullptr, nullptr, nullptr};
@@ -74,7 +74,7 @@ hipError_t sym_combine(const Tin* in, int64_t ldi, int64_t si, int64_t N, int64_
                        uint16_t* const* planes, int nplanes, int batch, hipStream_t s);
 
 // Split a master matrix into BF16 planes (batched).
-hipError_t split_planes(const float* x, int64_t n_elems, int64_t sx, uint16_t* const* planes,
+hipError_t split_planes(const double* x, int64_t n_elems, int64_t sx, uint16_t* const* planes,
                         int64_t sp, int nplanes, int batch, hipStream_t s);
 
 // Reductions; every result is FP64 and deterministic.

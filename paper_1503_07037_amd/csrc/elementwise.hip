@@ -40,12 +40,13 @@ __device__ inline uint16_t bf16_rne(float x) {
 }
 __device__ inline float bf16_to_f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
-__device__ inline void split_store(float v, uint16_t* const* pl, int np, int64_t idx) {
-  float r = v;
+// BF16 slices of v: slice p rounds what the earlier slices left (FP64 remainder).
+__device__ inline void split_store(double v, uint16_t* const* pl, int np, int64_t idx) {
+  double r = v;
   for (int p = 0; p < np; ++p) {
-    const uint16_t h = bf16_rne(r);
+    const uint16_t h = bf16_rne((float)r);
     pl[p][idx] = h;
-    r -= bf16_to_f(h);
+    r -= (double)bf16_to_f(h);
   }
 }
 
@@ -94,12 +95,12 @@ __global__ __launch_bounds__(kT) void k_sym(const Tin* in, int64_t ldi, int64_t 
       }
       const Tout o = (Tout)v;
       out[gi * ldo + gj] = o;
-      if (np) split_store((float)o, p3, np, gi * ldo + gj);
+      if (np) split_store((double)o, p3, np, gi * ldo + gj);
     }
   }
 }
 
-__global__ __launch_bounds__(kT) void k_split(const float* __restrict__ x, int64_t n, int64_t sx,
+__global__ __launch_bounds__(kT) void k_split(const double* __restrict__ x, int64_t n, int64_t sx,
                                               Planes pl, int64_t sp, int np) {
   const int z = blockIdx.y;
   x += z * sx;
@@ -199,7 +200,7 @@ __global__ __launch_bounds__(kT) void k_cg_p(T* __restrict__ P, const T* __restr
   for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
     const T p = R[i] + be * P[i];
     P[i] = p;
-    if (np) split_store((float)p, p3, np, i);
+    if (np) split_store((double)p, p3, np, i);
   }
 }
 
@@ -224,7 +225,7 @@ __global__ __launch_bounds__(kT) void k_axpby(const T* __restrict__ x, int64_t s
   for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
     const T v = ta * x[i] + tb * y[i];
     y[i] = v;
-    if (np) split_store((float)v, p3, np, i);
+    if (np) split_store((double)v, p3, np, i);
   }
 }
 
@@ -238,7 +239,7 @@ __global__ __launch_bounds__(kT) void k_spi(const T* __restrict__ x, T* __restri
     if (r == c && r < N) v += a;
     const T o = (T)v;
     out[i] = o;
-    if (np) split_store((float)o, pl.p, np, i);
+    if (np) split_store((double)o, pl.p, np, i);
   }
 }
 
@@ -374,7 +375,7 @@ template hipError_t sym_combine<float, double>(const float*, int64_t, int64_t, i
                                                double, const double*, int, double*, int64_t,
                                                int64_t, uint16_t* const*, int, int, hipStream_t);
 
-hipError_t split_planes(const float* x, int64_t n, int64_t sx, uint16_t* const* planes, int64_t sp,
+hipError_t split_planes(const double* x, int64_t n, int64_t sx, uint16_t* const* planes, int64_t sp,
                         int nplanes, int batch, hipStream_t s) {
   Planes pl{{nullptr, nullptr, nullptr}};
   for (int p = 0; p < nplanes; ++p) pl.p[p] = planes[p];

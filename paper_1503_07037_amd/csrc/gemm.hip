@@ -17,7 +17,8 @@
 //   F32     v_mfma_f32_32x32x2f32, FP32 accumulation
 //   BF16S2  x = x_hi + x_lo (BF16 splits): x_hi y_hi + x_hi y_lo + x_lo y_hi
 //   BF16S3  x = x_0 + x_1 + x_2: the six products x_p y_q with p + q <= 2
-//           (both BF16 engines use v_mfma_f32_32x32x16_bf16, FP32 accumulation)
+//           (both BF16 engines use v_mfma_f32_32x32x16_bf16, FP32 accumulation;
+//           their master copies, C1, C2, W and C are FP64)
 //
 // All engines: 128 x 128 output tile per 256-thread workgroup (four waves,
 // 64 x 64 each), K staged through LDS in a two-stage ring, operands
@@ -74,15 +75,17 @@ __device__ inline uint16_t bf16_rne(float x) {
 }
 __device__ inline float bf16_to_f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
-// Write the BF16 slices of v to planes[0..np-1] at offset idx.
-__device__ inline void write_split(float v, uint16_t* const* pl, int np, int64_t idx) {
-  float r = v;
+// Write the BF16 slices of v to planes[0..np-1] at offset idx: slice p is
+// the BF16 rounding of what the slices before it left over (the remainder is
+// exact in FP64, so three slices keep about 24 bits of v).
+__device__ inline void write_split(double v, uint16_t* const* pl, int np, int64_t idx) {
+  double r = v;
 #pragma unroll
   for (int p = 0; p < 3; ++p) {
     if (p < np) {
-      const uint16_t h = bf16_rne(r);
+      const uint16_t h = bf16_rne((float)r);
       pl[p][idx] = h;
-      r -= bf16_to_f(h);
+      r -= (double)bf16_to_f(h);
     }
   }
 }
@@ -99,7 +102,7 @@ __device__ inline void epi(const GemmArgs& a, int z, int64_t off, double acc, do
     uint16_t* pl[3] = {a.Cpl[0] ? a.Cpl[0] + z * a.sC : nullptr,
                        a.Cpl[1] ? a.Cpl[1] + z * a.sC : nullptr,
                        a.Cpl[2] ? a.Cpl[2] + z * a.sC : nullptr};
-    write_split((float)out, pl, a.Cpl[2] ? 3 : (a.Cpl[1] ? 2 : 1), off);
+    write_split((double)out, pl, a.Cpl[2] ? 3 : (a.Cpl[1] ? 2 : 1), off);
   }
   if (a.W) dsum += (double)((const T*)a.W)[z * a.sW + off] * (double)out;
 }
@@ -175,7 +178,8 @@ __global__ __launch_bounds__(kThreads) void k_gemm_f64(GemmArgs a) {
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = (int64_t)tm * BM + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
+        // v_mfma_f64_16x16x4f64 result: register r of lane l holds row 4r + l/16, column l%16
+        const int64_t row = (int64_t)tm * BM + wm * 64 + i * 16 + 4 * r + (lane >> 4);
         const int64_t col = (int64_t)tn * BN + wn * 64 + j * 16 + (lane & 15);
         epi<double>(a, z, row * Np + col, acc[i][j][r], dsum);
       }
@@ -379,7 +383,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(GemmArgs a) {
       for (int r = 0; r < 16; ++r) {
         const int64_t row = (int64_t)tm * BM + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         const int64_t col = (int64_t)tn * BN + wn * 64 + j * 32 + (lane & 31);
-        epi<float>(a, z, row * Np + col, (double)acc[i][j][r], dsum);
+        epi<double>(a, z, row * Np + col, (double)acc[i][j][r], dsum);
       }
   if (a.W) {
     const double s = block_sum(dsum, red);

@@ -106,11 +106,16 @@ def test_chain128_canonical_fp64(dm, chain128_ref):
     assert abs(st["trP"][0] - c["Ne"]) < 1e-9
 
 
-@pytest.mark.parametrize("prec,tol", [("fp32", 1e-6), ("bf16x6", 1e-6), ("bf16x3", 3e-5)])
-def test_chain128_canonical_low_precision(dm, chain128_ref, prec, tol):
-    print(f"case chain128 canonical {prec}", flush=True)
+@pytest.mark.parametrize("prec,extra,tol", [
+    ("fp32", {}, 3e-6),                # FP32 iterates: rounding floor of the 20-step chain
+    ("bf16x6", {}, 1e-6),              # 6-product split, FP64 iterates
+    ("bf16x3", {}, 5e-5),              # 3-product split alone
+    ("bf16x3", {"refine": 1}, 1e-6),   # 3-product passes, then the 6-product refinement
+])
+def test_chain128_canonical_low_precision(dm, chain128_ref, prec, extra, tol):
+    print(f"case chain128 canonical {prec} {extra}", flush=True)
     c, ref = chain128_ref
-    with dm.Context(c["N"], dirs_max=1, prec=prec) as ctx:
+    with dm.Context(c["N"], dirs_max=1, prec=prec, **extra) as ctx:
         P0, P1, P2, mu, st = ctx.mu_newton(T(c["H0"]), [T(h) for h in c["H1"]], None,
                                            beta=c["beta"], Ne=c["Ne"], n=c["n"], order=2)
     e0, e1, e2 = errs(P0, P1, P2, ref)

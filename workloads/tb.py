@@ -175,6 +175,7 @@ def config(name, n_override=None):
         x, y, z = grid_dipoles(n, grid)
         h1 = [np.diag(v) for v in (x, y, z)][: c["dirs"]]
         c["N"] = n
+        c["Ne"] = n / 2.0
     else:
         raise ValueError("batched workload: use batched_systems()")
     c.update(H0=h0, H1=h1, H2=[None] * len(h1))
