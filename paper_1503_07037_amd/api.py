@@ -199,6 +199,50 @@ class Context:
             self._raise(st, stats)
         return P0, P1, P2, list(mu_arr), stats
 
+    def mu_newton_batched(self, H0s, H1s=None, betas=(), Nes=(), n=20, order=0, mus=None,
+                          raise_on_error=True):
+        """Canonical responses of many systems of uneven size in one batched solve.
+
+        H0s: list of (N_s, N_s) tensors; H1s: list (per system) of d tensors;
+        betas, Nes: per system.  Returns (P0s, P1s, P2s, mus, stats) with P1s and
+        P2s lists of per-system lists and mus a list of jets (1 + 2d values).
+        """
+        nsys = len(H0s)
+        d = len(H1s[0]) if (order >= 1 and H1s) else 0
+        J = 1 + 2 * d
+        Ns = (ctypes.c_int64 * nsys)(*[h.shape[0] for h in H0s])
+        for s_, h in enumerate(H0s):
+            _check_mat(h, h.shape[0], f"H0s[{s_}]")
+        flat_h1 = []
+        for s_ in range(nsys):
+            for z in range(d):
+                _check_mat(H1s[s_][z], H0s[s_].shape[0], f"H1s[{s_}][{z}]")
+                flat_h1.append(H1s[s_][z])
+        P0 = [self._empty(h.shape[0]) for h in H0s]
+        P1 = [[self._empty(h.shape[0]) for _ in range(d)] for h in H0s] if order >= 1 else []
+        P2 = [[self._empty(h.shape[0]) for _ in range(d)] for h in H0s] if order >= 2 else []
+        m = [math.nan] * (nsys * J)
+        if mus is not None:
+            for s_, jet in enumerate(mus):
+                for j, v in enumerate(jet[:J]):
+                    m[s_ * J + j] = float(v)
+        mu_arr = (ctypes.c_double * (nsys * J))(*m)
+        b_arr = (ctypes.c_double * nsys)(*[float(b) for b in betas])
+        ne_arr = (ctypes.c_double * nsys)(*[float(x) for x in Nes])
+        st_ = L.Stats()
+        flat_p1 = [p for row in P1 for p in row]
+        flat_p2 = [p for row in P2 for p in row]
+        st = self.lib.dmpt_mu_newton_batched(
+            self.h, nsys, Ns, _ptr_array(list(H0s)), d, _ptr_array(flat_h1) if d else None, b_arr,
+            ne_arr, int(n), int(order), mu_arr, _ptr_array(P0), _ptr_array(flat_p1) if d else None,
+            _ptr_array(flat_p2) if flat_p2 else None, ctypes.byref(st_))
+        stats = st_.as_dict()
+        stats["status"] = st
+        if raise_on_error:
+            self._raise(st, stats)
+        jets = [list(mu_arr[s_ * J:(s_ + 1) * J]) for s_ in range(nsys)]
+        return P0, P1, P2, jets, stats
+
     def backward(self, H0, beta, Ne, n, Abar, mu0=None):
         """Adjoint G = d Tr(Abar P0)/d H0 of the canonical map.  Returns (G, stats)."""
         N = H0.shape[0]

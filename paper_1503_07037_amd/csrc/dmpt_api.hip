@@ -34,6 +34,20 @@ struct Group {
   int count = 0;
 };
 
+// The matrices and solver scalars one recursion pass works on.  Members of
+// the per-direction groups are laid out [system][direction]; the single
+// system entry points use one system.
+struct WS {
+  Group D0, D1, D2, S0, S1, S2, R, P, Q;
+  double* rr = nullptr;          // CG <r,r> history [member][hstride]
+  double* pq = nullptr;          // CG <p,Tp> history [member][hstride]
+  double* ref = nullptr;         // ||rhs||^2 [member]
+  int* active = nullptr;         // CG masks [member]
+  int* iters = nullptr;          // CG iteration counters [member]
+  int* mask0 = nullptr;          // system mask (order-0 members), batched passes only
+  int* mask1 = nullptr;          // system mask expanded to [system][direction] members
+};
+
 }  // namespace
 
 struct dmpt_ctx_s {
@@ -46,15 +60,17 @@ struct dmpt_ctx_s {
   size_t esize = 8;              // master element size of the workspace
   int planes = 0;                // BF16 planes per operand allocated
   std::vector<void*> allocs;
-  // matrix groups
-  Group D0, D1, D2, S0, S1, S2, R, P, Q;
+  // matrix groups and solver scalars of the single-system entry points
+  WS ws;
+  // adjoint workspace, allocated by the first dmpt_backward that needs it:
+  // seeds AY, CG unknowns AU, transposes AW, products AV, AG, the iterate
+  // D_m (AD), checkpoints CK and the recomputed segment SG
+  Group AY, AU, AW, AV, AG, AD, CK, SG;
+  std::vector<void*> ad_allocs;
+  // larger partial-sum blocks allocated by batched calls
+  std::vector<void*> bt_allocs;
   // scalars
   int hstride = 0;               // CG history length per right-hand side
-  double* d_rr = nullptr;        // [dirs][hstride]
-  double* d_pq = nullptr;        // [dirs][hstride]
-  double* d_ref = nullptr;       // [dirs]
-  int* d_active = nullptr;       // [dirs]
-  int* d_iters = nullptr;        // [dirs]
   int* d_flag = nullptr;         // non-finite flag
   double* d_res = nullptr;       // results block (traces etc.)
   double* d_part = nullptr;      // partials
@@ -157,12 +173,16 @@ size_t esize_needed(const dmpt_options& o) { return o.prec == DMPT_FP32 ? 4 : 8;
 // ------------------------------------------------------------------ views
 struct Call {
   dmpt_ctx c;
+  const WS* w;                   // matrices and scalars of this pass
   Engine eng;
   int np;                        // planes used by the engine
   int64_t N, Np, nn;             // nn = Np*Np
   int64_t stride;                // member stride of every group (elements)
   bool f64;                      // FP64 master copies
   double tol_cg;                 // relative residual of every solve of this pass
+  int m = 1;                     // systems in the pass (members of D0, S0)
+  bool graph = false;            // no host synchronisation: fixed CG iteration counts
+  int cg_iters = 0;              // iterations per solve when graph is set
 };
 
 // Member z of a group as an operand.
@@ -293,10 +313,16 @@ dmpt_status sym_to(const Call& k, const Group& in, const Group& out, int batch, 
 // Conjugate gradients on the transposed unknowns U (U T' = R^T, see gemm.hip):
 //   U (group `u`, members z = 0..batch-1) holds the initial guess and
 //   receives the solution; R holds the initial residual, whose squared norm
-//   is in d_rr[z][0]; d_ref[z] holds ||rhs||^2.
+//   is in rr[z][0]; ref[z] holds ||rhs||^2.  S0 member z / ydiv is the
+//   system matrix factor of member z.  `mask` (or all ones) seeds the
+//   per-member activity.  Without k.graph the host checks the masks after
+//   every iteration and stops when all members converged; with k.graph a
+//   fixed k.cg_iters iterations are queued and converged members skip their
+//   work on the device.
 template <class T>
-dmpt_status cg_solve(const Call& k, const Group& u, int batch) {
+dmpt_status cg_solve(const Call& k, const Group& u, int batch, int ydiv, const int* mask) {
   dmpt_ctx c = k.c;
+  const WS* w = k.w;
   hipStream_t s = c->stream;
   const int hs = c->hstride;
   const double tol = k.tol_cg;
@@ -304,55 +330,57 @@ dmpt_status cg_solve(const Call& k, const Group& u, int batch) {
   // P = R (with planes)
   {
     uint16_t* pl[3];
-    planes_of(k, c->P, 0, pl);
-    HIPCHK(c, axpby<T>((const T*)mptr(k, c->R, 0), k.stride, (T*)mptr(k, c->P, 0), k.stride, n,
+    planes_of(k, w->P, 0, pl);
+    HIPCHK(c, axpby<T>((const T*)mptr(k, w->R, 0), k.stride, (T*)mptr(k, w->P, 0), k.stride, n,
                        batch, 1.0, 0.0, pl, k.stride, k.np, s));
   }
-  // active[z] = 1; iters = 0; then the check against the initial residual
-  HIPCHK(c, set_values(c->d_active, 1, batch, nullptr, 0.0, 0, s));
-  HIPCHK(c, set_values(c->d_iters, 0, batch, nullptr, 0.0, 0, s));
-  HIPCHK(c, cg_check(c->d_rr, c->d_ref, hs, batch, tol * tol, c->d_active, c->d_iters, s));
+  if (mask) HIPCHK(c, expand_mask(mask, 1, w->active, batch, s));
+  else HIPCHK(c, set_values(w->active, 1, batch, nullptr, 0.0, 0, s));
+  HIPCHK(c, set_values(w->iters, 0, batch, nullptr, 0.0, 0, s));
+  HIPCHK(c, cg_check(w->rr, w->ref, hs, batch, tol * tol, w->active, w->iters, s));
   const int red_nb = reduce_blocks(n);
-  int it = 0;
-  for (; it < c->opt.max_cg; ++it) {
-    // which members are still active?
-    HIPCHK(c, hipMemcpyAsync(c->h_int, c->d_active, batch * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
-    bool any = false;
-    for (int z = 0; z < batch; ++z) any |= c->h_int[z] != 0;
-    if (!any) break;
-    if (it + 1 >= hs) break;
+  const int cap = k.graph ? std::min(k.cg_iters, c->opt.max_cg) : c->opt.max_cg;
+  for (int it = 0; it < cap && it + 1 < hs; ++it) {
+    if (!k.graph) {
+      HIPCHK(c, hipMemcpyAsync(c->h_int, w->active, batch * sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipStreamSynchronize(s));
+      bool any = false;
+      for (int z = 0; z < batch; ++z) any |= c->h_int[z] != 0;
+      if (!any) break;
+    }
     // Q = P + 4 P S0  (T' applied on the right), partials of <P, Q>
     G g;
-    g.X = op(k, c->P, 0, true);
-    g.Y = op(k, c->S0, 0, false);
-    g.C = mptr(k, c->Q, 0);
+    g.X = op(k, w->P, 0, true);
+    g.Y = op(k, w->S0, 0, true);
+    g.Y.div = ydiv;
+    g.C = mptr(k, w->Q, 0);
     g.sC = k.stride;
     g.alpha = 4.0;
-    g.C1 = mptr(k, c->P, 0); g.sC1 = k.stride; g.beta1 = 1.0;
-    g.W = mptr(k, c->P, 0); g.sW = k.stride;
+    g.C1 = mptr(k, w->P, 0); g.sC1 = k.stride; g.beta1 = 1.0;
+    g.W = mptr(k, w->P, 0); g.sW = k.stride;
     g.batch = batch;
-    g.active = c->d_active;
+    g.active = w->active;
     STCHK(run_gemm(k, g));
-    STCHK(sum_gemm_partials(k, batch, c->d_pq + it, hs, 0));
-    HIPCHK(c, cg_update_xr<T>((T*)mptr(k, u, 0), (T*)mptr(k, c->R, 0), (const T*)mptr(k, c->P, 0),
-                              (const T*)mptr(k, c->Q, 0), n, k.stride, batch, c->d_rr + it,
-                              c->d_pq + it, hs, c->d_active, c->d_part, s));
-    HIPCHK(c, sum_partials(c->d_part, red_nb, batch, c->d_rr + it + 1, hs, 0, s));
+    STCHK(sum_gemm_partials(k, batch, w->pq + it, hs, 0));
+    HIPCHK(c, cg_update_xr<T>((T*)mptr(k, u, 0), (T*)mptr(k, w->R, 0), (const T*)mptr(k, w->P, 0),
+                              (const T*)mptr(k, w->Q, 0), n, k.stride, batch, w->rr + it,
+                              w->pq + it, hs, w->active, c->d_part, s));
+    HIPCHK(c, sum_partials(c->d_part, red_nb, batch, w->rr + it + 1, hs, 0, s));
     {
       uint16_t* pl[3];
-      planes_of(k, c->P, 0, pl);
-      HIPCHK(c, cg_update_p<T>((T*)mptr(k, c->P, 0), (const T*)mptr(k, c->R, 0), n, k.stride, batch,
-                               c->d_rr + it + 1, c->d_rr + it, hs, c->d_active, pl, k.np, s));
+      planes_of(k, w->P, 0, pl);
+      HIPCHK(c, cg_update_p<T>((T*)mptr(k, w->P, 0), (const T*)mptr(k, w->R, 0), n, k.stride, batch,
+                               w->rr + it + 1, w->rr + it, hs, w->active, pl, k.np, s));
     }
-    HIPCHK(c, cg_check(c->d_rr + it + 1, c->d_ref, hs, batch, tol * tol, c->d_active, c->d_iters, s));
+    HIPCHK(c, cg_check(w->rr + it + 1, w->ref, hs, batch, tol * tol, w->active, w->iters, s));
   }
-  HIPCHK(c, hipMemcpyAsync(c->h_int, c->d_active, batch * sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(c, hipMemcpyAsync(c->h_int + DMPT_MAX_DIRS, c->d_iters, batch * sizeof(int),
+  if (k.graph) return DMPT_OK;  // counters are read by the caller after the pass
+  HIPCHK(c, hipMemcpyAsync(c->h_int, w->active, batch * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(c->h_int + DMPT_MAX_DIRS, w->iters, batch * sizeof(int),
                            hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
   for (int z = 0; z < batch; ++z) {
-    // d_iters counts the initial check too
+    // iters counts the initial check too
     const int its = std::max(0, c->h_int[DMPT_MAX_DIRS + z] - 1);
     c->cg_total += its;
     c->cg_max = std::max(c->cg_max, its);
@@ -377,6 +405,7 @@ struct PassIn {
 template <class T>
 dmpt_status init_d(const Call& k, const PassIn& in, double cscale) {
   dmpt_ctx c = k.c;
+  const WS* w = k.w;
   hipStream_t s = c->stream;
   auto one = [&](const double* h, const Group& g, int z, double mu) -> dmpt_status {
     uint16_t* pl[3];
@@ -392,151 +421,191 @@ dmpt_status init_d(const Call& k, const PassIn& in, double cscale) {
     }
     return DMPT_OK;
   };
-  STCHK(one(in.H0, c->D0, 0, in.mu[0]));
+  STCHK(one(in.H0, w->D0, 0, in.mu[0]));
   if (in.order >= 1)
-    for (int z = 0; z < in.d; ++z) STCHK(one(in.H1[z], c->D1, z, in.mu[1 + z]));
+    for (int z = 0; z < in.d; ++z) STCHK(one(in.H1[z], w->D1, z, in.mu[1 + z]));
   if (in.order >= 2)
     for (int z = 0; z < in.d; ++z)
-      STCHK(one(in.H2 ? in.H2[z] : nullptr, c->D2, z, in.mu[1 + in.d + z]));
+      STCHK(one(in.H2 ? in.H2[z] : nullptr, w->D2, z, in.mu[1 + in.d + z]));
   return DMPT_OK;
 }
 
-// One full pass of the recursion for orders 0..order.
+// S0 = D0^2 for every system of the pass.
+template <class T>
+dmpt_status square0(const Call& k) {
+  const WS* w = k.w;
+  G g;
+  g.X = op(k, w->D0, 0, true);
+  g.Y = op(k, w->D0, 0, true);
+  g.C = mptr(k, w->S0, 0);
+  g.sC = k.stride;
+  planes_of(k, w->S0, 0, g.Cpl);
+  g.batch = k.m;
+  g.active = w->mask0;
+  return run_gemm(k, g);
+}
+
+// Order 0 of one recursion step: T' Y0 = 2 D0 with S0 = D0^2 already formed;
+// the previous iterate D0 is the initial guess and D0 is overwritten by the
+// symmetrised solution.
+template <class T>
+dmpt_status solve_order0(const Call& k) {
+  dmpt_ctx c = k.c;
+  const WS* w = k.w;
+  hipStream_t s = c->stream;
+  const int hs = c->hstride;
+  uint16_t* pl[3] = {nullptr, nullptr, nullptr};
+  // ||rhs||^2 = 4 ||D0||^2
+  HIPCHK(c, dot_partials<T>((const T*)mptr(k, w->D0, 0), k.stride, (const T*)mptr(k, w->D0, 0),
+                            k.stride, k.nn, k.m, c->d_part, s));
+  HIPCHK(c, sum_partials(c->d_part, reduce_blocks(k.nn), k.m, w->ref, 1, 0, s));
+  HIPCHK(c, axpby<double>(w->ref, 0, w->ref, 0, k.m, 1, 0.0, 4.0, pl, 0, 0, s));
+  // R = 2 D0 - D0 - 4 D0 S0 = D0 - 4 D0 S0, with ||R||^2 -> rr[0]
+  G g;
+  g.X = op(k, w->D0, 0, true);
+  g.Y = op(k, w->S0, 0, true);
+  g.C = mptr(k, w->R, 0);
+  g.sC = k.stride;
+  g.alpha = -4.0;
+  g.C1 = mptr(k, w->D0, 0); g.sC1 = k.stride; g.beta1 = 1.0;
+  g.W = mptr(k, w->R, 0); g.sW = k.stride;
+  g.batch = k.m;
+  g.active = w->mask0;
+  STCHK(run_gemm(k, g));
+  STCHK(sum_gemm_partials(k, k.m, w->rr, hs, 0));
+  STCHK(cg_solve<T>(k, w->D0, k.m, 1, w->mask0));
+  STCHK(sym_inplace<T>(k, w->D0, 0, k.m, 0.5));
+  return DMPT_OK;
+}
+
+// One recursion step for orders 0..order, d directions per system, on the
+// iterates held in k.w (Algorithm 1's inner loop body, in D form).
+template <class T>
+dmpt_status recursion_step(const Call& k, int order, int d) {
+  const WS* w = k.w;
+  const int hs = k.c->hstride;
+  const int md = k.m * d;
+  STCHK(square0<T>(k));
+  if (order >= 1) {
+    // Q = D1 D0 -> S1 = Q + Q^T
+    G g;
+    g.X = op(k, w->D1, 0, true);
+    g.Y = op(k, w->D0, 0, true);
+    g.Y.div = d;
+    g.C = mptr(k, w->Q, 0);
+    g.sC = k.stride;
+    g.batch = md;
+    g.active = w->mask1;
+    STCHK(run_gemm(k, g));
+    STCHK(sym_to<T>(k, w->Q, w->S1, md, true));
+  }
+  if (order >= 2) {
+    // Q = D2 D0 -> S2 = Q + Q^T; S2 += D1 D1
+    G g;
+    g.X = op(k, w->D2, 0, true);
+    g.Y = op(k, w->D0, 0, true);
+    g.Y.div = d;
+    g.C = mptr(k, w->Q, 0);
+    g.sC = k.stride;
+    g.batch = md;
+    g.active = w->mask1;
+    STCHK(run_gemm(k, g));
+    STCHK(sym_to<T>(k, w->Q, w->S2, md, false));
+    G h;
+    h.X = op(k, w->D1, 0, true);
+    h.Y = op(k, w->D1, 0, true);
+    h.C = mptr(k, w->S2, 0);
+    h.sC = k.stride;
+    planes_of(k, w->S2, 0, h.Cpl);
+    h.C1 = mptr(k, w->S2, 0); h.sC1 = k.stride; h.beta1 = 1.0;
+    h.batch = md;
+    h.active = w->mask1;
+    STCHK(run_gemm(k, h));
+  }
+  STCHK(solve_order0<T>(k));
+  // ---- order 1: T' Y1 = 2 D1 - 4 S1 Y0; transposed: rhs^T = 2 D1 - 4 Y0 S1
+  if (order >= 1) {
+    G g;  // R = 2 D1 - 4 Y0 S1   (Y0 = new D0), ||rhs||^2 -> ref
+    g.X = op(k, w->D0, 0, true);
+    g.X.div = d;
+    g.Y = op(k, w->S1, 0, true);
+    g.C = mptr(k, w->R, 0);
+    g.sC = k.stride;
+    g.alpha = -4.0;
+    g.C1 = mptr(k, w->D1, 0); g.sC1 = k.stride; g.beta1 = 2.0;
+    g.W = mptr(k, w->R, 0); g.sW = k.stride;
+    g.batch = md;
+    g.active = w->mask1;
+    STCHK(run_gemm(k, g));
+    STCHK(sum_gemm_partials(k, md, w->ref, 1, 0));
+    G h;  // R -= D1 + 4 D1 S0  (guess U = D1)
+    h.X = op(k, w->D1, 0, true);
+    h.Y = op(k, w->S0, 0, true);
+    h.Y.div = d;
+    h.C = mptr(k, w->R, 0);
+    h.sC = k.stride;
+    h.alpha = -4.0;
+    h.C1 = mptr(k, w->R, 0); h.sC1 = k.stride; h.beta1 = 1.0;
+    h.C2 = mptr(k, w->D1, 0); h.sC2 = k.stride; h.beta2 = -1.0;
+    h.W = mptr(k, w->R, 0); h.sW = k.stride;
+    h.batch = md;
+    h.active = w->mask1;
+    STCHK(run_gemm(k, h));
+    STCHK(sum_gemm_partials(k, md, w->rr, hs, 0));
+    STCHK(cg_solve<T>(k, w->D1, md, d, w->mask1));
+    STCHK(sym_inplace<T>(k, w->D1, 0, md, 0.5));
+  }
+  // ---- order 2: rhs^T = 2 D2 - 4 Y1 S1 - 4 Y0 S2
+  if (order >= 2) {
+    G g;  // R = 2 D2 - 4 Y0 S2
+    g.X = op(k, w->D0, 0, true);
+    g.X.div = d;
+    g.Y = op(k, w->S2, 0, true);
+    g.C = mptr(k, w->R, 0);
+    g.sC = k.stride;
+    g.alpha = -4.0;
+    g.C1 = mptr(k, w->D2, 0); g.sC1 = k.stride; g.beta1 = 2.0;
+    g.batch = md;
+    g.active = w->mask1;
+    STCHK(run_gemm(k, g));
+    G g2;  // R -= 4 Y1 S1, ||rhs||^2 -> ref
+    g2.X = op(k, w->D1, 0, true);
+    g2.Y = op(k, w->S1, 0, true);
+    g2.C = mptr(k, w->R, 0);
+    g2.sC = k.stride;
+    g2.alpha = -4.0;
+    g2.C1 = mptr(k, w->R, 0); g2.sC1 = k.stride; g2.beta1 = 1.0;
+    g2.W = mptr(k, w->R, 0); g2.sW = k.stride;
+    g2.batch = md;
+    g2.active = w->mask1;
+    STCHK(run_gemm(k, g2));
+    STCHK(sum_gemm_partials(k, md, w->ref, 1, 0));
+    G h;  // R -= D2 + 4 D2 S0
+    h.X = op(k, w->D2, 0, true);
+    h.Y = op(k, w->S0, 0, true);
+    h.Y.div = d;
+    h.C = mptr(k, w->R, 0);
+    h.sC = k.stride;
+    h.alpha = -4.0;
+    h.C1 = mptr(k, w->R, 0); h.sC1 = k.stride; h.beta1 = 1.0;
+    h.C2 = mptr(k, w->D2, 0); h.sC2 = k.stride; h.beta2 = -1.0;
+    h.W = mptr(k, w->R, 0); h.sW = k.stride;
+    h.batch = md;
+    h.active = w->mask1;
+    STCHK(run_gemm(k, h));
+    STCHK(sum_gemm_partials(k, md, w->rr, hs, 0));
+    STCHK(cg_solve<T>(k, w->D2, md, d, w->mask1));
+    STCHK(sym_inplace<T>(k, w->D2, 0, md, 0.5));
+  }
+  return DMPT_OK;
+}
+
+// One full pass of the recursion for orders 0..order (single system).
 template <class T>
 dmpt_status recursion_pass(const Call& k, const PassIn& in) {
-  dmpt_ctx c = k.c;
-  hipStream_t s = c->stream;
-  const int d = in.d, hs = c->hstride;
   const double cscale = std::ldexp(in.beta, -(in.n + 2));
   STCHK(init_d<T>(k, in, cscale));
-  uint16_t* pl[3];
-  for (int step = 0; step < in.n; ++step) {
-    // S0 = D0 D0
-    {
-      G g;
-      g.X = op(k, c->D0, 0, false);
-      g.Y = op(k, c->D0, 0, false);
-      g.C = mptr(k, c->S0, 0);
-      planes_of(k, c->S0, 0, g.Cpl);
-      STCHK(run_gemm(k, g));
-    }
-    if (in.order >= 1) {
-      // Q = D1 D0 -> S1 = Q + Q^T
-      G g;
-      g.X = op(k, c->D1, 0, true);
-      g.Y = op(k, c->D0, 0, false);
-      g.C = mptr(k, c->Q, 0);
-      g.sC = k.stride;
-      g.batch = d;
-      STCHK(run_gemm(k, g));
-      STCHK(sym_to<T>(k, c->Q, c->S1, d, true));
-    }
-    if (in.order >= 2) {
-      // Q = D2 D0 -> S2 = Q + Q^T; S2 += D1 D1
-      G g;
-      g.X = op(k, c->D2, 0, true);
-      g.Y = op(k, c->D0, 0, false);
-      g.C = mptr(k, c->Q, 0);
-      g.sC = k.stride;
-      g.batch = d;
-      STCHK(run_gemm(k, g));
-      STCHK(sym_to<T>(k, c->Q, c->S2, d, false));
-      G h;
-      h.X = op(k, c->D1, 0, true);
-      h.Y = op(k, c->D1, 0, true);
-      h.C = mptr(k, c->S2, 0);
-      h.sC = k.stride;
-      planes_of(k, c->S2, 0, h.Cpl);
-      h.C1 = mptr(k, c->S2, 0); h.sC1 = k.stride; h.beta1 = 1.0;
-      h.batch = d;
-      STCHK(run_gemm(k, h));
-    }
-    // ---- order 0: T' Y0 = 2 D0, guess D0 (the previous iterate), U = D0 in place
-    {
-      // ||rhs||^2 = 4 ||D0||^2
-      HIPCHK(c, dot_partials<T>((const T*)mptr(k, c->D0, 0), 0, (const T*)mptr(k, c->D0, 0), 0, k.nn,
-                                1, c->d_part, s));
-      HIPCHK(c, sum_partials(c->d_part, reduce_blocks(k.nn), 1, c->d_ref, 1, 0, s));
-      HIPCHK(c, axpby<double>(c->d_ref, 0, c->d_ref, 0, 1, 1, 0.0, 4.0, pl, 0, 0, s));
-      // R = 2 D0 - D0 - 4 D0 S0 = D0 - 4 D0 S0, with ||R||^2 -> rr[0]
-      G g;
-      g.X = op(k, c->D0, 0, false);
-      g.Y = op(k, c->S0, 0, false);
-      g.C = mptr(k, c->R, 0);
-      g.alpha = -4.0;
-      g.C1 = mptr(k, c->D0, 0); g.beta1 = 1.0;
-      g.W = mptr(k, c->R, 0);
-      STCHK(run_gemm(k, g));
-      STCHK(sum_gemm_partials(k, 1, c->d_rr, hs, 0));
-      STCHK(cg_solve<T>(k, c->D0, 1));
-      STCHK(sym_inplace<T>(k, c->D0, 0, 1, 0.5));
-    }
-    // ---- order 1: T' Y1 = 2 D1 - 4 S1 Y0; transposed: rhs^T = 2 D1 - 4 Y0 S1
-    if (in.order >= 1) {
-      G g;  // R = 2 D1 - 4 Y0 S1   (Y0 = new D0), ||rhs||^2 -> ref
-      g.X = op(k, c->D0, 0, false);
-      g.Y = op(k, c->S1, 0, true);
-      g.C = mptr(k, c->R, 0);
-      g.sC = k.stride;
-      g.alpha = -4.0;
-      g.C1 = mptr(k, c->D1, 0); g.sC1 = k.stride; g.beta1 = 2.0;
-      g.W = mptr(k, c->R, 0); g.sW = k.stride;
-      g.batch = d;
-      STCHK(run_gemm(k, g));
-      STCHK(sum_gemm_partials(k, d, c->d_ref, 1, 0));
-      G h;  // R -= D1 + 4 D1 S0  (guess U = D1)
-      h.X = op(k, c->D1, 0, true);
-      h.Y = op(k, c->S0, 0, false);
-      h.C = mptr(k, c->R, 0);
-      h.sC = k.stride;
-      h.alpha = -4.0;
-      h.C1 = mptr(k, c->R, 0); h.sC1 = k.stride; h.beta1 = 1.0;
-      h.C2 = mptr(k, c->D1, 0); h.sC2 = k.stride; h.beta2 = -1.0;
-      h.W = mptr(k, c->R, 0); h.sW = k.stride;
-      h.batch = d;
-      STCHK(run_gemm(k, h));
-      STCHK(sum_gemm_partials(k, d, c->d_rr, hs, 0));
-      STCHK(cg_solve<T>(k, c->D1, d));
-      STCHK(sym_inplace<T>(k, c->D1, 0, d, 0.5));
-    }
-    // ---- order 2: rhs^T = 2 D2 - 4 Y1 S1 - 4 Y0 S2
-    if (in.order >= 2) {
-      G g;  // R = 2 D2 - 4 Y0 S2
-      g.X = op(k, c->D0, 0, false);
-      g.Y = op(k, c->S2, 0, true);
-      g.C = mptr(k, c->R, 0);
-      g.sC = k.stride;
-      g.alpha = -4.0;
-      g.C1 = mptr(k, c->D2, 0); g.sC1 = k.stride; g.beta1 = 2.0;
-      g.batch = d;
-      STCHK(run_gemm(k, g));
-      G g2;  // R -= 4 Y1 S1, ||rhs||^2 -> ref
-      g2.X = op(k, c->D1, 0, true);
-      g2.Y = op(k, c->S1, 0, true);
-      g2.C = mptr(k, c->R, 0);
-      g2.sC = k.stride;
-      g2.alpha = -4.0;
-      g2.C1 = mptr(k, c->R, 0); g2.sC1 = k.stride; g2.beta1 = 1.0;
-      g2.W = mptr(k, c->R, 0); g2.sW = k.stride;
-      g2.batch = d;
-      STCHK(run_gemm(k, g2));
-      STCHK(sum_gemm_partials(k, d, c->d_ref, 1, 0));
-      G h;  // R -= D2 + 4 D2 S0
-      h.X = op(k, c->D2, 0, true);
-      h.Y = op(k, c->S0, 0, false);
-      h.C = mptr(k, c->R, 0);
-      h.sC = k.stride;
-      h.alpha = -4.0;
-      h.C1 = mptr(k, c->R, 0); h.sC1 = k.stride; h.beta1 = 1.0;
-      h.C2 = mptr(k, c->D2, 0); h.sC2 = k.stride; h.beta2 = -1.0;
-      h.W = mptr(k, c->R, 0); h.sW = k.stride;
-      h.batch = d;
-      STCHK(run_gemm(k, h));
-      STCHK(sum_gemm_partials(k, d, c->d_rr, hs, 0));
-      STCHK(cg_solve<T>(k, c->D2, d));
-      STCHK(sym_inplace<T>(k, c->D2, 0, d, 0.5));
-    }
-  }
+  for (int step = 0; step < in.n; ++step) STCHK(recursion_step<T>(k, in.order, in.d));
   return DMPT_OK;
 }
 
@@ -549,14 +618,14 @@ dmpt_status finish_pass(const Call& k, const PassIn& in, double* P0, double* con
   dmpt_ctx c = k.c;
   hipStream_t s = c->stream;
   double* shift = c->d_res + RES_HALF;  // device constant 1/2 for the P0 diagonal
-  HIPCHK(c, (sym_combine<T, double>((const T*)mptr(k, c->D0, 0), k.Np, 0, k.N, k.Np, -0.5, shift, 0,
+  HIPCHK(c, (sym_combine<T, double>((const T*)mptr(k, c->ws.D0, 0), k.Np, 0, k.N, k.Np, -0.5, shift, 0,
                                     P0, k.N, 0, nullptr, 0, 1, s)));
   HIPCHK(c, trace(P0, k.N, 0, k.N, 1, c->d_res + RES_TR, 1, c->d_res + RES_ATR, s));
   HIPCHK(c, dot_partials<double>(P0, 0, P0, 0, k.N * k.N, 1, c->d_part, s));
   HIPCHK(c, sum_partials(c->d_part, reduce_blocks(k.N * k.N), 1, c->d_res + RES_FRO, 1, 0, s));
   const int d = in.d;
   for (int ord = 1; ord <= in.order; ++ord) {
-    const Group& g = ord == 1 ? c->D1 : c->D2;
+    const Group& g = ord == 1 ? c->ws.D1 : c->ws.D2;
     double* const* Pk = ord == 1 ? P1 : P2;
     for (int z = 0; z < d; ++z) {
       const int slot = (ord == 1 ? 1 : 1 + d) + z;
@@ -640,6 +709,7 @@ dmpt_status scan_inputs(dmpt_ctx c, int64_t N, const PassIn& in, double* glo, do
 Call make_call(dmpt_ctx c, int64_t N, bool refined) {
   Call k;
   k.c = c;
+  k.w = &c->ws;
   k.eng = engine_of(c->opt.prec);
   if (refined && c->opt.prec == DMPT_BF16X3 && c->opt.refine) k.eng = Engine::BF16S3;
   k.np = engine_planes(k.eng);
@@ -709,8 +779,8 @@ dmpt_status final_checks(dmpt_ctx c, int64_t N, const double* H0, const double* 
     k.eng = Engine::F64;
     k.np = 0;
     // copy H0, P0 into padded FP64 members S1[0] (if present) / Q
-    const Group& gh = c->S0;
-    const Group& gp = c->Q;
+    const Group& gh = c->ws.S0;
+    const Group& gp = c->ws.Q;
     HIPCHK(c, (sym_combine<double, double>(H0, N, 0, N, k.Np, 0.5, nullptr, 0, (double*)mptr(k, gh, 0),
                                            k.Np, 0, nullptr, 0, 1, s)));
     HIPCHK(c, (sym_combine<double, double>(P0, N, 0, N, k.Np, 0.5, nullptr, 0, (double*)mptr(k, gp, 0),
@@ -718,13 +788,13 @@ dmpt_status final_checks(dmpt_ctx c, int64_t N, const double* H0, const double* 
     G g;
     g.X = op(k, gh, 0, false);
     g.Y = op(k, gp, 0, false);
-    g.C = mptr(k, c->R, 0);
+    g.C = mptr(k, c->ws.R, 0);
     const double mf = c->mfma_flops, uf = c->useful_flops;
     STCHK(run_gemm(k, g));
     c->mfma_flops = mf;
     c->useful_flops = uf;
     // ||G - G^T||_F^2 = ||H P - P H||_F^2 (H, P symmetric)
-    HIPCHK(c, antisym_sq_partials<double>((const double*)mptr(k, c->R, 0), k.Np, N, c->d_part, s));
+    HIPCHK(c, antisym_sq_partials<double>((const double*)mptr(k, c->ws.R, 0), k.Np, N, c->d_part, s));
     HIPCHK(c, sum_partials(c->d_part, reduce_blocks(N * N), 1, c->d_res + RES_MISC + 1, 1, 0, s));
     HIPCHK(c, hipMemcpyAsync(c->h_res + RES_MISC + 1, c->d_res + RES_MISC + 1, sizeof(double),
                              hipMemcpyDeviceToHost, s));
@@ -740,6 +810,312 @@ dmpt_status final_checks(dmpt_ctx c, int64_t N, const double* H0, const double* 
   double m = 0;
   for (double v : mx) m = std::max(m, v);
   st->asymmetry = m;
+  return DMPT_OK;
+}
+
+// Allocate a group of `count` Np_max x Np_max members (master + planes).
+bool alloc_group(dmpt_ctx c, Group& g, int count, bool planes, std::vector<void*>& owner) {
+  const size_t nn = (size_t)c->np_max * c->np_max;
+  g.count = count;
+  void* p = nullptr;
+  if (hipMalloc(&p, nn * c->esize * count) != hipSuccess) return false;
+  owner.push_back(p);
+  g.m = p;
+  if (hipMemsetAsync(p, 0, nn * c->esize * count, c->stream) != hipSuccess) return false;
+  for (int q = 0; q < 3; ++q) g.pl[q] = nullptr;
+  if (planes)
+    for (int q = 0; q < c->planes; ++q) {
+      if (hipMalloc(&p, nn * 2 * count) != hipSuccess) return false;
+      owner.push_back(p);
+      g.pl[q] = (uint16_t*)p;
+      if (hipMemsetAsync(p, 0, nn * 2 * count, c->stream) != hipSuccess) return false;
+    }
+  return true;
+}
+
+dmpt_status ensure_adjoint(dmpt_ctx c, int n_ck, int n_seg) {
+  if (c->CK.count >= n_ck && c->SG.count >= n_seg && c->AY.m) return DMPT_OK;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (void* p : c->ad_allocs) (void)hipFree(p);
+  c->ad_allocs.clear();
+  auto& o = c->ad_allocs;
+  bool ok = alloc_group(c, c->AY, 2, true, o) && alloc_group(c, c->AU, 2, true, o) &&
+            alloc_group(c, c->AW, 2, true, o) && alloc_group(c, c->AV, 2, true, o) &&
+            alloc_group(c, c->AG, 2, false, o) && alloc_group(c, c->AD, 1, true, o) &&
+            alloc_group(c, c->CK, n_ck, false, o) && alloc_group(c, c->SG, n_seg, false, o);
+  if (!ok) {
+    for (void* p : c->ad_allocs) (void)hipFree(p);
+    c->ad_allocs.clear();
+    c->AY = c->AU = c->AW = c->AV = c->AG = c->AD = c->CK = c->SG = Group{};
+    return fail(c, DMPT_ERR_NOMEM, "adjoint workspace allocation failed");
+  }
+  return DMPT_OK;
+}
+
+// dst member (with planes) = src member
+template <class T>
+dmpt_status copy_member(const Call& k, const Group& src, int zs, const Group& dst, int zd) {
+  uint16_t* pl[3];
+  planes_of(k, dst, zd, pl);
+  HIPCHK(k.c, axpby<T>((const T*)mptr(k, src, zs), 0, (T*)mptr(k, dst, zd), 0, k.nn, 1, 1.0, 0.0,
+                       pl, 0, dst.pl[0] ? k.np : 0, k.c->stream));
+  return DMPT_OK;
+}
+
+// One order-0 recursion step on c->ws.D0 in place: S0 = D0^2, then T' Y = 2 D0.
+template <class T>
+dmpt_status forward_step0(const Call& k) {
+  G g;
+  g.X = op(k, k.c->ws.D0, 0, false);
+  g.Y = op(k, k.c->ws.D0, 0, false);
+  g.C = mptr(k, k.c->ws.S0, 0);
+  planes_of(k, k.c->ws.S0, 0, g.Cpl);
+  STCHK(run_gemm(k, g));
+  return solve_order0<T>(k);
+}
+
+// Reverse sweep of the order-0 recursion for the two seeds Abar and I:
+// with Y = D_m = 2 D (I + 4 D^2)^-1, D = D_{m-1}, a cotangent Ybar of Y maps to
+//   Dbar = 2 W - 4 (D V + V D),  W = T'^-1 Ybar,  V = W Y      (symmetrised),
+// and D_0 = c (H - mu I) gives Hbar = c Dbar_0, mubar = -c Tr Dbar_0.  The
+// canonical gradient eliminates mu through Tr P0 = Ne:
+//   G = Hbar_A - (mubar_A / mubar_I) Hbar_I.
+template <class T>
+dmpt_status adjoint_impl(const Call& k, const double* H0, double beta, double mu0, int n,
+                         const double* Abar, double* Gout, int ck) {
+  dmpt_ctx c = k.c;
+  hipStream_t s = c->stream;
+  const int hs = c->hstride;
+  const double cs = std::ldexp(beta, -(n + 2));
+  const int nseg = (n + ck - 1) / ck;
+  STCHK(ensure_adjoint(c, nseg, ck));
+  // forward: D_0 and every ck-th iterate
+  {
+    PassIn in{H0, 0, nullptr, nullptr, beta, n, 0, &mu0};
+    STCHK(init_d<T>(k, in, cs));
+  }
+  for (int m = 0; m < n; ++m) {
+    if (m % ck == 0) STCHK(copy_member<T>(k, c->ws.D0, 0, c->CK, m / ck));
+    STCHK(forward_step0<T>(k));
+  }
+  // seeds: Ybar_A = -sym(Abar), Ybar_I = -I
+  {
+    uint16_t* pl[3];
+    planes_of(k, c->AY, 0, pl);
+    HIPCHK(c, (sym_combine<double, T>(Abar, k.N, 0, k.N, k.Np, -0.5, nullptr, 0,
+                                      (T*)mptr(k, c->AY, 0), k.Np, 0, pl, k.np, 1, s)));
+    planes_of(k, c->AY, 1, pl);
+    HIPCHK(c, scaled_plus_identity<T>((const T*)mptr(k, c->AY, 1), (T*)mptr(k, c->AY, 1), k.N, k.Np,
+                                      -1.0, 0.0, pl, k.np, s));
+  }
+  for (int sg = nseg - 1; sg >= 0; --sg) {
+    const int n0 = sg * ck, n1 = std::min(n0 + ck, n);
+    // recompute D_{n0+1..n1} from the checkpoint D_{n0}
+    STCHK(copy_member<T>(k, c->CK, sg, c->ws.D0, 0));
+    for (int m = n0 + 1; m <= n1; ++m) {
+      STCHK(forward_step0<T>(k));
+      STCHK(copy_member<T>(k, c->ws.D0, 0, c->SG, m - n0 - 1));
+    }
+    for (int m = n1; m > n0; --m) {
+      // D = D_{m-1} in c->ws.D0, Y = D_m in AD
+      if (m - 1 == n0) STCHK(copy_member<T>(k, c->CK, sg, c->ws.D0, 0));
+      else STCHK(copy_member<T>(k, c->SG, m - 2 - n0, c->ws.D0, 0));
+      STCHK(copy_member<T>(k, c->SG, m - 1 - n0, c->AD, 0));
+      {
+        G g;  // S0 = D^2
+        g.X = op(k, c->ws.D0, 0, false);
+        g.Y = op(k, c->ws.D0, 0, false);
+        g.C = mptr(k, c->ws.S0, 0);
+        planes_of(k, c->ws.S0, 0, g.Cpl);
+        STCHK(run_gemm(k, g));
+      }
+      // U T' = Ybar (Ybar symmetric), initial guess U = Ybar
+      {
+        uint16_t* pl[3];
+        planes_of(k, c->AU, 0, pl);
+        HIPCHK(c, axpby<T>((const T*)mptr(k, c->AY, 0), k.stride, (T*)mptr(k, c->AU, 0), k.stride,
+                           k.nn, 2, 1.0, 0.0, pl, k.stride, k.np, s));
+        HIPCHK(c, dot_partials<T>((const T*)mptr(k, c->AY, 0), k.stride, (const T*)mptr(k, c->AY, 0),
+                                  k.stride, k.nn, 2, c->d_part, s));
+        HIPCHK(c, sum_partials(c->d_part, reduce_blocks(k.nn), 2, c->ws.ref, 1, 0, s));
+        G g;  // R = Ybar - U - 4 U S0 = -4 U S0
+        g.X = op(k, c->AU, 0, true);
+        g.Y = op(k, c->ws.S0, 0, false);
+        g.C = mptr(k, c->ws.R, 0);
+        g.sC = k.stride;
+        g.alpha = -4.0;
+        g.W = mptr(k, c->ws.R, 0);
+        g.sW = k.stride;
+        g.batch = 2;
+        STCHK(run_gemm(k, g));
+        STCHK(sum_gemm_partials(k, 2, c->ws.rr, hs, 0));
+        STCHK(cg_solve<T>(k, c->AU, 2, 1, nullptr));
+      }
+      // W = U^T;  V = W Y;  V <- sym(V);  AG = V D
+      {
+        uint16_t* pl[3];
+        planes_of(k, c->AW, 0, pl);
+        HIPCHK(c, transpose<T>((const T*)mptr(k, c->AU, 0), k.Np, k.stride, (T*)mptr(k, c->AW, 0), pl,
+                               k.np, 2, s));
+        G g;
+        g.X = op(k, c->AW, 0, true);
+        g.Y = op(k, c->AD, 0, false);
+        g.C = mptr(k, c->AV, 0);
+        g.sC = k.stride;
+        g.batch = 2;
+        STCHK(run_gemm(k, g));
+        STCHK(sym_inplace<T>(k, c->AV, 0, 2, 0.5));
+        G h;
+        h.X = op(k, c->AV, 0, true);
+        h.Y = op(k, c->ws.D0, 0, false);
+        h.C = mptr(k, c->AG, 0);
+        h.sC = k.stride;
+        h.batch = 2;
+        STCHK(run_gemm(k, h));
+      }
+      // Ybar <- 2 sym(W) - 4 (AG + AG^T) = (U + U^T) - 4 (AG + AG^T)
+      {
+        uint16_t* pl[3];
+        planes_of(k, c->AY, 0, pl);
+        HIPCHK(c, (sym_combine<T, T>((const T*)mptr(k, c->AU, 0), k.Np, k.stride, k.N, k.Np, 1.0,
+                                     nullptr, 0, (T*)mptr(k, c->AY, 0), k.Np, k.stride, pl, k.np, 2,
+                                     s, (const T*)mptr(k, c->AG, 0), -4.0)));
+      }
+    }
+  }
+  // G = c (Dbar_A - (Tr Dbar_A / Tr Dbar_I) Dbar_I)
+  HIPCHK(c, trace<T>((const T*)mptr(k, c->AY, 0), k.Np, k.stride, k.N, 2, c->d_res + RES_MISC + 4, 1,
+                     nullptr, s));
+  HIPCHK(c, hipMemcpyAsync(c->h_res + RES_MISC + 4, c->d_res + RES_MISC + 4, 2 * sizeof(double),
+                           hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  const double tA = c->h_res[RES_MISC + 4], tI = c->h_res[RES_MISC + 5];
+  if (!(std::fabs(tI) > 0.0) || !std::isfinite(tA) || !std::isfinite(tI))
+    return fail(c, DMPT_ERR_NONFINITE, "adjoint: d Tr P0 / d mu vanished or is not finite");
+  const double r = tA / tI;
+  HIPCHK(c, (sym_combine<T, double>((const T*)mptr(k, c->AY, 0), k.Np, 0, k.N, k.Np, 0.5 * cs, nullptr,
+                                    0, Gout, k.N, 0, nullptr, 0, 1, s, (const T*)mptr(k, c->AY, 1),
+                                    -0.5 * cs * r)));
+  HIPCHK(c, hipStreamSynchronize(s));
+  return DMPT_OK;
+}
+
+// ------------------------------------------------------------------ batched
+// Systems of similar size share a bucket (same padded size Np); every
+// product, solve and update of a bucket is one batched launch over its
+// systems (and directions).  A whole Newton pass over all buckets is
+// captured once into a HIP graph and replayed; the CG solves run a fixed,
+// a-priori iteration count (members that converge earlier are masked off on
+// the device) and the mu update runs on the device, so a pass needs no host
+// synchronisation.
+struct Bucket {
+  int64_t Np = 0;
+  int first = 0, m = 0;          // slots [first, first + m) of the bucketed order
+  WS wsA, wsB;                   // the same matrices, masks of the two stages
+  double xmax = 0.0;             // max_s c_s * spread_s (|D_0| bound)
+};
+
+// Smallest CG iteration count that the Chebyshev bound guarantees for
+// kappa(T') <= kappa and relative residual tol, plus a small margin.
+int cg_bound(double kappa, double tol, int cap) {
+  if (kappa <= 1.0 + 1e-14) return std::min(cap, 2);
+  const double sk = std::sqrt(kappa);
+  const double rho = (sk - 1.0) / (sk + 1.0);
+  const int kk = (int)std::ceil(std::log(tol / (2.0 * sk)) / std::log(rho)) + 2;
+  return std::max(1, std::min(cap, kk));
+}
+
+// kappa(T'_step) = 1 + 4 max d^2 with |d| <= tanh(2^step artanh(2 x)) / 2, x >= |c (eps - mu)|.
+double kappa_bound(double x, int step) {
+  const double z = std::min(2.0 * x, 1.0 - 1e-15);
+  const double t = std::tanh(std::ldexp(std::atanh(z), step));
+  return 1.0 + t * t;
+}
+
+template <class T>
+dmpt_status batched_pass(dmpt_ctx c, std::vector<Bucket>& bk, bool stageB, int ord, int d, int n,
+                         Engine eng, const std::vector<int>& slot_sys, const double* const* H0s,
+                         const double* const* H1s, double* const* P0s, double* const* P1s,
+                         double* const* P2s, const int64_t* Ns, const std::vector<double>& cs,
+                         double* d_mu_shift, double* d_tr, int rs, double* d_half) {
+  hipStream_t s = c->stream;
+  const int J = 1 + 2 * d;
+  std::vector<Call> ks(bk.size());
+  for (size_t b = 0; b < bk.size(); ++b) {
+    Call& k = ks[b];
+    k = make_call(c, bk[b].Np, false);
+    k.w = stageB ? &bk[b].wsB : &bk[b].wsA;
+    k.eng = eng;
+    k.np = engine_planes(eng);
+    k.N = bk[b].Np;  // inside the workspace every member is treated as Np x Np
+    k.Np = bk[b].Np;
+    k.nn = k.Np * k.Np;
+    k.stride = k.nn;
+    k.m = bk[b].m;
+    k.graph = true;
+    if (d > 0) HIPCHK(c, expand_mask(k.w->mask0, d, k.w->mask1, k.m * d, s));
+  }
+  // D_0 of every system and direction from the caller inputs; the shifts
+  // -c mu live on the device so the graph picks up each Newton update.
+  for (size_t b = 0; b < bk.size(); ++b) {
+    const Call& k = ks[b];
+    for (int i = 0; i < k.m; ++i) {
+      const int slot = bk[b].first + i, sys = slot_sys[slot];
+      const int64_t N = Ns[sys];
+      uint16_t* pl[3];
+      planes_of(k, k.w->D0, i, pl);
+      HIPCHK(c, (sym_combine<double, T>(H0s[sys], N, 0, N, k.Np, 0.5 * cs[sys],
+                                        d_mu_shift + (int64_t)slot * J, 0, (T*)mptr(k, k.w->D0, i),
+                                        k.Np, 0, pl, k.np, 1, s)));
+      for (int z = 0; z < d && ord >= 1; ++z) {
+        const int mem = i * d + z;
+        planes_of(k, k.w->D1, mem, pl);
+        HIPCHK(c, (sym_combine<double, T>(H1s[sys * d + z], N, 0, N, k.Np, 0.5 * cs[sys],
+                                          d_mu_shift + (int64_t)slot * J + 1 + z, 0,
+                                          (T*)mptr(k, k.w->D1, mem), k.Np, 0, pl, k.np, 1, s)));
+        if (ord >= 2) {
+          // H2 = 0: only the shift -c mu2 on the diagonal (a = 0 ignores the input)
+          planes_of(k, k.w->D2, mem, pl);
+          HIPCHK(c, (sym_combine<double, T>(H1s[sys * d + z], N, 0, N, k.Np, 0.0,
+                                            d_mu_shift + (int64_t)slot * J + 1 + d + z, 0,
+                                            (T*)mptr(k, k.w->D2, mem), k.Np, 0, pl, k.np, 1, s)));
+        }
+      }
+    }
+  }
+  for (int step = 0; step < n; ++step)
+    for (size_t b = 0; b < bk.size(); ++b) {
+      Call& k = ks[b];
+      k.cg_iters = cg_bound(kappa_bound(bk[b].xmax, step), k.tol_cg, c->opt.max_cg);
+      STCHK(recursion_step<T>(k, ord, d));
+    }
+  // outputs and traces, per system
+  for (size_t b = 0; b < bk.size(); ++b) {
+    const Call& k = ks[b];
+    for (int i = 0; i < k.m; ++i) {
+      const int slot = bk[b].first + i, sys = slot_sys[slot];
+      const int64_t N = Ns[sys];
+      double* t = d_tr + (int64_t)slot * rs;
+      HIPCHK(c, (sym_combine<T, double>((const T*)mptr(k, k.w->D0, i), k.Np, 0, N, k.Np, -0.5, d_half,
+                                        0, P0s[sys], N, 0, nullptr, 0, 1, s)));
+      HIPCHK(c, trace<double>(P0s[sys], N, 0, N, 1, t, 1, t + J, s));
+      HIPCHK(c, dot_partials<double>(P0s[sys], 0, P0s[sys], 0, N * N, 1, c->d_part, s));
+      HIPCHK(c, sum_partials(c->d_part, reduce_blocks(N * N), 1, t + 2 * J, 1, 0, s));
+      for (int o = 1; o <= ord; ++o)
+        for (int z = 0; z < d; ++z) {
+          const int mem = i * d + z;
+          double* Pk = o == 1 ? P1s[sys * d + z] : P2s[sys * d + z];
+          const Group& g = o == 1 ? k.w->D1 : k.w->D2;
+          const int jt = (o == 1 ? 1 : 1 + d) + z;
+          HIPCHK(c, (sym_combine<T, double>((const T*)mptr(k, g, mem), k.Np, 0, N, k.Np, -0.5, nullptr,
+                                            0, Pk, N, 0, nullptr, 0, 1, s)));
+          HIPCHK(c, trace<double>(Pk, N, 0, N, 1, t + jt, 1, t + J + jt, s));
+          HIPCHK(c, dot_partials<double>(H1s[sys * d + z], 0, Pk, 0, N * N, 1, c->d_part, s));
+          HIPCHK(c, sum_partials(c->d_part, reduce_blocks(N * N), 1,
+                                 t + 2 * J + 1 + (o == 1 ? 0 : d) + z, 1, 0, s));
+        }
+    }
+  }
   return DMPT_OK;
 }
 
@@ -839,7 +1215,8 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
   c->dirs_max = dirs_max;
   c->esize = esize_needed(c->opt);
   c->planes = planes_needed(c->opt);
-  const int dm = std::max(1, dirs_max);
+  // two members at least: the adjoint solves its two seeds together
+  const int dm = std::max(2, dirs_max);
   const size_t nn = (size_t)c->np_max * c->np_max;
   auto alloc = [&](size_t bytes) -> void* {
     void* p = nullptr;
@@ -859,25 +1236,25 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
     return true;
   };
   const int dd = dirs_max;  // groups for perturbations may be empty
-  bool ok = group(c->D0, 1, true) && group(c->S0, 1, true) && group(c->R, dm, false) &&
-            group(c->P, dm, true) && group(c->Q, dm, false);
+  bool ok = group(c->ws.D0, 1, true) && group(c->ws.S0, 1, true) && group(c->ws.R, dm, false) &&
+            group(c->ws.P, dm, true) && group(c->ws.Q, dm, false);
   if (ok && dd > 0)
-    ok = group(c->D1, dd, true) && group(c->D2, dd, true) && group(c->S1, dd, true) &&
-         group(c->S2, dd, true);
+    ok = group(c->ws.D1, dd, true) && group(c->ws.D2, dd, true) && group(c->ws.S1, dd, true) &&
+         group(c->ws.S2, dd, true);
   if (!ok) return bail(DMPT_ERR_NOMEM, "device workspace allocation failed");
   c->hstride = c->opt.max_cg + 2;
-  c->d_rr = (double*)alloc(sizeof(double) * dm * 512);
-  c->d_pq = (double*)alloc(sizeof(double) * dm * 512);
-  c->d_ref = (double*)alloc(sizeof(double) * DMPT_MAX_DIRS);
-  c->d_active = (int*)alloc(sizeof(int) * DMPT_MAX_DIRS);
-  c->d_iters = (int*)alloc(sizeof(int) * DMPT_MAX_DIRS);
+  c->ws.rr = (double*)alloc(sizeof(double) * dm * 512);
+  c->ws.pq = (double*)alloc(sizeof(double) * dm * 512);
+  c->ws.ref = (double*)alloc(sizeof(double) * dm);
+  c->ws.active = (int*)alloc(sizeof(int) * dm);
+  c->ws.iters = (int*)alloc(sizeof(int) * dm);
   c->d_flag = (int*)alloc(sizeof(int) * 4);
   c->d_res = (double*)alloc(sizeof(double) * RES_COUNT);
   const size_t tiles = (size_t)(c->np_max / 128) * (c->np_max / 128);
   c->part_count = std::max<size_t>(tiles, 1024) * dm;
   c->d_part = (double*)alloc(sizeof(double) * c->part_count);
   c->d_gersh = (double*)alloc(sizeof(double) * (2 + 2 * (size_t)n_max));
-  if (!c->d_rr || !c->d_pq || !c->d_ref || !c->d_active || !c->d_iters || !c->d_flag || !c->d_res ||
+  if (!c->ws.rr || !c->ws.pq || !c->ws.ref || !c->ws.active || !c->ws.iters || !c->d_flag || !c->d_res ||
       !c->d_part || !c->d_gersh)
     return bail(DMPT_ERR_NOMEM, "device scalar allocation failed");
   if (hipHostMalloc((void**)&c->h_res, sizeof(double) * RES_COUNT, hipHostMallocDefault) != hipSuccess)
@@ -895,8 +1272,8 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
           return false;
       return true;
     };
-    if (!(zero(c->D0) && zero(c->S0) && zero(c->R) && zero(c->P) && zero(c->Q) && zero(c->D1) &&
-          zero(c->D2) && zero(c->S1) && zero(c->S2)))
+    if (!(zero(c->ws.D0) && zero(c->ws.S0) && zero(c->ws.R) && zero(c->ws.P) && zero(c->ws.Q) && zero(c->ws.D1) &&
+          zero(c->ws.D2) && zero(c->ws.S1) && zero(c->ws.S2)))
       return bail(DMPT_ERR_HIP, "workspace clear failed");
     if (set_values(nullptr, 0, 0, c->d_res + RES_HALF, 0.5, 1, c->stream) != hipSuccess)
       return bail(DMPT_ERR_HIP, "constant init failed");
@@ -936,6 +1313,10 @@ dmpt_status dmpt_finalize(dmpt_ctx c) {
   for (auto e : c->prof_pool) (void)hipEventDestroy(e);
   for (void* p : c->allocs) (void)hipFree(p);
   c->allocs.clear();
+  for (void* p : c->ad_allocs) (void)hipFree(p);
+  c->ad_allocs.clear();
+  for (void* p : c->bt_allocs) (void)hipFree(p);
+  c->bt_allocs.clear();
   if (c->h_res) (void)hipHostFree(c->h_res);
   if (c->h_int) (void)hipHostFree(c->h_int);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -1108,16 +1489,358 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
                                    double* const* P0s, double* const* P1s, double* const* P2s,
                                    dmpt_stats* st) {
   if (!c) return DMPT_ERR_ARG;
-  (void)nsys; (void)Ns; (void)H0s; (void)d; (void)H1s; (void)betas; (void)Nes; (void)n; (void)order;
-  (void)mus; (void)P0s; (void)P1s; (void)P2s; (void)st;
-  return fail(c, DMPT_ERR_UNSUPPORTED, "batched solve not built yet");
+  if (nsys < 1 || !Ns || !H0s || !betas || !Nes || !mus || !P0s)
+    return fail(c, DMPT_ERR_ARG, "batched: nsys >= 1 and non-NULL Ns, H0s, betas, Nes, mus, P0s");
+  if (order < 0 || order > 2) return fail(c, DMPT_ERR_ARG, "order must be 0, 1 or 2");
+  if (order >= 1 && (d < 1 || d > DMPT_MAX_DIRS))
+    return fail(c, DMPT_ERR_ARG, "d must lie in [1, DMPT_MAX_DIRS]");
+  if (order == 0) d = 0;
+  if (n < 1 || n > 62) return fail(c, DMPT_ERR_ARG, "recursion depth n must lie in [1, 62]");
+  if (order >= 1 && (!H1s || !P1s)) return fail(c, DMPT_ERR_ARG, "H1s and P1s are required");
+  if (order >= 2 && !P2s) return fail(c, DMPT_ERR_ARG, "P2s is required");
+  for (int sy = 0; sy < nsys; ++sy) {
+    if (Ns[sy] < 1 || Ns[sy] > c->n_max) return fail(c, DMPT_ERR_ARG, "each N must lie in [1, n_max]");
+    if (!H0s[sy] || !P0s[sy]) return fail(c, DMPT_ERR_ARG, "NULL H0 or P0");
+    if (!(betas[sy] > 0.0) || !std::isfinite(betas[sy])) return fail(c, DMPT_ERR_ARG, "beta must be > 0");
+    if (!(Nes[sy] > 0.0 && Nes[sy] < (double)Ns[sy])) return fail(c, DMPT_ERR_ARG, "Ne must lie in (0, N)");
+    for (int z = 0; z < d; ++z) {
+      if (!H1s[sy * d + z] || !P1s[sy * d + z]) return fail(c, DMPT_ERR_ARG, "NULL H1 or P1");
+      if (order >= 2 && !P2s[sy * d + z]) return fail(c, DMPT_ERR_ARG, "NULL P2");
+    }
+  }
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, DMPT_ERR_HIP, "hipSetDevice failed");
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = c->stream;
+  reset_stats(c);
+  const int J = 1 + 2 * d;
+  const int rs = 2 * J + 1 + 2 * d;
+  // per system: Gershgorin interval, range guard, bounds of mu0, c
+  std::vector<double> cs(nsys), par(6 * (size_t)nsys), mu0(nsys), xs(nsys);
+  for (int sy = 0; sy < nsys; ++sy) {
+    PassIn in{H0s[sy], d, order >= 1 ? H1s + (size_t)sy * d : nullptr, nullptr, betas[sy], n,
+              order, nullptr};
+    double glo, ghi;
+    STCHK(scan_inputs(c, Ns[sy], in, &glo, &ghi));
+    if (betas[sy] * (ghi - glo) >= std::ldexp(1.0, n + 1))
+      return fail(c, DMPT_ERR_RANGE, "beta * spread(H0) >= 2^(n+1) for a system of the batch");
+    cs[sy] = std::ldexp(betas[sy], -(n + 2));
+    const double lr = 0.999 * std::ldexp(1.0, n + 1) / betas[sy];
+    const double lo = std::max(ghi - lr, glo - 50.0 / betas[sy]);
+    const double hi = std::min(glo + lr, ghi + 50.0 / betas[sy]);
+    par[6 * sy + 0] = betas[sy];
+    par[6 * sy + 1] = Nes[sy];
+    par[6 * sy + 2] = cs[sy];
+    par[6 * sy + 3] = lo;
+    par[6 * sy + 4] = hi;
+    par[6 * sy + 5] = (double)Ns[sy];
+    double m0 = mus[(size_t)sy * J];
+    if (!std::isfinite(m0)) m0 = 0.5 * (glo + ghi);
+    mu0[sy] = std::min(std::max(m0, lo), hi);
+    xs[sy] = cs[sy] * (ghi - glo);
+  }
+  // buckets by padded size, systems in bucket order ("slots")
+  std::vector<int> slot_sys(nsys);
+  for (int i = 0; i < nsys; ++i) slot_sys[i] = i;
+  std::stable_sort(slot_sys.begin(), slot_sys.end(),
+                   [&](int a, int b) { return padded(Ns[a]) < padded(Ns[b]); });
+  std::vector<Bucket> bk;
+  for (int i = 0; i < nsys; ++i) {
+    const int64_t Np = padded(Ns[slot_sys[i]]);
+    if (bk.empty() || bk.back().Np != Np) {
+      bk.push_back(Bucket{});
+      bk.back().Np = Np;
+      bk.back().first = i;
+    }
+    bk.back().m += 1;
+    bk.back().xmax = std::max(bk.back().xmax, xs[slot_sys[i]]);
+  }
+  // workspace: (re)allocate when this batch needs more than the cached one
+  const Engine eng = (c->opt.prec == DMPT_BF16X3 && c->opt.refine) ? Engine::BF16S3
+                                                                    : engine_of(c->opt.prec);
+  const int np = engine_planes(eng);
+  const int dmem = std::max(1, d);
+  size_t need = 0, part_need = c->part_count;
+  for (auto& b : bk) {
+    const size_t nn = (size_t)b.Np * b.Np;
+    const size_t per = nn * (c->esize + 2 * np);
+    need += per * (size_t)b.m * (2 + 3 * (size_t)dmem + (size_t)(order >= 1 ? 2 * d : 0) +
+                                 (size_t)(order >= 2 ? 2 * d : 0));
+    part_need = std::max(part_need, (size_t)(b.Np / 128) * (b.Np / 128) * b.m * dmem);
+    part_need = std::max(part_need, (size_t)reduce_blocks((int64_t)nn) * b.m * dmem);
+  }
+  const int hs = c->hstride;
+  (void)need;
+  if (part_need > c->part_count) {
+    // a larger partials block, kept until dmpt_finalize
+    HIPCHK(c, hipStreamSynchronize(s));
+    void* p = nullptr;
+    if (hipMalloc(&p, part_need * sizeof(double)) != hipSuccess)
+      return fail(c, DMPT_ERR_NOMEM, "batched partials allocation failed");
+    c->bt_allocs.push_back(p);
+    c->d_part = (double*)p;
+    c->part_count = part_need;
+  }
+  // carve every bucket's groups from per-bucket allocations
+  std::vector<void*> local;  // freed at the end of the call
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(s);
+    for (void* p : local) (void)hipFree(p);
+  };
+  auto galloc = [&](Group& g, int count, int64_t Np, bool planes) -> bool {
+    const size_t nn = (size_t)Np * Np;
+    void* p = nullptr;
+    if (hipMalloc(&p, nn * c->esize * count) != hipSuccess) return false;
+    local.push_back(p);
+    g.m = p;
+    g.count = count;
+    if (hipMemsetAsync(p, 0, nn * c->esize * count, s) != hipSuccess) return false;
+    for (int q = 0; q < 3; ++q) g.pl[q] = nullptr;
+    if (planes)
+      for (int q = 0; q < np; ++q) {
+        if (hipMalloc(&p, nn * 2 * count) != hipSuccess) return false;
+        local.push_back(p);
+        g.pl[q] = (uint16_t*)p;
+        if (hipMemsetAsync(p, 0, nn * 2 * count, s) != hipSuccess) return false;
+      }
+    return true;
+  };
+  auto dalloc = [&](size_t bytes) -> void* {
+    void* p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(bytes, 256)) != hipSuccess) return nullptr;
+    local.push_back(p);
+    return p;
+  };
+  // per-slot device state
+  double* d_mu = (double*)dalloc(sizeof(double) * nsys * J);
+  double* d_shift = (double*)dalloc(sizeof(double) * nsys * J);
+  double* d_tr = (double*)dalloc(sizeof(double) * nsys * rs);
+  double* d_par = (double*)dalloc(sizeof(double) * nsys * 6);
+  double* d_prev = (double*)dalloc(sizeof(double) * nsys);
+  double* d_occ = (double*)dalloc(sizeof(double) * nsys);
+  int* d_flags = (int*)dalloc(sizeof(int) * nsys * 6);  // activeA, activeB, done, passes, status, spare
+  if (!d_mu || !d_shift || !d_tr || !d_par || !d_prev || !d_occ || !d_flags) {
+    cleanup();
+    return fail(c, DMPT_ERR_NOMEM, "batched scalar allocation failed");
+  }
+  int* actA = d_flags;
+  int* actB = d_flags + nsys;
+  int* done = d_flags + 2 * nsys;
+  int* passes = d_flags + 3 * nsys;
+  int* status = d_flags + 4 * nsys;
+  for (auto& b : bk) {
+    const int md = b.m * dmem;
+    WS w;
+    bool ok = galloc(w.D0, b.m, b.Np, true) && galloc(w.S0, b.m, b.Np, true) &&
+              galloc(w.R, md, b.Np, false) && galloc(w.P, md, b.Np, true) && galloc(w.Q, md, b.Np, false);
+    if (ok && order >= 1) ok = galloc(w.D1, md, b.Np, true) && galloc(w.S1, md, b.Np, true);
+    if (ok && order >= 2) ok = galloc(w.D2, md, b.Np, true) && galloc(w.S2, md, b.Np, true);
+    w.rr = ok ? (double*)dalloc(sizeof(double) * md * hs) : nullptr;
+    w.pq = ok ? (double*)dalloc(sizeof(double) * md * hs) : nullptr;
+    w.ref = ok ? (double*)dalloc(sizeof(double) * md) : nullptr;
+    w.active = ok ? (int*)dalloc(sizeof(int) * md) : nullptr;
+    w.iters = ok ? (int*)dalloc(sizeof(int) * md) : nullptr;
+    w.mask1 = ok ? (int*)dalloc(sizeof(int) * md) : nullptr;
+    if (!ok || !w.rr || !w.pq || !w.ref || !w.active || !w.iters || !w.mask1) {
+      cleanup();
+      return fail(c, DMPT_ERR_NOMEM, "batched workspace allocation failed");
+    }
+    b.wsA = w;
+    b.wsB = w;
+    b.wsA.mask0 = actA + b.first;
+    b.wsB.mask0 = actB + b.first;
+  }
+  // initial state
+  {
+    std::vector<double> hmu((size_t)nsys * J, 0.0), hsh((size_t)nsys * J, 0.0), hpar(6 * (size_t)nsys);
+    for (int slot = 0; slot < nsys; ++slot) {
+      const int sy = slot_sys[slot];
+      for (int j = 0; j < J; ++j) {
+        double v = j == 0 ? mu0[sy] : mus[(size_t)sy * J + j];
+        if (!std::isfinite(v)) v = 0.0;
+        hmu[(size_t)slot * J + j] = v;
+        hsh[(size_t)slot * J + j] = -cs[sy] * v;
+      }
+      for (int q = 0; q < 6; ++q) hpar[6 * (size_t)slot + q] = par[6 * (size_t)sy + q];
+    }
+    std::vector<int> hfl(6 * (size_t)nsys, 0);
+    for (int i = 0; i < 2 * nsys; ++i) hfl[i] = 1;
+    std::vector<double> hprev(nsys, INFINITY);
+    if (hipMemcpy(d_mu, hmu.data(), hmu.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d_shift, hsh.data(), hsh.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d_par, hpar.data(), hpar.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d_prev, hprev.data(), hprev.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d_flags, hfl.data(), hfl.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+      cleanup();
+      return fail(c, DMPT_ERR_HIP, "batched state upload failed");
+    }
+  }
+  const bool staged = c->opt.staged && order > 0;
+  const bool prof = c->prof_on;
+  c->prof_on = false;  // no event records inside a captured graph
+  hipGraphExec_t gx[2] = {nullptr, nullptr};
+  hipGraph_t gg[2] = {nullptr, nullptr};
+  dmpt_status rc = DMPT_OK;
+  int total_passes = 0;
+  double flops_m = 0.0, flops_u = 0.0;  // executed over every replay
+  for (int stage = staged ? 0 : 1; stage <= 1 && rc == DMPT_OK; ++stage) {
+    const int ord = stage == 0 ? 0 : order;
+    const bool final_stage = stage == 1;
+    const double mf0 = c->mfma_flops, uf0 = c->useful_flops;
+    // capture one pass of this stage
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      rc = fail(c, DMPT_ERR_HIP, "hipStreamBeginCapture failed");
+      break;
+    }
+    dmpt_status cr = c->esize == 8
+        ? batched_pass<double>(c, bk, final_stage, ord, d, n, eng, slot_sys, H0s, H1s, P0s, P1s, P2s,
+                               Ns, cs, d_shift, d_tr, rs, c->d_res + RES_HALF)
+        : batched_pass<float>(c, bk, final_stage, ord, d, n, eng, slot_sys, H0s, H1s, P0s, P1s, P2s,
+                              Ns, cs, d_shift, d_tr, rs, c->d_res + RES_HALF);
+    if (cr == DMPT_OK) {
+      const hipError_t e = newton_update(d_tr, rs, d_par, d_mu, d_shift, J, ord * d, c->opt.tol_occ,
+                                         final_stage ? 1 : 0, final_stage ? actB : actA, done,
+                                         d_prev, d_occ, passes, status, nsys, s);
+      if (e != hipSuccess) cr = fail(c, DMPT_ERR_HIP, "newton_update launch failed");
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t ee = hipStreamEndCapture(s, &g);
+    if (cr != DMPT_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      rc = cr;
+      break;
+    }
+    if (ee != hipSuccess || hipGraphInstantiate(&gx[stage], g, nullptr, nullptr, 0) != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      rc = fail(c, DMPT_ERR_HIP, "graph capture / instantiation failed");
+      break;
+    }
+    gg[stage] = g;
+    const double pass_mf = c->mfma_flops - mf0, pass_uf = c->useful_flops - uf0;
+    int* act = final_stage ? actB : actA;
+    std::vector<int> hact(nsys);
+    for (int pass = 0; pass < c->opt.max_newton; ++pass) {
+      if (hipGraphLaunch(gx[stage], s) != hipSuccess) {
+        rc = fail(c, DMPT_ERR_HIP, "hipGraphLaunch failed");
+        break;
+      }
+      ++total_passes;
+      flops_m += pass_mf;
+      flops_u += pass_uf;
+      if (hipMemcpyAsync(hact.data(), act, nsys * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess) {
+        rc = fail(c, DMPT_ERR_HIP, "batched pass failed");
+        break;
+      }
+      bool any = false;
+      for (int v : hact) any |= v != 0;
+      if (!any) break;
+    }
+  }
+  c->prof_on = prof;
+  // results
+  std::vector<double> hmu((size_t)nsys * J), hocc(nsys), htr((size_t)nsys * rs);
+  std::vector<int> hfl(6 * (size_t)nsys);
+  if (rc == DMPT_OK) {
+    if (hipMemcpy(hmu.data(), d_mu, hmu.size() * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(hocc.data(), d_occ, hocc.size() * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(htr.data(), d_tr, htr.size() * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(hfl.data(), d_flags, hfl.size() * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+      rc = fail(c, DMPT_ERR_HIP, "batched result download failed");
+  }
+  for (int q = 0; q < 2; ++q) {
+    if (gx[q]) (void)hipGraphExecDestroy(gx[q]);
+    if (gg[q]) (void)hipGraphDestroy(gg[q]);
+  }
+  cleanup();
+  if (rc != DMPT_OK) return rc;
+  bool all_done = true, nonfinite = false;
+  double occ_sum = 0.0;
+  for (int slot = 0; slot < nsys; ++slot) {
+    const int sy = slot_sys[slot];
+    for (int j = 0; j < J; ++j) mus[(size_t)sy * J + j] = hmu[(size_t)slot * J + j];
+    if (!hfl[2 * nsys + slot]) all_done = false;
+    if (hfl[4 * nsys + slot] == -6) nonfinite = true;
+    occ_sum += hocc[slot];
+  }
+  if (st) {
+    std::memset(st, 0, sizeof(*st));
+    st->newton_iters = total_passes;
+    st->occ_err = occ_sum;
+    st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    // every captured product times the number of replays of its graph (the
+    // products of converged systems are still counted: they are skipped on
+    // the device, not removed from the graph)
+    st->mfma_flops = flops_m;
+    st->useful_flops = flops_u;
+  }
+  if (nonfinite) return fail(c, DMPT_ERR_NONFINITE, "non-finite trace in a batched system");
+  if (!all_done) return fail(c, DMPT_ERR_NOCONV, "a batched system did not converge within max_newton");
+  return DMPT_OK;
 }
 
 dmpt_status dmpt_backward(dmpt_ctx c, int64_t N, const double* H0, double beta, double Ne, int n,
                           const double* mu0, const double* Abar, double* G, dmpt_stats* st) {
-  if (!c) return DMPT_ERR_ARG;
-  (void)N; (void)H0; (void)beta; (void)Ne; (void)n; (void)mu0; (void)Abar; (void)G; (void)st;
-  return fail(c, DMPT_ERR_UNSUPPORTED, "adjoint not built yet");
+  STCHK(check_common(c, N, H0, beta, n));
+  if (!Abar) return fail(c, DMPT_ERR_ARG, "Abar is NULL");
+  if (!G) return fail(c, DMPT_ERR_ARG, "G is NULL");
+  if (!(Ne > 0.0 && Ne < (double)N)) return fail(c, DMPT_ERR_ARG, "Ne must lie in (0, N)");
+  if (mu0 && !std::isfinite(*mu0)) return fail(c, DMPT_ERR_ARG, "mu0 must be finite");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, DMPT_ERR_HIP, "hipSetDevice failed");
+  const auto t0 = std::chrono::steady_clock::now();
+  double mu = mu0 ? *mu0 : NAN;
+  int newton = 0;
+  double occ = 0.0;
+  long cg_fwd = 0;
+  int cg_fwd_max = 0;
+  double mf = 0.0, uf = 0.0;
+  if (!mu0) {
+    // canonical mu0 first (order 0); G serves as the scratch P0
+    dmpt_stats s0;
+    double m[1] = {NAN};
+    const dmpt_status r = dmpt_mu_newton(c, N, H0, 0, nullptr, nullptr, beta, Ne, n, 0, m, G, nullptr,
+                                         nullptr, &s0);
+    if (r != DMPT_OK) return r;
+    mu = m[0];
+    newton = s0.newton_iters;
+    occ = s0.occ_err;
+    cg_fwd = s0.cg_iters_total;
+    cg_fwd_max = s0.cg_iters_max;
+    mf = s0.mfma_flops;
+    uf = s0.useful_flops;
+  } else {
+    PassIn in{H0, 0, nullptr, nullptr, beta, n, 0, &mu};
+    double glo, ghi;
+    STCHK(scan_inputs(c, N, in, &glo, &ghi));
+    if (beta * std::max(std::fabs(glo - mu), std::fabs(ghi - mu)) >= std::ldexp(1.0, n + 1))
+      return fail(c, DMPT_ERR_RANGE, "beta * max|eps - mu| >= 2^(n+1)");
+  }
+  {
+    // Abar must be finite too
+    HIPCHK(c, set_values(c->d_flag, 0, 1, nullptr, 0.0, 0, c->stream));
+    HIPCHK(c, nonfinite_scan(Abar, N, N, c->d_flag, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->h_int, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->h_int[0]) return fail(c, DMPT_ERR_NONFINITE, "non-finite value in Abar");
+  }
+  reset_stats(c);
+  Call k = make_call(c, N, true);
+  const int ck = std::max(1, std::min(c->opt.ckpt_every, n));
+  dmpt_status r = k.f64 ? adjoint_impl<double>(k, H0, beta, mu, n, Abar, G, ck)
+                        : adjoint_impl<float>(k, H0, beta, mu, n, Abar, G, ck);
+  if (r != DMPT_OK) return r;
+  if (st) {
+    std::memset(st, 0, sizeof(*st));
+    st->newton_iters = newton;
+    st->occ_err = occ;
+    st->mu[0] = mu;
+    st->cg_iters_total = (int)(c->cg_total + cg_fwd);
+    st->cg_iters_max = std::max(c->cg_max, cg_fwd_max);
+    st->mfma_flops = c->mfma_flops + mf;
+    st->useful_flops = c->useful_flops + uf;
+    st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (c->cg_capped) return fail(c, DMPT_ERR_NOCONV, "a linear solve reached max_cg");
+  return DMPT_OK;
 }
 
 }  // extern "C"

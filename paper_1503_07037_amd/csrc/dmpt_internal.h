@@ -36,11 +36,13 @@ struct Mat {
 };
 
 // Batched operand: base matrix and element stride between batch members
-// (0 = the same matrix for every member).
+// (0 = the same matrix for every member).  Member z of the launch reads
+// operand member z / div, so div = d lets d directions share one matrix.
 struct BOp {
   const void* m = nullptr;
   const uint16_t* pl[3] = {nullptr, nullptr, nullptr};
   int64_t stride = 0;
+  int div = 1;
 };
 
 struct GemmArgs {
@@ -64,14 +66,21 @@ int gemm_tiles(Engine eng, int64_t Np);
 hipError_t gemm(const GemmArgs& a, hipStream_t s);
 
 // ---------------------------------------------------------------- element-wise
-// out = a (in + in^T) + dshift I on the leading N x N block, 0 elsewhere.
+// out = a (in + in^T) + a2 (in2 + in2^T) + dshift I on the leading N x N
+// block, 0 elsewhere (in2 may be null).
 // in: Tin with leading dim ldi; out: Tout with leading dim ldo (+ split planes).
 // Batched over `batch` members with element strides.
 // The tile pair (i, j) / (j, i) is handled by one block, so in == out is allowed.
 template <class Tin, class Tout>
 hipError_t sym_combine(const Tin* in, int64_t ldi, int64_t si, int64_t N, int64_t Np, double a,
                        const double* dshift, int dstride, Tout* out, int64_t ldo, int64_t so,
-                       uint16_t* const* planes, int nplanes, int batch, hipStream_t s);
+                       uint16_t* const* planes, int nplanes, int batch, hipStream_t s,
+                       const Tin* in2 = nullptr, double a2 = 0.0);
+
+// out = in^T (Np x Np members, batched, with planes); in != out.
+template <class T>
+hipError_t transpose(const T* in, int64_t Np, int64_t stride, T* out, uint16_t* const* planes,
+                     int nplanes, int batch, hipStream_t s);
 
 // Split a master matrix into BF16 planes (batched).
 hipError_t split_planes(const double* x, int64_t n_elems, int64_t sx, uint16_t* const* planes,
@@ -89,7 +98,8 @@ hipError_t sum_partials(const double* partials, int count, int batch, double* ou
                         int ostride, int oidx, hipStream_t s);
 // out[z*ostride] = sum_i x[z][i*ld + i], i < N (trace, FP64 input);
 // aout[z*ostride] = sum_i |x_ii| when aout is not null
-hipError_t trace(const double* x, int64_t ld, int64_t sx, int64_t N, int batch, double* out,
+template <class T>
+hipError_t trace(const T* x, int64_t ld, int64_t sx, int64_t N, int batch, double* out,
                  int ostride, double* aout, hipStream_t s);
 
 // CG updates (batched over right-hand sides z).
@@ -103,7 +113,7 @@ template <class T>
 hipError_t cg_update_p(T* P, const T* R, int64_t n, int64_t stride, int batch,
                        const double* rr_new, const double* rr_old, int hstride, const int* active,
                        uint16_t* const* planes, int nplanes, hipStream_t s);
-// convergence: active[z] = rr[z] > tol^2 * ref[z]  (with iteration counter)
+// convergence: active[z] = rr[z] > tol^2 * ref[z]  (with iteration counter), any batch size
 hipError_t cg_check(const double* rr, const double* ref, int hstride, int batch, double tol2,
                     int* active, int* iters, hipStream_t s);
 
@@ -117,8 +127,16 @@ template <class T>
 hipError_t scaled_plus_identity(const T* x, T* out, int64_t N, int64_t Np, double a, double b,
                                 uint16_t* const* planes, int nplanes, hipStream_t s);
 
-// p[0..n) = v and q[0..nq) = qv (n, nq <= 64); either pointer may be null with count 0
+// p[0..n) = v and q[0..nq) = qv; either pointer may be null with count 0
 hipError_t set_values(int* p, int v, int n, double* q, double qv, int nq, hipStream_t s);
+// dst[z] = src[z / div] for z < n (member masks from system masks)
+hipError_t expand_mask(const int* src, int div, int* dst, int n, hipStream_t s);
+
+// Device-side canonical Newton update of a batch of systems (see elementwise.hip).
+hipError_t newton_update(const double* tr, int rs, const double* par, double* mu, double* shift,
+                         int J, int nk, double tol, int final_stage, int* active, int* done,
+                         double* prev_err, double* occ, int* passes, int* status, int nsys,
+                         hipStream_t s);
 
 // Scan for non-finite values: flag |= any(!isfinite(x))
 hipError_t nonfinite_scan(const double* x, int64_t ld, int64_t N, int* flag, hipStream_t s);

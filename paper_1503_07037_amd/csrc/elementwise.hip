@@ -62,20 +62,27 @@ template <class Tin, class Tout>
 __global__ __launch_bounds__(kT) void k_sym(const Tin* in, int64_t ldi, int64_t si, int64_t N,
                                             int64_t Np, double a, const double* dshift,
                                             int dstride, Tout* out, int64_t ldo, int64_t so,
-                                            Planes pl, int np, int64_t out_rows) {
+                                            Planes pl, int np, int64_t out_rows, const Tin* in2,
+                                            double a2) {
   __shared__ double ta[32][33], tb[32][33];
   const int64_t bi = blockIdx.y, bj = blockIdx.x;
   if (bi > bj) return;
   const int z = blockIdx.z;
   in += z * si;
+  if (in2) in2 += z * si;
   out += z * so;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  // ta = a in(bi,bj) + a2 in2(bi,bj), tb likewise for (bj,bi)
   for (int r = ty; r < 32; r += 8) {
     int64_t gi = bi * 32 + r, gj = bj * 32 + tx;
-    ta[r][tx] = (gi < N && gj < N) ? (double)in[gi * ldi + gj] : 0.0;
+    bool ok = gi < N && gj < N;
+    ta[r][tx] = ok ? a * (double)in[gi * ldi + gj] + (in2 ? a2 * (double)in2[gi * ldi + gj] : 0.0)
+                   : 0.0;
     gi = bj * 32 + r;
     gj = bi * 32 + tx;
-    tb[r][tx] = (gi < N && gj < N) ? (double)in[gi * ldi + gj] : 0.0;
+    ok = gi < N && gj < N;
+    tb[r][tx] = ok ? a * (double)in[gi * ldi + gj] + (in2 ? a2 * (double)in2[gi * ldi + gj] : 0.0)
+                   : 0.0;
   }
   __syncthreads();
   const double ds = dshift ? dshift[z * dstride] : 0.0;
@@ -89,14 +96,36 @@ __global__ __launch_bounds__(kT) void k_sym(const Tin* in, int64_t ldi, int64_t 
       if (gi >= out_rows || gj >= out_rows) continue;
       double v = 0.0;
       if (gi < N && gj < N) {
-        // out(ti,tj)[r][tx] = a (in(ti,tj)[r][tx] + in(tj,ti)[tx][r])
-        v = pass ? a * (tb[r][tx] + ta[tx][r]) : a * (ta[r][tx] + tb[tx][r]);
+        // out(ti,tj)[r][tx] = ta(ti,tj)[r][tx] + ta(tj,ti)[tx][r] (scales already applied)
+        v = pass ? (tb[r][tx] + ta[tx][r]) : (ta[r][tx] + tb[tx][r]);
         if (gi == gj) v += ds;
       }
       const Tout o = (Tout)v;
       out[gi * ldo + gj] = o;
       if (np) split_store((double)o, p3, np, gi * ldo + gj);
     }
+  }
+}
+
+// out = in^T on Np x Np (batched, with planes); out and in must differ.
+template <class T>
+__global__ __launch_bounds__(kT) void k_transpose(const T* __restrict__ in, int64_t Np, int64_t s,
+                                                  T* __restrict__ out, Planes pl, int np) {
+  __shared__ T t[32][33];
+  const int z = blockIdx.z;
+  in += z * s;
+  out += z * s;
+  const int64_t bi = blockIdx.y, bj = blockIdx.x;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) t[r][tx] = in[(bi * 32 + r) * Np + bj * 32 + tx];
+  __syncthreads();
+  uint16_t* p3[3] = {pl.p[0] ? pl.p[0] + z * s : nullptr, pl.p[1] ? pl.p[1] + z * s : nullptr,
+                     pl.p[2] ? pl.p[2] + z * s : nullptr};
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t idx = (bj * 32 + r) * Np + bi * 32 + tx;
+    const T v = t[tx][r];
+    out[idx] = v;
+    if (np) split_store((double)v, p3, np, idx);
   }
 }
 
@@ -134,13 +163,14 @@ __global__ __launch_bounds__(kT) void k_sum_partials(const double* __restrict__ 
   if (threadIdx.x == 0) out[z * ostride + oidx] = s;
 }
 
-__global__ __launch_bounds__(kT) void k_trace(const double* __restrict__ x, int64_t ld, int64_t sx,
+template <class T>
+__global__ __launch_bounds__(kT) void k_trace(const T* __restrict__ x, int64_t ld, int64_t sx,
                                               int64_t N, double* out, int ostride, double* aout) {
   const int z = blockIdx.x;
   x += z * sx;
   double s = 0.0, sa = 0.0;
   for (int64_t i = threadIdx.x; i < N; i += kT) {
-    const double v = x[i * ld + i];
+    const double v = (double)x[i * ld + i];
     s += v;
     sa += fabs(v);
   }
@@ -206,7 +236,7 @@ __global__ __launch_bounds__(kT) void k_cg_p(T* __restrict__ P, const T* __restr
 
 __global__ void k_cg_check(const double* rr, const double* ref, int hstride, int batch,
                            double tol2, int* active, int* iters) {
-  const int z = threadIdx.x;
+  const int z = blockIdx.x * blockDim.x + threadIdx.x;
   if (z >= batch || !active[z]) return;
   iters[z] += 1;
   if (!(rr[z * hstride] > tol2 * ref[z])) active[z] = 0;
@@ -223,7 +253,7 @@ __global__ __launch_bounds__(kT) void k_axpby(const T* __restrict__ x, int64_t s
                      pl.p[2] ? pl.p[2] + z * sp : nullptr};
   const T ta = (T)a, tb = (T)b;
   for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
-    const T v = ta * x[i] + tb * y[i];
+    const T v = (b != 0.0) ? ta * x[i] + tb * y[i] : ta * x[i];  // b = 0: y is not read
     y[i] = v;
     if (np) split_store((double)v, p3, np, i);
   }
@@ -325,9 +355,60 @@ __global__ __launch_bounds__(kT) void k_antisym_sq(const T* __restrict__ x, int6
 }
 
 __global__ void k_set(int* p, int v, int n, double* q, double qv, int nq) {
-  const int i = threadIdx.x;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
   if (i < nq) q[i] = qv;
+}
+
+__global__ void k_expand(const int* src, int div, int* dst, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i / div];
+}
+
+// Canonical Newton update of every system of a batch (Algorithm 1's mu
+// update with Tr P_mu = beta (Tr P0 - ||P0||_F^2)), one thread per system.
+// tr[s*rs + ...]: Tr P^(k) (J values), sum |P^(k)_ii| (J), ||P0||_F^2.
+// par[s*6 + ...]: beta, Ne, c = 2^-(n+2) beta, mu0 lower bound, mu0 upper bound, N.
+__global__ void k_newton(const double* tr, int rs, const double* par, double* mu, double* shift,
+                         int J, int nk, double tol, int final_stage, int* active, int* done,
+                         double* prev_err, double* occ, int* passes, int* status, int nsys) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsys || !active[s]) return;
+  const double* t = tr + (int64_t)s * rs;
+  const double beta = par[s * 6 + 0], Ne = par[s * 6 + 1], c = par[s * 6 + 2];
+  const double lo = par[s * 6 + 3], hi = par[s * 6 + 4], N = par[s * 6 + 5];
+  double err = fabs(t[0] - Ne);
+  bool ok = err <= tol * N;
+  for (int i = 1; i <= nk; ++i) {
+    const double a = fabs(t[i]);
+    err += a;
+    if (!(a <= tol * fmax(t[J + i], 1e-300))) ok = false;
+  }
+  passes[s] += 1;
+  occ[s] = err;
+  if (!isfinite(err) || !isfinite(t[2 * J])) {
+    status[s] = -6;
+    active[s] = 0;
+    return;
+  }
+  if (final_stage && !ok && err > 0.5 * prev_err[s] && err <= 1e3 * tol * N) ok = true;
+  if (final_stage) prev_err[s] = err;
+  if (ok) {
+    active[s] = 0;
+    done[s] = 1;
+    return;
+  }
+  const double trpmu = beta * (t[0] - t[2 * J]);
+  if (!(trpmu > 0.0)) {
+    status[s] = -4;
+    active[s] = 0;
+    return;
+  }
+  double* m = mu + (int64_t)s * J;
+  double* sh = shift + (int64_t)s * J;
+  m[0] = fmin(fmax(m[0] + (Ne - t[0]) / trpmu, lo), hi);
+  for (int i = 1; i <= nk; ++i) m[i] -= t[i] / trpmu;
+  for (int i = 0; i < J; ++i) sh[i] = -c * m[i];
 }
 
 inline unsigned red_grid(int64_t n) {
@@ -348,32 +429,46 @@ inline unsigned ew_grid(int64_t n) {
 
 int reduce_blocks(int64_t n) { return (int)red_grid(n); }
 
+template <class T>
+hipError_t transpose(const T* in, int64_t Np, int64_t stride, T* out, uint16_t* const* planes,
+                     int nplanes, int batch, hipStream_t s) {
+  Planes pl{{nullptr, nullptr, nullptr}};
+  for (int p = 0; p < nplanes; ++p) pl.p[p] = planes[p];
+  const unsigned nb = (unsigned)(Np / 32);
+  hipLaunchKernelGGL(k_transpose<T>, dim3(nb, nb, batch), dim3(kT), 0, s, in, Np, stride, out, pl,
+                     nplanes);
+  return hipGetLastError();
+}
+template hipError_t transpose<double>(const double*, int64_t, int64_t, double*, uint16_t* const*,
+                                      int, int, hipStream_t);
+template hipError_t transpose<float>(const float*, int64_t, int64_t, float*, uint16_t* const*, int,
+                                     int, hipStream_t);
+
 template <class Tin, class Tout>
 hipError_t sym_combine(const Tin* in, int64_t ldi, int64_t si, int64_t N, int64_t Np, double a,
                        const double* dshift, int dstride, Tout* out, int64_t ldo, int64_t so,
-                       uint16_t* const* planes, int nplanes, int batch, hipStream_t s) {
+                       uint16_t* const* planes, int nplanes, int batch, hipStream_t s,
+                       const Tin* in2, double a2) {
   Planes pl{{nullptr, nullptr, nullptr}};
   for (int p = 0; p < nplanes; ++p) pl.p[p] = planes[p];
   const int64_t rows = (ldo == N && ldo != Np) ? N : ldo;  // caller buffer: only N x N
   const int64_t span = rows > N ? rows : N;
   const unsigned nb = (unsigned)((span + 31) / 32);
   hipLaunchKernelGGL((k_sym<Tin, Tout>), dim3(nb, nb, batch), dim3(kT), 0, s, in, ldi, si, N, Np, a,
-                     dshift, dstride, out, ldo, so, pl, nplanes, rows);
+                     dshift, dstride, out, ldo, so, pl, nplanes, rows, in2, a2);
   return hipGetLastError();
 }
 
-template hipError_t sym_combine<double, double>(const double*, int64_t, int64_t, int64_t, int64_t,
-                                                double, const double*, int, double*, int64_t,
-                                                int64_t, uint16_t* const*, int, int, hipStream_t);
-template hipError_t sym_combine<double, float>(const double*, int64_t, int64_t, int64_t, int64_t,
-                                               double, const double*, int, float*, int64_t, int64_t,
-                                               uint16_t* const*, int, int, hipStream_t);
-template hipError_t sym_combine<float, float>(const float*, int64_t, int64_t, int64_t, int64_t,
-                                              double, const double*, int, float*, int64_t, int64_t,
-                                              uint16_t* const*, int, int, hipStream_t);
-template hipError_t sym_combine<float, double>(const float*, int64_t, int64_t, int64_t, int64_t,
-                                               double, const double*, int, double*, int64_t,
-                                               int64_t, uint16_t* const*, int, int, hipStream_t);
+#define DMPT_SYM_INST(TI, TO)                                                                   \
+  template hipError_t sym_combine<TI, TO>(const TI*, int64_t, int64_t, int64_t, int64_t, double,  \
+                                          const double*, int, TO*, int64_t, int64_t,             \
+                                          uint16_t* const*, int, int, hipStream_t, const TI*,    \
+                                          double);
+DMPT_SYM_INST(double, double)
+DMPT_SYM_INST(double, float)
+DMPT_SYM_INST(float, float)
+DMPT_SYM_INST(float, double)
+#undef DMPT_SYM_INST
 
 hipError_t split_planes(const double* x, int64_t n, int64_t sx, uint16_t* const* planes, int64_t sp,
                         int nplanes, int batch, hipStream_t s) {
@@ -401,11 +496,16 @@ hipError_t sum_partials(const double* partials, int count, int batch, double* ou
   return hipGetLastError();
 }
 
-hipError_t trace(const double* x, int64_t ld, int64_t sx, int64_t N, int batch, double* out,
-                 int ostride, double* aout, hipStream_t s) {
-  hipLaunchKernelGGL(k_trace, dim3(batch), dim3(kT), 0, s, x, ld, sx, N, out, ostride, aout);
+template <class T>
+hipError_t trace(const T* x, int64_t ld, int64_t sx, int64_t N, int batch, double* out, int ostride,
+                 double* aout, hipStream_t s) {
+  hipLaunchKernelGGL(k_trace<T>, dim3(batch), dim3(kT), 0, s, x, ld, sx, N, out, ostride, aout);
   return hipGetLastError();
 }
+template hipError_t trace<double>(const double*, int64_t, int64_t, int64_t, int, double*, int,
+                                  double*, hipStream_t);
+template hipError_t trace<float>(const float*, int64_t, int64_t, int64_t, int, double*, int, double*,
+                                 hipStream_t);
 
 template <class T>
 hipError_t cg_update_xr(T* U, T* R, const T* P, const T* Q, int64_t n, int64_t stride, int batch,
@@ -441,8 +541,8 @@ template hipError_t cg_update_p<float>(float*, const float*, int64_t, int64_t, i
 
 hipError_t cg_check(const double* rr, const double* ref, int hstride, int batch, double tol2,
                     int* active, int* iters, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(64), 0, s, rr, ref, hstride, batch, tol2, active,
-                     iters);
+  hipLaunchKernelGGL(k_cg_check, dim3((batch + 63) / 64), dim3(64), 0, s, rr, ref, hstride, batch,
+                     tol2, active, iters);
   return hipGetLastError();
 }
 
@@ -475,7 +575,23 @@ template hipError_t scaled_plus_identity<float>(const float*, float*, int64_t, i
                                                 double, uint16_t* const*, int, hipStream_t);
 
 hipError_t set_values(int* p, int v, int n, double* q, double qv, int nq, hipStream_t s) {
-  hipLaunchKernelGGL(k_set, dim3(1), dim3(64), 0, s, p, v, n, q, qv, nq);
+  const int m = n > nq ? n : nq;
+  hipLaunchKernelGGL(k_set, dim3((m + 63) / 64 > 0 ? (m + 63) / 64 : 1), dim3(64), 0, s, p, v, n, q,
+                     qv, nq);
+  return hipGetLastError();
+}
+
+hipError_t expand_mask(const int* src, int div, int* dst, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_expand, dim3((n + 63) / 64), dim3(64), 0, s, src, div, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t newton_update(const double* tr, int rs, const double* par, double* mu, double* shift,
+                         int J, int nk, double tol, int final_stage, int* active, int* done,
+                         double* prev_err, double* occ, int* passes, int* status, int nsys,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_newton, dim3((nsys + 63) / 64), dim3(64), 0, s, tr, rs, par, mu, shift, J, nk,
+                     tol, final_stage, active, done, prev_err, occ, passes, status, nsys);
   return hipGetLastError();
 }
 

@@ -116,8 +116,8 @@ __global__ __launch_bounds__(kThreads) void k_gemm_f64(GemmArgs a) {
   const int64_t Np = a.Np;
   int tm, tn;
   tile_coords(blockIdx.x, (int)(Np / BM), (int)(Np / BN), tm, tn);
-  const double* X = (const double*)a.X.m + z * a.X.stride + (int64_t)tm * BM * Np;
-  const double* Y = (const double*)a.Y.m + z * a.Y.stride + (int64_t)tn * BN * Np;
+  const double* X = (const double*)a.X.m + (z / a.X.div) * a.X.stride + (int64_t)tm * BM * Np;
+  const double* Y = (const double*)a.Y.m + (z / a.Y.div) * a.Y.stride + (int64_t)tn * BN * Np;
   __shared__ double sX[2][BM][F64_LD];
   __shared__ double sY[2][BN][F64_LD];
   __shared__ double red[4];
@@ -198,8 +198,8 @@ __global__ __launch_bounds__(kThreads) void k_gemm_f32(GemmArgs a) {
   const int64_t Np = a.Np;
   int tm, tn;
   tile_coords(blockIdx.x, (int)(Np / BM), (int)(Np / BN), tm, tn);
-  const float* X = (const float*)a.X.m + z * a.X.stride + (int64_t)tm * BM * Np;
-  const float* Y = (const float*)a.Y.m + z * a.Y.stride + (int64_t)tn * BN * Np;
+  const float* X = (const float*)a.X.m + (z / a.X.div) * a.X.stride + (int64_t)tm * BM * Np;
+  const float* Y = (const float*)a.Y.m + (z / a.Y.div) * a.Y.stride + (int64_t)tn * BN * Np;
   __shared__ float sX[2][BM][F32_LD];
   __shared__ float sY[2][BN][F32_LD];
   __shared__ double red[4];
@@ -299,8 +299,8 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(GemmArgs a) {
   const uint16_t* Yp[S];
 #pragma unroll
   for (int p = 0; p < S; ++p) {
-    Xp[p] = a.X.pl[p] + z * a.X.stride + (int64_t)tm * BM * Np;
-    Yp[p] = a.Y.pl[p] + z * a.Y.stride + (int64_t)tn * BN * Np;
+    Xp[p] = a.X.pl[p] + (z / a.X.div) * a.X.stride + (int64_t)tm * BM * Np;
+    Yp[p] = a.Y.pl[p] + (z / a.Y.div) * a.Y.stride + (int64_t)tn * BN * Np;
   }
   // stage layout: [stage][operand X/Y][plane] tiles of kTileBytes
   auto tile = [&](int stage, int op, int p) -> unsigned char* {
@@ -410,7 +410,8 @@ hipError_t launch_bf16(const GemmArgs& a, dim3 grid, hipStream_t s) {
 int gemm_tiles(Engine, int64_t Np) { return (int)((Np / BM) * (Np / BN)); }
 
 hipError_t gemm(const GemmArgs& a, hipStream_t s) {
-  if (a.Np <= 0 || a.Np % BM != 0 || a.batch <= 0) return hipErrorInvalidValue;
+  if (a.Np <= 0 || a.Np % BM != 0 || a.batch <= 0 || a.X.div < 1 || a.Y.div < 1)
+    return hipErrorInvalidValue;
   const dim3 grid((unsigned)gemm_tiles(a.eng, a.Np), 1, (unsigned)a.batch);
   switch (a.eng) {
     case Engine::F64:

@@ -6,7 +6,7 @@ the canonical mu jet, response traces, max |P^(k)| and the values of P0,
 P1[d], P2[d] at a fixed set of seeded (i, j) positions (random pairs plus
 diagonal entries).
 
-    python tests/golden/make_samples.py banded8192 cubic2048
+    python tests/golden/make_samples.py banded8192 cubic2048 adjoint4096 batch64
 """
 import os
 import sys
@@ -29,7 +29,60 @@ def sample_positions(n, seed=12345, pairs=1024, diag=1024):
     return np.concatenate([i, k]), np.concatenate([j, k])
 
 
+def make_adjoint(name):
+    """Samples of G = d Tr(A P0)/d H0 with A = diag(x) (canonical, mu0 implicit)."""
+    c = workloads.config(name)
+    t0 = time.time()
+    a = np.diag(c["H1"][0]).copy()
+    G = oracle.adjoint_grad(c["H0"], c["beta"], c["Ne"], c["n"], a)
+    w, _ = np.linalg.eigh(c["H0"])
+    mu0 = oracle.mu_canonical(w, c["beta"], c["n"], c["Ne"])
+    ii, jj = sample_positions(c["N"])
+    out = dict(N=c["N"], beta=c["beta"], Ne=c["Ne"], n=c["n"], i=ii, j=jj, mu0=mu0, G=G[ii, jj],
+               max_G=np.abs(G).max(), trace_G=np.trace(G), seconds=time.time() - t0)
+    path = os.path.join(HERE, f"{name}_samples.npz")
+    np.savez_compressed(path, **out)
+    print(f"{name}: {time.time() - t0:.1f} s -> {path}", flush=True)
+
+
+def make_batch(name):
+    """Per-system mu jets, response traces and sampled P0 / P1 of the batch workload."""
+    c = workloads.CONFIGS[name]
+    t0 = time.time()
+    systems = workloads.batched_systems(c["seed"], count=c["count"])
+    rows = dict(N=[], beta=[], Ne=[], mu0=[], mu1=[], tr_h1p1=[], i=[], j=[], P0=[], P1=[],
+                max_P1=[])
+    for k, sy in enumerate(systems):
+        lx, ly, lz = sy["dims"]
+        h0 = workloads.cubic_lattice(lx, ly, lz, sy["seed"])
+        h1 = list(workloads.lattice_dipoles(lx, ly, lz))[: c["dirs"]]
+        r = oracle.canonical_response(h0, h1, None, sy["beta"], sy["Ne"], c["n"], order=1)
+        rng = np.random.default_rng(k)
+        ii = rng.integers(0, sy["N"], 64)
+        jj = np.where(np.arange(64) % 2 == 0, ii, rng.integers(0, sy["N"], 64))
+        rows["N"].append(sy["N"])
+        rows["beta"].append(sy["beta"])
+        rows["Ne"].append(sy["Ne"])
+        rows["mu0"].append(r["mu0"])
+        rows["mu1"].append(r["mu1"])
+        rows["tr_h1p1"].append(r["tr_h1p1"])
+        rows["i"].append(ii)
+        rows["j"].append(jj)
+        rows["P0"].append(r["P0"][ii, jj])
+        rows["P1"].append([p[ii, jj] for p in r["P1"]])
+        rows["max_P1"].append([np.abs(p).max() for p in r["P1"]])
+    out = {k: np.array(v) for k, v in rows.items()}
+    out["seconds"] = time.time() - t0
+    path = os.path.join(HERE, f"{name}_samples.npz")
+    np.savez_compressed(path, **out)
+    print(f"{name}: {time.time() - t0:.1f} s -> {path}", flush=True)
+
+
 def make(name):
+    if name.startswith("adjoint"):
+        return make_adjoint(name)
+    if name.startswith("batch"):
+        return make_batch(name)
     c = workloads.config(name)
     t0 = time.time()
     h1v = [np.diag(h).copy() for h in c["H1"]]   # the perturbations are diagonal
@@ -52,5 +105,5 @@ def make(name):
 
 
 if __name__ == "__main__":
-    for name in sys.argv[1:] or ["cubic2048", "banded8192"]:
+    for name in sys.argv[1:] or ["cubic2048", "banded8192", "adjoint4096", "batch64"]:
         make(name)
