@@ -198,6 +198,21 @@ typedef struct {
 dmpt_status dmpt_profile(dmpt_ctx ctx, int enable);
 dmpt_status dmpt_profile_get(dmpt_ctx ctx, dmpt_profile_data* out);
 
+/* Time the matrix-product kernel alone: `reps` products C = X Y^T of size N
+ * (N <= n_max; X, Y, C are workspace matrices filled with a fixed pattern)
+ * in precision `prec` with output tile edge `tile` (0: the library's
+ * choice, else 128 or 256).  *ms: mean device time per product (HIP events
+ * on the context stream); *tflops: matrix-core TFLOP/s (every split product
+ * counted).  prec must not need more workspace than the context holds. */
+dmpt_status dmpt_bench_product(dmpt_ctx ctx, int64_t N, dmpt_prec prec, int tile, int reps,
+                               double* ms, double* tflops);
+
+/* Product-tile autotuner: times every tile edge available for the
+ * context's precision at size N and keeps the fastest for all later
+ * products of that padded size on this context.  *tile (may be NULL)
+ * receives the choice. */
+dmpt_status dmpt_autotune(dmpt_ctx ctx, int64_t N, int* tile);
+
 #ifdef __cplusplus
 }
 #endif

@@ -122,6 +122,20 @@ class Context:
         return dict(launches=d.launches, ms=d.ms, mfma_flops=d.mfma_flops,
                     useful_flops=d.useful_flops)
 
+    def bench_product(self, N, prec=None, tile=0, reps=10):
+        """Mean device ms and TFLOP/s of the product kernel alone at size N."""
+        p = self.opts.prec if prec is None else L.PREC[prec]
+        ms, tf = ctypes.c_double(), ctypes.c_double()
+        self._raise(self.lib.dmpt_bench_product(self.h, int(N), int(p), int(tile), int(reps),
+                                                ctypes.byref(ms), ctypes.byref(tf)))
+        return ms.value, tf.value
+
+    def autotune(self, N):
+        """Pick the fastest product tile for size N (kept for later calls)."""
+        t = ctypes.c_int()
+        self._raise(self.lib.dmpt_autotune(self.h, int(N), ctypes.byref(t)))
+        return t.value
+
     # ------------------------------------------------------------------ calls
     def fermi_recursion(self, H0, beta, mu, n, out=None):
         """Grand-canonical P0 at fixed mu (Eq. Rec_F_2).  Returns (P0, stats)."""

@@ -67,6 +67,8 @@ struct dmpt_ctx_s {
   // D_m (AD), checkpoints CK and the recomputed segment SG
   Group AY, AU, AW, AV, AG, AD, CK, SG;
   std::vector<void*> ad_allocs;
+  int tile_pref = 0;             // product tile edge: 0 = largest available
+  std::vector<std::pair<int64_t, int>> tuned;  // autotuned tile edge per padded size
   // larger partial-sum blocks allocated by batched calls
   std::vector<void*> bt_allocs;
   // scalars
@@ -244,6 +246,12 @@ dmpt_status prof_resolve(dmpt_ctx c) {
   return DMPT_OK;
 }
 
+int tile_for(dmpt_ctx c, int64_t Np) {
+  for (auto& t : c->tuned)
+    if (t.first == Np) return t.second;
+  return c->tile_pref;
+}
+
 dmpt_status run_gemm(const Call& k, const G& g) {
   GemmArgs a{};
   a.eng = k.eng;
@@ -260,6 +268,7 @@ dmpt_status run_gemm(const Call& k, const G& g) {
   a.W = g.W; a.sW = g.sW;
   a.partials = k.c->d_part;
   a.active = g.active;
+  a.tile = tile_for(k.c, k.Np);
   const double n3 = 2.0 * (double)k.Np * k.Np * k.Np;
   const double mf = n3 * engine_terms(k.eng) * g.batch;
   const double uf = 2.0 * (double)k.N * k.N * k.N * g.batch;
@@ -283,8 +292,8 @@ dmpt_status run_gemm(const Call& k, const G& g) {
 
 // Sum the GEMM per-tile partials into out[z*ostride + oidx].
 dmpt_status sum_gemm_partials(const Call& k, int batch, double* out, int ostride, int oidx) {
-  HIPCHK(k.c, sum_partials(k.c->d_part, gemm_tiles(k.eng, k.Np), batch, out, ostride, oidx,
-                           k.c->stream));
+  HIPCHK(k.c, sum_partials(k.c->d_part, gemm_tiles(k.eng, k.Np, tile_for(k.c, k.Np)), batch, out,
+                           ostride, oidx, k.c->stream));
   return DMPT_OK;
 }
 
@@ -1299,6 +1308,90 @@ dmpt_status dmpt_profile_get(dmpt_ctx c, dmpt_profile_data* out) {
   HIPCHK(c, hipStreamSynchronize(c->stream));
   STCHK(prof_resolve(c));
   *out = c->prof;
+  return DMPT_OK;
+}
+
+dmpt_status dmpt_bench_product(dmpt_ctx c, int64_t N, dmpt_prec prec, int tile, int reps, double* ms,
+                               double* tflops) {
+  if (!c || !ms) return DMPT_ERR_ARG;
+  if (N < 1 || N > c->n_max) return fail(c, DMPT_ERR_ARG, "N must lie in [1, n_max]");
+  if (reps < 1 || reps > 100000) return fail(c, DMPT_ERR_ARG, "reps must lie in [1, 100000]");
+  if (tile != 0 && tile != 128 && tile != 256) return fail(c, DMPT_ERR_ARG, "tile must be 0, 128 or 256");
+  if (prec < DMPT_FP64 || prec > DMPT_BF16X6) return fail(c, DMPT_ERR_ARG, "unknown precision");
+  dmpt_options o = c->opt;
+  o.prec = prec;
+  o.refine = 0;
+  if (esize_needed(o) != c->esize || planes_needed(o) > c->planes)
+    return fail(c, DMPT_ERR_NOMEM, "precision needs a different workspace than the context holds");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, DMPT_ERR_HIP, "hipSetDevice failed");
+  Call k = make_call(c, N, false);
+  k.eng = engine_of(prec);
+  k.np = engine_planes(k.eng);
+  hipStream_t s = c->stream;
+  uint16_t* px[3];
+  uint16_t* py[3];
+  planes_of(k, c->ws.D0, 0, px);
+  planes_of(k, c->ws.S0, 0, py);
+  if (k.f64) {
+    HIPCHK(c, fill_pattern<double>((double*)mptr(k, c->ws.D0, 0), k.nn, 1u, px, k.np, s));
+    HIPCHK(c, fill_pattern<double>((double*)mptr(k, c->ws.S0, 0), k.nn, 2u, py, k.np, s));
+  } else {
+    HIPCHK(c, fill_pattern<float>((float*)mptr(k, c->ws.D0, 0), k.nn, 1u, px, k.np, s));
+    HIPCHK(c, fill_pattern<float>((float*)mptr(k, c->ws.S0, 0), k.nn, 2u, py, k.np, s));
+  }
+  GemmArgs a{};
+  a.eng = k.eng;
+  a.Np = k.Np;
+  a.batch = 1;
+  a.X = op(k, c->ws.D0, 0, false);
+  a.Y = op(k, c->ws.S0, 0, false);
+  a.C = mptr(k, c->ws.R, 0);
+  a.alpha = 1.0;
+  a.partials = c->d_part;
+  a.tile = tile;
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  HIPCHK(c, gemm(a, s));  // warm-up (and LDS attribute)
+  HIPCHK(c, hipEventRecord(e0, s));
+  for (int r = 0; r < reps; ++r) HIPCHK(c, gemm(a, s));
+  HIPCHK(c, hipEventRecord(e1, s));
+  HIPCHK(c, hipEventSynchronize(e1));
+  float t = 0.f;
+  HIPCHK(c, hipEventElapsedTime(&t, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = t / reps;
+  if (tflops)
+    *tflops = 2.0 * (double)k.Np * k.Np * k.Np * engine_terms(k.eng) / (*ms * 1e-3) / 1e12;
+  return DMPT_OK;
+}
+
+dmpt_status dmpt_autotune(dmpt_ctx c, int64_t N, int* tile) {
+  if (!c) return DMPT_ERR_ARG;
+  if (N < 1 || N > c->n_max) return fail(c, DMPT_ERR_ARG, "N must lie in [1, n_max]");
+  const int64_t Np = padded(N);
+  const Engine eng = engine_of(c->opt.prec);
+  const int cand[2] = {128, 256};
+  int best = 128;
+  double best_ms = INFINITY;
+  for (int t : cand) {
+    if (gemm_tile_edge(eng, Np, t) != t) continue;  // not available for this engine / size
+    double ms = 0.0;
+    STCHK(dmpt_bench_product(c, N, c->opt.prec, t, 3, &ms, nullptr));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = t;
+    }
+  }
+  bool found = false;
+  for (auto& p : c->tuned)
+    if (p.first == Np) {
+      p.second = best;
+      found = true;
+    }
+  if (!found) c->tuned.push_back({Np, best});
+  if (tile) *tile = best;
   return DMPT_OK;
 }
 

@@ -59,10 +59,13 @@ struct GemmArgs {
   const void* W; int64_t sW;   // optional: per-tile partials of <W, C>
   double* partials;            // [batch][tiles]
   const int* active;           // optional per-batch mask; 0 = skip the member
+  int tile;                    // output tile edge wanted: 0 = largest available, 128, 256
 };
 
-// Number of output tiles of a product of size Np (per batch member).
-int gemm_tiles(Engine eng, int64_t Np);
+// Output tile edge, and number of output tiles per batch member, of the
+// kernel that gemm() launches for this engine, size and tile preference.
+int gemm_tile_edge(Engine eng, int64_t Np, int tile_pref);
+int gemm_tiles(Engine eng, int64_t Np, int tile_pref);
 hipError_t gemm(const GemmArgs& a, hipStream_t s);
 
 // ---------------------------------------------------------------- element-wise
@@ -131,6 +134,11 @@ hipError_t scaled_plus_identity(const T* x, T* out, int64_t N, int64_t Np, doubl
 hipError_t set_values(int* p, int v, int n, double* q, double qv, int nq, hipStream_t s);
 // dst[z] = src[z / div] for z < n (member masks from system masks)
 hipError_t expand_mask(const int* src, int div, int* dst, int n, hipStream_t s);
+
+// Hashed pattern in [-1, 1) (with planes), for timing runs.
+template <class T>
+hipError_t fill_pattern(T* x, int64_t n, uint32_t seed, uint16_t* const* planes, int nplanes,
+                        hipStream_t s);
 
 // Device-side canonical Newton update of a batch of systems (see elementwise.hip).
 hipError_t newton_update(const double* tr, int rs, const double* par, double* mu, double* shift,

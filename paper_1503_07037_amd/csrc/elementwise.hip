@@ -365,6 +365,20 @@ __global__ void k_expand(const int* src, int div, int* dst, int n) {
   if (i < n) dst[i] = src[i / div];
 }
 
+// Deterministic non-trivial fill (a hashed pattern in [-1, 1)) with planes.
+template <class T>
+__global__ __launch_bounds__(kT) void k_fill(T* x, int64_t n, uint32_t seed, Planes pl, int np) {
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+    uint32_t h = (uint32_t)i * 2654435761u ^ seed;
+    h ^= h >> 15;
+    h *= 2246822519u;
+    h ^= h >> 13;
+    const T v = (T)((double)(h & 0xffffff) / 8388608.0 - 1.0);
+    x[i] = v;
+    if (np) split_store((double)v, pl.p, np, i);
+  }
+}
+
 // Canonical Newton update of every system of a batch (Algorithm 1's mu
 // update with Tr P_mu = beta (Tr P0 - ||P0||_F^2)), one thread per system.
 // tr[s*rs + ...]: Tr P^(k) (J values), sum |P^(k)_ii| (J), ||P0||_F^2.
@@ -585,6 +599,17 @@ hipError_t expand_mask(const int* src, int div, int* dst, int n, hipStream_t s) 
   hipLaunchKernelGGL(k_expand, dim3((n + 63) / 64), dim3(64), 0, s, src, div, dst, n);
   return hipGetLastError();
 }
+
+template <class T>
+hipError_t fill_pattern(T* x, int64_t n, uint32_t seed, uint16_t* const* planes, int nplanes,
+                        hipStream_t s) {
+  Planes pl{{nullptr, nullptr, nullptr}};
+  for (int p = 0; p < nplanes; ++p) pl.p[p] = planes[p];
+  hipLaunchKernelGGL(k_fill<T>, dim3(ew_grid(n)), dim3(kT), 0, s, x, n, seed, pl, nplanes);
+  return hipGetLastError();
+}
+template hipError_t fill_pattern<double>(double*, int64_t, uint32_t, uint16_t* const*, int, hipStream_t);
+template hipError_t fill_pattern<float>(float*, int64_t, uint32_t, uint16_t* const*, int, hipStream_t);
 
 hipError_t newton_update(const double* tr, int rs, const double* par, double* mu, double* shift,
                          int J, int nk, double tol, int final_stage, int* active, int* done,

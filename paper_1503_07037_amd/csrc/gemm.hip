@@ -391,6 +391,140 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(GemmArgs a) {
   }
 }
 
+// ------------------------------------------------------------------ split BF16, 256 x 256
+// Large-tile variant for Np a multiple of 256: each of the four waves owns a
+// 128 x 128 block (4 x 4 MFMA tiles of 32 x 32), which halves the L2 and LDS
+// traffic per MFMA of the 128 x 128 kernel.  K is staged BK at a time
+// through a two-stage LDS ring (BK = 32 for two planes, 16 for three, so the
+// ring fits in the 160 KB of LDS).  Row r of a plane tile holds BK/8 chunks
+// of 16 B; chunk c sits at c ^ swizzle(r) so a group of eight lanes reading
+// eight consecutive rows hits eight different 16-byte bank groups.
+constexpr int BM2 = 256;
+
+template <int BK>
+__device__ inline int swz2(int row, int c) {
+  if constexpr (BK == 32) return row * 64 + ((c ^ ((row >> 1) & 3)) << 4);
+  else return row * 32 + ((c ^ ((row >> 2) & 1)) << 4);
+}
+
+template <int S, int BK>
+__global__ __launch_bounds__(kThreads) void k_gemm_bf16_256(GemmArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  __shared__ double red[4];
+  constexpr int kTile = BM2 * BK * 2;              // bytes of one plane tile
+  constexpr int kChunks = BK / 8;                  // 16-byte chunks per row
+  constexpr int kLoads = BM2 * kChunks / kThreads; // 16-byte loads per thread, plane and operand
+  const int z = blockIdx.z;
+  if (a.active && !a.active[z]) return;
+  const int64_t Np = a.Np;
+  int tm, tn;
+  tile_coords(blockIdx.x, (int)(Np / BM2), (int)(Np / BM2), tm, tn);
+  const uint16_t* Xp[S];
+  const uint16_t* Yp[S];
+#pragma unroll
+  for (int p = 0; p < S; ++p) {
+    Xp[p] = a.X.pl[p] + (z / a.X.div) * a.X.stride + (int64_t)tm * BM2 * Np;
+    Yp[p] = a.Y.pl[p] + (z / a.Y.div) * a.Y.stride + (int64_t)tn * BM2 * Np;
+  }
+  auto tile = [&](int stage, int op, int p) -> unsigned char* {
+    return smem + ((stage * 2 + op) * S + p) * kTile;
+  };
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  u4v rx[S][kLoads], ry[S][kLoads];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int p = 0; p < S; ++p)
+#pragma unroll
+      for (int i = 0; i < kLoads; ++i) {
+        const int idx = tid + i * kThreads, row = idx / kChunks, c = idx % kChunks;
+        rx[p][i] = *(const u4v*)(Xp[p] + (int64_t)row * Np + k0 + 8 * c);
+        ry[p][i] = *(const u4v*)(Yp[p] + (int64_t)row * Np + k0 + 8 * c);
+      }
+  };
+  auto swrite = [&](int stage) {
+#pragma unroll
+    for (int p = 0; p < S; ++p)
+#pragma unroll
+      for (int i = 0; i < kLoads; ++i) {
+        const int idx = tid + i * kThreads, row = idx / kChunks, c = idx % kChunks;
+        *(u4v*)(tile(stage, 0, p) + swz2<BK>(row, c)) = rx[p][i];
+        *(u4v*)(tile(stage, 1, p) + swz2<BK>(row, c)) = ry[p][i];
+      }
+  };
+  f16v acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+  gload(0);
+  swrite(0);
+  __syncthreads();
+  const int nk = (int)(Np / BK);
+  for (int kt = 0; kt < nk; ++kt) {
+    const int st = kt & 1;
+    if (kt + 1 < nk) gload((kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK / 16; ++kk) {
+      const int c = kk * 2 + (lane >> 5);
+      bf8v xa[S][4], yb[S][4];
+#pragma unroll
+      for (int p = 0; p < S; ++p) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          xa[p][i] = __builtin_bit_cast(
+              bf8v, *(const u4v*)(tile(st, 0, p) + swz2<BK>(wm * 128 + i * 32 + (lane & 31), c)));
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          yb[p][j] = __builtin_bit_cast(
+              bf8v, *(const u4v*)(tile(st, 1, p) + swz2<BK>(wn * 128 + j * 32 + (lane & 31), c)));
+      }
+#pragma unroll
+      for (int t = S - 1; t >= 0; --t)
+#pragma unroll
+        for (int p = 0; p <= t; ++p)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa[p][i], yb[t - p][j], acc[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < nk) swrite(st ^ 1);
+    __syncthreads();
+  }
+  double dsum = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t row = (int64_t)tm * BM2 + wm * 128 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int64_t col = (int64_t)tn * BM2 + wn * 128 + j * 32 + (lane & 31);
+        epi<double>(a, z, row * Np + col, (double)acc[i][j][r], dsum);
+      }
+  if (a.W) {
+    const double s = block_sum(dsum, red);
+    if (tid == 0) a.partials[(int64_t)z * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+template <int S, int BK>
+hipError_t launch_bf16_256(const GemmArgs& a, dim3 grid, hipStream_t s) {
+  const size_t lds = (size_t)2 * 2 * S * BM2 * BK * 2;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_gemm_bf16_256<S, BK>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((k_gemm_bf16_256<S, BK>), grid, dim3(kThreads), lds, s, a);
+  return hipGetLastError();
+}
+
 template <int S>
 hipError_t launch_bf16(const GemmArgs& a, dim3 grid, hipStream_t s) {
   const size_t lds = (size_t)2 * 2 * S * kTileBytes;
@@ -407,12 +541,24 @@ hipError_t launch_bf16(const GemmArgs& a, dim3 grid, hipStream_t s) {
 
 }  // namespace
 
-int gemm_tiles(Engine, int64_t Np) { return (int)((Np / BM) * (Np / BN)); }
+// Output tile edge of the kernel `gemm` uses for an engine and size: the
+// 256-wide split-BF16 kernel when Np allows it and the tile choice allows it.
+int gemm_tile_edge(Engine eng, int64_t Np, int tile_pref) {
+  const bool bf = eng == Engine::BF16S2 || eng == Engine::BF16S3;
+  if (bf && tile_pref != 128 && Np % BM2 == 0) return BM2;
+  return BM;
+}
+
+int gemm_tiles(Engine eng, int64_t Np, int tile_pref) {
+  const int e = gemm_tile_edge(eng, Np, tile_pref);
+  return (int)((Np / e) * (Np / e));
+}
 
 hipError_t gemm(const GemmArgs& a, hipStream_t s) {
   if (a.Np <= 0 || a.Np % BM != 0 || a.batch <= 0 || a.X.div < 1 || a.Y.div < 1)
     return hipErrorInvalidValue;
-  const dim3 grid((unsigned)gemm_tiles(a.eng, a.Np), 1, (unsigned)a.batch);
+  const int edge = gemm_tile_edge(a.eng, a.Np, a.tile);
+  const dim3 grid((unsigned)gemm_tiles(a.eng, a.Np, a.tile), 1, (unsigned)a.batch);
   switch (a.eng) {
     case Engine::F64:
       hipLaunchKernelGGL(k_gemm_f64, grid, dim3(kThreads), 0, s, a);
@@ -421,9 +567,9 @@ hipError_t gemm(const GemmArgs& a, hipStream_t s) {
       hipLaunchKernelGGL(k_gemm_f32, grid, dim3(kThreads), 0, s, a);
       return hipGetLastError();
     case Engine::BF16S2:
-      return launch_bf16<2>(a, grid, s);
+      return edge == BM2 ? launch_bf16_256<2, 32>(a, grid, s) : launch_bf16<2>(a, grid, s);
     case Engine::BF16S3:
-      return launch_bf16<3>(a, grid, s);
+      return edge == BM2 ? launch_bf16_256<3, 16>(a, grid, s) : launch_bf16<3>(a, grid, s);
   }
   return hipErrorInvalidValue;
 }
