@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tol-cg", type=float, default=0.0)
     ap.add_argument("--tol-occ", type=float, default=0.0)
+    ap.add_argument("--refine", type=int, default=-1,
+                    help="bf16x3: finish with the 6-product refinement passes (default on)")
     return ap.parse_args()
 
 
@@ -109,7 +111,9 @@ def main():
     H0 = torch.tensor(c["H0"], device=dev)
     H1 = [torch.tensor(h, device=dev) for h in c["H1"]]
     torch.cuda.synchronize()
-    ctx = dm.Context(N, dirs_max=d, prec=args.prec, tol_cg=args.tol_cg, tol_occ=args.tol_occ)
+    refine = (1 if args.prec == "bf16x3" else 0) if args.refine < 0 else args.refine
+    ctx = dm.Context(N, dirs_max=d, prec=args.prec, tol_cg=args.tol_cg, tol_occ=args.tol_occ,
+                     refine=refine)
 
     def step():
         return ctx.mu_newton(H0, H1, None, beta=c["beta"], Ne=c["Ne"], n=c["n"], order=order)
@@ -133,9 +137,12 @@ def main():
     P0, P1, P2, mu, st = out
     ms_step = 1e3 * secs / args.steps
     value = d * args.steps / secs
-    avg_ms = prof["ms"] / max(prof["launches"], 1)
-    achieved = prof["mfma_flops"] / max(prof["ms"], 1e-12) / 1e9   # TFLOP/s
-    peak = PEAKS_TFLOPS[args.prec]
+    # dominant product kernel: the engine with the most device time
+    dom = max(prof["engines"], key=lambda e: prof["engines"][e]["ms"])
+    pe = prof["engines"][dom]
+    avg_ms = pe["ms"] / max(pe["launches"], 1)
+    achieved = pe["mfma_flops"] / max(pe["ms"], 1e-12) / 1e9   # TFLOP/s
+    peak = PEAKS_TFLOPS[dom]
     name = args.workload if not args.n else None
     acc = accuracy(name, P0, P1, P2, mu) if name else None
     res = {
@@ -147,11 +154,16 @@ def main():
                                f"beta={c['beta']}, n={c['n']}, Ne={c['Ne']}" if args.workload == "banded8192"
                    else args.workload,
                    "N": N, "dirs": d, "order": order, "beta": c["beta"], "n": c["n"],
-                   "precision": args.prec, "parallelism": "single GPU"},
+                   "precision": args.prec + ("+refine(bf16x6)" if refine else ""),
+                   "parallelism": "single GPU"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None,
-                     "kernel": f"split product kernel ({args.prec})", "launches": prof["launches"],
-                     "avg_launch_ms": avg_ms},
+                     "kernel": f"product kernel, {dom} engine", "launches": pe["launches"],
+                     "avg_launch_ms": avg_ms,
+                     "product_time_share": prof["ms"] / ms_step / args.steps,
+                     "engines": {e: {"launches": v["launches"], "ms": v["ms"],
+                                     "tflops": v["mfma_flops"] / max(v["ms"], 1e-12) / 1e9}
+                                 for e, v in prof["engines"].items() if v["launches"]}},
         "mfma_tflops_whole_step": st["mfma_flops"] / (ms_step / 1e3) / 1e12,
         "useful_tflops_whole_step": st["useful_flops"] / (ms_step / 1e3) / 1e12,
         "newton_iters": st["newton_iters"], "cg_iters_total": st["cg_iters_total"],

@@ -90,6 +90,9 @@ typedef struct {
   int ckpt_every;       /* adjoint: keep every ckpt_every-th iterate, recompute the rest (default 5) */
   int check;            /* 1: compute the commutator and idempotency checks at the end of a call */
   int staged;           /* 1: converge mu0 with order-0 passes first, then run full passes (same fixed point) */
+  int warm_traj;        /* 1: keep every step's iterates (FP32 copies) and start each CG of the next
+                           Newton pass from the same step's previous solution instead of the
+                           previous recursion step's iterate; falls back when memory is short */
 } dmpt_options;
 
 #define DMPT_MAX_DIRS 8
@@ -193,6 +196,10 @@ typedef struct {
   double ms;             /* summed device time of those launches (ms) */
   double mfma_flops;     /* matrix-core flops of those launches (every split product counted) */
   double useful_flops;   /* 2 N^3 per logical product and batch member */
+  /* the same, per product engine: [0] FP64, [1] FP32, [2] BF16 3-product, [3] BF16 6-product */
+  int64_t eng_launches[4];
+  double eng_ms[4];
+  double eng_mfma_flops[4];
 } dmpt_profile_data;
 
 dmpt_status dmpt_profile(dmpt_ctx ctx, int enable);

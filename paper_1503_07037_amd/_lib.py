@@ -37,6 +37,7 @@ class Options(ctypes.Structure):
         ("tol_occ", ctypes.c_double), ("tol_cg", ctypes.c_double),
         ("max_newton", ctypes.c_int), ("max_cg", ctypes.c_int), ("refine", ctypes.c_int),
         ("ckpt_every", ctypes.c_int), ("check", ctypes.c_int), ("staged", ctypes.c_int),
+        ("warm_traj", ctypes.c_int),
     ]
 
 
@@ -66,7 +67,9 @@ class Stats(ctypes.Structure):
 
 class ProfileData(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double),
-                ("mfma_flops", ctypes.c_double), ("useful_flops", ctypes.c_double)]
+                ("mfma_flops", ctypes.c_double), ("useful_flops", ctypes.c_double),
+                ("eng_launches", ctypes.c_int64 * 4), ("eng_ms", ctypes.c_double * 4),
+                ("eng_mfma_flops", ctypes.c_double * 4)]
 
 
 EXPORTS = [

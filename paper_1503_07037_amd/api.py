@@ -26,7 +26,7 @@ def _torch():
 
 
 def options(prec="fp64", solver="cg", guess="prev", tol_occ=0.0, tol_cg=0.0, max_newton=50,
-            max_cg=60, refine=0, ckpt_every=5, check=0, staged=1):
+            max_cg=60, refine=0, ckpt_every=5, check=0, staged=1, warm_traj=1):
     """Build an options struct; 0 tolerances select the precision's defaults."""
     lib = L.load()
     o = L.Options()
@@ -37,6 +37,7 @@ def options(prec="fp64", solver="cg", guess="prev", tol_occ=0.0, tol_cg=0.0, max
     o.tol_occ, o.tol_cg = float(tol_occ), float(tol_cg)
     o.max_newton, o.max_cg, o.refine = int(max_newton), int(max_cg), int(refine)
     o.ckpt_every, o.check, o.staged = int(ckpt_every), int(check), int(staged)
+    o.warm_traj = int(warm_traj)
     return o
 
 
@@ -119,8 +120,11 @@ class Context:
         """Totals since the last reset: launches, ms, mfma_flops, useful_flops."""
         d = L.ProfileData()
         self._raise(self.lib.dmpt_profile_get(self.h, ctypes.byref(d)))
+        names = ["fp64", "fp32", "bf16x3", "bf16x6"]
         return dict(launches=d.launches, ms=d.ms, mfma_flops=d.mfma_flops,
-                    useful_flops=d.useful_flops)
+                    useful_flops=d.useful_flops,
+                    engines={names[i]: dict(launches=d.eng_launches[i], ms=d.eng_ms[i],
+                                            mfma_flops=d.eng_mfma_flops[i]) for i in range(4)})
 
     def bench_product(self, N, prec=None, tile=0, reps=10):
         """Mean device ms and TFLOP/s of the product kernel alone at size N."""

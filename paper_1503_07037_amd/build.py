@@ -22,6 +22,8 @@ FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # unroll the MFMA loops completely so the accumulator tiles stay in registers
+    "-mllvm", "-unroll-threshold=100000",
     "-I" + INCLUDE, "-I" + CSRC,
 ]
 

@@ -67,8 +67,18 @@ struct dmpt_ctx_s {
   // D_m (AD), checkpoints CK and the recomputed segment SG
   Group AY, AU, AW, AV, AG, AD, CK, SG;
   std::vector<void*> ad_allocs;
+  // every device allocation of the context (base, bytes): launches are
+  // checked against it on the host before they are queued
+  std::vector<std::pair<const char*, size_t>> regions;
   int tile_pref = 0;             // product tile edge: 0 = largest available
   std::vector<std::pair<int64_t, int>> tuned;  // autotuned tile edge per padded size
+  // iterates of the previous Newton pass (FP32 copies, warm starts):
+  // [step][jet member] of tj_np^2 each; tj_valid = highest order stored
+  float* tj = nullptr;
+  size_t tj_bytes = 0;
+  int64_t tj_np = 0;
+  int tj_valid = -1;
+  Group U0;                      // order-0 CG unknown when the guess comes from tj
   // larger partial-sum blocks allocated by batched calls
   std::vector<void*> bt_allocs;
   // scalars
@@ -86,6 +96,7 @@ struct dmpt_ctx_s {
   struct Timed {
     hipEvent_t a, b;
     double mfma, useful;
+    int eng;
   };
   std::vector<Timed> prof_pending;
   std::vector<hipEvent_t> prof_pool;
@@ -185,6 +196,8 @@ struct Call {
   int m = 1;                     // systems in the pass (members of D0, S0)
   bool graph = false;            // no host synchronisation: fixed CG iteration counts
   int cg_iters = 0;              // iterations per solve when graph is set
+  bool traj = false;             // single system: read / write the trajectory c->tj
+  int jets = 1;                  // members per step in c->tj (1 + 2 d)
 };
 
 // Member z of a group as an operand.
@@ -218,6 +231,42 @@ struct G {
   const int* active = nullptr;
 };
 
+// ------------------------------------------------------------------ host-side bounds
+void reg_add(dmpt_ctx c, void* p, size_t bytes) { c->regions.push_back({(const char*)p, bytes}); }
+
+void reg_del(dmpt_ctx c, void* p) {
+  for (size_t i = 0; i < c->regions.size(); ++i)
+    if (c->regions[i].first == (const char*)p) {
+      c->regions.erase(c->regions.begin() + i);
+      return;
+    }
+}
+
+// True when [p, p + bytes) lies inside one device allocation of the context.
+bool reg_ok(dmpt_ctx c, const void* p, size_t bytes) {
+  const char* q = (const char*)p;
+  for (auto& r : c->regions)
+    if (q >= r.first && q + bytes <= r.first + r.second) return true;
+  return false;
+}
+
+// hipMalloc that records the allocation.
+void* dev_alloc(dmpt_ctx c, size_t bytes) {
+  void* p = nullptr;
+  if (hipMalloc(&p, std::max<size_t>(bytes, 256)) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  reg_add(c, p, std::max<size_t>(bytes, 256));
+  return p;
+}
+
+void dev_free(dmpt_ctx c, void* p) {
+  if (!p) return;
+  reg_del(c, p);
+  (void)hipFree(p);
+}
+
 dmpt_status prof_event(dmpt_ctx c, hipEvent_t* e) {
   if (!c->prof_pool.empty()) {
     *e = c->prof_pool.back();
@@ -239,6 +288,9 @@ dmpt_status prof_resolve(dmpt_ctx c) {
     c->prof.ms += ms;
     c->prof.mfma_flops += t.mfma;
     c->prof.useful_flops += t.useful;
+    c->prof.eng_launches[t.eng] += 1;
+    c->prof.eng_ms[t.eng] += ms;
+    c->prof.eng_mfma_flops[t.eng] += t.mfma;
     c->prof_pool.push_back(t.a);
     c->prof_pool.push_back(t.b);
   }
@@ -269,6 +321,28 @@ dmpt_status run_gemm(const Call& k, const G& g) {
   a.partials = k.c->d_part;
   a.active = g.active;
   a.tile = tile_for(k.c, k.Np);
+  // every member the launch touches must lie inside a workspace allocation
+  {
+    dmpt_ctx c = k.c;
+    const size_t es = c->esize, nn = (size_t)k.nn;
+    const int b = g.batch;
+    auto span = [&](int64_t stride, int div) -> size_t {
+      return (stride ? (size_t)((b - 1) / div) * (size_t)stride : 0) + nn;
+    };
+    bool ok = b >= 1 && reg_ok(c, a.X.m, span(a.X.stride, a.X.div) * es) &&
+              reg_ok(c, a.Y.m, span(a.Y.stride, a.Y.div) * es) && reg_ok(c, a.C, span(a.sC, 1) * es);
+    for (int p = 0; p < k.np && ok; ++p)
+      ok = a.X.pl[p] && a.Y.pl[p] && reg_ok(c, a.X.pl[p], span(a.X.stride, a.X.div) * 2) &&
+           reg_ok(c, a.Y.pl[p], span(a.Y.stride, a.Y.div) * 2);
+    for (int p = 0; p < 3 && ok; ++p)
+      if (a.Cpl[p]) ok = reg_ok(c, a.Cpl[p], span(a.sC, 1) * 2);
+    if (ok && a.C1) ok = reg_ok(c, a.C1, span(a.sC1, 1) * es);
+    if (ok && a.C2) ok = reg_ok(c, a.C2, span(a.sC2, 1) * es);
+    if (ok && a.W) ok = reg_ok(c, a.W, span(a.sW, 1) * es) &&
+                        (size_t)b * gemm_tiles(k.eng, k.Np, a.tile) <= c->part_count;
+    if (ok && b > 1) ok = a.sC != 0;
+    if (!ok) return fail(c, DMPT_ERR_ARG, "internal: a product would leave its workspace");
+  }
   const double n3 = 2.0 * (double)k.Np * k.Np * k.Np;
   const double mf = n3 * engine_terms(k.eng) * g.batch;
   const double uf = 2.0 * (double)k.N * k.N * k.N * g.batch;
@@ -283,7 +357,7 @@ dmpt_status run_gemm(const Call& k, const G& g) {
   HIPCHK(c, gemm(a, c->stream));
   if (c->prof_on) {
     HIPCHK(c, hipEventRecord(eb, c->stream));
-    c->prof_pending.push_back({ea, eb, mf, uf});
+    c->prof_pending.push_back({ea, eb, mf, uf, (int)k.eng});
   }
   c->mfma_flops += mf;
   c->useful_flops += uf;
@@ -300,6 +374,7 @@ dmpt_status sum_gemm_partials(const Call& k, int batch, double* out, int ostride
 // ------------------------------------------------------------------ typed helpers
 template <class T>
 dmpt_status sym_inplace(const Call& k, const Group& g, int z0, int batch, double a) {
+  if (z0 < 0 || z0 + batch > g.count) return fail(k.c, DMPT_ERR_ARG, "internal: sym batch too large");
   uint16_t* pl[3];
   planes_of(k, g, z0, pl);
   T* m = (T*)mptr(k, g, z0);
@@ -311,6 +386,7 @@ dmpt_status sym_inplace(const Call& k, const Group& g, int z0, int batch, double
 // out group (members z0..) = a (in + in^T), in and out distinct groups.
 template <class T>
 dmpt_status sym_to(const Call& k, const Group& in, const Group& out, int batch, bool planes) {
+  if (batch > in.count || batch > out.count) return fail(k.c, DMPT_ERR_ARG, "internal: sym batch too large");
   uint16_t* pl[3];
   planes_of(k, out, 0, pl);
   HIPCHK(k.c, (sym_combine<T, T>((const T*)mptr(k, in, 0), k.Np, k.stride, k.N, k.Np, 1.0, nullptr,
@@ -332,6 +408,10 @@ template <class T>
 dmpt_status cg_solve(const Call& k, const Group& u, int batch, int ydiv, const int* mask) {
   dmpt_ctx c = k.c;
   const WS* w = k.w;
+  if (batch < 1 || ydiv < 1 || u.count < batch || w->R.count < batch || w->P.count < batch ||
+      w->Q.count < batch || w->S0.count < (batch - 1) / ydiv + 1 ||
+      (size_t)batch * reduce_blocks(k.nn) > c->part_count)
+    return fail(c, DMPT_ERR_ARG, "internal: solve batch exceeds its workspace");
   hipStream_t s = c->stream;
   const int hs = c->hstride;
   const double tol = k.tol_cg;
@@ -454,11 +534,42 @@ dmpt_status square0(const Call& k) {
   return run_gemm(k, g);
 }
 
+// Pointer to the trajectory copy of jet member j at recursion step `step`.
+float* tj_ptr(const Call& k, int step, int j) {
+  return k.c->tj + ((size_t)step * k.jets + j) * (size_t)k.nn;
+}
+
+// Save member z of a group (its master) as trajectory entry (step, j).
+bool tj_fits(const Call& k, int step, int j) {
+  return step >= 0 && j >= 0 && j < k.jets &&
+         ((size_t)step * k.jets + j + 1) * (size_t)k.nn * sizeof(float) <= k.c->tj_bytes;
+}
+
+template <class T>
+dmpt_status tj_save(const Call& k, const Group& g, int z, int step, int j) {
+  if (!tj_fits(k, step, j) || z >= g.count) return fail(k.c, DMPT_ERR_ARG, "internal: trajectory index");
+  uint16_t* none[3] = {nullptr, nullptr, nullptr};
+  HIPCHK(k.c, (convert<T, float>((const T*)mptr(k, g, z), 0, tj_ptr(k, step, j), 0, k.nn, 1, none, 0,
+                                 0, k.c->stream)));
+  return DMPT_OK;
+}
+
+// Load trajectory entry (step, j) into member z of a group (master + planes).
+template <class T>
+dmpt_status tj_load(const Call& k, const Group& g, int z, int step, int j) {
+  if (!tj_fits(k, step, j) || z >= g.count) return fail(k.c, DMPT_ERR_ARG, "internal: trajectory index");
+  uint16_t* pl[3];
+  planes_of(k, g, z, pl);
+  HIPCHK(k.c, (convert<float, T>(tj_ptr(k, step, j), 0, (T*)mptr(k, g, z), 0, k.nn, 1, pl, 0,
+                                 g.pl[0] ? k.np : 0, k.c->stream)));
+  return DMPT_OK;
+}
+
 // Order 0 of one recursion step: T' Y0 = 2 D0 with S0 = D0^2 already formed;
 // the previous iterate D0 is the initial guess and D0 is overwritten by the
 // symmetrised solution.
 template <class T>
-dmpt_status solve_order0(const Call& k) {
+dmpt_status solve_order0(const Call& k, int step) {
   dmpt_ctx c = k.c;
   const WS* w = k.w;
   hipStream_t s = c->stream;
@@ -469,28 +580,51 @@ dmpt_status solve_order0(const Call& k) {
                             k.stride, k.nn, k.m, c->d_part, s));
   HIPCHK(c, sum_partials(c->d_part, reduce_blocks(k.nn), k.m, w->ref, 1, 0, s));
   HIPCHK(c, axpby<double>(w->ref, 0, w->ref, 0, k.m, 1, 0.0, 4.0, pl, 0, 0, s));
-  // R = 2 D0 - D0 - 4 D0 S0 = D0 - 4 D0 S0, with ||R||^2 -> rr[0]
-  G g;
-  g.X = op(k, w->D0, 0, true);
-  g.Y = op(k, w->S0, 0, true);
-  g.C = mptr(k, w->R, 0);
-  g.sC = k.stride;
-  g.alpha = -4.0;
-  g.C1 = mptr(k, w->D0, 0); g.sC1 = k.stride; g.beta1 = 1.0;
-  g.W = mptr(k, w->R, 0); g.sW = k.stride;
-  g.batch = k.m;
-  g.active = w->mask0;
-  STCHK(run_gemm(k, g));
-  STCHK(sum_gemm_partials(k, k.m, w->rr, hs, 0));
-  STCHK(cg_solve<T>(k, w->D0, k.m, 1, w->mask0));
-  STCHK(sym_inplace<T>(k, w->D0, 0, k.m, 0.5));
+  const bool guess_tj = k.traj && c->tj_valid >= 0 && step >= 0;
+  if (guess_tj) {
+    // U = this step's solution of the previous pass; R = 2 D0 - U - 4 U S0
+    STCHK(tj_load<T>(k, c->U0, 0, step, 0));
+    G g;
+    g.X = op(k, c->U0, 0, false);
+    g.Y = op(k, w->S0, 0, false);
+    g.C = mptr(k, w->R, 0);
+    g.alpha = -4.0;
+    g.C1 = mptr(k, w->D0, 0); g.beta1 = 2.0;
+    g.C2 = mptr(k, c->U0, 0); g.beta2 = -1.0;
+    g.W = mptr(k, w->R, 0);
+    STCHK(run_gemm(k, g));
+    STCHK(sum_gemm_partials(k, 1, w->rr, hs, 0));
+    STCHK(cg_solve<T>(k, c->U0, 1, 1, w->mask0));
+    uint16_t* pd[3];
+    planes_of(k, w->D0, 0, pd);
+    HIPCHK(c, (sym_combine<T, T>((const T*)mptr(k, c->U0, 0), k.Np, 0, k.N, k.Np, 0.5, nullptr, 0,
+                                 (T*)mptr(k, w->D0, 0), k.Np, 0, pd, k.np, 1, s)));
+  } else {
+    // R = 2 D0 - D0 - 4 D0 S0 = D0 - 4 D0 S0 (guess: the previous iterate), ||R||^2 -> rr[0]
+    G g;
+    g.X = op(k, w->D0, 0, true);
+    g.Y = op(k, w->S0, 0, true);
+    g.C = mptr(k, w->R, 0);
+    g.sC = k.stride;
+    g.alpha = -4.0;
+    g.C1 = mptr(k, w->D0, 0); g.sC1 = k.stride; g.beta1 = 1.0;
+    g.W = mptr(k, w->R, 0); g.sW = k.stride;
+    g.batch = k.m;
+    g.active = w->mask0;
+    STCHK(run_gemm(k, g));
+    STCHK(sum_gemm_partials(k, k.m, w->rr, hs, 0));
+    STCHK(cg_solve<T>(k, w->D0, k.m, 1, w->mask0));
+    STCHK(sym_inplace<T>(k, w->D0, 0, k.m, 0.5));
+  }
+  if (k.traj && step >= 0) STCHK(tj_save<T>(k, w->D0, 0, step, 0));
   return DMPT_OK;
 }
 
 // One recursion step for orders 0..order, d directions per system, on the
 // iterates held in k.w (Algorithm 1's inner loop body, in D form).
 template <class T>
-dmpt_status recursion_step(const Call& k, int order, int d) {
+dmpt_status recursion_step(const Call& k, int order, int d, int step) {
+  dmpt_ctx c = k.c;
   const WS* w = k.w;
   const int hs = k.c->hstride;
   const int md = k.m * d;
@@ -531,7 +665,7 @@ dmpt_status recursion_step(const Call& k, int order, int d) {
     h.active = w->mask1;
     STCHK(run_gemm(k, h));
   }
-  STCHK(solve_order0<T>(k));
+  STCHK(solve_order0<T>(k, step));
   // ---- order 1: T' Y1 = 2 D1 - 4 S1 Y0; transposed: rhs^T = 2 D1 - 4 Y0 S1
   if (order >= 1) {
     G g;  // R = 2 D1 - 4 Y0 S1   (Y0 = new D0), ||rhs||^2 -> ref
@@ -547,7 +681,9 @@ dmpt_status recursion_step(const Call& k, int order, int d) {
     g.active = w->mask1;
     STCHK(run_gemm(k, g));
     STCHK(sum_gemm_partials(k, md, w->ref, 1, 0));
-    G h;  // R -= D1 + 4 D1 S0  (guess U = D1)
+    if (k.traj && c->tj_valid >= 1)  // guess: this step's solution of the previous pass
+      for (int z = 0; z < md; ++z) STCHK(tj_load<T>(k, w->D1, z, step, 1 + z));
+    G h;  // R -= U + 4 U S0  (guess U held in D1: the previous iterate or the stored one)
     h.X = op(k, w->D1, 0, true);
     h.Y = op(k, w->S0, 0, true);
     h.Y.div = d;
@@ -563,6 +699,8 @@ dmpt_status recursion_step(const Call& k, int order, int d) {
     STCHK(sum_gemm_partials(k, md, w->rr, hs, 0));
     STCHK(cg_solve<T>(k, w->D1, md, d, w->mask1));
     STCHK(sym_inplace<T>(k, w->D1, 0, md, 0.5));
+    if (k.traj)
+      for (int z = 0; z < md; ++z) STCHK(tj_save<T>(k, w->D1, z, step, 1 + z));
   }
   // ---- order 2: rhs^T = 2 D2 - 4 Y1 S1 - 4 Y0 S2
   if (order >= 2) {
@@ -589,7 +727,9 @@ dmpt_status recursion_step(const Call& k, int order, int d) {
     g2.active = w->mask1;
     STCHK(run_gemm(k, g2));
     STCHK(sum_gemm_partials(k, md, w->ref, 1, 0));
-    G h;  // R -= D2 + 4 D2 S0
+    if (k.traj && c->tj_valid >= 2)
+      for (int z = 0; z < md; ++z) STCHK(tj_load<T>(k, w->D2, z, step, 1 + d + z));
+    G h;  // R -= U + 4 U S0 (guess U held in D2)
     h.X = op(k, w->D2, 0, true);
     h.Y = op(k, w->S0, 0, true);
     h.Y.div = d;
@@ -605,6 +745,8 @@ dmpt_status recursion_step(const Call& k, int order, int d) {
     STCHK(sum_gemm_partials(k, md, w->rr, hs, 0));
     STCHK(cg_solve<T>(k, w->D2, md, d, w->mask1));
     STCHK(sym_inplace<T>(k, w->D2, 0, md, 0.5));
+    if (k.traj)
+      for (int z = 0; z < md; ++z) STCHK(tj_save<T>(k, w->D2, z, step, 1 + d + z));
   }
   return DMPT_OK;
 }
@@ -614,7 +756,8 @@ template <class T>
 dmpt_status recursion_pass(const Call& k, const PassIn& in) {
   const double cscale = std::ldexp(in.beta, -(in.n + 2));
   STCHK(init_d<T>(k, in, cscale));
-  for (int step = 0; step < in.n; ++step) STCHK(recursion_step<T>(k, in.order, in.d));
+  for (int step = 0; step < in.n; ++step) STCHK(recursion_step<T>(k, in.order, in.d, step));
+  if (k.traj) k.c->tj_valid = in.order;
   return DMPT_OK;
 }
 
@@ -826,15 +969,16 @@ dmpt_status final_checks(dmpt_ctx c, int64_t N, const double* H0, const double* 
 bool alloc_group(dmpt_ctx c, Group& g, int count, bool planes, std::vector<void*>& owner) {
   const size_t nn = (size_t)c->np_max * c->np_max;
   g.count = count;
-  void* p = nullptr;
-  if (hipMalloc(&p, nn * c->esize * count) != hipSuccess) return false;
+  void* p = dev_alloc(c, nn * c->esize * count);
+  if (!p) return false;
   owner.push_back(p);
   g.m = p;
   if (hipMemsetAsync(p, 0, nn * c->esize * count, c->stream) != hipSuccess) return false;
   for (int q = 0; q < 3; ++q) g.pl[q] = nullptr;
   if (planes)
     for (int q = 0; q < c->planes; ++q) {
-      if (hipMalloc(&p, nn * 2 * count) != hipSuccess) return false;
+      p = dev_alloc(c, nn * 2 * count);
+      if (!p) return false;
       owner.push_back(p);
       g.pl[q] = (uint16_t*)p;
       if (hipMemsetAsync(p, 0, nn * 2 * count, c->stream) != hipSuccess) return false;
@@ -845,7 +989,7 @@ bool alloc_group(dmpt_ctx c, Group& g, int count, bool planes, std::vector<void*
 dmpt_status ensure_adjoint(dmpt_ctx c, int n_ck, int n_seg) {
   if (c->CK.count >= n_ck && c->SG.count >= n_seg && c->AY.m) return DMPT_OK;
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  for (void* p : c->ad_allocs) (void)hipFree(p);
+  for (void* p : c->ad_allocs) dev_free(c, p);
   c->ad_allocs.clear();
   auto& o = c->ad_allocs;
   bool ok = alloc_group(c, c->AY, 2, true, o) && alloc_group(c, c->AU, 2, true, o) &&
@@ -853,7 +997,7 @@ dmpt_status ensure_adjoint(dmpt_ctx c, int n_ck, int n_seg) {
             alloc_group(c, c->AG, 2, false, o) && alloc_group(c, c->AD, 1, true, o) &&
             alloc_group(c, c->CK, n_ck, false, o) && alloc_group(c, c->SG, n_seg, false, o);
   if (!ok) {
-    for (void* p : c->ad_allocs) (void)hipFree(p);
+    for (void* p : c->ad_allocs) dev_free(c, p);
     c->ad_allocs.clear();
     c->AY = c->AU = c->AW = c->AV = c->AG = c->AD = c->CK = c->SG = Group{};
     return fail(c, DMPT_ERR_NOMEM, "adjoint workspace allocation failed");
@@ -864,6 +1008,8 @@ dmpt_status ensure_adjoint(dmpt_ctx c, int n_ck, int n_seg) {
 // dst member (with planes) = src member
 template <class T>
 dmpt_status copy_member(const Call& k, const Group& src, int zs, const Group& dst, int zd) {
+  if (zs < 0 || zs >= src.count || zd < 0 || zd >= dst.count)
+    return fail(k.c, DMPT_ERR_ARG, "internal: member index out of range");
   uint16_t* pl[3];
   planes_of(k, dst, zd, pl);
   HIPCHK(k.c, axpby<T>((const T*)mptr(k, src, zs), 0, (T*)mptr(k, dst, zd), 0, k.nn, 1, 1.0, 0.0,
@@ -880,7 +1026,7 @@ dmpt_status forward_step0(const Call& k) {
   g.C = mptr(k, k.c->ws.S0, 0);
   planes_of(k, k.c->ws.S0, 0, g.Cpl);
   STCHK(run_gemm(k, g));
-  return solve_order0<T>(k);
+  return solve_order0<T>(k, -1);
 }
 
 // Reverse sweep of the order-0 recursion for the two seeds Abar and I:
@@ -958,7 +1104,7 @@ dmpt_status adjoint_impl(const Call& k, const double* H0, double beta, double mu
         g.batch = 2;
         STCHK(run_gemm(k, g));
         STCHK(sum_gemm_partials(k, 2, c->ws.rr, hs, 0));
-        STCHK(cg_solve<T>(k, c->AU, 2, 1, nullptr));
+        STCHK(cg_solve<T>(k, c->AU, 2, 2, nullptr));  // both seeds share S0
       }
       // W = U^T;  V = W Y;  V <- sym(V);  AG = V D
       {
@@ -1096,7 +1242,7 @@ dmpt_status batched_pass(dmpt_ctx c, std::vector<Bucket>& bk, bool stageB, int o
     for (size_t b = 0; b < bk.size(); ++b) {
       Call& k = ks[b];
       k.cg_iters = cg_bound(kappa_bound(bk[b].xmax, step), k.tol_cg, c->opt.max_cg);
-      STCHK(recursion_step<T>(k, ord, d));
+      STCHK(recursion_step<T>(k, ord, d, -1));
     }
   // outputs and traces, per system
   for (size_t b = 0; b < bk.size(); ++b) {
@@ -1126,6 +1272,29 @@ dmpt_status batched_pass(dmpt_ctx c, std::vector<Bucket>& bk, bool stageB, int o
     }
   }
   return DMPT_OK;
+}
+
+// Room for the trajectory of n steps x jets members of Np x Np FP32; false
+// (and no warm starts) when the device cannot hold it.
+bool ensure_traj(dmpt_ctx c, int n, int jets, int64_t Np) {
+  const size_t need = (size_t)n * jets * (size_t)Np * Np * sizeof(float);
+  c->tj_valid = -1;
+  if (c->tj && c->tj_bytes >= need) {
+    c->tj_np = Np;
+    return true;
+  }
+  if (c->tj) {
+    (void)hipStreamSynchronize(c->stream);
+    dev_free(c, c->tj);
+    c->tj = nullptr;
+    c->tj_bytes = 0;
+  }
+  void* p = dev_alloc(c, need);
+  if (!p) return false;
+  c->tj = (float*)p;
+  c->tj_bytes = need;
+  c->tj_np = Np;
+  return true;
 }
 
 bool converged(const double* res, int d, int order, double Ne, int64_t N, double tol, double* occ_err) {
@@ -1159,6 +1328,7 @@ void dmpt_default_options(dmpt_options* o) {
   o->ckpt_every = 5;
   o->check = 0;
   o->staged = 1;
+  o->warm_traj = 1;
 }
 
 static dmpt_status normalise_options(dmpt_ctx c, const dmpt_options* in, dmpt_options* out) {
@@ -1219,6 +1389,7 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
       return bail(DMPT_ERR_HIP, "hipStreamCreate failed");
     c->own_stream = true;
   }
+  if (gemm_prepare() != hipSuccess) return bail(DMPT_ERR_HIP, "product kernel attributes");
   c->n_max = n_max;
   c->np_max = padded(n_max);
   c->dirs_max = dirs_max;
@@ -1228,9 +1399,8 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
   const int dm = std::max(2, dirs_max);
   const size_t nn = (size_t)c->np_max * c->np_max;
   auto alloc = [&](size_t bytes) -> void* {
-    void* p = nullptr;
-    if (hipMalloc(&p, std::max<size_t>(bytes, 256)) != hipSuccess) return nullptr;
-    c->allocs.push_back(p);
+    void* p = dev_alloc(c, bytes);
+    if (p) c->allocs.push_back(p);
     return p;
   };
   auto group = [&](Group& g, int count, bool planes) -> bool {
@@ -1246,7 +1416,7 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
   };
   const int dd = dirs_max;  // groups for perturbations may be empty
   bool ok = group(c->ws.D0, 1, true) && group(c->ws.S0, 1, true) && group(c->ws.R, dm, false) &&
-            group(c->ws.P, dm, true) && group(c->ws.Q, dm, false);
+            group(c->ws.P, dm, true) && group(c->ws.Q, dm, false) && group(c->U0, 1, true);
   if (ok && dd > 0)
     ok = group(c->ws.D1, dd, true) && group(c->ws.D2, dd, true) && group(c->ws.S1, dd, true) &&
          group(c->ws.S2, dd, true);
@@ -1281,7 +1451,8 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
           return false;
       return true;
     };
-    if (!(zero(c->ws.D0) && zero(c->ws.S0) && zero(c->ws.R) && zero(c->ws.P) && zero(c->ws.Q) && zero(c->ws.D1) &&
+    if (!(zero(c->ws.D0) && zero(c->ws.S0) && zero(c->ws.R) && zero(c->ws.P) && zero(c->ws.Q) &&
+          zero(c->U0) && zero(c->ws.D1) &&
           zero(c->ws.D2) && zero(c->ws.S1) && zero(c->ws.S2)))
       return bail(DMPT_ERR_HIP, "workspace clear failed");
     if (set_values(nullptr, 0, 0, c->d_res + RES_HALF, 0.5, 1, c->stream) != hipSuccess)
@@ -1404,14 +1575,15 @@ dmpt_status dmpt_finalize(dmpt_ctx c) {
     (void)hipEventDestroy(t.b);
   }
   for (auto e : c->prof_pool) (void)hipEventDestroy(e);
-  for (void* p : c->allocs) (void)hipFree(p);
+  for (void* p : c->allocs) dev_free(c, p);
   c->allocs.clear();
-  for (void* p : c->ad_allocs) (void)hipFree(p);
+  for (void* p : c->ad_allocs) dev_free(c, p);
   c->ad_allocs.clear();
-  for (void* p : c->bt_allocs) (void)hipFree(p);
+  for (void* p : c->bt_allocs) dev_free(c, p);
   c->bt_allocs.clear();
   if (c->h_res) (void)hipHostFree(c->h_res);
   if (c->h_int) (void)hipHostFree(c->h_int);
+  if (c->tj) dev_free(c, c->tj);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
   return DMPT_OK;
@@ -1521,6 +1693,10 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
     Engine eng;
     double tol_cg, tol_occ;
   };
+  if (c->opt.warm_traj && ensure_traj(c, n, 1 + 2 * dd, k.Np)) {
+    k.traj = true;
+    k.jets = 1 + 2 * dd;
+  }
   Phase phases[2];
   int nph = 0;
   if (two_phase)
@@ -1666,9 +1842,8 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
   if (part_need > c->part_count) {
     // a larger partials block, kept until dmpt_finalize
     HIPCHK(c, hipStreamSynchronize(s));
-    void* p = nullptr;
-    if (hipMalloc(&p, part_need * sizeof(double)) != hipSuccess)
-      return fail(c, DMPT_ERR_NOMEM, "batched partials allocation failed");
+    void* p = dev_alloc(c, part_need * sizeof(double));
+    if (!p) return fail(c, DMPT_ERR_NOMEM, "batched partials allocation failed");
     c->bt_allocs.push_back(p);
     c->d_part = (double*)p;
     c->part_count = part_need;
@@ -1677,12 +1852,12 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
   std::vector<void*> local;  // freed at the end of the call
   auto cleanup = [&]() {
     (void)hipStreamSynchronize(s);
-    for (void* p : local) (void)hipFree(p);
+    for (void* p : local) dev_free(c, p);
   };
   auto galloc = [&](Group& g, int count, int64_t Np, bool planes) -> bool {
     const size_t nn = (size_t)Np * Np;
-    void* p = nullptr;
-    if (hipMalloc(&p, nn * c->esize * count) != hipSuccess) return false;
+    void* p = dev_alloc(c, nn * c->esize * count);
+    if (!p) return false;
     local.push_back(p);
     g.m = p;
     g.count = count;
@@ -1690,7 +1865,8 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
     for (int q = 0; q < 3; ++q) g.pl[q] = nullptr;
     if (planes)
       for (int q = 0; q < np; ++q) {
-        if (hipMalloc(&p, nn * 2 * count) != hipSuccess) return false;
+        p = dev_alloc(c, nn * 2 * count);
+        if (!p) return false;
         local.push_back(p);
         g.pl[q] = (uint16_t*)p;
         if (hipMemsetAsync(p, 0, nn * 2 * count, s) != hipSuccess) return false;
@@ -1698,9 +1874,8 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
     return true;
   };
   auto dalloc = [&](size_t bytes) -> void* {
-    void* p = nullptr;
-    if (hipMalloc(&p, std::max<size_t>(bytes, 256)) != hipSuccess) return nullptr;
-    local.push_back(p);
+    void* p = dev_alloc(c, bytes);
+    if (p) local.push_back(p);
     return p;
   };
   // per-slot device state

@@ -67,6 +67,8 @@ struct GemmArgs {
 int gemm_tile_edge(Engine eng, int64_t Np, int tile_pref);
 int gemm_tiles(Engine eng, int64_t Np, int tile_pref);
 hipError_t gemm(const GemmArgs& a, hipStream_t s);
+// Set the launch attributes of the product kernels (once per process and device).
+hipError_t gemm_prepare();
 
 // ---------------------------------------------------------------- element-wise
 // out = a (in + in^T) + a2 (in2 + in2^T) + dshift I on the leading N x N
@@ -124,6 +126,11 @@ hipError_t cg_check(const double* rr, const double* ref, int hstride, int batch,
 template <class T>
 hipError_t axpby(const T* x, int64_t sx, T* y, int64_t sy, int64_t n, int batch, double a,
                  double b, uint16_t* const* planes, int64_t sp, int nplanes, hipStream_t s);
+
+// out = (Tout) in for n elements per member (batched) + planes of out
+template <class Tin, class Tout>
+hipError_t convert(const Tin* in, int64_t si, Tout* out, int64_t so, int64_t n, int batch,
+                   uint16_t* const* planes, int64_t sp, int nplanes, hipStream_t s);
 
 // Fill identity-plus-scaled matrix: out = a I + b x (Np x Np, zero padding kept)
 template <class T>

@@ -259,6 +259,23 @@ __global__ __launch_bounds__(kT) void k_axpby(const T* __restrict__ x, int64_t s
   }
 }
 
+// out = (Tout) in, batched, with planes of out
+template <class Tin, class Tout>
+__global__ __launch_bounds__(kT) void k_convert(const Tin* __restrict__ in, int64_t si,
+                                                Tout* __restrict__ out, int64_t so, int64_t n,
+                                                Planes pl, int64_t sp, int np) {
+  const int z = blockIdx.y;
+  in += z * si;
+  out += z * so;
+  uint16_t* p3[3] = {pl.p[0] ? pl.p[0] + z * sp : nullptr, pl.p[1] ? pl.p[1] + z * sp : nullptr,
+                     pl.p[2] ? pl.p[2] + z * sp : nullptr};
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+    const Tout v = (Tout)in[i];
+    out[i] = v;
+    if (np) split_store((double)v, p3, np, i);
+  }
+}
+
 template <class T>
 __global__ __launch_bounds__(kT) void k_spi(const T* __restrict__ x, T* __restrict__ out, int64_t N,
                                             int64_t Np, double a, double b, Planes pl, int np) {
@@ -573,6 +590,24 @@ template hipError_t axpby<double>(const double*, int64_t, double*, int64_t, int6
                                   double, uint16_t* const*, int64_t, int, hipStream_t);
 template hipError_t axpby<float>(const float*, int64_t, float*, int64_t, int64_t, int, double,
                                  double, uint16_t* const*, int64_t, int, hipStream_t);
+
+template <class Tin, class Tout>
+hipError_t convert(const Tin* in, int64_t si, Tout* out, int64_t so, int64_t n, int batch,
+                   uint16_t* const* planes, int64_t sp, int nplanes, hipStream_t s) {
+  Planes pl{{nullptr, nullptr, nullptr}};
+  for (int p = 0; p < nplanes; ++p) pl.p[p] = planes[p];
+  hipLaunchKernelGGL((k_convert<Tin, Tout>), dim3(ew_grid(n), batch), dim3(kT), 0, s, in, si, out, so,
+                     n, pl, sp, nplanes);
+  return hipGetLastError();
+}
+#define DMPT_CONV_INST(TI, TO)                                                                \
+  template hipError_t convert<TI, TO>(const TI*, int64_t, TO*, int64_t, int64_t, int,         \
+                                      uint16_t* const*, int64_t, int, hipStream_t);
+DMPT_CONV_INST(double, float)
+DMPT_CONV_INST(float, double)
+DMPT_CONV_INST(float, float)
+DMPT_CONV_INST(double, double)
+#undef DMPT_CONV_INST
 
 template <class T>
 hipError_t scaled_plus_identity(const T* x, T* out, int64_t N, int64_t Np, double a, double b,

@@ -514,13 +514,6 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16_256(GemmArgs a) {
 template <int S, int BK>
 hipError_t launch_bf16_256(const GemmArgs& a, dim3 grid, hipStream_t s) {
   const size_t lds = (size_t)2 * 2 * S * BM2 * BK * 2;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_gemm_bf16_256<S, BK>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
   hipLaunchKernelGGL((k_gemm_bf16_256<S, BK>), grid, dim3(kThreads), lds, s, a);
   return hipGetLastError();
 }
@@ -528,13 +521,6 @@ hipError_t launch_bf16_256(const GemmArgs& a, dim3 grid, hipStream_t s) {
 template <int S>
 hipError_t launch_bf16(const GemmArgs& a, dim3 grid, hipStream_t s) {
   const size_t lds = (size_t)2 * 2 * S * kTileBytes;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_gemm_bf16<S>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
   hipLaunchKernelGGL(k_gemm_bf16<S>, grid, dim3(kThreads), lds, s, a);
   return hipGetLastError();
 }
@@ -547,6 +533,23 @@ int gemm_tile_edge(Engine eng, int64_t Np, int tile_pref) {
   const bool bf = eng == Engine::BF16S2 || eng == Engine::BF16S3;
   if (bf && tile_pref != 128 && Np % BM2 == 0) return BM2;
   return BM;
+}
+
+// Raise the dynamic-LDS limit of every kernel that needs more than the
+// default, once, before any launch (and so never inside a graph capture).
+hipError_t gemm_prepare() {
+  const void* k2 = (const void*)k_gemm_bf16<2>;
+  const void* k3 = (const void*)k_gemm_bf16<3>;
+  const void* l2 = (const void*)k_gemm_bf16_256<2, 16>;
+  const void* l3 = (const void*)k_gemm_bf16_256<3, 16>;
+  hipError_t e;
+  if ((e = hipFuncSetAttribute(k2, hipFuncAttributeMaxDynamicSharedMemorySize, 2 * 2 * 2 * kTileBytes)))
+    return e;
+  if ((e = hipFuncSetAttribute(k3, hipFuncAttributeMaxDynamicSharedMemorySize, 2 * 2 * 3 * kTileBytes)))
+    return e;
+  if ((e = hipFuncSetAttribute(l2, hipFuncAttributeMaxDynamicSharedMemorySize, 2 * 2 * 2 * BM2 * 16 * 2)))
+    return e;
+  return hipFuncSetAttribute(l3, hipFuncAttributeMaxDynamicSharedMemorySize, 2 * 2 * 3 * BM2 * 16 * 2);
 }
 
 int gemm_tiles(Engine eng, int64_t Np, int tile_pref) {
@@ -567,7 +570,7 @@ hipError_t gemm(const GemmArgs& a, hipStream_t s) {
       hipLaunchKernelGGL(k_gemm_f32, grid, dim3(kThreads), 0, s, a);
       return hipGetLastError();
     case Engine::BF16S2:
-      return edge == BM2 ? launch_bf16_256<2, 32>(a, grid, s) : launch_bf16<2>(a, grid, s);
+      return edge == BM2 ? launch_bf16_256<2, 16>(a, grid, s) : launch_bf16<2>(a, grid, s);
     case Engine::BF16S3:
       return edge == BM2 ? launch_bf16_256<3, 16>(a, grid, s) : launch_bf16<3>(a, grid, s);
   }

@@ -89,10 +89,11 @@ def chain128_ref():
     return c, r
 
 
-def test_chain128_canonical_fp64(dm, chain128_ref):
-    print("case chain128 canonical fp64", flush=True)
+@pytest.mark.parametrize("warm_traj", [1, 0])
+def test_chain128_canonical_fp64(dm, chain128_ref, warm_traj):
+    print(f"case chain128 canonical fp64 warm_traj={warm_traj}", flush=True)
     c, ref = chain128_ref
-    with dm.Context(c["N"], dirs_max=1, prec="fp64") as ctx:
+    with dm.Context(c["N"], dirs_max=1, prec="fp64", warm_traj=warm_traj) as ctx:
         P0, P1, P2, mu, st = ctx.mu_newton(T(c["H0"]), [T(h) for h in c["H1"]], None,
                                            beta=c["beta"], Ne=c["Ne"], n=c["n"], order=2)
     e0, e1, e2 = errs(P0, P1, P2, ref)
