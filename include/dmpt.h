@@ -82,7 +82,8 @@ typedef struct {
   dmpt_solver solver;   /* per-step solver */
   dmpt_guess guess;     /* CG initial guess */
   double tol_occ;       /* Newton stops when |Tr P0 - Ne| <= tol_occ * N and, for k >= 1,
-                           |Tr P^(k)| <= tol_occ * sum_i |P^(k)_ii|; <= 0: default for prec */
+                           |Tr P^(k)| <= tol_occ * sum_i |P^(k)_ii| (or when that normalised
+                           error stopped shrinking within 1000 tol_occ); <= 0: default for prec */
   double tol_cg;        /* relative residual of each solve; <= 0: default for prec */
   int max_newton;       /* Newton passes (default 50) */
   int max_cg;           /* CG iterations per solve (default 60) */
@@ -93,6 +94,10 @@ typedef struct {
   int warm_traj;        /* 1: keep every step's iterates (FP32 copies) and start each CG of the next
                            Newton pass from the same step's previous solution instead of the
                            previous recursion step's iterate; falls back when memory is short */
+  int schedule;         /* canonical loop for orders >= 1: 0 = Algorithm 1's Newton update of every
+                           mu^(k) with Tr P_mu; 1 = after mu0 has converged, one pass per order with
+                           the extra response J to H1 = I: P^(k) is affine in mu^(k) with slope -J,
+                           so mu^(k) = Tr P^(k)(0) / Tr J and P^(k) = P^(k)(0) - mu^(k) J exactly */
 } dmpt_options;
 
 #define DMPT_MAX_DIRS 8
@@ -119,8 +124,8 @@ typedef struct {
 /* Fill *opt with defaults: FP64, CG, previous-iterate guess, default tolerances. */
 void dmpt_default_options(dmpt_options* opt);
 
-/* Create a context on HIP device `device` able to handle N <= n_max and up
- * to dirs_max perturbation directions.  All device workspace is allocated
+/* Create a context on HIP device `device` able to handle N <= n_max
+ * (1 <= n_max <= 65408) and up to dirs_max perturbation directions.  All device workspace is allocated
  * here (sized by n_max, dirs_max and opt->prec) and freed in
  * dmpt_finalize.  `hip_stream` is a hipStream_t to queue work on; NULL
  * creates a private stream.  opt may be NULL (defaults). */
@@ -154,7 +159,9 @@ dmpt_status dmpt_response(dmpt_ctx ctx, int64_t N, const double* H0, int d,
                           double* const* P2, dmpt_stats* st);
 
 /* Canonical response (Algorithm 1): Newton on the mu jet until the
- * occupation error is at most tol_occ.  mu_inout (host, 1 + order*d
+ * occupation error is at most tol_occ (the mu0 step is safeguarded by a
+ * bracket and bisection; options.schedule picks how mu^(k), k >= 1, are
+ * found).  The context needs dirs_max >= d.  mu_inout (host, 1 + order*d
  * doubles): in, mu0 guess (NaN: Tr H0 / N) and mu^(k) guesses (NaN: 0); out,
  * the jet at which the returned P was computed.  On DMPT_ERR_NOCONV the
  * outputs and *st hold the last pass. */

@@ -26,7 +26,7 @@ def _torch():
 
 
 def options(prec="fp64", solver="cg", guess="prev", tol_occ=0.0, tol_cg=0.0, max_newton=50,
-            max_cg=60, refine=0, ckpt_every=5, check=0, staged=1, warm_traj=1):
+            max_cg=60, refine=0, ckpt_every=5, check=0, staged=1, warm_traj=1, schedule=1):
     """Build an options struct; 0 tolerances select the precision's defaults."""
     lib = L.load()
     o = L.Options()
@@ -38,6 +38,7 @@ def options(prec="fp64", solver="cg", guess="prev", tol_occ=0.0, tol_cg=0.0, max
     o.max_newton, o.max_cg, o.refine = int(max_newton), int(max_cg), int(refine)
     o.ckpt_every, o.check, o.staged = int(ckpt_every), int(check), int(staged)
     o.warm_traj = int(warm_traj)
+    o.schedule = int(schedule)
     return o
 
 

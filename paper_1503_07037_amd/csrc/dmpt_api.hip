@@ -16,6 +16,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -27,6 +28,10 @@ using namespace dmpt;
 namespace {
 
 const char* kNoCtx = "invalid context (NULL)";
+
+// Pinned host ints: CG active flags at [0, kIterSlot), iteration counts at
+// [kIterSlot, 2 kIterSlot); one solve covers at most kIterSlot members.
+constexpr int kIterSlot = 512;
 
 struct Group {
   void* m = nullptr;             // master base, members at m + z * stride elements
@@ -71,6 +76,7 @@ struct dmpt_ctx_s {
   // checked against it on the host before they are queued
   std::vector<std::pair<const char*, size_t>> regions;
   int tile_pref = 0;             // product tile edge: 0 = largest available
+  bool log = false;              // DMPT_LOG set: one line per Newton pass on stderr
   std::vector<std::pair<int64_t, int>> tuned;  // autotuned tile edge per padded size
   // iterates of the previous Newton pass (FP32 copies, warm starts):
   // [step][jet member] of tj_np^2 each; tj_valid = highest order stored
@@ -79,6 +85,7 @@ struct dmpt_ctx_s {
   int64_t tj_np = 0;
   int tj_valid = -1;
   Group U0;                      // order-0 CG unknown when the guess comes from tj
+  double* jout = nullptr;        // N x N FP64: response to H1 = I (linear schedule)
   // larger partial-sum blocks allocated by batched calls
   std::vector<void*> bt_allocs;
   // scalars
@@ -89,7 +96,7 @@ struct dmpt_ctx_s {
   size_t part_count = 0;
   double* d_gersh = nullptr;     // 2 + 2 n_max
   double* h_res = nullptr;       // pinned mirror of d_res
-  int* h_int = nullptr;          // pinned ints
+  int* h_int = nullptr;          // pinned ints: CG active flags, then iteration counts at kIterSlot
   std::string err;
   // product-kernel timing (dmpt_profile)
   bool prof_on = false;
@@ -163,13 +170,19 @@ double default_tol_cg(dmpt_prec p, int refine) {
   return 1e-14;
 }
 
+// Tolerances of the 3-product passes that precede the 6-product refinement
+// (they only bring the mu jet close; the 3-product split's rounding sits
+// near 1e-6 of the occupation).
+constexpr double kPhaseATolCg = 1e-5;
+constexpr double kPhaseATolOcc = 1e-5;
+
 double default_tol_occ(dmpt_prec p, int refine) {
   if (p == DMPT_BF16X3 && refine) p = DMPT_BF16X6;
   switch (p) {
     case DMPT_FP64: return 1e-12;
-    case DMPT_FP32: return 1e-7;
+    case DMPT_FP32: return 1e-6;
     case DMPT_BF16X3: return 1e-6;
-    case DMPT_BF16X6: return 1e-9;
+    case DMPT_BF16X6: return 1e-7;
   }
   return 1e-12;
 }
@@ -395,6 +408,10 @@ dmpt_status sym_to(const Call& k, const Group& in, const Group& out, int batch, 
   return DMPT_OK;
 }
 
+// Every solve also reduces its initial residual by this factor at least (see
+// k_cg_check): warm starts must not freeze the iterate below the tolerance.
+constexpr double kEta = 0.05;
+
 // Conjugate gradients on the transposed unknowns U (U T' = R^T, see gemm.hip):
 //   U (group `u`, members z = 0..batch-1) holds the initial guess and
 //   receives the solution; R holds the initial residual, whose squared norm
@@ -409,7 +426,7 @@ dmpt_status cg_solve(const Call& k, const Group& u, int batch, int ydiv, const i
   dmpt_ctx c = k.c;
   const WS* w = k.w;
   if (batch < 1 || ydiv < 1 || u.count < batch || w->R.count < batch || w->P.count < batch ||
-      w->Q.count < batch || w->S0.count < (batch - 1) / ydiv + 1 ||
+      w->Q.count < batch || w->S0.count < (batch - 1) / ydiv + 1 || batch > kIterSlot ||
       (size_t)batch * reduce_blocks(k.nn) > c->part_count)
     return fail(c, DMPT_ERR_ARG, "internal: solve batch exceeds its workspace");
   hipStream_t s = c->stream;
@@ -426,7 +443,7 @@ dmpt_status cg_solve(const Call& k, const Group& u, int batch, int ydiv, const i
   if (mask) HIPCHK(c, expand_mask(mask, 1, w->active, batch, s));
   else HIPCHK(c, set_values(w->active, 1, batch, nullptr, 0.0, 0, s));
   HIPCHK(c, set_values(w->iters, 0, batch, nullptr, 0.0, 0, s));
-  HIPCHK(c, cg_check(w->rr, w->ref, hs, batch, tol * tol, w->active, w->iters, s));
+  HIPCHK(c, cg_check(w->rr, w->rr, w->ref, hs, batch, tol * tol, kEta * kEta, w->active, w->iters, s));
   const int red_nb = reduce_blocks(n);
   const int cap = k.graph ? std::min(k.cg_iters, c->opt.max_cg) : c->opt.max_cg;
   for (int it = 0; it < cap && it + 1 < hs; ++it) {
@@ -461,16 +478,17 @@ dmpt_status cg_solve(const Call& k, const Group& u, int batch, int ydiv, const i
       HIPCHK(c, cg_update_p<T>((T*)mptr(k, w->P, 0), (const T*)mptr(k, w->R, 0), n, k.stride, batch,
                                w->rr + it + 1, w->rr + it, hs, w->active, pl, k.np, s));
     }
-    HIPCHK(c, cg_check(w->rr + it + 1, w->ref, hs, batch, tol * tol, w->active, w->iters, s));
+    HIPCHK(c, cg_check(w->rr + it + 1, w->rr, w->ref, hs, batch, tol * tol, kEta * kEta, w->active,
+                       w->iters, s));
   }
   if (k.graph) return DMPT_OK;  // counters are read by the caller after the pass
   HIPCHK(c, hipMemcpyAsync(c->h_int, w->active, batch * sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(c, hipMemcpyAsync(c->h_int + DMPT_MAX_DIRS, w->iters, batch * sizeof(int),
+  HIPCHK(c, hipMemcpyAsync(c->h_int + kIterSlot, w->iters, batch * sizeof(int),
                            hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
   for (int z = 0; z < batch; ++z) {
     // iters counts the initial check too
-    const int its = std::max(0, c->h_int[DMPT_MAX_DIRS + z] - 1);
+    const int its = std::max(0, c->h_int[kIterSlot + z] - 1);
     c->cg_total += its;
     c->cg_max = std::max(c->cg_max, its);
     if (c->h_int[z]) c->cg_capped = true;
@@ -786,9 +804,11 @@ dmpt_status finish_pass(const Call& k, const PassIn& in, double* P0, double* con
       HIPCHK(c, trace(Pk[z], k.N, 0, k.N, 1, c->d_res + RES_TR + slot, 1,
                       c->d_res + RES_ATR + slot, s));
       // Tr(H1 P^(k)) = <sym H1, P^(k)> = <H1, P^(k)> since P^(k) is symmetric
-      HIPCHK(c, dot_partials<double>(in.H1[z], 0, Pk[z], 0, k.N * k.N, 1, c->d_part, s));
-      HIPCHK(c, sum_partials(c->d_part, reduce_blocks(k.N * k.N), 1,
-                             c->d_res + (ord == 1 ? RES_H1P1 : RES_H1P2) + z, 1, 0, s));
+      if (in.H1[z]) {
+        HIPCHK(c, dot_partials<double>(in.H1[z], 0, Pk[z], 0, k.N * k.N, 1, c->d_part, s));
+        HIPCHK(c, sum_partials(c->d_part, reduce_blocks(k.N * k.N), 1,
+                               c->d_res + (ord == 1 ? RES_H1P1 : RES_H1P2) + z, 1, 0, s));
+      }
       if (ord == 2) {
         if (in.H2 && in.H2[z]) {
           HIPCHK(c, dot_partials<double>(in.H2[z], 0, P0, 0, k.N * k.N, 1, c->d_part, s));
@@ -1219,21 +1239,24 @@ dmpt_status batched_pass(dmpt_ctx c, std::vector<Bucket>& bk, bool stageB, int o
       const int64_t N = Ns[sys];
       uint16_t* pl[3];
       planes_of(k, k.w->D0, i, pl);
+      const int* gate = k.w->mask0 + i;  // this system's activity flag
       HIPCHK(c, (sym_combine<double, T>(H0s[sys], N, 0, N, k.Np, 0.5 * cs[sys],
                                         d_mu_shift + (int64_t)slot * J, 0, (T*)mptr(k, k.w->D0, i),
-                                        k.Np, 0, pl, k.np, 1, s)));
+                                        k.Np, 0, pl, k.np, 1, s, nullptr, 0.0, gate)));
       for (int z = 0; z < d && ord >= 1; ++z) {
         const int mem = i * d + z;
         planes_of(k, k.w->D1, mem, pl);
         HIPCHK(c, (sym_combine<double, T>(H1s[sys * d + z], N, 0, N, k.Np, 0.5 * cs[sys],
                                           d_mu_shift + (int64_t)slot * J + 1 + z, 0,
-                                          (T*)mptr(k, k.w->D1, mem), k.Np, 0, pl, k.np, 1, s)));
+                                          (T*)mptr(k, k.w->D1, mem), k.Np, 0, pl, k.np, 1, s,
+                                          nullptr, 0.0, gate)));
         if (ord >= 2) {
           // H2 = 0: only the shift -c mu2 on the diagonal (a = 0 ignores the input)
           planes_of(k, k.w->D2, mem, pl);
           HIPCHK(c, (sym_combine<double, T>(H1s[sys * d + z], N, 0, N, k.Np, 0.0,
                                             d_mu_shift + (int64_t)slot * J + 1 + d + z, 0,
-                                            (T*)mptr(k, k.w->D2, mem), k.Np, 0, pl, k.np, 1, s)));
+                                            (T*)mptr(k, k.w->D2, mem), k.Np, 0, pl, k.np, 1, s,
+                                            nullptr, 0.0, gate)));
         }
       }
     }
@@ -1251,8 +1274,9 @@ dmpt_status batched_pass(dmpt_ctx c, std::vector<Bucket>& bk, bool stageB, int o
       const int slot = bk[b].first + i, sys = slot_sys[slot];
       const int64_t N = Ns[sys];
       double* t = d_tr + (int64_t)slot * rs;
+      const int* gate = k.w->mask0 + i;  // converged systems keep their outputs
       HIPCHK(c, (sym_combine<T, double>((const T*)mptr(k, k.w->D0, i), k.Np, 0, N, k.Np, -0.5, d_half,
-                                        0, P0s[sys], N, 0, nullptr, 0, 1, s)));
+                                        0, P0s[sys], N, 0, nullptr, 0, 1, s, nullptr, 0.0, gate)));
       HIPCHK(c, trace<double>(P0s[sys], N, 0, N, 1, t, 1, t + J, s));
       HIPCHK(c, dot_partials<double>(P0s[sys], 0, P0s[sys], 0, N * N, 1, c->d_part, s));
       HIPCHK(c, sum_partials(c->d_part, reduce_blocks(N * N), 1, t + 2 * J, 1, 0, s));
@@ -1263,7 +1287,7 @@ dmpt_status batched_pass(dmpt_ctx c, std::vector<Bucket>& bk, bool stageB, int o
           const Group& g = o == 1 ? k.w->D1 : k.w->D2;
           const int jt = (o == 1 ? 1 : 1 + d) + z;
           HIPCHK(c, (sym_combine<T, double>((const T*)mptr(k, g, mem), k.Np, 0, N, k.Np, -0.5, nullptr,
-                                            0, Pk, N, 0, nullptr, 0, 1, s)));
+                                            0, Pk, N, 0, nullptr, 0, 1, s, nullptr, 0.0, gate)));
           HIPCHK(c, trace<double>(Pk, N, 0, N, 1, t + jt, 1, t + J + jt, s));
           HIPCHK(c, dot_partials<double>(H1s[sys * d + z], 0, Pk, 0, N * N, 1, c->d_part, s));
           HIPCHK(c, sum_partials(c->d_part, reduce_blocks(N * N), 1,
@@ -1297,16 +1321,75 @@ bool ensure_traj(dmpt_ctx c, int n, int jets, int64_t Np) {
   return true;
 }
 
-bool converged(const double* res, int d, int order, double Ne, int64_t N, double tol, double* occ_err) {
+// Occupation error of Algorithm 1 (*occ_err, absolute) and its normalised
+// form (*rel): max(|Tr P0 - Ne| / N, max_k |Tr P^(k)| / sum_i |P^(k)_ii|).
+void occupation_error(const double* res, int d, int order, double Ne, int64_t N, double* occ_err,
+                      double* rel) {
   double e = std::fabs(res[RES_TR] - Ne);
-  bool ok = e <= tol * (double)N;
+  double r = e / (double)N;
   for (int i = 1; i < 1 + order * d; ++i) {
     const double t = std::fabs(res[RES_TR + i]);
     e += t;
-    if (!(t <= tol * std::max(res[RES_ATR + i], 1e-300))) ok = false;
+    r = std::max(r, t / std::max(res[RES_ATR + i], 1e-300));
   }
   *occ_err = e;
-  return ok && std::isfinite(e);
+  *rel = std::isfinite(e) ? r : INFINITY;
+}
+
+// The canonical conditions Tr P^(k) = 0 (k >= 1) are linear in mu^(k): with
+// E^(k) = H^(k) - mu^(k) I, P^(k)(mu^(k)) = P^(k)(0) - mu^(k) J, where J is the
+// first-order response to H1 = I at the converged mu0.  One pass for order 1
+// (the d directions plus the identity, mu1 = 0) gives mu1 = Tr P1(0) / Tr J;
+// one pass for order 2 at that mu1 (mu2 = 0) gives mu2 = Tr P2(0) / Tr J.
+// This reaches the fixed point of Algorithm 1's Newton loop in one pass per
+// order instead of iterating all orders together.
+dmpt_status linear_orders(Call& k, const PassIn& base, int64_t N, int order, double* mu,
+                          double* P0, double* const* P1, double* const* P2) {
+  dmpt_ctx c = k.c;
+  hipStream_t s = c->stream;
+  const int d = base.d;
+  const int64_t nn = N * N;
+  uint16_t* none[3] = {nullptr, nullptr, nullptr};
+  // ---- order 1 with the identity as direction d
+  std::vector<const double*> h1x(base.H1, base.H1 + d);
+  h1x.push_back(nullptr);
+  std::vector<double*> p1x(P1, P1 + d);
+  p1x.push_back(c->jout);
+  std::vector<double> m1(2 + 2 * DMPT_MAX_DIRS, 0.0);
+  m1[0] = mu[0];
+  m1[1 + d] = -1.0;  // D0^(1) = c (0 - (-1) I) = c I: the response to H1 = I
+  PassIn in1{base.H0, d + 1, h1x.data(), nullptr, base.beta, base.n, 1, m1.data()};
+  STCHK(pass_dispatch(k, in1, P0, p1x.data(), nullptr));
+  const double trJ = c->h_res[RES_TR + 1 + d];
+  if (!(std::fabs(trJ) > 0.0) || !std::isfinite(trJ))
+    return fail(c, DMPT_ERR_NOCONV, "Tr J vanished: the occupation does not respond to mu");
+  for (int z = 0; z < d; ++z) {
+    mu[1 + z] = c->h_res[RES_TR + 1 + z] / trJ;
+    HIPCHK(c, axpby<double>(c->jout, 0, P1[z], 0, nn, 1, -mu[1 + z], 1.0, none, 0, 0, s));
+  }
+  if (order >= 2) {
+    std::vector<double> m2(1 + 2 * DMPT_MAX_DIRS, 0.0);
+    for (int i = 0; i <= d; ++i) m2[i] = mu[i];
+    PassIn in2{base.H0, d, base.H1, base.H2, base.beta, base.n, 2, m2.data()};
+    STCHK(pass_dispatch(k, in2, P0, P1, P2));
+    for (int z = 0; z < d; ++z) {
+      mu[1 + d + z] = c->h_res[RES_TR + 1 + d + z] / trJ;
+      HIPCHK(c, axpby<double>(c->jout, 0, P2[z], 0, nn, 1, -mu[1 + d + z], 1.0, none, 0, 0, s));
+    }
+  }
+  // traces and response traces of the returned (corrected) matrices
+  for (int o = 1; o <= order; ++o)
+    for (int z = 0; z < d; ++z) {
+      double* Pk = o == 1 ? P1[z] : P2[z];
+      const int slot = (o == 1 ? 1 : 1 + d) + z;
+      HIPCHK(c, trace(Pk, N, 0, N, 1, c->d_res + RES_TR + slot, 1, c->d_res + RES_ATR + slot, s));
+      HIPCHK(c, dot_partials<double>(base.H1[z], 0, Pk, 0, nn, 1, c->d_part, s));
+      HIPCHK(c, sum_partials(c->d_part, reduce_blocks(nn), 1,
+                             c->d_res + (o == 1 ? RES_H1P1 : RES_H1P2) + z, 1, 0, s));
+    }
+  HIPCHK(c, hipMemcpyAsync(c->h_res, c->d_res, RES_MISC * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  return DMPT_OK;
 }
 
 }  // namespace
@@ -1329,6 +1412,7 @@ void dmpt_default_options(dmpt_options* o) {
   o->check = 0;
   o->staged = 1;
   o->warm_traj = 1;
+  o->schedule = 1;
 }
 
 static dmpt_status normalise_options(dmpt_ctx c, const dmpt_options* in, dmpt_options* out) {
@@ -1354,8 +1438,9 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
                       void* hip_stream) {
   if (!out) return DMPT_ERR_ARG;
   *out = nullptr;
-  if (n_max < 1 || n_max > (int64_t)1 << 17) {
-    std::snprintf(g_noctx_err, sizeof g_noctx_err, "n_max must lie in [1, 131072]");
+  // the BF16 plane layout indexes an Np x Np member with 32-bit offsets
+  if (n_max < 1 || n_max > 65408) {
+    std::snprintf(g_noctx_err, sizeof g_noctx_err, "n_max must lie in [1, 65408]");
     return DMPT_ERR_ARG;
   }
   if (dirs_max < 0 || dirs_max > DMPT_MAX_DIRS) {
@@ -1390,13 +1475,15 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
     c->own_stream = true;
   }
   if (gemm_prepare() != hipSuccess) return bail(DMPT_ERR_HIP, "product kernel attributes");
+  c->log = std::getenv("DMPT_LOG") != nullptr;
   c->n_max = n_max;
   c->np_max = padded(n_max);
   c->dirs_max = dirs_max;
   c->esize = esize_needed(c->opt);
   c->planes = planes_needed(c->opt);
-  // two members at least: the adjoint solves its two seeds together
-  const int dm = std::max(2, dirs_max);
+  // two members at least (the adjoint solves its two seeds together) and one
+  // more than dirs_max (the response to the identity of the linear schedule)
+  const int dm = std::max(2, dirs_max + 1);
   const size_t nn = (size_t)c->np_max * c->np_max;
   auto alloc = [&](size_t bytes) -> void* {
     void* p = dev_alloc(c, bytes);
@@ -1414,7 +1501,7 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
       }
     return true;
   };
-  const int dd = dirs_max;  // groups for perturbations may be empty
+  const int dd = dirs_max > 0 ? dirs_max + 1 : 0;  // groups for perturbations may be empty
   bool ok = group(c->ws.D0, 1, true) && group(c->ws.S0, 1, true) && group(c->ws.R, dm, false) &&
             group(c->ws.P, dm, true) && group(c->ws.Q, dm, false) && group(c->U0, 1, true);
   if (ok && dd > 0)
@@ -1433,12 +1520,16 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
   c->part_count = std::max<size_t>(tiles, 1024) * dm;
   c->d_part = (double*)alloc(sizeof(double) * c->part_count);
   c->d_gersh = (double*)alloc(sizeof(double) * (2 + 2 * (size_t)n_max));
+  if (dirs_max > 0) {
+    c->jout = (double*)alloc(sizeof(double) * (size_t)n_max * n_max);
+    if (!c->jout) return bail(DMPT_ERR_NOMEM, "device workspace allocation failed");
+  }
   if (!c->ws.rr || !c->ws.pq || !c->ws.ref || !c->ws.active || !c->ws.iters || !c->d_flag || !c->d_res ||
       !c->d_part || !c->d_gersh)
     return bail(DMPT_ERR_NOMEM, "device scalar allocation failed");
   if (hipHostMalloc((void**)&c->h_res, sizeof(double) * RES_COUNT, hipHostMallocDefault) != hipSuccess)
     return bail(DMPT_ERR_NOMEM, "pinned allocation failed");
-  if (hipHostMalloc((void**)&c->h_int, sizeof(int) * 4 * DMPT_MAX_DIRS, hipHostMallocDefault) !=
+  if (hipHostMalloc((void**)&c->h_int, sizeof(int) * 2 * kIterSlot, hipHostMallocDefault) !=
       hipSuccess)
     return bail(DMPT_ERR_NOMEM, "pinned allocation failed");
   // zero the workspace once so the padding of every member starts at zero
@@ -1693,23 +1784,34 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
     Engine eng;
     double tol_cg, tol_occ;
   };
-  if (c->opt.warm_traj && ensure_traj(c, n, 1 + 2 * dd, k.Np)) {
+  // linear schedule: the loop converges mu0 with order-0 passes, then one
+  // pass per order (with the response J to H1 = I) fixes mu1 and mu2 exactly
+  const bool linear = c->opt.schedule == 1 && order >= 1;
+  const int loop_order = linear ? 0 : order;
+  // trajectory members: order 0, order 1 (plus the identity direction of the
+  // linear schedule), order 2
+  const int jets = linear ? std::max(2 + dd, 1 + 2 * dd) : 1 + 2 * dd;
+  if (c->opt.warm_traj && ensure_traj(c, n, jets, k.Np)) {
     k.traj = true;
-    k.jets = 1 + 2 * dd;
+    k.jets = jets;
   }
   Phase phases[2];
   int nph = 0;
   if (two_phase)
-    phases[nph++] = {Engine::BF16S2, default_tol_cg(DMPT_BF16X3, 0), default_tol_occ(DMPT_BF16X3, 0)};
+    phases[nph++] = {Engine::BF16S2, kPhaseATolCg, kPhaseATolOcc};
   phases[nph++] = {two_phase ? Engine::BF16S3 : k.eng, c->opt.tol_cg, c->opt.tol_occ};
   int ph = 0;
   double occ = 0;
   int it = 0;
   bool done = false;
   // staged: order-0 passes until mu0 is close, then passes of every order
-  const bool staged = c->opt.staged && order > 0;
-  int stage_order = staged ? 0 : order;
+  const bool staged = c->opt.staged && loop_order > 0;
+  int stage_order = staged ? 0 : loop_order;
   double prev_err = INFINITY;
+  // bracket of mu0 from the signs of Tr P0 - Ne seen so far (Tr P0 grows
+  // with mu0); a Newton step that leaves it, or a vanishing Tr P_mu, is
+  // replaced by bisection
+  double br_lo = mu_lo, br_hi = mu_hi;
   for (it = 1; it <= c->opt.max_newton; ++it) {
     const Phase& P = phases[ph];
     k.eng = P.eng;
@@ -1720,28 +1822,59 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
     const double* r = c->h_res;
     if (!std::isfinite(r[RES_TR]) || !std::isfinite(r[RES_FRO]))
       return fail(c, DMPT_ERR_NONFINITE, "non-finite trace in the Newton loop");
-    bool ok = converged(r, dd, stage_order, Ne, N, P.tol_occ, &occ);
-    const bool last = ph == nph - 1 && stage_order == order;
-    // noise floor: in the final phase, an error that stopped shrinking and is
-    // within 1000 tol_occ counts as converged (the traces carry the
-    // products' rounding)
-    if (!ok && last && occ > 0.5 * prev_err && occ <= 1e3 * P.tol_occ * (double)N) ok = true;
+    double rel = 0.0;
+    occupation_error(r, dd, stage_order, Ne, N, &occ, &rel);
+    bool ok = rel <= P.tol_occ;
+    const bool last = ph == nph - 1 && stage_order == loop_order;
+    if (c->log)
+      std::fprintf(stderr,
+                   "[dmpt] pass %d phase %d engine %d order %d mu0 %.15g TrP0-Ne %.3e occ_err %.3e "
+                   "rel %.3e cg_total %ld\n",
+                   it, ph, (int)P.eng, stage_order, mu[0], r[RES_TR] - Ne, occ, rel, c->cg_total);
+    // noise floor: a normalised error that stopped shrinking and is within
+    // 1000 tol_occ counts as converged (the traces carry the products'
+    // rounding); before the final phase and stage this only moves on
+    if (!ok && rel > 0.5 * prev_err && rel <= 1e3 * P.tol_occ) ok = true;
     if (ok && last) {
       done = true;
       break;
     }
-    prev_err = last ? occ : INFINITY;
+    prev_err = rel;
+    if (r[RES_TR] < Ne) br_lo = std::max(br_lo, mu[0]);
+    else br_hi = std::min(br_hi, mu[0]);
     const double trpmu = beta * (r[RES_TR] - r[RES_FRO]);
-    if (!(trpmu > 0.0)) return fail(c, DMPT_ERR_NOCONV, "Tr P_mu vanished: Newton step undefined");
-    mu[0] += (Ne - r[RES_TR]) / trpmu;
-    mu[0] = std::min(std::max(mu[0], mu_lo), mu_hi);
-    for (int i = 1; i < 1 + stage_order * dd; ++i) mu[i] -= r[RES_TR + i] / trpmu;
+    const double mu_n = mu[0] + (Ne - r[RES_TR]) / trpmu;
+    // once Tr P0 meets its own tolerance the (tiny) Newton step is always
+    // taken: the bracket's ends then carry the traces' rounding
+    const bool occ_met = std::fabs(r[RES_TR] - Ne) <= P.tol_occ * (double)N;
+    if (trpmu > 0.0 && (occ_met || (mu_n >= br_lo && mu_n <= br_hi))) {
+      mu[0] = mu_n;
+      for (int i = 1; i < 1 + stage_order * dd; ++i) mu[i] -= r[RES_TR + i] / trpmu;
+    } else {
+      mu[0] = 0.5 * (br_lo + br_hi);
+      if (c->log) std::fprintf(stderr, "[dmpt] bisection step to mu0 %.15g\n", mu[0]);
+    }
     if (ok) {
-      if (stage_order < order) stage_order = order;
-      else if (ph < nph - 1) ++ph;
+      prev_err = INFINITY;
+      if (stage_order < loop_order) {
+        stage_order = loop_order;
+      } else if (ph < nph - 1) {
+        ++ph;  // the bracket came from a noisier engine: start over
+        br_lo = mu_lo;
+        br_hi = mu_hi;
+      }
     }
   }
   if (it > c->opt.max_newton) it = c->opt.max_newton;
+  if (done && linear) {
+    const Phase& P = phases[nph - 1];
+    k.eng = P.eng;
+    k.np = engine_planes(P.eng);
+    k.tol_cg = P.tol_cg;
+    STCHK(linear_orders(k, in, N, order, mu.data(), P0, P1, P2));
+    it += order;
+    occupation_error(c->h_res, dd, order, Ne, N, &occ, &prev_err);
+  }
   in.order = order;
   for (int i = 0; i < nmu; ++i) mu_inout[i] = mu[i];
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1884,9 +2017,10 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
   double* d_tr = (double*)dalloc(sizeof(double) * nsys * rs);
   double* d_par = (double*)dalloc(sizeof(double) * nsys * 6);
   double* d_prev = (double*)dalloc(sizeof(double) * nsys);
+  double* d_brk = (double*)dalloc(sizeof(double) * 2 * nsys);
   double* d_occ = (double*)dalloc(sizeof(double) * nsys);
   int* d_flags = (int*)dalloc(sizeof(int) * nsys * 6);  // activeA, activeB, done, passes, status, spare
-  if (!d_mu || !d_shift || !d_tr || !d_par || !d_prev || !d_occ || !d_flags) {
+  if (!d_mu || !d_shift || !d_tr || !d_par || !d_prev || !d_brk || !d_occ || !d_flags) {
     cleanup();
     return fail(c, DMPT_ERR_NOMEM, "batched scalar allocation failed");
   }
@@ -1932,11 +2066,15 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
     }
     std::vector<int> hfl(6 * (size_t)nsys, 0);
     for (int i = 0; i < 2 * nsys; ++i) hfl[i] = 1;
-    std::vector<double> hprev(nsys, INFINITY);
+    std::vector<double> hbrk(2 * (size_t)nsys);
+    for (int slot = 0; slot < nsys; ++slot) {
+      hbrk[2 * slot] = hpar[6 * (size_t)slot + 3];
+      hbrk[2 * slot + 1] = hpar[6 * (size_t)slot + 4];
+    }
     if (hipMemcpy(d_mu, hmu.data(), hmu.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(d_shift, hsh.data(), hsh.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(d_par, hpar.data(), hpar.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(d_prev, hprev.data(), hprev.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d_brk, hbrk.data(), hbrk.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(d_flags, hfl.data(), hfl.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
       cleanup();
       return fail(c, DMPT_ERR_HIP, "batched state upload failed");
@@ -1954,6 +2092,14 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
     const int ord = stage == 0 ? 0 : order;
     const bool final_stage = stage == 1;
     const double mf0 = c->mfma_flops, uf0 = c->useful_flops;
+    {
+      // every stage starts its noise-floor test afresh
+      std::vector<double> hprev(nsys, INFINITY);
+      if (hipMemcpy(d_prev, hprev.data(), hprev.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
+        rc = fail(c, DMPT_ERR_HIP, "batched state upload failed");
+        break;
+      }
+    }
     // capture one pass of this stage
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
       rc = fail(c, DMPT_ERR_HIP, "hipStreamBeginCapture failed");
@@ -1967,7 +2113,7 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
     if (cr == DMPT_OK) {
       const hipError_t e = newton_update(d_tr, rs, d_par, d_mu, d_shift, J, ord * d, c->opt.tol_occ,
                                          final_stage ? 1 : 0, final_stage ? actB : actA, done,
-                                         d_prev, d_occ, passes, status, nsys, s);
+                                         d_prev, d_brk, d_occ, passes, status, nsys, s);
       if (e != hipSuccess) cr = fail(c, DMPT_ERR_HIP, "newton_update launch failed");
     }
     hipGraph_t g = nullptr;
@@ -2029,6 +2175,10 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
     if (!hfl[2 * nsys + slot]) all_done = false;
     if (hfl[4 * nsys + slot] == -6) nonfinite = true;
     occ_sum += hocc[slot];
+    if (c->log)
+      std::fprintf(stderr, "[dmpt] system %d N %ld beta %.4g: passes %d done %d status %d occ_err %.3e mu0 %.15g\n",
+                   sy, (long)Ns[sy], betas[sy], hfl[3 * nsys + slot], hfl[2 * nsys + slot],
+                   hfl[4 * nsys + slot], hocc[slot], hmu[(size_t)slot * J]);
   }
   if (st) {
     std::memset(st, 0, sizeof(*st));

@@ -72,7 +72,8 @@ hipError_t gemm_prepare();
 
 // ---------------------------------------------------------------- element-wise
 // out = a (in + in^T) + a2 (in2 + in2^T) + dshift I on the leading N x N
-// block, 0 elsewhere (in2 may be null).
+// block, 0 elsewhere (in2 may be null).  When gate is not null the kernel
+// does nothing while *gate == 0.
 // in: Tin with leading dim ldi; out: Tout with leading dim ldo (+ split planes).
 // Batched over `batch` members with element strides.
 // The tile pair (i, j) / (j, i) is handled by one block, so in == out is allowed.
@@ -80,7 +81,7 @@ template <class Tin, class Tout>
 hipError_t sym_combine(const Tin* in, int64_t ldi, int64_t si, int64_t N, int64_t Np, double a,
                        const double* dshift, int dstride, Tout* out, int64_t ldo, int64_t so,
                        uint16_t* const* planes, int nplanes, int batch, hipStream_t s,
-                       const Tin* in2 = nullptr, double a2 = 0.0);
+                       const Tin* in2 = nullptr, double a2 = 0.0, const int* gate = nullptr);
 
 // out = in^T (Np x Np members, batched, with planes); in != out.
 template <class T>
@@ -118,9 +119,10 @@ template <class T>
 hipError_t cg_update_p(T* P, const T* R, int64_t n, int64_t stride, int batch,
                        const double* rr_new, const double* rr_old, int hstride, const int* active,
                        uint16_t* const* planes, int nplanes, hipStream_t s);
-// convergence: active[z] = rr[z] > tol^2 * ref[z]  (with iteration counter), any batch size
-hipError_t cg_check(const double* rr, const double* ref, int hstride, int batch, double tol2,
-                    int* active, int* iters, hipStream_t s);
+// convergence: active[z] stays 1 while rr > tol2 ref or rr > eta2 rr0 (rr0: the
+// initial residual); iters[z] counts the checks.  Any batch size.
+hipError_t cg_check(const double* rr, const double* rr0, const double* ref, int hstride, int batch,
+                    double tol2, double eta2, int* active, int* iters, hipStream_t s);
 
 // Element-wise linear combination: y = a x + b y (batched, master only) + planes
 template <class T>
@@ -150,8 +152,8 @@ hipError_t fill_pattern(T* x, int64_t n, uint32_t seed, uint16_t* const* planes,
 // Device-side canonical Newton update of a batch of systems (see elementwise.hip).
 hipError_t newton_update(const double* tr, int rs, const double* par, double* mu, double* shift,
                          int J, int nk, double tol, int final_stage, int* active, int* done,
-                         double* prev_err, double* occ, int* passes, int* status, int nsys,
-                         hipStream_t s);
+                         double* prev_err, double* brk, double* occ, int* passes, int* status,
+                         int nsys, hipStream_t s);
 
 // Scan for non-finite values: flag |= any(!isfinite(x))
 hipError_t nonfinite_scan(const double* x, int64_t ld, int64_t N, int* flag, hipStream_t s);

@@ -63,10 +63,11 @@ __global__ __launch_bounds__(kT) void k_sym(const Tin* in, int64_t ldi, int64_t 
                                             int64_t Np, double a, const double* dshift,
                                             int dstride, Tout* out, int64_t ldo, int64_t so,
                                             Planes pl, int np, int64_t out_rows, const Tin* in2,
-                                            double a2) {
+                                            double a2, const int* gate) {
   __shared__ double ta[32][33], tb[32][33];
   const int64_t bi = blockIdx.y, bj = blockIdx.x;
   if (bi > bj) return;
+  if (gate && !*gate) return;  // a converged system of a batch keeps its outputs
   const int z = blockIdx.z;
   in += z * si;
   if (in2) in2 += z * si;
@@ -234,12 +235,17 @@ __global__ __launch_bounds__(kT) void k_cg_p(T* __restrict__ P, const T* __restr
   }
 }
 
-__global__ void k_cg_check(const double* rr, const double* ref, int hstride, int batch,
-                           double tol2, int* active, int* iters) {
+// A member stays active while ||r||^2 > tol2 ||rhs||^2 or ||r||^2 > eta2 ||r_0||^2:
+// a warm-started solve must also shrink its own initial residual, so the
+// solution follows small changes of the right-hand side (a mu update)
+// instead of keeping the previous solution within the tolerance.
+__global__ void k_cg_check(const double* rr, const double* rr0, const double* ref, int hstride,
+                           int batch, double tol2, double eta2, int* active, int* iters) {
   const int z = blockIdx.x * blockDim.x + threadIdx.x;
   if (z >= batch || !active[z]) return;
   iters[z] += 1;
-  if (!(rr[z * hstride] > tol2 * ref[z])) active[z] = 0;
+  const double r = rr[z * hstride];
+  if (!(r > tol2 * ref[z] || r > eta2 * rr0[z * hstride])) active[z] = 0;
 }
 
 template <class T>
@@ -400,20 +406,24 @@ __global__ __launch_bounds__(kT) void k_fill(T* x, int64_t n, uint32_t seed, Pla
 // update with Tr P_mu = beta (Tr P0 - ||P0||_F^2)), one thread per system.
 // tr[s*rs + ...]: Tr P^(k) (J values), sum |P^(k)_ii| (J), ||P0||_F^2.
 // par[s*6 + ...]: beta, Ne, c = 2^-(n+2) beta, mu0 lower bound, mu0 upper bound, N.
+// brk[s*2 + ...]: the current bracket of mu0 (starts as the bounds);
+// prev_err[s]: the previous pass's normalised error (starts at +inf).
 __global__ void k_newton(const double* tr, int rs, const double* par, double* mu, double* shift,
                          int J, int nk, double tol, int final_stage, int* active, int* done,
-                         double* prev_err, double* occ, int* passes, int* status, int nsys) {
+                         double* prev_err, double* brk, double* occ, int* passes, int* status,
+                         int nsys) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nsys || !active[s]) return;
   const double* t = tr + (int64_t)s * rs;
   const double beta = par[s * 6 + 0], Ne = par[s * 6 + 1], c = par[s * 6 + 2];
   const double lo = par[s * 6 + 3], hi = par[s * 6 + 4], N = par[s * 6 + 5];
+  // occupation error (absolute) and its normalised form
   double err = fabs(t[0] - Ne);
-  bool ok = err <= tol * N;
+  double rel = err / N;
   for (int i = 1; i <= nk; ++i) {
     const double a = fabs(t[i]);
     err += a;
-    if (!(a <= tol * fmax(t[J + i], 1e-300))) ok = false;
+    rel = fmax(rel, a / fmax(t[J + i], 1e-300));
   }
   passes[s] += 1;
   occ[s] = err;
@@ -422,23 +432,34 @@ __global__ void k_newton(const double* tr, int rs, const double* par, double* mu
     active[s] = 0;
     return;
   }
-  if (final_stage && !ok && err > 0.5 * prev_err[s] && err <= 1e3 * tol * N) ok = true;
-  if (final_stage) prev_err[s] = err;
+  bool ok = rel <= tol;
+  // noise floor: stopped shrinking within 1000 tol (the traces carry the
+  // products' rounding)
+  if (!ok && rel > 0.5 * prev_err[s] && rel <= 1e3 * tol) ok = true;
+  prev_err[s] = rel;
   if (ok) {
     active[s] = 0;
-    done[s] = 1;
-    return;
-  }
-  const double trpmu = beta * (t[0] - t[2 * J]);
-  if (!(trpmu > 0.0)) {
-    status[s] = -4;
-    active[s] = 0;
+    done[s] = final_stage;
     return;
   }
   double* m = mu + (int64_t)s * J;
   double* sh = shift + (int64_t)s * J;
-  m[0] = fmin(fmax(m[0] + (Ne - t[0]) / trpmu, lo), hi);
-  for (int i = 1; i <= nk; ++i) m[i] -= t[i] / trpmu;
+  // bracket of mu0 from the signs of Tr P0 - Ne (Tr P0 grows with mu0); a
+  // Newton step outside it, or a vanishing Tr P_mu, becomes a bisection
+  double* b = brk + 2 * (int64_t)s;
+  if (t[0] < Ne) b[0] = fmax(b[0], m[0]);
+  else b[1] = fmin(b[1], m[0]);
+  const double trpmu = beta * (t[0] - t[2 * J]);
+  const double mn = m[0] + (Ne - t[0]) / trpmu;
+  // once Tr P0 meets its own tolerance the (tiny) step is always taken
+  const bool occ_met = fabs(t[0] - Ne) <= tol * N;
+  if (trpmu > 0.0 && (occ_met || (mn >= b[0] && mn <= b[1]))) {
+    m[0] = mn;
+    for (int i = 1; i <= nk; ++i) m[i] -= t[i] / trpmu;
+  } else {
+    m[0] = 0.5 * (b[0] + b[1]);
+  }
+  m[0] = fmin(fmax(m[0], lo), hi);
   for (int i = 0; i < J; ++i) sh[i] = -c * m[i];
 }
 
@@ -479,14 +500,14 @@ template <class Tin, class Tout>
 hipError_t sym_combine(const Tin* in, int64_t ldi, int64_t si, int64_t N, int64_t Np, double a,
                        const double* dshift, int dstride, Tout* out, int64_t ldo, int64_t so,
                        uint16_t* const* planes, int nplanes, int batch, hipStream_t s,
-                       const Tin* in2, double a2) {
+                       const Tin* in2, double a2, const int* gate) {
   Planes pl{{nullptr, nullptr, nullptr}};
   for (int p = 0; p < nplanes; ++p) pl.p[p] = planes[p];
   const int64_t rows = (ldo == N && ldo != Np) ? N : ldo;  // caller buffer: only N x N
   const int64_t span = rows > N ? rows : N;
   const unsigned nb = (unsigned)((span + 31) / 32);
   hipLaunchKernelGGL((k_sym<Tin, Tout>), dim3(nb, nb, batch), dim3(kT), 0, s, in, ldi, si, N, Np, a,
-                     dshift, dstride, out, ldo, so, pl, nplanes, rows, in2, a2);
+                     dshift, dstride, out, ldo, so, pl, nplanes, rows, in2, a2, gate);
   return hipGetLastError();
 }
 
@@ -494,7 +515,7 @@ hipError_t sym_combine(const Tin* in, int64_t ldi, int64_t si, int64_t N, int64_
   template hipError_t sym_combine<TI, TO>(const TI*, int64_t, int64_t, int64_t, int64_t, double,  \
                                           const double*, int, TO*, int64_t, int64_t,             \
                                           uint16_t* const*, int, int, hipStream_t, const TI*,    \
-                                          double);
+                                          double, const int*);
 DMPT_SYM_INST(double, double)
 DMPT_SYM_INST(double, float)
 DMPT_SYM_INST(float, float)
@@ -570,10 +591,10 @@ template hipError_t cg_update_p<float>(float*, const float*, int64_t, int64_t, i
                                        const double*, int, const int*, uint16_t* const*, int,
                                        hipStream_t);
 
-hipError_t cg_check(const double* rr, const double* ref, int hstride, int batch, double tol2,
-                    int* active, int* iters, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_check, dim3((batch + 63) / 64), dim3(64), 0, s, rr, ref, hstride, batch,
-                     tol2, active, iters);
+hipError_t cg_check(const double* rr, const double* rr0, const double* ref, int hstride, int batch,
+                    double tol2, double eta2, int* active, int* iters, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_check, dim3((batch + 63) / 64), dim3(64), 0, s, rr, rr0, ref, hstride,
+                     batch, tol2, eta2, active, iters);
   return hipGetLastError();
 }
 
@@ -648,10 +669,10 @@ template hipError_t fill_pattern<float>(float*, int64_t, uint32_t, uint16_t* con
 
 hipError_t newton_update(const double* tr, int rs, const double* par, double* mu, double* shift,
                          int J, int nk, double tol, int final_stage, int* active, int* done,
-                         double* prev_err, double* occ, int* passes, int* status, int nsys,
-                         hipStream_t s) {
+                         double* prev_err, double* brk, double* occ, int* passes, int* status,
+                         int nsys, hipStream_t s) {
   hipLaunchKernelGGL(k_newton, dim3((nsys + 63) / 64), dim3(64), 0, s, tr, rs, par, mu, shift, J, nk,
-                     tol, final_stage, active, done, prev_err, occ, passes, status, nsys);
+                     tol, final_stage, active, done, prev_err, brk, occ, passes, status, nsys);
   return hipGetLastError();
 }
 

@@ -89,11 +89,13 @@ def chain128_ref():
     return c, r
 
 
-@pytest.mark.parametrize("warm_traj", [1, 0])
-def test_chain128_canonical_fp64(dm, chain128_ref, warm_traj):
-    print(f"case chain128 canonical fp64 warm_traj={warm_traj}", flush=True)
+@pytest.mark.parametrize("schedule,warm_traj", [(1, 1), (1, 0), (0, 1), (0, 0)])
+def test_chain128_canonical_fp64(dm, chain128_ref, schedule, warm_traj):
+    """Both canonical schedules: the linear one (mu0 loop, then one pass per
+    order with the identity response) and Algorithm 1's joint Newton loop."""
+    print(f"case chain128 canonical fp64 schedule={schedule} warm_traj={warm_traj}", flush=True)
     c, ref = chain128_ref
-    with dm.Context(c["N"], dirs_max=1, prec="fp64", warm_traj=warm_traj) as ctx:
+    with dm.Context(c["N"], dirs_max=1, prec="fp64", warm_traj=warm_traj, schedule=schedule) as ctx:
         P0, P1, P2, mu, st = ctx.mu_newton(T(c["H0"]), [T(h) for h in c["H1"]], None,
                                            beta=c["beta"], Ne=c["Ne"], n=c["n"], order=2)
     e0, e1, e2 = errs(P0, P1, P2, ref)
@@ -124,10 +126,10 @@ def test_chain128_canonical_low_precision(dm, chain128_ref, prec, extra, tol):
     assert e0 < tol and e1 < tol and e2 < tol
 
 
-@pytest.mark.parametrize("N,d", [(250, 3), (384, 2)])
-def test_ragged_multi_direction_fp64(dm, N, d):
+@pytest.mark.parametrize("N,d,schedule", [(250, 3, 1), (384, 2, 1), (250, 3, 0)])
+def test_ragged_multi_direction_fp64(dm, N, d, schedule):
     """N not a multiple of the tile, several directions, non-zero H2."""
-    print(f"case ragged canonical fp64 N={N} d={d}", flush=True)
+    print(f"case ragged canonical fp64 N={N} d={d} schedule={schedule}", flush=True)
     rng = np.random.default_rng(N)
     h0 = workloads.banded(N, 9, bandwidth=24, decay=8.0)
     grid = [np.arange(N) % 7 - 3.0, (np.arange(N) // 7) % 5 - 2.0, np.sin(np.arange(N))]
@@ -135,7 +137,7 @@ def test_ragged_multi_direction_fp64(dm, N, d):
     h2 = [_sym(rng, N, 0.02) if i == 0 else None for i in range(d)]
     beta, n, Ne = 12.0, 22, N / 2.0 - 3.0
     ref = oracle.canonical_response(h0, h1, h2, beta, Ne, n, order=2)
-    with dm.Context(N, dirs_max=d, prec="fp64") as ctx:
+    with dm.Context(N, dirs_max=d, prec="fp64", schedule=schedule) as ctx:
         P0, P1, P2, mu, st = ctx.mu_newton(T(h0), [T(h) for h in h1],
                                            [T(h) if h is not None else None for h in h2],
                                            beta=beta, Ne=Ne, n=n, order=2)
@@ -144,6 +146,9 @@ def test_ragged_multi_direction_fp64(dm, N, d):
     assert e0 < 1e-10 and e1 < 1e-10 and e2 < 1e-10
     for z in range(d):
         assert abs(st["tr_h2p0"][z] - ref["tr_h2p0"][z]) < 1e-10 * max(1, abs(ref["tr_h2p0"][z]))
+        assert abs(mu[1 + z] - ref["mu1"][z]) < 1e-9 * max(1, abs(ref["mu1"][z]))
+        assert abs(mu[1 + d + z] - ref["mu2"][z]) < 1e-9 * max(1, abs(ref["mu2"][z]))
+        assert abs(st["tr_h1p2"][z] - ref["tr_h1p2"][z]) < 1e-10 * max(1, abs(ref["tr_h1p2"][z]))
 
 
 def test_single_site(dm):
