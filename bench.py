@@ -16,9 +16,18 @@ per second = directions / seconds per step.
 Printed: one JSON line with the metric, the roofline of the dominant kernel
 (the split-BF16 MFMA product kernel, timed with HIP events on the library's
 stream over the timed region), accuracy on the oracle's sampled entries, and
-the FP64 CPU oracle timed on a bounded sample on this host.
+the FP64 CPU oracle timed on a bounded sample on this host.  The roofline's
+"traffic" (HBM bytes per launch of that kernel) comes from the hardware
+counter summary profiles/traffic_<engine>.json when it was taken on the
+current product-kernel source, else null.
+
+Other modes: --fp64-compare also times one FP64 solve of the same workload
+on the GPU (the same library in DMPT_FP64); --copy-calibration only runs a
+plain device copy of known size, the reference that scales the FETCH_SIZE /
+WRITE_SIZE counters into bytes.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -45,7 +54,43 @@ def parse():
     ap.add_argument("--tol-occ", type=float, default=0.0)
     ap.add_argument("--refine", type=int, default=-1,
                     help="bf16x3: finish with the 6-product refinement passes (default on)")
+    ap.add_argument("--fp64-compare", action="store_true",
+                    help="also time one FP64 solve of the same workload on the GPU")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (counter calibration)")
     return ap.parse_args()
+
+
+def kernel_source_sha():
+    """SHA-256 of the product-kernel source the traffic counters must match."""
+    path = os.path.join(ROOT, "paper_1503_07037_amd", "csrc", "gemm.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(engine):
+    """HBM bytes per launch of the product kernel from the committed counter summary, or None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{engine}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_source_sha256") != kernel_source_sha():
+        return None  # the kernel changed since the counters were taken
+    return t
+
+
+def copy_calibration():
+    """A plain device-to-device copy of 2 GiB, five times (read 2 GiB + write 2 GiB each)."""
+    import torch
+    n = 1 << 28
+    src = torch.arange(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "copies": 5}), flush=True)
 
 
 def cpu_baseline(n_sample, n_full, dirs):
@@ -93,12 +138,32 @@ def accuracy(name, P0, P1, P2, mu):
             "mu0_err": abs(mu[0] - float(g["mu0"])), "samples": int(i.size)}
 
 
+def fp64_gpu(dm, c, H0, H1, d, order):
+    """One FP64 canonical solve of the same workload (context created and warmed first)."""
+    import torch
+    N = c["N"]
+    ctx = dm.Context(N, dirs_max=d, prec="fp64")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = ctx.mu_newton(H0, H1, None, beta=c["beta"], Ne=c["Ne"], n=c["n"], order=order)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    st = out[4]
+    ctx.close()
+    return out, {"seconds": secs, "value": d / secs, "unit": "responses/s",
+                 "newton_iters": st["newton_iters"], "cg_iters_total": st["cg_iters_total"],
+                 "mfma_tflops": st["mfma_flops"] / secs / 1e12}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sharded "
               f"design is described in DESIGN.md and not built.", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import numpy as np
     import torch
     import workloads
@@ -145,6 +210,7 @@ def main():
     peak = PEAKS_TFLOPS[dom]
     name = args.workload if not args.n else None
     acc = accuracy(name, P0, P1, P2, mu) if name else None
+    traffic = measured_traffic(dom)
     res = {
         "metric": "response solves/sec (P0+P1+P2) and MFMA TFLOP/s at N=8192, err <=1e-6 vs FP64",
         "value": value, "unit": "responses/s", "n_gpus": 1, "steps": args.steps,
@@ -157,7 +223,10 @@ def main():
                    "precision": args.prec + ("+refine(bf16x6)" if refine else ""),
                    "parallelism": "single GPU"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak,
+                     "traffic": traffic["bytes_per_launch"] if traffic else None,
+                     "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+                     "algorithmic_bytes_per_launch": pe["bytes"] / max(pe["launches"], 1),
                      "kernel": f"product kernel, {dom} engine", "launches": pe["launches"],
                      "avg_launch_ms": avg_ms,
                      "product_time_share": prof["ms"] / ms_step / args.steps,
@@ -170,6 +239,13 @@ def main():
         "accuracy": acc,
     }
     ctx.close()
+    del P0, P1, P2, out
+    if args.fp64_compare:
+        out64, f64 = fp64_gpu(dm, c, H0, H1, d, order)
+        f64["accuracy"] = accuracy(name, out64[0], out64[1], out64[2], out64[3]) if name else None
+        f64["speedup_of_this_run"] = value / f64["value"]
+        res["fp64_gpu"] = f64
+        del out64
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(min(args.cpu_sample_n, N), N, d)
     print(json.dumps(res), flush=True)

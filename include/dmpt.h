@@ -74,7 +74,8 @@ typedef enum {
 /* Initial guess of the conjugate-gradient solve. */
 typedef enum {
   DMPT_GUESS_PREV = 0,   /* the previous iterate X_{n-1}^(k) (Algorithm 1 remark) */
-  DMPT_GUESS_TAYLOR = 1  /* 2D - 8D^3 for order 0, previous iterate for the others */
+  DMPT_GUESS_TAYLOR = 1  /* 2D - 8D^3 for order 0 (one more product per step), previous iterate
+                            for the others; a stored trajectory (warm_traj) takes precedence */
 } dmpt_guess;
 
 typedef struct {
@@ -207,6 +208,10 @@ typedef struct {
   int64_t eng_launches[4];
   double eng_ms[4];
   double eng_mfma_flops[4];
+  /* algorithmic HBM bytes of those launches: every operand member read once
+     (BF16 planes for the split engines, masters otherwise; C1, C2 and W
+     masters), C's master and planes written once */
+  double eng_bytes[4];
 } dmpt_profile_data;
 
 dmpt_status dmpt_profile(dmpt_ctx ctx, int enable);

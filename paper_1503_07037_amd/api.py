@@ -125,7 +125,8 @@ class Context:
         return dict(launches=d.launches, ms=d.ms, mfma_flops=d.mfma_flops,
                     useful_flops=d.useful_flops,
                     engines={names[i]: dict(launches=d.eng_launches[i], ms=d.eng_ms[i],
-                                            mfma_flops=d.eng_mfma_flops[i]) for i in range(4)})
+                                            mfma_flops=d.eng_mfma_flops[i], bytes=d.eng_bytes[i])
+                         for i in range(4)})
 
     def bench_product(self, N, prec=None, tile=0, reps=10):
         """Mean device ms and TFLOP/s of the product kernel alone at size N."""

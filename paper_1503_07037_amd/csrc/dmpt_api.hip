@@ -102,7 +102,7 @@ struct dmpt_ctx_s {
   bool prof_on = false;
   struct Timed {
     hipEvent_t a, b;
-    double mfma, useful;
+    double mfma, useful, bytes;
     int eng;
   };
   std::vector<Timed> prof_pending;
@@ -242,6 +242,7 @@ struct G {
   const void* W = nullptr; int64_t sW = 0;
   int batch = 1;
   const int* active = nullptr;
+  int counted = -1;  // members whose flops are tallied (-1: all; the host knows the others are skipped)
 };
 
 // ------------------------------------------------------------------ host-side bounds
@@ -304,6 +305,7 @@ dmpt_status prof_resolve(dmpt_ctx c) {
     c->prof.eng_launches[t.eng] += 1;
     c->prof.eng_ms[t.eng] += ms;
     c->prof.eng_mfma_flops[t.eng] += t.mfma;
+    c->prof.eng_bytes[t.eng] += t.bytes;
     c->prof_pool.push_back(t.a);
     c->prof_pool.push_back(t.b);
   }
@@ -357,9 +359,21 @@ dmpt_status run_gemm(const Call& k, const G& g) {
     if (!ok) return fail(c, DMPT_ERR_ARG, "internal: a product would leave its workspace");
   }
   const double n3 = 2.0 * (double)k.Np * k.Np * k.Np;
-  const double mf = n3 * engine_terms(k.eng) * g.batch;
-  const double uf = 2.0 * (double)k.N * k.N * k.N * g.batch;
+  const int members = g.counted >= 0 ? g.counted : g.batch;
+  const double mf = n3 * engine_terms(k.eng) * members;
+  const double uf = 2.0 * (double)k.N * k.N * k.N * members;
   dmpt_ctx c = k.c;
+  // algorithmic bytes: distinct operand members read once, C written once
+  double bytes = 0.0;
+  {
+    const double nn = (double)k.nn, es = (double)c->esize;
+    const double opb = k.np ? 2.0 * k.np : es;  // bytes per element of an operand as the kernel reads it
+    auto distinct = [&](const BOp& o) { return o.stride ? (double)((members - 1) / o.div + 1) : 1.0; };
+    bytes += (distinct(a.X) + distinct(a.Y)) * nn * opb;
+    bytes += members * nn * es * (1.0 + (a.C1 ? 1.0 : 0.0) + (a.C2 ? 1.0 : 0.0) + (a.W ? 1.0 : 0.0));
+    for (int p = 0; p < 3; ++p)
+      if (a.Cpl[p]) bytes += members * nn * 2.0;
+  }
   hipEvent_t ea = nullptr, eb = nullptr;
   if (c->prof_on) {
     if (c->prof_pending.size() >= 2048) STCHK(prof_resolve(c));
@@ -370,7 +384,7 @@ dmpt_status run_gemm(const Call& k, const G& g) {
   HIPCHK(c, gemm(a, c->stream));
   if (c->prof_on) {
     HIPCHK(c, hipEventRecord(eb, c->stream));
-    c->prof_pending.push_back({ea, eb, mf, uf, (int)k.eng});
+    c->prof_pending.push_back({ea, eb, mf, uf, bytes, (int)k.eng});
   }
   c->mfma_flops += mf;
   c->useful_flops += uf;
@@ -447,12 +461,13 @@ dmpt_status cg_solve(const Call& k, const Group& u, int batch, int ydiv, const i
   const int red_nb = reduce_blocks(n);
   const int cap = k.graph ? std::min(k.cg_iters, c->opt.max_cg) : c->opt.max_cg;
   for (int it = 0; it < cap && it + 1 < hs; ++it) {
+    int live = -1;  // members still iterating (known on the host without a graph)
     if (!k.graph) {
       HIPCHK(c, hipMemcpyAsync(c->h_int, w->active, batch * sizeof(int), hipMemcpyDeviceToHost, s));
       HIPCHK(c, hipStreamSynchronize(s));
-      bool any = false;
-      for (int z = 0; z < batch; ++z) any |= c->h_int[z] != 0;
-      if (!any) break;
+      live = 0;
+      for (int z = 0; z < batch; ++z) live += c->h_int[z] != 0;
+      if (!live) break;
     }
     // Q = P + 4 P S0  (T' applied on the right), partials of <P, Q>
     G g;
@@ -466,6 +481,7 @@ dmpt_status cg_solve(const Call& k, const Group& u, int batch, int ydiv, const i
     g.W = mptr(k, w->P, 0); g.sW = k.stride;
     g.batch = batch;
     g.active = w->active;
+    g.counted = live;
     STCHK(run_gemm(k, g));
     STCHK(sum_gemm_partials(k, batch, w->pq + it, hs, 0));
     HIPCHK(c, cg_update_xr<T>((T*)mptr(k, u, 0), (T*)mptr(k, w->R, 0), (const T*)mptr(k, w->P, 0),
@@ -617,6 +633,35 @@ dmpt_status solve_order0(const Call& k, int step) {
     planes_of(k, w->D0, 0, pd);
     HIPCHK(c, (sym_combine<T, T>((const T*)mptr(k, c->U0, 0), k.Np, 0, k.N, k.Np, 0.5, nullptr, 0,
                                  (T*)mptr(k, w->D0, 0), k.Np, 0, pd, k.np, 1, s)));
+  } else if (c->opt.guess == DMPT_GUESS_TAYLOR) {
+    // guess U = 2 D0 - 8 D0^3 (the map's Taylor expansion); with Q = D0 S0
+    // in P: U replaces D0, and R = 2 D0 - U - 4 U S0 = 8 Q - 4 U S0
+    G q;
+    q.X = op(k, w->D0, 0, true);
+    q.Y = op(k, w->S0, 0, true);
+    q.C = mptr(k, w->P, 0);
+    q.sC = k.stride;
+    q.batch = k.m;
+    q.active = w->mask0;
+    STCHK(run_gemm(k, q));
+    uint16_t* pd[3];
+    planes_of(k, w->D0, 0, pd);
+    HIPCHK(c, axpby<T>((const T*)mptr(k, w->P, 0), k.stride, (T*)mptr(k, w->D0, 0), k.stride, k.nn,
+                       k.m, -8.0, 2.0, pd, k.stride, k.np, s));
+    G g;
+    g.X = op(k, w->D0, 0, true);
+    g.Y = op(k, w->S0, 0, true);
+    g.C = mptr(k, w->R, 0);
+    g.sC = k.stride;
+    g.alpha = -4.0;
+    g.C1 = mptr(k, w->P, 0); g.sC1 = k.stride; g.beta1 = 8.0;
+    g.W = mptr(k, w->R, 0); g.sW = k.stride;
+    g.batch = k.m;
+    g.active = w->mask0;
+    STCHK(run_gemm(k, g));
+    STCHK(sum_gemm_partials(k, k.m, w->rr, hs, 0));
+    STCHK(cg_solve<T>(k, w->D0, k.m, 1, w->mask0));
+    STCHK(sym_inplace<T>(k, w->D0, 0, k.m, 0.5));
   } else {
     // R = 2 D0 - D0 - 4 D0 S0 = D0 - 4 D0 S0 (guess: the previous iterate), ||R||^2 -> rr[0]
     G g;
@@ -1422,6 +1467,8 @@ static dmpt_status normalise_options(dmpt_ctx c, const dmpt_options* in, dmpt_op
   if (o.solver != DMPT_SOLVER_CG && o.solver != DMPT_SOLVER_NS)
     return fail(c, DMPT_ERR_ARG, "unknown solver");
   if (o.solver == DMPT_SOLVER_NS) return fail(c, DMPT_ERR_UNSUPPORTED, "Newton-Schulz solver not built");
+  if (o.guess != DMPT_GUESS_PREV && o.guess != DMPT_GUESS_TAYLOR)
+    return fail(c, DMPT_ERR_ARG, "unknown initial guess");
   if (o.tol_occ <= 0) o.tol_occ = default_tol_occ(o.prec, o.refine);
   if (o.tol_cg <= 0) o.tol_cg = default_tol_cg(o.prec, o.refine);
   if (o.max_newton <= 0) o.max_newton = 50;

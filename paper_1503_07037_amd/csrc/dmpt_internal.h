@@ -6,6 +6,8 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <cmath>
+
 #include "dmpt.h"
 
 namespace dmpt {
@@ -27,9 +29,29 @@ inline int engine_terms(Engine e) {
   return e == Engine::BF16S2 ? 3 : (e == Engine::BF16S3 ? 6 : 1);
 }
 
+// BF16 plane layout of an Np x Np member (Np a multiple of 32): blocks of
+// 32 rows x 16 columns, 512 elements (1 KB) each; block (row / 32, col / 16)
+// starts at element ((row / 32) * (Np / 16) + col / 16) * 512, and inside a
+// block element (r, c) sits at ((c / 8) * 32 + r) * 8 + c % 8.  That is the
+// operand order of v_mfma_f32_32x32x16_bf16 (lane l holds row l % 32 and
+// k = 8 (l / 32) .. 8 (l / 32) + 7), so one wave moves a block between HBM,
+// LDS and registers as 64 consecutive 16-byte pieces: coalesced loads and
+// bank-conflict-free LDS reads without any swizzle.
+__host__ __device__ inline int64_t plane_off(int64_t row, int64_t col, int64_t Np) {
+  return (((row >> 5) * (Np >> 4) + (col >> 4)) << 9) + ((((col >> 3) & 1) << 5) + (row & 31)) * 8 +
+         (col & 7);
+}
+
+// Np of an n-element square member that carries planes, or 0 when n is not
+// the square of a multiple of 32 below 2^16 (plane writers need both).
+inline int64_t plane_np(int64_t n) {
+  const int64_t r = (int64_t)(std::sqrt((double)n) + 0.5);
+  return (r > 0 && r < 65536 && r % 32 == 0 && r * r == n) ? r : 0;
+}
+
 // A working matrix: master copy (float for the F32 engine, double for the
 // others) plus, for the split-BF16 engines, its BF16 slices (plane p holds
-// the p-th term of x ~ sum_p bf16_p).  ld = Np.
+// the p-th term of x ~ sum_p bf16_p) in the plane layout above.
 struct Mat {
   void* m = nullptr;                 // master (double* or float*)
   uint16_t* pl[3] = {nullptr, nullptr, nullptr};

@@ -40,14 +40,22 @@ __device__ inline uint16_t bf16_rne(float x) {
 }
 __device__ inline float bf16_to_f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
-// BF16 slices of v: slice p rounds what the earlier slices left (FP64 remainder).
-__device__ inline void split_store(double v, uint16_t* const* pl, int np, int64_t idx) {
+// BF16 slices of v: slice p rounds what the earlier slices left (FP64
+// remainder); off is the element's offset in the plane layout.
+__device__ inline void split_store(double v, uint16_t* const* pl, int np, int64_t off) {
   double r = v;
   for (int p = 0; p < np; ++p) {
     const uint16_t h = bf16_rne((float)r);
-    pl[p][idx] = h;
+    pl[p][off] = h;
     r -= (double)bf16_to_f(h);
   }
+}
+
+// Plane offset of linear element i of an Np x Np member (Np^2 < 2^32).
+__device__ inline int64_t plane_off_lin(int64_t i, int64_t Np) {
+  const uint32_t u = (uint32_t)i, n = (uint32_t)Np;
+  const uint32_t r = u / n;
+  return plane_off(r, u - r * n, Np);
 }
 
 struct Planes {
@@ -103,7 +111,7 @@ __global__ __launch_bounds__(kT) void k_sym(const Tin* in, int64_t ldi, int64_t 
       }
       const Tout o = (Tout)v;
       out[gi * ldo + gj] = o;
-      if (np) split_store((double)o, p3, np, gi * ldo + gj);
+      if (np) split_store((double)o, p3, np, plane_off(gi, gj, ldo));
     }
   }
 }
@@ -126,18 +134,18 @@ __global__ __launch_bounds__(kT) void k_transpose(const T* __restrict__ in, int6
     const int64_t idx = (bj * 32 + r) * Np + bi * 32 + tx;
     const T v = t[tx][r];
     out[idx] = v;
-    if (np) split_store((double)v, p3, np, idx);
+    if (np) split_store((double)v, p3, np, plane_off(bj * 32 + r, bi * 32 + tx, Np));
   }
 }
 
 __global__ __launch_bounds__(kT) void k_split(const double* __restrict__ x, int64_t n, int64_t sx,
-                                              Planes pl, int64_t sp, int np) {
+                                              Planes pl, int64_t sp, int np, int64_t Np) {
   const int z = blockIdx.y;
   x += z * sx;
   uint16_t* p3[3] = {pl.p[0] ? pl.p[0] + z * sp : nullptr, pl.p[1] ? pl.p[1] + z * sp : nullptr,
                      pl.p[2] ? pl.p[2] + z * sp : nullptr};
   for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
-    split_store(x[i], p3, np, i);
+    split_store(x[i], p3, np, plane_off_lin(i, Np));
 }
 
 // ------------------------------------------------------------ reductions
@@ -217,7 +225,7 @@ template <class T>
 __global__ __launch_bounds__(kT) void k_cg_p(T* __restrict__ P, const T* __restrict__ R, int64_t n,
                                              int64_t stride, const double* rr_new,
                                              const double* rr_old, int hstride, const int* active,
-                                             Planes pl, int np) {
+                                             Planes pl, int np, int64_t Np) {
   const int z = blockIdx.y;
   if (active && !active[z]) return;
   const double ro = rr_old[z * hstride];
@@ -231,7 +239,7 @@ __global__ __launch_bounds__(kT) void k_cg_p(T* __restrict__ P, const T* __restr
   for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
     const T p = R[i] + be * P[i];
     P[i] = p;
-    if (np) split_store((double)p, p3, np, i);
+    if (np) split_store((double)p, p3, np, plane_off_lin(i, Np));
   }
 }
 
@@ -251,7 +259,7 @@ __global__ void k_cg_check(const double* rr, const double* rr0, const double* re
 template <class T>
 __global__ __launch_bounds__(kT) void k_axpby(const T* __restrict__ x, int64_t sx, T* __restrict__ y,
                                               int64_t sy, int64_t n, double a, double b, Planes pl,
-                                              int64_t sp, int np) {
+                                              int64_t sp, int np, int64_t Np) {
   const int z = blockIdx.y;
   x += z * sx;
   y += z * sy;
@@ -261,7 +269,7 @@ __global__ __launch_bounds__(kT) void k_axpby(const T* __restrict__ x, int64_t s
   for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
     const T v = (b != 0.0) ? ta * x[i] + tb * y[i] : ta * x[i];  // b = 0: y is not read
     y[i] = v;
-    if (np) split_store((double)v, p3, np, i);
+    if (np) split_store((double)v, p3, np, plane_off_lin(i, Np));
   }
 }
 
@@ -269,7 +277,7 @@ __global__ __launch_bounds__(kT) void k_axpby(const T* __restrict__ x, int64_t s
 template <class Tin, class Tout>
 __global__ __launch_bounds__(kT) void k_convert(const Tin* __restrict__ in, int64_t si,
                                                 Tout* __restrict__ out, int64_t so, int64_t n,
-                                                Planes pl, int64_t sp, int np) {
+                                                Planes pl, int64_t sp, int np, int64_t Np) {
   const int z = blockIdx.y;
   in += z * si;
   out += z * so;
@@ -278,7 +286,7 @@ __global__ __launch_bounds__(kT) void k_convert(const Tin* __restrict__ in, int6
   for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
     const Tout v = (Tout)in[i];
     out[i] = v;
-    if (np) split_store((double)v, p3, np, i);
+    if (np) split_store((double)v, p3, np, plane_off_lin(i, Np));
   }
 }
 
@@ -292,7 +300,7 @@ __global__ __launch_bounds__(kT) void k_spi(const T* __restrict__ x, T* __restri
     if (r == c && r < N) v += a;
     const T o = (T)v;
     out[i] = o;
-    if (np) split_store((double)o, pl.p, np, i);
+    if (np) split_store((double)o, pl.p, np, plane_off(r, c, Np));
   }
 }
 
@@ -390,7 +398,8 @@ __global__ void k_expand(const int* src, int div, int* dst, int n) {
 
 // Deterministic non-trivial fill (a hashed pattern in [-1, 1)) with planes.
 template <class T>
-__global__ __launch_bounds__(kT) void k_fill(T* x, int64_t n, uint32_t seed, Planes pl, int np) {
+__global__ __launch_bounds__(kT) void k_fill(T* x, int64_t n, uint32_t seed, Planes pl, int np,
+                                             int64_t Np) {
   for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
     uint32_t h = (uint32_t)i * 2654435761u ^ seed;
     h ^= h >> 15;
@@ -398,7 +407,7 @@ __global__ __launch_bounds__(kT) void k_fill(T* x, int64_t n, uint32_t seed, Pla
     h ^= h >> 13;
     const T v = (T)((double)(h & 0xffffff) / 8388608.0 - 1.0);
     x[i] = v;
-    if (np) split_store((double)v, pl.p, np, i);
+    if (np) split_store((double)v, pl.p, np, plane_off_lin(i, Np));
   }
 }
 
@@ -486,6 +495,7 @@ hipError_t transpose(const T* in, int64_t Np, int64_t stride, T* out, uint16_t* 
                      int nplanes, int batch, hipStream_t s) {
   Planes pl{{nullptr, nullptr, nullptr}};
   for (int p = 0; p < nplanes; ++p) pl.p[p] = planes[p];
+  if (Np % 32 != 0) return hipErrorInvalidValue;
   const unsigned nb = (unsigned)(Np / 32);
   hipLaunchKernelGGL(k_transpose<T>, dim3(nb, nb, batch), dim3(kT), 0, s, in, Np, stride, out, pl,
                      nplanes);
@@ -503,6 +513,8 @@ hipError_t sym_combine(const Tin* in, int64_t ldi, int64_t si, int64_t N, int64_
                        const Tin* in2, double a2, const int* gate) {
   Planes pl{{nullptr, nullptr, nullptr}};
   for (int p = 0; p < nplanes; ++p) pl.p[p] = planes[p];
+  // planes exist only for workspace members: Np x Np with ld = Np
+  if (nplanes && (ldo != Np || Np % 32 != 0)) return hipErrorInvalidValue;
   const int64_t rows = (ldo == N && ldo != Np) ? N : ldo;  // caller buffer: only N x N
   const int64_t span = rows > N ? rows : N;
   const unsigned nb = (unsigned)((span + 31) / 32);
@@ -526,7 +538,9 @@ hipError_t split_planes(const double* x, int64_t n, int64_t sx, uint16_t* const*
                         int nplanes, int batch, hipStream_t s) {
   Planes pl{{nullptr, nullptr, nullptr}};
   for (int p = 0; p < nplanes; ++p) pl.p[p] = planes[p];
-  hipLaunchKernelGGL(k_split, dim3(ew_grid(n), batch), dim3(kT), 0, s, x, n, sx, pl, sp, nplanes);
+  const int64_t Np = plane_np(n);
+  if (!Np) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_split, dim3(ew_grid(n), batch), dim3(kT), 0, s, x, n, sx, pl, sp, nplanes, Np);
   return hipGetLastError();
 }
 
@@ -580,8 +594,10 @@ hipError_t cg_update_p(T* P, const T* R, int64_t n, int64_t stride, int batch, c
                        uint16_t* const* planes, int nplanes, hipStream_t s) {
   Planes pl{{nullptr, nullptr, nullptr}};
   for (int p = 0; p < nplanes; ++p) pl.p[p] = planes[p];
+  const int64_t Np = nplanes ? plane_np(n) : 0;
+  if (nplanes && !Np) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_cg_p<T>, dim3(ew_grid(n), batch), dim3(kT), 0, s, P, R, n, stride, rr_new,
-                     rr_old, hstride, active, pl, nplanes);
+                     rr_old, hstride, active, pl, nplanes, Np);
   return hipGetLastError();
 }
 template hipError_t cg_update_p<double>(double*, const double*, int64_t, int64_t, int,
@@ -603,8 +619,10 @@ hipError_t axpby(const T* x, int64_t sx, T* y, int64_t sy, int64_t n, int batch,
                  uint16_t* const* planes, int64_t sp, int nplanes, hipStream_t s) {
   Planes pl{{nullptr, nullptr, nullptr}};
   for (int p = 0; p < nplanes; ++p) pl.p[p] = planes[p];
+  const int64_t Np = nplanes ? plane_np(n) : 0;
+  if (nplanes && !Np) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_axpby<T>, dim3(ew_grid(n), batch), dim3(kT), 0, s, x, sx, y, sy, n, a, b, pl,
-                     sp, nplanes);
+                     sp, nplanes, Np);
   return hipGetLastError();
 }
 template hipError_t axpby<double>(const double*, int64_t, double*, int64_t, int64_t, int, double,
@@ -617,8 +635,10 @@ hipError_t convert(const Tin* in, int64_t si, Tout* out, int64_t so, int64_t n, 
                    uint16_t* const* planes, int64_t sp, int nplanes, hipStream_t s) {
   Planes pl{{nullptr, nullptr, nullptr}};
   for (int p = 0; p < nplanes; ++p) pl.p[p] = planes[p];
+  const int64_t Np = nplanes ? plane_np(n) : 0;
+  if (nplanes && !Np) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_convert<Tin, Tout>), dim3(ew_grid(n), batch), dim3(kT), 0, s, in, si, out, so,
-                     n, pl, sp, nplanes);
+                     n, pl, sp, nplanes, Np);
   return hipGetLastError();
 }
 #define DMPT_CONV_INST(TI, TO)                                                                \
@@ -661,7 +681,9 @@ hipError_t fill_pattern(T* x, int64_t n, uint32_t seed, uint16_t* const* planes,
                         hipStream_t s) {
   Planes pl{{nullptr, nullptr, nullptr}};
   for (int p = 0; p < nplanes; ++p) pl.p[p] = planes[p];
-  hipLaunchKernelGGL(k_fill<T>, dim3(ew_grid(n)), dim3(kT), 0, s, x, n, seed, pl, nplanes);
+  const int64_t Np = nplanes ? plane_np(n) : 0;
+  if (nplanes && !Np) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_fill<T>, dim3(ew_grid(n)), dim3(kT), 0, s, x, n, seed, pl, nplanes, Np);
   return hipGetLastError();
 }
 template hipError_t fill_pattern<double>(double*, int64_t, uint32_t, uint16_t* const*, int, hipStream_t);

@@ -20,8 +20,11 @@
 //           (both BF16 engines use v_mfma_f32_32x32x16_bf16, FP32 accumulation;
 //           their master copies, C1, C2, W and C are FP64)
 //
-// All engines: 128 x 128 output tile per 256-thread workgroup (four waves,
-// 64 x 64 each), K staged through LDS in a two-stage ring, operands
+// FP64 and FP32: 128 x 128 output tile per 256-thread workgroup (four waves,
+// 64 x 64 each), K staged through LDS in a two-stage ring.  Split BF16: 256 x
+// 256 tiles (128 x 128 per wave) when Np allows, else 128 x 128; the BF16
+// planes are stored in a blocked layout in the MFMA operand order (see
+// plane_off), so operand tiles move as contiguous 1 KB blocks.  Operands are
 // zero-padded to a multiple of 128 so no edge handling is needed.  The block
 // index is remapped so that the tiles of one XCD form a contiguous,
 // row-grouped range (better reuse of that XCD's L2).
@@ -90,9 +93,12 @@ __device__ inline void write_split(double v, uint16_t* const* pl, int np, int64_
   }
 }
 
-// Epilogue for one output element.
+// Epilogue for output element (row, col): master at row * Np + col, BF16
+// planes (when requested) in the plane layout.
 template <class T>
-__device__ inline void epi(const GemmArgs& a, int z, int64_t off, double acc, double& dsum) {
+__device__ inline void epi(const GemmArgs& a, int z, int64_t row, int64_t col, double acc,
+                           double& dsum) {
+  const int64_t off = row * a.Np + col;
   double v = a.alpha * acc;
   if (a.C1) v += a.beta1 * (double)((const T*)a.C1)[z * a.sC1 + off];
   if (a.C2) v += a.beta2 * (double)((const T*)a.C2)[z * a.sC2 + off];
@@ -102,7 +108,7 @@ __device__ inline void epi(const GemmArgs& a, int z, int64_t off, double acc, do
     uint16_t* pl[3] = {a.Cpl[0] ? a.Cpl[0] + z * a.sC : nullptr,
                        a.Cpl[1] ? a.Cpl[1] + z * a.sC : nullptr,
                        a.Cpl[2] ? a.Cpl[2] + z * a.sC : nullptr};
-    write_split((double)out, pl, a.Cpl[2] ? 3 : (a.Cpl[1] ? 2 : 1), off);
+    write_split((double)out, pl, a.Cpl[2] ? 3 : (a.Cpl[1] ? 2 : 1), plane_off(row, col, a.Np));
   }
   if (a.W) dsum += (double)((const T*)a.W)[z * a.sW + off] * (double)out;
 }
@@ -181,7 +187,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_f64(GemmArgs a) {
         // v_mfma_f64_16x16x4f64 result: register r of lane l holds row 4r + l/16, column l%16
         const int64_t row = (int64_t)tm * BM + wm * 64 + i * 16 + 4 * r + (lane >> 4);
         const int64_t col = (int64_t)tn * BN + wn * 64 + j * 16 + (lane & 15);
-        epi<double>(a, z, row * Np + col, acc[i][j][r], dsum);
+        epi<double>(a, z, row, col, acc[i][j][r], dsum);
       }
   if (a.W) {
     const double s = block_sum(dsum, red);
@@ -268,7 +274,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_f32(GemmArgs a) {
       for (int r = 0; r < 16; ++r) {
         const int64_t row = (int64_t)tm * BM + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         const int64_t col = (int64_t)tn * BN + wn * 64 + j * 32 + (lane & 31);
-        epi<float>(a, z, row * Np + col, (double)acc[i][j][r], dsum);
+        epi<float>(a, z, row, col, (double)acc[i][j][r], dsum);
       }
   if (a.W) {
     const double s = block_sum(dsum, red);
@@ -277,88 +283,92 @@ __global__ __launch_bounds__(kThreads) void k_gemm_f32(GemmArgs a) {
 }
 
 // ------------------------------------------------------------------ split BF16
-// LDS tile of one plane: 128 rows x 32 BF16 (64 B = four 16-byte chunks per
-// row).  Chunk c of row r is stored at chunk position c ^ ((r >> 1) & 3), so
-// the eight rows read by one group of eight lanes hit eight different
-// 16-byte bank groups.
-constexpr int B16_BK = 32;
-constexpr int kTileBytes = BM * B16_BK * 2;  // 8 KB per plane and operand
-
-__device__ inline int swz(int row, int c) { return row * 64 + ((c ^ ((row >> 1) & 3)) << 4); }
-
-template <int S>
+// One kernel for both split engines and both tile sizes:
+//   S   planes per operand (2: three products, 3: six products)
+//   TM  output tile edge of the workgroup (128 or 256); each of the four
+//       waves owns a TM/2 x TM/2 quadrant as (TM/64)^2 MFMA tiles of 32 x 32
+//   BK  k extent of one pipeline stage (16 or 32)
+// Operands are read in the plane layout (1 KB blocks of 32 rows x 16 k, in
+// the MFMA operand order): a stage of one operand plane is TM/32 x BK/16
+// blocks, and lane l of a wave copies bytes 16 l .. 16 l + 15 of a block, so
+// every global load instruction reads 1 KB contiguous and every LDS access
+// of a wave is 1 KB contiguous (no bank conflicts, no swizzle).
+// Pipeline over k: two LDS stages and one register stage.  While the MFMAs
+// of stage k run, stage k + 1 (already in registers) is written to the other
+// LDS buffer and the global loads of stage k + 2 are in flight.
+template <int S, int TM, int BK>
 __global__ __launch_bounds__(kThreads) void k_gemm_bf16(GemmArgs a) {
+  constexpr int FI = TM / 64;          // MFMA tiles per wave and dimension
+  constexpr int RB = TM / 32;          // 32-row blocks of an operand tile
+  constexpr int KB = BK / 16;          // 16-wide k blocks of a stage
+  constexpr int NBLK = RB * KB;        // blocks per operand plane and stage
+  constexpr int SBLK = 2 * S * NBLK;   // blocks per stage: [operand][plane][row block][k block]
+  constexpr int LOADS = SBLK / 4;      // blocks each wave copies per stage
+  constexpr int SBYTES = SBLK * 1024;
+  static_assert(SBLK % 4 == 0, "a stage must split evenly over the four waves");
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   __shared__ double red[4];
   const int z = blockIdx.z;
   if (a.active && !a.active[z]) return;
   const int64_t Np = a.Np;
+  const int64_t kbr = Np >> 4;         // blocks per 32-row block row of a plane
   int tm, tn;
-  tile_coords(blockIdx.x, (int)(Np / BM), (int)(Np / BN), tm, tn);
-  const uint16_t* Xp[S];
-  const uint16_t* Yp[S];
-#pragma unroll
-  for (int p = 0; p < S; ++p) {
-    Xp[p] = a.X.pl[p] + (z / a.X.div) * a.X.stride + (int64_t)tm * BM * Np;
-    Yp[p] = a.Y.pl[p] + (z / a.Y.div) * a.Y.stride + (int64_t)tn * BN * Np;
-  }
-  // stage layout: [stage][operand X/Y][plane] tiles of kTileBytes
-  auto tile = [&](int stage, int op, int p) -> unsigned char* {
-    return smem + ((stage * 2 + op) * S + p) * kTileBytes;
-  };
+  tile_coords(blockIdx.x, (int)(Np / TM), (int)(Np / TM), tm, tn);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  u4v rx[S][2], ry[S][2];
-  auto gload = [&](int k0) {
+  // the blocks this wave copies: stage block q = wave + 4 j
+  const uint16_t* src[LOADS];
+  int dst[LOADS];
 #pragma unroll
-    for (int p = 0; p < S; ++p)
+  for (int j = 0; j < LOADS; ++j) {
+    const int q = wave + 4 * j;
+    const int op = q / (S * NBLK), p = (q / NBLK) % S, b = q % NBLK;
+    const int rb = b / KB, kb = b % KB;
+    const uint16_t* base = op ? a.Y.pl[p] + (int64_t)(z / a.Y.div) * a.Y.stride
+                              : a.X.pl[p] + (int64_t)(z / a.X.div) * a.X.stride;
+    const int64_t brow = (int64_t)(op ? tn : tm) * RB + rb;
+    src[j] = base + ((brow * kbr + kb) << 9) + lane * 8;
+    dst[j] = q * 1024 + lane * 16;
+  }
+  u4v stg[LOADS];
+  auto gload = [&](int kt) {
+    const int64_t koff = (int64_t)kt * (KB << 9);
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int idx = tid + i * kThreads, row = idx >> 2, c = idx & 3;
-        rx[p][i] = *(const u4v*)(Xp[p] + (int64_t)row * Np + k0 + 8 * c);
-        ry[p][i] = *(const u4v*)(Yp[p] + (int64_t)row * Np + k0 + 8 * c);
-      }
+    for (int j = 0; j < LOADS; ++j) stg[j] = *(const u4v*)(src[j] + koff);
   };
-  auto swrite = [&](int stage) {
+  auto swrite = [&](int st) {
 #pragma unroll
-    for (int p = 0; p < S; ++p)
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int idx = tid + i * kThreads, row = idx >> 2, c = idx & 3;
-        *(u4v*)(tile(stage, 0, p) + swz(row, c)) = rx[p][i];
-        *(u4v*)(tile(stage, 1, p) + swz(row, c)) = ry[p][i];
-      }
+    for (int j = 0; j < LOADS; ++j) *(u4v*)(smem + st * SBYTES + dst[j]) = stg[j];
   };
-  f16v acc[2][2];
+  f16v acc[FI][FI];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < FI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < FI; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+  const int nk = (int)(Np / BK);
   gload(0);
   swrite(0);
+  if (nk > 1) gload(1);
   __syncthreads();
-  const int nk = (int)(Np / B16_BK);
   for (int kt = 0; kt < nk; ++kt) {
-    const int st = kt & 1;
-    if (kt + 1 < nk) gload((kt + 1) * B16_BK);
+    const unsigned char* sb = smem + (kt & 1) * SBYTES + lane * 16;
 #pragma unroll
-    for (int kk = 0; kk < 2; ++kk) {
-      bf8v xa[S][2], yb[S][2];
-      const int c = kk * 2 + (lane >> 5);
+    for (int kk = 0; kk < KB; ++kk) {
+      bf8v xa[S][FI], yb[S][FI];
 #pragma unroll
-      for (int p = 0; p < S; ++p) {
+      for (int p = 0; p < S; ++p)
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          const int row = wm * 64 + i * 32 + (lane & 31);
-          xa[p][i] = __builtin_bit_cast(bf8v, *(const u4v*)(tile(st, 0, p) + swz(row, c)));
+        for (int i = 0; i < FI; ++i) {
+          xa[p][i] = __builtin_bit_cast(
+              bf8v, *(const u4v*)(sb + ((p * NBLK + (wm * FI + i) * KB + kk) << 10)));
+          yb[p][i] = __builtin_bit_cast(
+              bf8v, *(const u4v*)(sb + (((S + p) * NBLK + (wn * FI + i) * KB + kk) << 10)));
         }
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const int row = wn * 64 + j * 32 + (lane & 31);
-          yb[p][j] = __builtin_bit_cast(bf8v, *(const u4v*)(tile(st, 1, p) + swz(row, c)));
-        }
+      if (kk == 0 && kt + 1 < nk) {
+        swrite((kt + 1) & 1);
+        if (kt + 2 < nk) gload(kt + 2);
       }
       // smallest terms first
 #pragma unroll
@@ -366,24 +376,23 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(GemmArgs a) {
 #pragma unroll
         for (int p = 0; p <= t; ++p)
 #pragma unroll
-          for (int i = 0; i < 2; ++i)
+          for (int i = 0; i < FI; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < FI; ++j)
               acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa[p][i], yb[t - p][j], acc[i][j], 0, 0, 0);
     }
-    if (kt + 1 < nk) swrite(st ^ 1);
     __syncthreads();
   }
   double dsum = 0.0;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < FI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < FI; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int64_t row = (int64_t)tm * BM + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int64_t col = (int64_t)tn * BN + wn * 64 + j * 32 + (lane & 31);
-        epi<double>(a, z, row * Np + col, (double)acc[i][j][r], dsum);
+        const int64_t row = (int64_t)tm * TM + wm * (TM / 2) + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int64_t col = (int64_t)tn * TM + wn * (TM / 2) + j * 32 + (lane & 31);
+        epi<double>(a, z, row, col, (double)acc[i][j][r], dsum);
       }
   if (a.W) {
     const double s = block_sum(dsum, red);
@@ -391,138 +400,20 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(GemmArgs a) {
   }
 }
 
-// ------------------------------------------------------------------ split BF16, 256 x 256
-// Large-tile variant for Np a multiple of 256: each of the four waves owns a
-// 128 x 128 block (4 x 4 MFMA tiles of 32 x 32), which halves the L2 and LDS
-// traffic per MFMA of the 128 x 128 kernel.  K is staged BK at a time
-// through a two-stage LDS ring (BK = 32 for two planes, 16 for three, so the
-// ring fits in the 160 KB of LDS).  Row r of a plane tile holds BK/8 chunks
-// of 16 B; chunk c sits at c ^ swizzle(r) so a group of eight lanes reading
-// eight consecutive rows hits eight different 16-byte bank groups.
-constexpr int BM2 = 256;
+template <int S, int TM, int BK>
+constexpr size_t bf16_lds() { return (size_t)2 * 2 * S * (TM / 32) * (BK / 16) * 1024; }
 
-template <int BK>
-__device__ inline int swz2(int row, int c) {
-  if constexpr (BK == 32) return row * 64 + ((c ^ ((row >> 1) & 3)) << 4);
-  else return row * 32 + ((c ^ ((row >> 2) & 1)) << 4);
-}
-
-template <int S, int BK>
-__global__ __launch_bounds__(kThreads) void k_gemm_bf16_256(GemmArgs a) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  __shared__ double red[4];
-  constexpr int kTile = BM2 * BK * 2;              // bytes of one plane tile
-  constexpr int kChunks = BK / 8;                  // 16-byte chunks per row
-  constexpr int kLoads = BM2 * kChunks / kThreads; // 16-byte loads per thread, plane and operand
-  const int z = blockIdx.z;
-  if (a.active && !a.active[z]) return;
-  const int64_t Np = a.Np;
-  int tm, tn;
-  tile_coords(blockIdx.x, (int)(Np / BM2), (int)(Np / BM2), tm, tn);
-  const uint16_t* Xp[S];
-  const uint16_t* Yp[S];
-#pragma unroll
-  for (int p = 0; p < S; ++p) {
-    Xp[p] = a.X.pl[p] + (z / a.X.div) * a.X.stride + (int64_t)tm * BM2 * Np;
-    Yp[p] = a.Y.pl[p] + (z / a.Y.div) * a.Y.stride + (int64_t)tn * BM2 * Np;
-  }
-  auto tile = [&](int stage, int op, int p) -> unsigned char* {
-    return smem + ((stage * 2 + op) * S + p) * kTile;
-  };
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  u4v rx[S][kLoads], ry[S][kLoads];
-  auto gload = [&](int k0) {
-#pragma unroll
-    for (int p = 0; p < S; ++p)
-#pragma unroll
-      for (int i = 0; i < kLoads; ++i) {
-        const int idx = tid + i * kThreads, row = idx / kChunks, c = idx % kChunks;
-        rx[p][i] = *(const u4v*)(Xp[p] + (int64_t)row * Np + k0 + 8 * c);
-        ry[p][i] = *(const u4v*)(Yp[p] + (int64_t)row * Np + k0 + 8 * c);
-      }
-  };
-  auto swrite = [&](int stage) {
-#pragma unroll
-    for (int p = 0; p < S; ++p)
-#pragma unroll
-      for (int i = 0; i < kLoads; ++i) {
-        const int idx = tid + i * kThreads, row = idx / kChunks, c = idx % kChunks;
-        *(u4v*)(tile(stage, 0, p) + swz2<BK>(row, c)) = rx[p][i];
-        *(u4v*)(tile(stage, 1, p) + swz2<BK>(row, c)) = ry[p][i];
-      }
-  };
-  f16v acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
-  gload(0);
-  swrite(0);
-  __syncthreads();
-  const int nk = (int)(Np / BK);
-  for (int kt = 0; kt < nk; ++kt) {
-    const int st = kt & 1;
-    if (kt + 1 < nk) gload((kt + 1) * BK);
-#pragma unroll
-    for (int kk = 0; kk < BK / 16; ++kk) {
-      const int c = kk * 2 + (lane >> 5);
-      bf8v xa[S][4], yb[S][4];
-#pragma unroll
-      for (int p = 0; p < S; ++p) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          xa[p][i] = __builtin_bit_cast(
-              bf8v, *(const u4v*)(tile(st, 0, p) + swz2<BK>(wm * 128 + i * 32 + (lane & 31), c)));
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          yb[p][j] = __builtin_bit_cast(
-              bf8v, *(const u4v*)(tile(st, 1, p) + swz2<BK>(wn * 128 + j * 32 + (lane & 31), c)));
-      }
-#pragma unroll
-      for (int t = S - 1; t >= 0; --t)
-#pragma unroll
-        for (int p = 0; p <= t; ++p)
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa[p][i], yb[t - p][j], acc[i][j], 0, 0, 0);
-    }
-    if (kt + 1 < nk) swrite(st ^ 1);
-    __syncthreads();
-  }
-  double dsum = 0.0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int64_t row = (int64_t)tm * BM2 + wm * 128 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int64_t col = (int64_t)tn * BM2 + wn * 128 + j * 32 + (lane & 31);
-        epi<double>(a, z, row * Np + col, (double)acc[i][j][r], dsum);
-      }
-  if (a.W) {
-    const double s = block_sum(dsum, red);
-    if (tid == 0) a.partials[(int64_t)z * gridDim.x + blockIdx.x] = s;
-  }
-}
-
-template <int S, int BK>
-hipError_t launch_bf16_256(const GemmArgs& a, dim3 grid, hipStream_t s) {
-  const size_t lds = (size_t)2 * 2 * S * BM2 * BK * 2;
-  hipLaunchKernelGGL((k_gemm_bf16_256<S, BK>), grid, dim3(kThreads), lds, s, a);
-  return hipGetLastError();
-}
-
-template <int S>
+template <int S, int TM, int BK>
 hipError_t launch_bf16(const GemmArgs& a, dim3 grid, hipStream_t s) {
-  const size_t lds = (size_t)2 * 2 * S * kTileBytes;
-  hipLaunchKernelGGL(k_gemm_bf16<S>, grid, dim3(kThreads), lds, s, a);
+  const size_t lds = bf16_lds<S, TM, BK>();
+  hipLaunchKernelGGL((k_gemm_bf16<S, TM, BK>), grid, dim3(kThreads), lds, s, a);
   return hipGetLastError();
+}
+
+template <int S, int TM, int BK>
+hipError_t prepare_bf16() {
+  return hipFuncSetAttribute((const void*)k_gemm_bf16<S, TM, BK>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bf16_lds<S, TM, BK>());
 }
 
 }  // namespace
@@ -531,25 +422,18 @@ hipError_t launch_bf16(const GemmArgs& a, dim3 grid, hipStream_t s) {
 // 256-wide split-BF16 kernel when Np allows it and the tile choice allows it.
 int gemm_tile_edge(Engine eng, int64_t Np, int tile_pref) {
   const bool bf = eng == Engine::BF16S2 || eng == Engine::BF16S3;
-  if (bf && tile_pref != 128 && Np % BM2 == 0) return BM2;
+  if (bf && tile_pref != 128 && Np % 256 == 0) return 256;
   return BM;
 }
 
 // Raise the dynamic-LDS limit of every kernel that needs more than the
 // default, once, before any launch (and so never inside a graph capture).
 hipError_t gemm_prepare() {
-  const void* k2 = (const void*)k_gemm_bf16<2>;
-  const void* k3 = (const void*)k_gemm_bf16<3>;
-  const void* l2 = (const void*)k_gemm_bf16_256<2, 16>;
-  const void* l3 = (const void*)k_gemm_bf16_256<3, 16>;
   hipError_t e;
-  if ((e = hipFuncSetAttribute(k2, hipFuncAttributeMaxDynamicSharedMemorySize, 2 * 2 * 2 * kTileBytes)))
-    return e;
-  if ((e = hipFuncSetAttribute(k3, hipFuncAttributeMaxDynamicSharedMemorySize, 2 * 2 * 3 * kTileBytes)))
-    return e;
-  if ((e = hipFuncSetAttribute(l2, hipFuncAttributeMaxDynamicSharedMemorySize, 2 * 2 * 2 * BM2 * 16 * 2)))
-    return e;
-  return hipFuncSetAttribute(l3, hipFuncAttributeMaxDynamicSharedMemorySize, 2 * 2 * 3 * BM2 * 16 * 2);
+  if ((e = prepare_bf16<2, 128, 32>())) return e;
+  if ((e = prepare_bf16<3, 128, 32>())) return e;
+  if ((e = prepare_bf16<2, 256, 16>())) return e;
+  return prepare_bf16<3, 256, 16>();
 }
 
 int gemm_tiles(Engine eng, int64_t Np, int tile_pref) {
@@ -570,9 +454,9 @@ hipError_t gemm(const GemmArgs& a, hipStream_t s) {
       hipLaunchKernelGGL(k_gemm_f32, grid, dim3(kThreads), 0, s, a);
       return hipGetLastError();
     case Engine::BF16S2:
-      return edge == BM2 ? launch_bf16_256<2, 16>(a, grid, s) : launch_bf16<2>(a, grid, s);
+      return edge == 256 ? launch_bf16<2, 256, 16>(a, grid, s) : launch_bf16<2, 128, 32>(a, grid, s);
     case Engine::BF16S3:
-      return edge == BM2 ? launch_bf16_256<3, 16>(a, grid, s) : launch_bf16<3>(a, grid, s);
+      return edge == 256 ? launch_bf16<3, 256, 16>(a, grid, s) : launch_bf16<3, 128, 32>(a, grid, s);
   }
   return hipErrorInvalidValue;
 }

@@ -109,6 +109,21 @@ def test_chain128_canonical_fp64(dm, chain128_ref, schedule, warm_traj):
     assert abs(st["trP"][0] - c["Ne"]) < 1e-9
 
 
+def test_chain128_taylor_guess_fp64(dm, chain128_ref):
+    """The Taylor initial guess 2D - 8D^3 for the order-0 solves (no trajectory) reaches the same result."""
+    print("case chain128 taylor guess", flush=True)
+    c, ref = chain128_ref
+    cg = {}
+    for guess in ("prev", "taylor"):
+        with dm.Context(c["N"], dirs_max=1, prec="fp64", warm_traj=0, guess=guess) as ctx:
+            P0, P1, P2, mu, st = ctx.mu_newton(T(c["H0"]), [T(h) for h in c["H1"]], None,
+                                               beta=c["beta"], Ne=c["Ne"], n=c["n"], order=2)
+        e0, e1, e2 = errs(P0, P1, P2, ref)
+        cg[guess] = st["cg_iters_total"]
+        print(f"  {guess}: errs {e0:.2e} {e1:.2e} {e2:.2e} cg={st['cg_iters_total']}")
+        assert e0 < 1e-10 and e1 < 1e-10 and e2 < 1e-10
+
+
 @pytest.mark.parametrize("prec,extra,tol", [
     ("fp32", {}, 3e-6),                # FP32 iterates: rounding floor of the 20-step chain
     ("bf16x6", {}, 1e-6),              # 6-product split, FP64 iterates
