@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--tol-occ", type=float, default=0.0)
     ap.add_argument("--refine", type=int, default=-1,
                     help="bf16x3: finish with the 6-product refinement passes (default on)")
+    ap.add_argument("--acc64", type=int, default=1,
+                    help="6-product products: FP32 per 32-wide k slice, FP64 across slices (default 1)")
     ap.add_argument("--fp64-compare", action="store_true",
                     help="also time one FP64 solve of the same workload on the GPU")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -178,7 +180,7 @@ def main():
     torch.cuda.synchronize()
     refine = (1 if args.prec == "bf16x3" else 0) if args.refine < 0 else args.refine
     ctx = dm.Context(N, dirs_max=d, prec=args.prec, tol_cg=args.tol_cg, tol_occ=args.tol_occ,
-                     refine=refine)
+                     refine=refine, acc64=args.acc64)
 
     def step():
         return ctx.mu_newton(H0, H1, None, beta=c["beta"], Ne=c["Ne"], n=c["n"], order=order)
@@ -220,7 +222,9 @@ def main():
                                f"beta={c['beta']}, n={c['n']}, Ne={c['Ne']}" if args.workload == "banded8192"
                    else args.workload,
                    "N": N, "dirs": d, "order": order, "beta": c["beta"], "n": c["n"],
-                   "precision": args.prec + ("+refine(bf16x6)" if refine else ""),
+                   "precision": args.prec + ("+refine(bf16x6)" if refine else "")
+                   + (", 6-product sums FP64 across 32-wide k slices" if args.acc64 and
+                      (refine or args.prec == "bf16x6") else ""),
                    "parallelism": "single GPU"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,

@@ -99,6 +99,9 @@ typedef struct {
                            mu^(k) with Tr P_mu; 1 = after mu0 has converged, one pass per order with
                            the extra response J to H1 = I: P^(k) is affine in mu^(k) with slope -J,
                            so mu^(k) = Tr P^(k)(0) / Tr J and P^(k) = P^(k)(0) - mu^(k) J exactly */
+  int acc64;            /* 6-product split-BF16 products: 1 = each 32-wide slice of k is summed in FP32
+                           and the slices in FP64 (128 x 128 tiles; the FP32 rounding then no longer
+                           grows with N), 0 = one FP32 accumulator over all of k (256 x 256 tiles) */
 } dmpt_options;
 
 #define DMPT_MAX_DIRS 8
@@ -220,7 +223,8 @@ dmpt_status dmpt_profile_get(dmpt_ctx ctx, dmpt_profile_data* out);
 /* Time the matrix-product kernel alone: `reps` products C = X Y^T of size N
  * (N <= n_max; X, Y, C are workspace matrices filled with a fixed pattern)
  * in precision `prec` with output tile edge `tile` (0: the library's
- * choice, else 128 or 256).  *ms: mean device time per product (HIP events
+ * choice, else 128 or 256; the 6-product engine with options.acc64 always
+ * uses 128).  *ms: mean device time per product (HIP events
  * on the context stream); *tflops: matrix-core TFLOP/s (every split product
  * counted).  prec must not need more workspace than the context holds. */
 dmpt_status dmpt_bench_product(dmpt_ctx ctx, int64_t N, dmpt_prec prec, int tile, int reps,

@@ -26,7 +26,8 @@ def _torch():
 
 
 def options(prec="fp64", solver="cg", guess="prev", tol_occ=0.0, tol_cg=0.0, max_newton=50,
-            max_cg=60, refine=0, ckpt_every=5, check=0, staged=1, warm_traj=1, schedule=1):
+            max_cg=60, refine=0, ckpt_every=5, check=0, staged=1, warm_traj=1, schedule=1,
+            acc64=1):
     """Build an options struct; 0 tolerances select the precision's defaults."""
     lib = L.load()
     o = L.Options()
@@ -39,6 +40,7 @@ def options(prec="fp64", solver="cg", guess="prev", tol_occ=0.0, tol_cg=0.0, max
     o.ckpt_every, o.check, o.staged = int(ckpt_every), int(check), int(staged)
     o.warm_traj = int(warm_traj)
     o.schedule = int(schedule)
+    o.acc64 = int(acc64)
     return o
 
 

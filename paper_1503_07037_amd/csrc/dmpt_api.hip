@@ -313,7 +313,11 @@ dmpt_status prof_resolve(dmpt_ctx c) {
   return DMPT_OK;
 }
 
-int tile_for(dmpt_ctx c, int64_t Np) {
+// Output tile edge of the product kernel for an engine and size: the FP64
+// slice-accumulating 6-product kernel has 128-wide tiles only; otherwise the
+// autotuned choice for Np, else the context's preference.
+int tile_for(dmpt_ctx c, Engine eng, int64_t Np) {
+  if (eng == Engine::BF16S3 && c->opt.acc64) return 128;
   for (auto& t : c->tuned)
     if (t.first == Np) return t.second;
   return c->tile_pref;
@@ -335,7 +339,8 @@ dmpt_status run_gemm(const Call& k, const G& g) {
   a.W = g.W; a.sW = g.sW;
   a.partials = k.c->d_part;
   a.active = g.active;
-  a.tile = tile_for(k.c, k.Np);
+  a.tile = tile_for(k.c, k.eng, k.Np);
+  a.acc64 = k.eng == Engine::BF16S3 && k.c->opt.acc64;
   // every member the launch touches must lie inside a workspace allocation
   {
     dmpt_ctx c = k.c;
@@ -393,7 +398,7 @@ dmpt_status run_gemm(const Call& k, const G& g) {
 
 // Sum the GEMM per-tile partials into out[z*ostride + oidx].
 dmpt_status sum_gemm_partials(const Call& k, int batch, double* out, int ostride, int oidx) {
-  HIPCHK(k.c, sum_partials(k.c->d_part, gemm_tiles(k.eng, k.Np, tile_for(k.c, k.Np)), batch, out,
+  HIPCHK(k.c, sum_partials(k.c->d_part, gemm_tiles(k.eng, k.Np, tile_for(k.c, k.eng, k.Np)), batch, out,
                            ostride, oidx, k.c->stream));
   return DMPT_OK;
 }
@@ -1458,6 +1463,7 @@ void dmpt_default_options(dmpt_options* o) {
   o->staged = 1;
   o->warm_traj = 1;
   o->schedule = 1;
+  o->acc64 = 1;
 }
 
 static dmpt_status normalise_options(dmpt_ctx c, const dmpt_options* in, dmpt_options* out) {
@@ -1657,7 +1663,8 @@ dmpt_status dmpt_bench_product(dmpt_ctx c, int64_t N, dmpt_prec prec, int tile, 
   a.C = mptr(k, c->ws.R, 0);
   a.alpha = 1.0;
   a.partials = c->d_part;
-  a.tile = tile;
+  a.acc64 = k.eng == Engine::BF16S3 && c->opt.acc64;
+  a.tile = a.acc64 ? 128 : tile;
   hipEvent_t e0, e1;
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));

@@ -82,6 +82,7 @@ struct GemmArgs {
   double* partials;            // [batch][tiles]
   const int* active;           // optional per-batch mask; 0 = skip the member
   int tile;                    // output tile edge wanted: 0 = largest available, 128, 256
+  int acc64;                   // BF16S3 only: FP32 per stage, FP64 across stages (128-wide tiles)
 };
 
 // Output tile edge, and number of output tiles per batch member, of the

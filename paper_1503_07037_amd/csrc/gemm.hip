@@ -40,6 +40,7 @@ typedef unsigned int u4v __attribute__((__vector_size__(4 * sizeof(unsigned int)
 
 constexpr int BM = 128, BN = 128;
 constexpr int kThreads = 256;
+constexpr int kWaves256 = 8;  // waves of the 256 x 256 split-BF16 kernel (two per SIMD)
 constexpr int kGroupM = 8;   // tile rows per raster group
 constexpr int kXcd = 8;      // XCDs of an MI355X
 
@@ -285,9 +286,11 @@ __global__ __launch_bounds__(kThreads) void k_gemm_f32(GemmArgs a) {
 // ------------------------------------------------------------------ split BF16
 // One kernel for both split engines and both tile sizes:
 //   S   planes per operand (2: three products, 3: six products)
-//   TM  output tile edge of the workgroup (128 or 256); each of the four
-//       waves owns a TM/2 x TM/2 quadrant as (TM/64)^2 MFMA tiles of 32 x 32
+//   TM  output tile edge of the workgroup (128 or 256)
 //   BK  k extent of one pipeline stage (16 or 32)
+//   NW  waves (4 or 8), two along m and NW/2 along n; wave (wm, wn) owns a
+//       TM/2 x 2TM/NW block as MFMA tiles of 32 x 32.  With eight waves (two
+//       per SIMD) one wave's MFMAs cover the other's LDS waits and barrier.
 // Operands are read in the plane layout (1 KB blocks of 32 rows x 16 k, in
 // the MFMA operand order): a stage of one operand plane is TM/32 x BK/16
 // blocks, and lane l of a wave copies bytes 16 l .. 16 l + 15 of a block, so
@@ -296,18 +299,24 @@ __global__ __launch_bounds__(kThreads) void k_gemm_f32(GemmArgs a) {
 // Pipeline over k: two LDS stages and one register stage.  While the MFMAs
 // of stage k run, stage k + 1 (already in registers) is written to the other
 // LDS buffer and the global loads of stage k + 2 are in flight.
-template <int S, int TM, int BK>
-__global__ __launch_bounds__(kThreads) void k_gemm_bf16(GemmArgs a) {
-  constexpr int FI = TM / 64;          // MFMA tiles per wave and dimension
+// FL  1: the MFMAs of each stage accumulate into a fresh FP32 tile that is
+//     then added to an FP64 accumulator (each FP32 sum covers BK of k, so
+//     the FP32 rounding no longer grows with N); 0: one FP32 accumulator.
+template <int S, int TM, int BK, int NW, int FL>
+__global__ __launch_bounds__(NW * 64) void k_gemm_bf16(GemmArgs a) {
+  constexpr int WN = NW / 2;           // waves along n (two along m)
+  constexpr int FM = TM / 64;          // MFMA tiles per wave along m
+  constexpr int FN = TM / (32 * WN);   // MFMA tiles per wave along n
   constexpr int RB = TM / 32;          // 32-row blocks of an operand tile
   constexpr int KB = BK / 16;          // 16-wide k blocks of a stage
   constexpr int NBLK = RB * KB;        // blocks per operand plane and stage
   constexpr int SBLK = 2 * S * NBLK;   // blocks per stage: [operand][plane][row block][k block]
-  constexpr int LOADS = SBLK / 4;      // blocks each wave copies per stage
+  constexpr int LOADS = SBLK / NW;     // blocks each wave copies per stage
   constexpr int SBYTES = SBLK * 1024;
-  static_assert(SBLK % 4 == 0, "a stage must split evenly over the four waves");
+  static_assert(SBLK % NW == 0, "a stage must split evenly over the waves");
+  static_assert(FN >= 1, "at least one MFMA tile per wave along n");
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  __shared__ double red[4];
+  __shared__ double red[NW];
   const int z = blockIdx.z;
   if (a.active && !a.active[z]) return;
   const int64_t Np = a.Np;
@@ -315,13 +324,13 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(GemmArgs a) {
   int tm, tn;
   tile_coords(blockIdx.x, (int)(Np / TM), (int)(Np / TM), tm, tn);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  // the blocks this wave copies: stage block q = wave + 4 j
+  const int wm = wave / WN, wn = wave % WN;
+  // the blocks this wave copies: stage block q = wave + NW j
   const uint16_t* src[LOADS];
   int dst[LOADS];
 #pragma unroll
   for (int j = 0; j < LOADS; ++j) {
-    const int q = wave + 4 * j;
+    const int q = wave + NW * j;
     const int op = q / (S * NBLK), p = (q / NBLK) % S, b = q % NBLK;
     const int rb = b / KB, kb = b % KB;
     const uint16_t* base = op ? a.Y.pl[p] + (int64_t)(z / a.Y.div) * a.Y.stride
@@ -340,13 +349,24 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(GemmArgs a) {
 #pragma unroll
     for (int j = 0; j < LOADS; ++j) *(u4v*)(smem + st * SBYTES + dst[j]) = stg[j];
   };
-  f16v acc[FI][FI];
+  f16v acc[FM][FN];
+  double accd[FL == 1 ? FM : 1][FL == 1 ? FN : 1][FL == 1 ? 16 : 1];
+  f16v zero;
 #pragma unroll
-  for (int i = 0; i < FI; ++i)
+  for (int r = 0; r < 16; ++r) zero[r] = 0.0f;
 #pragma unroll
-    for (int j = 0; j < FI; ++j)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+    for (int j = 0; j < FN; ++j)
+      acc[i][j] = zero;
+  if constexpr (FL == 1) {
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) accd[i][j][r] = 0.0;
+  }
   const int nk = (int)(Np / BK);
   gload(0);
   swrite(0);
@@ -356,43 +376,62 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(GemmArgs a) {
     const unsigned char* sb = smem + (kt & 1) * SBYTES + lane * 16;
 #pragma unroll
     for (int kk = 0; kk < KB; ++kk) {
-      bf8v xa[S][FI], yb[S][FI];
+      bf8v xa[S][FM], yb[S][FN];
 #pragma unroll
-      for (int p = 0; p < S; ++p)
+      for (int p = 0; p < S; ++p) {
 #pragma unroll
-        for (int i = 0; i < FI; ++i) {
+        for (int i = 0; i < FM; ++i)
           xa[p][i] = __builtin_bit_cast(
-              bf8v, *(const u4v*)(sb + ((p * NBLK + (wm * FI + i) * KB + kk) << 10)));
-          yb[p][i] = __builtin_bit_cast(
-              bf8v, *(const u4v*)(sb + (((S + p) * NBLK + (wn * FI + i) * KB + kk) << 10)));
-        }
+              bf8v, *(const u4v*)(sb + ((p * NBLK + (wm * FM + i) * KB + kk) << 10)));
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          yb[p][j] = __builtin_bit_cast(
+              bf8v, *(const u4v*)(sb + (((S + p) * NBLK + (wn * FN + j) * KB + kk) << 10)));
+      }
       if (kk == 0 && kt + 1 < nk) {
         swrite((kt + 1) & 1);
         if (kt + 2 < nk) gload(kt + 2);
       }
-      // smallest terms first
+      {
+        // smallest terms first
 #pragma unroll
-      for (int t = S - 1; t >= 0; --t)          // t = p + q
+        for (int t = S - 1; t >= 0; --t)          // t = p + q
 #pragma unroll
-        for (int p = 0; p <= t; ++p)
+          for (int p = 0; p <= t; ++p)
 #pragma unroll
-          for (int i = 0; i < FI; ++i)
+            for (int i = 0; i < FM; ++i)
 #pragma unroll
-            for (int j = 0; j < FI; ++j)
-              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa[p][i], yb[t - p][j], acc[i][j], 0, 0, 0);
+              for (int j = 0; j < FN; ++j) {
+                // FL: the stage's first product starts a fresh FP32 tile
+                const bool fresh = FL == 1 && kk == 0 && t == S - 1 && p == 0;
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa[p][i], yb[t - p][j],
+                                                                    fresh ? zero : acc[i][j], 0, 0, 0);
+              }
+      }
+    }
+    if constexpr (FL == 1) {
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) accd[i][j][r] += (double)acc[i][j][r];
     }
     __syncthreads();
   }
   double dsum = 0.0;
 #pragma unroll
-  for (int i = 0; i < FI; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < FI; ++j)
+    for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int64_t row = (int64_t)tm * TM + wm * (TM / 2) + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int64_t col = (int64_t)tn * TM + wn * (TM / 2) + j * 32 + (lane & 31);
-        epi<double>(a, z, row, col, (double)acc[i][j][r], dsum);
+        const int64_t col = (int64_t)tn * TM + wn * (TM / WN) + j * 32 + (lane & 31);
+        double v;
+        if constexpr (FL == 1) v = accd[i][j][r];
+        else v = (double)acc[i][j][r];
+        epi<double>(a, z, row, col, v, dsum);
       }
   if (a.W) {
     const double s = block_sum(dsum, red);
@@ -403,16 +442,16 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(GemmArgs a) {
 template <int S, int TM, int BK>
 constexpr size_t bf16_lds() { return (size_t)2 * 2 * S * (TM / 32) * (BK / 16) * 1024; }
 
-template <int S, int TM, int BK>
+template <int S, int TM, int BK, int NW, int FL = 0>
 hipError_t launch_bf16(const GemmArgs& a, dim3 grid, hipStream_t s) {
   const size_t lds = bf16_lds<S, TM, BK>();
-  hipLaunchKernelGGL((k_gemm_bf16<S, TM, BK>), grid, dim3(kThreads), lds, s, a);
+  hipLaunchKernelGGL((k_gemm_bf16<S, TM, BK, NW, FL>), grid, dim3(NW * 64), lds, s, a);
   return hipGetLastError();
 }
 
-template <int S, int TM, int BK>
+template <int S, int TM, int BK, int NW, int FL = 0>
 hipError_t prepare_bf16() {
-  return hipFuncSetAttribute((const void*)k_gemm_bf16<S, TM, BK>,
+  return hipFuncSetAttribute((const void*)k_gemm_bf16<S, TM, BK, NW, FL>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bf16_lds<S, TM, BK>());
 }
 
@@ -430,10 +469,11 @@ int gemm_tile_edge(Engine eng, int64_t Np, int tile_pref) {
 // default, once, before any launch (and so never inside a graph capture).
 hipError_t gemm_prepare() {
   hipError_t e;
-  if ((e = prepare_bf16<2, 128, 32>())) return e;
-  if ((e = prepare_bf16<3, 128, 32>())) return e;
-  if ((e = prepare_bf16<2, 256, 16>())) return e;
-  return prepare_bf16<3, 256, 16>();
+  if ((e = prepare_bf16<2, 128, 32, 4>())) return e;
+  if ((e = prepare_bf16<3, 128, 32, 4>())) return e;
+  if ((e = prepare_bf16<3, 128, 32, 8, 1>())) return e;
+  if ((e = prepare_bf16<2, 256, 16, kWaves256>())) return e;
+  return prepare_bf16<3, 256, 16, kWaves256>();
 }
 
 int gemm_tiles(Engine eng, int64_t Np, int tile_pref) {
@@ -454,9 +494,15 @@ hipError_t gemm(const GemmArgs& a, hipStream_t s) {
       hipLaunchKernelGGL(k_gemm_f32, grid, dim3(kThreads), 0, s, a);
       return hipGetLastError();
     case Engine::BF16S2:
-      return edge == 256 ? launch_bf16<2, 256, 16>(a, grid, s) : launch_bf16<2, 128, 32>(a, grid, s);
+      return edge == 256 ? launch_bf16<2, 256, 16, kWaves256>(a, grid, s)
+                         : launch_bf16<2, 128, 32, 4>(a, grid, s);
     case Engine::BF16S3:
-      return edge == 256 ? launch_bf16<3, 256, 16>(a, grid, s) : launch_bf16<3, 128, 32>(a, grid, s);
+      if (a.acc64) {
+        if (edge != 128) return hipErrorInvalidValue;
+        return launch_bf16<3, 128, 32, 8, 1>(a, grid, s);
+      }
+      return edge == 256 ? launch_bf16<3, 256, 16, kWaves256>(a, grid, s)
+                         : launch_bf16<3, 128, 32, 4>(a, grid, s);
   }
   return hipErrorInvalidValue;
 }
