@@ -98,7 +98,10 @@ typedef struct {
   int schedule;         /* canonical loop for orders >= 1: 0 = Algorithm 1's Newton update of every
                            mu^(k) with Tr P_mu; 1 = after mu0 has converged, one pass per order with
                            the extra response J to H1 = I: P^(k) is affine in mu^(k) with slope -J,
-                           so mu^(k) = Tr P^(k)(0) / Tr J and P^(k) = P^(k)(0) - mu^(k) J exactly */
+                           so mu^(k) = Tr P^(k)(0) / Tr J and P^(k) = P^(k)(0) - mu^(k) J exactly;
+                           the order-1 pass keeps its order-0/1 solutions of every step (memory:
+                           n (d + 2) N^2 master elements) and the order-2 pass reuses them;
+                           2 = as 1 but the order-2 pass solves orders 0 and 1 again */
   int acc64;            /* 6-product split-BF16 products: 1 = each 32-wide slice of k is summed in FP32
                            and the slices in FP64 (128 x 128 tiles; the FP32 rounding then no longer
                            grows with N), 0 = one FP32 accumulator over all of k (256 x 256 tiles) */

@@ -82,6 +82,10 @@ struct dmpt_ctx_s {
   // [step][jet member] of tj_np^2 each; tj_valid = highest order stored
   float* tj = nullptr;
   size_t tj_bytes = 0;
+  // master-precision chains of the linear schedule's order-1 pass: per step,
+  // the order-0 solution and the order-1 solutions of its d + 1 jets
+  void* st = nullptr;
+  size_t st_bytes = 0;
   int64_t tj_np = 0;
   int tj_valid = -1;
   Group U0;                      // order-0 CG unknown when the guess comes from tj
@@ -211,6 +215,9 @@ struct Call {
   int cg_iters = 0;              // iterations per solve when graph is set
   bool traj = false;             // single system: read / write the trajectory c->tj
   int jets = 1;                  // members per step in c->tj (1 + 2 d)
+  int chain = 0;                 // 1: save every step's order-0/1 solutions in c->st; 2: load them
+  int cj = 0;                    // order-1 members per step in c->st (the directions and J)
+  const double* cmu = nullptr;   // chain 2: mu1 per direction, D1 = D1(mu1 = 0) - mu1 D_J
 };
 
 // Member z of a group as an operand.
@@ -604,6 +611,48 @@ dmpt_status tj_load(const Call& k, const Group& g, int z, int step, int j) {
   return DMPT_OK;
 }
 
+// Chain store of the linear schedule (c->st, master precision): step s holds
+// the order-0 solution (member 0) and the order-1 solutions (members 1 .. cj).
+template <class T>
+T* st_ptr(const Call& k, int step, int j) {
+  return (T*)k.c->st + ((size_t)step * (1 + k.cj) + j) * (size_t)k.nn;
+}
+
+bool st_fits(const Call& k, int step, int j) {
+  return step >= 0 && j >= 0 && j <= k.cj &&
+         ((size_t)step * (1 + k.cj) + j + 1) * (size_t)k.nn * k.c->esize <= k.c->st_bytes;
+}
+
+// Save member z of a group (master only) as chain entry (step, j).
+template <class T>
+dmpt_status st_save(const Call& k, const Group& g, int z, int step, int j) {
+  if (!st_fits(k, step, j) || z >= g.count) return fail(k.c, DMPT_ERR_ARG, "internal: chain index");
+  uint16_t* none[3] = {nullptr, nullptr, nullptr};
+  HIPCHK(k.c, (convert<T, T>((const T*)mptr(k, g, z), 0, st_ptr<T>(k, step, j), 0, k.nn, 1, none, 0,
+                             0, k.c->stream)));
+  return DMPT_OK;
+}
+
+// Member z of a group (with planes) = chain entry (step, j) - a * chain entry (step, jb).
+template <class T>
+dmpt_status st_load(const Call& k, const Group& g, int z, int step, int j, double a, int jb) {
+  if (!st_fits(k, step, j) || (a != 0.0 && !st_fits(k, step, jb)) || z >= g.count)
+    return fail(k.c, DMPT_ERR_ARG, "internal: chain index");
+  uint16_t* pl[3];
+  planes_of(k, g, z, pl);
+  uint16_t* none[3] = {nullptr, nullptr, nullptr};
+  T* dst = (T*)mptr(k, g, z);
+  if (a == 0.0) {
+    HIPCHK(k.c, (convert<T, T>(st_ptr<T>(k, step, j), 0, dst, 0, k.nn, 1, pl, 0,
+                               g.pl[0] ? k.np : 0, k.c->stream)));
+  } else {
+    HIPCHK(k.c, (convert<T, T>(st_ptr<T>(k, step, j), 0, dst, 0, k.nn, 1, none, 0, 0, k.c->stream)));
+    HIPCHK(k.c, axpby<T>(st_ptr<T>(k, step, jb), 0, dst, 0, k.nn, 1, -a, 1.0, pl, 0,
+                         g.pl[0] ? k.np : 0, k.c->stream));
+  }
+  return DMPT_OK;
+}
+
 // Order 0 of one recursion step: T' Y0 = 2 D0 with S0 = D0^2 already formed;
 // the previous iterate D0 is the initial guess and D0 is overwritten by the
 // symmetrised solution.
@@ -733,9 +782,18 @@ dmpt_status recursion_step(const Call& k, int order, int d, int step) {
     h.active = w->mask1;
     STCHK(run_gemm(k, h));
   }
-  STCHK(solve_order0<T>(k, step));
+  if (k.chain == 2) {
+    // the order-0 chain of this mu0 is stored: Y0 = its solution at this step
+    STCHK(st_load<T>(k, w->D0, 0, step, 0, 0.0, 0));
+  } else {
+    STCHK(solve_order0<T>(k, step));
+    if (k.chain == 1) STCHK(st_save<T>(k, w->D0, 0, step, 0));
+  }
   // ---- order 1: T' Y1 = 2 D1 - 4 S1 Y0; transposed: rhs^T = 2 D1 - 4 Y0 S1
-  if (order >= 1) {
+  if (order >= 1 && k.chain == 2) {
+    // the order-1 solutions are linear in mu1: Y1 = Y1(mu1 = 0) - mu1 Y_J
+    for (int z = 0; z < md; ++z) STCHK(st_load<T>(k, w->D1, z, step, 1 + z, k.cmu[z], k.cj));
+  } else if (order >= 1) {
     G g;  // R = 2 D1 - 4 Y0 S1   (Y0 = new D0), ||rhs||^2 -> ref
     g.X = op(k, w->D0, 0, true);
     g.X.div = d;
@@ -769,6 +827,8 @@ dmpt_status recursion_step(const Call& k, int order, int d, int step) {
     STCHK(sym_inplace<T>(k, w->D1, 0, md, 0.5));
     if (k.traj)
       for (int z = 0; z < md; ++z) STCHK(tj_save<T>(k, w->D1, z, step, 1 + z));
+    if (k.chain == 1)
+      for (int z = 0; z < md; ++z) STCHK(st_save<T>(k, w->D1, z, step, 1 + z));
   }
   // ---- order 2: rhs^T = 2 D2 - 4 Y1 S1 - 4 Y0 S2
   if (order >= 2) {
@@ -1371,6 +1431,24 @@ bool ensure_traj(dmpt_ctx c, int n, int jets, int64_t Np) {
   return true;
 }
 
+// Chain store for n steps of 1 + jets1 members of Np x Np masters; false when
+// the memory is not there (the order-2 pass then solves orders 0 and 1 again).
+bool ensure_chain(dmpt_ctx c, int n, int jets1, int64_t Np) {
+  const size_t need = (size_t)n * (1 + jets1) * (size_t)Np * Np * c->esize;
+  if (c->st && c->st_bytes >= need) return true;
+  if (c->st) {
+    (void)hipStreamSynchronize(c->stream);
+    dev_free(c, c->st);
+    c->st = nullptr;
+    c->st_bytes = 0;
+  }
+  void* p = dev_alloc(c, need);
+  if (!p) return false;
+  c->st = p;
+  c->st_bytes = need;
+  return true;
+}
+
 // Occupation error of Algorithm 1 (*occ_err, absolute) and its normalised
 // form (*rel): max(|Tr P0 - Ne| / N, max_k |Tr P^(k)| / sum_i |P^(k)_ii|).
 void occupation_error(const double* res, int d, int order, double Ne, int64_t N, double* occ_err,
@@ -1388,31 +1466,61 @@ void occupation_error(const double* res, int d, int order, double Ne, int64_t N,
 
 // The canonical conditions Tr P^(k) = 0 (k >= 1) are linear in mu^(k): with
 // E^(k) = H^(k) - mu^(k) I, P^(k)(mu^(k)) = P^(k)(0) - mu^(k) J, where J is the
-// first-order response to H1 = I at the converged mu0.  One pass for order 1
-// (the d directions plus the identity, mu1 = 0) gives mu1 = Tr P1(0) / Tr J;
-// one pass for order 2 at that mu1 (mu2 = 0) gives mu2 = Tr P2(0) / Tr J.
-// This reaches the fixed point of Algorithm 1's Newton loop in one pass per
-// order instead of iterating all orders together.
+// first-order response to H1 = I (the k-th jet starts from c E^(k), and the
+// recursion of every jet is linear in its start).  One pass for order 1 (the
+// d directions plus J, mu1 = 0) gives mu1 = Tr P1(0) / Tr J; one pass for
+// order 2 at that mu1 (mu2 = 0) gives mu2 = Tr P2(0) / Tr J.  This reaches
+// the fixed point of Algorithm 1's Newton loop in one pass per order.
+//
+// The order-1 pass also settles mu0: Tr J = -d Tr P0 / d mu0 exactly (for
+// the finite recursion), so while |Tr P0 - Ne| misses the tolerance the pass
+// is repeated after the step mu0 += (Tr P0 - Ne) / Tr J.  Its order-0 and
+// order-1 solutions of every step are kept (when memory allows) and the
+// order-2 pass loads them instead of solving again, with
+// Y1 = Y1(mu1 = 0) - mu1 Y_J.
+// *settled: whether mu0 met the tolerance (or its noise floor).
 dmpt_status linear_orders(Call& k, const PassIn& base, int64_t N, int order, double* mu,
-                          double* P0, double* const* P1, double* const* P2) {
+                          double mu_lo, double mu_hi, double Ne, double tol, double* P0,
+                          double* const* P1, double* const* P2, bool* settled, int* passes) {
   dmpt_ctx c = k.c;
   hipStream_t s = c->stream;
   const int d = base.d;
   const int64_t nn = N * N;
   uint16_t* none[3] = {nullptr, nullptr, nullptr};
+  *settled = false;
   // ---- order 1 with the identity as direction d
   std::vector<const double*> h1x(base.H1, base.H1 + d);
   h1x.push_back(nullptr);
   std::vector<double*> p1x(P1, P1 + d);
   p1x.push_back(c->jout);
   std::vector<double> m1(2 + 2 * DMPT_MAX_DIRS, 0.0);
-  m1[0] = mu[0];
   m1[1 + d] = -1.0;  // D0^(1) = c (0 - (-1) I) = c I: the response to H1 = I
   PassIn in1{base.H0, d + 1, h1x.data(), nullptr, base.beta, base.n, 1, m1.data()};
-  STCHK(pass_dispatch(k, in1, P0, p1x.data(), nullptr));
-  const double trJ = c->h_res[RES_TR + 1 + d];
-  if (!(std::fabs(trJ) > 0.0) || !std::isfinite(trJ))
-    return fail(c, DMPT_ERR_NOCONV, "Tr J vanished: the occupation does not respond to mu");
+  const bool keep = order >= 2 && c->opt.schedule == 1 && ensure_chain(c, base.n, d + 1, k.Np);
+  double trJ = 0.0, prev = INFINITY;
+  constexpr int kMaxPasses = 4;
+  for (int a = 0; a < kMaxPasses; ++a) {
+    m1[0] = mu[0];
+    k.chain = keep ? 1 : 0;
+    k.cj = d + 1;
+    STCHK(pass_dispatch(k, in1, P0, p1x.data(), nullptr));
+    k.chain = 0;
+    *passes += 1;
+    trJ = c->h_res[RES_TR + 1 + d];
+    if (!(std::fabs(trJ) > 0.0) || !std::isfinite(trJ))
+      return fail(c, DMPT_ERR_NOCONV, "Tr J vanished: the occupation does not respond to mu");
+    const double rel = std::fabs(c->h_res[RES_TR] - Ne) / (double)N;
+    if (c->log)
+      std::fprintf(stderr, "[dmpt] order-1 pass: mu0 %.15g TrP0-Ne %.3e rel %.3e TrJ %.6e\n", mu[0],
+                   c->h_res[RES_TR] - Ne, rel, trJ);
+    if (rel <= tol || (rel > 0.5 * prev && rel <= 1e3 * tol)) {
+      *settled = true;
+      break;
+    }
+    prev = rel;
+    mu[0] = std::min(std::max(mu[0] + (c->h_res[RES_TR] - Ne) / trJ, mu_lo), mu_hi);
+  }
+  if (!*settled) return DMPT_OK;
   for (int z = 0; z < d; ++z) {
     mu[1 + z] = c->h_res[RES_TR + 1 + z] / trJ;
     HIPCHK(c, axpby<double>(c->jout, 0, P1[z], 0, nn, 1, -mu[1 + z], 1.0, none, 0, 0, s));
@@ -1421,7 +1529,13 @@ dmpt_status linear_orders(Call& k, const PassIn& base, int64_t N, int order, dou
     std::vector<double> m2(1 + 2 * DMPT_MAX_DIRS, 0.0);
     for (int i = 0; i <= d; ++i) m2[i] = mu[i];
     PassIn in2{base.H0, d, base.H1, base.H2, base.beta, base.n, 2, m2.data()};
+    k.chain = keep ? 2 : 0;
+    k.cj = d + 1;
+    k.cmu = mu + 1;
     STCHK(pass_dispatch(k, in2, P0, P1, P2));
+    k.chain = 0;
+    k.cmu = nullptr;
+    *passes += 1;
     for (int z = 0; z < d; ++z) {
       mu[1 + d + z] = c->h_res[RES_TR + 1 + d + z] / trJ;
       HIPCHK(c, axpby<double>(c->jout, 0, P2[z], 0, nn, 1, -mu[1 + d + z], 1.0, none, 0, 0, s));
@@ -1475,6 +1589,7 @@ static dmpt_status normalise_options(dmpt_ctx c, const dmpt_options* in, dmpt_op
   if (o.solver == DMPT_SOLVER_NS) return fail(c, DMPT_ERR_UNSUPPORTED, "Newton-Schulz solver not built");
   if (o.guess != DMPT_GUESS_PREV && o.guess != DMPT_GUESS_TAYLOR)
     return fail(c, DMPT_ERR_ARG, "unknown initial guess");
+  if (o.schedule < 0 || o.schedule > 2) return fail(c, DMPT_ERR_ARG, "schedule must be 0, 1 or 2");
   if (o.tol_occ <= 0) o.tol_occ = default_tol_occ(o.prec, o.refine);
   if (o.tol_cg <= 0) o.tol_cg = default_tol_cg(o.prec, o.refine);
   if (o.max_newton <= 0) o.max_newton = 50;
@@ -1729,6 +1844,7 @@ dmpt_status dmpt_finalize(dmpt_ctx c) {
   if (c->h_res) (void)hipHostFree(c->h_res);
   if (c->h_int) (void)hipHostFree(c->h_int);
   if (c->tj) dev_free(c, c->tj);
+  if (c->st) dev_free(c, c->st);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
   return DMPT_OK;
@@ -1840,7 +1956,7 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
   };
   // linear schedule: the loop converges mu0 with order-0 passes, then one
   // pass per order (with the response J to H1 = I) fixes mu1 and mu2 exactly
-  const bool linear = c->opt.schedule == 1 && order >= 1;
+  const bool linear = c->opt.schedule >= 1 && order >= 1;
   const int loop_order = linear ? 0 : order;
   // trajectory members: order 0, order 1 (plus the identity direction of the
   // linear schedule), order 2
@@ -1901,7 +2017,8 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
     // once Tr P0 meets its own tolerance the (tiny) Newton step is always
     // taken: the bracket's ends then carry the traces' rounding
     const bool occ_met = std::fabs(r[RES_TR] - Ne) <= P.tol_occ * (double)N;
-    if (trpmu > 0.0 && (occ_met || (mu_n >= br_lo && mu_n <= br_hi))) {
+    const bool newton_step = trpmu > 0.0 && (occ_met || (mu_n >= br_lo && mu_n <= br_hi));
+    if (newton_step) {
       mu[0] = mu_n;
       for (int i = 1; i < 1 + stage_order * dd; ++i) mu[i] -= r[RES_TR + i] / trpmu;
     } else {
@@ -1918,6 +2035,13 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
         br_hi = mu_hi;
       }
     }
+    // linear schedule: in the final phase an error this small is settled by
+    // the Newton step just taken (quadratic convergence); the order-1 pass
+    // measures the result and corrects mu0 with the exact slope if needed
+    if (linear && last && newton_step && 100.0 * rel * rel <= P.tol_occ) {
+      done = true;
+      break;
+    }
   }
   if (it > c->opt.max_newton) it = c->opt.max_newton;
   if (done && linear) {
@@ -1925,9 +2049,13 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
     k.eng = P.eng;
     k.np = engine_planes(P.eng);
     k.tol_cg = P.tol_cg;
-    STCHK(linear_orders(k, in, N, order, mu.data(), P0, P1, P2));
-    it += order;
-    occupation_error(c->h_res, dd, order, Ne, N, &occ, &prev_err);
+    bool settled = false;
+    int passes = 0;
+    STCHK(linear_orders(k, in, N, order, mu.data(), mu_lo, mu_hi, Ne, P.tol_occ, P0, P1, P2,
+                        &settled, &passes));
+    it += passes;
+    done = settled;
+    occupation_error(c->h_res, dd, settled ? order : 1, Ne, N, &occ, &prev_err);
   }
   in.order = order;
   for (int i = 0; i < nmu; ++i) mu_inout[i] = mu[i];

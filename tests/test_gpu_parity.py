@@ -89,7 +89,7 @@ def chain128_ref():
     return c, r
 
 
-@pytest.mark.parametrize("schedule,warm_traj", [(1, 1), (1, 0), (0, 1), (0, 0)])
+@pytest.mark.parametrize("schedule,warm_traj", [(1, 1), (1, 0), (2, 1), (0, 1), (0, 0)])
 def test_chain128_canonical_fp64(dm, chain128_ref, schedule, warm_traj):
     """Both canonical schedules: the linear one (mu0 loop, then one pass per
     order with the identity response) and Algorithm 1's joint Newton loop."""
@@ -141,7 +141,7 @@ def test_chain128_canonical_low_precision(dm, chain128_ref, prec, extra, tol):
     assert e0 < tol and e1 < tol and e2 < tol
 
 
-@pytest.mark.parametrize("N,d,schedule", [(250, 3, 1), (384, 2, 1), (250, 3, 0)])
+@pytest.mark.parametrize("N,d,schedule", [(250, 3, 1), (384, 2, 1), (250, 3, 2), (250, 3, 0)])
 def test_ragged_multi_direction_fp64(dm, N, d, schedule):
     """N not a multiple of the tile, several directions, non-zero H2."""
     print(f"case ragged canonical fp64 N={N} d={d} schedule={schedule}", flush=True)
