@@ -1590,6 +1590,7 @@ static dmpt_status normalise_options(dmpt_ctx c, const dmpt_options* in, dmpt_op
   if (o.guess != DMPT_GUESS_PREV && o.guess != DMPT_GUESS_TAYLOR)
     return fail(c, DMPT_ERR_ARG, "unknown initial guess");
   if (o.schedule < 0 || o.schedule > 2) return fail(c, DMPT_ERR_ARG, "schedule must be 0, 1 or 2");
+  if (o.acc64 != 0 && o.acc64 != 1) return fail(c, DMPT_ERR_ARG, "acc64 must be 0 or 1");
   if (o.tol_occ <= 0) o.tol_occ = default_tol_occ(o.prec, o.refine);
   if (o.tol_cg <= 0) o.tol_cg = default_tol_cg(o.prec, o.refine);
   if (o.max_newton <= 0) o.max_newton = 50;
