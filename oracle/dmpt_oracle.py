@@ -18,11 +18,18 @@ matrix perturbation theory"):
   ``phi`` evaluates this closed form; ``phi_pade`` evaluates the Pade power
   form of Appendix A in log space, an independent second closed form.
 * Sec. II, Eqs. (P_resp), (H_prt) and the mu expansion: P(lambda) is the same
-  matrix function of K(lambda) = H(lambda) - mu(lambda) I, so P^(1) and P^(2)
-  are the first and second Frechet (Daleckii-Krein) derivatives in the
-  eigenbasis of H0, and the canonical mu^(k) are fixed by Tr P^(k) = 0
-  (Tr P^(0) = Ne).  Algorithm 1's Newton loop converges to exactly this fixed
-  point; the oracle computes the fixed point directly.
+  matrix function of K(lambda) = H(lambda) - mu(lambda) I, so P^(1), P^(2)
+  and P^(3) are the Taylor coefficients of that matrix function, written in
+  the eigenbasis of H0 with divided differences of phi (Daleckii-Krein):
+  with E_k = V^T H^(k) V - mu^(k) I,
+    P^(1) = phi[1] o E_1,
+    P^(2) = phi[1] o E_2 + T2(E_1, E_1),
+    P^(3) = phi[1] o E_3 + T2(E_1, E_2) + T2(E_2, E_1) + T3(E_1, E_1, E_1),
+  T2(X, Y)_ij = sum_k phi[e_i, e_k, e_j] X_ik Y_kj and
+  T3(X, Y, Z)_ij = sum_kl phi[e_i, e_k, e_l, e_j] X_ik Y_kl Z_lj.  The
+  canonical mu^(k) are fixed by Tr P^(k) = 0 (Tr P^(0) = Ne).  Algorithm 1
+  (written there up to third order) converges to exactly this fixed point;
+  the oracle computes the fixed point directly.
 * Sec. III, Eq. (Resp_0): free-energy response traces Tr[H^(k) P^(m-k)].
 * The adjoint d Tr(A P0)/d H0 of the canonical map, which by the symmetry of
   the first-order kernel equals the canonical first-order response to sym(A).
@@ -35,7 +42,7 @@ import math
 import numpy as np
 
 __all__ = [
-    "phi", "phi_pade", "phi_derivs", "fermi_dirac", "dd1", "dd2",
+    "phi", "phi_pade", "phi_derivs", "phi_derivs5", "fermi_dirac", "dd1", "dd2", "dd3",
     "mu_canonical", "eig", "density", "response", "canonical_response",
     "adjoint_grad", "entropy", "omega", "range_ok",
 ]
@@ -92,15 +99,17 @@ def fermi_dirac(e, beta):
     return 0.5 * (1.0 - np.tanh(0.5 * beta * np.asarray(e, dtype=np.float64)))
 
 
-def phi_derivs(e, beta, M):
-    """Analytic derivatives (phi', phi'', phi'''') of the closed form at e.
+def phi_derivs5(e, beta, M):
+    """Analytic derivatives phi', ..., phi^(5) of the closed form at e.
 
     phi = h(u(e)) with h(u) = 1/2 - tanh(u)/2 and u = 2^M artanh(s e);
-    chain rule (Faa di Bruno) with t = tanh u:
-      h'  = -(1-t^2)/2, h'' = t(1-t^2), h''' = (1-t^2)(1-3t^2),
-      h'''' = -4t(1-t^2)(2-3t^2);
-      w = artanh(z), z = s e:  w' = s/(1-z^2), w'' = 2 s^2 z/(1-z^2)^2,
-      w''' = 2 s^3 (1+3z^2)/(1-z^2)^3, w'''' = 24 s^4 z (1+z^2)/(1-z^2)^4.
+    chain rule (Faa di Bruno, Bell polynomials) with t = tanh u, c = 1 - t^2:
+      h1 = -c/2, h2 = t c, h3 = c (1 - 3t^2), h4 = -4 t c (2 - 3t^2),
+      h5 = -4 c (2 - 15 t^2 + 15 t^4)   (hk the k-th derivative of h);
+      w = artanh(z), z = s e, q = 1 - z^2:  w1 = 1/q, w2 = 2z/q^2,
+      w3 = 2 (1 + 3z^2)/q^3, w4 = 24 z (1 + z^2)/q^4,
+      w5 = 24 (1 + 10 z^2 + 5 z^4)/q^5, and the k-th derivative of u is
+      2^M s^k wk.
     """
     s, K = _s(beta, M)
     e = np.asarray(e, dtype=np.float64)
@@ -108,14 +117,29 @@ def phi_derivs(e, beta, M):
     q = 1.0 - z * z
     t = np.tanh(_u(e, beta, M))
     c = 1.0 - t * t
-    h1, h2, h3, h4 = -0.5 * c, t * c, c * (1.0 - 3.0 * t * t), -4.0 * t * c * (2.0 - 3.0 * t * t)
+    t2 = t * t
+    h1 = -0.5 * c
+    h2 = t * c
+    h3 = c * (1.0 - 3.0 * t2)
+    h4 = -4.0 * t * c * (2.0 - 3.0 * t2)
+    h5 = -4.0 * c * (2.0 - 15.0 * t2 + 15.0 * t2 * t2)
     u1 = K * s / q
     u2 = K * 2.0 * s * s * z / q**2
     u3 = K * 2.0 * s**3 * (1.0 + 3.0 * z * z) / q**3
     u4 = K * 24.0 * s**4 * z * (1.0 + z * z) / q**4
+    u5 = K * 24.0 * s**5 * (1.0 + 10.0 * z * z + 5.0 * z**4) / q**5
     p1 = h1 * u1
     p2 = h2 * u1**2 + h1 * u2
+    p3 = h3 * u1**3 + 3.0 * h2 * u1 * u2 + h1 * u3
     p4 = h4 * u1**4 + 6.0 * h3 * u1**2 * u2 + h2 * (3.0 * u2**2 + 4.0 * u1 * u3) + h1 * u4
+    p5 = (h5 * u1**5 + 10.0 * h4 * u1**3 * u2 + h3 * (15.0 * u1 * u2**2 + 10.0 * u1**2 * u3)
+          + h2 * (10.0 * u2 * u3 + 5.0 * u1 * u4) + h1 * u5)
+    return p1, p2, p3, p4, p5
+
+
+def phi_derivs(e, beta, M):
+    """The first, second and fourth derivatives of phi at e (see ``phi_derivs5``)."""
+    p1, p2, _, p4, _ = phi_derivs5(e, beta, M)
     return p1, p2, p4
 
 
@@ -207,6 +231,43 @@ def dd2(x, y, z, beta, M, delta):
         ss = (x[near] - m) ** 2 + (y[near] - m) ** 2 + (z[near] - m) ** 2
         _, p2, p4 = phi_derivs(m, beta, M)
         out[near] = 0.5 * p2 + p4 * ss / 48.0
+    return out
+
+
+def dd3(a, b, c, d, beta, M, delta):
+    """Third divided difference phi[a, b, c, d] (symmetric in its arguments), broadcasting.
+
+    As in ``dd2``: the pair (p, q) with the largest gap gives
+    phi[p, r1, r2, q] = (phi[p, r1, r2] - phi[r1, r2, q]) / (p - q) when the gap
+    is at least ``delta``; otherwise the four points lie in a cluster of width
+    < delta and the expansion about their mean m,
+    p3(m)/6 + p5(m) * sum((x_i - m)^2) / 240 (pk the k-th derivative of phi),
+    is used; the term in the fourth derivative vanishes at the mean.
+    """
+    pts = np.broadcast_arrays(*(np.asarray(v, dtype=np.float64) for v in (a, b, c, d)))
+    X = np.stack(pts, axis=0)                      # (4, ...)
+    pairs = [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]
+    gaps = np.stack([np.abs(X[i] - X[j]) for i, j in pairs], axis=0)
+    best = np.argmax(gaps, axis=0)
+    gap = np.max(gaps, axis=0)
+    out = np.empty(X.shape[1:])
+    far = gap >= delta
+    if np.any(far):
+        for idx, (i, j) in enumerate(pairs):
+            sel = far & (best == idx)
+            if not np.any(sel):
+                continue
+            rest = [k for k in range(4) if k not in (i, j)]
+            p, q = X[i][sel], X[j][sel]
+            r1, r2 = X[rest[0]][sel], X[rest[1]][sel]
+            out[sel] = (dd2(p, r1, r2, beta, M, delta) - dd2(r1, r2, q, beta, M, delta)) / (p - q)
+    near = ~far
+    if np.any(near):
+        Xn = X[:, near]
+        m = Xn.mean(axis=0)
+        ss = np.sum((Xn - m) ** 2, axis=0)
+        _, _, p3, _, p5 = phi_derivs5(m, beta, M)
+        out[near] = p3 / 6.0 + p5 * ss / 240.0
     return out
 
 
@@ -309,47 +370,99 @@ def _second_order_kernel(e, F1, E, beta, M, delta):
     return Q
 
 
+def _t2(e, F1, X, Y, beta, M, delta):
+    """T2(X, Y)_ij = sum_k phi[e_i, e_k, e_j] X_ik Y_kj for general X, Y.
+
+    Separated pairs (|e_i - e_j| >= delta) use
+    phi[e_i, e_k, e_j] = (phi[e_i, e_k] - phi[e_k, e_j]) / (e_i - e_j):
+    T2 = ((F1 o X) Y - X (F1 o Y)) / (e_i - e_j); the other pairs, the
+    diagonal included, are summed directly over k.
+    """
+    n = e.size
+    num = (F1 * X) @ Y - X @ (F1 * Y)
+    de = e[:, None] - e[None, :]
+    close = np.abs(de) < delta
+    with np.errstate(divide="ignore", invalid="ignore"):
+        T = np.where(close, 0.0, num / np.where(close, 1.0, de))
+    ii, jj = np.nonzero(close)
+    chunk = max(1, (1 << 22) // max(n, 1))
+    for c0 in range(0, ii.size, chunk):
+        i = ii[c0:c0 + chunk]
+        j = jj[c0:c0 + chunk]
+        w2 = dd2(e[i][:, None], e[None, :], e[j][:, None], beta, M, delta)
+        T[i, j] = np.sum(w2 * X[i, :] * Y[:, j].T, axis=1)
+    return T
+
+
+def _t3(e, F1, X, Q, beta, M, delta):
+    """T3(X, X, X)_ij = sum_kl phi[e_i, e_k, e_l, e_j] X_ik X_kl X_lj, Q = T2(X, X).
+
+    Separated pairs use phi[e_i, e_k, e_l, e_j] =
+    (phi[e_i, e_k, e_l] - phi[e_k, e_l, e_j]) / (e_i - e_j), i.e.
+    T3 = (Q X - X Q) / (e_i - e_j); the other pairs are summed directly over
+    (k, l) with ``dd3``.
+    """
+    num = Q @ X - X @ Q
+    de = e[:, None] - e[None, :]
+    close = np.abs(de) < delta
+    with np.errstate(divide="ignore", invalid="ignore"):
+        T = np.where(close, 0.0, num / np.where(close, 1.0, de))
+    for i, j in zip(*np.nonzero(close)):
+        w3 = dd3(e[i], e[:, None], e[None, :], e[j], beta, M, delta)
+        T[i, j] = float(np.sum(w3 * X[i, :][:, None] * X * X[:, j][None, :]))
+    return T
+
+
 def _delta(e):
     width = float(e.max() - e.min()) if e.size > 1 else 1.0
     return 1e-5 * max(width, 1e-3)
 
 
-def response(h0, h1s, h2s, beta, M, mu, order=2, eigh=None):
-    """P0, P1[d], P2[d] at a fixed mu jet (grand canonical; one pass of Algorithm 1).
+def response(h0, h1s, h2s, beta, M, mu, order=2, eigh=None, h3s=None):
+    """P0, P1[d], P2[d], P3[d] at a fixed mu jet (grand canonical; one pass of Algorithm 1).
 
-    mu = (mu0, [mu1_d], [mu2_d]).  H1s, H2s are lists of N x N matrices or
-    length-N vectors (diagonal); an entry of H2s may be None (zero).
-    Returns a dict with P0, P1, P2 (lists) in the original basis.
+    mu = (mu0, [mu1_d], [mu2_d]) or (mu0, [mu1_d], [mu2_d], [mu3_d]).  H1s,
+    H2s, H3s are lists of N x N matrices or length-N vectors (diagonal); an
+    entry of H2s / H3s may be None (zero), and H2s / H3s may be None.
+    Returns a dict with P0, P1, P2, P3 (lists) in the original basis.
     """
     w, v = eigh if eigh is not None else eig(h0)
     mu0 = mu[0]
     e = w - mu0
     F = phi(e, beta, M)
     P0 = (v * F) @ v.T
-    out = dict(P0=P0, P1=[], P2=[], eigh=(w, v))
+    out = dict(P0=P0, P1=[], P2=[], P3=[], eigh=(w, v))
     if order == 0:
         return out
     F1 = dd1(e[:, None], e[None, :], beta, M)
     delta = _delta(e)
+    eye = np.eye(e.size)
     for d, h1 in enumerate(h1s):
-        E1 = _rot(v, h1) - mu[1][d] * np.eye(e.size)
+        E1 = _rot(v, h1) - mu[1][d] * eye
         out["P1"].append(v @ (F1 * E1) @ v.T)
         if order >= 2:
             h2 = h2s[d] if h2s is not None else None
-            E2 = _rot(v, h2) - mu[2][d] * np.eye(e.size)
+            E2 = _rot(v, h2) - mu[2][d] * eye
             Q = _second_order_kernel(e, F1, E1, beta, M, delta)
             out["P2"].append(v @ (Q + F1 * E2) @ v.T)
+        if order >= 3:
+            h3 = h3s[d] if h3s is not None else None
+            E3 = _rot(v, h3) - mu[3][d] * eye
+            R = (F1 * E3 + _t2(e, F1, E1, E2, beta, M, delta) + _t2(e, F1, E2, E1, beta, M, delta)
+                 + _t3(e, F1, E1, Q, beta, M, delta))
+            out["P3"].append(v @ R @ v.T)
     return out
 
 
-def canonical_response(h0, h1s, h2s, beta, Ne, M, order=2, eigh=None):
-    """Canonical P0, P1, P2 and the mu jet (the fixed point of Algorithm 1).
+def canonical_response(h0, h1s, h2s, beta, Ne, M, order=2, eigh=None, h3s=None):
+    """Canonical P0, P1, P2, P3 and the mu jet (the fixed point of Algorithm 1).
 
     mu0 solves Tr P0 = Ne; mu1 = sum_i phi'(e_i) E_ii / sum_i phi'(e_i) makes
     Tr P1 = 0; mu2 = (Tr Q + sum_i phi'(e_i) (V^T H2 V)_ii) / sum_i phi'(e_i)
-    makes Tr P2 = 0 (P1, P2 are affine in mu1 resp. mu2 with slope -phi'(K)).
-    Returns a dict with P0, P1, P2, mu0, mu1, mu2, and the response traces
-    tr_h1p1[d] = Tr(H1 P1), tr_h1p2[d] = Tr(H1 P2), tr_h2p0[d] = Tr(H2 P0).
+    makes Tr P2 = 0; mu3 likewise with the third-order terms (each P^(k) is
+    affine in mu^(k) with slope -phi'(K)).  Returns a dict with P0, P1, P2,
+    P3, mu0, mu1, mu2, mu3, and the response traces tr_h1p1[d] = Tr(H1 P1),
+    tr_h1p2[d] = Tr(H1 P2), tr_h2p0[d] = Tr(H2 P0), tr_h1p3[d] = Tr(H1 P3).
     """
     w, v = eigh if eigh is not None else eig(h0)
     n = w.size
@@ -357,8 +470,8 @@ def canonical_response(h0, h1s, h2s, beta, Ne, M, order=2, eigh=None):
     e = w - mu0
     F = phi(e, beta, M)
     P0 = (v * F) @ v.T
-    res = dict(P0=P0, P1=[], P2=[], mu0=mu0, mu1=[], mu2=[], tr_h1p1=[], tr_h1p2=[],
-               tr_h2p0=[], eigh=(w, v), occ=F)
+    res = dict(P0=P0, P1=[], P2=[], P3=[], mu0=mu0, mu1=[], mu2=[], mu3=[], tr_h1p1=[],
+               tr_h1p2=[], tr_h2p0=[], tr_h1p3=[], eigh=(w, v), occ=F)
     if order == 0:
         return res
     F1 = dd1(e[:, None], e[None, :], beta, M)
@@ -390,6 +503,17 @@ def canonical_response(h0, h1s, h2s, beta, Ne, M, order=2, eigh=None):
             else:
                 h2m = np.diag(h2) if h2.ndim == 1 else h2
                 res["tr_h2p0"].append(float(np.sum(0.5 * (h2m + h2m.T) * P0)))
+        if order >= 3:
+            E2 = H2t - mu2 * eye
+            h3 = h3s[d] if h3s is not None else None
+            H3t = _rot(v, h3)
+            R = (_t2(e, F1, E1, E2, beta, M, delta) + _t2(e, F1, E2, E1, beta, M, delta)
+                 + _t3(e, F1, E1, Q, beta, M, delta))
+            mu3 = float((np.trace(R) + np.sum(fd * np.diag(H3t))) / sfd)
+            P3 = v @ (R + F1 * (H3t - mu3 * eye)) @ v.T
+            res["P3"].append(P3)
+            res["mu3"].append(mu3)
+            res["tr_h1p3"].append(float(np.sum(0.5 * (h1m + h1m.T) * P3)))
     return res
 
 

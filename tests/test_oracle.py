@@ -390,3 +390,180 @@ def test_planted_mistakes_are_caught(monkeypatch):
     monkeypatch.setattr(o.dmpt_oracle, "dd1", lambda a, b, be, m: orig_dd1(b, a, be, m) * 1.01)
     bad = o.canonical_response(h0, [h1], None, beta, Ne, M, order=1)
     assert np.max(np.abs(bad["P1"][0] - P[1])) > 1e-4
+
+
+# ---------------------------------------------------------------- third order
+
+def test_third_and_fifth_derivatives_vs_finite_differences():
+    """phi''' and phi^(5) of phi_derivs5 against differences of the analytic lower derivatives."""
+    beta, M = 20.0, 12
+    e = np.linspace(-1.0, 1.0, 41)
+    p1, p2, p3, p4, p5 = o.phi_derivs5(e, beta, M)
+    h = 1e-4
+    g2 = lambda x: o.phi_derivs5(x, beta, M)[1]
+    g4 = lambda x: o.phi_derivs5(x, beta, M)[3]
+    d3 = (g2(e - 2 * h) - 8 * g2(e - h) + 8 * g2(e + h) - g2(e + 2 * h)) / (12 * h)
+    d5 = (g4(e - 2 * h) - 8 * g4(e - h) + 8 * g4(e + h) - g4(e + 2 * h)) / (12 * h)
+    assert np.max(np.abs(d3 - p3)) < 1e-6 * beta ** 3
+    assert np.max(np.abs(d5 - p5)) < 1e-4 * beta ** 5
+    # the two functions agree on what they share
+    q1, q2, q4 = o.phi_derivs(e, beta, M)
+    assert np.array_equal(q1, p1) and np.array_equal(q2, p2) and np.array_equal(q4, p4)
+
+
+def _dd_mp(pts, beta, M):
+    """Divided difference of phi by the plain recursive quotient rule at 150 digits.
+
+    Repeated points are separated by multiples of 1e-35 (the confluent limit
+    is reached to about 1e-35; each quotient level loses at most ~35 digits).
+    """
+    import mpmath as mp
+    mp.mp.dps = 150
+    s = mp.ldexp(mp.mpf(beta), -(M + 1))
+    K = mp.mpf(2) ** M
+    f = lambda x: mp.mpf(1) / 2 - mp.tanh(K * mp.atanh(s * x)) / 2
+    xs = [mp.mpf(float(p)) + (j + 1) * mp.mpf(10) ** -35 for j, p in enumerate(pts)]
+
+    def rec(lo, hi):
+        if lo == hi:
+            return f(xs[lo])
+        return (rec(lo, hi - 1) - rec(lo + 1, hi)) / (xs[lo] - xs[hi])
+    return float(rec(0, len(xs) - 1))
+
+
+def test_third_divided_differences_vs_high_precision():
+    """dd3 against the plain quotient rule in 150-digit arithmetic; coincident points give phi'''/6."""
+    beta, M = 20.0, 16
+    rng = np.random.default_rng(9)
+    for _ in range(40):
+        pts = rng.uniform(-0.4, 0.4, 4)
+        if rng.random() < 0.3:
+            pts[1] = pts[0] + 3e-6                      # a nearly coincident pair
+        ref = _dd_mp(pts, beta, M)
+        got = float(o.dd3(*pts, beta, M, 1e-5))
+        assert abs(got - ref) < 1e-8 * max(1.0, abs(ref)), (pts, got, ref)
+    a = np.linspace(-0.3, 0.3, 7)
+    _, _, p3, _, _ = o.phi_derivs5(a, beta, M)
+    assert np.max(np.abs(o.dd3(a, a, a, a, beta, M, 1e-5) - p3 / 6.0)) < 1e-12 * beta ** 3
+    # a tight cluster (expansion path) agrees with the high-precision quotient rule
+    for c in (-0.2, 0.05, 0.3):
+        pts = np.array([c, c + 2e-6, c - 1e-6, c + 4e-6])
+        ref = _dd_mp(pts, beta, M)
+        assert abs(float(o.dd3(*pts, beta, M, 1e-5)) - ref) < 1e-9 * max(1.0, abs(ref))
+
+
+def test_third_order_kernels_bruteforce():
+    """T2(X, Y) and T3(X, X, X) against plain loops over 150-digit divided differences."""
+    n, M, beta = 6, 12, 5.0
+    rng = np.random.default_rng(21)
+    e = np.sort(rng.uniform(-1, 1, n))
+    e[3] = e[2] + 2e-7              # a near-degenerate pair takes the direct path
+    X = _sym(rng, n)
+    Y = _sym(rng, n)
+    F1 = o.dd1(e[:, None], e[None, :], beta, M)
+    T2 = o.dmpt_oracle._t2(e, F1, X, Y, beta, M, 1e-5)
+    Q = o.dmpt_oracle._t2(e, F1, X, X, beta, M, 1e-5)
+    T3 = o.dmpt_oracle._t3(e, F1, X, Q, beta, M, 1e-5)
+    ref2 = np.zeros((n, n))
+    ref3 = np.zeros((n, n))
+    for i in range(n):
+        for j in range(n):
+            ref2[i, j] = sum(_dd_mp([e[i], e[k], e[j]], beta, M) * X[i, k] * Y[k, j] for k in range(n))
+            ref3[i, j] = sum(_dd_mp([e[i], e[k], e[l], e[j]], beta, M) * X[i, k] * X[k, l] * X[l, j]
+                             for k in range(n) for l in range(n))
+    assert np.max(np.abs(T2 - ref2)) < 1e-9 * np.max(np.abs(ref2))
+    assert np.max(np.abs(T3 - ref3)) < 1e-8 * np.max(np.abs(ref3))
+
+
+def test_third_order_agrees_with_literal_algorithm1():
+    """Fixed-mu pass and canonical fixed point at third order against the literal Algorithm 1."""
+    n, M, beta = 10, 8, 5.0
+    rng = np.random.default_rng(12)
+    h0 = _sym(rng, n)
+    h1 = _sym(rng, n, 0.3)
+    h2 = _sym(rng, n, 0.2)
+    h3 = _sym(rng, n, 0.1)
+    mu = [0.1, 0.25, -0.4, 0.3]
+    X = alg1_literal.recursion([h0, h1, h2, h3], beta, M, mu, 3)
+    r = o.response(h0, [h1], [h2], beta, M, (mu[0], [mu[1]], [mu[2]], [mu[3]]), order=3, h3s=[h3])
+    assert np.max(np.abs(X[3] - r["P3"][0])) < 1e-11 * max(1.0, np.max(np.abs(X[3])))
+    # canonical
+    n, M, beta, Ne = 14, 10, 8.0, 6.0
+    h0 = w.chain_1d(n, M)
+    h1 = np.diag(np.arange(n) - n / 2.0)
+    h2 = _sym(rng, n, 0.05)
+    h3 = _sym(rng, n, 0.03)
+    # the third-order traces are O(100) here: their rounding floor is ~1e-11
+    P, muj, _ = alg1_literal.canonical([h0, h1, h2, h3], beta, Ne, M, 3, tol=1e-10)
+    rc = o.canonical_response(h0, [h1], [h2], beta, Ne, M, order=3, h3s=[h3])
+    tol = 1e-15 * 2 ** M * 10
+    assert np.max(np.abs(P[3] - rc["P3"][0])) < tol * np.max(np.abs(rc["P3"][0])) * 100
+    assert abs(muj[3] - rc["mu3"][0]) < tol * 1000 * max(1.0, abs(rc["mu3"][0]))
+    assert abs(np.trace(rc["P3"][0])) < 1e-10 * np.max(np.abs(rc["P3"][0]))
+
+
+def test_canonical_third_order_finite_differences():
+    """P3 = (1/6) d^3 P / dlambda^3 with mu(lambda) re-solved, H = H0 + l H1 + l^2 H2 + l^3 H3."""
+    n, M, beta, Ne = 20, 16, 8.0, 9.0
+    rng = np.random.default_rng(6)
+    h0 = w.chain_1d(n, 6)
+    h1 = np.diag(np.arange(n) - n / 2.0) / n
+    h2 = _sym(rng, n, 0.05)
+    h3 = _sym(rng, n, 0.05)
+    r = o.canonical_response(h0, [h1], [h2], beta, Ne, M, order=3, h3s=[h3])
+
+    def p_of(lam):
+        h = h0 + lam * h1 + lam ** 2 * h2 + lam ** 3 * h3
+        wv = o.eig(h)
+        mu = o.mu_canonical(wv[0], beta, M, Ne)
+        return o.density(h, beta, M, mu, eigh=wv), mu
+
+    def d3(h):
+        vals = [p_of(k * h) for k in (-2, -1, 1, 2)]
+        P = (vals[3][0] - 2 * vals[2][0] + 2 * vals[1][0] - vals[0][0]) / (2 * h ** 3)
+        m = (vals[3][1] - 2 * vals[2][1] + 2 * vals[1][1] - vals[0][1]) / (2 * h ** 3)
+        return P / 6.0, m / 6.0
+
+    h = 2e-2
+    a1, b1 = d3(h)
+    a2, b2 = d3(2 * h)
+    P3_fd = (4 * a1 - a2) / 3
+    mu3_fd = (4 * b1 - b2) / 3
+    s3 = np.max(np.abs(r["P3"][0]))
+    assert np.max(np.abs(P3_fd - r["P3"][0])) < 2e-5 * s3
+    assert abs(mu3_fd - r["mu3"][0]) < 2e-5 * max(abs(r["mu3"][0]), s3)
+
+
+def test_third_order_identity_perturbations():
+    """H3 = I gives mu3 = 1 and P3 = 0; H1 = I gives P3 = 0 (a pure shift of mu)."""
+    c = w.config("chain128")
+    n = c["N"]
+    z = np.zeros((n, n))
+    r = o.canonical_response(c["H0"], [z], [z], c["beta"], c["Ne"], c["n"], order=3, h3s=[np.eye(n)])
+    assert abs(r["mu3"][0] - 1.0) < 1e-13
+    assert np.max(np.abs(r["P3"][0])) < 1e-12
+    r = o.canonical_response(c["H0"][:48, :48], [np.eye(48)], None, c["beta"], 24.0, c["n"], order=3)
+    assert np.max(np.abs(r["P3"][0])) < 1e-9 * max(1.0, np.max(np.abs(r["P2"][0])) + 1)
+    assert abs(r["mu1"][0] - 1.0) < 1e-13
+
+
+def test_planted_third_order_mistakes_are_caught(monkeypatch):
+    """A dropped T3 term or a swapped T2 pair is caught by the literal Algorithm 1 pin."""
+    n, M, beta = 10, 8, 5.0
+    rng = np.random.default_rng(12)
+    h0 = _sym(rng, n)
+    h1 = _sym(rng, n, 0.3)
+    h2 = _sym(rng, n, 0.2)
+    h3 = _sym(rng, n, 0.1)
+    mu = [0.1, 0.25, -0.4, 0.3]
+    X = alg1_literal.recursion([h0, h1, h2, h3], beta, M, mu, 3)
+    args = (h0, [h1], [h2], beta, M, (mu[0], [mu[1]], [mu[2]], [mu[3]]))
+    orig3 = o.dmpt_oracle._t3
+    monkeypatch.setattr(o.dmpt_oracle, "_t3", lambda *a: 0.0 * orig3(*a))
+    bad = o.response(*args, order=3, h3s=[h3])
+    assert np.max(np.abs(bad["P3"][0] - X[3])) > 1e-4 * np.max(np.abs(X[3]))
+    monkeypatch.setattr(o.dmpt_oracle, "_t3", orig3)
+    orig2 = o.dmpt_oracle._t2
+    monkeypatch.setattr(o.dmpt_oracle, "_t2", lambda e, F1, Xm, Ym, *a: orig2(e, F1, Xm, Xm, *a))
+    bad = o.response(*args, order=3, h3s=[h3])
+    assert np.max(np.abs(bad["P3"][0] - X[3])) > 1e-4 * np.max(np.abs(X[3]))
