@@ -114,12 +114,13 @@ typedef struct {
   int cg_iters_total;                    /* CG iterations summed over steps, orders and directions */
   int cg_iters_max;                      /* largest CG iteration count of a single solve */
   double occ_err;                        /* |Tr P0 - Ne| + sum_k |Tr P^(k)| of the returned P */
-  double mu[1 + 2 * DMPT_MAX_DIRS];      /* mu0, mu1[d], mu2[d] used for the returned P */
-  double trP[1 + 2 * DMPT_MAX_DIRS];     /* Tr P0, Tr P1[d], Tr P2[d] */
+  double mu[1 + 3 * DMPT_MAX_DIRS];      /* mu0, mu1[d], mu2[d], mu3[d] used for the returned P */
+  double trP[1 + 3 * DMPT_MAX_DIRS];     /* Tr P0, Tr P1[d], Tr P2[d], Tr P3[d] */
   double tr_pmu;                         /* Tr P_mu = beta (Tr P0 - ||P0||_F^2) */
   double tr_h1p1[DMPT_MAX_DIRS];         /* Tr(H1 P1) per direction */
   double tr_h1p2[DMPT_MAX_DIRS];         /* Tr(H1 P2) per direction */
   double tr_h2p0[DMPT_MAX_DIRS];         /* Tr(H2 P0) per direction (0 when H2 is absent) */
+  double tr_h1p3[DMPT_MAX_DIRS];         /* Tr(H1 P3) per direction (order 3) */
   double idempotency;                    /* Tr[P0 (I - P0)] (check = 1) */
   double commutator;                     /* ||H0 P0 - P0 H0||_F (check = 1) */
   double asymmetry;                      /* max |P - P^T| over the outputs (check = 1) */
@@ -155,15 +156,19 @@ dmpt_status dmpt_fermi_recursion(dmpt_ctx ctx, int64_t N, const double* H0, doub
                                  double mu, int n, double* P0, dmpt_stats* st);
 
 /* One pass of Algorithm 1's inner loop at a given mu jet (no Newton):
- * orders 0..order (order in {0, 1, 2}) for d directions.
+ * orders 0..order (order in {0, 1, 2, 3}: Algorithm 1's solve lines) for d
+ * directions of H(lambda) = H0 + lambda H1 + lambda^2 H2 + lambda^3 H3.
  *   H1[d]  device pointers to the first-order perturbations (order >= 1)
  *   H2[d]  device pointers to second-order perturbations, or H2 == NULL / H2[i] == NULL for zero
- *   mu     host array: mu0, then mu1[0..d-1] (order >= 1), then mu2[0..d-1] (order >= 2)
- *   P0, P1[d], P2[d]  device outputs (P1 / P2 may be NULL when order is lower). */
+ *   H3[d]  third-order perturbations, likewise (order 3)
+ *   mu     host array: mu0, then mu1[0..d-1] (order >= 1), mu2[0..d-1] (order >= 2),
+ *          mu3[0..d-1] (order 3)
+ *   P0, P1[d], P2[d], P3[d]  device outputs (P1 / P2 / P3 may be NULL when order is lower). */
 dmpt_status dmpt_response(dmpt_ctx ctx, int64_t N, const double* H0, int d,
-                          const double* const* H1, const double* const* H2, double beta, int n,
-                          int order, const double* mu, double* P0, double* const* P1,
-                          double* const* P2, dmpt_stats* st);
+                          const double* const* H1, const double* const* H2,
+                          const double* const* H3, double beta, int n, int order, const double* mu,
+                          double* P0, double* const* P1, double* const* P2, double* const* P3,
+                          dmpt_stats* st);
 
 /* Canonical response (Algorithm 1): Newton on the mu jet until the
  * occupation error is at most tol_occ (the mu0 step is safeguarded by a
@@ -171,18 +176,20 @@ dmpt_status dmpt_response(dmpt_ctx ctx, int64_t N, const double* H0, int d,
  * found).  The context needs dirs_max >= d.  mu_inout (host, 1 + order*d
  * doubles): in, mu0 guess (NaN: Tr H0 / N) and mu^(k) guesses (NaN: 0); out,
  * the jet at which the returned P was computed.  On DMPT_ERR_NOCONV the
- * outputs and *st hold the last pass. */
+ * outputs and *st hold the last pass.  order in {0, 1, 2, 3}; arguments as
+ * for dmpt_response. */
 dmpt_status dmpt_mu_newton(dmpt_ctx ctx, int64_t N, const double* H0, int d,
-                           const double* const* H1, const double* const* H2, double beta,
-                           double Ne, int n, int order, double* mu_inout, double* P0,
-                           double* const* P1, double* const* P2, dmpt_stats* st);
+                           const double* const* H1, const double* const* H2,
+                           const double* const* H3, double beta, double Ne, int n, int order,
+                           double* mu_inout, double* P0, double* const* P1, double* const* P2,
+                           double* const* P3, dmpt_stats* st);
 
 /* Batched canonical response: nsys independent systems of sizes Ns[s] (each
  * <= the context's n_max), with per-system beta and Ne, d directions each.
  * H0s[s], P0s[s]: N_s x N_s device FP64; H1s[s*d + i], P1s[s*d + i],
  * P2s[s*d + i] likewise (P1s / P2s may be NULL for lower orders).  mus
  * (host, nsys * (1 + 2d)) receives each system's jet; st (may be NULL) the
- * aggregate statistics.  Systems converge independently. */
+ * aggregate statistics.  Systems converge independently.  order in {0, 1, 2}. */
 dmpt_status dmpt_mu_newton_batched(dmpt_ctx ctx, int nsys, const int64_t* Ns,
                                    const double* const* H0s, int d, const double* const* H1s,
                                    const double* betas, const double* Nes, int n, int order,

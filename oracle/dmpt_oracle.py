@@ -370,18 +370,19 @@ def _second_order_kernel(e, F1, E, beta, M, delta):
     return Q
 
 
-def _t2(e, F1, X, Y, beta, M, delta):
+def _t2(e, F1, X, Y, beta, M, delta, pair_delta):
     """T2(X, Y)_ij = sum_k phi[e_i, e_k, e_j] X_ik Y_kj for general X, Y.
 
-    Separated pairs (|e_i - e_j| >= delta) use
+    Separated pairs (|e_i - e_j| >= pair_delta) use
     phi[e_i, e_k, e_j] = (phi[e_i, e_k] - phi[e_k, e_j]) / (e_i - e_j):
     T2 = ((F1 o X) Y - X (F1 o Y)) / (e_i - e_j); the other pairs, the
-    diagonal included, are summed directly over k.
+    diagonal included, are summed directly over k (``dd2`` with its own
+    cluster threshold delta).
     """
     n = e.size
     num = (F1 * X) @ Y - X @ (F1 * Y)
     de = e[:, None] - e[None, :]
-    close = np.abs(de) < delta
+    close = np.abs(de) < pair_delta
     with np.errstate(divide="ignore", invalid="ignore"):
         T = np.where(close, 0.0, num / np.where(close, 1.0, de))
     ii, jj = np.nonzero(close)
@@ -394,17 +395,17 @@ def _t2(e, F1, X, Y, beta, M, delta):
     return T
 
 
-def _t3(e, F1, X, Q, beta, M, delta):
+def _t3(e, F1, X, Q, beta, M, delta, pair_delta):
     """T3(X, X, X)_ij = sum_kl phi[e_i, e_k, e_l, e_j] X_ik X_kl X_lj, Q = T2(X, X).
 
-    Separated pairs use phi[e_i, e_k, e_l, e_j] =
+    Separated pairs (|e_i - e_j| >= pair_delta) use phi[e_i, e_k, e_l, e_j] =
     (phi[e_i, e_k, e_l] - phi[e_k, e_l, e_j]) / (e_i - e_j), i.e.
     T3 = (Q X - X Q) / (e_i - e_j); the other pairs are summed directly over
     (k, l) with ``dd3``.
     """
     num = Q @ X - X @ Q
     de = e[:, None] - e[None, :]
-    close = np.abs(de) < delta
+    close = np.abs(de) < pair_delta
     with np.errstate(divide="ignore", invalid="ignore"):
         T = np.where(close, 0.0, num / np.where(close, 1.0, de))
     for i, j in zip(*np.nonzero(close)):
@@ -416,6 +417,18 @@ def _t3(e, F1, X, Q, beta, M, delta):
 def _delta(e):
     width = float(e.max() - e.min()) if e.size > 1 else 1.0
     return 1e-5 * max(width, 1e-3)
+
+
+def _pair_delta(e):
+    """Eigenvalue gap below which the third-order kernels sum a pair (i, j) directly.
+
+    The separated-pair identities divide by e_i - e_j twice over (T3 is
+    built from T2), so a pair just above the scalar threshold of ``_delta``
+    would lose about eps * width / gap^2; 1e-3 of the spectral width keeps
+    that below ~1e-12 at a few direct sums per eigenvalue.
+    """
+    width = float(e.max() - e.min()) if e.size > 1 else 1.0
+    return 1e-3 * max(width, 1e-3)
 
 
 def response(h0, h1s, h2s, beta, M, mu, order=2, eigh=None, h3s=None):
@@ -448,8 +461,9 @@ def response(h0, h1s, h2s, beta, M, mu, order=2, eigh=None, h3s=None):
         if order >= 3:
             h3 = h3s[d] if h3s is not None else None
             E3 = _rot(v, h3) - mu[3][d] * eye
-            R = (F1 * E3 + _t2(e, F1, E1, E2, beta, M, delta) + _t2(e, F1, E2, E1, beta, M, delta)
-                 + _t3(e, F1, E1, Q, beta, M, delta))
+            pd = _pair_delta(e)
+            R = (F1 * E3 + _t2(e, F1, E1, E2, beta, M, delta, pd)
+                 + _t2(e, F1, E2, E1, beta, M, delta, pd) + _t3(e, F1, E1, Q, beta, M, delta, pd))
             out["P3"].append(v @ R @ v.T)
     return out
 
@@ -507,8 +521,9 @@ def canonical_response(h0, h1s, h2s, beta, Ne, M, order=2, eigh=None, h3s=None):
             E2 = H2t - mu2 * eye
             h3 = h3s[d] if h3s is not None else None
             H3t = _rot(v, h3)
-            R = (_t2(e, F1, E1, E2, beta, M, delta) + _t2(e, F1, E2, E1, beta, M, delta)
-                 + _t3(e, F1, E1, Q, beta, M, delta))
+            pd = _pair_delta(e)
+            R = (_t2(e, F1, E1, E2, beta, M, delta, pd) + _t2(e, F1, E2, E1, beta, M, delta, pd)
+                 + _t3(e, F1, E1, Q, beta, M, delta, pd))
             mu3 = float((np.trace(R) + np.sum(fd * np.diag(H3t))) / sfd)
             P3 = v @ (R + F1 * (H3t - mu3 * eye)) @ v.T
             res["P3"].append(P3)

@@ -45,9 +45,10 @@ class Stats(ctypes.Structure):
     _fields_ = [
         ("newton_iters", ctypes.c_int), ("cg_iters_total", ctypes.c_int),
         ("cg_iters_max", ctypes.c_int), ("occ_err", ctypes.c_double),
-        ("mu", ctypes.c_double * (1 + 2 * MAX_DIRS)), ("trP", ctypes.c_double * (1 + 2 * MAX_DIRS)),
+        ("mu", ctypes.c_double * (1 + 3 * MAX_DIRS)), ("trP", ctypes.c_double * (1 + 3 * MAX_DIRS)),
         ("tr_pmu", ctypes.c_double), ("tr_h1p1", ctypes.c_double * MAX_DIRS),
         ("tr_h1p2", ctypes.c_double * MAX_DIRS), ("tr_h2p0", ctypes.c_double * MAX_DIRS),
+        ("tr_h1p3", ctypes.c_double * MAX_DIRS),
         ("idempotency", ctypes.c_double), ("commutator", ctypes.c_double),
         ("asymmetry", ctypes.c_double), ("mfma_flops", ctypes.c_double),
         ("useful_flops", ctypes.c_double), ("seconds", ctypes.c_double),
@@ -60,7 +61,8 @@ class Stats(ctypes.Structure):
             cg_iters_max=self.cg_iters_max, occ_err=self.occ_err,
             mu=list(self.mu[:nmu]), trP=list(self.trP[:nmu]), tr_pmu=self.tr_pmu,
             tr_h1p1=list(self.tr_h1p1[:d]), tr_h1p2=list(self.tr_h1p2[:d]),
-            tr_h2p0=list(self.tr_h2p0[:d]), idempotency=self.idempotency,
+            tr_h2p0=list(self.tr_h2p0[:d]), tr_h1p3=list(self.tr_h1p3[:d]),
+            idempotency=self.idempotency,
             commutator=self.commutator, asymmetry=self.asymmetry, mfma_flops=self.mfma_flops,
             useful_flops=self.useful_flops, seconds=self.seconds)
 
@@ -104,8 +106,9 @@ def load(path=None):
     lib.dmpt_last_error.restype = ctypes.c_char_p
     lib.dmpt_set_options.argtypes = [P, ctypes.POINTER(Options)]
     lib.dmpt_fermi_recursion.argtypes = [P, I64, P, D, D, I, P, ctypes.POINTER(Stats)]
-    lib.dmpt_response.argtypes = [P, I64, P, I, PP, PP, D, I, I, DP, P, PP, PP, ctypes.POINTER(Stats)]
-    lib.dmpt_mu_newton.argtypes = [P, I64, P, I, PP, PP, D, D, I, I, DP, P, PP, PP,
+    lib.dmpt_response.argtypes = [P, I64, P, I, PP, PP, PP, D, I, I, DP, P, PP, PP, PP,
+                                  ctypes.POINTER(Stats)]
+    lib.dmpt_mu_newton.argtypes = [P, I64, P, I, PP, PP, PP, D, D, I, I, DP, P, PP, PP, PP,
                                    ctypes.POINTER(Stats)]
     lib.dmpt_mu_newton_batched.argtypes = [P, I, ctypes.POINTER(I64), PP, I, PP, DP, DP, I, I, DP,
                                            PP, PP, PP, ctypes.POINTER(Stats)]

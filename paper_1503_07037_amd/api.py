@@ -20,6 +20,24 @@ class DMPTError(RuntimeError):
         self.stats = stats
 
 
+class Response(tuple):
+    """(P0, [P1], [P2], mu_jet, stats) of a canonical solve; .P3 holds [P3] (order 3)."""
+
+    def __new__(cls, P0, P1, P2, mu, stats, P3=()):
+        r = super().__new__(cls, (P0, P1, P2, mu, stats))
+        r.P3 = list(P3)
+        return r
+
+
+class Pass(tuple):
+    """(P0, [P1], [P2], stats) of one pass at a fixed mu jet; .P3 holds [P3] (order 3)."""
+
+    def __new__(cls, P0, P1, P2, stats, P3=()):
+        r = super().__new__(cls, (P0, P1, P2, stats))
+        r.P3 = list(P3)
+        return r
+
+
 def _torch():
     import torch
     return torch
@@ -156,8 +174,9 @@ class Context:
         self._raise(st, s)
         return P0, s.as_dict()
 
-    def response(self, H0, H1=(), H2=None, beta=1.0, n=20, order=0, mu=(0.0,), raise_on_error=True):
-        """One pass at a fixed mu jet.  Returns (P0, [P1], [P2], stats)."""
+    def response(self, H0, H1=(), H2=None, beta=1.0, n=20, order=0, mu=(0.0,), raise_on_error=True,
+                 H3=None):
+        """One pass at a fixed mu jet (orders 0..3).  Returns Pass(P0, [P1], [P2], stats), .P3."""
         N = H0.shape[0]
         _check_mat(H0, N, "H0")
         d = len(H1) if order >= 1 else 0
@@ -169,27 +188,32 @@ class Context:
                 if h is not None:
                     _check_mat(h, N, f"H2[{i}]")
             h2 = _ptr_array(list(H2))
+        h3 = self._opt_mats(H3, N, "H3") if order >= 3 else None
         mu = [float(m) for m in mu]
         if len(mu) < 1 + order * d:
             raise ValueError(f"mu must hold 1 + order*d = {1 + order * d} values")
         P0 = self._empty(N)
         P1 = [self._empty(N) for _ in range(d)] if order >= 1 else []
         P2 = [self._empty(N) for _ in range(d)] if order >= 2 else []
+        P3 = [self._empty(N) for _ in range(d)] if order >= 3 else []
         s = L.Stats()
         mu_arr = (ctypes.c_double * len(mu))(*mu)
-        st = self.lib.dmpt_response(self.h, N, _ptr(H0), d, _ptr_array(list(H1[:d])), h2,
+        st = self.lib.dmpt_response(self.h, N, _ptr(H0), d, _ptr_array(list(H1[:d])), h2, h3,
                                     float(beta), int(n), int(order), mu_arr, _ptr(P0),
                                     _ptr_array(P1) if P1 else None, _ptr_array(P2) if P2 else None,
-                                    ctypes.byref(s))
+                                    _ptr_array(P3) if P3 else None, ctypes.byref(s))
         stats = s.as_dict(d, order)
         if raise_on_error:
             self._raise(st, stats)
         stats["status"] = st
-        return P0, P1, P2, stats
+        return Pass(P0, P1, P2, stats, P3)
 
     def mu_newton(self, H0, H1=(), H2=None, beta=1.0, Ne=1.0, n=20, order=0, mu=None,
-                  raise_on_error=True):
-        """Canonical response (Algorithm 1).  Returns (P0, [P1], [P2], mu_jet, stats)."""
+                  raise_on_error=True, H3=None):
+        """Canonical response (Algorithm 1, orders 0..3).
+
+        Returns Response(P0, [P1], [P2], mu_jet, stats) with .P3 ([P3] for order 3).
+        """
         N = H0.shape[0]
         _check_mat(H0, N, "H0")
         d = len(H1) if order >= 1 else 0
@@ -201,6 +225,7 @@ class Context:
                 if h is not None:
                     _check_mat(h, N, f"H2[{i}]")
             h2 = _ptr_array(list(H2))
+        h3 = self._opt_mats(H3, N, "H3") if order >= 3 else None
         nmu = 1 + order * d
         m = [math.nan] * nmu
         if mu is not None:
@@ -210,16 +235,28 @@ class Context:
         P0 = self._empty(N)
         P1 = [self._empty(N) for _ in range(d)] if order >= 1 else []
         P2 = [self._empty(N) for _ in range(d)] if order >= 2 else []
+        P3 = [self._empty(N) for _ in range(d)] if order >= 3 else []
         s = L.Stats()
-        st = self.lib.dmpt_mu_newton(self.h, N, _ptr(H0), d, _ptr_array(list(H1[:d])), h2,
+        st = self.lib.dmpt_mu_newton(self.h, N, _ptr(H0), d, _ptr_array(list(H1[:d])), h2, h3,
                                      float(beta), float(Ne), int(n), int(order), mu_arr, _ptr(P0),
                                      _ptr_array(P1) if P1 else None,
-                                     _ptr_array(P2) if P2 else None, ctypes.byref(s))
+                                     _ptr_array(P2) if P2 else None,
+                                     _ptr_array(P3) if P3 else None, ctypes.byref(s))
         stats = s.as_dict(d, order)
         stats["status"] = st
         if raise_on_error:
             self._raise(st, stats)
-        return P0, P1, P2, list(mu_arr), stats
+        return Response(P0, P1, P2, list(mu_arr), stats, P3)
+
+    @staticmethod
+    def _opt_mats(Hs, N, name):
+        """Pointer array for an optional per-direction list (None entries: zero)."""
+        if Hs is None:
+            return None
+        for i, h in enumerate(Hs):
+            if h is not None:
+                _check_mat(h, N, f"{name}[{i}]")
+        return _ptr_array(list(Hs))
 
     def mu_newton_batched(self, H0s, H1s=None, betas=(), Nes=(), n=20, order=0, mus=None,
                           raise_on_error=True):

@@ -8,10 +8,12 @@
 //     T' Y^(0) = 2 D^(0)
 //     T' Y^(1) = 2 D^(1) - 4 S^(1) Y^(0)
 //     T' Y^(2) = 2 D^(2) - 4 S^(1) Y^(1) - 4 S^(2) Y^(0)
-// with S^(1) = D^(0) D^(1) + D^(1) D^(0), S^(2) = D^(0) D^(2) + D^(2) D^(0) + D^(1) D^(1)
+//     T' Y^(3) = 2 D^(3) - 4 S^(1) Y^(2) - 4 S^(2) Y^(1) - 4 S^(3) Y^(0)
+// with S^(1) = D^(0) D^(1) + D^(1) D^(0), S^(2) = D^(0) D^(2) + D^(2) D^(0) + D^(1) D^(1),
+// S^(3) = D^(0) D^(3) + D^(3) D^(0) + D^(1) D^(2) + D^(2) D^(1)
 // (the lambda-expansion of T'(lambda) Y(lambda) = 2 D(lambda); these are the
-// systems of Algorithm 1 written for D).  After n steps P^(0) = I/2 - D^(0),
-// P^(k) = -D^(k).
+// systems of Algorithm 1, up to its third order, written for D).  After n
+// steps P^(0) = I/2 - D^(0), P^(k) = -D^(k).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -43,7 +45,7 @@ struct Group {
 // the per-direction groups are laid out [system][direction]; the single
 // system entry points use one system.
 struct WS {
-  Group D0, D1, D2, S0, S1, S2, R, P, Q;
+  Group D0, D1, D2, D3, S0, S1, S2, S3, R, P, Q;
   double* rr = nullptr;          // CG <r,r> history [member][hstride]
   double* pq = nullptr;          // CG <p,Tp> history [member][hstride]
   double* ref = nullptr;         // ||rhs||^2 [member]
@@ -123,12 +125,13 @@ namespace {
 
 // Layout of the results block d_res.
 enum : int {
-  RES_TR = 0,                          // Tr P0, Tr P1[d], Tr P2[d]
-  RES_ATR = RES_TR + 1 + 2 * DMPT_MAX_DIRS,
-  RES_FRO = RES_ATR + 1 + 2 * DMPT_MAX_DIRS,
+  RES_TR = 0,                          // Tr P0, Tr P1[d], Tr P2[d], Tr P3[d]
+  RES_ATR = RES_TR + 1 + 3 * DMPT_MAX_DIRS,
+  RES_FRO = RES_ATR + 1 + 3 * DMPT_MAX_DIRS,
   RES_H1P1 = RES_FRO + 1,
   RES_H1P2 = RES_H1P1 + DMPT_MAX_DIRS,
-  RES_H2P0 = RES_H1P2 + DMPT_MAX_DIRS,
+  RES_H1P3 = RES_H1P2 + DMPT_MAX_DIRS,
+  RES_H2P0 = RES_H1P3 + DMPT_MAX_DIRS,
   RES_MISC = RES_H2P0 + DMPT_MAX_DIRS,  // scratch scalars
   RES_HALF = RES_MISC + 15,             // constant 1/2
   RES_COUNT = RES_MISC + 16
@@ -215,10 +218,15 @@ struct Call {
   int cg_iters = 0;              // iterations per solve when graph is set
   bool traj = false;             // single system: read / write the trajectory c->tj
   int jets = 1;                  // members per step in c->tj (1 + 2 d)
-  int chain = 0;                 // 1: save every step's order-0/1 solutions in c->st; 2: load them
-  int cj = 0;                    // order-1 members per step in c->st (the directions and J)
-  const double* cmu = nullptr;   // chain 2: mu1 per direction, D1 = D1(mu1 = 0) - mu1 D_J
+  int chain = 0;                 // kSave01 | kLoad01 | kSave2 | kLoad2 (c->st, see st_ptr)
+  int cs = 0;                    // members per step in c->st
+  int cj = 0;                    // member of the J jet's solution in c->st (1 + d)
+  const double* cmu = nullptr;   // chain loads: mu1[d], mu2[d]; D^(k) = D^(k)(mu = 0) - mu D_J
 };
+
+// Chain flags of a pass (linear schedule): save or load the order-0/1
+// solutions, save or load the order-2 solutions.
+constexpr int kSave01 = 1, kLoad01 = 2, kSave2 = 4, kLoad2 = 8;
 
 // Member z of a group as an operand.
 BOp op(const Call& k, const Group& g, int z, bool batched) {
@@ -533,8 +541,15 @@ struct PassIn {
   double beta;
   int n;
   int order;
-  const double* mu;  // mu0, mu1[d], mu2[d]
+  const double* mu;                    // mu0, mu1[d], mu2[d], mu3[d]
+  const double* const* H3 = nullptr;   // third-order perturbations (NULL: zero)
 };
+
+// Group of the order-o jet (o = 1..3) and of its square term S^(o).
+const Group& jet(const WS* w, int o) { return o == 1 ? w->D1 : (o == 2 ? w->D2 : w->D3); }
+const Group& sqr(const WS* w, int o) { return o == 1 ? w->S1 : (o == 2 ? w->S2 : w->S3); }
+// Slot of (order o >= 1, direction z) in the mu jet and in the trace results.
+inline int slot_of(int o, int z, int d) { return 1 + (o - 1) * d + z; }
 
 // Initialise D0^(k) = c (sym H^(k) - mu^(k) I) from the FP64 caller inputs.
 template <class T>
@@ -562,6 +577,9 @@ dmpt_status init_d(const Call& k, const PassIn& in, double cscale) {
   if (in.order >= 2)
     for (int z = 0; z < in.d; ++z)
       STCHK(one(in.H2 ? in.H2[z] : nullptr, w->D2, z, in.mu[1 + in.d + z]));
+  if (in.order >= 3)
+    for (int z = 0; z < in.d; ++z)
+      STCHK(one(in.H3 ? in.H3[z] : nullptr, w->D3, z, in.mu[1 + 2 * in.d + z]));
   return DMPT_OK;
 }
 
@@ -611,16 +629,18 @@ dmpt_status tj_load(const Call& k, const Group& g, int z, int step, int j) {
   return DMPT_OK;
 }
 
-// Chain store of the linear schedule (c->st, master precision): step s holds
-// the order-0 solution (member 0) and the order-1 solutions (members 1 .. cj).
+// Chain store of the linear schedule (c->st, master precision), k.cs members
+// per step: the order-0 solution (member 0), the order-1 solutions of the d
+// directions and of J (members 1 .. d + 1) and, when a third-order pass
+// follows, the order-2 solutions (members d + 2 .. 2d + 1).
 template <class T>
 T* st_ptr(const Call& k, int step, int j) {
-  return (T*)k.c->st + ((size_t)step * (1 + k.cj) + j) * (size_t)k.nn;
+  return (T*)k.c->st + ((size_t)step * k.cs + j) * (size_t)k.nn;
 }
 
 bool st_fits(const Call& k, int step, int j) {
-  return step >= 0 && j >= 0 && j <= k.cj &&
-         ((size_t)step * (1 + k.cj) + j + 1) * (size_t)k.nn * k.c->esize <= k.c->st_bytes;
+  return step >= 0 && j >= 0 && j < k.cs &&
+         ((size_t)step * k.cs + j + 1) * (size_t)k.nn * k.c->esize <= k.c->st_bytes;
 }
 
 // Save member z of a group (master only) as chain entry (step, j).
@@ -737,6 +757,31 @@ dmpt_status solve_order0(const Call& k, int step) {
   return DMPT_OK;
 }
 
+// Finish the solve of one jet order: R holds rhs^T (its norm in ref); with
+// the guess U in group g (the previous iterate or a stored one) form the
+// initial residual R -= U + 4 U S0, run CG and symmetrise the solution.
+template <class T>
+dmpt_status solve_jet(const Call& k, const Group& g, int md, int d) {
+  const WS* w = k.w;
+  G h;
+  h.X = op(k, g, 0, true);
+  h.Y = op(k, w->S0, 0, true);
+  h.Y.div = d;
+  h.C = mptr(k, w->R, 0);
+  h.sC = k.stride;
+  h.alpha = -4.0;
+  h.C1 = mptr(k, w->R, 0); h.sC1 = k.stride; h.beta1 = 1.0;
+  h.C2 = mptr(k, g, 0); h.sC2 = k.stride; h.beta2 = -1.0;
+  h.W = mptr(k, w->R, 0); h.sW = k.stride;
+  h.batch = md;
+  h.active = w->mask1;
+  STCHK(run_gemm(k, h));
+  STCHK(sum_gemm_partials(k, md, w->rr, k.c->hstride, 0));
+  STCHK(cg_solve<T>(k, g, md, d, w->mask1));
+  STCHK(sym_inplace<T>(k, g, 0, md, 0.5));
+  return DMPT_OK;
+}
+
 // One recursion step for orders 0..order, d directions per system, on the
 // iterates held in k.w (Algorithm 1's inner loop body, in D form).
 template <class T>
@@ -782,15 +827,43 @@ dmpt_status recursion_step(const Call& k, int order, int d, int step) {
     h.active = w->mask1;
     STCHK(run_gemm(k, h));
   }
-  if (k.chain == 2) {
+  if (order >= 3) {
+    // Q = D3 D0, R = D2 D1 -> S3 = Q + Q^T + R + R^T
+    G g;
+    g.X = op(k, w->D3, 0, true);
+    g.Y = op(k, w->D0, 0, true);
+    g.Y.div = d;
+    g.C = mptr(k, w->Q, 0);
+    g.sC = k.stride;
+    g.batch = md;
+    g.active = w->mask1;
+    STCHK(run_gemm(k, g));
+    G h;
+    h.X = op(k, w->D2, 0, true);
+    h.Y = op(k, w->D1, 0, true);
+    h.C = mptr(k, w->R, 0);
+    h.sC = k.stride;
+    h.batch = md;
+    h.active = w->mask1;
+    STCHK(run_gemm(k, h));
+    if (md > w->Q.count || md > w->R.count || md > w->S3.count)
+      return fail(c, DMPT_ERR_ARG, "internal: sym batch too large");
+    uint16_t* pl[3];
+    planes_of(k, w->S3, 0, pl);
+    HIPCHK(c, (sym_combine<T, T>((const T*)mptr(k, w->Q, 0), k.Np, k.stride, k.N, k.Np, 1.0, nullptr, 0,
+                                 (T*)mptr(k, w->S3, 0), k.Np, k.stride, pl, k.np, md, c->stream,
+                                 (const T*)mptr(k, w->R, 0), 1.0)));
+  }
+  // ---- order 0
+  if (k.chain & kLoad01) {
     // the order-0 chain of this mu0 is stored: Y0 = its solution at this step
     STCHK(st_load<T>(k, w->D0, 0, step, 0, 0.0, 0));
   } else {
     STCHK(solve_order0<T>(k, step));
-    if (k.chain == 1) STCHK(st_save<T>(k, w->D0, 0, step, 0));
+    if (k.chain & kSave01) STCHK(st_save<T>(k, w->D0, 0, step, 0));
   }
   // ---- order 1: T' Y1 = 2 D1 - 4 S1 Y0; transposed: rhs^T = 2 D1 - 4 Y0 S1
-  if (order >= 1 && k.chain == 2) {
+  if (order >= 1 && (k.chain & kLoad01)) {
     // the order-1 solutions are linear in mu1: Y1 = Y1(mu1 = 0) - mu1 Y_J
     for (int z = 0; z < md; ++z) STCHK(st_load<T>(k, w->D1, z, step, 1 + z, k.cmu[z], k.cj));
   } else if (order >= 1) {
@@ -809,29 +882,17 @@ dmpt_status recursion_step(const Call& k, int order, int d, int step) {
     STCHK(sum_gemm_partials(k, md, w->ref, 1, 0));
     if (k.traj && c->tj_valid >= 1)  // guess: this step's solution of the previous pass
       for (int z = 0; z < md; ++z) STCHK(tj_load<T>(k, w->D1, z, step, 1 + z));
-    G h;  // R -= U + 4 U S0  (guess U held in D1: the previous iterate or the stored one)
-    h.X = op(k, w->D1, 0, true);
-    h.Y = op(k, w->S0, 0, true);
-    h.Y.div = d;
-    h.C = mptr(k, w->R, 0);
-    h.sC = k.stride;
-    h.alpha = -4.0;
-    h.C1 = mptr(k, w->R, 0); h.sC1 = k.stride; h.beta1 = 1.0;
-    h.C2 = mptr(k, w->D1, 0); h.sC2 = k.stride; h.beta2 = -1.0;
-    h.W = mptr(k, w->R, 0); h.sW = k.stride;
-    h.batch = md;
-    h.active = w->mask1;
-    STCHK(run_gemm(k, h));
-    STCHK(sum_gemm_partials(k, md, w->rr, hs, 0));
-    STCHK(cg_solve<T>(k, w->D1, md, d, w->mask1));
-    STCHK(sym_inplace<T>(k, w->D1, 0, md, 0.5));
+    STCHK(solve_jet<T>(k, w->D1, md, d));
     if (k.traj)
       for (int z = 0; z < md; ++z) STCHK(tj_save<T>(k, w->D1, z, step, 1 + z));
-    if (k.chain == 1)
+    if (k.chain & kSave01)
       for (int z = 0; z < md; ++z) STCHK(st_save<T>(k, w->D1, z, step, 1 + z));
   }
   // ---- order 2: rhs^T = 2 D2 - 4 Y1 S1 - 4 Y0 S2
-  if (order >= 2) {
+  if (order >= 2 && (k.chain & kLoad2)) {
+    for (int z = 0; z < md; ++z)
+      STCHK(st_load<T>(k, w->D2, z, step, 2 + d + z, k.cmu[d + z], k.cj));
+  } else if (order >= 2) {
     G g;  // R = 2 D2 - 4 Y0 S2
     g.X = op(k, w->D0, 0, true);
     g.X.div = d;
@@ -857,24 +918,52 @@ dmpt_status recursion_step(const Call& k, int order, int d, int step) {
     STCHK(sum_gemm_partials(k, md, w->ref, 1, 0));
     if (k.traj && c->tj_valid >= 2)
       for (int z = 0; z < md; ++z) STCHK(tj_load<T>(k, w->D2, z, step, 1 + d + z));
-    G h;  // R -= U + 4 U S0 (guess U held in D2)
-    h.X = op(k, w->D2, 0, true);
-    h.Y = op(k, w->S0, 0, true);
-    h.Y.div = d;
-    h.C = mptr(k, w->R, 0);
-    h.sC = k.stride;
-    h.alpha = -4.0;
-    h.C1 = mptr(k, w->R, 0); h.sC1 = k.stride; h.beta1 = 1.0;
-    h.C2 = mptr(k, w->D2, 0); h.sC2 = k.stride; h.beta2 = -1.0;
-    h.W = mptr(k, w->R, 0); h.sW = k.stride;
-    h.batch = md;
-    h.active = w->mask1;
-    STCHK(run_gemm(k, h));
-    STCHK(sum_gemm_partials(k, md, w->rr, hs, 0));
-    STCHK(cg_solve<T>(k, w->D2, md, d, w->mask1));
-    STCHK(sym_inplace<T>(k, w->D2, 0, md, 0.5));
+    STCHK(solve_jet<T>(k, w->D2, md, d));
     if (k.traj)
       for (int z = 0; z < md; ++z) STCHK(tj_save<T>(k, w->D2, z, step, 1 + d + z));
+    if (k.chain & kSave2)
+      for (int z = 0; z < md; ++z) STCHK(st_save<T>(k, w->D2, z, step, 2 + d + z));
+  }
+  // ---- order 3: rhs^T = 2 D3 - 4 Y0 S3 - 4 Y1 S2 - 4 Y2 S1
+  if (order >= 3) {
+    G g;  // R = 2 D3 - 4 Y0 S3
+    g.X = op(k, w->D0, 0, true);
+    g.X.div = d;
+    g.Y = op(k, w->S3, 0, true);
+    g.C = mptr(k, w->R, 0);
+    g.sC = k.stride;
+    g.alpha = -4.0;
+    g.C1 = mptr(k, w->D3, 0); g.sC1 = k.stride; g.beta1 = 2.0;
+    g.batch = md;
+    g.active = w->mask1;
+    STCHK(run_gemm(k, g));
+    G g2;  // R -= 4 Y1 S2
+    g2.X = op(k, w->D1, 0, true);
+    g2.Y = op(k, w->S2, 0, true);
+    g2.C = mptr(k, w->R, 0);
+    g2.sC = k.stride;
+    g2.alpha = -4.0;
+    g2.C1 = mptr(k, w->R, 0); g2.sC1 = k.stride; g2.beta1 = 1.0;
+    g2.batch = md;
+    g2.active = w->mask1;
+    STCHK(run_gemm(k, g2));
+    G g3;  // R -= 4 Y2 S1, ||rhs||^2 -> ref
+    g3.X = op(k, w->D2, 0, true);
+    g3.Y = op(k, w->S1, 0, true);
+    g3.C = mptr(k, w->R, 0);
+    g3.sC = k.stride;
+    g3.alpha = -4.0;
+    g3.C1 = mptr(k, w->R, 0); g3.sC1 = k.stride; g3.beta1 = 1.0;
+    g3.W = mptr(k, w->R, 0); g3.sW = k.stride;
+    g3.batch = md;
+    g3.active = w->mask1;
+    STCHK(run_gemm(k, g3));
+    STCHK(sum_gemm_partials(k, md, w->ref, 1, 0));
+    if (k.traj && c->tj_valid >= 3)
+      for (int z = 0; z < md; ++z) STCHK(tj_load<T>(k, w->D3, z, step, 1 + 2 * d + z));
+    STCHK(solve_jet<T>(k, w->D3, md, d));
+    if (k.traj)
+      for (int z = 0; z < md; ++z) STCHK(tj_save<T>(k, w->D3, z, step, 1 + 2 * d + z));
   }
   return DMPT_OK;
 }
@@ -894,7 +983,7 @@ dmpt_status recursion_pass(const Call& k, const PassIn& in) {
 // traces; then one synchronisation and the values land in c->h_res.
 template <class T>
 dmpt_status finish_pass(const Call& k, const PassIn& in, double* P0, double* const* P1,
-                        double* const* P2) {
+                        double* const* P2, double* const* P3) {
   dmpt_ctx c = k.c;
   hipStream_t s = c->stream;
   double* shift = c->d_res + RES_HALF;  // device constant 1/2 for the P0 diagonal
@@ -905,10 +994,10 @@ dmpt_status finish_pass(const Call& k, const PassIn& in, double* P0, double* con
   HIPCHK(c, sum_partials(c->d_part, reduce_blocks(k.N * k.N), 1, c->d_res + RES_FRO, 1, 0, s));
   const int d = in.d;
   for (int ord = 1; ord <= in.order; ++ord) {
-    const Group& g = ord == 1 ? c->ws.D1 : c->ws.D2;
-    double* const* Pk = ord == 1 ? P1 : P2;
+    const Group& g = jet(&c->ws, ord);
+    double* const* Pk = ord == 1 ? P1 : (ord == 2 ? P2 : P3);
     for (int z = 0; z < d; ++z) {
-      const int slot = (ord == 1 ? 1 : 1 + d) + z;
+      const int slot = slot_of(ord, z, d);
       HIPCHK(c, (sym_combine<T, double>((const T*)mptr(k, g, z), k.Np, 0, k.N, k.Np, -0.5, nullptr,
                                         0, Pk[z], k.N, 0, nullptr, 0, 1, s)));
       HIPCHK(c, trace(Pk[z], k.N, 0, k.N, 1, c->d_res + RES_TR + slot, 1,
@@ -917,7 +1006,8 @@ dmpt_status finish_pass(const Call& k, const PassIn& in, double* P0, double* con
       if (in.H1[z]) {
         HIPCHK(c, dot_partials<double>(in.H1[z], 0, Pk[z], 0, k.N * k.N, 1, c->d_part, s));
         HIPCHK(c, sum_partials(c->d_part, reduce_blocks(k.N * k.N), 1,
-                               c->d_res + (ord == 1 ? RES_H1P1 : RES_H1P2) + z, 1, 0, s));
+                               c->d_res + (ord == 1 ? RES_H1P1 : (ord == 2 ? RES_H1P2 : RES_H1P3)) + z,
+                               1, 0, s));
       }
       if (ord == 2) {
         if (in.H2 && in.H2[z]) {
@@ -946,8 +1036,8 @@ dmpt_status check_common(dmpt_ctx c, int64_t N, const double* H0, double beta, i
 }
 
 dmpt_status check_dirs(dmpt_ctx c, int d, int order, const double* const* H1, const double* const* P1v,
-                       const double* const* P2v) {
-  if (order < 0 || order > 2) return fail(c, DMPT_ERR_ARG, "order must be 0, 1 or 2");
+                       const double* const* P2v, const double* const* P3v) {
+  if (order < 0 || order > 3) return fail(c, DMPT_ERR_ARG, "order must be 0, 1, 2 or 3");
   if (order == 0) return DMPT_OK;
   if (d < 1 || d > c->dirs_max || d > DMPT_MAX_DIRS)
     return fail(c, DMPT_ERR_ARG, "d must lie in [1, dirs_max]");
@@ -962,6 +1052,11 @@ dmpt_status check_dirs(dmpt_ctx c, int d, int order, const double* const* H1, co
     for (int i = 0; i < d; ++i)
       if (!P2v[i]) return fail(c, DMPT_ERR_ARG, "P2[i] is NULL");
   }
+  if (order >= 3) {
+    if (!P3v) return fail(c, DMPT_ERR_ARG, "P3 is NULL");
+    for (int i = 0; i < d; ++i)
+      if (!P3v[i]) return fail(c, DMPT_ERR_ARG, "P3[i] is NULL");
+  }
   return DMPT_OK;
 }
 
@@ -972,7 +1067,8 @@ dmpt_status scan_inputs(dmpt_ctx c, int64_t N, const PassIn& in, double* glo, do
   HIPCHK(c, nonfinite_scan(in.H0, N, N, c->d_flag, s));
   for (int o = 1; o <= in.order; ++o)
     for (int z = 0; z < in.d; ++z) {
-      const double* h = o == 1 ? in.H1[z] : (in.H2 ? in.H2[z] : nullptr);
+      const double* h = o == 1 ? in.H1[z]
+                               : (o == 2 ? (in.H2 ? in.H2[z] : nullptr) : (in.H3 ? in.H3[z] : nullptr));
       if (h) HIPCHK(c, nonfinite_scan(h, N, N, c->d_flag, s));
     }
   HIPCHK(c, gershgorin(in.H0, N, c->d_gersh, s));
@@ -1029,6 +1125,7 @@ void fill_stats(dmpt_ctx c, const PassIn& in, dmpt_stats* st, int newton, double
       st->tr_h1p2[z] = c->h_res[RES_H1P2 + z];
       st->tr_h2p0[z] = c->h_res[RES_H2P0 + z];
     }
+    if (in.order >= 3) st->tr_h1p3[z] = c->h_res[RES_H1P3 + z];
   }
   st->idempotency = c->h_res[RES_TR] - c->h_res[RES_FRO];
   st->mfma_flops = c->mfma_flops;
@@ -1038,15 +1135,16 @@ void fill_stats(dmpt_ctx c, const PassIn& in, dmpt_stats* st, int newton, double
 
 template <class T>
 dmpt_status one_pass(const Call& k, const PassIn& in, double* P0, double* const* P1,
-                     double* const* P2) {
+                     double* const* P2, double* const* P3) {
   STCHK(recursion_pass<T>(k, in));
-  return finish_pass<T>(k, in, P0, P1, P2);
+  return finish_pass<T>(k, in, P0, P1, P2, P3);
 }
 
 dmpt_status pass_dispatch(const Call& k, const PassIn& in, double* P0, double* const* P1,
-                          double* const* P2) {
-  if (k.f64) return one_pass<double>(k, in, P0, P1, P2);
-  return one_pass<float>(k, in, P0, P1, P2);
+                          double* const* P2, double* const* P3 = nullptr) {
+  if (in.order >= 3 && !P3) return fail(k.c, DMPT_ERR_ARG, "internal: P3 missing");
+  if (k.f64) return one_pass<double>(k, in, P0, P1, P2, P3);
+  return one_pass<float>(k, in, P0, P1, P2, P3);
 }
 
 // Commutator ||H0 P0 - P0 H0||_F and output asymmetry (FP64 checks).
@@ -1481,7 +1579,8 @@ void occupation_error(const double* res, int d, int order, double Ne, int64_t N,
 // *settled: whether mu0 met the tolerance (or its noise floor).
 dmpt_status linear_orders(Call& k, const PassIn& base, int64_t N, int order, double* mu,
                           double mu_lo, double mu_hi, double Ne, double tol, double* P0,
-                          double* const* P1, double* const* P2, bool* settled, int* passes) {
+                          double* const* P1, double* const* P2, double* const* P3, bool* settled,
+                          int* passes) {
   dmpt_ctx c = k.c;
   hipStream_t s = c->stream;
   const int d = base.d;
@@ -1496,13 +1595,16 @@ dmpt_status linear_orders(Call& k, const PassIn& base, int64_t N, int order, dou
   std::vector<double> m1(2 + 2 * DMPT_MAX_DIRS, 0.0);
   m1[1 + d] = -1.0;  // D0^(1) = c (0 - (-1) I) = c I: the response to H1 = I
   PassIn in1{base.H0, d + 1, h1x.data(), nullptr, base.beta, base.n, 1, m1.data()};
-  const bool keep = order >= 2 && c->opt.schedule == 1 && ensure_chain(c, base.n, d + 1, k.Np);
+  // chain store: order 0, order 1 (d + J), order 2 (d, when order 3 follows)
+  const int cs = 2 + d + (order >= 3 ? d : 0);
+  const bool keep = order >= 2 && c->opt.schedule == 1 && ensure_chain(c, base.n, cs, k.Np);
+  k.cs = cs;
+  k.cj = 1 + d;
   double trJ = 0.0, prev = INFINITY;
   constexpr int kMaxPasses = 4;
   for (int a = 0; a < kMaxPasses; ++a) {
     m1[0] = mu[0];
-    k.chain = keep ? 1 : 0;
-    k.cj = d + 1;
+    k.chain = keep ? kSave01 : 0;
     STCHK(pass_dispatch(k, in1, P0, p1x.data(), nullptr));
     k.chain = 0;
     *passes += 1;
@@ -1526,11 +1628,10 @@ dmpt_status linear_orders(Call& k, const PassIn& base, int64_t N, int order, dou
     HIPCHK(c, axpby<double>(c->jout, 0, P1[z], 0, nn, 1, -mu[1 + z], 1.0, none, 0, 0, s));
   }
   if (order >= 2) {
-    std::vector<double> m2(1 + 2 * DMPT_MAX_DIRS, 0.0);
+    std::vector<double> m2(1 + 3 * DMPT_MAX_DIRS, 0.0);
     for (int i = 0; i <= d; ++i) m2[i] = mu[i];
     PassIn in2{base.H0, d, base.H1, base.H2, base.beta, base.n, 2, m2.data()};
-    k.chain = keep ? 2 : 0;
-    k.cj = d + 1;
+    k.chain = keep ? (kLoad01 | (order >= 3 ? kSave2 : 0)) : 0;
     k.cmu = mu + 1;
     STCHK(pass_dispatch(k, in2, P0, P1, P2));
     k.chain = 0;
@@ -1541,15 +1642,34 @@ dmpt_status linear_orders(Call& k, const PassIn& base, int64_t N, int order, dou
       HIPCHK(c, axpby<double>(c->jout, 0, P2[z], 0, nn, 1, -mu[1 + d + z], 1.0, none, 0, 0, s));
     }
   }
+  if (order >= 3) {
+    // order 3 at the exact mu1, mu2 (mu3 = 0); the stored order-2 chain is
+    // affine in mu2 with the same slope: Y2 = Y2(mu2 = 0) - mu2 Y_J
+    std::vector<double> m3(1 + 3 * DMPT_MAX_DIRS, 0.0);
+    for (int i = 0; i <= 2 * d; ++i) m3[i] = mu[i];
+    PassIn in3{base.H0, d, base.H1, base.H2, base.beta, base.n, 3, m3.data()};
+    in3.H3 = base.H3;
+    k.chain = keep ? (kLoad01 | kLoad2) : 0;
+    k.cmu = mu + 1;
+    STCHK(pass_dispatch(k, in3, P0, P1, P2, P3));
+    k.chain = 0;
+    k.cmu = nullptr;
+    *passes += 1;
+    for (int z = 0; z < d; ++z) {
+      mu[1 + 2 * d + z] = c->h_res[RES_TR + 1 + 2 * d + z] / trJ;
+      HIPCHK(c, axpby<double>(c->jout, 0, P3[z], 0, nn, 1, -mu[1 + 2 * d + z], 1.0, none, 0, 0, s));
+    }
+  }
   // traces and response traces of the returned (corrected) matrices
   for (int o = 1; o <= order; ++o)
     for (int z = 0; z < d; ++z) {
-      double* Pk = o == 1 ? P1[z] : P2[z];
-      const int slot = (o == 1 ? 1 : 1 + d) + z;
+      double* Pk = o == 1 ? P1[z] : (o == 2 ? P2[z] : P3[z]);
+      const int slot = slot_of(o, z, d);
       HIPCHK(c, trace(Pk, N, 0, N, 1, c->d_res + RES_TR + slot, 1, c->d_res + RES_ATR + slot, s));
       HIPCHK(c, dot_partials<double>(base.H1[z], 0, Pk, 0, nn, 1, c->d_part, s));
       HIPCHK(c, sum_partials(c->d_part, reduce_blocks(nn), 1,
-                             c->d_res + (o == 1 ? RES_H1P1 : RES_H1P2) + z, 1, 0, s));
+                             c->d_res + (o == 1 ? RES_H1P1 : (o == 2 ? RES_H1P2 : RES_H1P3)) + z, 1,
+                             0, s));
     }
   HIPCHK(c, hipMemcpyAsync(c->h_res, c->d_res, RES_MISC * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
@@ -1674,8 +1794,8 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
   bool ok = group(c->ws.D0, 1, true) && group(c->ws.S0, 1, true) && group(c->ws.R, dm, false) &&
             group(c->ws.P, dm, true) && group(c->ws.Q, dm, false) && group(c->U0, 1, true);
   if (ok && dd > 0)
-    ok = group(c->ws.D1, dd, true) && group(c->ws.D2, dd, true) && group(c->ws.S1, dd, true) &&
-         group(c->ws.S2, dd, true);
+    ok = group(c->ws.D1, dd, true) && group(c->ws.D2, dd, true) && group(c->ws.D3, dd, true) &&
+         group(c->ws.S1, dd, true) && group(c->ws.S2, dd, true) && group(c->ws.S3, dd, true);
   if (!ok) return bail(DMPT_ERR_NOMEM, "device workspace allocation failed");
   c->hstride = c->opt.max_cg + 2;
   c->ws.rr = (double*)alloc(sizeof(double) * dm * 512);
@@ -1712,8 +1832,8 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
       return true;
     };
     if (!(zero(c->ws.D0) && zero(c->ws.S0) && zero(c->ws.R) && zero(c->ws.P) && zero(c->ws.Q) &&
-          zero(c->U0) && zero(c->ws.D1) &&
-          zero(c->ws.D2) && zero(c->ws.S1) && zero(c->ws.S2)))
+          zero(c->U0) && zero(c->ws.D1) && zero(c->ws.D2) && zero(c->ws.D3) && zero(c->ws.S1) &&
+          zero(c->ws.S2) && zero(c->ws.S3)))
       return bail(DMPT_ERR_HIP, "workspace clear failed");
     if (set_values(nullptr, 0, 0, c->d_res + RES_HALF, 0.5, 1, c->stream) != hipSuccess)
       return bail(DMPT_ERR_HIP, "constant init failed");
@@ -1874,14 +1994,17 @@ dmpt_status dmpt_fermi_recursion(dmpt_ctx c, int64_t N, const double* H0, double
   if (!P0) return fail(c, DMPT_ERR_ARG, "P0 is NULL");
   if (!std::isfinite(mu)) return fail(c, DMPT_ERR_ARG, "mu must be finite");
   double m[1] = {mu};
-  return dmpt_response(c, N, H0, 0, nullptr, nullptr, beta, n, 0, m, P0, nullptr, nullptr, st);
+  return dmpt_response(c, N, H0, 0, nullptr, nullptr, nullptr, beta, n, 0, m, P0, nullptr, nullptr,
+                       nullptr, st);
 }
 
 dmpt_status dmpt_response(dmpt_ctx c, int64_t N, const double* H0, int d, const double* const* H1,
-                          const double* const* H2, double beta, int n, int order, const double* mu,
-                          double* P0, double* const* P1, double* const* P2, dmpt_stats* st) {
+                          const double* const* H2, const double* const* H3, double beta, int n,
+                          int order, const double* mu, double* P0, double* const* P1,
+                          double* const* P2, double* const* P3, dmpt_stats* st) {
   STCHK(check_common(c, N, H0, beta, n));
-  STCHK(check_dirs(c, d, order, H1, (const double* const*)P1, (const double* const*)P2));
+  STCHK(check_dirs(c, d, order, H1, (const double* const*)P1, (const double* const*)P2,
+                   (const double* const*)P3));
   if (!P0) return fail(c, DMPT_ERR_ARG, "P0 is NULL");
   if (!mu) return fail(c, DMPT_ERR_ARG, "mu is NULL");
   const int nmu = 1 + order * (order >= 1 ? d : 0);
@@ -1891,13 +2014,14 @@ dmpt_status dmpt_response(dmpt_ctx c, int64_t N, const double* H0, int d, const 
   const auto t0 = std::chrono::steady_clock::now();
   reset_stats(c);
   PassIn in{H0, order >= 1 ? d : 0, H1, H2, beta, n, order, mu};
+  in.H3 = H3;
   double glo, ghi;
   STCHK(scan_inputs(c, N, in, &glo, &ghi));
   const double emax = std::max(std::fabs(glo - mu[0]), std::fabs(ghi - mu[0]));
   if (beta * emax >= std::ldexp(1.0, n + 1))
     return fail(c, DMPT_ERR_RANGE, "beta * max|eps - mu| >= 2^(n+1): the recursion's start leaves [0, 1]");
   Call k = make_call(c, N, true);
-  STCHK(pass_dispatch(k, in, P0, P1, P2));
+  STCHK(pass_dispatch(k, in, P0, P1, P2, P3));
   double occ = 0;
   for (int i = 1; i < nmu; ++i) occ += std::fabs(c->h_res[RES_TR + i]);
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1909,11 +2033,12 @@ dmpt_status dmpt_response(dmpt_ctx c, int64_t N, const double* H0, int d, const 
 }
 
 dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const double* const* H1,
-                           const double* const* H2, double beta, double Ne, int n, int order,
-                           double* mu_inout, double* P0, double* const* P1, double* const* P2,
-                           dmpt_stats* st) {
+                           const double* const* H2, const double* const* H3, double beta, double Ne,
+                           int n, int order, double* mu_inout, double* P0, double* const* P1,
+                           double* const* P2, double* const* P3, dmpt_stats* st) {
   STCHK(check_common(c, N, H0, beta, n));
-  STCHK(check_dirs(c, d, order, H1, (const double* const*)P1, (const double* const*)P2));
+  STCHK(check_dirs(c, d, order, H1, (const double* const*)P1, (const double* const*)P2,
+                   (const double* const*)P3));
   if (!P0) return fail(c, DMPT_ERR_ARG, "P0 is NULL");
   if (!mu_inout) return fail(c, DMPT_ERR_ARG, "mu_inout is NULL");
   if (!(Ne > 0.0 && Ne < (double)N)) return fail(c, DMPT_ERR_ARG, "Ne must lie in (0, N)");
@@ -1922,11 +2047,12 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
   reset_stats(c);
   const int dd = order >= 1 ? d : 0;
   const int nmu = 1 + order * dd;
-  std::vector<double> mu(1 + 2 * DMPT_MAX_DIRS, 0.0);
+  std::vector<double> mu(1 + 3 * DMPT_MAX_DIRS, 0.0);
   for (int i = 0; i < nmu; ++i) mu[i] = mu_inout[i];
   for (int i = 1; i < nmu; ++i)
     if (std::isnan(mu[i])) mu[i] = 0.0;
   PassIn in{H0, dd, H1, H2, beta, n, order, mu.data()};
+  in.H3 = H3;
   double glo, ghi;
   STCHK(scan_inputs(c, N, in, &glo, &ghi));
   if (beta * (ghi - glo) >= std::ldexp(1.0, n + 1))
@@ -1956,12 +2082,12 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
     double tol_cg, tol_occ;
   };
   // linear schedule: the loop converges mu0 with order-0 passes, then one
-  // pass per order (with the response J to H1 = I) fixes mu1 and mu2 exactly
+  // pass per order (with the response J to H1 = I) fixes mu1, mu2, mu3 exactly
   const bool linear = c->opt.schedule >= 1 && order >= 1;
   const int loop_order = linear ? 0 : order;
   // trajectory members: order 0, order 1 (plus the identity direction of the
-  // linear schedule), order 2
-  const int jets = linear ? std::max(2 + dd, 1 + 2 * dd) : 1 + 2 * dd;
+  // linear schedule), orders 2 and 3
+  const int jets = linear ? std::max(2 + dd, 1 + order * dd) : 1 + order * dd;
   if (c->opt.warm_traj && ensure_traj(c, n, jets, k.Np)) {
     k.traj = true;
     k.jets = jets;
@@ -1989,7 +2115,7 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
     k.np = engine_planes(P.eng);
     k.tol_cg = P.tol_cg;
     in.order = stage_order;
-    STCHK(pass_dispatch(k, in, P0, P1, P2));
+    STCHK(pass_dispatch(k, in, P0, P1, P2, P3));
     const double* r = c->h_res;
     if (!std::isfinite(r[RES_TR]) || !std::isfinite(r[RES_FRO]))
       return fail(c, DMPT_ERR_NONFINITE, "non-finite trace in the Newton loop");
@@ -2052,7 +2178,7 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
     k.tol_cg = P.tol_cg;
     bool settled = false;
     int passes = 0;
-    STCHK(linear_orders(k, in, N, order, mu.data(), mu_lo, mu_hi, Ne, P.tol_occ, P0, P1, P2,
+    STCHK(linear_orders(k, in, N, order, mu.data(), mu_lo, mu_hi, Ne, P.tol_occ, P0, P1, P2, P3,
                         &settled, &passes));
     it += passes;
     done = settled;
@@ -2076,7 +2202,7 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
   if (!c) return DMPT_ERR_ARG;
   if (nsys < 1 || !Ns || !H0s || !betas || !Nes || !mus || !P0s)
     return fail(c, DMPT_ERR_ARG, "batched: nsys >= 1 and non-NULL Ns, H0s, betas, Nes, mus, P0s");
-  if (order < 0 || order > 2) return fail(c, DMPT_ERR_ARG, "order must be 0, 1 or 2");
+  if (order < 0 || order > 2) return fail(c, DMPT_ERR_ARG, "batched order must be 0, 1 or 2");
   if (order >= 1 && (d < 1 || d > DMPT_MAX_DIRS))
     return fail(c, DMPT_ERR_ARG, "d must lie in [1, DMPT_MAX_DIRS]");
   if (order == 0) d = 0;
@@ -2398,8 +2524,8 @@ dmpt_status dmpt_backward(dmpt_ctx c, int64_t N, const double* H0, double beta, 
     // canonical mu0 first (order 0); G serves as the scratch P0
     dmpt_stats s0;
     double m[1] = {NAN};
-    const dmpt_status r = dmpt_mu_newton(c, N, H0, 0, nullptr, nullptr, beta, Ne, n, 0, m, G, nullptr,
-                                         nullptr, &s0);
+    const dmpt_status r = dmpt_mu_newton(c, N, H0, 0, nullptr, nullptr, nullptr, beta, Ne, n, 0, m, G,
+                                         nullptr, nullptr, nullptr, &s0);
     if (r != DMPT_OK) return r;
     mu = m[0];
     newton = s0.newton_iters;

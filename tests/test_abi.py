@@ -50,8 +50,8 @@ def test_null_context_is_rejected(lib):
     from paper_1503_07037_amd import _lib as L
     s = L.Stats()
     assert lib.dmpt_fermi_recursion(None, 4, None, 1.0, 0.0, 10, None, ctypes.byref(s)) == L.DMPT_ERR_ARG
-    assert lib.dmpt_mu_newton(None, 4, None, 0, None, None, 1.0, 2.0, 10, 0, None, None, None, None,
-                              None) == L.DMPT_ERR_ARG
+    assert lib.dmpt_mu_newton(None, 4, None, 0, None, None, None, 1.0, 2.0, 10, 0, None, None, None,
+                              None, None, None) == L.DMPT_ERR_ARG
     assert lib.dmpt_backward(None, 4, None, 1.0, 2.0, 10, None, None, None, None) == L.DMPT_ERR_ARG
     assert lib.dmpt_finalize(None) == L.DMPT_OK
     assert lib.dmpt_last_error(None)

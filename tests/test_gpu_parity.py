@@ -80,6 +80,72 @@ def test_response_at_fixed_mu_fp64(dm, order):
     assert e0 < 1e-12 and e1 < 1e-10 and e2 < 1e-10, (e0, e1, e2)
 
 
+def _rel(gpu, ref):
+    return max(float(np.abs(g.cpu().numpy() - r).max()) / float(np.abs(r).max()) for g, r in zip(gpu, ref))
+
+
+def test_response_third_order_at_fixed_mu_fp64(dm):
+    """Algorithm 1's fourth solve line at a fixed mu jet (H2, H3 partly zero) against the oracle."""
+    print("case response fp64 order=3", flush=True)
+    N, n, beta = 160, 18, 8.0
+    rng = np.random.default_rng(31)
+    h0 = workloads.chain_1d(N, 3)
+    h1 = [np.diag(np.arange(N) - N / 2.0) / N, _sym(rng, N, 0.1)]
+    h2 = [_sym(rng, N, 0.05), None]
+    h3 = [None, _sym(rng, N, 0.04)]
+    mu = [0.02, 0.3, -0.1, 0.05, 0.2, -0.15, 0.1]
+    ref = oracle.response(h0, h1, h2, beta, n, (mu[0], mu[1:3], mu[3:5], mu[5:7]), order=3, h3s=h3)
+    with dm.Context(N, dirs_max=2, prec="fp64") as ctx:
+        r = ctx.response(T(h0), [T(h) for h in h1], [T(h2[0]), None], beta=beta, n=n, order=3, mu=mu,
+                         H3=[None, T(h3[1])])
+    P0, P1, P2, st = r
+    e0, e1, e2 = errs(P0, P1, P2, ref)
+    e3 = _rel(r.P3, ref["P3"])
+    print(f"  errs {e0:.2e} {e1:.2e} {e2:.2e} {e3:.2e}")
+    assert e0 < 1e-12 and e1 < 1e-10 and e2 < 1e-10 and e3 < 1e-10, (e0, e1, e2, e3)
+    assert abs(st["trP"][5] - float(np.trace(ref["P3"][0]))) < 1e-9 * float(np.abs(ref["P3"][0]).max()) * N
+
+
+@pytest.mark.parametrize("schedule", [1, 2, 0])
+def test_third_order_canonical_fp64(dm, schedule):
+    """Canonical orders 0..3 (mu1, mu2, mu3 from Tr P^(k) = 0), ragged N, two directions."""
+    print(f"case canonical fp64 order=3 schedule={schedule}", flush=True)
+    N, n, beta, Ne = 200, 20, 10.0, 97.0
+    rng = np.random.default_rng(32)
+    h0 = workloads.banded(N, 5, bandwidth=16, decay=6.0)
+    h1 = [np.diag(np.arange(N) % 9 - 4.0), np.diag(np.cos(0.3 * np.arange(N)))]
+    h2 = [_sym(rng, N, 0.03), None]
+    h3 = [None, _sym(rng, N, 0.02)]
+    ref = oracle.canonical_response(h0, h1, h2, beta, Ne, n, order=3, h3s=h3)
+    with dm.Context(N, dirs_max=2, prec="fp64", schedule=schedule) as ctx:
+        r = ctx.mu_newton(T(h0), [T(h) for h in h1], [T(h2[0]), None], beta=beta, Ne=Ne, n=n,
+                          order=3, H3=[None, T(h3[1])])
+    P0, P1, P2, mu, st = r
+    e0, e1, e2 = errs(P0, P1, P2, ref)
+    e3 = _rel(r.P3, ref["P3"])
+    print(f"  errs {e0:.2e} {e1:.2e} {e2:.2e} {e3:.2e} newton={st['newton_iters']}")
+    assert e0 < 1e-10 and e1 < 1e-10 and e2 < 1e-10 and e3 < 1e-10, (e0, e1, e2, e3)
+    for z in range(2):
+        assert abs(mu[5 + z] - ref["mu3"][z]) < 1e-9 * max(1.0, abs(ref["mu3"][z]))
+        assert abs(st["tr_h1p3"][z] - ref["tr_h1p3"][z]) < 1e-9 * max(1.0, abs(ref["tr_h1p3"][z]))
+
+
+def test_third_order_canonical_bf16x6(dm):
+    """Third order through the 6-product split with FP64 slice sums: <= 1e-6 (normalised)."""
+    print("case canonical bf16x6 order=3", flush=True)
+    c = workloads.config("chain128")
+    h3 = [_sym(np.random.default_rng(33), c["N"], 0.02)]
+    ref = oracle.canonical_response(c["H0"], c["H1"], None, c["beta"], c["Ne"], c["n"], order=3, h3s=h3)
+    with dm.Context(c["N"], dirs_max=1, prec="bf16x6") as ctx:
+        r = ctx.mu_newton(T(c["H0"]), [T(h) for h in c["H1"]], None, beta=c["beta"], Ne=c["Ne"],
+                          n=c["n"], order=3, H3=[T(h3[0])])
+    P0, P1, P2, mu, st = r
+    e0, e1, e2 = errs(P0, P1, P2, ref)
+    e3 = _rel(r.P3, ref["P3"])
+    print(f"  errs {e0:.2e} {e1:.2e} {e2:.2e} {e3:.2e}")
+    assert e0 < 1e-6 and e1 < 1e-6 and e2 < 1e-6 and e3 < 1e-6, (e0, e1, e2, e3)
+
+
 # ------------------------------------------------------------------ canonical
 
 @pytest.fixture(scope="module")

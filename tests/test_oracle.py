@@ -461,9 +461,9 @@ def test_third_order_kernels_bruteforce():
     X = _sym(rng, n)
     Y = _sym(rng, n)
     F1 = o.dd1(e[:, None], e[None, :], beta, M)
-    T2 = o.dmpt_oracle._t2(e, F1, X, Y, beta, M, 1e-5)
-    Q = o.dmpt_oracle._t2(e, F1, X, X, beta, M, 1e-5)
-    T3 = o.dmpt_oracle._t3(e, F1, X, Q, beta, M, 1e-5)
+    T2 = o.dmpt_oracle._t2(e, F1, X, Y, beta, M, 1e-5, 1e-3)
+    Q = o.dmpt_oracle._t2(e, F1, X, X, beta, M, 1e-5, 1e-3)
+    T3 = o.dmpt_oracle._t3(e, F1, X, Q, beta, M, 1e-5, 1e-3)
     ref2 = np.zeros((n, n))
     ref3 = np.zeros((n, n))
     for i in range(n):
