@@ -230,6 +230,21 @@ typedef struct {
 dmpt_status dmpt_profile(dmpt_ctx ctx, int enable);
 dmpt_status dmpt_profile_get(dmpt_ctx ctx, dmpt_profile_data* out);
 
+/* Change of basis for a non-orthogonal basis set (Sec. II, self-consistent
+ * free energy response: F_perp = Z^T F Z, D = Z D_perp Z^T, with Z the
+ * inverse factor of the overlap, Z^T S Z = I).
+ *   mode 0: B = Z^T A Z  (an operator into the orthogonalised basis)
+ *   mode 1: B = Z A Z^T  (a density matrix or response back to the basis)
+ * Z: N x N device FP64, row major, any inverse factor (need not be
+ * triangular); A: N x N device FP64, used as sym(A); B: N x N device FP64
+ * output, symmetrised; B must not alias A or Z.  Two FP64 MFMA products on
+ * the context's workspace; not available in an FP32 context
+ * (DMPT_ERR_UNSUPPORTED).  For a restricted (two electrons per state)
+ * calculation with 2 Tr[D S] = Ne the orthogonalised problem has
+ * Tr P_perp = Ne / 2. */
+dmpt_status dmpt_congruence(dmpt_ctx ctx, int64_t N, const double* Z, const double* A, double* B,
+                            int mode, dmpt_stats* st);
+
 /* Time the matrix-product kernel alone: `reps` products C = X Y^T of size N
  * (N <= n_max; X, Y, C are workspace matrices filled with a fixed pattern)
  * in precision `prec` with output tile edge `tile` (0: the library's

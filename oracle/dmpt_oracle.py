@@ -44,7 +44,7 @@ import numpy as np
 __all__ = [
     "phi", "phi_pade", "phi_derivs", "phi_derivs5", "fermi_dirac", "dd1", "dd2", "dd3",
     "mu_canonical", "eig", "density", "response", "canonical_response",
-    "adjoint_grad", "entropy", "omega", "range_ok",
+    "adjoint_grad", "entropy", "omega", "range_ok", "nonorthogonal_response",
 ]
 
 
@@ -541,6 +541,22 @@ def adjoint_grad(h0, beta, Ne, M, A, eigh=None):
     """
     r = canonical_response(h0, [np.asarray(A)], None, beta, Ne, M, order=1, eigh=eigh)
     return r["P1"][0]
+
+
+def nonorthogonal_response(f0, f1s, f2s, z, beta, Ne, M, order=2):
+    """Canonical response in a non-orthogonal basis (Sec. II, self-consistent free energy response).
+
+    With Z the inverse factor of the overlap (Z^T S Z = I) the operators are
+    taken to the orthogonalised basis, F_perp = Z^T F Z, the canonical problem
+    is solved there with Tr P_perp = Ne, and D^(k) = Z P^(k) Z^T.
+    Returns a dict with D0, D1, D2 (lists) and the mu jet.
+    """
+    to = lambda f: None if f is None else z.T @ (0.5 * (f + f.T)) @ z
+    r = canonical_response(to(f0), [to(f) for f in f1s],
+                           None if f2s is None else [to(f) for f in f2s], beta, Ne, M, order=order)
+    back = lambda p: z @ p @ z.T
+    return dict(D0=back(r["P0"]), D1=[back(p) for p in r["P1"]], D2=[back(p) for p in r["P2"]],
+                mu0=r["mu0"], mu1=r["mu1"], mu2=r["mu2"])
 
 
 # ----------------------------------------------------------------------------

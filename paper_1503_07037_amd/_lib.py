@@ -78,6 +78,7 @@ EXPORTS = [
     "dmpt_default_options", "dmpt_init", "dmpt_finalize", "dmpt_last_error", "dmpt_set_options",
     "dmpt_fermi_recursion", "dmpt_response", "dmpt_mu_newton", "dmpt_mu_newton_batched",
     "dmpt_backward", "dmpt_profile", "dmpt_profile_get", "dmpt_bench_product", "dmpt_autotune",
+    "dmpt_congruence",
 ]
 
 _lib = None
@@ -117,6 +118,7 @@ def load(path=None):
     lib.dmpt_profile_get.argtypes = [P, ctypes.POINTER(ProfileData)]
     lib.dmpt_bench_product.argtypes = [P, I64, I, I, I, DP, DP]
     lib.dmpt_autotune.argtypes = [P, I64, ctypes.POINTER(I)]
+    lib.dmpt_congruence.argtypes = [P, I64, P, P, P, I, ctypes.POINTER(Stats)]
     for name in EXPORTS:
         if name not in ("dmpt_default_options", "dmpt_last_error"):
             getattr(lib, name).restype = ctypes.c_int

@@ -258,6 +258,35 @@ class Context:
                 _check_mat(h, N, f"{name}[{i}]")
         return _ptr_array(list(Hs))
 
+    def congruence(self, Z, A, mode, out=None):
+        """mode 0: Z^T A Z (into the orthogonalised basis); mode 1: Z A Z^T (back)."""
+        N = A.shape[0]
+        _check_mat(Z, N, "Z")
+        _check_mat(A, N, "A")
+        B = out if out is not None else self._empty(N)
+        s = L.Stats()
+        self._raise(self.lib.dmpt_congruence(self.h, N, _ptr(Z), _ptr(A), _ptr(B), int(mode),
+                                             ctypes.byref(s)))
+        return B
+
+    def mu_newton_nonorthogonal(self, F0, Z, F1=(), F2=None, beta=1.0, Ne=1.0, n=20, order=0,
+                                mu=None, F3=None):
+        """Canonical response in a non-orthogonal basis (Sec. II, self-consistent response).
+
+        The perturbed operators F^(k) are taken to the orthogonalised basis,
+        F_perp = Z^T F Z (Z^T S Z = I), solved there with Tr P_perp = Ne, and the
+        density matrix and its responses brought back, D^(k) = Z P^(k) Z^T.
+        Returns Response(D0, [D1], [D2], mu_jet, stats) with .P3 = [D3].
+        """
+        to = lambda X: None if X is None else self.congruence(Z, X, 0)
+        back = lambda X: self.congruence(Z, X, 1)
+        r = self.mu_newton(to(F0), [to(f) for f in F1], None if F2 is None else [to(f) for f in F2],
+                           beta=beta, Ne=Ne, n=n, order=order, mu=mu,
+                           H3=None if F3 is None else [to(f) for f in F3])
+        P0, P1, P2, m, st = r
+        return Response(back(P0), [back(p) for p in P1], [back(p) for p in P2], m, st,
+                        [back(p) for p in r.P3])
+
     def mu_newton_batched(self, H0s, H1s=None, betas=(), Nes=(), n=20, order=0, mus=None,
                           raise_on_error=True):
         """Canonical responses of many systems of uneven size in one batched solve.

@@ -1862,6 +1862,59 @@ dmpt_status dmpt_profile_get(dmpt_ctx c, dmpt_profile_data* out) {
   return DMPT_OK;
 }
 
+dmpt_status dmpt_congruence(dmpt_ctx c, int64_t N, const double* Z, const double* A, double* B,
+                            int mode, dmpt_stats* st) {
+  if (!c) return DMPT_ERR_ARG;
+  if (N < 1 || N > c->n_max) return fail(c, DMPT_ERR_ARG, "N must lie in [1, n_max]");
+  if (!Z || !A || !B) return fail(c, DMPT_ERR_ARG, "Z, A and B must be non-NULL");
+  if (mode != 0 && mode != 1) return fail(c, DMPT_ERR_ARG, "mode must be 0 (Z^T A Z) or 1 (Z A Z^T)");
+  if (B == A || B == Z) return fail(c, DMPT_ERR_ARG, "B must not alias A or Z");
+  if (c->esize != 8)
+    return fail(c, DMPT_ERR_UNSUPPORTED, "the basis change needs FP64 masters (not an FP32 context)");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, DMPT_ERR_HIP, "hipSetDevice failed");
+  const auto t0 = std::chrono::steady_clock::now();
+  reset_stats(c);
+  hipStream_t s = c->stream;
+  HIPCHK(c, set_values(c->d_flag, 0, 1, nullptr, 0.0, 0, s));
+  HIPCHK(c, nonfinite_scan(Z, N, N, c->d_flag, s));
+  HIPCHK(c, nonfinite_scan(A, N, N, c->d_flag, s));
+  HIPCHK(c, hipMemcpyAsync(c->h_int, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  if (c->h_int[0]) return fail(c, DMPT_ERR_NONFINITE, "non-finite value in Z or A");
+  Call k = make_call(c, N, false);
+  k.eng = Engine::F64;
+  k.np = 0;
+  const WS* w = k.w;
+  if (w->R.count < 2) return fail(c, DMPT_ERR_ARG, "internal: workspace too small");
+  double* zp = (double*)mptr(k, w->R, 0);  // Z^T (mode 0) or Z (mode 1), padded
+  double* ap = (double*)mptr(k, w->R, 1);  // sym(A), padded
+  HIPCHK(c, pad_copy(Z, N, N, zp, k.Np, mode == 0, s));
+  HIPCHK(c, (sym_combine<double, double>(A, N, 0, N, k.Np, 0.5, nullptr, 0, ap, k.Np, 0, nullptr, 0, 1,
+                                         s)));
+  // C = X Y^T: mode 0: W = Z^T A, B = W Z; mode 1: V = Z A, B = V Z^T
+  G g1;
+  g1.X = op(k, w->R, 0, false);
+  g1.Y = op(k, w->R, 1, false);
+  g1.C = mptr(k, w->Q, 0);
+  STCHK(run_gemm(k, g1));
+  G g2;
+  g2.X = op(k, w->Q, 0, false);
+  g2.Y = op(k, w->R, 0, false);
+  g2.C = mptr(k, w->P, 0);
+  STCHK(run_gemm(k, g2));
+  // B = its symmetric part (the exact result is symmetric)
+  HIPCHK(c, (sym_combine<double, double>((const double*)mptr(k, w->P, 0), k.Np, 0, N, k.Np, 0.5, nullptr,
+                                         0, B, N, 0, nullptr, 0, 1, s)));
+  HIPCHK(c, hipStreamSynchronize(s));
+  if (st) {
+    std::memset(st, 0, sizeof(*st));
+    st->mfma_flops = c->mfma_flops;
+    st->useful_flops = c->useful_flops;
+    st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return DMPT_OK;
+}
+
 dmpt_status dmpt_bench_product(dmpt_ctx c, int64_t N, dmpt_prec prec, int tile, int reps, double* ms,
                                double* tflops) {
   if (!c || !ms) return DMPT_ERR_ARG;

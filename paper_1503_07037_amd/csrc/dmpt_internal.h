@@ -179,6 +179,10 @@ hipError_t newton_update(const double* tr, int rs, const double* par, double* mu
                          int nsys, hipStream_t s);
 
 // Scan for non-finite values: flag |= any(!isfinite(x))
+// out (Np x Np) = in (N x N, leading dimension ldi) or its transpose, zero
+// outside the leading N x N block (no planes).
+hipError_t pad_copy(const double* in, int64_t ldi, int64_t N, double* out, int64_t Np, bool trans,
+                    hipStream_t s);
 hipError_t nonfinite_scan(const double* x, int64_t ld, int64_t N, int* flag, hipStream_t s);
 // Gershgorin interval of sym(H): out[0] = min_i (h_ii - r_i), out[1] = max_i (h_ii + r_i)
 hipError_t gershgorin(const double* h, int64_t N, double* out, hipStream_t s);

@@ -304,6 +304,27 @@ __global__ __launch_bounds__(kT) void k_spi(const T* __restrict__ x, T* __restri
   }
 }
 
+// out (Np x Np, ld Np) = in (N x N, ld ldi) or its transpose, zero outside
+// the leading N x N block; 32 x 32 tiles staged in LDS so both sides stay
+// row-contiguous.
+__global__ __launch_bounds__(kT) void k_pad_copy(const double* __restrict__ in, int64_t ldi, int64_t N,
+                                                 double* __restrict__ out, int64_t Np, int trans) {
+  __shared__ double t[32][33];
+  const int64_t bi = blockIdx.y, bj = blockIdx.x;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  // source tile: (bi, bj) or, transposed, (bj, bi)
+  const int64_t si = trans ? bj : bi, sj = trans ? bi : bj;
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t gi = si * 32 + r, gj = sj * 32 + tx;
+    t[r][tx] = (gi < N && gj < N) ? in[gi * ldi + gj] : 0.0;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t gi = bi * 32 + r, gj = bj * 32 + tx;
+    out[gi * Np + gj] = trans ? t[tx][r] : t[r][tx];
+  }
+}
+
 __global__ __launch_bounds__(kT) void k_nonfinite(const double* __restrict__ x, int64_t ld, int64_t N,
                                                   int* flag) {
   int bad = 0;
@@ -695,6 +716,14 @@ hipError_t newton_update(const double* tr, int rs, const double* par, double* mu
                          int nsys, hipStream_t s) {
   hipLaunchKernelGGL(k_newton, dim3((nsys + 63) / 64), dim3(64), 0, s, tr, rs, par, mu, shift, J, nk,
                      tol, final_stage, active, done, prev_err, brk, occ, passes, status, nsys);
+  return hipGetLastError();
+}
+
+hipError_t pad_copy(const double* in, int64_t ldi, int64_t N, double* out, int64_t Np, bool trans,
+                    hipStream_t s) {
+  if (Np % 32 != 0 || N > Np) return hipErrorInvalidValue;
+  const unsigned nb = (unsigned)(Np / 32);
+  hipLaunchKernelGGL(k_pad_copy, dim3(nb, nb), dim3(kT), 0, s, in, ldi, N, out, Np, trans ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -53,6 +53,7 @@ def test_null_context_is_rejected(lib):
     assert lib.dmpt_mu_newton(None, 4, None, 0, None, None, None, 1.0, 2.0, 10, 0, None, None, None,
                               None, None, None) == L.DMPT_ERR_ARG
     assert lib.dmpt_backward(None, 4, None, 1.0, 2.0, 10, None, None, None, None) == L.DMPT_ERR_ARG
+    assert lib.dmpt_congruence(None, 4, None, None, None, 0, None) == L.DMPT_ERR_ARG
     assert lib.dmpt_finalize(None) == L.DMPT_OK
     assert lib.dmpt_last_error(None)
 

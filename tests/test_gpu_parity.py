@@ -275,3 +275,43 @@ def test_newton_cap_reports_noconv(dm):
                                          raise_on_error=False)
     assert st["status"] == -4
     assert st["newton_iters"] == 1 and math.isfinite(st["trP"][0])
+
+
+# ------------------------------------------------------------------ non-orthogonal basis
+
+def test_congruence_fp64(dm):
+    """Z^T A Z and Z A Z^T on the FP64 engine against numpy (ragged N, general Z)."""
+    print("case congruence", flush=True)
+    N = 230
+    rng = np.random.default_rng(41)
+    A = _sym(rng, N)
+    Z = workloads.inverse_factor(workloads.overlap(N, 5))
+    with dm.Context(N, dirs_max=1, prec="fp64") as ctx:
+        B0 = ctx.congruence(T(Z), T(A), 0).cpu().numpy()
+        B1 = ctx.congruence(T(Z), T(A), 1).cpu().numpy()
+    r0, r1 = Z.T @ A @ Z, Z @ A @ Z.T
+    assert np.abs(B0 - r0).max() < 1e-13 * np.abs(r0).max()
+    assert np.abs(B1 - r1).max() < 1e-13 * np.abs(r1).max()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("bf16x6", 1e-6)])
+def test_nonorthogonal_canonical(dm, prec, tol):
+    """D^(k) = Z P^(k)(Z^T F Z) Z^T with Tr P_perp = Ne against the oracle (orders 0-2)."""
+    print(f"case non-orthogonal canonical {prec}", flush=True)
+    N, n, beta, Ne = 200, 20, 9.0, 93.0
+    rng = np.random.default_rng(42)
+    f0 = workloads.chain_1d(N, 12)
+    f1 = [np.diag(np.arange(N) - N / 2.0) / N]
+    f2 = [_sym(rng, N, 0.02)]
+    S = workloads.overlap(N, 6)
+    Z = workloads.inverse_factor(S)
+    ref = oracle.nonorthogonal_response(f0, f1, f2, Z, beta, Ne, n, order=2)
+    with dm.Context(N, dirs_max=1, prec=prec) as ctx:
+        D0, D1, D2, mu, st = ctx.mu_newton_nonorthogonal(T(f0), T(Z), [T(f1[0])], [T(f2[0])], beta=beta,
+                                                         Ne=Ne, n=n, order=2)
+    e0 = float(np.abs(D0.cpu().numpy() - ref["D0"]).max())
+    e1 = float(np.abs(D1[0].cpu().numpy() - ref["D1"][0]).max() / np.abs(ref["D1"][0]).max())
+    e2 = float(np.abs(D2[0].cpu().numpy() - ref["D2"][0]).max() / np.abs(ref["D2"][0]).max())
+    print(f"  errs {e0:.2e} {e1:.2e} {e2:.2e}")
+    assert e0 < tol and e1 < tol and e2 < tol
+    assert abs(float(np.trace(D0.cpu().numpy() @ S)) - Ne) < max(tol, 1e-9) * N

@@ -567,3 +567,48 @@ def test_planted_third_order_mistakes_are_caught(monkeypatch):
     monkeypatch.setattr(o.dmpt_oracle, "_t2", lambda e, F1, Xm, Ym, *a: orig2(e, F1, Xm, Xm, *a))
     bad = o.response(*args, order=3, h3s=[h3])
     assert np.max(np.abs(bad["P3"][0] - X[3])) > 1e-4 * np.max(np.abs(X[3]))
+
+
+# ---------------------------------------------------------------- non-orthogonal basis
+
+def test_nonorthogonal_basis_matches_generalized_eigenproblem():
+    """D = Z P(Z^T F Z) Z^T equals C phi(eps - mu) C^T from F C = S C eps (LAPACK sygvd),
+    is the same for two different inverse factors (Cholesky and Loewdin), and 2 Tr(D S) / 2 = Ne."""
+    import scipy.linalg as sl
+    n, M, beta, Ne = 40, 18, 9.0, 17.0
+    f0 = w.chain_1d(n, 8)
+    S = w.overlap(n, 3)
+    z1 = w.inverse_factor(S)
+    ev, U = np.linalg.eigh(S)
+    z2 = (U / np.sqrt(ev)) @ U.T                      # S^(-1/2), symmetric
+    r1 = o.nonorthogonal_response(f0, [], None, z1, beta, Ne, M, order=0)
+    r2 = o.nonorthogonal_response(f0, [], None, z2, beta, Ne, M, order=0)
+    eps, C = sl.eigh(f0, S)
+    mu = o.mu_canonical(eps, beta, M, Ne)
+    D = (C * o.phi(eps - mu, beta, M)) @ C.T
+    assert np.max(np.abs(r1["D0"] - D)) < 1e-12
+    assert np.max(np.abs(r2["D0"] - D)) < 1e-12
+    assert abs(np.trace(r1["D0"] @ S) - Ne) < 1e-11
+
+
+def test_nonorthogonal_first_order_finite_difference():
+    """D1 = dD/dlambda for F = F0 + lambda F1 in the non-orthogonal basis (generalized eigenproblem, FD)."""
+    import scipy.linalg as sl
+    n, M, beta, Ne = 30, 16, 7.0, 13.0
+    f0 = w.chain_1d(n, 9)
+    f1 = np.diag(np.arange(n) - n / 2.0) / n
+    S = w.overlap(n, 4)
+    z = w.inverse_factor(S)
+    r = o.nonorthogonal_response(f0, [f1], None, z, beta, Ne, M, order=1)
+
+    def d_of(lam):
+        eps, C = sl.eigh(f0 + lam * f1, S)
+        mu = o.mu_canonical(eps, beta, M, Ne)
+        return (C * o.phi(eps - mu, beta, M)) @ C.T
+
+    h = 1e-4
+    fd = (d_of(h) - d_of(-h)) / (2 * h)
+    assert np.max(np.abs(fd - r["D1"][0])) < 1e-7 * np.max(np.abs(r["D1"][0]))
+    # the congruence with Z^T instead of Z (a plausible slip) is visibly wrong
+    bad = o.nonorthogonal_response(f0, [f1], None, z.T, beta, Ne, M, order=1)
+    assert np.max(np.abs(bad["D0"] - d_of(0.0))) > 1e-3

@@ -6,7 +6,7 @@ so both the FP64 CPU oracle and the GPU library can be fed from it without
 sharing any computation.
 """
 from .tb import (chain_1d, cubic_lattice, banded, lattice_dipoles, grid_dipoles,
-                 batched_systems, config, CONFIGS)
+                 batched_systems, config, CONFIGS, overlap, inverse_factor)
 
 __all__ = ["chain_1d", "cubic_lattice", "banded", "lattice_dipoles", "grid_dipoles",
-           "batched_systems", "config", "CONFIGS"]
+           "batched_systems", "config", "CONFIGS", "overlap", "inverse_factor"]

@@ -23,7 +23,7 @@ import math
 import numpy as np
 
 __all__ = ["chain_1d", "cubic_lattice", "banded", "lattice_dipoles", "grid_dipoles",
-           "batched_systems", "config", "CONFIGS"]
+           "batched_systems", "config", "CONFIGS", "overlap", "inverse_factor"]
 
 
 def chain_1d(n, seed, onsite=1.0, hop=-1.0):
@@ -100,6 +100,25 @@ def banded(n, seed, bandwidth=256, sigma=0.3, decay=32.0, diag=2.0):
         h[i, i + k] = v
         h[i + k, i] = v
     return h
+
+
+def overlap(n, seed, strength=0.15, reach=3):
+    """Synthetic basis-set overlap S: unit diagonal, neighbours within `reach`
+    with strength * U(0.5, 1) * 0.5^(|i-j|-1), symmetric and diagonally dominant
+    (so positive definite) for strength < 1/4."""
+    rng = np.random.default_rng(seed)
+    s = np.eye(n)
+    for k in range(1, reach + 1):
+        v = strength * rng.uniform(0.5, 1.0, n - k) * 0.5 ** (k - 1)
+        s += np.diag(v, k) + np.diag(v, -k)
+    return s
+
+
+def inverse_factor(s):
+    """An inverse factor Z of the overlap, Z^T S Z = I: Z = L^-T for S = L L^T
+    (an input of the non-orthogonal problem, prepared on the host)."""
+    L = np.linalg.cholesky(s)
+    return np.linalg.inv(L).T
 
 
 def _lattice_for(n_target, lo=4, hi=24):
