@@ -56,6 +56,8 @@ def parse():
                     help="bf16x3: finish with the 6-product refinement passes (default on)")
     ap.add_argument("--acc64", type=int, default=1,
                     help="6-product products: FP32 per 32-wide k slice, FP64 across slices (default 1)")
+    ap.add_argument("--solver", default="cg", choices=["cg", "ns"],
+                    help="per-step solver: conjugate gradients or the Newton-Schulz shared inverse")
     ap.add_argument("--fp64-compare", action="store_true",
                     help="also time one FP64 solve of the same workload on the GPU")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -141,10 +143,11 @@ def accuracy(name, P0, P1, P2, mu):
 
 
 def fp64_gpu(dm, c, H0, H1, d, order):
-    """One FP64 canonical solve of the same workload (context created and warmed first)."""
+    """One FP64 canonical solve of the same workload on the GPU, with the faster FP64 solver
+    (the Newton-Schulz shared inverse: one product per right-hand side, no refinement needed)."""
     import torch
     N = c["N"]
-    ctx = dm.Context(N, dirs_max=d, prec="fp64")
+    ctx = dm.Context(N, dirs_max=d, prec="fp64", solver="ns")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     out = ctx.mu_newton(H0, H1, None, beta=c["beta"], Ne=c["Ne"], n=c["n"], order=order)
@@ -152,7 +155,7 @@ def fp64_gpu(dm, c, H0, H1, d, order):
     secs = time.perf_counter() - t0
     st = out[4]
     ctx.close()
-    return out, {"seconds": secs, "value": d / secs, "unit": "responses/s",
+    return out, {"seconds": secs, "value": d / secs, "unit": "responses/s", "solver": "ns",
                  "newton_iters": st["newton_iters"], "cg_iters_total": st["cg_iters_total"],
                  "mfma_tflops": st["mfma_flops"] / secs / 1e12}
 
@@ -180,7 +183,7 @@ def main():
     torch.cuda.synchronize()
     refine = (1 if args.prec == "bf16x3" else 0) if args.refine < 0 else args.refine
     ctx = dm.Context(N, dirs_max=d, prec=args.prec, tol_cg=args.tol_cg, tol_occ=args.tol_occ,
-                     refine=refine, acc64=args.acc64)
+                     refine=refine, acc64=args.acc64, solver=args.solver)
 
     def step():
         return ctx.mu_newton(H0, H1, None, beta=c["beta"], Ne=c["Ne"], n=c["n"], order=order)
@@ -222,6 +225,7 @@ def main():
                                f"beta={c['beta']}, n={c['n']}, Ne={c['Ne']}" if args.workload == "banded8192"
                    else args.workload,
                    "N": N, "dirs": d, "order": order, "beta": c["beta"], "n": c["n"],
+                   "solver": args.solver,
                    "precision": args.prec + ("+refine(bf16x6)" if refine else "")
                    + (", 6-product sums FP64 across 32-wide k slices" if args.acc64 and
                       (refine or args.prec == "bf16x6") else ""),

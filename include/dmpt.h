@@ -68,7 +68,10 @@ typedef enum {
 /* Per-step linear solver for T' Y = R, T' = I + 4 D^2 (2 T of Algorithm 1). */
 typedef enum {
   DMPT_SOLVER_CG = 0,  /* conjugate gradients, one product per iteration and right-hand side (Sec. II) */
-  DMPT_SOLVER_NS = 1   /* shared inverse of T' by Newton-Schulz, reused for every order (Sec. II remark) */
+  DMPT_SOLVER_NS = 1   /* shared inverse Z of T' by Newton-Schulz (four steps from the minimax linear
+                          start), reused for every order and direction (Sec. II remark): one product
+                          per right-hand side, plus one refinement step below FP64; single-system
+                          paths (the batched and adjoint paths keep CG) */
 } dmpt_solver;
 
 /* Initial guess of the conjugate-gradient solve. */

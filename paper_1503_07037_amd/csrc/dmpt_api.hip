@@ -46,6 +46,7 @@ struct Group {
 // system entry points use one system.
 struct WS {
   Group D0, D1, D2, D3, S0, S1, S2, S3, R, P, Q;
+  Group Zi;                      // T'^-1 of the current step (Newton-Schulz solver)
   double* rr = nullptr;          // CG <r,r> history [member][hstride]
   double* pq = nullptr;          // CG <p,Tp> history [member][hstride]
   double* ref = nullptr;         // ||rhs||^2 [member]
@@ -757,6 +758,99 @@ dmpt_status solve_order0(const Call& k, int step) {
   return DMPT_OK;
 }
 
+// ---------------------------------------------------------------- Newton-Schulz
+// Every system of a step has the same matrix T' = I + 4 S0 (Sec. II remark:
+// one inverse serves all orders), whose eigenvalues lie in [1, 2].  The
+// inverse Z is built from Z0 = (24 I - 8 T') / 17 = (16 I - 32 S0) / 17, the
+// linear polynomial in T' with the smallest max |1 - y p(y)| on [1, 2] (it
+// equioscillates at y = 1, 3/2, 2 with error 1/17), by
+// Z <- Z (2 I - T' Z): the error squares each time, 17^-16 after four
+// iterations.  Z is a polynomial in S0, so it commutes with T' and stays
+// symmetric; it is re-symmetrised after every iteration.  Single system only.
+constexpr int kNsIters = 4;
+
+template <class T>
+dmpt_status ns_inverse(const Call& k) {
+  dmpt_ctx c = k.c;
+  const WS* w = k.w;
+  hipStream_t s = c->stream;
+  if (k.m != 1) return fail(c, DMPT_ERR_ARG, "internal: Newton-Schulz runs on one system");
+  uint16_t* pz[3];
+  planes_of(k, w->Zi, 0, pz);
+  HIPCHK(c, scaled_plus_identity<T>((const T*)mptr(k, w->S0, 0), (T*)mptr(k, w->Zi, 0), k.N, k.Np,
+                                    16.0 / 17.0, -32.0 / 17.0, pz, k.np, s));
+  for (int it = 0; it < kNsIters; ++it) {
+    G g;  // M = T' Z = Z + 4 S0 Z  -> P[0] (with planes)
+    g.X = op(k, w->S0, 0, false);
+    g.Y = op(k, w->Zi, 0, false);
+    g.C = mptr(k, w->P, 0);
+    planes_of(k, w->P, 0, g.Cpl);
+    g.alpha = 4.0;
+    g.C1 = mptr(k, w->Zi, 0); g.beta1 = 1.0;
+    STCHK(run_gemm(k, g));
+    G h;  // R[0] = 2 Z - Z M
+    h.X = op(k, w->Zi, 0, false);
+    h.Y = op(k, w->P, 0, false);
+    h.C = mptr(k, w->R, 0);
+    h.alpha = -1.0;
+    h.C1 = mptr(k, w->Zi, 0); h.beta1 = 2.0;
+    STCHK(run_gemm(k, h));
+    HIPCHK(c, (sym_combine<T, T>((const T*)mptr(k, w->R, 0), k.Np, 0, k.N, k.Np, 0.5, nullptr, 0,
+                                 (T*)mptr(k, w->Zi, 0), k.Np, 0, pz, k.np, 1, s)));
+  }
+  return DMPT_OK;
+}
+
+// Solve with the shared inverse: the unknowns U (transposed solutions) of the
+// md members of group g from the right-hand sides rhs^T held in R:
+// U = R Z; with products below FP64 one refinement U += (R - U T') Z follows.
+template <class T>
+dmpt_status ns_solve(const Call& k, const Group& g, int md) {
+  const WS* w = k.w;
+  if (k.np > 0) {
+    // the products that formed R wrote its master only
+    uint16_t* pr[3];
+    planes_of(k, w->R, 0, pr);
+    if (!k.f64) return fail(k.c, DMPT_ERR_ARG, "internal: split planes need FP64 masters");
+    HIPCHK(k.c, split_planes((const double*)mptr(k, w->R, 0), k.nn, k.stride, pr, k.stride, k.np, md,
+                             k.c->stream));
+  }
+  G a;
+  a.X = op(k, w->R, 0, true);
+  a.Y = op(k, w->Zi, 0, true);
+  a.Y.div = md;
+  a.C = mptr(k, g, 0);
+  a.sC = k.stride;
+  planes_of(k, g, 0, a.Cpl);
+  a.batch = md;
+  STCHK(run_gemm(k, a));
+  if (k.eng != Engine::F64) {
+    G r;  // R -= U + 4 U S0
+    r.X = op(k, g, 0, true);
+    r.Y = op(k, w->S0, 0, true);
+    r.Y.div = md;
+    r.C = mptr(k, w->R, 0);
+    r.sC = k.stride;
+    planes_of(k, w->R, 0, r.Cpl);
+    r.alpha = -4.0;
+    r.C1 = mptr(k, w->R, 0); r.sC1 = k.stride; r.beta1 = 1.0;
+    r.C2 = mptr(k, g, 0); r.sC2 = k.stride; r.beta2 = -1.0;
+    r.batch = md;
+    STCHK(run_gemm(k, r));
+    G u;  // U += R Z
+    u.X = op(k, w->R, 0, true);
+    u.Y = op(k, w->Zi, 0, true);
+    u.Y.div = md;
+    u.C = mptr(k, g, 0);
+    u.sC = k.stride;
+    planes_of(k, g, 0, u.Cpl);
+    u.C1 = mptr(k, g, 0); u.sC1 = k.stride; u.beta1 = 1.0;
+    u.batch = md;
+    STCHK(run_gemm(k, u));
+  }
+  return sym_inplace<T>(k, g, 0, md, 0.5);
+}
+
 // Finish the solve of one jet order: R holds rhs^T (its norm in ref); with
 // the guess U in group g (the previous iterate or a stored one) form the
 // initial residual R -= U + 4 U S0, run CG and symmetrise the solution.
@@ -791,6 +885,8 @@ dmpt_status recursion_step(const Call& k, int order, int d, int step) {
   const int hs = k.c->hstride;
   const int md = k.m * d;
   STCHK(square0<T>(k));
+  const bool ns = c->opt.solver == DMPT_SOLVER_NS && k.m == 1 && !k.graph;
+  if (ns) STCHK(ns_inverse<T>(k));
   if (order >= 1) {
     // Q = D1 D0 -> S1 = Q + Q^T
     G g;
@@ -859,7 +955,16 @@ dmpt_status recursion_step(const Call& k, int order, int d, int step) {
     // the order-0 chain of this mu0 is stored: Y0 = its solution at this step
     STCHK(st_load<T>(k, w->D0, 0, step, 0, 0.0, 0));
   } else {
-    STCHK(solve_order0<T>(k, step));
+    if (ns) {
+      // R = 2 D0 (with planes), D0 = R Z
+      uint16_t* pr[3];
+      planes_of(k, w->R, 0, pr);
+      HIPCHK(c, axpby<T>((const T*)mptr(k, w->D0, 0), 0, (T*)mptr(k, w->R, 0), 0, k.nn, 1, 2.0, 0.0,
+                         pr, 0, k.np, c->stream));
+      STCHK(ns_solve<T>(k, w->D0, 1));
+    } else {
+      STCHK(solve_order0<T>(k, step));
+    }
     if (k.chain & kSave01) STCHK(st_save<T>(k, w->D0, 0, step, 0));
   }
   // ---- order 1: T' Y1 = 2 D1 - 4 S1 Y0; transposed: rhs^T = 2 D1 - 4 Y0 S1
@@ -880,9 +985,13 @@ dmpt_status recursion_step(const Call& k, int order, int d, int step) {
     g.active = w->mask1;
     STCHK(run_gemm(k, g));
     STCHK(sum_gemm_partials(k, md, w->ref, 1, 0));
-    if (k.traj && c->tj_valid >= 1)  // guess: this step's solution of the previous pass
-      for (int z = 0; z < md; ++z) STCHK(tj_load<T>(k, w->D1, z, step, 1 + z));
-    STCHK(solve_jet<T>(k, w->D1, md, d));
+    if (ns) {
+      STCHK(ns_solve<T>(k, w->D1, md));
+    } else {
+      if (k.traj && c->tj_valid >= 1)  // guess: this step's solution of the previous pass
+        for (int z = 0; z < md; ++z) STCHK(tj_load<T>(k, w->D1, z, step, 1 + z));
+      STCHK(solve_jet<T>(k, w->D1, md, d));
+    }
     if (k.traj)
       for (int z = 0; z < md; ++z) STCHK(tj_save<T>(k, w->D1, z, step, 1 + z));
     if (k.chain & kSave01)
@@ -916,9 +1025,13 @@ dmpt_status recursion_step(const Call& k, int order, int d, int step) {
     g2.active = w->mask1;
     STCHK(run_gemm(k, g2));
     STCHK(sum_gemm_partials(k, md, w->ref, 1, 0));
-    if (k.traj && c->tj_valid >= 2)
-      for (int z = 0; z < md; ++z) STCHK(tj_load<T>(k, w->D2, z, step, 1 + d + z));
-    STCHK(solve_jet<T>(k, w->D2, md, d));
+    if (ns) {
+      STCHK(ns_solve<T>(k, w->D2, md));
+    } else {
+      if (k.traj && c->tj_valid >= 2)
+        for (int z = 0; z < md; ++z) STCHK(tj_load<T>(k, w->D2, z, step, 1 + d + z));
+      STCHK(solve_jet<T>(k, w->D2, md, d));
+    }
     if (k.traj)
       for (int z = 0; z < md; ++z) STCHK(tj_save<T>(k, w->D2, z, step, 1 + d + z));
     if (k.chain & kSave2)
@@ -959,9 +1072,13 @@ dmpt_status recursion_step(const Call& k, int order, int d, int step) {
     g3.active = w->mask1;
     STCHK(run_gemm(k, g3));
     STCHK(sum_gemm_partials(k, md, w->ref, 1, 0));
-    if (k.traj && c->tj_valid >= 3)
-      for (int z = 0; z < md; ++z) STCHK(tj_load<T>(k, w->D3, z, step, 1 + 2 * d + z));
-    STCHK(solve_jet<T>(k, w->D3, md, d));
+    if (ns) {
+      STCHK(ns_solve<T>(k, w->D3, md));
+    } else {
+      if (k.traj && c->tj_valid >= 3)
+        for (int z = 0; z < md; ++z) STCHK(tj_load<T>(k, w->D3, z, step, 1 + 2 * d + z));
+      STCHK(solve_jet<T>(k, w->D3, md, d));
+    }
     if (k.traj)
       for (int z = 0; z < md; ++z) STCHK(tj_save<T>(k, w->D3, z, step, 1 + 2 * d + z));
   }
@@ -1706,7 +1823,6 @@ static dmpt_status normalise_options(dmpt_ctx c, const dmpt_options* in, dmpt_op
   if (o.prec < DMPT_FP64 || o.prec > DMPT_BF16X6) return fail(c, DMPT_ERR_ARG, "unknown precision");
   if (o.solver != DMPT_SOLVER_CG && o.solver != DMPT_SOLVER_NS)
     return fail(c, DMPT_ERR_ARG, "unknown solver");
-  if (o.solver == DMPT_SOLVER_NS) return fail(c, DMPT_ERR_UNSUPPORTED, "Newton-Schulz solver not built");
   if (o.guess != DMPT_GUESS_PREV && o.guess != DMPT_GUESS_TAYLOR)
     return fail(c, DMPT_ERR_ARG, "unknown initial guess");
   if (o.schedule < 0 || o.schedule > 2) return fail(c, DMPT_ERR_ARG, "schedule must be 0, 1 or 2");
@@ -1791,8 +1907,10 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
     return true;
   };
   const int dd = dirs_max > 0 ? dirs_max + 1 : 0;  // groups for perturbations may be empty
-  bool ok = group(c->ws.D0, 1, true) && group(c->ws.S0, 1, true) && group(c->ws.R, dm, false) &&
-            group(c->ws.P, dm, true) && group(c->ws.Q, dm, false) && group(c->U0, 1, true);
+  // R carries planes: the Newton-Schulz solve reads the right-hand sides as an operand
+  bool ok = group(c->ws.D0, 1, true) && group(c->ws.S0, 1, true) && group(c->ws.R, dm, true) &&
+            group(c->ws.P, dm, true) && group(c->ws.Q, dm, false) && group(c->U0, 1, true) &&
+            group(c->ws.Zi, 1, true);
   if (ok && dd > 0)
     ok = group(c->ws.D1, dd, true) && group(c->ws.D2, dd, true) && group(c->ws.D3, dd, true) &&
          group(c->ws.S1, dd, true) && group(c->ws.S2, dd, true) && group(c->ws.S3, dd, true);

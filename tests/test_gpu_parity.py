@@ -315,3 +315,38 @@ def test_nonorthogonal_canonical(dm, prec, tol):
     print(f"  errs {e0:.2e} {e1:.2e} {e2:.2e}")
     assert e0 < tol and e1 < tol and e2 < tol
     assert abs(float(np.trace(D0.cpu().numpy() @ S)) - Ne) < max(tol, 1e-9) * N
+
+
+# ------------------------------------------------------------------ Newton-Schulz shared inverse
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("bf16x6", 1e-6), ("fp32", 3e-6)])
+def test_newton_schulz_solver_canonical(dm, chain128_ref, prec, tol):
+    """The shared-inverse solver (one inverse of T' per step for all orders) reaches the oracle."""
+    print(f"case newton-schulz {prec}", flush=True)
+    c, ref = chain128_ref
+    with dm.Context(c["N"], dirs_max=1, prec=prec, solver="ns") as ctx:
+        P0, P1, P2, mu, st = ctx.mu_newton(T(c["H0"]), [T(h) for h in c["H1"]], None,
+                                           beta=c["beta"], Ne=c["Ne"], n=c["n"], order=2)
+    e0, e1, e2 = errs(P0, P1, P2, ref)
+    print(f"  errs {e0:.2e} {e1:.2e} {e2:.2e} newton={st['newton_iters']} cg={st['cg_iters_total']}")
+    assert e0 < tol and e1 < tol and e2 < tol
+    assert st["cg_iters_total"] == 0
+
+
+def test_newton_schulz_third_order_ragged(dm):
+    print("case newton-schulz order 3 ragged", flush=True)
+    N, n, beta, Ne = 200, 20, 10.0, 97.0
+    rng = np.random.default_rng(32)
+    h0 = workloads.banded(N, 5, bandwidth=16, decay=6.0)
+    h1 = [np.diag(np.arange(N) % 9 - 4.0), np.diag(np.cos(0.3 * np.arange(N)))]
+    h2 = [_sym(rng, N, 0.03), None]
+    h3 = [None, _sym(rng, N, 0.02)]
+    ref = oracle.canonical_response(h0, h1, h2, beta, Ne, n, order=3, h3s=h3)
+    with dm.Context(N, dirs_max=2, prec="fp64", solver="ns") as ctx:
+        r = ctx.mu_newton(T(h0), [T(h) for h in h1], [T(h2[0]), None], beta=beta, Ne=Ne, n=n,
+                          order=3, H3=[None, T(h3[1])])
+    P0, P1, P2, mu, st = r
+    e0, e1, e2 = errs(P0, P1, P2, ref)
+    e3 = _rel(r.P3, ref["P3"])
+    print(f"  errs {e0:.2e} {e1:.2e} {e2:.2e} {e3:.2e}")
+    assert e0 < 1e-10 and e1 < 1e-10 and e2 < 1e-10 and e3 < 1e-10
