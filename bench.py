@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--workload", default="banded8192", choices=["banded8192", "cubic2048", "chain128"])
     ap.add_argument("--prec", default="bf16x3", choices=list(PEAKS_TFLOPS))
     ap.add_argument("--n", type=int, default=0, help="shrink the banded workload to this N (testing)")
-    ap.add_argument("--cpu-sample-n", type=int, default=2048)
+    ap.add_argument("--cpu-sample-n", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tol-cg", type=float, default=0.0)
     ap.add_argument("--tol-occ", type=float, default=0.0)
@@ -97,14 +97,29 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "copies": 5}), flush=True)
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(n_sample, n_full, dirs):
     """The FP64 oracle on the same recipe at N = n_sample, scaled by (n_full/n_sample)^3."""
     import numpy as np
     import oracle
     import workloads
+    blas = "unknown"
     try:
         from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+        info = threadpool_info()
+        threads = max([p.get("num_threads", 1) for p in info] or [1])
+        blas = ", ".join(sorted({f"{p.get('internal_api')} {p.get('version')}" for p in info
+                                 if p.get("user_api") == "blas"})) or blas
     except Exception:
         threads = len(os.sched_getaffinity(0))
     c = workloads.config("banded8192", n_override=n_sample)
@@ -115,14 +130,16 @@ def cpu_baseline(n_sample, n_full, dirs):
     scale = (n_full / n_sample) ** 3
     return {
         "value": dirs / (t * scale), "unit": "responses/s", "cores": threads, "kind": "oracle",
+        "cpu_model": _cpu_model(), "blas": blas,
         "sample": (f"FP64 oracle (eigh + Daleckii-Krein, orders 0-2, {dirs} directions) on the banded "
                    f"recipe at N={n_sample}: {t:.2f} s, scaled by (N/{n_sample})^3 = {scale:.0f} to "
                    f"N={n_full}"),
     }
 
 
-def accuracy(name, P0, P1, P2, mu):
-    """Max errors on the oracle's stored samples (tests/golden/<name>_samples.npz)."""
+def accuracy(name, P0, P1, P2, mu, st=None):
+    """Max errors on the oracle's stored samples (tests/golden/<name>_samples.npz), and the
+    relative errors of the polarisability Tr(H1 P1) and hyperpolarisability Tr(H1 P2)."""
     import numpy as np
     path = os.path.join(ROOT, "tests", "golden", f"{name}_samples.npz")
     if not os.path.exists(path):
@@ -138,8 +155,13 @@ def accuracy(name, P0, P1, P2, mu):
              for z, p in enumerate(P1))
     e2 = max(float(np.abs(p[ii, jj].cpu().numpy() - g["P2"][z]).max() / g["max_P2"][z])
              for z, p in enumerate(P2))
-    return {"P0_maxabs": e0, "P1_maxabs_rel": e1, "P2_maxabs_rel": e2,
-            "mu0_err": abs(mu[0] - float(g["mu0"])), "samples": int(i.size)}
+    res = {"P0_maxabs": e0, "P1_maxabs_rel": e1, "P2_maxabs_rel": e2,
+           "mu0_err": abs(mu[0] - float(g["mu0"])), "samples": int(i.size)}
+    if st is not None:
+        res["tr_h1p1_rel"] = max(abs(a - b) / abs(b) for a, b in zip(st["tr_h1p1"], g["tr_h1p1"]))
+        if len(P2):
+            res["tr_h1p2_rel"] = max(abs(a - b) / abs(b) for a, b in zip(st["tr_h1p2"], g["tr_h1p2"]))
+    return res
 
 
 def fp64_gpu(dm, c, H0, H1, d, order):
@@ -214,7 +236,7 @@ def main():
     achieved = pe["mfma_flops"] / max(pe["ms"], 1e-12) / 1e9   # TFLOP/s
     peak = PEAKS_TFLOPS[dom]
     name = args.workload if not args.n else None
-    acc = accuracy(name, P0, P1, P2, mu) if name else None
+    acc = accuracy(name, P0, P1, P2, mu, st) if name else None
     traffic = measured_traffic(dom)
     res = {
         "metric": "response solves/sec (P0+P1+P2) and MFMA TFLOP/s at N=8192, err <=1e-6 vs FP64",
@@ -250,7 +272,7 @@ def main():
     del P0, P1, P2, out
     if args.fp64_compare:
         out64, f64 = fp64_gpu(dm, c, H0, H1, d, order)
-        f64["accuracy"] = accuracy(name, out64[0], out64[1], out64[2], out64[3]) if name else None
+        f64["accuracy"] = accuracy(name, out64[0], out64[1], out64[2], out64[3], out64[4]) if name else None
         f64["speedup_of_this_run"] = value / f64["value"]
         res["fp64_gpu"] = f64
         del out64

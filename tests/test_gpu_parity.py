@@ -5,6 +5,7 @@ of the oracle), FP32 / split-BF16 paths <= 1e-6 on the same measures.
 Sizes span several 128-wide tiles and ragged tails (N not a multiple of 128).
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -350,3 +351,32 @@ def test_newton_schulz_third_order_ragged(dm):
     e3 = _rel(r.P3, ref["P3"])
     print(f"  errs {e0:.2e} {e1:.2e} {e2:.2e} {e3:.2e}")
     assert e0 < 1e-10 and e1 < 1e-10 and e2 < 1e-10 and e3 < 1e-10
+
+
+# ------------------------------------------------------------------ N = 2048 cubic lattice
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("prec,refine,tol", [("fp64", 0, 1e-10), ("fp32", 0, 1e-5), ("bf16x6", 0, 1e-6),
+                                             ("bf16x3", 1, 1e-6)])
+def test_cubic2048_all_forms(dm, prec, refine, tol):
+    """16 x 16 x 8 simple-cubic lattice, beta 20, n 25, orders 0-2, against the oracle's samples.
+
+    Plain FP32 products carry relative errors of a few 1e-6 on P1 and P2 here (25
+    squarings of FP32 rounding); the six-product split-BF16 form, alone or as the
+    refinement after three-product passes, meets 1e-6.
+    """
+    print(f"case cubic2048 {prec} refine={refine}", flush=True)
+    c = workloads.config("cubic2048")
+    g = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cubic2048_samples.npz"))
+    with dm.Context(c["N"], dirs_max=len(c["H1"]), prec=prec, refine=refine) as ctx:
+        P0, P1, P2, mu, st = ctx.mu_newton(T(c["H0"]), [T(h) for h in c["H1"]], None, beta=c["beta"],
+                                           Ne=c["Ne"], n=c["n"], order=int(g["order"]))
+    ii = torch.as_tensor(g["i"], device=P0.device)
+    jj = torch.as_tensor(g["j"], device=P0.device)
+    e0 = float(np.abs(P0[ii, jj].cpu().numpy() - g["P0"]).max())
+    e1 = max(float(np.abs(p[ii, jj].cpu().numpy() - g["P1"][z]).max() / g["max_P1"][z]) for z, p in enumerate(P1))
+    e2 = max((float(np.abs(p[ii, jj].cpu().numpy() - g["P2"][z]).max() / g["max_P2"][z])
+              for z, p in enumerate(P2)), default=0.0)
+    t1 = max(abs(a - b) / abs(b) for a, b in zip(st["tr_h1p1"], g["tr_h1p1"]))
+    print(f"  errs {e0:.2e} {e1:.2e} {e2:.2e} Tr(H1P1) {t1:.2e} seconds={st['seconds']:.2f}")
+    assert e0 < tol and e1 < tol and e2 < tol and t1 < tol
