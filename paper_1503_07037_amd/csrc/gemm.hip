@@ -301,7 +301,11 @@ __global__ __launch_bounds__(kThreads) void k_gemm_f32(GemmArgs a) {
 // LDS buffer and the global loads of stage k + 2 are in flight.
 // FL  1: the MFMAs of each stage accumulate into a fresh FP32 tile that is
 //     then added to an FP64 accumulator (each FP32 sum covers BK of k, so
-//     the FP32 rounding no longer grows with N); 0: one FP32 accumulator.
+//     the FP32 rounding no longer grows with N).  Two FP32 tiles alternate
+//     between stages: while the MFMAs of stage k fill one, the VALU adds the
+//     other (stage k - 1) into FP64, a few values after each MFMA of the
+//     first k block, so the conversions and FP64 adds run beside the matrix
+//     core instead of after it.  0: one FP32 accumulator over all of k.
 template <int S, int TM, int BK, int NW, int FL>
 __global__ __launch_bounds__(NW * 64) void k_gemm_bf16(GemmArgs a) {
   constexpr int WN = NW / 2;           // waves along n (two along m)
@@ -349,7 +353,7 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_bf16(GemmArgs a) {
 #pragma unroll
     for (int j = 0; j < LOADS; ++j) *(u4v*)(smem + st * SBYTES + dst[j]) = stg[j];
   };
-  f16v acc[FM][FN];
+  f16v acc[FM][FN], acc2[FM][FN];
   double accd[FL == 1 ? FM : 1][FL == 1 ? FN : 1][FL == 1 ? 16 : 1];
   f16v zero;
 #pragma unroll
@@ -372,7 +376,18 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_bf16(GemmArgs a) {
   swrite(0);
   if (nk > 1) gload(1);
   __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
+  auto fold = [&](f16v (&ac)[FM][FN]) {
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) accd[i][j][r] += (double)ac[i][j][r];
+  };
+  // One stage: MFMAs into acur; with FL = 1 the other FP32 tile, filled by
+  // the previous stage, is added into FP64 meanwhile (independent of the
+  // MFMAs in flight, so the VALU work overlaps them).
+  auto stage = [&](int kt, f16v (&acur)[FM][FN], f16v (&aprev)[FM][FN], bool fold_prev) {
     const unsigned char* sb = smem + (kt & 1) * SBYTES + lane * 16;
 #pragma unroll
     for (int kk = 0; kk < KB; ++kk) {
@@ -392,32 +407,46 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_bf16(GemmArgs a) {
         swrite((kt + 1) & 1);
         if (kt + 2 < nk) gload(kt + 2);
       }
-      {
-        // smallest terms first
+      // smallest terms first
+      int m = 0;  // MFMA index within the k block
 #pragma unroll
-        for (int t = S - 1; t >= 0; --t)          // t = p + q
+      for (int t = S - 1; t >= 0; --t)          // t = p + q
 #pragma unroll
-          for (int p = 0; p <= t; ++p)
+        for (int p = 0; p <= t; ++p)
 #pragma unroll
-            for (int i = 0; i < FM; ++i)
+          for (int i = 0; i < FM; ++i)
 #pragma unroll
-              for (int j = 0; j < FN; ++j) {
-                // FL: the stage's first product starts a fresh FP32 tile
-                const bool fresh = FL == 1 && kk == 0 && t == S - 1 && p == 0;
-                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa[p][i], yb[t - p][j],
-                                                                    fresh ? zero : acc[i][j], 0, 0, 0);
+            for (int j = 0; j < FN; ++j) {
+              // FL: the stage's first product starts a fresh FP32 tile
+              const bool fresh = FL == 1 && kk == 0 && t == S - 1 && p == 0;
+              acur[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa[p][i], yb[t - p][j],
+                                                                   fresh ? zero : acur[i][j], 0, 0, 0);
+              if constexpr (FL == 1) {
+                // four values of the previous tile after each MFMA of the first k block
+                constexpr int kFold = 4;
+                static_assert(kFold * (S * (S + 1) / 2) >= 16, "the first k block must fold the whole tile");
+                if (kk == 0 && fold_prev && m * kFold < FM * FN * 16) {
+#pragma unroll
+                  for (int q = 0; q < kFold; ++q) {
+                    const int v = m * kFold + q;
+                    const int fi = v / (16 * FN), fj = (v / 16) % FN, fr = v % 16;
+                    accd[fi][fj][fr] += (double)aprev[fi][fj][fr];
+                  }
+                }
               }
-      }
-    }
-    if constexpr (FL == 1) {
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-#pragma unroll
-          for (int r = 0; r < 16; ++r) accd[i][j][r] += (double)acc[i][j][r];
+              ++m;
+            }
     }
     __syncthreads();
+  };
+  if constexpr (FL == 1) {
+    for (int kt = 0; kt < nk; kt += 2) {
+      stage(kt, acc, acc2, kt > 0);
+      if (kt + 1 < nk) stage(kt + 1, acc2, acc, true);
+    }
+    fold((nk & 1) ? acc : acc2);  // the last stage's tile
+  } else {
+    for (int kt = 0; kt < nk; ++kt) stage(kt, acc, acc2, false);
   }
   double dsum = 0.0;
 #pragma unroll
