@@ -24,7 +24,11 @@ current product-kernel source, else null.
 Other modes: --fp64-compare also times one FP64 solve of the same workload
 on the GPU (the same library in DMPT_FP64); --copy-calibration only runs a
 plain device copy of known size, the reference that scales the FETCH_SIZE /
-WRITE_SIZE counters into bytes.
+WRITE_SIZE counters into bytes; --workload batch64 times the batched
+canonical solve of 64 uneven systems (FP32, orders 0-1, 3 directions, one
+graph-captured pass per Newton update) and --workload adjoint4096 the
+adjoint gradient of Tr(A P0) on the 16^3 cubic lattice (FP32, checkpoints
+every 5 steps), each in the same JSON form.
 """
 import argparse
 import hashlib
@@ -43,9 +47,10 @@ DTYPE = {"bf16x3": "bf16", "bf16x6": "bf16", "fp32": "f32", "fp64": "f64"}
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="banded8192", choices=["banded8192", "cubic2048", "chain128"])
+    ap.add_argument("--workload", default="banded8192",
+                    choices=["banded8192", "cubic2048", "chain128", "batch64", "adjoint4096"])
     ap.add_argument("--prec", default="bf16x3", choices=list(PEAKS_TFLOPS))
     ap.add_argument("--n", type=int, default=0, help="shrink the banded workload to this N (testing)")
     ap.add_argument("--cpu-sample-n", type=int, default=4096)
@@ -182,6 +187,176 @@ def fp64_gpu(dm, c, H0, H1, d, order):
                  "mfma_tflops": st["mfma_flops"] / secs / 1e12}
 
 
+def _timed(fn, steps, warmup, sync):
+    """Run fn warmup times untimed, then steps times; returns (last result, seconds per step list)."""
+    out = None
+    for w in range(warmup):
+        t0 = time.perf_counter()
+        out = fn()
+        sync()
+        print(f"warmup {w}: {time.perf_counter() - t0:.2f} s", file=sys.stderr, flush=True)
+    times = []
+    sync()
+    for s in range(steps):
+        t0 = time.perf_counter()
+        out = fn()
+        sync()
+        times.append(time.perf_counter() - t0)
+        print(f"step {s}: {times[-1]:.2f} s", file=sys.stderr, flush=True)
+    return out, times
+
+
+def _cpu_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        return len(os.sched_getaffinity(0))
+
+
+def run_batch64(args):
+    """64 uneven cubic systems, FP32, orders 0-1, 3 directions: one batched canonical solve per step."""
+    import numpy as np
+    import torch
+    import oracle
+    import workloads
+    import paper_1503_07037_amd as dm
+    c = workloads.CONFIGS["batch64"]
+    systems = workloads.batched_systems(c["seed"], count=c["count"])
+    dev = torch.device("cuda:0")
+    T = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    H0s, H1s = [], []
+    for sy in systems:
+        lx, ly, lz = sy["dims"]
+        H0s.append(T(workloads.cubic_lattice(lx, ly, lz, sy["seed"])))
+        H1s.append([T(np.diag(v)) for v in workloads.lattice_dipoles(lx, ly, lz)])
+    nmax = max(sy["N"] for sy in systems)
+    d = c["dirs"]
+    ctx = dm.Context(nmax, dirs_max=d, prec="fp32")
+    betas = [sy["beta"] for sy in systems]
+    nes = [sy["Ne"] for sy in systems]
+    step = lambda: ctx.mu_newton_batched(H0s, H1s, betas, nes, n=c["n"], order=c["order"])
+    out, times = _timed(step, args.steps, args.warmup, torch.cuda.synchronize)
+    P0, P1, _, mus, st = out
+    secs = sum(times)
+    value = len(systems) * d * args.steps / secs
+    mfma_tf = st["mfma_flops"] / (secs / args.steps) / 1e12
+    acc = None
+    path = os.path.join(ROOT, "tests", "golden", "batch64_samples.npz")
+    if os.path.exists(path):
+        g = np.load(path)
+        e0 = e1 = 0.0
+        for k in range(len(systems)):
+            ii = torch.as_tensor(g["i"][k], device=dev)
+            jj = torch.as_tensor(g["j"][k], device=dev)
+            e0 = max(e0, float(np.abs(P0[k][ii, jj].cpu().numpy() - g["P0"][k]).max()))
+            e1 = max(e1, max(float(np.abs(P1[k][z][ii, jj].cpu().numpy() - g["P1"][k][z]).max()
+                                   / g["max_P1"][k][z]) for z in range(d)))
+        acc = {"P0_maxabs": e0, "P1_maxabs_rel": e1, "systems": len(systems),
+               "samples_per_system": int(g["i"].shape[1])}
+    res = {
+        "metric": "batched canonical response solves/sec (P0+P1), 64 uneven systems, FP32 MFMA",
+        "value": value, "unit": "responses/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * secs / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batch64: 64 cubic tight-binding systems, N log-uniform in [256, 3072], "
+                               "beta U(5, 40), Ne = N/2, n = 25, 3 directions, orders 0-1",
+                   "systems": len(systems), "sum_N": sum(sy["N"] for sy in systems),
+                   "precision": "fp32", "parallelism": "single GPU"},
+        "roofline": {"bound": "mfma", "achieved": mfma_tf, "peak": PEAKS_TFLOPS["fp32"],
+                     "unit": "TFLOP/s", "frac": mfma_tf / PEAKS_TFLOPS["fp32"], "traffic": None,
+                     "kernel": "every FP32 product of the call: executed MFMA flops (tallied on the "
+                               "device by the members that run) over the wall time of one solve"},
+        "newton_passes": st["newton_iters"], "step_seconds": times, "accuracy": acc,
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        # the oracle on the batch's systems in order until about 15 s, scaled by sum N^3
+        t0 = time.perf_counter()
+        done = 0
+        for sy in systems:
+            lx, ly, lz = sy["dims"]
+            h0 = workloads.cubic_lattice(lx, ly, lz, sy["seed"])
+            oracle.canonical_response(h0, list(workloads.lattice_dipoles(lx, ly, lz)), None, sy["beta"],
+                                      sy["Ne"], c["n"], order=c["order"])
+            done += 1
+            if time.perf_counter() - t0 > 15.0:
+                break
+        t = time.perf_counter() - t0
+        frac = sum(sy["N"] ** 3 for sy in systems[:done]) / sum(sy["N"] ** 3 for sy in systems)
+        res["cpu_baseline"] = {
+            "value": len(systems) * d / (t / frac), "unit": "responses/s", "cores": _cpu_threads(),
+            "kind": "oracle", "cpu_model": _cpu_model(),
+            "sample": f"FP64 oracle on the first {done} of the 64 systems ({t:.1f} s, "
+                      f"{100 * frac:.1f} % of the batch's sum of N^3), scaled to the batch"}
+    print(json.dumps(res), flush=True)
+
+
+def run_adjoint(args):
+    """Adjoint gradient of Tr(A P0) w.r.t. H0 (canonical), 16^3 cubic lattice, FP32 forward and backward."""
+    import numpy as np
+    import torch
+    import oracle
+    import workloads
+    import paper_1503_07037_amd as dm
+    c = workloads.config("adjoint4096")
+    dev = torch.device("cuda:0")
+    T = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    N = c["N"]
+    H0 = T(c["H0"])
+    A = T(c["H1"][0])
+    ctx = dm.Context(N, dirs_max=1, prec="fp32", ckpt_every=5)
+    step = lambda: ctx.backward(H0, c["beta"], c["Ne"], c["n"], A)
+    out, _ = _timed(step, args.warmup, 0, torch.cuda.synchronize)
+    ctx.profile(True)
+    out, times = _timed(step, args.steps, 0, torch.cuda.synchronize)
+    prof = ctx.profile_get()
+    ctx.profile(False)
+    G, st = out
+    secs = sum(times)
+    dom = max(prof["engines"], key=lambda e: prof["engines"][e]["ms"])
+    pe = prof["engines"][dom]
+    achieved = pe["mfma_flops"] / max(pe["ms"], 1e-12) / 1e9
+    acc = None
+    path = os.path.join(ROOT, "tests", "golden", "adjoint4096_samples.npz")
+    if os.path.exists(path):
+        g = np.load(path)
+        ii = torch.as_tensor(g["i"], device=dev)
+        jj = torch.as_tensor(g["j"], device=dev)
+        acc = {"G_maxabs_rel": float(np.abs(G[ii, jj].cpu().numpy() - g["G"]).max() / g["max_G"]),
+               "samples": int(g["i"].size)}
+    res = {
+        "metric": "adjoint gradients/sec of Tr(A P0) w.r.t. H0 (canonical), N=4096, FP32 MFMA",
+        "value": args.steps / secs, "unit": "gradients/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * secs / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "adjoint4096: 16^3 cubic tight-binding, beta 20, n 25, Ne 2048, "
+                               "A = diag(x), checkpoints every 5 steps",
+                   "N": N, "precision": "fp32", "parallelism": "single GPU"},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAKS_TFLOPS["fp32"],
+                     "unit": "TFLOP/s", "frac": achieved / PEAKS_TFLOPS["fp32"], "traffic": None,
+                     "kernel": f"product kernel, {dom} engine", "launches": pe["launches"],
+                     "avg_launch_ms": pe["ms"] / max(pe["launches"], 1),
+                     "product_time_share": prof["ms"] / (1e3 * secs)},
+        "mfma_tflops_whole_step": st["mfma_flops"] / (secs / args.steps) / 1e12,
+        "newton_iters": st["newton_iters"], "cg_iters_total": st["cg_iters_total"],
+        "step_seconds": times, "accuracy": acc,
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        ns = 2048  # the same recipe on a 16 x 16 x 8 lattice, scaled by (N/2048)^3
+        h0 = workloads.cubic_lattice(16, 16, 8, c["seed"])
+        x = workloads.lattice_dipoles(16, 16, 8)[0]
+        t0 = time.perf_counter()
+        oracle.adjoint_grad(h0, c["beta"], ns / 2.0, c["n"], np.diag(x))
+        t = time.perf_counter() - t0
+        res["cpu_baseline"] = {
+            "value": 1.0 / (t * (N / ns) ** 3), "unit": "gradients/s", "cores": _cpu_threads(),
+            "kind": "oracle", "cpu_model": _cpu_model(),
+            "sample": f"FP64 oracle adjoint on the 16 x 16 x 8 lattice: {t:.2f} s, scaled by (N/2048)^3 = 8"}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -190,6 +365,12 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.workload == "batch64":
+        run_batch64(args)
+        return
+    if args.workload == "adjoint4096":
+        run_adjoint(args)
         return
     import numpy as np
     import torch
@@ -219,9 +400,11 @@ def main():
     ctx.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    marks = []
     for s in range(args.steps):
         out = step()
-        print(f"step {s}: {time.perf_counter() - t0:.2f} s cumulative", file=sys.stderr, flush=True)
+        marks.append(time.perf_counter() - t0)
+        print(f"step {s}: {marks[-1]:.2f} s cumulative", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
     prof = ctx.profile_get()
@@ -266,6 +449,7 @@ def main():
         "mfma_tflops_whole_step": st["mfma_flops"] / (ms_step / 1e3) / 1e12,
         "useful_tflops_whole_step": st["useful_flops"] / (ms_step / 1e3) / 1e12,
         "newton_iters": st["newton_iters"], "cg_iters_total": st["cg_iters_total"],
+        "step_seconds": [b - a for a, b in zip([0.0] + marks[:-1], marks)],
         "accuracy": acc,
     }
     ctx.close()

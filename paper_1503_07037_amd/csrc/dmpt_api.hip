@@ -79,6 +79,7 @@ struct dmpt_ctx_s {
   // checked against it on the host before they are queued
   std::vector<std::pair<const char*, size_t>> regions;
   int tile_pref = 0;             // product tile edge: 0 = largest available
+  double* d_tally = nullptr;     // [executed MFMA flops, useful flops] of graph-replayed products
   bool log = false;              // DMPT_LOG set: one line per Newton pass on stderr
   std::vector<std::pair<int64_t, int>> tuned;  // autotuned tile edge per padded size
   // iterates of the previous Newton pass (FP32 copies, warm starts):
@@ -380,6 +381,12 @@ dmpt_status run_gemm(const Call& k, const G& g) {
     if (!ok) return fail(c, DMPT_ERR_ARG, "internal: a product would leave its workspace");
   }
   const double n3 = 2.0 * (double)k.Np * k.Np * k.Np;
+  if (k.graph) {
+    // replays skip converged members on the device: count there
+    a.tally = k.c->d_tally;
+    a.tally_m = n3 * engine_terms(k.eng);
+    a.tally_u = 2.0 * (double)k.N * k.N * k.N;
+  }
   const int members = g.counted >= 0 ? g.counted : g.batch;
   const double mf = n3 * engine_terms(k.eng) * members;
   const double uf = 2.0 * (double)k.N * k.N * k.N * members;
@@ -1532,14 +1539,21 @@ double kappa_bound(double x, int step) {
   return 1.0 + t * t;
 }
 
+// lin: order 1 with the linear schedule; the response P_J to H1 = I runs as
+// an extra direction (its D_0 is c I: no input, no mu shift), is written to
+// PJs[slot], and each system's P1 is then corrected to Tr P1 = 0 exactly
+// (lin_correct), so one pass settles mu1.
 template <class T>
 dmpt_status batched_pass(dmpt_ctx c, std::vector<Bucket>& bk, bool stageB, int ord, int d, int n,
                          Engine eng, const std::vector<int>& slot_sys, const double* const* H0s,
                          const double* const* H1s, double* const* P0s, double* const* P1s,
                          double* const* P2s, const int64_t* Ns, const std::vector<double>& cs,
-                         double* d_mu_shift, double* d_tr, int rs, double* d_half) {
+                         double* d_mu_shift, double* d_tr, int rs, double* d_half, int lin,
+                         const double* d_par, double* d_mu, double* const* PJs, int rs0,
+                         double* d_delta) {
   hipStream_t s = c->stream;
   const int J = 1 + 2 * d;
+  const int dd = d + lin;  // directions the recursion carries
   std::vector<Call> ks(bk.size());
   for (size_t b = 0; b < bk.size(); ++b) {
     Call& k = ks[b];
@@ -1553,7 +1567,7 @@ dmpt_status batched_pass(dmpt_ctx c, std::vector<Bucket>& bk, bool stageB, int o
     k.stride = k.nn;
     k.m = bk[b].m;
     k.graph = true;
-    if (d > 0) HIPCHK(c, expand_mask(k.w->mask0, d, k.w->mask1, k.m * d, s));
+    if (dd > 0) HIPCHK(c, expand_mask(k.w->mask0, dd, k.w->mask1, k.m * dd, s));
   }
   // D_0 of every system and direction from the caller inputs; the shifts
   // -c mu live on the device so the graph picks up each Newton update.
@@ -1568,8 +1582,15 @@ dmpt_status batched_pass(dmpt_ctx c, std::vector<Bucket>& bk, bool stageB, int o
       HIPCHK(c, (sym_combine<double, T>(H0s[sys], N, 0, N, k.Np, 0.5 * cs[sys],
                                         d_mu_shift + (int64_t)slot * J, 0, (T*)mptr(k, k.w->D0, i),
                                         k.Np, 0, pl, k.np, 1, s, nullptr, 0.0, gate)));
+      if (lin) {
+        // D_0 of the J direction: c I (the input is not read with a = 0)
+        planes_of(k, k.w->D1, i * dd + d, pl);
+        HIPCHK(c, (sym_combine<double, T>(H0s[sys], N, 0, N, k.Np, 0.0, d_par + 6 * (int64_t)slot + 2, 0,
+                                          (T*)mptr(k, k.w->D1, i * dd + d), k.Np, 0, pl, k.np, 1, s,
+                                          nullptr, 0.0, gate)));
+      }
       for (int z = 0; z < d && ord >= 1; ++z) {
-        const int mem = i * d + z;
+        const int mem = i * dd + z;
         planes_of(k, k.w->D1, mem, pl);
         HIPCHK(c, (sym_combine<double, T>(H1s[sys * d + z], N, 0, N, k.Np, 0.5 * cs[sys],
                                           d_mu_shift + (int64_t)slot * J + 1 + z, 0,
@@ -1590,7 +1611,7 @@ dmpt_status batched_pass(dmpt_ctx c, std::vector<Bucket>& bk, bool stageB, int o
     for (size_t b = 0; b < bk.size(); ++b) {
       Call& k = ks[b];
       k.cg_iters = cg_bound(kappa_bound(bk[b].xmax, step), k.tol_cg, c->opt.max_cg);
-      STCHK(recursion_step<T>(k, ord, d, -1));
+      STCHK(recursion_step<T>(k, ord, dd, -1));
     }
   // outputs and traces, per system
   for (size_t b = 0; b < bk.size(); ++b) {
@@ -1607,7 +1628,7 @@ dmpt_status batched_pass(dmpt_ctx c, std::vector<Bucket>& bk, bool stageB, int o
       HIPCHK(c, sum_partials(c->d_part, reduce_blocks(N * N), 1, t + 2 * J, 1, 0, s));
       for (int o = 1; o <= ord; ++o)
         for (int z = 0; z < d; ++z) {
-          const int mem = i * d + z;
+          const int mem = i * dd + z;
           double* Pk = o == 1 ? P1s[sys * d + z] : P2s[sys * d + z];
           const Group& g = o == 1 ? k.w->D1 : k.w->D2;
           const int jt = (o == 1 ? 1 : 1 + d) + z;
@@ -1618,6 +1639,19 @@ dmpt_status batched_pass(dmpt_ctx c, std::vector<Bucket>& bk, bool stageB, int o
           HIPCHK(c, sum_partials(c->d_part, reduce_blocks(N * N), 1,
                                  t + 2 * J + 1 + (o == 1 ? 0 : d) + z, 1, 0, s));
         }
+      if (lin) {
+        double* PJ = PJs[slot];
+        HIPCHK(c, (sym_combine<T, double>((const T*)mptr(k, k.w->D1, i * dd + d), k.Np, 0, N, k.Np, -0.5,
+                                          nullptr, 0, PJ, N, 0, nullptr, 0, 1, s, nullptr, 0.0, gate)));
+        HIPCHK(c, trace<double>(PJ, N, 0, N, 1, t + rs0, 1, t + rs0 + 1, s));
+        for (int z = 0; z < d; ++z) {
+          HIPCHK(c, dot_partials<double>(H1s[sys * d + z], 0, PJ, 0, N * N, 1, c->d_part, s));
+          HIPCHK(c, sum_partials(c->d_part, reduce_blocks(N * N), 1, t + rs0 + 2 + z, 1, 0, s));
+        }
+        HIPCHK(c, lin_correct(t, d, J, rs0, d_mu + (int64_t)slot * J, d_mu_shift + (int64_t)slot * J,
+                              cs[sys], d_delta + (int64_t)slot * d, P1s + (size_t)sys * d, PJ, N, gate,
+                              s));
+      }
     }
   }
   return DMPT_OK;
@@ -1923,6 +1957,7 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
   c->ws.iters = (int*)alloc(sizeof(int) * dm);
   c->d_flag = (int*)alloc(sizeof(int) * 4);
   c->d_res = (double*)alloc(sizeof(double) * RES_COUNT);
+  c->d_tally = (double*)alloc(sizeof(double) * 2);
   const size_t tiles = (size_t)(c->np_max / 128) * (c->np_max / 128);
   c->part_count = std::max<size_t>(tiles, 1024) * dm;
   c->d_part = (double*)alloc(sizeof(double) * c->part_count);
@@ -1932,7 +1967,7 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
     if (!c->jout) return bail(DMPT_ERR_NOMEM, "device workspace allocation failed");
   }
   if (!c->ws.rr || !c->ws.pq || !c->ws.ref || !c->ws.active || !c->ws.iters || !c->d_flag || !c->d_res ||
-      !c->d_part || !c->d_gersh)
+      !c->d_tally || !c->d_part || !c->d_gersh)
     return bail(DMPT_ERR_NOMEM, "device scalar allocation failed");
   if (hipHostMalloc((void**)&c->h_res, sizeof(double) * RES_COUNT, hipHostMallocDefault) != hipSuccess)
     return bail(DMPT_ERR_NOMEM, "pinned allocation failed");
@@ -2395,7 +2430,11 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
   hipStream_t s = c->stream;
   reset_stats(c);
   const int J = 1 + 2 * d;
-  const int rs = 2 * J + 1 + 2 * d;
+  // linear schedule (order 1): the final stage carries the J direction and
+  // settles mu1 in one pass (batched_pass); its records follow the others
+  const int lin = (c->opt.schedule >= 1 && order == 1) ? 1 : 0;
+  const int rs0 = 2 * J + 1 + 2 * d;
+  const int rs = rs0 + (lin ? 2 + d : 0);
   // per system: Gershgorin interval, range guard, bounds of mu0, c
   std::vector<double> cs(nsys), par(6 * (size_t)nsys), mu0(nsys), xs(nsys);
   for (int sy = 0; sy < nsys; ++sy) {
@@ -2440,7 +2479,7 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
   const Engine eng = (c->opt.prec == DMPT_BF16X3 && c->opt.refine) ? Engine::BF16S3
                                                                     : engine_of(c->opt.prec);
   const int np = engine_planes(eng);
-  const int dmem = std::max(1, d);
+  const int dmem = std::max(1, d + lin);
   size_t need = 0, part_need = c->part_count;
   for (auto& b : bk) {
     const size_t nn = (size_t)b.Np * b.Np;
@@ -2500,7 +2539,20 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
   double* d_brk = (double*)dalloc(sizeof(double) * 2 * nsys);
   double* d_occ = (double*)dalloc(sizeof(double) * nsys);
   int* d_flags = (int*)dalloc(sizeof(int) * nsys * 6);  // activeA, activeB, done, passes, status, spare
-  if (!d_mu || !d_shift || !d_tr || !d_par || !d_prev || !d_brk || !d_occ || !d_flags) {
+  double* d_delta = lin ? (double*)dalloc(sizeof(double) * nsys * d) : nullptr;
+  int64_t nbig = 1;
+  for (int sy = 0; sy < nsys; ++sy) nbig = std::max(nbig, Ns[sy]);
+  double* d_w = lin ? (double*)dalloc(sizeof(double) * nbig) : nullptr;  // mu1 guess scratch
+  int* d_want = lin ? (int*)dalloc(sizeof(int) * nsys * d) : nullptr;
+  std::vector<double*> pjs(nsys, nullptr);  // per slot: P_J (N x N FP64)
+  bool pj_ok = true;
+  for (int slot = 0; slot < nsys && lin; ++slot) {
+    const int64_t N = Ns[slot_sys[slot]];
+    pjs[slot] = (double*)dalloc(sizeof(double) * (size_t)N * N);
+    pj_ok = pj_ok && pjs[slot];
+  }
+  if (!d_mu || !d_shift || !d_tr || !d_par || !d_prev || !d_brk || !d_occ || !d_flags ||
+      (lin && (!d_delta || !pj_ok || !d_w || !d_want))) {
     cleanup();
     return fail(c, DMPT_ERR_NOMEM, "batched scalar allocation failed");
   }
@@ -2551,7 +2603,14 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
       hbrk[2 * slot] = hpar[6 * (size_t)slot + 3];
       hbrk[2 * slot + 1] = hpar[6 * (size_t)slot + 4];
     }
-    if (hipMemcpy(d_mu, hmu.data(), hmu.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+    // first-order mu values the caller left open get a guess before the final stage
+    std::vector<int> hwant(lin ? (size_t)nsys * d : 0);
+    for (int slot = 0; slot < nsys && lin; ++slot)
+      for (int z = 0; z < d; ++z)
+        hwant[(size_t)slot * d + z] = !std::isfinite(mus[(size_t)slot_sys[slot] * J + 1 + z]);
+    if ((lin && hipMemcpy(d_want, hwant.data(), hwant.size() * sizeof(int), hipMemcpyHostToDevice) !=
+                    hipSuccess) ||
+        hipMemcpy(d_mu, hmu.data(), hmu.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(d_shift, hsh.data(), hsh.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(d_par, hpar.data(), hpar.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(d_brk, hbrk.data(), hbrk.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
@@ -2567,11 +2626,24 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
   hipGraph_t gg[2] = {nullptr, nullptr};
   dmpt_status rc = DMPT_OK;
   int total_passes = 0;
-  double flops_m = 0.0, flops_u = 0.0;  // executed over every replay
+  // executed work over every replay, tallied on the device by the products
+  // of members that actually run
+  if (rc == DMPT_OK && hipMemsetAsync(c->d_tally, 0, 2 * sizeof(double), s) != hipSuccess)
+    rc = fail(c, DMPT_ERR_HIP, "tally reset failed");
   for (int stage = staged ? 0 : 1; stage <= 1 && rc == DMPT_OK; ++stage) {
     const int ord = stage == 0 ? 0 : order;
     const bool final_stage = stage == 1;
-    const double mf0 = c->mfma_flops, uf0 = c->useful_flops;
+    if (final_stage && lin && staged) {
+      // mu1 guesses from the converged P0 of the first stage, so the final
+      // pass's affine correction is small (the response is FP32 in this mode)
+      for (int slot = 0; slot < nsys && rc == DMPT_OK; ++slot) {
+        const int sy = slot_sys[slot];
+        if (mu1_guess(P0s[sy], Ns[sy], H1s + (size_t)sy * d, d, d_w, d_mu + (size_t)slot * J,
+                      d_shift + (size_t)slot * J, cs[sy], d_want + (size_t)slot * d, s) != hipSuccess)
+          rc = fail(c, DMPT_ERR_HIP, "mu1 guess launch failed");
+      }
+      if (rc != DMPT_OK) break;
+    }
     {
       // every stage starts its noise-floor test afresh
       std::vector<double> hprev(nsys, INFINITY);
@@ -2587,11 +2659,17 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
     }
     dmpt_status cr = c->esize == 8
         ? batched_pass<double>(c, bk, final_stage, ord, d, n, eng, slot_sys, H0s, H1s, P0s, P1s, P2s,
-                               Ns, cs, d_shift, d_tr, rs, c->d_res + RES_HALF)
+                               Ns, cs, d_shift, d_tr, rs, c->d_res + RES_HALF,
+                               final_stage ? lin : 0, d_par, d_mu, pjs.data(), rs0, d_delta)
         : batched_pass<float>(c, bk, final_stage, ord, d, n, eng, slot_sys, H0s, H1s, P0s, P1s, P2s,
-                              Ns, cs, d_shift, d_tr, rs, c->d_res + RES_HALF);
+                              Ns, cs, d_shift, d_tr, rs, c->d_res + RES_HALF,
+                              final_stage ? lin : 0, d_par, d_mu, pjs.data(), rs0, d_delta);
     if (cr == DMPT_OK) {
-      const hipError_t e = newton_update(d_tr, rs, d_par, d_mu, d_shift, J, ord * d, c->opt.tol_occ,
+      // with the linear schedule the final stage runs one pass and no longer
+      // moves mu0: the first stage settles it a hundred times tighter (the
+      // first-order responses carry mu0's error times dP1/dmu0)
+      const double tol_pass = (lin && !final_stage) ? 1e-2 * c->opt.tol_occ : c->opt.tol_occ;
+      const hipError_t e = newton_update(d_tr, rs, d_par, d_mu, d_shift, J, ord * d, tol_pass,
                                          final_stage ? 1 : 0, final_stage ? actB : actA, done,
                                          d_prev, d_brk, d_occ, passes, status, nsys, s);
       if (e != hipSuccess) cr = fail(c, DMPT_ERR_HIP, "newton_update launch failed");
@@ -2609,17 +2687,16 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
       break;
     }
     gg[stage] = g;
-    const double pass_mf = c->mfma_flops - mf0, pass_uf = c->useful_flops - uf0;
     int* act = final_stage ? actB : actA;
     std::vector<int> hact(nsys);
+    const int passes0 = total_passes;
+    const auto ts = std::chrono::steady_clock::now();
     for (int pass = 0; pass < c->opt.max_newton; ++pass) {
       if (hipGraphLaunch(gx[stage], s) != hipSuccess) {
         rc = fail(c, DMPT_ERR_HIP, "hipGraphLaunch failed");
         break;
       }
       ++total_passes;
-      flops_m += pass_mf;
-      flops_u += pass_uf;
       if (hipMemcpyAsync(hact.data(), act, nsys * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
           hipStreamSynchronize(s) != hipSuccess) {
         rc = fail(c, DMPT_ERR_HIP, "batched pass failed");
@@ -2629,13 +2706,19 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
       for (int v : hact) any |= v != 0;
       if (!any) break;
     }
+    if (c->log)
+      std::fprintf(stderr, "[dmpt] batched stage %d (orders 0-%d): %d passes, %.3f s\n", stage, ord,
+                   total_passes - passes0,
+                   std::chrono::duration<double>(std::chrono::steady_clock::now() - ts).count());
   }
   c->prof_on = prof;
   // results
   std::vector<double> hmu((size_t)nsys * J), hocc(nsys), htr((size_t)nsys * rs);
   std::vector<int> hfl(6 * (size_t)nsys);
+  double htally[2] = {0.0, 0.0};
   if (rc == DMPT_OK) {
-    if (hipMemcpy(hmu.data(), d_mu, hmu.size() * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+    if (hipMemcpy(htally, c->d_tally, sizeof(htally), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(hmu.data(), d_mu, hmu.size() * 8, hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(hocc.data(), d_occ, hocc.size() * 8, hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(htr.data(), d_tr, htr.size() * 8, hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(hfl.data(), d_flags, hfl.size() * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
@@ -2665,11 +2748,10 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
     st->newton_iters = total_passes;
     st->occ_err = occ_sum;
     st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    // every captured product times the number of replays of its graph (the
-    // products of converged systems are still counted: they are skipped on
-    // the device, not removed from the graph)
-    st->mfma_flops = flops_m;
-    st->useful_flops = flops_u;
+    // products of the members that ran, tallied on the device (useful flops
+    // at the padded size of each bucket)
+    st->mfma_flops = htally[0];
+    st->useful_flops = htally[1];
   }
   if (nonfinite) return fail(c, DMPT_ERR_NONFINITE, "non-finite trace in a batched system");
   if (!all_done) return fail(c, DMPT_ERR_NOCONV, "a batched system did not converge within max_newton");

@@ -83,6 +83,11 @@ struct GemmArgs {
   const int* active;           // optional per-batch mask; 0 = skip the member
   int tile;                    // output tile edge wanted: 0 = largest available, 128, 256
   int acc64;                   // BF16S3 only: FP32 per stage, FP64 across stages (128-wide tiles)
+  // optional executed-work tally (graph replays, where the host cannot see
+  // which members are skipped): every member that runs adds tally_m and
+  // tally_u to tally[0] and tally[1]
+  double* tally;
+  double tally_m, tally_u;
 };
 
 // Output tile edge, and number of output tiles per batch member, of the
@@ -171,6 +176,23 @@ hipError_t expand_mask(const int* src, int div, int* dst, int n, hipStream_t s);
 template <class T>
 hipError_t fill_pattern(T* x, int64_t n, uint32_t seed, uint16_t* const* planes, int nplanes,
                         hipStream_t s);
+
+// Linear canonical correction of one system (batched solve): with t its
+// trace record (Tr P1_z at 1 + z, Tr(H1_z P1_z) at 2J + 1 + z, Tr P_J at rs0,
+// Tr(H1_z P_J) at rs0 + 2 + z), mu / shift its mu jet and shifts, c its
+// scale: delta_z = Tr P1_z / Tr P_J, mu1_z += delta_z, P1[z] -= delta_z PJ
+// (N x N FP64), records updated.  Does nothing while *gate == 0.
+hipError_t lin_correct(double* t, int d, int J, int rs0, double* mu, double* shift, double c,
+                       double* delta, double* const* P1, const double* PJ, int64_t N, const int* gate,
+                       hipStream_t s);
+
+// First guess of mu1 for each of d directions from a converged P0 (N x N FP64):
+// with w_i = (P0 - P0^2)_ii, mu1_z = sum_i w_i (H1_z)_ii / sum_i w_i (the
+// Tr P1 = 0 condition with the response to H1 = I taken as beta P0 (I - P0)
+// and only the diagonal of H1).  w: N doubles of scratch.  Entries z with
+// want[z] == 0 are left as they are (want: device ints).
+hipError_t mu1_guess(const double* P0, int64_t N, const double* const* H1, int d, double* w,
+                     double* mu, double* shift, double c, const int* want, hipStream_t s);
 
 // Device-side canonical Newton update of a batch of systems (see elementwise.hip).
 hipError_t newton_update(const double* tr, int rs, const double* par, double* mu, double* shift,

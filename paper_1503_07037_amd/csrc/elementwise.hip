@@ -493,6 +493,89 @@ __global__ void k_newton(const double* tr, int rs, const double* par, double* mu
   for (int i = 0; i < J; ++i) sh[i] = -c * m[i];
 }
 
+// Linear canonical correction of one system's first-order responses (the
+// order-1 response is affine in mu1 with slope -P_J, P_J the response to
+// H1 = I, Sec. III's Tr P^(1) = 0 condition): thread z takes
+// delta_z = Tr P1_z / Tr P_J, moves mu1_z by it, and updates the trace
+// record (Tr P1_z and Tr(H1_z P1_z)) to the corrected response.
+__global__ void k_lin_delta(double* t, int d, int J, int rs0, double* mu, double* shift, double c,
+                            double* delta, const int* gate) {
+  const int z = threadIdx.x;
+  if (z >= d || (gate && !*gate)) return;
+  const double trj = t[rs0];
+  const double dl = trj != 0.0 ? t[1 + z] / trj : 0.0;
+  delta[z] = dl;
+  t[1 + z] -= dl * trj;
+  t[2 * J + 1 + z] -= dl * t[rs0 + 2 + z];
+  mu[1 + z] += dl;
+  shift[1 + z] = -c * mu[1 + z];
+}
+
+// w_i = (P0 - P0^2)_ii for one row per block (P0 symmetric, FP64, N x N).
+__global__ __launch_bounds__(kT) void k_row_w(const double* P0, int64_t N, double* w) {
+  __shared__ double red[kT / 64];
+  const int64_t i = blockIdx.x;
+  const double* row = P0 + i * N;
+  double s = 0.0;
+  for (int64_t j = threadIdx.x; j < N; j += kT) s += row[j] * row[j];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < kT / 64; ++q) t += red[q];
+    w[i] = row[i] - t;
+  }
+}
+
+struct DiagPtrs {
+  const double* h[8];
+};
+
+// mu1_z = sum_i w_i (H1_z)_ii / sum_i w_i (one block; fixed summation order),
+// written with its shift -c mu1_z where the caller gave no value (want[z]).
+__global__ __launch_bounds__(kT) void k_mu1_guess(const double* w, int64_t N, DiagPtrs h1, int d,
+                                                  double* mu, double* shift, double c,
+                                                  const int* want) {
+  __shared__ double red[kT / 64][9];
+  double acc[9];
+  for (int z = 0; z <= 8; ++z) acc[z] = 0.0;
+  for (int64_t i = threadIdx.x; i < N; i += kT) {
+    const double wi = w[i];
+    acc[8] += wi;
+    for (int z = 0; z < d; ++z) acc[z] += wi * h1.h[z][i * N + i];
+  }
+  for (int z = 0; z <= 8; ++z) {
+    double v = acc[z];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][z] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < d && want[threadIdx.x]) {
+    const int z = threadIdx.x;
+    double num = 0.0, den = 0.0;
+    for (int q = 0; q < kT / 64; ++q) {
+      num += red[q][z];
+      den += red[q][8];
+    }
+    if (den > 1e-12 * (double)N) {
+      mu[1 + z] = num / den;
+      shift[1 + z] = -c * mu[1 + z];
+    }
+  }
+}
+
+// P1 -= delta * PJ over an N x N FP64 caller matrix.
+__global__ __launch_bounds__(kT) void k_lin_axpy(double* P1, const double* PJ, int64_t n,
+                                                 const double* delta, const int* gate) {
+  if (gate && !*gate) return;
+  const double dl = *delta;
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
+    P1[i] -= dl * PJ[i];
+}
+
 inline unsigned red_grid(int64_t n) {
   int64_t b = (n + kT * 8 - 1) / (kT * 8);
   if (b < 1) b = 1;
@@ -709,6 +792,32 @@ hipError_t fill_pattern(T* x, int64_t n, uint32_t seed, uint16_t* const* planes,
 }
 template hipError_t fill_pattern<double>(double*, int64_t, uint32_t, uint16_t* const*, int, hipStream_t);
 template hipError_t fill_pattern<float>(float*, int64_t, uint32_t, uint16_t* const*, int, hipStream_t);
+
+hipError_t lin_correct(double* t, int d, int J, int rs0, double* mu, double* shift, double c,
+                       double* delta, double* const* P1, const double* PJ, int64_t N, const int* gate,
+                       hipStream_t s) {
+  if (d < 1 || d > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_lin_delta, dim3(1), dim3(64), 0, s, t, d, J, rs0, mu, shift, c, delta, gate);
+  hipError_t e = hipGetLastError();
+  for (int z = 0; z < d && e == hipSuccess; ++z) {
+    hipLaunchKernelGGL(k_lin_axpy, dim3(ew_grid(N * N)), dim3(kT), 0, s, P1[z], PJ, N * N, delta + z,
+                       gate);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+hipError_t mu1_guess(const double* P0, int64_t N, const double* const* H1, int d, double* w,
+                     double* mu, double* shift, double c, const int* want, hipStream_t s) {
+  if (d < 1 || d > 8 || N < 1) return hipErrorInvalidValue;
+  DiagPtrs h{};
+  for (int z = 0; z < d; ++z) h.h[z] = H1[z];
+  hipLaunchKernelGGL(k_row_w, dim3((unsigned)N), dim3(kT), 0, s, P0, N, w);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mu1_guess, dim3(1), dim3(kT), 0, s, w, N, h, d, mu, shift, c, want);
+  return hipGetLastError();
+}
 
 hipError_t newton_update(const double* tr, int rs, const double* par, double* mu, double* shift,
                          int J, int nk, double tol, int final_stage, int* active, int* done,

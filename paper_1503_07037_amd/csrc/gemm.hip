@@ -114,12 +114,21 @@ __device__ inline void epi(const GemmArgs& a, int z, int64_t row, int64_t col, d
   if (a.W) dsum += (double)((const T*)a.W)[z * a.sW + off] * (double)out;
 }
 
+// One thread per running member adds the member's work to the tally.
+__device__ inline void count_member(const GemmArgs& a) {
+  if (a.tally && blockIdx.x == 0 && threadIdx.x == 0) {
+    atomicAdd(a.tally, a.tally_m);
+    atomicAdd(a.tally + 1, a.tally_u);
+  }
+}
+
 // ------------------------------------------------------------------ FP64
 constexpr int F64_BK = 8, F64_LD = F64_BK + 1;
 
 __global__ __launch_bounds__(kThreads) void k_gemm_f64(GemmArgs a) {
   const int z = blockIdx.z;
   if (a.active && !a.active[z]) return;
+  count_member(a);
   const int64_t Np = a.Np;
   int tm, tn;
   tile_coords(blockIdx.x, (int)(Np / BM), (int)(Np / BN), tm, tn);
@@ -202,6 +211,7 @@ constexpr int F32_BK = 16, F32_LD = F32_BK + 1;
 __global__ __launch_bounds__(kThreads) void k_gemm_f32(GemmArgs a) {
   const int z = blockIdx.z;
   if (a.active && !a.active[z]) return;
+  count_member(a);
   const int64_t Np = a.Np;
   int tm, tn;
   tile_coords(blockIdx.x, (int)(Np / BM), (int)(Np / BN), tm, tn);
@@ -323,6 +333,7 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_bf16(GemmArgs a) {
   __shared__ double red[NW];
   const int z = blockIdx.z;
   if (a.active && !a.active[z]) return;
+  count_member(a);
   const int64_t Np = a.Np;
   const int64_t kbr = Np >> 4;         // blocks per 32-row block row of a plane
   int tm, tn;

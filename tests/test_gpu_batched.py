@@ -57,7 +57,10 @@ def test_small_uneven_batch(dm, small_batch, prec, order, tol):
         P0, P1, P2, mus, st = ctx.mu_newton_batched(
             [T(s["h0"]) for s in small_batch], [[T(h) for h in s["h1"]] for s in small_batch],
             [s["beta"] for s in small_batch], [s["Ne"] for s in small_batch], n=25, order=order)
-    print(f"  passes={st['newton_iters']} seconds={st['seconds']:.2f}")
+    print(f"  passes={st['newton_iters']} seconds={st['seconds']:.2f} mfma_flops={st['mfma_flops']:.3e}")
+    # executed work is tallied on the device: positive, and at most every captured
+    # product of every system on every replay
+    assert 0.0 < st["mfma_flops"] and st["useful_flops"] <= st["mfma_flops"]
     for k, s in enumerate(small_batch):
         r = s["ref"]
         e0 = np.abs(P0[k].cpu().numpy() - r["P0"]).max()
