@@ -402,6 +402,9 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_bf16(GemmArgs a) {
     const unsigned char* sb = smem + (kt & 1) * SBYTES + lane * 16;
 #pragma unroll
     for (int kk = 0; kk < KB; ++kk) {
+      // fragments in the order the MFMAs below consume them (X plane p with
+      // Y plane S - 1 - p first), so the first products wait for two reads,
+      // not for all of them
       bf8v xa[S][FM], yb[S][FN];
 #pragma unroll
       for (int p = 0; p < S; ++p) {
@@ -409,10 +412,12 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_bf16(GemmArgs a) {
         for (int i = 0; i < FM; ++i)
           xa[p][i] = __builtin_bit_cast(
               bf8v, *(const u4v*)(sb + ((p * NBLK + (wm * FM + i) * KB + kk) << 10)));
+        const int q = S - 1 - p;
 #pragma unroll
         for (int j = 0; j < FN; ++j)
-          yb[p][j] = __builtin_bit_cast(
-              bf8v, *(const u4v*)(sb + (((S + p) * NBLK + (wn * FN + j) * KB + kk) << 10)));
+          yb[q][j] = __builtin_bit_cast(
+              bf8v, *(const u4v*)(sb + (((S + q) * NBLK + (wn * FN + j) * KB + kk) << 10)));
+        __builtin_amdgcn_sched_barrier(0);  // keep this order
       }
       if (kk == 0 && kt + 1 < nk) {
         swrite((kt + 1) & 1);
