@@ -191,8 +191,16 @@ dmpt_status dmpt_mu_newton(dmpt_ctx ctx, int64_t N, const double* H0, int d,
  * <= the context's n_max), with per-system beta and Ne, d directions each.
  * H0s[s], P0s[s]: N_s x N_s device FP64; H1s[s*d + i], P1s[s*d + i],
  * P2s[s*d + i] likewise (P1s / P2s may be NULL for lower orders).  mus
- * (host, nsys * (1 + 2d)) receives each system's jet; st (may be NULL) the
- * aggregate statistics.  Systems converge independently.  order in {0, 1, 2}. */
+ * (host, nsys * (1 + 2d)): in, guesses (NaN: none); out, each system's jet.
+ * st (may be NULL) receives the aggregate statistics; its mfma_flops and
+ * useful_flops count the products of the members that actually ran (tallied
+ * on the device; useful flops at each size bucket's padded size).  Systems
+ * converge independently, one graph replay per Newton update of every
+ * system still active.  order in {0, 1, 2}.  With options.schedule >= 1 and
+ * order 1: mu0 first (order-0 replays, to 1e-2 tol_occ), then mu1 from a
+ * guess out of the converged P0 and one order-1 replay that carries the
+ * response to H1 = I and moves each P1 to Tr P1 = 0 exactly; otherwise (and
+ * at order 2) Algorithm 1's joint Newton. */
 dmpt_status dmpt_mu_newton_batched(dmpt_ctx ctx, int nsys, const int64_t* Ns,
                                    const double* const* H0s, int d, const double* const* H1s,
                                    const double* betas, const double* Nes, int n, int order,
