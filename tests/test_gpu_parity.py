@@ -380,3 +380,31 @@ def test_cubic2048_all_forms(dm, prec, refine, tol):
     t1 = max(abs(a - b) / abs(b) for a, b in zip(st["tr_h1p1"], g["tr_h1p1"]))
     print(f"  errs {e0:.2e} {e1:.2e} {e2:.2e} Tr(H1P1) {t1:.2e} seconds={st['seconds']:.2f}")
     assert e0 < tol and e1 < tol and e2 < tol and t1 < tol
+
+
+# ------------------------------------------------------------------ N = 8192 banded (the benchmark)
+
+@pytest.mark.timeout(600)
+def test_banded8192_benchmark_configuration(dm):
+    """The benchmark's workload and launch configuration (bf16x3 passes, bf16x6 refinement with
+    FP64 slice accumulation, orders 0-2, 3 directions) against the oracle's stored samples."""
+    print("case banded8192 mixed", flush=True)
+    c = workloads.config("banded8192")
+    g = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "banded8192_samples.npz"))
+    with dm.Context(c["N"], dirs_max=len(c["H1"]), prec="bf16x3", refine=1, acc64=1) as ctx:
+        P0, P1, P2, mu, st = ctx.mu_newton(T(c["H0"]), [T(h) for h in c["H1"]], None, beta=c["beta"],
+                                           Ne=c["Ne"], n=c["n"], order=2)
+    ii = torch.as_tensor(g["i"], device=P0.device)
+    jj = torch.as_tensor(g["j"], device=P0.device)
+    e0 = float(np.abs(P0[ii, jj].cpu().numpy() - g["P0"]).max())
+    e1 = max(float(np.abs(p[ii, jj].cpu().numpy() - g["P1"][z]).max() / g["max_P1"][z]) for z, p in enumerate(P1))
+    e2 = max(float(np.abs(p[ii, jj].cpu().numpy() - g["P2"][z]).max() / g["max_P2"][z]) for z, p in enumerate(P2))
+    t1 = max(abs(a - b) / abs(b) for a, b in zip(st["tr_h1p1"], g["tr_h1p1"]))
+    t2 = max(abs(a - b) / abs(b) for a, b in zip(st["tr_h1p2"], g["tr_h1p2"]))
+    print(f"  errs {e0:.2e} {e1:.2e} {e2:.2e} Tr(H1P1) {t1:.2e} Tr(H1P2) {t2:.2e} seconds={st['seconds']:.1f}")
+    assert e0 < 1e-6 and e1 < 1e-6 and e2 < 1e-6 and t1 < 1e-6 and t2 < 1e-6
+    assert abs(mu[0] - float(g["mu0"])) < 1e-6
+    # the canonical conditions hold on the device results
+    assert abs(float(torch.trace(P0)) - c["Ne"]) < 1e-6 * c["N"]
+    for p in P1 + P2:
+        assert abs(float(torch.trace(p))) < 1e-6 * float(p.abs().max()) * c["N"]
