@@ -2703,7 +2703,21 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
         break;
       }
       bool any = false;
-      for (int v : hact) any |= v != 0;
+      int live = 0;
+      for (int v : hact) {
+        any |= v != 0;
+        live += v != 0;
+      }
+      if (c->log) {
+        std::vector<double> hocc_now(nsys), hmu_now((size_t)nsys * J);
+        if (hipMemcpy(hocc_now.data(), d_occ, nsys * 8, hipMemcpyDeviceToHost) == hipSuccess &&
+            hipMemcpy(hmu_now.data(), d_mu, hmu_now.size() * 8, hipMemcpyDeviceToHost) == hipSuccess) {
+          double worst = 0.0;
+          for (int q = 0; q < nsys; ++q) worst = std::max(worst, hocc_now[q] / (double)Ns[slot_sys[q]]);
+          std::fprintf(stderr, "[dmpt] batched stage %d replay %d: %d systems still active, max occ_err/N %.3e\n",
+                       stage, pass + 1, live, worst);
+        }
+      }
       if (!any) break;
     }
     if (c->log)
