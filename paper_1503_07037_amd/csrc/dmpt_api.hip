@@ -2714,8 +2714,11 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
             hipMemcpy(hmu_now.data(), d_mu, hmu_now.size() * 8, hipMemcpyDeviceToHost) == hipSuccess) {
           double worst = 0.0;
           for (int q = 0; q < nsys; ++q) worst = std::max(worst, hocc_now[q] / (double)Ns[slot_sys[q]]);
-          std::fprintf(stderr, "[dmpt] batched stage %d replay %d: %d systems still active, max occ_err/N %.3e\n",
-                       stage, pass + 1, live, worst);
+          std::fprintf(stderr,
+                       "[dmpt] batched stage %d replay %d: %d systems still active, max occ_err/N %.3e, "
+                       "%.3f s since the stage began\n",
+                       stage, pass + 1, live, worst,
+                       std::chrono::duration<double>(std::chrono::steady_clock::now() - ts).count());
         }
       }
       if (!any) break;
