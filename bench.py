@@ -361,7 +361,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sharded "
-              f"design is described in DESIGN.md and not built.", file=sys.stderr)
+              f"path is not built.", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
