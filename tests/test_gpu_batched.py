@@ -121,3 +121,29 @@ def test_batch64_fp32_full_workload(dm):
         worst = max(worst, e0, e1)
     print(f"  worst sampled error {worst:.2e}")
     assert worst < 1e-5
+
+
+@pytest.mark.parametrize("d", [1, 3])
+def test_linear_and_joint_schedules_agree(dm, small_batch, d):
+    """Order 1, FP64: the device-side linear schedule (identity response as an extra direction,
+    exact Tr P1 = 0 correction) and Algorithm 1's joint Newton reach the oracle's fixed point."""
+    print(f"case batched schedules d={d}", flush=True)
+    nmax = max(s["h0"].shape[0] for s in small_batch)
+    out = {}
+    for sched in (0, 1):
+        with dm.Context(nmax, dirs_max=d, prec="fp64", schedule=sched) as ctx:
+            P0, P1, _, mus, st = ctx.mu_newton_batched(
+                [T(s["h0"]) for s in small_batch], [[T(h) for h in s["h1"][:d]] for s in small_batch],
+                [s["beta"] for s in small_batch], [s["Ne"] for s in small_batch], n=25, order=1)
+        out[sched] = (P0, P1, mus)
+        print(f"  schedule {sched}: passes={st['newton_iters']} seconds={st['seconds']:.2f}")
+    for k, s in enumerate(small_batch):
+        r = s["ref"]
+        for sched in (0, 1):
+            P0, P1, mus = out[sched]
+            e0 = np.abs(P0[k].cpu().numpy() - r["P0"]).max()
+            e1 = max(np.abs(P1[k][z].cpu().numpy() - r["P1"][z]).max() / np.abs(r["P1"][z]).max()
+                     for z in range(d))
+            assert e0 < 1e-10 and e1 < 1e-10, (k, sched, e0, e1)
+            for z in range(d):
+                assert abs(mus[k][1 + z] - r["mu1"][z]) < 1e-9 * max(1.0, abs(r["mu1"][z]))
