@@ -2,8 +2,9 @@
 
 Each test checks the oracle against something other than itself: the
 closed forms of Appendix A evaluated independently, the scalar recursions of
-Eq. (Rec_F_2), the Fermi-Dirac limit of Eq. (Rec_F_1), the literal
-Algorithm 1 (dense solves, X-form), canonical finite differences in lambda,
+Eq. (Rec_F_2), the Fermi-Dirac limit of Eq. (Rec_F_1), the matrix recursion
+of Eq. (Rec_F_2) carried out on truncated power series in lambda (X form, no
+eigenvalues), canonical finite differences in lambda,
 special cases with known answers, brute-force sums and the free-energy
 identities of Sec. III.
 """
@@ -14,7 +15,7 @@ import pytest
 
 import oracle as o
 import workloads as w
-import alg1_literal
+import series_recursion as sr
 
 pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
 
@@ -158,18 +159,18 @@ def test_mu_root_is_unique_and_tight():
     assert np.sum(o.phi(ev - (mu - 1e-6), c["beta"], c["n"])) < occ < np.sum(o.phi(ev - (mu + 1e-6), c["beta"], c["n"]))
 
 
-# ---------------------------------------------------------------- Algorithm 1
+# ---------------------------------------------------------------- series evaluation of Eq. (Rec_F_2)
 
 @pytest.mark.parametrize("M,beta", [(6, 4.0), (10, 8.0), (12, 3.0)])
-def test_literal_algorithm1_agrees(M, beta):
-    """The paper's Algorithm 1 (X-form, dense solves, its Newton loop) reaches the oracle's fixed point."""
+def test_series_recursion_canonical_agrees(M, beta):
+    """Eq. (Rec_F_2) on truncated series in lambda (X form, Newton on the mu jet) reaches the oracle's fixed point."""
     n = 14
     rng = np.random.default_rng(M)
     h0 = w.chain_1d(n, M)
     h1 = np.diag(np.arange(n) - n / 2.0)
     h2 = _sym(rng, n, 0.05)
     Ne = 6.0
-    P, mu, _ = alg1_literal.canonical([h0, h1, h2], beta, Ne, M, 2)
+    P, mu, _ = sr.canonical([h0, h1, h2], beta, Ne, M, 2)
     r = o.canonical_response(h0, [h1], [h2], beta, Ne, M, order=2)
     tol = 1e-15 * 2 ** M * 10
     assert np.max(np.abs(P[0] - r["P0"])) < tol
@@ -180,15 +181,15 @@ def test_literal_algorithm1_agrees(M, beta):
     assert abs(mu[2] - r["mu2"][0]) < tol * 100
 
 
-def test_grand_canonical_response_agrees_with_literal_pass():
-    """One pass at a fixed mu jet (no Newton) against the literal recursion."""
+def test_grand_canonical_response_agrees_with_series_pass():
+    """One pass at a fixed mu jet (no Newton) against the series recursion."""
     n, M, beta = 10, 8, 5.0
     rng = np.random.default_rng(11)
     h0 = _sym(rng, n)
     h1 = _sym(rng, n, 0.3)
     h2 = _sym(rng, n, 0.2)
     mu = [0.1, 0.25, -0.4]
-    X = alg1_literal.recursion([h0, h1, h2], beta, M, mu, 2)
+    X = sr.recursion([h0, h1, h2], beta, M, mu, 2)
     r = o.response(h0, [h1], [h2], beta, M, (mu[0], [mu[1]], [mu[2]]), order=2)
     assert np.max(np.abs(X[0] - r["P0"])) < 1e-12
     assert np.max(np.abs(X[1] - r["P1"][0])) < 1e-12
@@ -378,7 +379,7 @@ def test_planted_mistakes_are_caught(monkeypatch):
     n, M, beta, Ne = 12, 10, 5.0, 5.0
     h0 = w.chain_1d(n, 3)
     h1 = np.diag(np.arange(n) - n / 2.0) / n
-    P, mu, _ = alg1_literal.canonical([h0, h1, np.zeros((n, n))], beta, Ne, M, 2)
+    P, mu, _ = sr.canonical([h0, h1, np.zeros((n, n))], beta, Ne, M, 2)
     good = o.canonical_response(h0, [h1], None, beta, Ne, M, order=2)
     assert np.max(np.abs(good["P2"][0] - P[2])) < 1e-10
     orig = o.dmpt_oracle._second_order_kernel
@@ -475,8 +476,8 @@ def test_third_order_kernels_bruteforce():
     assert np.max(np.abs(T3 - ref3)) < 1e-8 * np.max(np.abs(ref3))
 
 
-def test_third_order_agrees_with_literal_algorithm1():
-    """Fixed-mu pass and canonical fixed point at third order against the literal Algorithm 1."""
+def test_third_order_agrees_with_series_recursion():
+    """Fixed-mu pass and canonical fixed point at third order against the series recursion."""
     n, M, beta = 10, 8, 5.0
     rng = np.random.default_rng(12)
     h0 = _sym(rng, n)
@@ -484,7 +485,7 @@ def test_third_order_agrees_with_literal_algorithm1():
     h2 = _sym(rng, n, 0.2)
     h3 = _sym(rng, n, 0.1)
     mu = [0.1, 0.25, -0.4, 0.3]
-    X = alg1_literal.recursion([h0, h1, h2, h3], beta, M, mu, 3)
+    X = sr.recursion([h0, h1, h2, h3], beta, M, mu, 3)
     r = o.response(h0, [h1], [h2], beta, M, (mu[0], [mu[1]], [mu[2]], [mu[3]]), order=3, h3s=[h3])
     assert np.max(np.abs(X[3] - r["P3"][0])) < 1e-11 * max(1.0, np.max(np.abs(X[3])))
     # canonical
@@ -494,7 +495,7 @@ def test_third_order_agrees_with_literal_algorithm1():
     h2 = _sym(rng, n, 0.05)
     h3 = _sym(rng, n, 0.03)
     # the third-order traces are O(100) here: their rounding floor is ~1e-11
-    P, muj, _ = alg1_literal.canonical([h0, h1, h2, h3], beta, Ne, M, 3, tol=1e-10)
+    P, muj, _ = sr.canonical([h0, h1, h2, h3], beta, Ne, M, 3, tol=1e-10)
     rc = o.canonical_response(h0, [h1], [h2], beta, Ne, M, order=3, h3s=[h3])
     tol = 1e-15 * 2 ** M * 10
     assert np.max(np.abs(P[3] - rc["P3"][0])) < tol * np.max(np.abs(rc["P3"][0])) * 100
@@ -548,7 +549,7 @@ def test_third_order_identity_perturbations():
 
 
 def test_planted_third_order_mistakes_are_caught(monkeypatch):
-    """A dropped T3 term or a swapped T2 pair is caught by the literal Algorithm 1 pin."""
+    """A dropped T3 term or a swapped T2 pair is caught by the series recursion pin."""
     n, M, beta = 10, 8, 5.0
     rng = np.random.default_rng(12)
     h0 = _sym(rng, n)
@@ -556,7 +557,7 @@ def test_planted_third_order_mistakes_are_caught(monkeypatch):
     h2 = _sym(rng, n, 0.2)
     h3 = _sym(rng, n, 0.1)
     mu = [0.1, 0.25, -0.4, 0.3]
-    X = alg1_literal.recursion([h0, h1, h2, h3], beta, M, mu, 3)
+    X = sr.recursion([h0, h1, h2, h3], beta, M, mu, 3)
     args = (h0, [h1], [h2], beta, M, (mu[0], [mu[1]], [mu[2]], [mu[3]]))
     orig3 = o.dmpt_oracle._t3
     monkeypatch.setattr(o.dmpt_oracle, "_t3", lambda *a: 0.0 * orig3(*a))
@@ -612,3 +613,122 @@ def test_nonorthogonal_first_order_finite_difference():
     # the congruence with Z^T instead of Z (a plausible slip) is visibly wrong
     bad = o.nonorthogonal_response(f0, [f1], None, z.T, beta, Ne, M, order=1)
     assert np.max(np.abs(bad["D0"] - d_of(0.0))) > 1e-3
+
+
+# ---------------------------------------------------------------- diagonal perturbations given as vectors
+
+def test_diagonal_vector_perturbation_matches_full_matrix():
+    """A diagonal H1 passed as its vector (the scaling branch of the basis rotation) gives the same
+    P1, P2, mu jet and response traces as the same H1 passed as a full matrix, at every order, and the
+    adjoint accepts a diagonal A as a vector; the full-matrix branch is pinned by every other test."""
+    n, M, beta, Ne = 24, 14, 9.0, 11.0
+    rng = np.random.default_rng(71)
+    h0 = w.banded(n, 4, bandwidth=5, decay=3.0)
+    x = np.linspace(-1.0, 1.0, n) + 0.1 * rng.standard_normal(n)
+    h2 = _sym(rng, n, 0.05)
+    h3 = _sym(rng, n, 0.03)
+    rv = o.canonical_response(h0, [x], [h2], beta, Ne, M, order=3, h3s=[h3])
+    rm = o.canonical_response(h0, [np.diag(x)], [h2], beta, Ne, M, order=3, h3s=[h3])
+    for key in ("P1", "P2", "P3"):
+        assert np.max(np.abs(rv[key][0] - rm[key][0])) < 1e-13 * np.max(np.abs(rm[key][0]))
+    for key in ("mu1", "mu2", "mu3", "tr_h1p1", "tr_h1p2", "tr_h1p3"):
+        assert abs(rv[key][0] - rm[key][0]) < 1e-12 * max(1.0, abs(rm[key][0])), key
+    # second-order perturbation as a vector too
+    rv2 = o.canonical_response(h0, [np.diag(x)], [x ** 2], beta, Ne, M, order=2)
+    rm2 = o.canonical_response(h0, [np.diag(x)], [np.diag(x ** 2)], beta, Ne, M, order=2)
+    assert np.max(np.abs(rv2["P2"][0] - rm2["P2"][0])) < 1e-13 * np.max(np.abs(rm2["P2"][0]))
+    assert abs(rv2["tr_h2p0"][0] - rm2["tr_h2p0"][0]) < 1e-12 * abs(rm2["tr_h2p0"][0])
+    # fixed mu jet (grand canonical pass)
+    mu = (0.05, [0.2], [-0.1])
+    pv = o.response(h0, [x], [x], beta, M, mu, order=2)
+    pm = o.response(h0, [np.diag(x)], [np.diag(x)], beta, M, mu, order=2)
+    assert np.max(np.abs(pv["P2"][0] - pm["P2"][0])) < 1e-13 * np.max(np.abs(pm["P2"][0]))
+    # the adjoint with A = diag(x) as a vector
+    gv = o.adjoint_grad(h0, beta, Ne, M, x)
+    gm = o.adjoint_grad(h0, beta, Ne, M, np.diag(x))
+    assert np.max(np.abs(gv - gm)) < 1e-13 * np.max(np.abs(gm))
+
+
+def test_diagonal_vector_against_series_recursion():
+    """The vector form of a diagonal H1 against the power-series recursion, which never sees vectors."""
+    n, M, beta, Ne = 12, 10, 5.0, 5.0
+    h0 = w.chain_1d(n, 5)
+    x = (np.arange(n) - n / 2.0) / n
+    P, mu, _ = sr.canonical([h0, np.diag(x), np.zeros((n, n))], beta, Ne, M, 2)
+    r = o.canonical_response(h0, [x], None, beta, Ne, M, order=2)
+    assert np.max(np.abs(r["P1"][0] - P[1])) < 1e-10 * np.max(np.abs(P[1]))
+    assert np.max(np.abs(r["P2"][0] - P[2])) < 1e-10 * np.max(np.abs(P[2]))
+    assert abs(r["tr_h1p1"][0] - float(np.sum(x * np.diag(P[1])))) < 1e-10 * abs(r["tr_h1p1"][0])
+
+
+def test_planted_row_column_slip_in_diagonal_branch_is_caught(monkeypatch):
+    """Scaling the columns of V by h (h[None, :] * V, which gives V^T V diag(h) = diag(h)) instead of
+    its rows (diag(h) V, giving V^T diag(h) V) changes P1 and Tr(H1 P1) far beyond rounding."""
+    n, M, beta, Ne = 16, 12, 6.0, 7.0
+    h0 = w.chain_1d(n, 9)
+    x = np.linspace(-2.0, 2.0, n)
+    good = o.canonical_response(h0, [np.diag(x)], None, beta, Ne, M, order=2)
+    orig = o.dmpt_oracle._rot
+
+    def slipped(v, h):
+        if h is not None and h.ndim == 1:
+            return v.T @ (h[None, :] * v)
+        return orig(v, h)
+
+    monkeypatch.setattr(o.dmpt_oracle, "_rot", slipped)
+    bad = o.canonical_response(h0, [x], None, beta, Ne, M, order=2)
+    assert np.max(np.abs(bad["P1"][0] - good["P1"][0])) > 1e-3 * np.max(np.abs(good["P1"][0]))
+    assert abs(bad["tr_h1p1"][0] - good["tr_h1p1"][0]) > 1e-3 * abs(good["tr_h1p1"][0])
+
+
+# ---------------------------------------------------------------- range of the recursion (Appendix A)
+
+@pytest.mark.parametrize("M,beta", [(4, 3.0), (10, 40.0), (20, 7.0), (30, 40.0)])
+def test_range_ok_is_appendix_a_interval(M, beta):
+    """range_ok(e) holds exactly when the start x = 1/2 - beta e / (4 n), n = 2^M, of Appendix A's
+    Pade form lies in the open interval (0, 1).  At the edge x = 0 the recursion is stuck at 0 and
+    beyond it the occupation computed by the scalar X-form recursion rises again with the energy:
+    the monotone Fermi-like map is lost exactly where range_ok turns false."""
+    n = 2.0 ** M
+    edge = 2.0 * n / beta                      # x = 0 at e = +edge, x = 1 at e = -edge
+    inside = [0.0, 0.5 * edge, edge * (1 - 1e-9), -edge * (1 - 1e-9)]
+    outside = [edge * (1 + 1e-9), -edge * (1 + 1e-9), 3.0 * edge, -7.0 * edge]
+    for e in inside:
+        x = 0.5 - beta * e / (4.0 * n)
+        assert 0.0 < x < 1.0
+        assert o.range_ok(np.array([e]), beta, M)
+    for e in outside:
+        x = 0.5 - beta * e / (4.0 * n)
+        assert not (0.0 < x < 1.0)
+        assert not o.range_ok(np.array([e]), beta, M)
+    # a spectrum is in range only when every eigenvalue is
+    assert not o.range_ok(np.array(inside + outside[:1]), beta, M)
+    assert o.range_ok(np.array(inside), beta, M)
+    # the closed forms refuse exactly the out-of-range energies
+    with pytest.raises(ValueError):
+        o.phi(np.array([outside[0]]), beta, M)
+    with pytest.raises(ValueError):
+        o.phi_pade(np.array([outside[1]]), beta, M)
+
+
+def test_range_edge_breaks_monotone_occupation():
+    """Scalar X-form recursion of Eq. (Rec_F_2) across the range edge: decreasing in e inside,
+    stuck at 0 on the edge, increasing in e beyond it."""
+    M, beta = 3, 2.0
+    n = 2.0 ** M
+    edge = 2.0 * n / beta
+
+    def occ(e):
+        x = 0.5 - beta * e / (4.0 * n)
+        for _ in range(M):
+            x = x * x / (x * x + (1.0 - x) ** 2)
+        return x
+
+    es = np.linspace(0.9 * edge, 0.999 * edge, 20)
+    vals = [occ(e) for e in es]
+    assert all(a > b for a, b in zip(vals, vals[1:]))
+    assert occ(edge) == 0.0
+    beyond = [occ(e) for e in np.linspace(1.01 * edge, 1.5 * edge, 20)]
+    assert all(b > a for a, b in zip(beyond, beyond[1:]))
+    assert all(o.range_ok(np.array([e]), beta, M) for e in es)
+    assert not any(o.range_ok(np.array([e]), beta, M) for e in np.linspace(1.01 * edge, 1.5 * edge, 20))
