@@ -26,9 +26,11 @@
  *     full and are symmetric.  The library keeps no reference to caller
  *     buffers after a call returns.  A diagonal perturbation must still be
  *     passed as a full matrix.
- *   - Work is queued on the context's HIP stream.  A call returns after the
- *     values it reports on the host (statistics, the mu jet) are final; output
- *     matrices are complete when the call returns.
+ *   - Work is queued on the context's HIP stream, in order with the work the
+ *     caller queued before the call on the stream given to dmpt_init (see
+ *     there for NULL).  A call returns after the values it reports on the
+ *     host (statistics, the mu jet) are final; output matrices are complete
+ *     when the call returns.
  *   - Errors are status codes; nothing is thrown across the ABI.  Arguments
  *     are checked on the host before any device work; dmpt_last_error()
  *     describes the most recent failure of a context.
@@ -56,13 +58,18 @@ typedef enum {
   DMPT_ERR_UNSUPPORTED = -7 /* feature not built for this configuration */
 } dmpt_status;
 
-/* Arithmetic of the matrix products and of the iterates.  Every mode keeps
- * FP64 for traces, norms, the mu jet and the reported outputs. */
+/* Arithmetic of the matrix products.  Every mode keeps the iterates (the
+ * D^(k) of every step, the solver vectors) in FP64 storage, and FP64 for
+ * traces, norms, the mu jet and the reported outputs; the modes differ in
+ * the products only. */
 typedef enum {
-  DMPT_FP64 = 0,    /* FP64 iterates, FP64 MFMA products */
-  DMPT_FP32 = 1,    /* FP32 iterates, FP32 MFMA products */
-  DMPT_BF16X3 = 2,  /* FP32 iterates; products as hi*hi + hi*lo + lo*hi of BF16 splits, FP32 accumulation */
-  DMPT_BF16X6 = 3   /* FP32 iterates; three-way BF16 split, six cross products, FP32 accumulation */
+  DMPT_FP64 = 0,    /* FP64 MFMA products */
+  DMPT_FP32 = 1,    /* operands rounded to FP32, FP32 MFMA products; each 16-wide slice of the
+                       inner index is summed in FP32 and the slices in FP64 */
+  DMPT_BF16X3 = 2,  /* products as hi*hi + hi*lo + lo*hi of two-way BF16 splits, FP32 accumulation */
+  DMPT_BF16X6 = 3   /* three-way BF16 split, the six cross products with p + q <= 2; with
+                       options.acc64 each 32-wide slice of the inner index is summed in FP32
+                       and the slices in FP64 */
 } dmpt_prec;
 
 /* Per-step linear solver for T' Y = R, T' = I + 4 D^2 (2 T of Algorithm 1). */
@@ -112,18 +119,42 @@ typedef struct {
 
 #define DMPT_MAX_DIRS 8
 
+/* Bits of dmpt_stats.flags. */
+#define DMPT_FLAG_NOISE_FLOOR 1  /* the Newton loop accepted a normalised occupation error that had
+                                    stopped shrinking (between tol_occ and 1000 tol_occ: the traces
+                                    carry the products' rounding) instead of one below tol_occ */
+#define DMPT_FLAG_CG_FLOOR 2     /* a solve of a graph-replayed (batched) pass ended its fixed,
+                                    a-priori iteration count above tol_cg; cg_unconverged counts them */
+
 typedef struct {
-  int newton_iters;                      /* Newton passes executed */
-  int cg_iters_total;                    /* CG iterations summed over steps, orders and directions */
+  int newton_iters;                      /* Newton passes executed (batched: graph replays) */
+  int cg_iters_total;                    /* CG iterations summed over steps, orders, directions (and
+                                            systems) */
   int cg_iters_max;                      /* largest CG iteration count of a single solve */
+  int flags;                             /* DMPT_FLAG_* */
+  int cg_unconverged;                    /* solves that ended above tol_cg (graph-replayed passes) */
   double occ_err;                        /* |Tr P0 - Ne| + sum_k |Tr P^(k)| of the returned P */
   double mu[1 + 3 * DMPT_MAX_DIRS];      /* mu0, mu1[d], mu2[d], mu3[d] used for the returned P */
   double trP[1 + 3 * DMPT_MAX_DIRS];     /* Tr P0, Tr P1[d], Tr P2[d], Tr P3[d] */
   double tr_pmu;                         /* Tr P_mu = beta (Tr P0 - ||P0||_F^2) */
-  double tr_h1p1[DMPT_MAX_DIRS];         /* Tr(H1 P1) per direction */
-  double tr_h1p2[DMPT_MAX_DIRS];         /* Tr(H1 P2) per direction */
-  double tr_h2p0[DMPT_MAX_DIRS];         /* Tr(H2 P0) per direction (0 when H2 is absent) */
-  double tr_h1p3[DMPT_MAX_DIRS];         /* Tr(H1 P3) per direction (order 3) */
+  /* Response traces Tr[H^(k) P^(j)] per direction (Sec. III, Eq. Resp_0), with
+   * H^(k) used through its symmetric part and an absent H2 / H3 counting as 0;
+   * computed on the returned matrices for k >= 1, j <= order, k + j <= order + 1 */
+  double tr_h1p1[DMPT_MAX_DIRS];         /* Tr(H1 P1) */
+  double tr_h1p2[DMPT_MAX_DIRS];         /* Tr(H1 P2) (order >= 2) */
+  double tr_h2p0[DMPT_MAX_DIRS];         /* Tr(H2 P0) (order >= 2) */
+  double tr_h1p3[DMPT_MAX_DIRS];         /* Tr(H1 P3) (order 3) */
+  double tr_h1p0[DMPT_MAX_DIRS];         /* Tr(H1 P0) (order >= 1) */
+  double tr_h2p1[DMPT_MAX_DIRS];         /* Tr(H2 P1) (order >= 2) */
+  double tr_h2p2[DMPT_MAX_DIRS];         /* Tr(H2 P2) (order 3) */
+  double tr_h3p0[DMPT_MAX_DIRS];         /* Tr(H3 P0) (order 3) */
+  double tr_h3p1[DMPT_MAX_DIRS];         /* Tr(H3 P1) (order 3) */
+  /* Free-energy responses by Eq. Resp_0, Omega^(m) = (1/m) sum_{k=1..m} k Tr[H^(k) P^(m-k)]
+   * (H^(k) = 0 for k > order): Omega^(m) for m <= order + 1, 0 otherwise */
+  double omega1[DMPT_MAX_DIRS];          /* Tr(H1 P0) */
+  double omega2[DMPT_MAX_DIRS];          /* Tr(H1 P1) / 2 + Tr(H2 P0) */
+  double omega3[DMPT_MAX_DIRS];          /* (Tr(H1 P2) + 2 Tr(H2 P1) + 3 Tr(H3 P0)) / 3 */
+  double omega4[DMPT_MAX_DIRS];          /* (Tr(H1 P3) + 2 Tr(H2 P2) + 3 Tr(H3 P1)) / 4 */
   double idempotency;                    /* Tr[P0 (I - P0)] (check = 1) */
   double commutator;                     /* ||H0 P0 - P0 H0||_F (check = 1) */
   double asymmetry;                      /* max |P - P^T| over the outputs (check = 1) */
@@ -138,8 +169,14 @@ void dmpt_default_options(dmpt_options* opt);
 /* Create a context on HIP device `device` able to handle N <= n_max
  * (1 <= n_max <= 65408) and up to dirs_max perturbation directions.  All device workspace is allocated
  * here (sized by n_max, dirs_max and opt->prec) and freed in
- * dmpt_finalize.  `hip_stream` is a hipStream_t to queue work on; NULL
- * creates a private stream.  opt may be NULL (defaults). */
+ * dmpt_finalize.  `hip_stream` is the caller's hipStream_t: the context
+ * queues its work on it, in order with the caller's own work.  NULL stands
+ * for the null (default) stream: the context then queues on a private
+ * stream, and every entry point first makes that stream wait for the work
+ * already queued on the null stream (an event recorded there) and at the
+ * end makes the null stream wait for the context's work, so inputs written
+ * by earlier kernels on the null stream are complete before they are read.
+ * opt may be NULL (defaults). */
 dmpt_status dmpt_init(dmpt_ctx* ctx, int device, int64_t n_max, int dirs_max,
                       const dmpt_options* opt, void* hip_stream);
 

@@ -475,8 +475,12 @@ def canonical_response(h0, h1s, h2s, beta, Ne, M, order=2, eigh=None, h3s=None):
     Tr P1 = 0; mu2 = (Tr Q + sum_i phi'(e_i) (V^T H2 V)_ii) / sum_i phi'(e_i)
     makes Tr P2 = 0; mu3 likewise with the third-order terms (each P^(k) is
     affine in mu^(k) with slope -phi'(K)).  Returns a dict with P0, P1, P2,
-    P3, mu0, mu1, mu2, mu3, and the response traces tr_h1p1[d] = Tr(H1 P1),
-    tr_h1p2[d] = Tr(H1 P2), tr_h2p0[d] = Tr(H2 P0), tr_h1p3[d] = Tr(H1 P3).
+    P3, mu0, mu1, mu2, mu3, the response traces tr_hkpj[d] = Tr(H^(k) P^(j))
+    for k >= 1, j <= order, k + j <= order + 1 (tr_h1p0, tr_h1p1, tr_h1p2,
+    tr_h1p3, tr_h2p0, tr_h2p1, tr_h2p2, tr_h3p0, tr_h3p1 as far as the order
+    reaches; an absent H2 or H3 counts as zero) and the free-energy responses
+    omega1 .. omega(order + 1) of Sec. III, Eq. (Resp_0):
+    Omega^(m) = (1/m) sum_{k=1..m} k Tr[H^(k) P^(m-k)], H^(k) = 0 beyond the order.
     """
     w, v = eigh if eigh is not None else eig(h0)
     n = w.size
@@ -529,7 +533,38 @@ def canonical_response(h0, h1s, h2s, beta, Ne, M, order=2, eigh=None, h3s=None):
             res["P3"].append(P3)
             res["mu3"].append(mu3)
             res["tr_h1p3"].append(float(np.sum(0.5 * (h1m + h1m.T) * P3)))
+    _response_traces(res, h1s, h2s, h3s, order)
     return res
+
+
+def _response_traces(res, h1s, h2s, h3s, order):
+    """Tr[H^(k) P^(j)] for k >= 1, k + j <= order + 1, and Omega^(m), m <= order + 1 (Eq. Resp_0)."""
+    def full(h):
+        if h is None:
+            return None
+        h = np.diag(h) if np.ndim(h) == 1 else np.asarray(h)
+        return 0.5 * (h + h.T)
+
+    for d in range(len(h1s)):
+        H = {1: full(h1s[d]),
+             2: full(h2s[d]) if (order >= 2 and h2s is not None) else None,
+             3: full(h3s[d]) if (order >= 3 and h3s is not None) else None}
+        P = {0: res["P0"]}
+        for j in range(1, order + 1):
+            P[j] = res["P%d" % j][d]
+        tr = {}
+        for k in range(1, order + 1):
+            for j in range(0, order + 2 - k):
+                if j > order:
+                    continue
+                tr[(k, j)] = 0.0 if H[k] is None else float(np.sum(H[k] * P[j]))
+                key = "tr_h%dp%d" % (k, j)
+                if key in ("tr_h1p1", "tr_h1p2", "tr_h2p0", "tr_h1p3"):
+                    continue  # already filled above
+                res.setdefault(key, []).append(tr[(k, j)])
+        for m in range(1, order + 2):
+            om = sum(k * tr.get((k, m - k), 0.0) for k in range(1, m + 1) if k <= order) / m
+            res.setdefault("omega%d" % m, []).append(om)
 
 
 def adjoint_grad(h0, beta, Ne, M, A, eigh=None):

@@ -41,14 +41,21 @@ class Options(ctypes.Structure):
     ]
 
 
+FLAG_NOISE_FLOOR = 1
+FLAG_CG_FLOOR = 2
+
+_TRACES = ["tr_h1p1", "tr_h1p2", "tr_h2p0", "tr_h1p3", "tr_h1p0", "tr_h2p1", "tr_h2p2", "tr_h3p0",
+           "tr_h3p1", "omega1", "omega2", "omega3", "omega4"]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [
         ("newton_iters", ctypes.c_int), ("cg_iters_total", ctypes.c_int),
-        ("cg_iters_max", ctypes.c_int), ("occ_err", ctypes.c_double),
+        ("cg_iters_max", ctypes.c_int), ("flags", ctypes.c_int), ("cg_unconverged", ctypes.c_int),
+        ("occ_err", ctypes.c_double),
         ("mu", ctypes.c_double * (1 + 3 * MAX_DIRS)), ("trP", ctypes.c_double * (1 + 3 * MAX_DIRS)),
-        ("tr_pmu", ctypes.c_double), ("tr_h1p1", ctypes.c_double * MAX_DIRS),
-        ("tr_h1p2", ctypes.c_double * MAX_DIRS), ("tr_h2p0", ctypes.c_double * MAX_DIRS),
-        ("tr_h1p3", ctypes.c_double * MAX_DIRS),
+        ("tr_pmu", ctypes.c_double),
+    ] + [(name, ctypes.c_double * MAX_DIRS) for name in _TRACES] + [
         ("idempotency", ctypes.c_double), ("commutator", ctypes.c_double),
         ("asymmetry", ctypes.c_double), ("mfma_flops", ctypes.c_double),
         ("useful_flops", ctypes.c_double), ("seconds", ctypes.c_double),
@@ -56,15 +63,16 @@ class Stats(ctypes.Structure):
 
     def as_dict(self, d=0, order=0):
         nmu = 1 + order * d
-        return dict(
+        out = dict(
             newton_iters=self.newton_iters, cg_iters_total=self.cg_iters_total,
-            cg_iters_max=self.cg_iters_max, occ_err=self.occ_err,
-            mu=list(self.mu[:nmu]), trP=list(self.trP[:nmu]), tr_pmu=self.tr_pmu,
-            tr_h1p1=list(self.tr_h1p1[:d]), tr_h1p2=list(self.tr_h1p2[:d]),
-            tr_h2p0=list(self.tr_h2p0[:d]), tr_h1p3=list(self.tr_h1p3[:d]),
+            cg_iters_max=self.cg_iters_max, flags=self.flags, cg_unconverged=self.cg_unconverged,
+            occ_err=self.occ_err, mu=list(self.mu[:nmu]), trP=list(self.trP[:nmu]), tr_pmu=self.tr_pmu,
             idempotency=self.idempotency,
             commutator=self.commutator, asymmetry=self.asymmetry, mfma_flops=self.mfma_flops,
             useful_flops=self.useful_flops, seconds=self.seconds)
+        for name in _TRACES:
+            out[name] = list(getattr(self, name)[:d])
+        return out
 
 
 class ProfileData(ctypes.Structure):

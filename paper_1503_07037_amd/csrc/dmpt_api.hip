@@ -62,6 +62,11 @@ struct dmpt_ctx_s {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // private stream standing in for the null stream: every entry point
+  // orders it after the null stream's queued work (ev_in) and the null
+  // stream after it (ev_out)
+  bool sync_null = false;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
   int64_t n_max = 0, np_max = 0;
   int dirs_max = 0;
   dmpt_options opt{};
@@ -121,6 +126,10 @@ struct dmpt_ctx_s {
   long cg_total = 0;
   int cg_max = 0;
   bool cg_capped = false;
+  int flags = 0;                 // DMPT_FLAG_* of the call
+  long cg_unconv = 0;            // graph-replayed solves that ended above tol_cg
+  // graph-replayed solves: [0] iterations summed, [1] largest count, [2] unconverged solves
+  int* d_cgstat = nullptr;
 };
 
 namespace {
@@ -130,14 +139,15 @@ enum : int {
   RES_TR = 0,                          // Tr P0, Tr P1[d], Tr P2[d], Tr P3[d]
   RES_ATR = RES_TR + 1 + 3 * DMPT_MAX_DIRS,
   RES_FRO = RES_ATR + 1 + 3 * DMPT_MAX_DIRS,
-  RES_H1P1 = RES_FRO + 1,
-  RES_H1P2 = RES_H1P1 + DMPT_MAX_DIRS,
-  RES_H1P3 = RES_H1P2 + DMPT_MAX_DIRS,
-  RES_H2P0 = RES_H1P3 + DMPT_MAX_DIRS,
-  RES_MISC = RES_H2P0 + DMPT_MAX_DIRS,  // scratch scalars
+  // response traces Tr[H^(k) P^(j)], k = 1..3, j = 0..3, per direction:
+  // RES_HP + ((k - 1) * 4 + j) * DMPT_MAX_DIRS + z
+  RES_HP = RES_FRO + 1,
+  RES_MISC = RES_HP + 12 * DMPT_MAX_DIRS,  // scratch scalars
   RES_HALF = RES_MISC + 15,             // constant 1/2
   RES_COUNT = RES_MISC + 16
 };
+
+inline int res_hp(int k, int j, int z) { return RES_HP + ((k - 1) * 4 + j) * DMPT_MAX_DIRS + z; }
 
 dmpt_status fail(dmpt_ctx c, dmpt_status s, const std::string& msg) {
   if (c) c->err = msg;
@@ -158,6 +168,31 @@ dmpt_status fail(dmpt_ctx c, dmpt_status s, const std::string& msg) {
     if (s_ != DMPT_OK) return s_;      \
   } while (0)
 
+// A context created without a caller stream works on a private stream that
+// stands in for the null stream: order it after the work already queued on
+// the null stream before any device work of a call ...
+dmpt_status enter_call(dmpt_ctx c) {
+  if (c->sync_null) {
+    HIPCHK(c, hipEventRecord(c->ev_in, nullptr));
+    HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_in, 0));
+  }
+  return DMPT_OK;
+}
+
+// ... and the null stream after the call's work, on every return path.
+struct CallScope {
+  dmpt_ctx c = nullptr;
+  ~CallScope() {
+    if (c && c->sync_null && hipEventRecord(c->ev_out, c->stream) == hipSuccess)
+      (void)hipStreamWaitEvent(nullptr, c->ev_out, 0);
+  }
+};
+
+#define ENTER(ctx)             \
+  CallScope scope_{};          \
+  STCHK(enter_call(ctx));      \
+  scope_.c = (ctx)
+
 Engine engine_of(dmpt_prec p) {
   switch (p) {
     case DMPT_FP64: return Engine::F64;
@@ -172,7 +207,7 @@ double default_tol_cg(dmpt_prec p, int refine) {
   if (p == DMPT_BF16X3 && refine) p = DMPT_BF16X6;
   switch (p) {
     case DMPT_FP64: return 1e-14;
-    case DMPT_FP32: return 1e-7;
+    case DMPT_FP32: return 1e-9;
     case DMPT_BF16X3: return 1e-5;
     case DMPT_BF16X6: return 1e-9;
   }
@@ -189,7 +224,7 @@ double default_tol_occ(dmpt_prec p, int refine) {
   if (p == DMPT_BF16X3 && refine) p = DMPT_BF16X6;
   switch (p) {
     case DMPT_FP64: return 1e-12;
-    case DMPT_FP32: return 1e-6;
+    case DMPT_FP32: return 1e-7;
     case DMPT_BF16X3: return 1e-6;
     case DMPT_BF16X6: return 1e-7;
   }
@@ -202,8 +237,9 @@ int planes_needed(const dmpt_options& o) {
   return p;
 }
 
-// Master copies are FP64 except in the all-FP32 mode.
-size_t esize_needed(const dmpt_options& o) { return o.prec == DMPT_FP32 ? 4 : 8; }
+// Master copies (iterates, solver vectors) are FP64 in every mode; the
+// modes differ in the products only.
+size_t esize_needed(const dmpt_options&) { return 8; }
 
 // ------------------------------------------------------------------ views
 struct Call {
@@ -213,7 +249,6 @@ struct Call {
   int np;                        // planes used by the engine
   int64_t N, Np, nn;             // nn = Np*Np
   int64_t stride;                // member stride of every group (elements)
-  bool f64;                      // FP64 master copies
   double tol_cg;                 // relative residual of every solve of this pass
   int m = 1;                     // systems in the pass (members of D0, S0)
   bool graph = false;            // no host synchronisation: fixed CG iteration counts
@@ -525,7 +560,11 @@ dmpt_status cg_solve(const Call& k, const Group& u, int batch, int ydiv, const i
     HIPCHK(c, cg_check(w->rr + it + 1, w->rr, w->ref, hs, batch, tol * tol, kEta * kEta, w->active,
                        w->iters, s));
   }
-  if (k.graph) return DMPT_OK;  // counters are read by the caller after the pass
+  if (k.graph) {
+    // fixed-count solve: its statistics accumulate on the device (read after the replays)
+    HIPCHK(c, cg_account(w->active, w->iters, batch, c->d_cgstat, s));
+    return DMPT_OK;
+  }
   HIPCHK(c, hipMemcpyAsync(c->h_int, w->active, batch * sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipMemcpyAsync(c->h_int + kIterSlot, w->iters, batch * sizeof(int),
                            hipMemcpyDeviceToHost, s));
@@ -818,7 +857,6 @@ dmpt_status ns_solve(const Call& k, const Group& g, int md) {
     // the products that formed R wrote its master only
     uint16_t* pr[3];
     planes_of(k, w->R, 0, pr);
-    if (!k.f64) return fail(k.c, DMPT_ERR_ARG, "internal: split planes need FP64 masters");
     HIPCHK(k.c, split_planes((const double*)mptr(k, w->R, 0), k.nn, k.stride, pr, k.stride, k.np, md,
                              k.c->stream));
   }
@@ -889,7 +927,6 @@ template <class T>
 dmpt_status recursion_step(const Call& k, int order, int d, int step) {
   dmpt_ctx c = k.c;
   const WS* w = k.w;
-  const int hs = k.c->hstride;
   const int md = k.m * d;
   STCHK(square0<T>(k));
   const bool ns = c->opt.solver == DMPT_SOLVER_NS && k.m == 1 && !k.graph;
@@ -1103,8 +1140,8 @@ dmpt_status recursion_pass(const Call& k, const PassIn& in) {
 }
 
 // Outputs and traces of a pass: P0 = I/2 - D0, P^(k) = -D^(k) (FP64,
-// caller buffers), Tr P^(k), sum |P^(k)_ii|, ||P0||_F^2 and the response
-// traces; then one synchronisation and the values land in c->h_res.
+// caller buffers), Tr P^(k), sum |P^(k)_ii| and ||P0||_F^2; then one
+// synchronisation and the values land in c->h_res.
 template <class T>
 dmpt_status finish_pass(const Call& k, const PassIn& in, double* P0, double* const* P1,
                         double* const* P2, double* const* P3) {
@@ -1126,25 +1163,38 @@ dmpt_status finish_pass(const Call& k, const PassIn& in, double* P0, double* con
                                         0, Pk[z], k.N, 0, nullptr, 0, 1, s)));
       HIPCHK(c, trace(Pk[z], k.N, 0, k.N, 1, c->d_res + RES_TR + slot, 1,
                       c->d_res + RES_ATR + slot, s));
-      // Tr(H1 P^(k)) = <sym H1, P^(k)> = <H1, P^(k)> since P^(k) is symmetric
-      if (in.H1[z]) {
-        HIPCHK(c, dot_partials<double>(in.H1[z], 0, Pk[z], 0, k.N * k.N, 1, c->d_part, s));
-        HIPCHK(c, sum_partials(c->d_part, reduce_blocks(k.N * k.N), 1,
-                               c->d_res + (ord == 1 ? RES_H1P1 : (ord == 2 ? RES_H1P2 : RES_H1P3)) + z,
-                               1, 0, s));
-      }
-      if (ord == 2) {
-        if (in.H2 && in.H2[z]) {
-          HIPCHK(c, dot_partials<double>(in.H2[z], 0, P0, 0, k.N * k.N, 1, c->d_part, s));
-          HIPCHK(c, sum_partials(c->d_part, reduce_blocks(k.N * k.N), 1, c->d_res + RES_H2P0 + z, 1,
-                                 0, s));
-        } else {
-          HIPCHK(c, set_values(nullptr, 0, 0, c->d_res + RES_H2P0 + z, 0.0, 1, s));
-        }
-      }
     }
   }
   HIPCHK(c, hipMemcpyAsync(c->h_res, c->d_res, RES_MISC * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  return DMPT_OK;
+}
+
+// Response traces Tr[H^(k) P^(j)] of the returned matrices (Sec. III, Eq.
+// Resp_0) for k = 1..order, j = 0..order, k + j <= order + 1, every
+// direction: <sym H^(k), P^(j)> = <H^(k), P^(j)> since P^(j) is symmetric; an
+// absent H2 / H3 gives 0.  Lands in c->h_res after one synchronisation.
+dmpt_status response_traces(dmpt_ctx c, int64_t N, const PassIn& in, const double* P0,
+                            double* const* P1, double* const* P2, double* const* P3) {
+  hipStream_t s = c->stream;
+  const int64_t nn = N * N;
+  for (int kk = 1; kk <= in.order; ++kk)
+    for (int z = 0; z < in.d; ++z) {
+      const double* h = kk == 1 ? in.H1[z]
+                                : (kk == 2 ? (in.H2 ? in.H2[z] : nullptr) : (in.H3 ? in.H3[z] : nullptr));
+      for (int j = 0; j <= in.order && kk + j <= in.order + 1; ++j) {
+        double* out = c->d_res + res_hp(kk, j, z);
+        const double* P = j == 0 ? P0 : (j == 1 ? P1[z] : (j == 2 ? P2[z] : P3[z]));
+        if (!h) {
+          HIPCHK(c, set_values(nullptr, 0, 0, out, 0.0, 1, s));
+          continue;
+        }
+        HIPCHK(c, dot_partials<double>(h, 0, P, 0, nn, 1, c->d_part, s));
+        HIPCHK(c, sum_partials(c->d_part, reduce_blocks(nn), 1, out, 1, 0, s));
+      }
+    }
+  HIPCHK(c, hipMemcpyAsync(c->h_res + RES_HP, c->d_res + RES_HP, 12 * DMPT_MAX_DIRS * sizeof(double),
+                           hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
   return DMPT_OK;
 }
@@ -1219,7 +1269,6 @@ Call make_call(dmpt_ctx c, int64_t N, bool refined) {
   k.Np = padded(N);
   k.nn = k.Np * k.Np;
   k.stride = c->np_max * c->np_max;
-  k.f64 = c->esize == 8;
   k.tol_cg = c->opt.tol_cg;
   return k;
 }
@@ -1229,6 +1278,8 @@ void reset_stats(dmpt_ctx c) {
   c->cg_total = 0;
   c->cg_max = 0;
   c->cg_capped = false;
+  c->flags = 0;
+  c->cg_unconv = 0;
 }
 
 void fill_stats(dmpt_ctx c, const PassIn& in, dmpt_stats* st, int newton, double occ_err, double secs) {
@@ -1237,19 +1288,34 @@ void fill_stats(dmpt_ctx c, const PassIn& in, dmpt_stats* st, int newton, double
   st->newton_iters = newton;
   st->cg_iters_total = (int)c->cg_total;
   st->cg_iters_max = c->cg_max;
+  st->flags = c->flags;
+  st->cg_unconverged = (int)c->cg_unconv;
   st->occ_err = occ_err;
   const int d = in.order >= 1 ? in.d : 0;
   const int nmu = 1 + in.order * d;
   for (int i = 0; i < nmu; ++i) st->mu[i] = in.mu[i];
   for (int i = 0; i < nmu; ++i) st->trP[i] = c->h_res[RES_TR + i];
   st->tr_pmu = in.beta * (c->h_res[RES_TR] - c->h_res[RES_FRO]);
+  // response traces Tr[H^(k) P^(j)] (0 where not computed) and Eq. Resp_0
+  auto hp = [&](int kk, int j, int z) -> double {
+    return (kk <= in.order && j <= in.order && kk + j <= in.order + 1) ? c->h_res[res_hp(kk, j, z)] : 0.0;
+  };
   for (int z = 0; z < d; ++z) {
-    st->tr_h1p1[z] = c->h_res[RES_H1P1 + z];
-    if (in.order >= 2) {
-      st->tr_h1p2[z] = c->h_res[RES_H1P2 + z];
-      st->tr_h2p0[z] = c->h_res[RES_H2P0 + z];
+    st->tr_h1p0[z] = hp(1, 0, z);
+    st->tr_h1p1[z] = hp(1, 1, z);
+    st->tr_h1p2[z] = hp(1, 2, z);
+    st->tr_h1p3[z] = hp(1, 3, z);
+    st->tr_h2p0[z] = hp(2, 0, z);
+    st->tr_h2p1[z] = hp(2, 1, z);
+    st->tr_h2p2[z] = hp(2, 2, z);
+    st->tr_h3p0[z] = hp(3, 0, z);
+    st->tr_h3p1[z] = hp(3, 1, z);
+    double* om[4] = {st->omega1, st->omega2, st->omega3, st->omega4};
+    for (int m = 1; m <= in.order + 1 && m <= 4; ++m) {
+      double v = 0.0;
+      for (int kk = 1; kk <= m; ++kk) v += kk * hp(kk, m - kk, z);
+      om[m - 1][z] = v / m;
     }
-    if (in.order >= 3) st->tr_h1p3[z] = c->h_res[RES_H1P3 + z];
   }
   st->idempotency = c->h_res[RES_TR] - c->h_res[RES_FRO];
   st->mfma_flops = c->mfma_flops;
@@ -1267,18 +1333,15 @@ dmpt_status one_pass(const Call& k, const PassIn& in, double* P0, double* const*
 dmpt_status pass_dispatch(const Call& k, const PassIn& in, double* P0, double* const* P1,
                           double* const* P2, double* const* P3 = nullptr) {
   if (in.order >= 3 && !P3) return fail(k.c, DMPT_ERR_ARG, "internal: P3 missing");
-  if (k.f64) return one_pass<double>(k, in, P0, P1, P2, P3);
-  return one_pass<float>(k, in, P0, P1, P2, P3);
+  return one_pass<double>(k, in, P0, P1, P2, P3);
 }
 
 // Commutator ||H0 P0 - P0 H0||_F and output asymmetry (FP64 checks).
 dmpt_status final_checks(dmpt_ctx c, int64_t N, const double* H0, const double* P0, dmpt_stats* st) {
   if (!st) return DMPT_OK;
   hipStream_t s = c->stream;
-  // G = H0 P0 computed with the FP64 engine into the (FP64-sized or not)
-  // workspace is only possible when the workspace holds doubles; otherwise
-  // the commutator is evaluated on the host-visible FP64 data in tiles.
-  if (c->esize == 8) {
+  // G = H0 P0 with the FP64 engine on workspace members
+  {
     Call k = make_call(c, N, false);
     k.eng = Engine::F64;
     k.np = 0;
@@ -1304,8 +1367,6 @@ dmpt_status final_checks(dmpt_ctx c, int64_t N, const double* H0, const double* 
                              hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
     st->commutator = std::sqrt(std::max(0.0, c->h_res[RES_MISC + 1]));
-  } else {
-    st->commutator = NAN;
   }
   HIPCHK(c, asym_max(P0, N, c->d_part, s));
   std::vector<double> mx(reduce_blocks(N * N));
@@ -1738,6 +1799,7 @@ dmpt_status linear_orders(Call& k, const PassIn& base, int64_t N, int order, dou
   const int64_t nn = N * N;
   uint16_t* none[3] = {nullptr, nullptr, nullptr};
   *settled = false;
+  c->flags &= ~DMPT_FLAG_NOISE_FLOOR;  // the order-1 pass measures the occupation again
   // ---- order 1 with the identity as direction d
   std::vector<const double*> h1x(base.H1, base.H1 + d);
   h1x.push_back(nullptr);
@@ -1767,6 +1829,7 @@ dmpt_status linear_orders(Call& k, const PassIn& base, int64_t N, int order, dou
       std::fprintf(stderr, "[dmpt] order-1 pass: mu0 %.15g TrP0-Ne %.3e rel %.3e TrJ %.6e\n", mu[0],
                    c->h_res[RES_TR] - Ne, rel, trJ);
     if (rel <= tol || (rel > 0.5 * prev && rel <= 1e3 * tol)) {
+      if (rel > tol) c->flags |= DMPT_FLAG_NOISE_FLOOR;
       *settled = true;
       break;
     }
@@ -1811,16 +1874,12 @@ dmpt_status linear_orders(Call& k, const PassIn& base, int64_t N, int order, dou
       HIPCHK(c, axpby<double>(c->jout, 0, P3[z], 0, nn, 1, -mu[1 + 2 * d + z], 1.0, none, 0, 0, s));
     }
   }
-  // traces and response traces of the returned (corrected) matrices
+  // traces of the returned (corrected) matrices
   for (int o = 1; o <= order; ++o)
     for (int z = 0; z < d; ++z) {
       double* Pk = o == 1 ? P1[z] : (o == 2 ? P2[z] : P3[z]);
       const int slot = slot_of(o, z, d);
       HIPCHK(c, trace(Pk, N, 0, N, 1, c->d_res + RES_TR + slot, 1, c->d_res + RES_ATR + slot, s));
-      HIPCHK(c, dot_partials<double>(base.H1[z], 0, Pk, 0, nn, 1, c->d_part, s));
-      HIPCHK(c, sum_partials(c->d_part, reduce_blocks(nn), 1,
-                             c->d_res + (o == 1 ? RES_H1P1 : (o == 2 ? RES_H1P2 : RES_H1P3)) + z, 1,
-                             0, s));
     }
   HIPCHK(c, hipMemcpyAsync(c->h_res, c->d_res, RES_MISC * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
@@ -1912,6 +1971,10 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
     if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess)
       return bail(DMPT_ERR_HIP, "hipStreamCreate failed");
     c->own_stream = true;
+    c->sync_null = true;
+    if (hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess)
+      return bail(DMPT_ERR_HIP, "hipEventCreate failed");
   }
   if (gemm_prepare() != hipSuccess) return bail(DMPT_ERR_HIP, "product kernel attributes");
   c->log = std::getenv("DMPT_LOG") != nullptr;
@@ -1958,6 +2021,7 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
   c->d_flag = (int*)alloc(sizeof(int) * 4);
   c->d_res = (double*)alloc(sizeof(double) * RES_COUNT);
   c->d_tally = (double*)alloc(sizeof(double) * 2);
+  c->d_cgstat = (int*)alloc(sizeof(int) * 4);
   const size_t tiles = (size_t)(c->np_max / 128) * (c->np_max / 128);
   c->part_count = std::max<size_t>(tiles, 1024) * dm;
   c->d_part = (double*)alloc(sizeof(double) * c->part_count);
@@ -1967,7 +2031,7 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
     if (!c->jout) return bail(DMPT_ERR_NOMEM, "device workspace allocation failed");
   }
   if (!c->ws.rr || !c->ws.pq || !c->ws.ref || !c->ws.active || !c->ws.iters || !c->d_flag || !c->d_res ||
-      !c->d_tally || !c->d_part || !c->d_gersh)
+      !c->d_tally || !c->d_cgstat || !c->d_part || !c->d_gersh)
     return bail(DMPT_ERR_NOMEM, "device scalar allocation failed");
   if (hipHostMalloc((void**)&c->h_res, sizeof(double) * RES_COUNT, hipHostMallocDefault) != hipSuccess)
     return bail(DMPT_ERR_NOMEM, "pinned allocation failed");
@@ -2022,9 +2086,8 @@ dmpt_status dmpt_congruence(dmpt_ctx c, int64_t N, const double* Z, const double
   if (!Z || !A || !B) return fail(c, DMPT_ERR_ARG, "Z, A and B must be non-NULL");
   if (mode != 0 && mode != 1) return fail(c, DMPT_ERR_ARG, "mode must be 0 (Z^T A Z) or 1 (Z A Z^T)");
   if (B == A || B == Z) return fail(c, DMPT_ERR_ARG, "B must not alias A or Z");
-  if (c->esize != 8)
-    return fail(c, DMPT_ERR_UNSUPPORTED, "the basis change needs FP64 masters (not an FP32 context)");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, DMPT_ERR_HIP, "hipSetDevice failed");
+  ENTER(c);
   const auto t0 = std::chrono::steady_clock::now();
   reset_stats(c);
   hipStream_t s = c->stream;
@@ -2081,6 +2144,7 @@ dmpt_status dmpt_bench_product(dmpt_ctx c, int64_t N, dmpt_prec prec, int tile, 
   if (esize_needed(o) != c->esize || planes_needed(o) > c->planes)
     return fail(c, DMPT_ERR_NOMEM, "precision needs a different workspace than the context holds");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, DMPT_ERR_HIP, "hipSetDevice failed");
+  ENTER(c);
   Call k = make_call(c, N, false);
   k.eng = engine_of(prec);
   k.np = engine_planes(k.eng);
@@ -2089,13 +2153,8 @@ dmpt_status dmpt_bench_product(dmpt_ctx c, int64_t N, dmpt_prec prec, int tile, 
   uint16_t* py[3];
   planes_of(k, c->ws.D0, 0, px);
   planes_of(k, c->ws.S0, 0, py);
-  if (k.f64) {
-    HIPCHK(c, fill_pattern<double>((double*)mptr(k, c->ws.D0, 0), k.nn, 1u, px, k.np, s));
-    HIPCHK(c, fill_pattern<double>((double*)mptr(k, c->ws.S0, 0), k.nn, 2u, py, k.np, s));
-  } else {
-    HIPCHK(c, fill_pattern<float>((float*)mptr(k, c->ws.D0, 0), k.nn, 1u, px, k.np, s));
-    HIPCHK(c, fill_pattern<float>((float*)mptr(k, c->ws.S0, 0), k.nn, 2u, py, k.np, s));
-  }
+  HIPCHK(c, fill_pattern<double>((double*)mptr(k, c->ws.D0, 0), k.nn, 1u, px, k.np, s));
+  HIPCHK(c, fill_pattern<double>((double*)mptr(k, c->ws.S0, 0), k.nn, 2u, py, k.np, s));
   GemmArgs a{};
   a.eng = k.eng;
   a.Np = k.Np;
@@ -2172,6 +2231,8 @@ dmpt_status dmpt_finalize(dmpt_ctx c) {
   if (c->h_int) (void)hipHostFree(c->h_int);
   if (c->tj) dev_free(c, c->tj);
   if (c->st) dev_free(c, c->st);
+  if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+  if (c->ev_out) (void)hipEventDestroy(c->ev_out);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
   return DMPT_OK;
@@ -2217,6 +2278,7 @@ dmpt_status dmpt_response(dmpt_ctx c, int64_t N, const double* H0, int d, const 
   for (int i = 0; i < nmu; ++i)
     if (!std::isfinite(mu[i])) return fail(c, DMPT_ERR_ARG, "mu jet must be finite");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, DMPT_ERR_HIP, "hipSetDevice failed");
+  ENTER(c);
   const auto t0 = std::chrono::steady_clock::now();
   reset_stats(c);
   PassIn in{H0, order >= 1 ? d : 0, H1, H2, beta, n, order, mu};
@@ -2230,6 +2292,7 @@ dmpt_status dmpt_response(dmpt_ctx c, int64_t N, const double* H0, int d, const 
   STCHK(pass_dispatch(k, in, P0, P1, P2, P3));
   double occ = 0;
   for (int i = 1; i < nmu; ++i) occ += std::fabs(c->h_res[RES_TR + i]);
+  STCHK(response_traces(c, N, in, P0, P1, P2, P3));
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   fill_stats(c, in, st, 1, occ, secs);
   if (c->opt.check) STCHK(final_checks(c, N, H0, P0, st));
@@ -2249,6 +2312,7 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
   if (!mu_inout) return fail(c, DMPT_ERR_ARG, "mu_inout is NULL");
   if (!(Ne > 0.0 && Ne < (double)N)) return fail(c, DMPT_ERR_ARG, "Ne must lie in (0, N)");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, DMPT_ERR_HIP, "hipSetDevice failed");
+  ENTER(c);
   const auto t0 = std::chrono::steady_clock::now();
   reset_stats(c);
   const int dd = order >= 1 ? d : 0;
@@ -2337,8 +2401,10 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
     // noise floor: a normalised error that stopped shrinking and is within
     // 1000 tol_occ counts as converged (the traces carry the products'
     // rounding); before the final phase and stage this only moves on
-    if (!ok && rel > 0.5 * prev_err && rel <= 1e3 * P.tol_occ) ok = true;
+    const bool floor_ok = !ok && rel > 0.5 * prev_err && rel <= 1e3 * P.tol_occ;
+    if (floor_ok) ok = true;
     if (ok && last) {
+      if (floor_ok) c->flags |= DMPT_FLAG_NOISE_FLOOR;
       done = true;
       break;
     }
@@ -2392,6 +2458,7 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
   }
   in.order = order;
   for (int i = 0; i < nmu; ++i) mu_inout[i] = mu[i];
+  STCHK(response_traces(c, N, in, P0, P1, P2, P3));
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   fill_stats(c, in, st, it, occ, secs);
   if (c->opt.check) STCHK(final_checks(c, N, H0, P0, st));
@@ -2426,6 +2493,7 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
     }
   }
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, DMPT_ERR_HIP, "hipSetDevice failed");
+  ENTER(c);
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t s = c->stream;
   reset_stats(c);
@@ -2628,7 +2696,8 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
   int total_passes = 0;
   // executed work over every replay, tallied on the device by the products
   // of members that actually run
-  if (rc == DMPT_OK && hipMemsetAsync(c->d_tally, 0, 2 * sizeof(double), s) != hipSuccess)
+  if (rc == DMPT_OK && (hipMemsetAsync(c->d_tally, 0, 2 * sizeof(double), s) != hipSuccess ||
+                        hipMemsetAsync(c->d_cgstat, 0, 4 * sizeof(int), s) != hipSuccess))
     rc = fail(c, DMPT_ERR_HIP, "tally reset failed");
   for (int stage = staged ? 0 : 1; stage <= 1 && rc == DMPT_OK; ++stage) {
     const int ord = stage == 0 ? 0 : order;
@@ -2657,13 +2726,9 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
       rc = fail(c, DMPT_ERR_HIP, "hipStreamBeginCapture failed");
       break;
     }
-    dmpt_status cr = c->esize == 8
-        ? batched_pass<double>(c, bk, final_stage, ord, d, n, eng, slot_sys, H0s, H1s, P0s, P1s, P2s,
-                               Ns, cs, d_shift, d_tr, rs, c->d_res + RES_HALF,
-                               final_stage ? lin : 0, d_par, d_mu, pjs.data(), rs0, d_delta)
-        : batched_pass<float>(c, bk, final_stage, ord, d, n, eng, slot_sys, H0s, H1s, P0s, P1s, P2s,
-                              Ns, cs, d_shift, d_tr, rs, c->d_res + RES_HALF,
-                              final_stage ? lin : 0, d_par, d_mu, pjs.data(), rs0, d_delta);
+    dmpt_status cr = batched_pass<double>(c, bk, final_stage, ord, d, n, eng, slot_sys, H0s, H1s, P0s,
+                                          P1s, P2s, Ns, cs, d_shift, d_tr, rs, c->d_res + RES_HALF,
+                                          final_stage ? lin : 0, d_par, d_mu, pjs.data(), rs0, d_delta);
     if (cr == DMPT_OK) {
       // with the linear schedule the final stage runs one pass and no longer
       // moves mu0: the first stage settles it a hundred times tighter (the
@@ -2733,8 +2798,10 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
   std::vector<double> hmu((size_t)nsys * J), hocc(nsys), htr((size_t)nsys * rs);
   std::vector<int> hfl(6 * (size_t)nsys);
   double htally[2] = {0.0, 0.0};
+  int hcg[4] = {0, 0, 0, 0};
   if (rc == DMPT_OK) {
     if (hipMemcpy(htally, c->d_tally, sizeof(htally), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(hcg, c->d_cgstat, sizeof(hcg), hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(hmu.data(), d_mu, hmu.size() * 8, hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(hocc.data(), d_occ, hocc.size() * 8, hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(htr.data(), d_tr, htr.size() * 8, hipMemcpyDeviceToHost) != hipSuccess ||
@@ -2747,13 +2814,14 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
   }
   cleanup();
   if (rc != DMPT_OK) return rc;
-  bool all_done = true, nonfinite = false;
+  bool all_done = true, nonfinite = false, floor_acc = false;
   double occ_sum = 0.0;
   for (int slot = 0; slot < nsys; ++slot) {
     const int sy = slot_sys[slot];
     for (int j = 0; j < J; ++j) mus[(size_t)sy * J + j] = hmu[(size_t)slot * J + j];
     if (!hfl[2 * nsys + slot]) all_done = false;
     if (hfl[4 * nsys + slot] == -6) nonfinite = true;
+    if (hfl[4 * nsys + slot] == 1) floor_acc = true;
     occ_sum += hocc[slot];
     if (c->log)
       std::fprintf(stderr, "[dmpt] system %d N %ld beta %.4g: passes %d done %d status %d occ_err %.3e mu0 %.15g\n",
@@ -2763,6 +2831,10 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
   if (st) {
     std::memset(st, 0, sizeof(*st));
     st->newton_iters = total_passes;
+    st->cg_iters_total = hcg[0];
+    st->cg_iters_max = hcg[1];
+    st->cg_unconverged = hcg[2];
+    st->flags = (floor_acc ? DMPT_FLAG_NOISE_FLOOR : 0) | (hcg[2] > 0 ? DMPT_FLAG_CG_FLOOR : 0);
     st->occ_err = occ_sum;
     st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     // products of the members that ran, tallied on the device (useful flops
@@ -2783,6 +2855,7 @@ dmpt_status dmpt_backward(dmpt_ctx c, int64_t N, const double* H0, double beta, 
   if (!(Ne > 0.0 && Ne < (double)N)) return fail(c, DMPT_ERR_ARG, "Ne must lie in (0, N)");
   if (mu0 && !std::isfinite(*mu0)) return fail(c, DMPT_ERR_ARG, "mu0 must be finite");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, DMPT_ERR_HIP, "hipSetDevice failed");
+  ENTER(c);
   const auto t0 = std::chrono::steady_clock::now();
   double mu = mu0 ? *mu0 : NAN;
   int newton = 0;
@@ -2822,8 +2895,7 @@ dmpt_status dmpt_backward(dmpt_ctx c, int64_t N, const double* H0, double beta, 
   reset_stats(c);
   Call k = make_call(c, N, true);
   const int ck = std::max(1, std::min(c->opt.ckpt_every, n));
-  dmpt_status r = k.f64 ? adjoint_impl<double>(k, H0, beta, mu, n, Abar, G, ck)
-                        : adjoint_impl<float>(k, H0, beta, mu, n, Abar, G, ck);
+  dmpt_status r = adjoint_impl<double>(k, H0, beta, mu, n, Abar, G, ck);
   if (r != DMPT_OK) return r;
   if (st) {
     std::memset(st, 0, sizeof(*st));

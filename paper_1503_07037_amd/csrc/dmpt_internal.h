@@ -49,14 +49,6 @@ inline int64_t plane_np(int64_t n) {
   return (r > 0 && r < 65536 && r % 32 == 0 && r * r == n) ? r : 0;
 }
 
-// A working matrix: master copy (float for the F32 engine, double for the
-// others) plus, for the split-BF16 engines, its BF16 slices (plane p holds
-// the p-th term of x ~ sum_p bf16_p) in the plane layout above.
-struct Mat {
-  void* m = nullptr;                 // master (double* or float*)
-  uint16_t* pl[3] = {nullptr, nullptr, nullptr};
-};
-
 // Batched operand: base matrix and element stride between batch members
 // (0 = the same matrix for every member).  Member z of the launch reads
 // operand member z / div, so div = d lets d directions share one matrix.
@@ -151,6 +143,10 @@ hipError_t cg_update_p(T* P, const T* R, int64_t n, int64_t stride, int batch,
 // initial residual); iters[z] counts the checks.  Any batch size.
 hipError_t cg_check(const double* rr, const double* rr0, const double* ref, int hstride, int batch,
                     double tol2, double eta2, int* active, int* iters, hipStream_t s);
+
+// Statistics of a fixed-count solve: stat[0] += sum of iterations, stat[1] =
+// max(stat[1], iterations), stat[2] += members still active (unconverged).
+hipError_t cg_account(const int* active, const int* iters, int batch, int* stat, hipStream_t s);
 
 // Element-wise linear combination: y = a x + b y (batched, master only) + planes
 template <class T>

@@ -326,6 +326,20 @@ __global__ void k_cg_check(const double* rr, const double* rr0, const double* re
   if (!(r > tol2 * ref[z] || r > eta2 * rr0[z * hstride])) active[z] = 0;
 }
 
+// Statistics of a fixed-count (graph-replayed) solve: iterations summed and
+// their maximum over the members that ran, and the members still above their
+// tolerance at the end (iters counts the initial check as well).
+__global__ void k_cg_account(const int* active, const int* iters, int batch, int* stat) {
+  const int z = blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= batch) return;
+  const int its = max(0, iters[z] - 1);
+  if (its > 0) {
+    atomicAdd(stat, its);
+    atomicMax(stat + 1, its);
+  }
+  if (active[z]) atomicAdd(stat + 2, 1);
+}
+
 template <class T>
 __global__ __launch_bounds__(kT) void k_axpby(const T* __restrict__ x, int64_t sx, T* __restrict__ y,
                                               int64_t sy, int64_t n, double a, double b, Planes pl,
@@ -560,12 +574,13 @@ __global__ void k_newton(const double* tr, int rs, const double* par, double* mu
   }
   bool ok = rel <= tol;
   // noise floor: stopped shrinking within 1000 tol (the traces carry the
-  // products' rounding)
-  if (!ok && rel > 0.5 * prev_err[s] && rel <= 1e3 * tol) ok = true;
+  // products' rounding); status 1 records such an acceptance
+  const bool floor_ok = !ok && rel > 0.5 * prev_err[s] && rel <= 1e3 * tol;
   prev_err[s] = rel;
-  if (ok) {
+  if (ok || floor_ok) {
     active[s] = 0;
     done[s] = final_stage;
+    if (final_stage && floor_ok) status[s] = 1;
     return;
   }
   double* m = mu + (int64_t)s * J;
@@ -815,6 +830,11 @@ hipError_t cg_check(const double* rr, const double* rr0, const double* ref, int 
                     double tol2, double eta2, int* active, int* iters, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_check, dim3((batch + 63) / 64), dim3(64), 0, s, rr, rr0, ref, hstride,
                      batch, tol2, eta2, active, iters);
+  return hipGetLastError();
+}
+
+hipError_t cg_account(const int* active, const int* iters, int batch, int* stat, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_account, dim3((batch + 63) / 64), dim3(64), 0, s, active, iters, batch, stat);
   return hipGetLastError();
 }
 

@@ -14,11 +14,13 @@
 //
 // Engines:
 //   F64     v_mfma_f64_16x16x4f64, FP64 accumulation
-//   F32     v_mfma_f32_32x32x2f32, FP32 accumulation
+//   F32     v_mfma_f32_32x32x2f32 on operands rounded to FP32; FP32 sums over
+//           16-wide k slices, FP64 across slices
 //   BF16S2  x = x_hi + x_lo (BF16 splits): x_hi y_hi + x_hi y_lo + x_lo y_hi
 //   BF16S3  x = x_0 + x_1 + x_2: the six products x_p y_q with p + q <= 2
-//           (both BF16 engines use v_mfma_f32_32x32x16_bf16, FP32 accumulation;
-//           their master copies, C1, C2, W and C are FP64)
+//           (both BF16 engines use v_mfma_f32_32x32x16_bf16, FP32 accumulation)
+// Master copies (the operands of the FP64 and FP32 engines, C1, C2, W and C)
+// are FP64 for every engine.
 //
 // FP64 and FP32: 128 x 128 output tile per 256-thread workgroup (four waves,
 // 64 x 64 each), K staged through LDS in a two-stage ring.  Split BF16: 256 x
@@ -206,6 +208,13 @@ __global__ __launch_bounds__(kThreads) void k_gemm_f64(GemmArgs a) {
 }
 
 // ------------------------------------------------------------------ FP32
+// Operands are the FP64 masters, rounded to FP32 as a stage is written to
+// LDS.  The MFMAs of each 16-wide k stage accumulate into a fresh FP32 tile
+// which is then added into an FP64 accumulator, so the FP32 rounding covers
+// 16 products per output instead of all of k.  Two FP32 tiles alternate
+// between stages: while the MFMAs of stage k fill one, the other (stage
+// k - 1) is converted and added into FP64, four values after each of the
+// stage's first 16 MFMAs, so that VALU work runs beside the matrix core.
 constexpr int F32_BK = 16, F32_LD = F32_BK + 1;
 
 __global__ __launch_bounds__(kThreads) void k_gemm_f32(GemmArgs a) {
@@ -215,51 +224,56 @@ __global__ __launch_bounds__(kThreads) void k_gemm_f32(GemmArgs a) {
   const int64_t Np = a.Np;
   int tm, tn;
   tile_coords(blockIdx.x, (int)(Np / BM), (int)(Np / BN), tm, tn);
-  const float* X = (const float*)a.X.m + (z / a.X.div) * a.X.stride + (int64_t)tm * BM * Np;
-  const float* Y = (const float*)a.Y.m + (z / a.Y.div) * a.Y.stride + (int64_t)tn * BN * Np;
+  const double* X = (const double*)a.X.m + (z / a.X.div) * a.X.stride + (int64_t)tm * BM * Np;
+  const double* Y = (const double*)a.Y.m + (z / a.Y.div) * a.Y.stride + (int64_t)tn * BN * Np;
   __shared__ float sX[2][BM][F32_LD];
   __shared__ float sY[2][BN][F32_LD];
   __shared__ double red[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  // 128 rows x 16 floats = 512 float4 per operand: two per thread
-  float4 rx[2], ry[2];
+  // 128 rows x 16 doubles = 1024 double2 per operand and stage: four per thread
+  constexpr int L = BM * F32_BK / 2 / kThreads;
+  double2 rx[L], ry[L];
   auto gload = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int idx = tid + i * kThreads, row = idx >> 2, q = idx & 3;
-      rx[i] = *(const float4*)(X + (int64_t)row * Np + k0 + 4 * q);
-      ry[i] = *(const float4*)(Y + (int64_t)row * Np + k0 + 4 * q);
+    for (int i = 0; i < L; ++i) {
+      const int idx = tid + i * kThreads, row = idx >> 3, q = idx & 7;
+      rx[i] = *(const double2*)(X + (int64_t)row * Np + k0 + 2 * q);
+      ry[i] = *(const double2*)(Y + (int64_t)row * Np + k0 + 2 * q);
     }
   };
   auto swrite = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int idx = tid + i * kThreads, row = idx >> 2, q = idx & 3;
-      sX[buf][row][4 * q + 0] = rx[i].x;
-      sX[buf][row][4 * q + 1] = rx[i].y;
-      sX[buf][row][4 * q + 2] = rx[i].z;
-      sX[buf][row][4 * q + 3] = rx[i].w;
-      sY[buf][row][4 * q + 0] = ry[i].x;
-      sY[buf][row][4 * q + 1] = ry[i].y;
-      sY[buf][row][4 * q + 2] = ry[i].z;
-      sY[buf][row][4 * q + 3] = ry[i].w;
+    for (int i = 0; i < L; ++i) {
+      const int idx = tid + i * kThreads, row = idx >> 3, q = idx & 7;
+      sX[buf][row][2 * q] = (float)rx[i].x;
+      sX[buf][row][2 * q + 1] = (float)rx[i].y;
+      sY[buf][row][2 * q] = (float)ry[i].x;
+      sY[buf][row][2 * q + 1] = (float)ry[i].y;
     }
   };
-  f16v acc[2][2];
+  f16v acc[2][2], acc2[2][2];
+  double accd[2][2][16];
+  f16v zero;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) zero[r] = 0.0f;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < 2; ++j) {
+      acc[i][j] = zero;
+      acc2[i][j] = zero;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+      for (int r = 0; r < 16; ++r) accd[i][j][r] = 0.0;
+    }
+  const int nk = (int)(Np / F32_BK);
   gload(0);
   swrite(0);
   __syncthreads();
-  const int nk = (int)(Np / F32_BK);
-  for (int kt = 0; kt < nk; ++kt) {
+  auto stage = [&](int kt, f16v (&acur)[2][2], f16v (&aprev)[2][2], bool fold_prev) {
     const int buf = kt & 1;
     if (kt + 1 < nk) gload((kt + 1) * F32_BK);
+    int m = 0;  // MFMA index within the stage
 #pragma unroll
     for (int kk = 0; kk < F32_BK; kk += 2) {
       float av[2], bv[2];
@@ -270,11 +284,35 @@ __global__ __launch_bounds__(kThreads) void k_gemm_f32(GemmArgs a) {
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 2; ++j) {
+          acur[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv[j], kk == 0 ? zero : acur[i][j], 0,
+                                                            0, 0);
+          if (fold_prev && m < 16) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int v = 4 * m + q;
+              accd[v >> 5][(v >> 4) & 1][v & 15] += (double)aprev[v >> 5][(v >> 4) & 1][v & 15];
+            }
+          }
+          ++m;
+        }
     }
     if (kt + 1 < nk) swrite(buf ^ 1);
     __syncthreads();
+  };
+  for (int kt = 0; kt < nk; kt += 2) {
+    stage(kt, acc, acc2, kt > 0);
+    if (kt + 1 < nk) stage(kt + 1, acc2, acc, true);
+  }
+  {
+    // the last stage's tile
+    f16v (&last)[2][2] = (nk & 1) ? acc : acc2;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) accd[i][j][r] += (double)last[i][j][r];
   }
   double dsum = 0.0;
 #pragma unroll
@@ -285,7 +323,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_f32(GemmArgs a) {
       for (int r = 0; r < 16; ++r) {
         const int64_t row = (int64_t)tm * BM + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         const int64_t col = (int64_t)tn * BN + wn * 64 + j * 32 + (lane & 31);
-        epi<float>(a, z, row, col, (double)acc[i][j][r], dsum);
+        epi<double>(a, z, row, col, accd[i][j][r], dsum);
       }
   if (a.W) {
     const double s = block_sum(dsum, red);

@@ -70,3 +70,40 @@ def test_init_argument_checks(lib):
     o.prec = 17
     assert lib.dmpt_init(ctypes.byref(h), 0, 128, 1, ctypes.byref(o), None) == L.DMPT_ERR_ARG
     assert not h.value
+
+
+def _c_layout(struct, fields):
+    """sizeof and offsetof of a header struct, from a C program compiled with gcc."""
+    import json
+    import shutil
+    import subprocess
+    import tempfile
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if not cc:
+        pytest.skip("no C compiler")
+    body = ",".join(f'\\"{f}\\":%zu' for f in fields)
+    args = ", ".join(f"offsetof({struct}, {f})" for f in fields)
+    src = f"""#include <stddef.h>
+#include <stdio.h>
+#include "dmpt.h"
+int main(void) {{ printf("{{\\"size\\":%zu,{body}}}", sizeof({struct}), {args}); return 0; }}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "layout.c")
+        exe = os.path.join(d, "layout")
+        open(c, "w").write(src)
+        subprocess.run([cc, "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        return json.loads(subprocess.run([exe], check=True, stdout=subprocess.PIPE, text=True).stdout)
+
+
+@pytest.mark.parametrize("struct,pyname", [("dmpt_stats", "Stats"), ("dmpt_options", "Options"),
+                                           ("dmpt_profile_data", "ProfileData")])
+def test_struct_layouts_match_the_header(struct, pyname):
+    """The binding's ctypes structures have the header's size and field offsets."""
+    from paper_1503_07037_amd import _lib as L
+    cls = getattr(L, pyname)
+    names = [f[0] for f in cls._fields_]
+    lay = _c_layout(struct, names)
+    assert lay["size"] == ctypes.sizeof(cls)
+    for n in names:
+        assert lay[n] == getattr(cls, n).offset, n

@@ -4,7 +4,7 @@ Checked against the oracle's canonical first-order response to sym(A) (the
 exact adjoint of the canonical map), the identity Tr(A P1[H1]) = <G, H1>,
 Tr G = 0 (a shift of H0 by the identity only moves mu0), checkpoint-stride
 independence, the torch.autograd wrapper, and the full-size workload
-(16^3 cubic lattice, FP32) on the oracle's stored samples.
+(16^3 cubic lattice, FP32 products) element by element.
 """
 import os
 
@@ -106,15 +106,17 @@ def test_autograd_function(dm):
 
 @pytest.mark.timeout(600)
 def test_adjoint4096_fp32_full_size(dm):
-    """The 16^3 cubic workload (beta 20, n 25, A = diag(x), checkpoints every 5), FP32."""
+    """The 16^3 cubic workload (beta 20, n 25, A = diag(x), checkpoints every 5), FP32 products:
+    every element of G against the oracle's canonical first-order response to A (relative to
+    max |G|), and Tr G = 0."""
     print("case adjoint4096 fp32", flush=True)
     c = workloads.config("adjoint4096")
-    g = np.load(os.path.join(HERE, "golden", "adjoint4096_samples.npz"))
-    A = np.diag(c["H1"][0])
+    x = np.diag(c["H1"][0]).copy()
+    ref = oracle.adjoint_grad(c["H0"], c["beta"], c["Ne"], c["n"], x)
     with dm.Context(c["N"], dirs_max=1, prec="fp32", ckpt_every=5) as ctx:
-        G, st = ctx.backward(T(c["H0"]), c["beta"], c["Ne"], c["n"], T(np.diag(A)))
-    ii = torch.as_tensor(g["i"], device=G.device)
-    jj = torch.as_tensor(g["j"], device=G.device)
-    err = float(np.abs(G[ii, jj].cpu().numpy() - g["G"]).max() / g["max_G"])
+        G, st = ctx.backward(T(c["H0"]), c["beta"], c["Ne"], c["n"], T(np.diag(x)))
+    g = G.cpu().numpy()
+    err = float(np.abs(g - ref).max() / np.abs(ref).max())
     print(f"  rel err {err:.2e} seconds={st['seconds']:.1f} cg={st['cg_iters_total']}")
-    assert err < 1e-5
+    assert err < 1e-6
+    assert abs(np.trace(g)) < 1e-6 * np.abs(g).sum()

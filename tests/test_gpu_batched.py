@@ -49,7 +49,7 @@ def small_batch():
     return systems
 
 
-@pytest.mark.parametrize("prec,order,tol", [("fp64", 2, 1e-10), ("fp32", 1, 3e-6)])
+@pytest.mark.parametrize("prec,order,tol", [("fp64", 2, 1e-10), ("fp32", 1, 1e-6), ("fp32", 2, 1e-6)])
 def test_small_uneven_batch(dm, small_batch, prec, order, tol):
     print(f"case batched {prec} order {order}", flush=True)
     nmax = max(s["h0"].shape[0] for s in small_batch)
@@ -120,7 +120,7 @@ def test_batch64_fp32_full_workload(dm):
                  for z in range(3))
         worst = max(worst, e0, e1)
     print(f"  worst sampled error {worst:.2e}")
-    assert worst < 1e-5
+    assert worst < 1e-6
 
 
 @pytest.mark.parametrize("d", [1, 3])

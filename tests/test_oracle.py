@@ -340,8 +340,8 @@ def test_n_plus_one_rule_second_order():
     h1 = np.diag(np.arange(n) - n / 2.0) / n
     h2 = _sym(rng, n, 0.05)
     r = o.canonical_response(h0, [h1], [h2], beta, Ne, M, order=2)
-    om2 = 0.5 * r["tr_h1p1"][0] + r["tr_h2p0"][0]
-    om3 = (r["tr_h1p2"][0] + 2 * float(np.sum(h2 * r["P1"][0]))) / 3.0
+    om2 = r["omega2"][0]
+    om3 = r["omega3"][0]
     f = lambda lam: o.omega(h0 + lam * h1 + lam * lam * h2, beta, Ne, M)
     h = 2e-3
     f0, fp, fm, fp2, fm2 = f(0), f(h), f(-h), f(2 * h), f(-2 * h)
@@ -352,6 +352,32 @@ def test_n_plus_one_rule_second_order():
     # first order: Omega^(1) = Tr[H1 P0]
     c1 = (fp - fm) / (2 * h)
     assert abs(c1 - float(np.sum(h1 * r["P0"]))) < 1e-5
+
+
+def test_n_plus_one_rule_third_and_fourth_order():
+    """Eq. (Resp_0) at m = 3 and 4 with H = H0 + l H1 + l^2 H2 + l^3 H3: the oracle's Omega^(3) and
+    Omega^(4) from Tr[H^(k) P^(m-k)] equal the l^3 and l^4 coefficients of the canonical free energy
+    (seven-point differences), while dropping the weights k of the sum misses them."""
+    n, beta, Ne, M = 16, 5.0, 7.0, 40
+    rng = np.random.default_rng(9)
+    h0 = w.chain_1d(n, 2)
+    h1 = np.diag(np.linspace(-1, 1, n))
+    h2 = _sym(rng, n, 0.05)
+    h3 = _sym(rng, n, 0.03)
+    r = o.canonical_response(h0, [h1], [h2], beta, Ne, M, order=3, h3s=[h3])
+    f = lambda lam: o.omega(h0 + lam * h1 + lam ** 2 * h2 + lam ** 3 * h3, beta, Ne, M)
+    h = 0.02
+    F = {k: f(k * h) for k in range(-3, 4)}
+    c3 = (-F[3] + 8 * F[2] - 13 * F[1] + 13 * F[-1] - 8 * F[-2] + F[-3]) / (8 * h ** 3) / 6.0
+    c4 = (-F[3] + 12 * F[2] - 39 * F[1] + 56 * F[0] - 39 * F[-1] + 12 * F[-2] - F[-3]) / (6 * h ** 4) / 24.0
+    assert abs(c3 - r["omega3"][0]) < 1e-4 * abs(c3)
+    assert abs(c4 - r["omega4"][0]) < 1e-2 * abs(c4)
+    unweighted = (r["tr_h1p3"][0] + r["tr_h2p2"][0] + r["tr_h3p1"][0]) / 4.0
+    assert abs(c4 - unweighted) > 0.1 * abs(c4)
+    # the traces are those of the returned matrices
+    assert abs(r["tr_h2p1"][0] - float(np.sum(h2 * r["P1"][0]))) < 1e-12 * max(1.0, abs(r["tr_h2p1"][0]))
+    assert abs(r["tr_h3p0"][0] - float(np.sum(h3 * r["P0"]))) < 1e-12
+    assert abs(r["omega1"][0] - float(np.sum(h1 * r["P0"]))) < 1e-12
 
 
 def test_entropy_derivative_identity():
