@@ -273,6 +273,8 @@ typedef struct {
      (BF16 planes for the split engines, masters otherwise; C1, C2 and W
      masters), C's master and planes written once */
   double eng_bytes[4];
+  /* algorithmic flops of those launches: 2 N^3 per logical product and member */
+  double eng_useful_flops[4];
 } dmpt_profile_data;
 
 dmpt_status dmpt_profile(dmpt_ctx ctx, int enable);

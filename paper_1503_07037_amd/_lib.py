@@ -79,7 +79,8 @@ class ProfileData(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double),
                 ("mfma_flops", ctypes.c_double), ("useful_flops", ctypes.c_double),
                 ("eng_launches", ctypes.c_int64 * 4), ("eng_ms", ctypes.c_double * 4),
-                ("eng_mfma_flops", ctypes.c_double * 4), ("eng_bytes", ctypes.c_double * 4)]
+                ("eng_mfma_flops", ctypes.c_double * 4), ("eng_bytes", ctypes.c_double * 4),
+                ("eng_useful_flops", ctypes.c_double * 4)]
 
 
 EXPORTS = [

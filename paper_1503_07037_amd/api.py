@@ -1,7 +1,11 @@
 """Python front end of the DMPT library: torch tensors in, torch tensors out.
 
-PyTorch is used only for device memory and the current HIP stream; every
-operation of the method runs in libdmpt.so (the C ABI of include/dmpt.h).
+PyTorch is used only for device memory and streams; every operation of the
+method runs in libdmpt.so (the C ABI of include/dmpt.h).  A Context works in
+order with torch's current stream at the time it is created: a side stream
+is handed to the library as its stream; torch's default (null) stream is
+handed over as NULL, and the library then orders its private stream after
+the null stream's queued work at every call (see dmpt_init).
 All matrices are N x N float64 CUDA (HIP) tensors; inputs are used through
 their symmetric part.
 """
@@ -84,7 +88,10 @@ def _check_mat(t, n, name):
 
 
 class Context:
-    """A library context (device workspace for N <= n_max, dirs_max directions)."""
+    """A library context (device workspace for N <= n_max, dirs_max directions).
+
+    ``stream`` (default: torch's current stream on ``device``) is the stream the
+    context's calls are ordered with for its whole life."""
 
     def __init__(self, n_max, dirs_max=1, device=0, stream=None, **opts):
         torch = _torch()
@@ -138,14 +145,15 @@ class Context:
         self._raise(self.lib.dmpt_profile(self.h, 1 if enable else 0))
 
     def profile_get(self):
-        """Totals since the last reset: launches, ms, mfma_flops, useful_flops."""
+        """Totals since the last reset: launches, ms, mfma_flops, useful_flops, and per engine."""
         d = L.ProfileData()
         self._raise(self.lib.dmpt_profile_get(self.h, ctypes.byref(d)))
         names = ["fp64", "fp32", "bf16x3", "bf16x6"]
         return dict(launches=d.launches, ms=d.ms, mfma_flops=d.mfma_flops,
                     useful_flops=d.useful_flops,
                     engines={names[i]: dict(launches=d.eng_launches[i], ms=d.eng_ms[i],
-                                            mfma_flops=d.eng_mfma_flops[i], bytes=d.eng_bytes[i])
+                                            mfma_flops=d.eng_mfma_flops[i], bytes=d.eng_bytes[i],
+                                            useful_flops=d.eng_useful_flops[i])
                          for i in range(4)})
 
     def bench_product(self, N, prec=None, tile=0, reps=10):

@@ -358,6 +358,7 @@ dmpt_status prof_resolve(dmpt_ctx c) {
     c->prof.eng_ms[t.eng] += ms;
     c->prof.eng_mfma_flops[t.eng] += t.mfma;
     c->prof.eng_bytes[t.eng] += t.bytes;
+    c->prof.eng_useful_flops[t.eng] += t.useful;
     c->prof_pool.push_back(t.a);
     c->prof_pool.push_back(t.b);
   }

@@ -22,8 +22,8 @@
 // Master copies (the operands of the FP64 and FP32 engines, C1, C2, W and C)
 // are FP64 for every engine.
 //
-// FP64 and FP32: 128 x 128 output tile per 256-thread workgroup (four waves,
-// 64 x 64 each), K staged through LDS in a two-stage ring.  Split BF16: 256 x
+// FP64 and FP32: 128 x 128 output tile per 512-thread workgroup (eight waves,
+// 64 x 32 each, two per SIMD), K staged through LDS in a two-stage ring.  Split BF16: 256 x
 // 256 tiles (128 x 128 per wave) when Np allows, else 128 x 128; the BF16
 // planes are stored in a blocked layout in the MFMA operand order (see
 // plane_off), so operand tiles move as contiguous 1 KB blocks.  Operands are
@@ -41,7 +41,6 @@ typedef __bf16 bf8v __attribute__((__vector_size__(8 * sizeof(__bf16))));
 typedef unsigned int u4v __attribute__((__vector_size__(4 * sizeof(unsigned int))));
 
 constexpr int BM = 128, BN = 128;
-constexpr int kThreads = 256;
 constexpr int kWaves256 = 8;  // waves of the 256 x 256 split-BF16 kernel (two per SIMD)
 constexpr int kGroupM = 8;   // tile rows per raster group
 constexpr int kXcd = 8;      // XCDs of an MI355X
@@ -125,9 +124,25 @@ __device__ inline void count_member(const GemmArgs& a) {
 }
 
 // ------------------------------------------------------------------ FP64
-constexpr int F64_BK = 8, F64_LD = F64_BK + 1;
+// 128 x 128 output tile, NW waves (two along m, NW / 2 along n; wave (wm, wn)
+// owns 64 x (256 / NW) as 16 x 16 MFMA tiles), k staged through a two-stage
+// LDS ring of BK-wide slices.
+#ifndef DMPT_F64_BK
+#define DMPT_F64_BK 8
+#endif
+#ifndef DMPT_F64_NW
+#define DMPT_F64_NW 8
+#endif
+constexpr int kF64BK = DMPT_F64_BK, kF64NW = DMPT_F64_NW;
 
-__global__ __launch_bounds__(kThreads) void k_gemm_f64(GemmArgs a) {
+template <int BK, int NW>
+__global__ __launch_bounds__(NW * 64) void k_gemm_f64(GemmArgs a) {
+  constexpr int LD = BK + 1;
+  constexpr int FN = 16 / NW;                  // 16-wide MFMA tiles per wave along n
+  constexpr int THREADS = NW * 64;
+  constexpr int Q = BK / 2;                    // double2 per row and stage
+  constexpr int L = BM * Q / THREADS;          // double2 loads per thread, operand and stage
+  static_assert(L >= 1 && FN >= 1, "tile split");
   const int z = blockIdx.z;
   if (a.active && !a.active[z]) return;
   count_member(a);
@@ -136,54 +151,53 @@ __global__ __launch_bounds__(kThreads) void k_gemm_f64(GemmArgs a) {
   tile_coords(blockIdx.x, (int)(Np / BM), (int)(Np / BN), tm, tn);
   const double* X = (const double*)a.X.m + (z / a.X.div) * a.X.stride + (int64_t)tm * BM * Np;
   const double* Y = (const double*)a.Y.m + (z / a.Y.div) * a.Y.stride + (int64_t)tn * BN * Np;
-  __shared__ double sX[2][BM][F64_LD];
-  __shared__ double sY[2][BN][F64_LD];
-  __shared__ double red[4];
+  __shared__ double sX[2][BM][LD];
+  __shared__ double sY[2][BN][LD];
+  __shared__ double red[NW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  // 128 rows x 8 doubles = 512 double2 per operand: two per thread
-  double2 rx[2], ry[2];
+  const int wm = wave / (NW / 2), wn = wave % (NW / 2);
+  double2 rx[L], ry[L];
   auto gload = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int idx = tid + i * kThreads, row = idx >> 2, q = idx & 3;
+    for (int i = 0; i < L; ++i) {
+      const int idx = tid + i * THREADS, row = idx / Q, q = idx % Q;
       rx[i] = *(const double2*)(X + (int64_t)row * Np + k0 + 2 * q);
       ry[i] = *(const double2*)(Y + (int64_t)row * Np + k0 + 2 * q);
     }
   };
   auto swrite = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int idx = tid + i * kThreads, row = idx >> 2, q = idx & 3;
+    for (int i = 0; i < L; ++i) {
+      const int idx = tid + i * THREADS, row = idx / Q, q = idx % Q;
       sX[buf][row][2 * q] = rx[i].x;
       sX[buf][row][2 * q + 1] = rx[i].y;
       sY[buf][row][2 * q] = ry[i].x;
       sY[buf][row][2 * q + 1] = ry[i].y;
     }
   };
-  d4v acc[4][4];
+  d4v acc[4][FN];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = (d4v){0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < FN; ++j) acc[i][j] = (d4v){0.0, 0.0, 0.0, 0.0};
   gload(0);
   swrite(0);
   __syncthreads();
-  const int nk = (int)(Np / F64_BK);
+  const int nk = (int)(Np / BK);
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
-    if (kt + 1 < nk) gload((kt + 1) * F64_BK);
+    if (kt + 1 < nk) gload((kt + 1) * BK);
 #pragma unroll
-    for (int kk = 0; kk < F64_BK; kk += 4) {
-      double av[4], bv[4];
+    for (int kk = 0; kk < BK; kk += 4) {
+      double av[4], bv[FN];
 #pragma unroll
       for (int i = 0; i < 4; ++i) av[i] = sX[buf][wm * 64 + i * 16 + (lane & 15)][kk + (lane >> 4)];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = sY[buf][wn * 64 + j * 16 + (lane & 15)][kk + (lane >> 4)];
+      for (int j = 0; j < FN; ++j) bv[j] = sY[buf][wn * (16 * FN) + j * 16 + (lane & 15)][kk + (lane >> 4)];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < FN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
     if (kt + 1 < nk) swrite(buf ^ 1);
@@ -193,12 +207,12 @@ __global__ __launch_bounds__(kThreads) void k_gemm_f64(GemmArgs a) {
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         // v_mfma_f64_16x16x4f64 result: register r of lane l holds row 4r + l/16, column l%16
         const int64_t row = (int64_t)tm * BM + wm * 64 + i * 16 + 4 * r + (lane >> 4);
-        const int64_t col = (int64_t)tn * BN + wn * 64 + j * 16 + (lane & 15);
+        const int64_t col = (int64_t)tn * BN + wn * (16 * FN) + j * 16 + (lane & 15);
         epi<double>(a, z, row, col, acc[i][j][r], dsum);
       }
   if (a.W) {
@@ -209,15 +223,31 @@ __global__ __launch_bounds__(kThreads) void k_gemm_f64(GemmArgs a) {
 
 // ------------------------------------------------------------------ FP32
 // Operands are the FP64 masters, rounded to FP32 as a stage is written to
-// LDS.  The MFMAs of each 16-wide k stage accumulate into a fresh FP32 tile
-// which is then added into an FP64 accumulator, so the FP32 rounding covers
-// 16 products per output instead of all of k.  Two FP32 tiles alternate
-// between stages: while the MFMAs of stage k fill one, the other (stage
-// k - 1) is converted and added into FP64, four values after each of the
-// stage's first 16 MFMAs, so that VALU work runs beside the matrix core.
-constexpr int F32_BK = 16, F32_LD = F32_BK + 1;
+// LDS (BK-wide k stages, two-stage ring).  The MFMAs of each 16-wide slice of
+// k accumulate into a fresh FP32 tile which is then added into an FP64
+// accumulator, so the FP32 rounding covers 16 products per output instead of
+// all of k.  Two FP32 tiles alternate between slices: while the MFMAs of
+// slice s fill one, the other (slice s - 1) is converted and added into
+// FP64, four values after each of the slice's first MFMAs, so that VALU work
+// runs beside the matrix core.  NW waves: two along m, NW / 2 along n; wave
+// (wm, wn) owns 64 x (256 / NW).
+#ifndef DMPT_F32_BK
+#define DMPT_F32_BK 32
+#endif
+#ifndef DMPT_F32_NW
+#define DMPT_F32_NW 8
+#endif
+constexpr int kF32BK = DMPT_F32_BK, kF32NW = DMPT_F32_NW;
+constexpr int kF32Slice = 16;  // k extent of one FP32 partial sum
 
-__global__ __launch_bounds__(kThreads) void k_gemm_f32(GemmArgs a) {
+template <int BK, int NW>
+__global__ __launch_bounds__(NW * 64) void k_gemm_f32(GemmArgs a) {
+  constexpr int LD = BK + 1;
+  constexpr int FN = 8 / NW;                      // MFMA tiles per wave along n: 2 (NW 4), 1 (NW 8)
+  constexpr int THREADS = NW * 64;
+  constexpr int L = BM * BK / 2 / THREADS;        // double2 loads per thread, operand and stage
+  constexpr int SL = BK / kF32Slice;              // FP32 slices per stage
+  static_assert(FN >= 1 && L >= 1 && SL >= 1 && BK % kF32Slice == 0, "tile split");
   const int z = blockIdx.z;
   if (a.active && !a.active[z]) return;
   count_member(a);
@@ -226,18 +256,17 @@ __global__ __launch_bounds__(kThreads) void k_gemm_f32(GemmArgs a) {
   tile_coords(blockIdx.x, (int)(Np / BM), (int)(Np / BN), tm, tn);
   const double* X = (const double*)a.X.m + (z / a.X.div) * a.X.stride + (int64_t)tm * BM * Np;
   const double* Y = (const double*)a.Y.m + (z / a.Y.div) * a.Y.stride + (int64_t)tn * BN * Np;
-  __shared__ float sX[2][BM][F32_LD];
-  __shared__ float sY[2][BN][F32_LD];
-  __shared__ double red[4];
+  __shared__ float sX[2][BM][LD];
+  __shared__ float sY[2][BN][LD];
+  __shared__ double red[NW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  // 128 rows x 16 doubles = 1024 double2 per operand and stage: four per thread
-  constexpr int L = BM * F32_BK / 2 / kThreads;
+  const int wm = wave / (NW / 2), wn = wave % (NW / 2);
+  constexpr int Q = BK / 2;  // double2 per row and stage
   double2 rx[L], ry[L];
   auto gload = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < L; ++i) {
-      const int idx = tid + i * kThreads, row = idx >> 3, q = idx & 7;
+      const int idx = tid + i * THREADS, row = idx / Q, q = idx % Q;
       rx[i] = *(const double2*)(X + (int64_t)row * Np + k0 + 2 * q);
       ry[i] = *(const double2*)(Y + (int64_t)row * Np + k0 + 2 * q);
     }
@@ -245,72 +274,83 @@ __global__ __launch_bounds__(kThreads) void k_gemm_f32(GemmArgs a) {
   auto swrite = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < L; ++i) {
-      const int idx = tid + i * kThreads, row = idx >> 3, q = idx & 7;
+      const int idx = tid + i * THREADS, row = idx / Q, q = idx % Q;
       sX[buf][row][2 * q] = (float)rx[i].x;
       sX[buf][row][2 * q + 1] = (float)rx[i].y;
       sY[buf][row][2 * q] = (float)ry[i].x;
       sY[buf][row][2 * q + 1] = (float)ry[i].y;
     }
   };
-  f16v acc[2][2], acc2[2][2];
-  double accd[2][2][16];
+  f16v acc[2][FN], acc2[2][FN];
+  double accd[2][FN][16];
   f16v zero;
 #pragma unroll
   for (int r = 0; r < 16; ++r) zero[r] = 0.0f;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < FN; ++j) {
       acc[i][j] = zero;
       acc2[i][j] = zero;
 #pragma unroll
       for (int r = 0; r < 16; ++r) accd[i][j][r] = 0.0;
     }
-  const int nk = (int)(Np / F32_BK);
+  const int nk = (int)(Np / BK);
   gload(0);
   swrite(0);
   __syncthreads();
-  auto stage = [&](int kt, f16v (&acur)[2][2], f16v (&aprev)[2][2], bool fold_prev) {
-    const int buf = kt & 1;
-    if (kt + 1 < nk) gload((kt + 1) * F32_BK);
-    int m = 0;  // MFMA index within the stage
+  constexpr int V = 2 * FN * 16;  // FP32 values per lane to fold
+  static_assert(4 * (kF32Slice / 2) * 2 * FN >= V, "a slice must fold the whole previous tile");
+  // One 16-wide slice of k from LDS buffer buf at column k0: MFMAs into a
+  // fresh acur; when fold_prev, aprev (the previous slice) is added into FP64
+  // meanwhile.
+  auto slice = [&](int buf, int k0, f16v (&acur)[2][FN], f16v (&aprev)[2][FN], bool fold_prev) {
+    int m = 0;  // MFMA index within the slice
 #pragma unroll
-    for (int kk = 0; kk < F32_BK; kk += 2) {
-      float av[2], bv[2];
+    for (int kk = 0; kk < kF32Slice; kk += 2) {
+      float av[2], bv[FN];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) av[i] = sX[buf][wm * 64 + i * 32 + (lane & 31)][kk + (lane >> 5)];
+      for (int i = 0; i < 2; ++i) av[i] = sX[buf][wm * 64 + i * 32 + (lane & 31)][k0 + kk + (lane >> 5)];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) bv[j] = sY[buf][wn * 64 + j * 32 + (lane & 31)][kk + (lane >> 5)];
+      for (int j = 0; j < FN; ++j)
+        bv[j] = sY[buf][wn * (32 * FN) + j * 32 + (lane & 31)][k0 + kk + (lane >> 5)];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < FN; ++j) {
           acur[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv[j], kk == 0 ? zero : acur[i][j], 0,
                                                             0, 0);
-          if (fold_prev && m < 16) {
+          if (fold_prev && 4 * m < V) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
               const int v = 4 * m + q;
-              accd[v >> 5][(v >> 4) & 1][v & 15] += (double)aprev[v >> 5][(v >> 4) & 1][v & 15];
+              accd[v / (16 * FN)][(v / 16) % FN][v % 16] += (double)aprev[v / (16 * FN)][(v / 16) % FN][v % 16];
             }
           }
           ++m;
         }
     }
+  };
+  // slices alternate between acc (even global slice index) and acc2 (odd)
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload((kt + 1) * BK);
+#pragma unroll
+    for (int sl = 0; sl < SL; ++sl) {
+      const int gs = kt * SL + sl;  // global slice index
+      if ((gs & 1) == 0) slice(buf, sl * kF32Slice, acc, acc2, gs > 0);
+      else slice(buf, sl * kF32Slice, acc2, acc, true);
+    }
     if (kt + 1 < nk) swrite(buf ^ 1);
     __syncthreads();
-  };
-  for (int kt = 0; kt < nk; kt += 2) {
-    stage(kt, acc, acc2, kt > 0);
-    if (kt + 1 < nk) stage(kt + 1, acc2, acc, true);
   }
   {
-    // the last stage's tile
-    f16v (&last)[2][2] = (nk & 1) ? acc : acc2;
+    // the last slice's tile
+    f16v (&last)[2][FN] = ((nk * SL) & 1) ? acc : acc2;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < FN; ++j)
 #pragma unroll
         for (int r = 0; r < 16; ++r) accd[i][j][r] += (double)last[i][j][r];
   }
@@ -318,11 +358,11 @@ __global__ __launch_bounds__(kThreads) void k_gemm_f32(GemmArgs a) {
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int64_t row = (int64_t)tm * BM + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int64_t col = (int64_t)tn * BN + wn * 64 + j * 32 + (lane & 31);
+        const int64_t col = (int64_t)tn * BN + wn * (32 * FN) + j * 32 + (lane & 31);
         epi<double>(a, z, row, col, accd[i][j][r], dsum);
       }
   if (a.W) {
@@ -571,10 +611,10 @@ hipError_t gemm(const GemmArgs& a, hipStream_t s) {
   const dim3 grid((unsigned)gemm_tiles(a.eng, a.Np, a.tile), 1, (unsigned)a.batch);
   switch (a.eng) {
     case Engine::F64:
-      hipLaunchKernelGGL(k_gemm_f64, grid, dim3(kThreads), 0, s, a);
+      hipLaunchKernelGGL((k_gemm_f64<kF64BK, kF64NW>), grid, dim3(kF64NW * 64), 0, s, a);
       return hipGetLastError();
     case Engine::F32:
-      hipLaunchKernelGGL(k_gemm_f32, grid, dim3(kThreads), 0, s, a);
+      hipLaunchKernelGGL((k_gemm_f32<kF32BK, kF32NW>), grid, dim3(kF32NW * 64), 0, s, a);
       return hipGetLastError();
     case Engine::BF16S2:
       return edge == 256 ? launch_bf16<2, 256, 16, kWaves256>(a, grid, s)

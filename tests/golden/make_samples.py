@@ -6,7 +6,9 @@ the canonical mu jet, response traces, max |P^(k)| and the values of P0,
 P1[d], P2[d] at a fixed set of seeded (i, j) positions (random pairs plus
 diagonal entries).
 
-    python tests/golden/make_samples.py banded8192 cubic2048 adjoint4096 batch64
+    python tests/golden/make_samples.py banded8192 cubic2048 adjoint4096 batch64 banded8192_rows
+
+``banded8192_rows`` writes whole row blocks instead (see ``make_rows``).
 """
 import os
 import sys
@@ -50,13 +52,16 @@ def make_batch(name):
     c = workloads.CONFIGS[name]
     t0 = time.time()
     systems = workloads.batched_systems(c["seed"], count=c["count"])
+    order = c["order"]
     rows = dict(N=[], beta=[], Ne=[], mu0=[], mu1=[], tr_h1p1=[], i=[], j=[], P0=[], P1=[],
                 max_P1=[])
+    if order >= 2:
+        rows.update(mu2=[], tr_h1p2=[], P2=[], max_P2=[])
     for k, sy in enumerate(systems):
         lx, ly, lz = sy["dims"]
         h0 = workloads.cubic_lattice(lx, ly, lz, sy["seed"])
         h1 = list(workloads.lattice_dipoles(lx, ly, lz))[: c["dirs"]]
-        r = oracle.canonical_response(h0, h1, None, sy["beta"], sy["Ne"], c["n"], order=1)
+        r = oracle.canonical_response(h0, h1, None, sy["beta"], sy["Ne"], c["n"], order=order)
         rng = np.random.default_rng(k)
         ii = rng.integers(0, sy["N"], 64)
         jj = np.where(np.arange(64) % 2 == 0, ii, rng.integers(0, sy["N"], 64))
@@ -71,14 +76,45 @@ def make_batch(name):
         rows["P0"].append(r["P0"][ii, jj])
         rows["P1"].append([p[ii, jj] for p in r["P1"]])
         rows["max_P1"].append([np.abs(p).max() for p in r["P1"]])
+        if order >= 2:
+            rows["mu2"].append(r["mu2"])
+            rows["tr_h1p2"].append(r["tr_h1p2"])
+            rows["P2"].append([p[ii, jj] for p in r["P2"]])
+            rows["max_P2"].append([np.abs(p).max() for p in r["P2"]])
     out = {k: np.array(v) for k, v in rows.items()}
+    out["order"] = order
     out["seconds"] = time.time() - t0
     path = os.path.join(HERE, f"{name}_samples.npz")
     np.savez_compressed(path, **out)
     print(f"{name}: {time.time() - t0:.1f} s -> {path}", flush=True)
 
 
+ROW_BLOCKS = [(0, 16), (4088, 16), (8176, 16)]  # first tile, across the 4096 tile edge, last tile
+
+
+def make_rows(name):
+    """Whole rows of P0, P1[0] and P2[0] (the x direction) of the banded workload: rows 0-15,
+    4088-4103 and 8176-8191.  Stored as FP32 values of P0 and of P^(k) / max |P^(k)| (k = 1, 2):
+    the storage rounding (at most 6e-8 of the scale) sits far below the 1e-6 bound the values
+    check."""
+    c = workloads.config(name.replace("_rows", ""))
+    t0 = time.time()
+    h1v = [np.diag(h).copy() for h in c["H1"]]
+    r = oracle.canonical_response(c["H0"], h1v[:1], None, c["beta"], c["Ne"], c["n"], order=2)
+    rows = np.concatenate([np.arange(a, a + n) for a, n in ROW_BLOCKS])
+    m1 = np.abs(r["P1"][0]).max()
+    m2 = np.abs(r["P2"][0]).max()
+    out = dict(N=c["N"], rows=rows, max_P1=m1, max_P2=m2, mu0=r["mu0"], mu1=r["mu1"][0], mu2=r["mu2"][0],
+               P0=r["P0"][rows].astype(np.float32), P1=(r["P1"][0][rows] / m1).astype(np.float32),
+               P2=(r["P2"][0][rows] / m2).astype(np.float32), seconds=time.time() - t0)
+    path = os.path.join(HERE, f"{name}.npz")
+    np.savez_compressed(path, **out)
+    print(f"{name}: {time.time() - t0:.1f} s -> {path}", flush=True)
+
+
 def make(name):
+    if name.endswith("_rows"):
+        return make_rows(name)
     if name.startswith("adjoint"):
         return make_adjoint(name)
     if name.startswith("batch"):

@@ -161,7 +161,7 @@ CONFIGS = {
                       dirs=1, order=2),
     "banded8192": dict(kind="banded", N=8192, grid=(32, 16, 16), seed=3, beta=40.0, Ne=4096.0,
                        n=30, dirs=3, order=2),
-    "batch64": dict(kind="batch", seed=4, count=64, n=25, dirs=3, order=1),
+    "batch64": dict(kind="batch", seed=4, count=64, n=25, dirs=3, order=2),
     "adjoint4096": dict(kind="cubic", dims=(16, 16, 16), N=4096, seed=5, beta=20.0, Ne=2048.0,
                         n=25, dirs=1, order=0),
 }
