@@ -195,6 +195,27 @@ dmpt_status dmpt_set_options(dmpt_ctx ctx, const dmpt_options* opt);
 dmpt_status dmpt_fermi_recursion(dmpt_ctx ctx, int64_t N, const double* H0, double beta,
                                  double mu, int n, double* P0, dmpt_stats* st);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same P0 as
+ * dmpt_fermi_recursion in FP64 (FP64 MFMA products, conjugate gradients from
+ * the previous iterate), without a context and without any allocation.  The
+ * workspace is a file-scope device array of the library (11 MiB per device,
+ * held until the process ends), which limits N to 1 <= N <= 512 (larger N:
+ * DMPT_ERR_ARG).  Work is queued on `hip_stream` (NULL: the null stream) of
+ * the current device; the call returns without waiting and reads nothing
+ * back, so every solve runs a fixed, a-priori number of CG iterations (the
+ * Chebyshev bound for the system matrix's condition number of at most 2;
+ * solves that converge earlier stop on the device).  Inputs are checked on the
+ * device: `status` (device int, may be NULL) receives DMPT_OK,
+ * DMPT_ERR_NONFINITE or DMPT_ERR_RANGE when the queued work runs; P0 is
+ * meaningless unless it reads DMPT_OK.  Host-side argument errors return
+ * DMPT_ERR_ARG before anything is queued (dmpt_last_error(NULL) explains).
+ * Every call on a device shares that device's array: calls that overlap in
+ * time on one device (two streams, two host threads) race and give wrong
+ * results.  H0, P0: N x N device FP64, row major. */
+dmpt_status dmpt_fermi_recursion_noalloc(int64_t N, const double* H0, double beta, double mu, int n,
+                                         double* P0, int* status, void* hip_stream);
+
 /* One pass of Algorithm 1's inner loop at a given mu jet (no Newton):
  * orders 0..order (order in {0, 1, 2, 3}: Algorithm 1's solve lines) for d
  * directions of H(lambda) = H0 + lambda H1 + lambda^2 H2 + lambda^3 H3.

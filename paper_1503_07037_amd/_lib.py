@@ -87,7 +87,7 @@ EXPORTS = [
     "dmpt_default_options", "dmpt_init", "dmpt_finalize", "dmpt_last_error", "dmpt_set_options",
     "dmpt_fermi_recursion", "dmpt_response", "dmpt_mu_newton", "dmpt_mu_newton_batched",
     "dmpt_backward", "dmpt_profile", "dmpt_profile_get", "dmpt_bench_product", "dmpt_autotune",
-    "dmpt_congruence",
+    "dmpt_congruence", "dmpt_fermi_recursion_noalloc",
 ]
 
 _lib = None
@@ -128,6 +128,7 @@ def load(path=None):
     lib.dmpt_bench_product.argtypes = [P, I64, I, I, I, DP, DP]
     lib.dmpt_autotune.argtypes = [P, I64, ctypes.POINTER(I)]
     lib.dmpt_congruence.argtypes = [P, I64, P, P, P, I, ctypes.POINTER(Stats)]
+    lib.dmpt_fermi_recursion_noalloc.argtypes = [I64, P, D, D, I, P, P, P]
     for name in EXPORTS:
         if name not in ("dmpt_default_options", "dmpt_last_error"):
             getattr(lib, name).restype = ctypes.c_int

@@ -20,6 +20,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1887,6 +1888,85 @@ dmpt_status linear_orders(Call& k, const PassIn& base, int64_t N, int order, dou
   return DMPT_OK;
 }
 
+// ---------------------------------------------------------------- no-allocation path
+// dmpt_fermi_recursion_noalloc works in a file-scope device array instead of
+// a context's workspace.  Each device holds its own copy of the array; its
+// device address is looked up once per device (hipGetSymbolAddress, with the
+// device current) and the host-side views of the workspace are built then.
+// Nothing is allocated on the device afterwards.
+constexpr int64_t kScratchNmax = 512;                     // largest N of the no-allocation path
+constexpr size_t kScratchMember = (size_t)kScratchNmax * kScratchNmax * sizeof(double);
+constexpr int kScratchMembers = 5;                        // D0, S0, R, P, Q
+constexpr size_t kScratchBytes = kScratchMembers * kScratchMember + ((size_t)1 << 20);  // 11 MiB
+constexpr int kScratchDevices = 64;
+
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+struct ScratchDevice {
+  std::once_flag once;
+  dmpt_status st = DMPT_ERR_HIP;
+  std::string err;
+  dmpt_ctx c = nullptr;      // host-side views of this device's array (never freed)
+  int* d_status = nullptr;   // in the array: status word when the caller passes none
+};
+ScratchDevice g_scratch[kScratchDevices];
+
+// Carve the views once per device: five Np x Np FP64 members of the largest
+// padded size, then the solver scalars, partial sums and results.
+void scratch_setup(ScratchDevice& sd, int device) {
+  char* base = nullptr;
+  const hipError_t e = hipGetSymbolAddress((void**)&base, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !base) {
+    sd.err = std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e);
+    sd.st = DMPT_ERR_HIP;
+    return;
+  }
+  dmpt_ctx c = new dmpt_ctx_s();
+  c->device = device;
+  dmpt_default_options(&c->opt);
+  c->opt.tol_occ = default_tol_occ(DMPT_FP64, 0);
+  c->opt.tol_cg = default_tol_cg(DMPT_FP64, 0);
+  c->n_max = kScratchNmax;
+  c->np_max = padded(kScratchNmax);
+  c->dirs_max = 0;
+  c->esize = 8;
+  c->planes = 0;
+  c->hstride = c->opt.max_cg + 2;
+  reg_add(c, base, kScratchBytes);
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base + off;
+    off += (bytes + 255) / 256 * 256;
+    return p;
+  };
+  Group* gs[kScratchMembers] = {&c->ws.D0, &c->ws.S0, &c->ws.R, &c->ws.P, &c->ws.Q};
+  for (Group* g : gs) {
+    g->m = take(kScratchMember);
+    g->count = 1;
+  }
+  c->ws.rr = (double*)take(sizeof(double) * c->hstride);
+  c->ws.pq = (double*)take(sizeof(double) * c->hstride);
+  c->ws.ref = (double*)take(sizeof(double));
+  c->ws.active = (int*)take(sizeof(int));
+  c->ws.iters = (int*)take(sizeof(int));
+  c->part_count = std::max<size_t>((size_t)(c->np_max / 128) * (c->np_max / 128),
+                                   (size_t)reduce_blocks((int64_t)c->np_max * c->np_max));
+  c->d_part = (double*)take(sizeof(double) * c->part_count);
+  c->d_res = (double*)take(sizeof(double) * RES_COUNT);
+  c->d_flag = (int*)take(sizeof(int) * 4);
+  c->d_gersh = (double*)take(sizeof(double) * (2 + 2 * (size_t)kScratchNmax));
+  c->d_cgstat = (int*)take(sizeof(int) * 4);
+  sd.d_status = (int*)take(sizeof(int));
+  if (off > kScratchBytes) {
+    sd.err = "internal: the no-allocation workspace does not fit its array";
+    sd.st = DMPT_ERR_NOMEM;
+    delete c;
+    return;
+  }
+  sd.c = c;
+  sd.st = DMPT_OK;
+}
+
 }  // namespace
 
 // ======================================================================= C ABI
@@ -2264,6 +2344,65 @@ dmpt_status dmpt_fermi_recursion(dmpt_ctx c, int64_t N, const double* H0, double
   double m[1] = {mu};
   return dmpt_response(c, N, H0, 0, nullptr, nullptr, nullptr, beta, n, 0, m, P0, nullptr, nullptr,
                        nullptr, st);
+}
+
+dmpt_status dmpt_fermi_recursion_noalloc(int64_t N, const double* H0, double beta, double mu, int n,
+                                         double* P0, int* status, void* hip_stream) {
+  auto arg = [](const char* msg) {
+    std::snprintf(g_noctx_err, sizeof g_noctx_err, "%s", msg);
+    return DMPT_ERR_ARG;
+  };
+  if (N < 1 || N > kScratchNmax) return arg("no-allocation path: N must lie in [1, 512]");
+  if (!H0 || !P0) return arg("no-allocation path: H0 and P0 must be non-NULL");
+  if (!(beta > 0.0) || !std::isfinite(beta)) return arg("no-allocation path: beta must be finite and > 0");
+  if (!std::isfinite(mu)) return arg("no-allocation path: mu must be finite");
+  if (n < 1 || n > 62) return arg("no-allocation path: n must lie in [1, 62]");
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess || device < 0 || device >= kScratchDevices) {
+    std::snprintf(g_noctx_err, sizeof g_noctx_err, "no-allocation path: no usable current device");
+    return DMPT_ERR_HIP;
+  }
+  ScratchDevice& sd = g_scratch[device];
+  std::call_once(sd.once, [&]() { scratch_setup(sd, device); });
+  if (sd.st != DMPT_OK) {
+    std::snprintf(g_noctx_err, sizeof g_noctx_err, "%s", sd.err.c_str());
+    return sd.st;
+  }
+  dmpt_ctx c = sd.c;
+  c->stream = (hipStream_t)hip_stream;
+  hipStream_t s = c->stream;
+  int* st_word = status ? status : sd.d_status;
+  auto hip = [&](hipError_t e) {
+    if (e == hipSuccess) return DMPT_OK;
+    std::snprintf(g_noctx_err, sizeof g_noctx_err, "no-allocation path: HIP error %s",
+                  hipGetErrorString(e));
+    return DMPT_ERR_HIP;
+  };
+  // inputs: non-finite values and the range of the recursion, decided on the device
+  STCHK(hip(set_values(c->d_flag, 0, 1, c->d_res + RES_HALF, 0.5, 1, s)));
+  STCHK(hip(set_values(c->d_cgstat, 0, 4, nullptr, 0.0, 0, s)));
+  STCHK(hip(nonfinite_scan(H0, N, N, c->d_flag, s)));
+  STCHK(hip(gershgorin(H0, N, c->d_gersh, s)));
+  STCHK(hip(input_status(c->d_gersh, c->d_flag, beta, mu, n, st_word, s)));
+  // the recursion with fixed-count solves (no host synchronisation): every
+  // step's T' has eigenvalues in [1, 2], so the Chebyshev bound at kappa 2
+  // covers every solve; converged solves stop early on the device
+  Call k = make_call(c, N, false);
+  k.graph = true;
+  k.cg_iters = cg_bound(2.0, k.tol_cg, c->opt.max_cg);
+  const double cs = std::ldexp(beta, -(n + 2));
+  PassIn in{H0, 0, nullptr, nullptr, beta, n, 0, &mu};
+  dmpt_status r = init_d<double>(k, in, cs);
+  for (int step = 0; r == DMPT_OK && step < n; ++step) r = recursion_step<double>(k, 0, 0, -1);
+  if (r == DMPT_OK) {
+    // P0 = I/2 - sym(D_n)
+    r = hip(sym_combine<double, double>((const double*)mptr(k, c->ws.D0, 0), k.Np, 0, k.N, k.Np, -0.5,
+                                        c->d_res + RES_HALF, 0, P0, k.N, 0, nullptr, 0, 1, s));
+  }
+  if (r != DMPT_OK && r != DMPT_ERR_HIP) {
+    std::snprintf(g_noctx_err, sizeof g_noctx_err, "%s", c->err.c_str());
+  }
+  return r;
 }
 
 dmpt_status dmpt_response(dmpt_ctx c, int64_t N, const double* H0, int d, const double* const* H1,

@@ -144,6 +144,11 @@ hipError_t cg_update_p(T* P, const T* R, int64_t n, int64_t stride, int batch,
 hipError_t cg_check(const double* rr, const double* rr0, const double* ref, int hstride, int batch,
                     double tol2, double eta2, int* active, int* iters, hipStream_t s);
 
+// *status = DMPT_ERR_NONFINITE when *flag is set, DMPT_ERR_RANGE when
+// beta max(|gersh[0] - mu|, |gersh[1] - mu|) >= 2^(n+1), else DMPT_OK (one thread).
+hipError_t input_status(const double* gersh, const int* flag, double beta, double mu, int n, int* status,
+                        hipStream_t s);
+
 // Statistics of a fixed-count solve: stat[0] += sum of iterations, stat[1] =
 // max(stat[1], iterations), stat[2] += members still active (unconverged).
 hipError_t cg_account(const int* active, const int* iters, int batch, int* stat, hipStream_t s);

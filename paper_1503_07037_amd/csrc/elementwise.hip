@@ -326,6 +326,19 @@ __global__ void k_cg_check(const double* rr, const double* rr0, const double* re
   if (!(r > tol2 * ref[z] || r > eta2 * rr0[z * hstride])) active[z] = 0;
 }
 
+// Device-side verdict on the inputs of a call that reads nothing back: a
+// non-finite value (flag set) gives DMPT_ERR_NONFINITE, beta max|eps - mu| >=
+// 2^(n+1) over the Gershgorin interval g[0..1] gives DMPT_ERR_RANGE, else 0.
+__global__ void k_input_status(const double* g, const int* flag, double beta, double mu, int n,
+                               int* status) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double emax = fmax(fabs(g[0] - mu), fabs(g[1] - mu));
+  int st = 0;
+  if (*flag) st = DMPT_ERR_NONFINITE;
+  else if (!(beta * emax < ldexp(1.0, n + 1))) st = DMPT_ERR_RANGE;
+  *status = st;
+}
+
 // Statistics of a fixed-count (graph-replayed) solve: iterations summed and
 // their maximum over the members that ran, and the members still above their
 // tolerance at the end (iters counts the initial check as well).
@@ -830,6 +843,12 @@ hipError_t cg_check(const double* rr, const double* rr0, const double* ref, int 
                     double tol2, double eta2, int* active, int* iters, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_check, dim3((batch + 63) / 64), dim3(64), 0, s, rr, rr0, ref, hstride,
                      batch, tol2, eta2, active, iters);
+  return hipGetLastError();
+}
+
+hipError_t input_status(const double* gersh, const int* flag, double beta, double mu, int n, int* status,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_input_status, dim3(1), dim3(64), 0, s, gersh, flag, beta, mu, n, status);
   return hipGetLastError();
 }
 
