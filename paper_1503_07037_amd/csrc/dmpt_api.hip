@@ -1828,8 +1828,8 @@ dmpt_status linear_orders(Call& k, const PassIn& base, int64_t N, int order, dou
       return fail(c, DMPT_ERR_NOCONV, "Tr J vanished: the occupation does not respond to mu");
     const double rel = std::fabs(c->h_res[RES_TR] - Ne) / (double)N;
     if (c->log)
-      std::fprintf(stderr, "[dmpt] order-1 pass: mu0 %.15g TrP0-Ne %.3e rel %.3e TrJ %.6e\n", mu[0],
-                   c->h_res[RES_TR] - Ne, rel, trJ);
+      std::fprintf(stderr, "[dmpt] order-1 pass: mu0 %.15g TrP0-Ne %.3e rel %.3e TrJ %.6e cg_total %ld\n",
+                   mu[0], c->h_res[RES_TR] - Ne, rel, trJ, c->cg_total);
     if (rel <= tol || (rel > 0.5 * prev && rel <= 1e3 * tol)) {
       if (rel > tol) c->flags |= DMPT_FLAG_NOISE_FLOOR;
       *settled = true;
@@ -1853,6 +1853,7 @@ dmpt_status linear_orders(Call& k, const PassIn& base, int64_t N, int order, dou
     k.chain = 0;
     k.cmu = nullptr;
     *passes += 1;
+    if (c->log) std::fprintf(stderr, "[dmpt] order-2 pass: cg_total %ld\n", c->cg_total);
     for (int z = 0; z < d; ++z) {
       mu[1 + d + z] = c->h_res[RES_TR + 1 + d + z] / trJ;
       HIPCHK(c, axpby<double>(c->jout, 0, P2[z], 0, nn, 1, -mu[1 + d + z], 1.0, none, 0, 0, s));

@@ -2,7 +2,8 @@
 
 Systems of uneven size share graph-captured batched passes; each one must
 match the FP64 oracle as if solved alone.  The full 64-system workload runs
-in FP32 and is compared on the oracle's stored per-system samples.
+with FP32 products at orders 0-2 and is compared on the oracle's stored
+per-system samples and, for five systems, element by element.
 """
 import os
 
@@ -92,7 +93,9 @@ def test_batch_matches_single_system_path(dm, small_batch):
 
 @pytest.mark.timeout(900)
 def test_batch64_fp32_full_workload(dm):
-    """64 cubic systems, N in [256, 3072] log-uniform, beta in U(5, 40), 3 directions, FP32."""
+    """64 cubic systems, N in [256, 3072] log-uniform, beta in U(5, 40), 3 directions, orders 0-2,
+    FP32 products: every system on the oracle's stored samples of P0, P1 and P2, and five systems
+    (the smallest, the largest and three between) element by element against the oracle."""
     print("case batch64 fp32", flush=True)
     path = os.path.join(HERE, "golden", "batch64_samples.npz")
     if not os.path.exists(path):
@@ -107,9 +110,10 @@ def test_batch64_fp32_full_workload(dm):
         H1s.append([T(np.diag(v)) for v in workloads.lattice_dipoles(lx, ly, lz)])
     nmax = max(sy["N"] for sy in systems)
     with dm.Context(nmax, dirs_max=3, prec="fp32") as ctx:
-        P0, P1, _, mus, st = ctx.mu_newton_batched(H0s, H1s, [sy["beta"] for sy in systems],
-                                                   [sy["Ne"] for sy in systems], n=c["n"], order=1)
-    print(f"  passes={st['newton_iters']} seconds={st['seconds']:.1f} "
+        P0, P1, P2, mus, st = ctx.mu_newton_batched(H0s, H1s, [sy["beta"] for sy in systems],
+                                                    [sy["Ne"] for sy in systems], n=c["n"], order=2)
+    print(f"  passes={st['newton_iters']} seconds={st['seconds']:.1f} cg={st['cg_iters_total']} "
+          f"unconverged={st['cg_unconverged']} flags={st['flags']} "
           f"useful TFLOP/s={st['useful_flops'] / st['seconds'] / 1e12:.1f}")
     worst = 0.0
     for k in range(len(systems)):
@@ -118,9 +122,25 @@ def test_batch64_fp32_full_workload(dm):
         e0 = float(np.abs(P0[k][ii, jj].cpu().numpy() - g["P0"][k]).max())
         e1 = max(float(np.abs(P1[k][z][ii, jj].cpu().numpy() - g["P1"][k][z]).max() / g["max_P1"][k][z])
                  for z in range(3))
-        worst = max(worst, e0, e1)
+        e2 = max(float(np.abs(P2[k][z][ii, jj].cpu().numpy() - g["P2"][k][z]).max() / g["max_P2"][k][z])
+                 for z in range(3))
+        worst = max(worst, e0, e1, e2)
     print(f"  worst sampled error {worst:.2e}")
     assert worst < 1e-6
+    order = sorted(range(len(systems)), key=lambda k: systems[k]["N"])
+    for k in [order[0], order[16], order[32], order[48], order[-1]]:
+        sy = systems[k]
+        lx, ly, lz = sy["dims"]
+        r = oracle.canonical_response(workloads.cubic_lattice(lx, ly, lz, sy["seed"]),
+                                      list(workloads.lattice_dipoles(lx, ly, lz)), None, sy["beta"],
+                                      sy["Ne"], c["n"], order=2)
+        e0 = float(np.abs(P0[k].cpu().numpy() - r["P0"]).max())
+        e1 = max(float(np.abs(P1[k][z].cpu().numpy() - r["P1"][z]).max() / np.abs(r["P1"][z]).max())
+                 for z in range(3))
+        e2 = max(float(np.abs(P2[k][z].cpu().numpy() - r["P2"][z]).max() / np.abs(r["P2"][z]).max())
+                 for z in range(3))
+        print(f"  system {k} N={sy['N']} beta={sy['beta']:.1f}: full {e0:.2e} {e1:.2e} {e2:.2e}")
+        assert e0 < 1e-6 and e1 < 1e-6 and e2 < 1e-6
 
 
 @pytest.mark.parametrize("d", [1, 3])

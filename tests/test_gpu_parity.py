@@ -412,6 +412,15 @@ def test_banded8192_benchmark_configuration(dm):
     assert abs(float(torch.trace(P0)) - c["Ne"]) < 1e-6 * c["N"]
     for p in P1 + P2:
         assert abs(float(torch.trace(p))) < 1e-6 * float(p.abs().max()) * c["N"]
+    # whole rows: the first and last 128-wide tiles and across the tile edge at 4096 (x direction)
+    rb = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "banded8192_rows.npz"))
+    rows = torch.as_tensor(rb["rows"], device=P0.device)
+    q = float(rb["quantum"])
+    r0 = float(np.abs(P0[rows].cpu().numpy() - rb["P0"] * q).max())
+    r1 = float(np.abs(P1[0][rows].cpu().numpy() / float(rb["max_P1"]) - rb["P1"] * q).max())
+    r2 = float(np.abs(P2[0][rows].cpu().numpy() / float(rb["max_P2"]) - rb["P2"] * q).max())
+    print(f"  row blocks ({len(rb['rows'])} rows x {c['N']}): {r0:.2e} {r1:.2e} {r2:.2e}")
+    assert r0 < 1e-6 and r1 < 1e-6 and r2 < 1e-6
 
 
 # ------------------------------------------------------------------ checks (check = 1)
