@@ -1581,7 +1581,7 @@ dmpt_status adjoint_impl(const Call& k, const double* H0, double beta, double mu
 struct Bucket {
   int64_t Np = 0;
   int first = 0, m = 0;          // slots [first, first + m) of the bucketed order
-  WS wsA, wsB;                   // the same matrices, masks of the two stages
+  WS ws[3];                      // the same matrices with the system masks of each stage
   double xmax = 0.0;             // max_s c_s * spread_s (|D_0| bound)
 };
 
@@ -1602,12 +1602,14 @@ double kappa_bound(double x, int step) {
   return 1.0 + t * t;
 }
 
-// lin: order 1 with the linear schedule; the response P_J to H1 = I runs as
-// an extra direction (its D_0 is c I: no input, no mu shift), is written to
+// lin = 1: order 1 with the linear schedule; the response P_J to H1 = I runs
+// as an extra direction (its D_0 is c I: no input, no mu shift), is written to
 // PJs[slot], and each system's P1 is then corrected to Tr P1 = 0 exactly
-// (lin_correct), so one pass settles mu1.
+// (lin_correct), so one pass settles mu1.  lin = 2: order 2 at the settled
+// mu1 (no extra direction); each P2 is corrected to Tr P2 = 0 with the P_J
+// the order-1 pass stored, so one pass settles mu2.  wsi: the stage's masks.
 template <class T>
-dmpt_status batched_pass(dmpt_ctx c, std::vector<Bucket>& bk, bool stageB, int ord, int d, int n,
+dmpt_status batched_pass(dmpt_ctx c, std::vector<Bucket>& bk, int wsi, int ord, int d, int n,
                          Engine eng, const std::vector<int>& slot_sys, const double* const* H0s,
                          const double* const* H1s, double* const* P0s, double* const* P1s,
                          double* const* P2s, const int64_t* Ns, const std::vector<double>& cs,
@@ -1616,12 +1618,12 @@ dmpt_status batched_pass(dmpt_ctx c, std::vector<Bucket>& bk, bool stageB, int o
                          double* d_delta) {
   hipStream_t s = c->stream;
   const int J = 1 + 2 * d;
-  const int dd = d + lin;  // directions the recursion carries
+  const int dd = d + (lin == 1 ? 1 : 0);  // directions the recursion carries
   std::vector<Call> ks(bk.size());
   for (size_t b = 0; b < bk.size(); ++b) {
     Call& k = ks[b];
     k = make_call(c, bk[b].Np, false);
-    k.w = stageB ? &bk[b].wsB : &bk[b].wsA;
+    k.w = &bk[b].ws[wsi];
     k.eng = eng;
     k.np = engine_planes(eng);
     k.N = bk[b].Np;  // inside the workspace every member is treated as Np x Np
@@ -1645,7 +1647,7 @@ dmpt_status batched_pass(dmpt_ctx c, std::vector<Bucket>& bk, bool stageB, int o
       HIPCHK(c, (sym_combine<double, T>(H0s[sys], N, 0, N, k.Np, 0.5 * cs[sys],
                                         d_mu_shift + (int64_t)slot * J, 0, (T*)mptr(k, k.w->D0, i),
                                         k.Np, 0, pl, k.np, 1, s, nullptr, 0.0, gate)));
-      if (lin) {
+      if (lin == 1) {
         // D_0 of the J direction: c I (the input is not read with a = 0)
         planes_of(k, k.w->D1, i * dd + d, pl);
         HIPCHK(c, (sym_combine<double, T>(H0s[sys], N, 0, N, k.Np, 0.0, d_par + 6 * (int64_t)slot + 2, 0,
@@ -1702,7 +1704,7 @@ dmpt_status batched_pass(dmpt_ctx c, std::vector<Bucket>& bk, bool stageB, int o
           HIPCHK(c, sum_partials(c->d_part, reduce_blocks(N * N), 1,
                                  t + 2 * J + 1 + (o == 1 ? 0 : d) + z, 1, 0, s));
         }
-      if (lin) {
+      if (lin == 1) {
         double* PJ = PJs[slot];
         HIPCHK(c, (sym_combine<T, double>((const T*)mptr(k, k.w->D1, i * dd + d), k.Np, 0, N, k.Np, -0.5,
                                           nullptr, 0, PJ, N, 0, nullptr, 0, 1, s, nullptr, 0.0, gate)));
@@ -1713,7 +1715,13 @@ dmpt_status batched_pass(dmpt_ctx c, std::vector<Bucket>& bk, bool stageB, int o
         }
         HIPCHK(c, lin_correct(t, d, J, rs0, d_mu + (int64_t)slot * J, d_mu_shift + (int64_t)slot * J,
                               cs[sys], d_delta + (int64_t)slot * d, P1s + (size_t)sys * d, PJ, N, gate,
-                              s));
+                              s, 1));
+      }
+      if (lin == 2) {
+        // P2 -= (Tr P2 / Tr P_J) P_J with the P_J of the order-1 pass
+        HIPCHK(c, lin_correct(t, d, J, rs0, d_mu + (int64_t)slot * J, d_mu_shift + (int64_t)slot * J,
+                              cs[sys], d_delta + (int64_t)slot * d, P2s + (size_t)sys * d, PJs[slot], N,
+                              gate, s, 2));
       }
     }
   }
@@ -2639,9 +2647,11 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
   hipStream_t s = c->stream;
   reset_stats(c);
   const int J = 1 + 2 * d;
-  // linear schedule (order 1): the final stage carries the J direction and
-  // settles mu1 in one pass (batched_pass); its records follow the others
-  const int lin = (c->opt.schedule >= 1 && order == 1) ? 1 : 0;
+  // linear schedule (orders 1 and 2): after the order-0 stage, one order-1
+  // pass carries the J direction and settles mu1 (batched_pass), and at order
+  // 2 one more pass settles mu2 with the stored P_J; J's records follow the
+  // others
+  const int lin = (c->opt.schedule >= 1 && order >= 1) ? 1 : 0;
   const int rs0 = 2 * J + 1 + 2 * d;
   const int rs = rs0 + (lin ? 2 + d : 0);
   // per system: Gershgorin interval, range guard, bounds of mu0, c
@@ -2770,6 +2780,7 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
   int* done = d_flags + 2 * nsys;
   int* passes = d_flags + 3 * nsys;
   int* status = d_flags + 4 * nsys;
+  int* actC = d_flags + 5 * nsys;
   for (auto& b : bk) {
     const int md = b.m * dmem;
     WS w;
@@ -2787,10 +2798,10 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
       cleanup();
       return fail(c, DMPT_ERR_NOMEM, "batched workspace allocation failed");
     }
-    b.wsA = w;
-    b.wsB = w;
-    b.wsA.mask0 = actA + b.first;
-    b.wsB.mask0 = actB + b.first;
+    for (int q = 0; q < 3; ++q) b.ws[q] = w;
+    b.ws[0].mask0 = actA + b.first;
+    b.ws[1].mask0 = actB + b.first;
+    b.ws[2].mask0 = actC + b.first;
   }
   // initial state
   {
@@ -2807,6 +2818,7 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
     }
     std::vector<int> hfl(6 * (size_t)nsys, 0);
     for (int i = 0; i < 2 * nsys; ++i) hfl[i] = 1;
+    for (int i = 5 * nsys; i < 6 * nsys; ++i) hfl[i] = 1;
     std::vector<double> hbrk(2 * (size_t)nsys);
     for (int slot = 0; slot < nsys; ++slot) {
       hbrk[2 * slot] = hpar[6 * (size_t)slot + 3];
@@ -2831,8 +2843,8 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
   const bool staged = c->opt.staged && order > 0;
   const bool prof = c->prof_on;
   c->prof_on = false;  // no event records inside a captured graph
-  hipGraphExec_t gx[2] = {nullptr, nullptr};
-  hipGraph_t gg[2] = {nullptr, nullptr};
+  hipGraphExec_t gx[3] = {nullptr, nullptr, nullptr};
+  hipGraph_t gg[3] = {nullptr, nullptr, nullptr};
   dmpt_status rc = DMPT_OK;
   int total_passes = 0;
   // executed work over every replay, tallied on the device by the products
@@ -2840,12 +2852,30 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
   if (rc == DMPT_OK && (hipMemsetAsync(c->d_tally, 0, 2 * sizeof(double), s) != hipSuccess ||
                         hipMemsetAsync(c->d_cgstat, 0, 4 * sizeof(int), s) != hipSuccess))
     rc = fail(c, DMPT_ERR_HIP, "tally reset failed");
-  for (int stage = staged ? 0 : 1; stage <= 1 && rc == DMPT_OK; ++stage) {
-    const int ord = stage == 0 ? 0 : order;
-    const bool final_stage = stage == 1;
-    if (final_stage && lin && staged) {
-      // mu1 guesses from the converged P0 of the first stage, so the final
-      // pass's affine correction is small (the response is FP32 in this mode)
+  // stages: order-0 Newton replays (staged), then either the linear schedule
+  // (an order-1 pass with J, and at order 2 an order-2 pass) or Algorithm 1's
+  // joint Newton replays of every order
+  struct Stage {
+    int ord, lin, wsi;
+    bool final_stage;
+    double tol;
+  };
+  std::vector<Stage> stages;
+  if (staged) stages.push_back({0, 0, 0, false, lin ? 1e-2 * c->opt.tol_occ : c->opt.tol_occ});
+  if (lin) {
+    stages.push_back({1, 1, order == 1 ? 1 : 2, order == 1, c->opt.tol_occ});
+    if (order == 2) stages.push_back({2, 2, 1, true, c->opt.tol_occ});
+  } else {
+    stages.push_back({order, 0, 1, true, c->opt.tol_occ});
+  }
+  for (size_t si = 0; si < stages.size() && rc == DMPT_OK; ++si) {
+    const Stage& SG = stages[si];
+    const int stage = (int)si;
+    const int ord = SG.ord;
+    const bool final_stage = SG.final_stage;
+    if (SG.lin == 1 && staged) {
+      // mu1 guesses from the converged P0 of the first stage, so the linear
+      // correction after the pass is small
       for (int slot = 0; slot < nsys && rc == DMPT_OK; ++slot) {
         const int sy = slot_sys[slot];
         if (mu1_guess(P0s[sy], Ns[sy], H1s + (size_t)sy * d, d, d_w, d_mu + (size_t)slot * J,
@@ -2867,17 +2897,17 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
       rc = fail(c, DMPT_ERR_HIP, "hipStreamBeginCapture failed");
       break;
     }
-    dmpt_status cr = batched_pass<double>(c, bk, final_stage, ord, d, n, eng, slot_sys, H0s, H1s, P0s,
+    dmpt_status cr = batched_pass<double>(c, bk, SG.wsi, ord, d, n, eng, slot_sys, H0s, H1s, P0s,
                                           P1s, P2s, Ns, cs, d_shift, d_tr, rs, c->d_res + RES_HALF,
-                                          final_stage ? lin : 0, d_par, d_mu, pjs.data(), rs0, d_delta);
+                                          SG.lin, d_par, d_mu, pjs.data(), rs0, d_delta);
     if (cr == DMPT_OK) {
-      // with the linear schedule the final stage runs one pass and no longer
-      // moves mu0: the first stage settles it a hundred times tighter (the
-      // first-order responses carry mu0's error times dP1/dmu0)
-      const double tol_pass = (lin && !final_stage) ? 1e-2 * c->opt.tol_occ : c->opt.tol_occ;
-      const hipError_t e = newton_update(d_tr, rs, d_par, d_mu, d_shift, J, ord * d, tol_pass,
-                                         final_stage ? 1 : 0, final_stage ? actB : actA, done,
-                                         d_prev, d_brk, d_occ, passes, status, nsys, s);
+      // with the linear schedule the later stages run one pass each and no
+      // longer move mu0: the first stage settles it a hundred times tighter
+      // (the responses carry mu0's error times their derivative in mu0)
+      int* act_stage = SG.wsi == 0 ? actA : (SG.wsi == 1 ? actB : actC);
+      const hipError_t e = newton_update(d_tr, rs, d_par, d_mu, d_shift, J, ord * d, SG.tol,
+                                         final_stage ? 1 : 0, act_stage, done, d_prev, d_brk, d_occ,
+                                         passes, status, nsys, s);
       if (e != hipSuccess) cr = fail(c, DMPT_ERR_HIP, "newton_update launch failed");
     }
     hipGraph_t g = nullptr;
@@ -2893,7 +2923,7 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
       break;
     }
     gg[stage] = g;
-    int* act = final_stage ? actB : actA;
+    int* act = SG.wsi == 0 ? actA : (SG.wsi == 1 ? actB : actC);
     std::vector<int> hact(nsys);
     const int passes0 = total_passes;
     const auto ts = std::chrono::steady_clock::now();
@@ -2949,7 +2979,7 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
         hipMemcpy(hfl.data(), d_flags, hfl.size() * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
       rc = fail(c, DMPT_ERR_HIP, "batched result download failed");
   }
-  for (int q = 0; q < 2; ++q) {
+  for (int q = 0; q < 3; ++q) {
     if (gx[q]) (void)hipGraphExecDestroy(gx[q]);
     if (gg[q]) (void)hipGraphDestroy(gg[q]);
   }

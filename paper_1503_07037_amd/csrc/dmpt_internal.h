@@ -178,14 +178,15 @@ template <class T>
 hipError_t fill_pattern(T* x, int64_t n, uint32_t seed, uint16_t* const* planes, int nplanes,
                         hipStream_t s);
 
-// Linear canonical correction of one system (batched solve): with t its
-// trace record (Tr P1_z at 1 + z, Tr(H1_z P1_z) at 2J + 1 + z, Tr P_J at rs0,
-// Tr(H1_z P_J) at rs0 + 2 + z), mu / shift its mu jet and shifts, c its
-// scale: delta_z = Tr P1_z / Tr P_J, mu1_z += delta_z, P1[z] -= delta_z PJ
-// (N x N FP64), records updated.  Does nothing while *gate == 0.
+// Linear canonical correction of one system's order-k responses, k = order
+// (1 or 2; batched solve): with t its trace record (Tr Pk_z at 1 + (k-1) d + z,
+// Tr(H1_z Pk_z) at 2J + 1 + (k-1) d + z, Tr P_J at rs0, Tr(H1_z P_J) at
+// rs0 + 2 + z), mu / shift its mu jet and shifts, c its scale:
+// delta_z = Tr Pk_z / Tr P_J, muk_z += delta_z, Pk[z] -= delta_z PJ (N x N
+// FP64), records updated.  Does nothing while *gate == 0.
 hipError_t lin_correct(double* t, int d, int J, int rs0, double* mu, double* shift, double c,
-                       double* delta, double* const* P1, const double* PJ, int64_t N, const int* gate,
-                       hipStream_t s);
+                       double* delta, double* const* Pk, const double* PJ, int64_t N, const int* gate,
+                       hipStream_t s, int order);
 
 // First guess of mu1 for each of d directions from a converged P0 (N x N FP64):
 // with w_i = (P0 - P0^2)_ii, mu1_z = sum_i w_i (H1_z)_ii / sum_i w_i (the

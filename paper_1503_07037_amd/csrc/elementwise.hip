@@ -623,16 +623,17 @@ __global__ void k_newton(const double* tr, int rs, const double* par, double* mu
 // delta_z = Tr P1_z / Tr P_J, moves mu1_z by it, and updates the trace
 // record (Tr P1_z and Tr(H1_z P1_z)) to the corrected response.
 __global__ void k_lin_delta(double* t, int d, int J, int rs0, double* mu, double* shift, double c,
-                            double* delta, const int* gate) {
+                            double* delta, const int* gate, int off) {
   const int z = threadIdx.x;
   if (z >= d || (gate && !*gate)) return;
+  const int i = 1 + off + z;  // slot of the corrected order's trace and mu
   const double trj = t[rs0];
-  const double dl = trj != 0.0 ? t[1 + z] / trj : 0.0;
+  const double dl = trj != 0.0 ? t[i] / trj : 0.0;
   delta[z] = dl;
-  t[1 + z] -= dl * trj;
-  t[2 * J + 1 + z] -= dl * t[rs0 + 2 + z];
-  mu[1 + z] += dl;
-  shift[1 + z] = -c * mu[1 + z];
+  t[i] -= dl * trj;
+  t[2 * J + i] -= dl * t[rs0 + 2 + z];
+  mu[i] += dl;
+  shift[i] = -c * mu[i];
 }
 
 // w_i = (P0 - P0^2)_ii for one row per block (P0 symmetric, FP64, N x N).
@@ -938,9 +939,10 @@ template hipError_t fill_pattern<float>(float*, int64_t, uint32_t, uint16_t* con
 
 hipError_t lin_correct(double* t, int d, int J, int rs0, double* mu, double* shift, double c,
                        double* delta, double* const* P1, const double* PJ, int64_t N, const int* gate,
-                       hipStream_t s) {
-  if (d < 1 || d > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_lin_delta, dim3(1), dim3(64), 0, s, t, d, J, rs0, mu, shift, c, delta, gate);
+                       hipStream_t s, int order) {
+  if (d < 1 || d > 64 || order < 1 || order > 2) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_lin_delta, dim3(1), dim3(64), 0, s, t, d, J, rs0, mu, shift, c, delta, gate,
+                     (order - 1) * d);
   hipError_t e = hipGetLastError();
   for (int z = 0; z < d && e == hipSuccess; ++z) {
     hipLaunchKernelGGL(k_lin_axpy, dim3(ew_grid(N * N)), dim3(kT), 0, s, P1[z], PJ, N * N, delta + z,

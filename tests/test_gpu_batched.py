@@ -143,27 +143,35 @@ def test_batch64_fp32_full_workload(dm):
         assert e0 < 1e-6 and e1 < 1e-6 and e2 < 1e-6
 
 
-@pytest.mark.parametrize("d", [1, 3])
-def test_linear_and_joint_schedules_agree(dm, small_batch, d):
-    """Order 1, FP64: the device-side linear schedule (identity response as an extra direction,
-    exact Tr P1 = 0 correction) and Algorithm 1's joint Newton reach the oracle's fixed point."""
-    print(f"case batched schedules d={d}", flush=True)
+@pytest.mark.parametrize("d,order", [(1, 1), (3, 1), (3, 2)])
+def test_linear_and_joint_schedules_agree(dm, small_batch, d, order):
+    """FP64: the device-side linear schedule (identity response as an extra direction, exact
+    Tr P1 = 0 and Tr P2 = 0 corrections) and Algorithm 1's joint Newton reach the oracle's fixed
+    point at orders 1 and 2."""
+    print(f"case batched schedules d={d} order={order}", flush=True)
     nmax = max(s["h0"].shape[0] for s in small_batch)
     out = {}
     for sched in (0, 1):
         with dm.Context(nmax, dirs_max=d, prec="fp64", schedule=sched) as ctx:
-            P0, P1, _, mus, st = ctx.mu_newton_batched(
+            P0, P1, P2, mus, st = ctx.mu_newton_batched(
                 [T(s["h0"]) for s in small_batch], [[T(h) for h in s["h1"][:d]] for s in small_batch],
-                [s["beta"] for s in small_batch], [s["Ne"] for s in small_batch], n=25, order=1)
-        out[sched] = (P0, P1, mus)
-        print(f"  schedule {sched}: passes={st['newton_iters']} seconds={st['seconds']:.2f}")
+                [s["beta"] for s in small_batch], [s["Ne"] for s in small_batch], n=25, order=order)
+        out[sched] = (P0, P1, P2, mus)
+        print(f"  schedule {sched}: passes={st['newton_iters']} seconds={st['seconds']:.2f} "
+              f"flags={st['flags']}")
     for k, s in enumerate(small_batch):
         r = s["ref"]
         for sched in (0, 1):
-            P0, P1, mus = out[sched]
+            P0, P1, P2, mus = out[sched]
             e0 = np.abs(P0[k].cpu().numpy() - r["P0"]).max()
             e1 = max(np.abs(P1[k][z].cpu().numpy() - r["P1"][z]).max() / np.abs(r["P1"][z]).max()
                      for z in range(d))
-            assert e0 < 1e-10 and e1 < 1e-10, (k, sched, e0, e1)
+            e2 = 0.0
+            if order >= 2:
+                e2 = max(np.abs(P2[k][z].cpu().numpy() - r["P2"][z]).max() / np.abs(r["P2"][z]).max()
+                         for z in range(d))
+            assert e0 < 1e-10 and e1 < 1e-10 and e2 < 1e-10, (k, sched, e0, e1, e2)
             for z in range(d):
                 assert abs(mus[k][1 + z] - r["mu1"][z]) < 1e-9 * max(1.0, abs(r["mu1"][z]))
+                if order >= 2:
+                    assert abs(mus[k][1 + d + z] - r["mu2"][z]) < 1e-9 * max(1.0, abs(r["mu2"][z]))
