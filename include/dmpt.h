@@ -274,6 +274,52 @@ dmpt_status dmpt_backward(dmpt_ctx ctx, int64_t N, const double* H0, double beta
                           int n, const double* mu0, const double* Abar, double* G,
                           dmpt_stats* st);
 
+/* Statistics of the thresholded block-sparse path (dmpt_sparse_response). */
+typedef struct {
+  int newton_iters;                      /* order-0 Newton passes plus the order-1 / order-2 passes */
+  int block;                             /* block edge of the sparse form (32) */
+  double mu[1 + 2 * DMPT_MAX_DIRS];      /* mu0, mu1[d], mu2[d] of the returned P */
+  double trP[1 + 2 * DMPT_MAX_DIRS];     /* Tr P0, Tr P1[d], Tr P2[d] */
+  double tr_h1p1[DMPT_MAX_DIRS];         /* Tr(H1 P1) */
+  double tr_h1p2[DMPT_MAX_DIRS];         /* Tr(H1 P2) (order 2) */
+  double nnz_p0;                         /* elements of P0 with |x| >= count_thr */
+  double nnz_p1[DMPT_MAX_DIRS];          /* likewise for P1[d] */
+  double nnz_p2[DMPT_MAX_DIRS];          /* likewise for P2[d] */
+  double blocks_p0, blocks_p1[DMPT_MAX_DIRS], blocks_p2[DMPT_MAX_DIRS];  /* stored 32 x 32 blocks */
+  double blocks_max;                     /* most candidate blocks of any intermediate result */
+  double block_products;                 /* 32 x 32 block products formed (2 * 32^3 flop each) */
+  double seconds;                        /* wall time of the call */
+} dmpt_sparse_stats;
+
+/* Thresholded block-sparse canonical response (Sec. V.B, linear scaling):
+ * the recursion of Eq. Rec_F_2 and its perturbed forms to order 0, 1 or 2 in
+ * 32 x 32 block-sparse FP64 storage.  After every product or combination the
+ * blocks whose largest element is below tau times the largest element of the
+ * result are dropped (tau = 0: no truncation, the result equals the dense
+ * one up to rounding).  Each step's linear systems share T' = I + 4 D0^2 and
+ * are solved with its Newton-Schulz inverse (four steps from the minimax
+ * linear start), so every operation is a sparse product or combination; mu0
+ * by safeguarded Newton passes, then mu1 and mu2 by the linear schedule (one
+ * order-1 pass with the response J to H1 = I, one order-2 pass), as in
+ * dmpt_mu_newton.  Work and memory grow with the number of stored blocks,
+ * i.e. linearly in N for matrices whose significant elements lie within a
+ * fixed distance of the diagonal.
+ *   H0, H1[d]      N x N device FP64 inputs (dense, used through sym(.); no H2)
+ *   tau            relative truncation threshold (>= 0)
+ *   count_thr      elements of the returned P0, P1, P2 with |x| >= count_thr are
+ *                  counted into st (e.g. 1e-5, the threshold of Fig. Fig_Scaling)
+ *   blocks_per_row capacity of every sparse matrix: blocks_per_row * ceil(N / 32)
+ *                  blocks (0: all); a result that does not fit gives DMPT_ERR_NOMEM
+ *   mu_inout       host, 1 + order * d doubles, as for dmpt_mu_newton
+ *   P0, P1[d], P2[d]  dense N x N device FP64 outputs, each may be NULL (then
+ *                  only the statistics are produced)
+ * N may exceed the context's n_max (the dense workspace is not used); the
+ * sparse storage is allocated for the call and freed before it returns. */
+dmpt_status dmpt_sparse_response(dmpt_ctx ctx, int64_t N, const double* H0, int d, const double* const* H1,
+                                 double beta, double Ne, int n, int order, double tau, double count_thr,
+                                 int blocks_per_row, double* mu_inout, double* P0, double* const* P1,
+                                 double* const* P2, dmpt_sparse_stats* st);
+
 /* Device-time accounting of the matrix-product kernels (the MFMA engine of
  * the context's precision).  dmpt_profile(ctx, 1) resets the totals and
  * starts recording a pair of HIP events on the context stream around every

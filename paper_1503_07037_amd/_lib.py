@@ -75,6 +75,27 @@ class Stats(ctypes.Structure):
         return out
 
 
+class SparseStats(ctypes.Structure):
+    _fields_ = [
+        ("newton_iters", ctypes.c_int), ("block", ctypes.c_int),
+        ("mu", ctypes.c_double * (1 + 2 * MAX_DIRS)), ("trP", ctypes.c_double * (1 + 2 * MAX_DIRS)),
+        ("tr_h1p1", ctypes.c_double * MAX_DIRS), ("tr_h1p2", ctypes.c_double * MAX_DIRS),
+        ("nnz_p0", ctypes.c_double), ("nnz_p1", ctypes.c_double * MAX_DIRS),
+        ("nnz_p2", ctypes.c_double * MAX_DIRS), ("blocks_p0", ctypes.c_double),
+        ("blocks_p1", ctypes.c_double * MAX_DIRS), ("blocks_p2", ctypes.c_double * MAX_DIRS),
+        ("blocks_max", ctypes.c_double), ("block_products", ctypes.c_double), ("seconds", ctypes.c_double),
+    ]
+
+    def as_dict(self, d=0, order=0):
+        nmu = 1 + order * d
+        out = dict(newton_iters=self.newton_iters, block=self.block, mu=list(self.mu[:nmu]),
+                   trP=list(self.trP[:nmu]), nnz_p0=self.nnz_p0, blocks_p0=self.blocks_p0,
+                   blocks_max=self.blocks_max, block_products=self.block_products, seconds=self.seconds)
+        for name in ("tr_h1p1", "tr_h1p2", "nnz_p1", "nnz_p2", "blocks_p1", "blocks_p2"):
+            out[name] = list(getattr(self, name)[:d])
+        return out
+
+
 class ProfileData(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double),
                 ("mfma_flops", ctypes.c_double), ("useful_flops", ctypes.c_double),
@@ -87,7 +108,7 @@ EXPORTS = [
     "dmpt_default_options", "dmpt_init", "dmpt_finalize", "dmpt_last_error", "dmpt_set_options",
     "dmpt_fermi_recursion", "dmpt_response", "dmpt_mu_newton", "dmpt_mu_newton_batched",
     "dmpt_backward", "dmpt_profile", "dmpt_profile_get", "dmpt_bench_product", "dmpt_autotune",
-    "dmpt_congruence", "dmpt_fermi_recursion_noalloc",
+    "dmpt_congruence", "dmpt_fermi_recursion_noalloc", "dmpt_sparse_response",
 ]
 
 _lib = None
@@ -129,6 +150,8 @@ def load(path=None):
     lib.dmpt_autotune.argtypes = [P, I64, ctypes.POINTER(I)]
     lib.dmpt_congruence.argtypes = [P, I64, P, P, P, I, ctypes.POINTER(Stats)]
     lib.dmpt_fermi_recursion_noalloc.argtypes = [I64, P, D, D, I, P, P, P]
+    lib.dmpt_sparse_response.argtypes = [P, I64, P, I, PP, D, D, I, I, D, D, I, DP, P, PP, PP,
+                                         ctypes.POINTER(SparseStats)]
     for name in EXPORTS:
         if name not in ("dmpt_default_options", "dmpt_last_error"):
             getattr(lib, name).restype = ctypes.c_int

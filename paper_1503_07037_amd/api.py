@@ -339,6 +339,40 @@ class Context:
         jets = [list(mu_arr[s_ * J:(s_ + 1) * J]) for s_ in range(nsys)]
         return P0, P1, P2, jets, stats
 
+    def sparse_response(self, H0, H1=(), beta=1.0, Ne=1.0, n=20, order=0, tau=1e-8, count_thr=1e-5,
+                        blocks_per_row=0, mu=None, outputs=True, raise_on_error=True):
+        """Thresholded block-sparse canonical response (Sec. V.B; dmpt_sparse_response).
+
+        tau: relative truncation of every intermediate; count_thr: the element magnitude counted
+        into the statistics (nnz_p0, nnz_p1, nnz_p2).  With outputs=False only statistics are
+        produced.  Returns (P0, [P1], [P2], mu_jet, stats) (P's None without outputs).
+        """
+        N = H0.shape[0]
+        _check_mat(H0, N, "H0")
+        d = len(H1) if order >= 1 else 0
+        for i, h in enumerate(H1[:d]):
+            _check_mat(h, N, f"H1[{i}]")
+        nmu = 1 + order * d
+        m = [math.nan] * nmu
+        if mu is not None:
+            for i, v in enumerate(mu[:nmu]):
+                m[i] = float(v)
+        mu_arr = (ctypes.c_double * nmu)(*m)
+        P0 = self._empty(N) if outputs else None
+        P1 = [self._empty(N) for _ in range(d)] if (outputs and order >= 1) else []
+        P2 = [self._empty(N) for _ in range(d)] if (outputs and order >= 2) else []
+        s = L.SparseStats()
+        st = self.lib.dmpt_sparse_response(self.h, N, _ptr(H0), d, _ptr_array(list(H1[:d])) if d else None,
+                                           float(beta), float(Ne), int(n), int(order), float(tau),
+                                           float(count_thr), int(blocks_per_row), mu_arr, _ptr(P0),
+                                           _ptr_array(P1) if P1 else None, _ptr_array(P2) if P2 else None,
+                                           ctypes.byref(s))
+        stats = s.as_dict(d, order)
+        stats["status"] = st
+        if raise_on_error:
+            self._raise(st, stats)
+        return P0, P1, P2, list(mu_arr), stats
+
     def backward(self, H0, beta, Ne, n, Abar, mu0=None):
         """Adjoint G = d Tr(Abar P0)/d H0 of the canonical map.  Returns (G, stats)."""
         N = H0.shape[0]

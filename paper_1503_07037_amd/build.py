@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libdmpt.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["gemm.hip", "elementwise.hip", "dmpt_api.hip"]
+SOURCES = ["gemm.hip", "elementwise.hip", "sparse.hip", "dmpt_api.hip"]
 ARCH = os.environ.get("DMPT_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -1897,6 +1897,198 @@ dmpt_status linear_orders(Call& k, const PassIn& base, int64_t N, int order, dou
   return DMPT_OK;
 }
 
+// ---------------------------------------------------------------- thresholded block-sparse path
+// A block-sparse matrix (see sparse.hip) with its block count.
+struct BSMat {
+  BSView v;
+  int nslots = 0;
+};
+
+// Storage and scratch of one sparse call; every matrix holds up to cap blocks.
+struct Sparse {
+  dmpt_ctx c = nullptr;
+  hipStream_t s = nullptr;
+  int64_t N = 0;
+  int nb = 0;
+  int cap = 0;
+  double tau = 0.0;
+  uint32_t* bits = nullptr;     // nb bit rows
+  int* counts = nullptr;        // nb
+  int* keep = nullptr;          // cap
+  double* bmax = nullptr;       // max(cap, nb^2)
+  double* part = nullptr;       // 4 cap
+  double* nprods = nullptr;     // cap
+  double* scal = nullptr;       // 8
+  BSMat tmp;                    // candidate blocks of the current result
+  std::vector<void*> allocs;
+  double products = 0.0;
+  double blocks_max = 0.0;
+  ~Sparse() {
+    if (s) (void)hipStreamSynchronize(s);
+    for (void* p : allocs) dev_free(c, p);
+  }
+  void* alloc(size_t bytes) {
+    void* p = dev_alloc(c, bytes);
+    if (p) allocs.push_back(p);
+    return p;
+  }
+  bool make(BSMat& m) {
+    m.v.rows = (int*)alloc(sizeof(int) * (nb + 1));
+    m.v.cols = (int*)alloc(sizeof(int) * (size_t)cap);
+    m.v.ridx = (int*)alloc(sizeof(int) * (size_t)cap);
+    m.v.val = (double*)alloc(sizeof(double) * (size_t)cap * kSparseBlock * kSparseBlock);
+    m.nslots = 0;
+    if (!m.v.rows || !m.v.cols || !m.v.ridx || !m.v.val) return false;
+    return hipMemsetAsync(m.v.rows, 0, sizeof(int) * (nb + 1), s) == hipSuccess;
+  }
+};
+
+dmpt_status sp_read_int(Sparse& w, const int* dev, int* out) {
+  HIPCHK(w.c, hipMemcpyAsync(w.c->h_int, dev, sizeof(int), hipMemcpyDeviceToHost, w.s));
+  HIPCHK(w.c, hipStreamSynchronize(w.s));
+  *out = w.c->h_int[0];
+  return DMPT_OK;
+}
+
+dmpt_status sp_capacity(Sparse& w, int need) {
+  if (need > w.cap)
+    return fail(w.c, DMPT_ERR_NOMEM,
+                "sparse path: a result needs " + std::to_string(need) + " blocks, capacity " +
+                    std::to_string(w.cap) + " (raise blocks_per_row)");
+  return DMPT_OK;
+}
+
+// out = e, truncated (out must not be an operand of e).
+dmpt_status sp_eval(Sparse& w, const BSExpr& e0, BSMat& out) {
+  BSExpr e = e0;
+  e.n = w.N;
+  hipStream_t s = w.s;
+  HIPCHK(w.c, sparse_symbolic(e, w.nb, w.bits, w.counts, w.tmp.v.rows, s));
+  int cand = 0;
+  STCHK(sp_read_int(w, w.tmp.v.rows + w.nb, &cand));
+  STCHK(sp_capacity(w, cand));
+  w.blocks_max = std::max(w.blocks_max, (double)cand);
+  HIPCHK(w.c, sparse_fill(w.bits, w.nb, w.tmp.v.rows, w.tmp.v.cols, w.tmp.v.ridx, s));
+  HIPCHK(w.c, sparse_numeric(e, w.tmp.v, cand, w.tau, w.bmax, w.keep, w.nprods, w.scal, s));
+  HIPCHK(w.c, sparse_keep_rows(w.tmp.v.rows, w.keep, w.nb, w.counts, out.v.rows, s));
+  HIPCHK(w.c, sparse_compact(w.tmp.v, w.keep, w.nb, out.v, s));
+  HIPCHK(w.c, hipMemcpyAsync(w.c->h_int, out.v.rows + w.nb, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(w.c, hipMemcpyAsync(w.c->h_res + RES_MISC, w.scal, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(w.c, hipStreamSynchronize(s));
+  out.nslots = w.c->h_int[0];
+  w.products += w.c->h_res[RES_MISC];
+  return DMPT_OK;
+}
+
+// out = a sym(H) + shift I from a dense N x N input (H may be null), truncated.
+dmpt_status sp_from_dense(Sparse& w, const double* H, double a, double shift, BSMat& out) {
+  HIPCHK(w.c, sparse_dense_pattern(H, w.N, w.nb, a, shift, w.tau, w.bmax, w.scal + 2, w.bits, w.counts,
+                                   out.v.rows, w.s));
+  int nsl = 0;
+  STCHK(sp_read_int(w, out.v.rows + w.nb, &nsl));
+  STCHK(sp_capacity(w, nsl));
+  HIPCHK(w.c, sparse_fill(w.bits, w.nb, out.v.rows, out.v.cols, out.v.ridx, w.s));
+  HIPCHK(w.c, sparse_dense_values(H, w.N, a, shift, out.v, nsl, w.s));
+  out.nslots = nsl;
+  return DMPT_OK;
+}
+
+// Trace, sum of squares, count of |shift I - m| >= thr, sum of H .* m.
+dmpt_status sp_stats(Sparse& w, const BSMat& m, double shift, double thr, const double* H, double out[4]) {
+  HIPCHK(w.c, sparse_stats(m.v, m.nslots, w.N, shift, thr, H, w.part, w.scal + 4, w.s));
+  HIPCHK(w.c, hipMemcpyAsync(w.c->h_res + RES_MISC, w.scal + 4, 4 * sizeof(double), hipMemcpyDeviceToHost,
+                             w.s));
+  HIPCHK(w.c, hipStreamSynchronize(w.s));
+  for (int q = 0; q < 4; ++q) out[q] = w.c->h_res[RES_MISC + q];
+  return DMPT_OK;
+}
+
+BSExpr sp_prod(const BSMat& A, const BSMat& B, double alpha) {
+  BSExpr e;
+  e.nterm = 1;
+  e.A[0] = A.v;
+  e.B[0] = B.v;
+  e.alpha[0] = alpha;
+  return e;
+}
+void sp_term(BSExpr& e, const BSMat& A, const BSMat& B, double alpha) {
+  e.A[e.nterm] = A.v;
+  e.B[e.nterm] = B.v;
+  e.alpha[e.nterm] = alpha;
+  ++e.nterm;
+}
+void sp_add(BSExpr& e, const BSMat& C, double beta) {
+  e.C[e.nadd] = C.v;
+  e.beta[e.nadd] = beta;
+  ++e.nadd;
+}
+
+// The matrices of one sparse pass: D^(k) jets and their per-step scratch.
+struct SparseJets {
+  BSMat D0, S0, Z, M, Zn, Y0;
+  std::vector<BSMat> D1, S1, R, Y1;  // order-1 directions (+ J)
+  std::vector<BSMat> D2, T2, S2, Y2; // order-2 directions
+};
+
+// One pass of the recursion (orders 0..order) at a fixed mu jet with the
+// shared Newton-Schulz inverse Z of T' = I + 4 D0^2 per step:
+//   T' Y0 = 2 D0, T' Y1 = 2 D1 - 4 S1 Y0, T' Y2 = 2 D2 - 4 S1 Y1 - 4 S2 Y0,
+// each solved as Y = Z R (Z a polynomial in D0, so Y0 = 2 Z D0 as well).
+// d1 order-1 jets start from c (sym H1[z] - mu1[z] I) (H1[z] null: c (-mu1[z]) I),
+// d2 order-2 jets from -c mu2[z] I (no H2).
+dmpt_status sparse_pass(Sparse& w, SparseJets& J, const double* H0, int d1, const double* const* H1,
+                        const double* mu1, int d2, const double* mu2, double mu0, double beta, int n) {
+  const double cs = std::ldexp(beta, -(n + 2));
+  STCHK(sp_from_dense(w, H0, cs, -cs * mu0, J.D0));
+  for (int z = 0; z < d1; ++z) STCHK(sp_from_dense(w, H1[z], H1[z] ? cs : 0.0, -cs * mu1[z], J.D1[z]));
+  for (int z = 0; z < d2; ++z) STCHK(sp_from_dense(w, nullptr, 0.0, -cs * mu2[z], J.D2[z]));
+  for (int step = 0; step < n; ++step) {
+    STCHK(sp_eval(w, sp_prod(J.D0, J.D0, 1.0), J.S0));
+    {
+      // minimax linear start on [1, 2]: Z = (16 I - 32 S0) / 17
+      BSExpr e;
+      sp_add(e, J.S0, -32.0 / 17.0);
+      e.diag = 16.0 / 17.0;
+      STCHK(sp_eval(w, e, J.Z));
+    }
+    for (int it = 0; it < kNsIters; ++it) {
+      BSExpr m = sp_prod(J.S0, J.Z, 4.0);  // M = T' Z = Z + 4 S0 Z
+      sp_add(m, J.Z, 1.0);
+      STCHK(sp_eval(w, m, J.M));
+      BSExpr z = sp_prod(J.Z, J.M, -1.0);  // Z <- 2 Z - Z M
+      sp_add(z, J.Z, 2.0);
+      STCHK(sp_eval(w, z, J.Zn));
+      std::swap(J.Z, J.Zn);
+    }
+    STCHK(sp_eval(w, sp_prod(J.Z, J.D0, 2.0), J.Y0));
+    for (int z = 0; z < d1; ++z) {
+      BSExpr e = sp_prod(J.D1[z], J.D0, 1.0);  // S1 = D1 D0 + D0 D1
+      sp_term(e, J.D0, J.D1[z], 1.0);
+      STCHK(sp_eval(w, e, J.S1[z]));
+      BSExpr r = sp_prod(J.S1[z], J.Y0, -4.0);  // R = 2 D1 - 4 S1 Y0
+      sp_add(r, J.D1[z], 2.0);
+      STCHK(sp_eval(w, r, J.R[z]));
+      STCHK(sp_eval(w, sp_prod(J.Z, J.R[z], 1.0), J.Y1[z]));
+    }
+    for (int z = 0; z < d2; ++z) {
+      STCHK(sp_eval(w, sp_prod(J.D1[z], J.D1[z], 1.0), J.T2[z]));
+      BSExpr e = sp_prod(J.D2[z], J.D0, 1.0);  // S2 = D2 D0 + D0 D2 + D1 D1
+      sp_term(e, J.D0, J.D2[z], 1.0);
+      sp_add(e, J.T2[z], 1.0);
+      STCHK(sp_eval(w, e, J.S2[z]));
+      BSExpr r = sp_prod(J.S2[z], J.Y0, -4.0);  // R = 2 D2 - 4 S2 Y0 - 4 S1 Y1
+      sp_term(r, J.S1[z], J.Y1[z], -4.0);
+      sp_add(r, J.D2[z], 2.0);
+      STCHK(sp_eval(w, r, J.R[z]));
+      STCHK(sp_eval(w, sp_prod(J.Z, J.R[z], 1.0), J.Y2[z]));
+    }
+    std::swap(J.D0, J.Y0);
+    for (int z = 0; z < d1; ++z) std::swap(J.D1[z], J.Y1[z]);
+    for (int z = 0; z < d2; ++z) std::swap(J.D2[z], J.Y2[z]);
+  }
+  return DMPT_OK;
+}
+
 // ---------------------------------------------------------------- no-allocation path
 // dmpt_fermi_recursion_noalloc works in a file-scope device array instead of
 // a context's workspace.  Each device holds its own copy of the array; its
@@ -2353,6 +2545,209 @@ dmpt_status dmpt_fermi_recursion(dmpt_ctx c, int64_t N, const double* H0, double
   double m[1] = {mu};
   return dmpt_response(c, N, H0, 0, nullptr, nullptr, nullptr, beta, n, 0, m, P0, nullptr, nullptr,
                        nullptr, st);
+}
+
+dmpt_status dmpt_sparse_response(dmpt_ctx c, int64_t N, const double* H0, int d, const double* const* H1,
+                                 double beta, double Ne, int n, int order, double tau, double count_thr,
+                                 int blocks_per_row, double* mu_inout, double* P0, double* const* P1,
+                                 double* const* P2, dmpt_sparse_stats* st) {
+  if (!c) return DMPT_ERR_ARG;
+  if (N < 1 || N > (int64_t)kSparseBlock * 32768) return fail(c, DMPT_ERR_ARG, "sparse path: N must lie in [1, 2^20]");
+  if (!H0) return fail(c, DMPT_ERR_ARG, "H0 is NULL");
+  if (order < 0 || order > 2) return fail(c, DMPT_ERR_ARG, "sparse path: order must be 0, 1 or 2");
+  if (order >= 1 && (d < 1 || d > DMPT_MAX_DIRS || !H1)) return fail(c, DMPT_ERR_ARG, "d must lie in [1, 8] with H1");
+  for (int z = 0; order >= 1 && z < d; ++z)
+    if (!H1[z]) return fail(c, DMPT_ERR_ARG, "H1[i] is NULL");
+  if (!(beta > 0.0) || !std::isfinite(beta)) return fail(c, DMPT_ERR_ARG, "beta must be finite and > 0");
+  if (n < 1 || n > 62) return fail(c, DMPT_ERR_ARG, "recursion depth n must lie in [1, 62]");
+  if (!(Ne > 0.0 && Ne < (double)N)) return fail(c, DMPT_ERR_ARG, "Ne must lie in (0, N)");
+  if (!(tau >= 0.0) || !(tau < 1.0)) return fail(c, DMPT_ERR_ARG, "tau must lie in [0, 1)");
+  if (!(count_thr >= 0.0)) return fail(c, DMPT_ERR_ARG, "count_thr must be >= 0");
+  if (blocks_per_row < 0) return fail(c, DMPT_ERR_ARG, "blocks_per_row must be >= 0");
+  if (!mu_inout) return fail(c, DMPT_ERR_ARG, "mu_inout is NULL");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, DMPT_ERR_HIP, "hipSetDevice failed");
+  ENTER(c);
+  const auto t0 = std::chrono::steady_clock::now();
+  const int dd = order >= 1 ? d : 0;
+  // inputs: non-finite values, range of the recursion
+  PassIn pin{H0, dd, H1, nullptr, beta, n, order >= 1 ? 1 : 0, nullptr};
+  double glo, ghi;
+  STCHK(scan_inputs(c, N, pin, &glo, &ghi));
+  if (beta * (ghi - glo) >= std::ldexp(1.0, n + 1))
+    return fail(c, DMPT_ERR_RANGE, "beta * spread(H0) >= 2^(n+1): the recursion's start leaves [0, 1]");
+  double mu0 = mu_inout[0];
+  if (std::isnan(mu0)) {
+    HIPCHK(c, trace(H0, N, 0, N, 1, c->d_res + RES_MISC + 2, 1, nullptr, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->h_res + RES_MISC + 2, c->d_res + RES_MISC + 2, sizeof(double),
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    mu0 = c->h_res[RES_MISC + 2] / (double)N;
+  }
+  if (!std::isfinite(mu0)) return fail(c, DMPT_ERR_ARG, "mu0 guess must be finite");
+  const double lrange = 0.999 * std::ldexp(1.0, n + 1) / beta;
+  const double mu_lo = std::max(ghi - lrange, glo - 50.0 / beta);
+  const double mu_hi = std::min(glo + lrange, ghi + 50.0 / beta);
+  mu0 = std::min(std::max(mu0, mu_lo), mu_hi);
+  // storage
+  Sparse w;
+  w.c = c;
+  w.s = c->stream;
+  w.N = N;
+  w.nb = (int)((N + kSparseBlock - 1) / kSparseBlock);
+  w.cap = blocks_per_row > 0 ? (int)std::min<int64_t>((int64_t)blocks_per_row * w.nb, (int64_t)w.nb * w.nb)
+                             : (int)std::min<int64_t>((int64_t)w.nb * w.nb, INT32_MAX / 2);
+  w.tau = tau;
+  const int words = sparse_words(w.nb);
+  w.bits = (uint32_t*)w.alloc(sizeof(uint32_t) * (size_t)w.nb * words);
+  w.counts = (int*)w.alloc(sizeof(int) * (size_t)(w.nb + 1));
+  w.keep = (int*)w.alloc(sizeof(int) * (size_t)w.cap);
+  w.bmax = (double*)w.alloc(sizeof(double) * std::max<size_t>((size_t)w.cap, (size_t)w.nb * w.nb));
+  w.part = (double*)w.alloc(sizeof(double) * 4 * (size_t)w.cap);
+  w.nprods = (double*)w.alloc(sizeof(double) * (size_t)w.cap);
+  w.scal = (double*)w.alloc(sizeof(double) * 8);
+  const int d1max = dd + (order >= 1 ? 1 : 0);  // directions plus J
+  SparseJets J;
+  J.D1.resize(d1max); J.S1.resize(d1max); J.R.resize(d1max); J.Y1.resize(d1max);
+  J.D2.resize(order >= 2 ? dd : 0); J.T2.resize(J.D2.size()); J.S2.resize(J.D2.size()); J.Y2.resize(J.D2.size());
+  BSMat PJ, tmpJ;
+  bool ok = w.bits && w.counts && w.keep && w.bmax && w.part && w.nprods && w.scal && w.make(w.tmp) &&
+            w.make(J.D0) && w.make(J.S0) && w.make(J.Z) && w.make(J.M) && w.make(J.Zn) && w.make(J.Y0) &&
+            w.make(PJ) && w.make(tmpJ);
+  for (int z = 0; ok && z < d1max; ++z) ok = w.make(J.D1[z]) && w.make(J.S1[z]) && w.make(J.R[z]) && w.make(J.Y1[z]);
+  for (size_t z = 0; ok && z < J.D2.size(); ++z)
+    ok = w.make(J.D2[z]) && w.make(J.T2[z]) && w.make(J.S2[z]) && w.make(J.Y2[z]);
+  if (!ok) return fail(c, DMPT_ERR_NOMEM, "sparse path: storage allocation failed (lower blocks_per_row)");
+  const double tol = std::max(c->opt.tol_occ, tau);
+  double st4[4];
+  auto occupation = [&](double* trp0, double* frob) -> dmpt_status {
+    STCHK(sp_stats(w, J.D0, 0.5, 0.0, nullptr, st4));
+    *trp0 = 0.5 * (double)N - st4[0];                      // Tr (I/2 - D0)
+    *frob = 0.25 * (double)N - st4[0] + st4[1];            // ||I/2 - D0||_F^2
+    return DMPT_OK;
+  };
+  // ---- mu0: safeguarded Newton on order-0 passes
+  int passes = 0;
+  double br_lo = mu_lo, br_hi = mu_hi, prev = INFINITY, trp0 = 0.0, frob = 0.0;
+  bool settled = false;
+  std::vector<double> zero(DMPT_MAX_DIRS + 1, 0.0);
+  for (int it = 0; it < c->opt.max_newton; ++it) {
+    STCHK(sparse_pass(w, J, H0, 0, nullptr, nullptr, 0, nullptr, mu0, beta, n));
+    ++passes;
+    STCHK(occupation(&trp0, &frob));
+    if (!std::isfinite(trp0)) return fail(c, DMPT_ERR_NONFINITE, "sparse path: non-finite trace");
+    const double rel = std::fabs(trp0 - Ne) / (double)N;
+    if (c->log)
+      std::fprintf(stderr, "[dmpt] sparse pass %d mu0 %.15g TrP0-Ne %.3e blocks %d products %.3e\n", passes,
+                   mu0, trp0 - Ne, J.D0.nslots, w.products);
+    if (rel <= tol || (rel > 0.5 * prev && rel <= 1e3 * tol)) {
+      settled = true;
+      break;
+    }
+    prev = rel;
+    if (trp0 < Ne) br_lo = std::max(br_lo, mu0);
+    else br_hi = std::min(br_hi, mu0);
+    const double trpmu = beta * (trp0 - frob);
+    const double mn = mu0 + (Ne - trp0) / trpmu;
+    const bool occ_met = std::fabs(trp0 - Ne) <= tol * (double)N;
+    if (trpmu > 0.0 && (occ_met || (mn >= br_lo && mn <= br_hi))) mu0 = mn;
+    else mu0 = 0.5 * (br_lo + br_hi);
+  }
+  if (!settled) return fail(c, DMPT_ERR_NOCONV, "sparse path: mu0 did not converge within max_newton passes");
+  std::vector<double> mu1(DMPT_MAX_DIRS + 1, 0.0), mu2(DMPT_MAX_DIRS, 0.0);
+  double trJ = 0.0;
+  if (order >= 1) {
+    // order 1 with J (the response to H1 = I: start c I, i.e. mu = -1 and no H1)
+    std::vector<const double*> h1x(H1, H1 + dd);
+    h1x.push_back(nullptr);
+    std::vector<double> m1(dd + 1, 0.0);
+    m1[dd] = -1.0;
+    bool ok1 = false;
+    for (int a = 0; a < 4 && !ok1; ++a) {
+      STCHK(sparse_pass(w, J, H0, dd + 1, h1x.data(), m1.data(), 0, nullptr, mu0, beta, n));
+      ++passes;
+      STCHK(occupation(&trp0, &frob));
+      STCHK(sp_stats(w, J.D1[dd], 0.0, 0.0, nullptr, st4));
+      trJ = -st4[0];
+      if (!(std::fabs(trJ) > 0.0) || !std::isfinite(trJ))
+        return fail(c, DMPT_ERR_NOCONV, "sparse path: Tr J vanished");
+      const double rel = std::fabs(trp0 - Ne) / (double)N;
+      if (rel <= tol || rel <= 1e3 * tol) ok1 = rel <= tol || a > 0;
+      if (!ok1) mu0 = std::min(std::max(mu0 + (trp0 - Ne) / trJ, mu_lo), mu_hi);
+    }
+    if (!ok1) return fail(c, DMPT_ERR_NOCONV, "sparse path: mu0 did not settle in the order-1 pass");
+    // mu1 = Tr P1(0) / Tr J, P1 = P1(0) - mu1 J  (P = -D)
+    for (int z = 0; z < dd; ++z) {
+      STCHK(sp_stats(w, J.D1[z], 0.0, 0.0, nullptr, st4));
+      mu1[z] = -st4[0] / trJ;
+      BSExpr e;
+      sp_add(e, J.D1[z], 1.0);
+      sp_add(e, J.D1[dd], -mu1[z]);
+      STCHK(sp_eval(w, e, J.Y1[z]));
+      std::swap(J.D1[z], J.Y1[z]);
+    }
+    {
+      BSExpr e;  // keep P_J's D for the order-2 correction
+      sp_add(e, J.D1[dd], 1.0);
+      STCHK(sp_eval(w, e, PJ));
+    }
+  }
+  if (order >= 2) {
+    // order 2 at the settled mu1 (mu2 = 0), then P2 = P2(0) - mu2 J
+    STCHK(sparse_pass(w, J, H0, dd, H1, mu1.data(), dd, mu2.data(), mu0, beta, n));
+    ++passes;
+    STCHK(occupation(&trp0, &frob));
+    for (int z = 0; z < dd; ++z) {
+      STCHK(sp_stats(w, J.D2[z], 0.0, 0.0, nullptr, st4));
+      mu2[z] = -st4[0] / trJ;
+      BSExpr e;
+      sp_add(e, J.D2[z], 1.0);
+      sp_add(e, PJ, -mu2[z]);
+      STCHK(sp_eval(w, e, J.Y2[z]));
+      std::swap(J.D2[z], J.Y2[z]);
+    }
+  }
+  // outputs and statistics
+  if (P0) HIPCHK(c, sparse_to_dense(J.D0.v, w.nb, N, -1.0, 0.5, P0, c->stream));
+  for (int z = 0; z < dd; ++z) {
+    if (P1 && P1[z]) HIPCHK(c, sparse_to_dense(J.D1[z].v, w.nb, N, -1.0, 0.0, P1[z], c->stream));
+    if (order >= 2 && P2 && P2[z]) HIPCHK(c, sparse_to_dense(J.D2[z].v, w.nb, N, -1.0, 0.0, P2[z], c->stream));
+  }
+  mu_inout[0] = mu0;
+  for (int z = 0; z < dd; ++z) {
+    mu_inout[1 + z] = mu1[z];
+    if (order >= 2) mu_inout[1 + dd + z] = mu2[z];
+  }
+  if (st) {
+    std::memset(st, 0, sizeof(*st));
+    st->newton_iters = passes;
+    st->block = kSparseBlock;
+    st->mu[0] = mu0;
+    STCHK(sp_stats(w, J.D0, 0.5, count_thr, nullptr, st4));
+    st->trP[0] = 0.5 * (double)N - st4[0];
+    st->nnz_p0 = st4[2];
+    st->blocks_p0 = J.D0.nslots;
+    for (int z = 0; z < dd; ++z) {
+      st->mu[1 + z] = mu1[z];
+      STCHK(sp_stats(w, J.D1[z], 0.0, count_thr, H1[z], st4));
+      st->trP[1 + z] = -st4[0];
+      st->nnz_p1[z] = st4[2];
+      st->tr_h1p1[z] = -st4[3];
+      st->blocks_p1[z] = J.D1[z].nslots;
+      if (order >= 2) {
+        st->mu[1 + dd + z] = mu2[z];
+        STCHK(sp_stats(w, J.D2[z], 0.0, count_thr, H1[z], st4));
+        st->trP[1 + dd + z] = -st4[0];
+        st->nnz_p2[z] = st4[2];
+        st->tr_h1p2[z] = -st4[3];
+        st->blocks_p2[z] = J.D2[z].nslots;
+      }
+    }
+    st->blocks_max = w.blocks_max;
+    st->block_products = w.products;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (st) st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return DMPT_OK;
 }
 
 dmpt_status dmpt_fermi_recursion_noalloc(int64_t N, const double* H0, double beta, double mu, int n,

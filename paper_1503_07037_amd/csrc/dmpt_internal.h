@@ -215,4 +215,61 @@ hipError_t asym_max(const double* x, int64_t N, double* out_max, hipStream_t s);
 template <class T>
 hipError_t antisym_sq_partials(const T* x, int64_t ld, int64_t N, double* partials, hipStream_t s);
 
+// ---------------------------------------------------------------- block sparse (sparse.hip)
+constexpr int kSparseBlock = 32;  // block edge of the thresholded block-sparse form
+
+// Device view of a block-sparse matrix: rows[nb + 1] block-row pointers,
+// cols[s] / ridx[s] block column / row of slot s (ascending columns within a
+// row), val[s * 1024 ...] the 32 x 32 block, row major.
+struct BSView {
+  int* rows = nullptr;
+  int* cols = nullptr;
+  int* ridx = nullptr;
+  double* val = nullptr;
+};
+
+// C = alpha[0] A[0] B[0] + alpha[1] A[1] B[1] + beta[0] C[0] + beta[1] C[1] + diag I
+// (the first nterm products and nadd addends; I restricted to the n x n region).
+struct BSExpr {
+  int nterm = 0;
+  BSView A[2], B[2];
+  double alpha[2] = {1.0, 1.0};
+  int nadd = 0;
+  BSView C[2];
+  double beta[2] = {1.0, 1.0};
+  double diag = 0.0;
+  int64_t n = 0;
+};
+
+int sparse_words(int nb);
+// Candidate pattern of e: bit rows, block-row counts and their exclusive scan rows[0..nb].
+hipError_t sparse_symbolic(const BSExpr& e, int nb, uint32_t* bits, int* counts, int* rows, hipStream_t s);
+// cols / ridx of a pattern from its bit rows and scanned rows.
+hipError_t sparse_fill(const uint32_t* bits, int nb, const int* rows, int* cols, int* ridx, hipStream_t s);
+// Values of the candidate blocks of C (pattern given), their largest elements bmax, keep
+// flags (bmax >= tau max(bmax); tau = 0: all), the number of 32 x 32 block products formed
+// (per slot in nprods, summed into scal[0]) and the largest element in scal[1].
+hipError_t sparse_numeric(const BSExpr& e, const BSView& C, int nslots, double tau, double* bmax, int* keep,
+                          double* nprods, double* scal, hipStream_t s);
+// Kept-block counts per row and their scan into out_rows[0..nb].
+hipError_t sparse_keep_rows(const int* rows, const int* keep, int nb, int* counts, int* out_rows, hipStream_t s);
+// The kept blocks of src into dst (dst.rows from sparse_keep_rows).
+hipError_t sparse_compact(const BSView& src, const int* keep, int nb, const BSView& dst, hipStream_t s);
+// Pattern of a sym(H) + shift I (H N x N dense FP64, may be null): the blocks whose largest
+// element reaches tau times the largest element (tau = 0: non-zero blocks); bmax: nb^2
+// doubles of scratch, gmax: one.
+hipError_t sparse_dense_pattern(const double* H, int64_t N, int nb, double a, double shift, double tau,
+                                double* bmax, double* gmax, uint32_t* bits, int* counts, int* rows,
+                                hipStream_t s);
+hipError_t sparse_dense_values(const double* H, int64_t N, double a, double shift, const BSView& m, int nslots,
+                               hipStream_t s);
+// out (N x N dense FP64) = a sym(m) + shift I.
+hipError_t sparse_to_dense(const BSView& m, int nb, int64_t N, double a, double shift, double* out,
+                           hipStream_t s);
+// out[0] = trace over the n x n region, out[1] = sum of squares, out[2] = number of elements of
+// shift I - m with magnitude >= thr, out[3] = sum of H .* m (H: n x n dense FP64, or null: 0);
+// part: 4 nslots doubles of scratch.
+hipError_t sparse_stats(const BSView& m, int nslots, int64_t n, double shift, double thr, const double* H,
+                        double* part, double* out, hipStream_t s);
+
 }  // namespace dmpt

@@ -96,7 +96,7 @@ int main(void) {{ printf("{{\\"size\\":%zu,{body}}}", sizeof({struct}), {args});
         return json.loads(subprocess.run([exe], check=True, stdout=subprocess.PIPE, text=True).stdout)
 
 
-@pytest.mark.parametrize("struct,pyname", [("dmpt_stats", "Stats"), ("dmpt_options", "Options"),
+@pytest.mark.parametrize("struct,pyname", [("dmpt_stats", "Stats"), ("dmpt_options", "Options"), ("dmpt_sparse_stats", "SparseStats"),
                                            ("dmpt_profile_data", "ProfileData")])
 def test_struct_layouts_match_the_header(struct, pyname):
     """The binding's ctypes structures have the header's size and field offsets."""

@@ -10,6 +10,9 @@ version reproduces them bit for bit.
 Recipes (energies in eV, beta in 1/eV):
 
 * ``chain_1d``      periodic 1D chain, onsite U(-1, 1), hopping -1.
+* ``dimer_chain``   open 1D chain with alternating hoppings -1.2 / -0.8 (gapped at
+                    half filling), onsite U(-0.2, 0.2): the linear-scaling workload
+                    (stands in for the paper's hydrocarbon chains).
 * ``cubic_lattice`` periodic simple-cubic lattice, one s orbital per site,
                     onsite U(-w, w), 6 nearest neighbours t1, 12 face-diagonal
                     second neighbours t2; site index i = ix + Lx*(iy + Ly*iz).
@@ -22,7 +25,7 @@ centred on the cell (x_i = ix - Lx/2); for the 1D chain x_i = i - N/2.
 import math
 import numpy as np
 
-__all__ = ["chain_1d", "cubic_lattice", "banded", "lattice_dipoles", "grid_dipoles",
+__all__ = ["chain_1d", "dimer_chain", "cubic_lattice", "banded", "lattice_dipoles", "grid_dipoles",
            "batched_systems", "config", "CONFIGS", "overlap", "inverse_factor"]
 
 
@@ -35,6 +38,19 @@ def chain_1d(n, seed, onsite=1.0, hop=-1.0):
     j = (i + 1) % n
     np.add.at(h, (i, j), hop)
     np.add.at(h, (j, i), hop)
+    return h
+
+
+def dimer_chain(n, seed, t_strong=-1.2, t_weak=-0.8, onsite=0.2):
+    """Open 1D chain with alternating hoppings (a gapped, non-metallic chain: the gap at half
+    filling is 2 |t_strong - t_weak|) and onsite U(-onsite, onsite)."""
+    rng = np.random.default_rng(seed)
+    h = np.zeros((n, n))
+    h[np.arange(n), np.arange(n)] = rng.uniform(-onsite, onsite, n)
+    i = np.arange(n - 1)
+    t = np.where(i % 2 == 0, t_strong, t_weak)
+    h[i, i + 1] = t
+    h[i + 1, i] = t
     return h
 
 
