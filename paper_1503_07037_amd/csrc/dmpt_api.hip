@@ -96,6 +96,10 @@ struct dmpt_ctx_s {
   // the order-0 solution and the order-1 solutions of its d + 1 jets
   void* st = nullptr;
   size_t st_bytes = 0;
+  // square terms of the order-1 pass of every step (S0 and the d + 1 S1 jets),
+  // loaded by the order-2 pass instead of forming them again (optional)
+  void* ss = nullptr;
+  size_t ss_bytes = 0;
   int64_t tj_np = 0;
   int tj_valid = -1;
   Group U0;                      // order-0 CG unknown when the guess comes from tj
@@ -256,7 +260,7 @@ struct Call {
   int cg_iters = 0;              // iterations per solve when graph is set
   bool traj = false;             // single system: read / write the trajectory c->tj
   int jets = 1;                  // members per step in c->tj (1 + 2 d)
-  int chain = 0;                 // kSave01 | kLoad01 | kSave2 | kLoad2 (c->st, see st_ptr)
+  int chain = 0;                 // kSave01 | kLoad01 | kSave2 | kLoad2 (c->st, see st_ptr), kSaveS | kLoadS
   int cs = 0;                    // members per step in c->st
   int cj = 0;                    // member of the J jet's solution in c->st (1 + d)
   const double* cmu = nullptr;   // chain loads: mu1[d], mu2[d]; D^(k) = D^(k)(mu = 0) - mu D_J
@@ -265,6 +269,8 @@ struct Call {
 // Chain flags of a pass (linear schedule): save or load the order-0/1
 // solutions, save or load the order-2 solutions.
 constexpr int kSave01 = 1, kLoad01 = 2, kSave2 = 4, kLoad2 = 8;
+// ... and save or load the square terms S0, S1 of every step (c->ss, see ss_ptr)
+constexpr int kSaveS = 16, kLoadS = 32;
 
 // Member z of a group as an operand.
 BOp op(const Call& k, const Group& g, int z, bool batched) {
@@ -722,6 +728,47 @@ dmpt_status st_load(const Call& k, const Group& g, int z, int step, int j, doubl
   return DMPT_OK;
 }
 
+// Square-term store (c->ss, masters): per step, S0 (member 0) and the order-1
+// square terms S1 of the d directions and of J (members 1 .. d + 1).
+bool ss_fits(const Call& k, int step, int j) {
+  return step >= 0 && j >= 0 && j < k.cj + 1 &&
+         ((size_t)step * (k.cj + 1) + j + 1) * (size_t)k.nn * k.c->esize <= k.c->ss_bytes;
+}
+
+template <class T>
+T* ss_ptr(const Call& k, int step, int j) {
+  return (T*)k.c->ss + ((size_t)step * (k.cj + 1) + j) * (size_t)k.nn;
+}
+
+template <class T>
+dmpt_status ss_save(const Call& k, const Group& g, int z, int step, int j) {
+  if (!ss_fits(k, step, j) || z >= g.count) return fail(k.c, DMPT_ERR_ARG, "internal: square-term index");
+  uint16_t* none[3] = {nullptr, nullptr, nullptr};
+  HIPCHK(k.c, (convert<T, T>((const T*)mptr(k, g, z), 0, ss_ptr<T>(k, step, j), 0, k.nn, 1, none, 0, 0,
+                             k.c->stream)));
+  return DMPT_OK;
+}
+
+// Member z of a group (with planes) = stored (step, j) - a * stored (step, jb).
+template <class T>
+dmpt_status ss_load(const Call& k, const Group& g, int z, int step, int j, double a, int jb) {
+  if (!ss_fits(k, step, j) || (a != 0.0 && !ss_fits(k, step, jb)) || z >= g.count)
+    return fail(k.c, DMPT_ERR_ARG, "internal: square-term index");
+  uint16_t* pl[3];
+  planes_of(k, g, z, pl);
+  uint16_t* none[3] = {nullptr, nullptr, nullptr};
+  T* dst = (T*)mptr(k, g, z);
+  if (a == 0.0) {
+    HIPCHK(k.c, (convert<T, T>(ss_ptr<T>(k, step, j), 0, dst, 0, k.nn, 1, pl, 0, g.pl[0] ? k.np : 0,
+                               k.c->stream)));
+  } else {
+    HIPCHK(k.c, (convert<T, T>(ss_ptr<T>(k, step, j), 0, dst, 0, k.nn, 1, none, 0, 0, k.c->stream)));
+    HIPCHK(k.c, axpby<T>(ss_ptr<T>(k, step, jb), 0, dst, 0, k.nn, 1, -a, 1.0, pl, 0, g.pl[0] ? k.np : 0,
+                         k.c->stream));
+  }
+  return DMPT_OK;
+}
+
 // Order 0 of one recursion step: T' Y0 = 2 D0 with S0 = D0^2 already formed;
 // the previous iterate D0 is the initial guess and D0 is overwritten by the
 // symmetrised solution.
@@ -930,10 +977,15 @@ dmpt_status recursion_step(const Call& k, int order, int d, int step) {
   dmpt_ctx c = k.c;
   const WS* w = k.w;
   const int md = k.m * d;
-  STCHK(square0<T>(k));
+  if (k.chain & kLoadS) STCHK(ss_load<T>(k, w->S0, 0, step, 0, 0.0, 0));
+  else STCHK(square0<T>(k));
+  if (k.chain & kSaveS) STCHK(ss_save<T>(k, w->S0, 0, step, 0));
   const bool ns = c->opt.solver == DMPT_SOLVER_NS && k.m == 1 && !k.graph;
   if (ns) STCHK(ns_inverse<T>(k));
-  if (order >= 1) {
+  if (order >= 1 && (k.chain & kLoadS)) {
+    // the order-1 pass stored S1 at mu1 = 0; S1 is linear in mu1: S1 = S1(0) - mu1 S1_J
+    for (int z = 0; z < md; ++z) STCHK(ss_load<T>(k, w->S1, z, step, 1 + z, k.cmu[z], k.cj));
+  } else if (order >= 1) {
     // Q = D1 D0 -> S1 = Q + Q^T
     G g;
     g.X = op(k, w->D1, 0, true);
@@ -945,6 +997,8 @@ dmpt_status recursion_step(const Call& k, int order, int d, int step) {
     g.active = w->mask1;
     STCHK(run_gemm(k, g));
     STCHK(sym_to<T>(k, w->Q, w->S1, md, true));
+    if (k.chain & kSaveS)
+      for (int z = 0; z < md; ++z) STCHK(ss_save<T>(k, w->S1, z, step, 1 + z));
   }
   if (order >= 2) {
     // Q = D2 D0 -> S2 = Q + Q^T; S2 += D1 D1
@@ -1769,6 +1823,24 @@ bool ensure_chain(dmpt_ctx c, int n, int jets1, int64_t Np) {
   return true;
 }
 
+// Square-term store for n steps of `members` masters of Np x Np; false when
+// the memory is not there (the order-2 pass then forms S0 and S1 again).
+bool ensure_squares(dmpt_ctx c, int n, int members, int64_t Np) {
+  const size_t need = (size_t)n * members * (size_t)Np * Np * c->esize;
+  if (c->ss && c->ss_bytes >= need) return true;
+  if (c->ss) {
+    (void)hipStreamSynchronize(c->stream);
+    dev_free(c, c->ss);
+    c->ss = nullptr;
+    c->ss_bytes = 0;
+  }
+  void* p = dev_alloc(c, need);
+  if (!p) return false;
+  c->ss = p;
+  c->ss_bytes = need;
+  return true;
+}
+
 // Occupation error of Algorithm 1 (*occ_err, absolute) and its normalised
 // form (*rel): max(|Tr P0 - Ne| / N, max_k |Tr P^(k)| / sum_i |P^(k)_ii|).
 void occupation_error(const double* res, int d, int order, double Ne, int64_t N, double* occ_err,
@@ -1821,13 +1893,15 @@ dmpt_status linear_orders(Call& k, const PassIn& base, int64_t N, int order, dou
   // chain store: order 0, order 1 (d + J), order 2 (d, when order 3 follows)
   const int cs = 2 + d + (order >= 3 ? d : 0);
   const bool keep = order >= 2 && c->opt.schedule == 1 && ensure_chain(c, base.n, cs, k.Np);
+  // and the square terms S0, S1 (d directions and J) for the order-2 pass
+  const bool keep_s = keep && ensure_squares(c, base.n, 2 + d, k.Np);
   k.cs = cs;
   k.cj = 1 + d;
   double trJ = 0.0, prev = INFINITY;
   constexpr int kMaxPasses = 4;
   for (int a = 0; a < kMaxPasses; ++a) {
     m1[0] = mu[0];
-    k.chain = keep ? kSave01 : 0;
+    k.chain = keep ? (kSave01 | (keep_s ? kSaveS : 0)) : 0;
     STCHK(pass_dispatch(k, in1, P0, p1x.data(), nullptr));
     k.chain = 0;
     *passes += 1;
@@ -1855,7 +1929,7 @@ dmpt_status linear_orders(Call& k, const PassIn& base, int64_t N, int order, dou
     std::vector<double> m2(1 + 3 * DMPT_MAX_DIRS, 0.0);
     for (int i = 0; i <= d; ++i) m2[i] = mu[i];
     PassIn in2{base.H0, d, base.H1, base.H2, base.beta, base.n, 2, m2.data()};
-    k.chain = keep ? (kLoad01 | (order >= 3 ? kSave2 : 0)) : 0;
+    k.chain = keep ? (kLoad01 | (keep_s ? kLoadS : 0) | (order >= 3 ? kSave2 : 0)) : 0;
     k.cmu = mu + 1;
     STCHK(pass_dispatch(k, in2, P0, P1, P2));
     k.chain = 0;
@@ -2513,6 +2587,7 @@ dmpt_status dmpt_finalize(dmpt_ctx c) {
   if (c->h_int) (void)hipHostFree(c->h_int);
   if (c->tj) dev_free(c, c->tj);
   if (c->st) dev_free(c, c->st);
+  if (c->ss) dev_free(c, c->ss);
   if (c->ev_in) (void)hipEventDestroy(c->ev_in);
   if (c->ev_out) (void)hipEventDestroy(c->ev_out);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
