@@ -115,6 +115,9 @@ typedef struct {
   int acc64;            /* 6-product split-BF16 products: 1 = each 32-wide slice of k is summed in FP32
                            and the slices in FP64 (128 x 128 tiles; the FP32 rounding then no longer
                            grows with N), 0 = one FP32 accumulator over all of k (256 x 256 tiles) */
+  int autotune;         /* 1: before the first products of a padded size, time every product-kernel
+                           variant of the context's engines at that size and keep the fastest
+                           (dmpt_autotune); the batched solve tunes every bucket size */
 } dmpt_options;
 
 #define DMPT_MAX_DIRS 8
@@ -362,21 +365,42 @@ dmpt_status dmpt_profile_get(dmpt_ctx ctx, dmpt_profile_data* out);
 dmpt_status dmpt_congruence(dmpt_ctx ctx, int64_t N, const double* Z, const double* A, double* B,
                             int mode, dmpt_stats* st);
 
+/* Product-kernel variants (per engine; 0 is the default):
+ *   DMPT_FP64    0: 8-deep k stages, 8 waves   1: 16-deep, 8 waves   2: 8-deep, 4 waves
+ *   DMPT_FP32    0: 32-deep k stages, 8 waves  1: 16-deep, 8 waves   2: 32-deep, 4 waves
+ *   DMPT_BF16X3, DMPT_BF16X6 (options.acc64 = 0)
+ *                0: 256 x 256 output tiles where the padded size allows   1: 128 x 128 tiles
+ *   DMPT_BF16X6 with options.acc64 = 1: 0 only (128 x 128 tiles, FP64 slice sums)
+ * Every variant computes the same products; they differ in speed. */
+
 /* Time the matrix-product kernel alone: `reps` products C = X Y^T of size N
  * (N <= n_max; X, Y, C are workspace matrices filled with a fixed pattern)
- * in precision `prec` with output tile edge `tile` (0: the library's
- * choice, else 128 or 256; the 6-product engine with options.acc64 always
- * uses 128).  *ms: mean device time per product (HIP events
- * on the context stream); *tflops: matrix-core TFLOP/s (every split product
- * counted).  prec must not need more workspace than the context holds. */
-dmpt_status dmpt_bench_product(dmpt_ctx ctx, int64_t N, dmpt_prec prec, int tile, int reps,
+ * in precision `prec` with kernel variant `variant`.  *ms: mean device time
+ * per product (HIP events on the context stream); *tflops: matrix-core
+ * TFLOP/s (every split product counted).  prec must not need more workspace
+ * than the context holds. */
+dmpt_status dmpt_bench_product(dmpt_ctx ctx, int64_t N, dmpt_prec prec, int variant, int reps,
                                double* ms, double* tflops);
 
-/* Product-tile autotuner: times every tile edge available for the
- * context's precision at size N and keeps the fastest for all later
- * products of that padded size on this context.  *tile (may be NULL)
- * receives the choice. */
-dmpt_status dmpt_autotune(dmpt_ctx ctx, int64_t N, int* tile);
+/* Product-kernel autotuner: times every variant of the context's engines
+ * (its precision's, and the 6-product refinement's when enabled) at the
+ * padded size of N and keeps the fastest for all later products of that
+ * padded size on this context.  When the environment variable
+ * DMPT_TUNE_CACHE names a file, choices are read from it (per GPU
+ * architecture, engine and padded size) and new ones appended, so later
+ * processes skip the timing.  *variant (may be NULL) receives the choice for
+ * the context's precision. */
+dmpt_status dmpt_autotune(dmpt_ctx ctx, int64_t N, int* variant);
+
+/* Pin the product-kernel variant of precision prec's engine for the padded
+ * size of N on this context (as the autotuner would). */
+dmpt_status dmpt_set_variant(dmpt_ctx ctx, int64_t N, dmpt_prec prec, int variant);
+
+/* The variant later products of precision prec at the padded size of N use:
+ * *variant, *tuned (may be NULL) = 1 when it was tuned or pinned, 0 for the
+ * default, and its name in name[0 .. name_len) (may be NULL). */
+dmpt_status dmpt_get_variant(dmpt_ctx ctx, int64_t N, dmpt_prec prec, int* variant, int* tuned,
+                             char* name, int name_len);
 
 #ifdef __cplusplus
 }

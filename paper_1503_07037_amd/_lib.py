@@ -38,6 +38,7 @@ class Options(ctypes.Structure):
         ("max_newton", ctypes.c_int), ("max_cg", ctypes.c_int), ("refine", ctypes.c_int),
         ("ckpt_every", ctypes.c_int), ("check", ctypes.c_int), ("staged", ctypes.c_int),
         ("warm_traj", ctypes.c_int), ("schedule", ctypes.c_int), ("acc64", ctypes.c_int),
+        ("autotune", ctypes.c_int),
     ]
 
 
@@ -108,7 +109,8 @@ EXPORTS = [
     "dmpt_default_options", "dmpt_init", "dmpt_finalize", "dmpt_last_error", "dmpt_set_options",
     "dmpt_fermi_recursion", "dmpt_response", "dmpt_mu_newton", "dmpt_mu_newton_batched",
     "dmpt_backward", "dmpt_profile", "dmpt_profile_get", "dmpt_bench_product", "dmpt_autotune",
-    "dmpt_congruence", "dmpt_fermi_recursion_noalloc", "dmpt_sparse_response",
+    "dmpt_congruence", "dmpt_fermi_recursion_noalloc", "dmpt_sparse_response", "dmpt_set_variant",
+    "dmpt_get_variant",
 ]
 
 _lib = None
@@ -148,6 +150,8 @@ def load(path=None):
     lib.dmpt_profile_get.argtypes = [P, ctypes.POINTER(ProfileData)]
     lib.dmpt_bench_product.argtypes = [P, I64, I, I, I, DP, DP]
     lib.dmpt_autotune.argtypes = [P, I64, ctypes.POINTER(I)]
+    lib.dmpt_set_variant.argtypes = [P, I64, I, I]
+    lib.dmpt_get_variant.argtypes = [P, I64, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.c_char_p, I]
     lib.dmpt_congruence.argtypes = [P, I64, P, P, P, I, ctypes.POINTER(Stats)]
     lib.dmpt_fermi_recursion_noalloc.argtypes = [I64, P, D, D, I, P, P, P]
     lib.dmpt_sparse_response.argtypes = [P, I64, P, I, PP, D, D, I, I, D, D, I, DP, P, PP, PP,

@@ -49,7 +49,7 @@ def _torch():
 
 def options(prec="fp64", solver="cg", guess="prev", tol_occ=0.0, tol_cg=0.0, max_newton=50,
             max_cg=60, refine=0, ckpt_every=5, check=0, staged=1, warm_traj=1, schedule=1,
-            acc64=1):
+            acc64=1, autotune=0):
     """Build an options struct; 0 tolerances select the precision's defaults."""
     lib = L.load()
     o = L.Options()
@@ -63,6 +63,7 @@ def options(prec="fp64", solver="cg", guess="prev", tol_occ=0.0, tol_cg=0.0, max
     o.warm_traj = int(warm_traj)
     o.schedule = int(schedule)
     o.acc64 = int(acc64)
+    o.autotune = int(autotune)
     return o
 
 
@@ -156,19 +157,33 @@ class Context:
                                             useful_flops=d.eng_useful_flops[i])
                          for i in range(4)})
 
-    def bench_product(self, N, prec=None, tile=0, reps=10):
-        """Mean device ms and TFLOP/s of the product kernel alone at size N."""
+    def bench_product(self, N, prec=None, variant=0, reps=10):
+        """Mean device ms and TFLOP/s of the product kernel (a variant) alone at size N."""
         p = self.opts.prec if prec is None else L.PREC[prec]
         ms, tf = ctypes.c_double(), ctypes.c_double()
-        self._raise(self.lib.dmpt_bench_product(self.h, int(N), int(p), int(tile), int(reps),
+        self._raise(self.lib.dmpt_bench_product(self.h, int(N), int(p), int(variant), int(reps),
                                                 ctypes.byref(ms), ctypes.byref(tf)))
         return ms.value, tf.value
 
     def autotune(self, N):
-        """Pick the fastest product tile for size N (kept for later calls)."""
+        """Pick the fastest product-kernel variant for size N (kept for later calls)."""
         t = ctypes.c_int()
         self._raise(self.lib.dmpt_autotune(self.h, int(N), ctypes.byref(t)))
         return t.value
+
+    def set_variant(self, N, variant, prec=None):
+        """Pin a product-kernel variant for the padded size of N."""
+        p = self.opts.prec if prec is None else L.PREC[prec]
+        self._raise(self.lib.dmpt_set_variant(self.h, int(N), int(p), int(variant)))
+
+    def get_variant(self, N, prec=None):
+        """(variant, tuned, name) the products at the padded size of N use."""
+        p = self.opts.prec if prec is None else L.PREC[prec]
+        v, t = ctypes.c_int(), ctypes.c_int()
+        buf = ctypes.create_string_buffer(96)
+        self._raise(self.lib.dmpt_get_variant(self.h, int(N), int(p), ctypes.byref(v), ctypes.byref(t),
+                                              buf, 96))
+        return v.value, bool(t.value), buf.value.decode()
 
     # ------------------------------------------------------------------ calls
     def fermi_recursion(self, H0, beta, mu, n, out=None):

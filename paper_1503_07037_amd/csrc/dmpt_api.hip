@@ -84,10 +84,15 @@ struct dmpt_ctx_s {
   // every device allocation of the context (base, bytes): launches are
   // checked against it on the host before they are queued
   std::vector<std::pair<const char*, size_t>> regions;
-  int tile_pref = 0;             // product tile edge: 0 = largest available
   double* d_tally = nullptr;     // [executed MFMA flops, useful flops] of graph-replayed products
   bool log = false;              // DMPT_LOG set: one line per Newton pass on stderr
-  std::vector<std::pair<int64_t, int>> tuned;  // autotuned tile edge per padded size
+  // product-kernel variant per (engine, padded size): chosen by the autotuner or pinned
+  struct Tuned {
+    int eng;
+    int64_t Np;
+    int variant;
+  };
+  std::vector<Tuned> tuned;
   // iterates of the previous Newton pass (FP32 copies, warm starts):
   // [step][jet member] of tj_np^2 each; tj_valid = highest order stored
   float* tj = nullptr;
@@ -197,6 +202,8 @@ struct CallScope {
   CallScope scope_{};          \
   STCHK(enter_call(ctx));      \
   scope_.c = (ctx)
+
+dmpt_status autotune_if_asked(dmpt_ctx c, int64_t N);
 
 Engine engine_of(dmpt_prec p) {
   switch (p) {
@@ -373,15 +380,16 @@ dmpt_status prof_resolve(dmpt_ctx c) {
   return DMPT_OK;
 }
 
-// Output tile edge of the product kernel for an engine and size: the FP64
-// slice-accumulating 6-product kernel has 128-wide tiles only; otherwise the
-// autotuned choice for Np, else the context's preference.
-int tile_for(dmpt_ctx c, Engine eng, int64_t Np) {
-  if (eng == Engine::BF16S3 && c->opt.acc64) return 128;
+// Product-kernel variant for an engine and padded size: the autotuned (or
+// pinned) one, else the default.
+int variant_for(dmpt_ctx c, Engine eng, int64_t Np) {
+  const int acc64 = eng == Engine::BF16S3 && c->opt.acc64;
   for (auto& t : c->tuned)
-    if (t.first == Np) return t.second;
-  return c->tile_pref;
+    if (t.eng == (int)eng && t.Np == Np && t.variant < gemm_variants(eng, acc64)) return t.variant;
+  return 0;
 }
+
+int acc64_of(dmpt_ctx c, Engine eng) { return eng == Engine::BF16S3 && c->opt.acc64 ? 1 : 0; }
 
 dmpt_status run_gemm(const Call& k, const G& g) {
   GemmArgs a{};
@@ -399,8 +407,8 @@ dmpt_status run_gemm(const Call& k, const G& g) {
   a.W = g.W; a.sW = g.sW;
   a.partials = k.c->d_part;
   a.active = g.active;
-  a.tile = tile_for(k.c, k.eng, k.Np);
-  a.acc64 = k.eng == Engine::BF16S3 && k.c->opt.acc64;
+  a.variant = variant_for(k.c, k.eng, k.Np);
+  a.acc64 = acc64_of(k.c, k.eng);
   // every member the launch touches must lie inside a workspace allocation
   {
     dmpt_ctx c = k.c;
@@ -419,7 +427,7 @@ dmpt_status run_gemm(const Call& k, const G& g) {
     if (ok && a.C1) ok = reg_ok(c, a.C1, span(a.sC1, 1) * es);
     if (ok && a.C2) ok = reg_ok(c, a.C2, span(a.sC2, 1) * es);
     if (ok && a.W) ok = reg_ok(c, a.W, span(a.sW, 1) * es) &&
-                        (size_t)b * gemm_tiles(k.eng, k.Np, a.tile) <= c->part_count;
+                        (size_t)b * gemm_tiles(k.eng, k.Np, a.variant, a.acc64) <= c->part_count;
     if (ok && b > 1) ok = a.sC != 0;
     if (!ok) return fail(c, DMPT_ERR_ARG, "internal: a product would leave its workspace");
   }
@@ -464,7 +472,7 @@ dmpt_status run_gemm(const Call& k, const G& g) {
 
 // Sum the GEMM per-tile partials into out[z*ostride + oidx].
 dmpt_status sum_gemm_partials(const Call& k, int batch, double* out, int ostride, int oidx) {
-  HIPCHK(k.c, sum_partials(k.c->d_part, gemm_tiles(k.eng, k.Np, tile_for(k.c, k.eng, k.Np)), batch, out,
+  HIPCHK(k.c, sum_partials(k.c->d_part, gemm_tiles(k.eng, k.Np, variant_for(k.c, k.eng, k.Np), acc64_of(k.c, k.eng)), batch, out,
                            ostride, oidx, k.c->stream));
   return DMPT_OK;
 }
@@ -2264,6 +2272,7 @@ void dmpt_default_options(dmpt_options* o) {
   o->warm_traj = 1;
   o->schedule = 1;
   o->acc64 = 1;
+  o->autotune = 0;
 }
 
 static dmpt_status normalise_options(dmpt_ctx c, const dmpt_options* in, dmpt_options* out) {
@@ -2276,6 +2285,7 @@ static dmpt_status normalise_options(dmpt_ctx c, const dmpt_options* in, dmpt_op
     return fail(c, DMPT_ERR_ARG, "unknown initial guess");
   if (o.schedule < 0 || o.schedule > 2) return fail(c, DMPT_ERR_ARG, "schedule must be 0, 1 or 2");
   if (o.acc64 != 0 && o.acc64 != 1) return fail(c, DMPT_ERR_ARG, "acc64 must be 0 or 1");
+  if (o.autotune != 0 && o.autotune != 1) return fail(c, DMPT_ERR_ARG, "autotune must be 0 or 1");
   if (o.tol_occ <= 0) o.tol_occ = default_tol_occ(o.prec, o.refine);
   if (o.tol_cg <= 0) o.tol_cg = default_tol_cg(o.prec, o.refine);
   if (o.max_newton <= 0) o.max_newton = 50;
@@ -2487,13 +2497,15 @@ dmpt_status dmpt_congruence(dmpt_ctx c, int64_t N, const double* Z, const double
   return DMPT_OK;
 }
 
-dmpt_status dmpt_bench_product(dmpt_ctx c, int64_t N, dmpt_prec prec, int tile, int reps, double* ms,
+dmpt_status dmpt_bench_product(dmpt_ctx c, int64_t N, dmpt_prec prec, int variant, int reps, double* ms,
                                double* tflops) {
   if (!c || !ms) return DMPT_ERR_ARG;
   if (N < 1 || N > c->n_max) return fail(c, DMPT_ERR_ARG, "N must lie in [1, n_max]");
   if (reps < 1 || reps > 100000) return fail(c, DMPT_ERR_ARG, "reps must lie in [1, 100000]");
-  if (tile != 0 && tile != 128 && tile != 256) return fail(c, DMPT_ERR_ARG, "tile must be 0, 128 or 256");
   if (prec < DMPT_FP64 || prec > DMPT_BF16X6) return fail(c, DMPT_ERR_ARG, "unknown precision");
+  const Engine eng = engine_of(prec);
+  if (variant < 0 || variant >= gemm_variants(eng, acc64_of(c, eng)))
+    return fail(c, DMPT_ERR_ARG, "no such kernel variant for this precision");
   dmpt_options o = c->opt;
   o.prec = prec;
   o.refine = 0;
@@ -2502,7 +2514,7 @@ dmpt_status dmpt_bench_product(dmpt_ctx c, int64_t N, dmpt_prec prec, int tile, 
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, DMPT_ERR_HIP, "hipSetDevice failed");
   ENTER(c);
   Call k = make_call(c, N, false);
-  k.eng = engine_of(prec);
+  k.eng = eng;
   k.np = engine_planes(k.eng);
   hipStream_t s = c->stream;
   uint16_t* px[3];
@@ -2520,8 +2532,8 @@ dmpt_status dmpt_bench_product(dmpt_ctx c, int64_t N, dmpt_prec prec, int tile, 
   a.C = mptr(k, c->ws.R, 0);
   a.alpha = 1.0;
   a.partials = c->d_part;
-  a.acc64 = k.eng == Engine::BF16S3 && c->opt.acc64;
-  a.tile = a.acc64 ? 128 : tile;
+  a.acc64 = acc64_of(c, k.eng);
+  a.variant = variant;
   hipEvent_t e0, e1;
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
@@ -2540,31 +2552,150 @@ dmpt_status dmpt_bench_product(dmpt_ctx c, int64_t N, dmpt_prec prec, int tile, 
   return DMPT_OK;
 }
 
-dmpt_status dmpt_autotune(dmpt_ctx c, int64_t N, int* tile) {
+}  // extern "C"
+
+namespace {
+
+void set_variant(dmpt_ctx c, Engine eng, int64_t Np, int v) {
+  for (auto& t : c->tuned)
+    if (t.eng == (int)eng && t.Np == Np) {
+      t.variant = v;
+      return;
+    }
+  c->tuned.push_back({(int)eng, Np, v});
+}
+
+bool is_tuned(dmpt_ctx c, Engine eng, int64_t Np) {
+  for (auto& t : c->tuned)
+    if (t.eng == (int)eng && t.Np == Np) return true;
+  return false;
+}
+
+dmpt_prec prec_of(Engine e) {
+  switch (e) {
+    case Engine::F64: return DMPT_FP64;
+    case Engine::F32: return DMPT_FP32;
+    case Engine::BF16S2: return DMPT_BF16X3;
+    case Engine::BF16S3: return DMPT_BF16X6;
+  }
+  return DMPT_FP64;
+}
+
+// Variant from the tuning cache file (DMPT_TUNE_CACHE: lines "arch engine Np acc64 variant ms"),
+// or -1.
+int cache_lookup(const char* path, const std::string& arch, Engine eng, int64_t Np, int acc64) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return -1;
+  char a[128];
+  int e = 0, acc = 0, v = -1, found = -1;
+  long long np = 0;
+  double ms = 0.0;
+  while (std::fscanf(f, "%127s %d %lld %d %d %lf", a, &e, &np, &acc, &v, &ms) == 6)
+    if (arch == a && e == (int)eng && np == Np && acc == acc64) found = v;
+  std::fclose(f);
+  return found;
+}
+
+void cache_store(const char* path, const std::string& arch, Engine eng, int64_t Np, int acc64, int v,
+                 double ms) {
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s %d %lld %d %d %.6f\n", arch.c_str(), (int)eng, (long long)Np, acc64, v, ms);
+  std::fclose(f);
+}
+
+// Time every variant of one engine at padded size Np (a few products each) and
+// keep the fastest; a cached choice for this architecture is taken as is.
+dmpt_status tune_engine(dmpt_ctx c, Engine eng, int64_t N, int* chosen) {
+  const int64_t Np = padded(N);
+  const int acc64 = acc64_of(c, eng);
+  const int nv = gemm_variants(eng, acc64);
+  const char* path = std::getenv("DMPT_TUNE_CACHE");
+  std::string arch;
+  {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, c->device) == hipSuccess) arch = p.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch.resize(colon);
+    if (arch.empty()) arch = "unknown";
+  }
+  int best = path ? cache_lookup(path, arch, eng, Np, acc64) : -1;
+  if (best < 0 || best >= nv) {
+    best = 0;
+    double best_ms = INFINITY;
+    const int reps = Np >= 4096 ? 2 : (Np >= 1024 ? 5 : 20);
+    for (int v = 0; v < nv; ++v) {
+      double ms = 0.0;
+      STCHK(dmpt_bench_product(c, N, prec_of(eng), v, reps, &ms, nullptr));
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = v;
+      }
+    }
+    if (path) cache_store(path, arch, eng, Np, acc64, best, best_ms);
+    if (c->log)
+      std::fprintf(stderr, "[dmpt] autotune engine %d Np %lld: %s (%.3f ms)\n", (int)eng, (long long)Np,
+                   gemm_variant_name(eng, acc64, best), best_ms);
+  }
+  set_variant(c, eng, Np, best);
+  if (chosen) *chosen = best;
+  return DMPT_OK;
+}
+
+// The engines a context's products use: its precision's, and the refinement's.
+int context_engines(dmpt_ctx c, Engine* out) {
+  int n = 0;
+  out[n++] = engine_of(c->opt.prec);
+  if (c->opt.prec == DMPT_BF16X3 && c->opt.refine) out[n++] = Engine::BF16S3;
+  return n;
+}
+
+// options.autotune: tune every engine of the context at N unless done already.
+dmpt_status autotune_if_asked(dmpt_ctx c, int64_t N) {
+  if (!c->opt.autotune) return DMPT_OK;
+  Engine e[2];
+  const int ne = context_engines(c, e);
+  for (int q = 0; q < ne; ++q)
+    if (!is_tuned(c, e[q], padded(N))) STCHK(tune_engine(c, e[q], N, nullptr));
+  return DMPT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dmpt_status dmpt_autotune(dmpt_ctx c, int64_t N, int* variant) {
   if (!c) return DMPT_ERR_ARG;
   if (N < 1 || N > c->n_max) return fail(c, DMPT_ERR_ARG, "N must lie in [1, n_max]");
-  const int64_t Np = padded(N);
-  const Engine eng = engine_of(c->opt.prec);
-  const int cand[2] = {128, 256};
-  int best = 128;
-  double best_ms = INFINITY;
-  for (int t : cand) {
-    if (gemm_tile_edge(eng, Np, t) != t) continue;  // not available for this engine / size
-    double ms = 0.0;
-    STCHK(dmpt_bench_product(c, N, c->opt.prec, t, 3, &ms, nullptr));
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = t;
-    }
-  }
-  bool found = false;
-  for (auto& p : c->tuned)
-    if (p.first == Np) {
-      p.second = best;
-      found = true;
-    }
-  if (!found) c->tuned.push_back({Np, best});
-  if (tile) *tile = best;
+  Engine e[2];
+  const int ne = context_engines(c, e);
+  int first = 0;
+  for (int q = 0; q < ne; ++q) STCHK(tune_engine(c, e[q], N, q == 0 ? &first : nullptr));
+  if (variant) *variant = first;
+  return DMPT_OK;
+}
+
+dmpt_status dmpt_set_variant(dmpt_ctx c, int64_t N, dmpt_prec prec, int variant) {
+  if (!c) return DMPT_ERR_ARG;
+  if (N < 1 || N > c->n_max) return fail(c, DMPT_ERR_ARG, "N must lie in [1, n_max]");
+  if (prec < DMPT_FP64 || prec > DMPT_BF16X6) return fail(c, DMPT_ERR_ARG, "unknown precision");
+  const Engine eng = engine_of(prec);
+  if (variant < 0 || variant >= gemm_variants(eng, acc64_of(c, eng)))
+    return fail(c, DMPT_ERR_ARG, "no such kernel variant for this precision");
+  set_variant(c, eng, padded(N), variant);
+  return DMPT_OK;
+}
+
+dmpt_status dmpt_get_variant(dmpt_ctx c, int64_t N, dmpt_prec prec, int* variant, int* tuned, char* name,
+                             int name_len) {
+  if (!c || !variant) return DMPT_ERR_ARG;
+  if (N < 1) return fail(c, DMPT_ERR_ARG, "N must be >= 1");
+  if (prec < DMPT_FP64 || prec > DMPT_BF16X6) return fail(c, DMPT_ERR_ARG, "unknown precision");
+  const Engine eng = engine_of(prec);
+  *variant = variant_for(c, eng, padded(N));
+  if (tuned) *tuned = is_tuned(c, eng, padded(N)) ? 1 : 0;
+  if (name && name_len > 0)
+    std::snprintf(name, (size_t)name_len, "%s", gemm_variant_name(eng, acc64_of(c, eng), *variant));
   return DMPT_OK;
 }
 
@@ -2902,6 +3033,7 @@ dmpt_status dmpt_response(dmpt_ctx c, int64_t N, const double* H0, int d, const 
   reset_stats(c);
   PassIn in{H0, order >= 1 ? d : 0, H1, H2, beta, n, order, mu};
   in.H3 = H3;
+  STCHK(autotune_if_asked(c, N));
   double glo, ghi;
   STCHK(scan_inputs(c, N, in, &glo, &ghi));
   const double emax = std::max(std::fabs(glo - mu[0]), std::fabs(ghi - mu[0]));
@@ -2942,6 +3074,7 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
     if (std::isnan(mu[i])) mu[i] = 0.0;
   PassIn in{H0, dd, H1, H2, beta, n, order, mu.data()};
   in.H3 = H3;
+  STCHK(autotune_if_asked(c, N));
   double glo, ghi;
   STCHK(scan_inputs(c, N, in, &glo, &ghi));
   if (beta * (ghi - glo) >= std::ldexp(1.0, n + 1))
@@ -3164,9 +3297,12 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
     bk.back().m += 1;
     bk.back().xmax = std::max(bk.back().xmax, xs[slot_sys[i]]);
   }
-  // workspace: (re)allocate when this batch needs more than the cached one
+  // the batch's product engine; with options.autotune every bucket size is tuned first
   const Engine eng = (c->opt.prec == DMPT_BF16X3 && c->opt.refine) ? Engine::BF16S3
                                                                     : engine_of(c->opt.prec);
+  if (c->opt.autotune)
+    for (auto& b : bk)
+      if (!is_tuned(c, eng, b.Np)) STCHK(tune_engine(c, eng, std::min<int64_t>(b.Np, c->n_max), nullptr));
   const int np = engine_planes(eng);
   const int dmem = std::max(1, d + lin);
   size_t need = 0, part_need = c->part_count;

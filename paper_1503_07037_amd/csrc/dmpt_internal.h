@@ -73,7 +73,7 @@ struct GemmArgs {
   const void* W; int64_t sW;   // optional: per-tile partials of <W, C>
   double* partials;            // [batch][tiles]
   const int* active;           // optional per-batch mask; 0 = skip the member
-  int tile;                    // output tile edge wanted: 0 = largest available, 128, 256
+  int variant;                 // kernel variant of the engine (gemm_variants; 0 = default)
   int acc64;                   // BF16S3 only: FP32 per stage, FP64 across stages (128-wide tiles)
   // optional executed-work tally (graph replays, where the host cannot see
   // which members are skipped): every member that runs adds tally_m and
@@ -82,10 +82,13 @@ struct GemmArgs {
   double tally_m, tally_u;
 };
 
-// Output tile edge, and number of output tiles per batch member, of the
-// kernel that gemm() launches for this engine, size and tile preference.
-int gemm_tile_edge(Engine eng, int64_t Np, int tile_pref);
-int gemm_tiles(Engine eng, int64_t Np, int tile_pref);
+// Kernel variants of an engine (gemm.hip), their names, and the output tile
+// edge and number of output tiles per batch member of the kernel gemm()
+// launches for an engine, size and variant.
+int gemm_variants(Engine eng, int acc64);
+const char* gemm_variant_name(Engine eng, int acc64, int variant);
+int gemm_tile_edge(Engine eng, int64_t Np, int variant, int acc64);
+int gemm_tiles(Engine eng, int64_t Np, int variant, int acc64);
 hipError_t gemm(const GemmArgs& a, hipStream_t s);
 // Set the launch attributes of the product kernels (once per process and device).
 hipError_t gemm_prepare();

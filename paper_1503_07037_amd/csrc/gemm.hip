@@ -580,11 +580,38 @@ hipError_t prepare_bf16() {
 
 }  // namespace
 
-// Output tile edge of the kernel `gemm` uses for an engine and size: the
-// 256-wide split-BF16 kernel when Np allows it and the tile choice allows it.
-int gemm_tile_edge(Engine eng, int64_t Np, int tile_pref) {
-  const bool bf = eng == Engine::BF16S2 || eng == Engine::BF16S3;
-  if (bf && tile_pref != 128 && Np % 256 == 0) return 256;
+// Kernel variants of each engine, chosen per padded size by the autotuner
+// (0 is the default):
+//   FP64  0: BK 8, 8 waves   1: BK 16, 8 waves   2: BK 8, 4 waves
+//   FP32  0: BK 32, 8 waves  1: BK 16, 8 waves   2: BK 32, 4 waves
+//   split BF16  0: 256 x 256 tiles where Np allows (else 128)   1: 128 x 128 tiles
+//   (the 6-product kernel with FP64 slice sums has 128 x 128 tiles only)
+int gemm_variants(Engine eng, int acc64) {
+  switch (eng) {
+    case Engine::F64: return 3;
+    case Engine::F32: return 3;
+    case Engine::BF16S2: return 2;
+    case Engine::BF16S3: return acc64 ? 1 : 2;
+  }
+  return 1;
+}
+
+const char* gemm_variant_name(Engine eng, int acc64, int v) {
+  static const char* f64[3] = {"FP64 BK 8, 8 waves", "FP64 BK 16, 8 waves", "FP64 BK 8, 4 waves"};
+  static const char* f32[3] = {"FP32 BK 32, 8 waves", "FP32 BK 16, 8 waves", "FP32 BK 32, 4 waves"};
+  static const char* bf[2] = {"BF16 256 x 256 tiles", "BF16 128 x 128 tiles"};
+  if (v < 0 || v >= gemm_variants(eng, acc64)) return "invalid";
+  if (eng == Engine::F64) return f64[v];
+  if (eng == Engine::F32) return f32[v];
+  if (eng == Engine::BF16S3 && acc64) return "BF16 128 x 128 tiles, FP64 slice sums";
+  return bf[v];
+}
+
+// Output tile edge of the kernel `gemm` uses for an engine, size and variant:
+// the 256-wide split-BF16 kernel when Np and the variant allow it.
+int gemm_tile_edge(Engine eng, int64_t Np, int variant, int acc64) {
+  const bool bf = eng == Engine::BF16S2 || (eng == Engine::BF16S3 && !acc64);
+  if (bf && variant == 0 && Np % 256 == 0) return 256;
   return BM;
 }
 
@@ -599,22 +626,27 @@ hipError_t gemm_prepare() {
   return prepare_bf16<3, 256, 16, kWaves256>();
 }
 
-int gemm_tiles(Engine eng, int64_t Np, int tile_pref) {
-  const int e = gemm_tile_edge(eng, Np, tile_pref);
+int gemm_tiles(Engine eng, int64_t Np, int variant, int acc64) {
+  const int e = gemm_tile_edge(eng, Np, variant, acc64);
   return (int)((Np / e) * (Np / e));
 }
 
 hipError_t gemm(const GemmArgs& a, hipStream_t s) {
-  if (a.Np <= 0 || a.Np % BM != 0 || a.batch <= 0 || a.X.div < 1 || a.Y.div < 1)
+  if (a.Np <= 0 || a.Np % BM != 0 || a.batch <= 0 || a.X.div < 1 || a.Y.div < 1 || a.variant < 0 ||
+      a.variant >= gemm_variants(a.eng, a.acc64))
     return hipErrorInvalidValue;
-  const int edge = gemm_tile_edge(a.eng, a.Np, a.tile);
-  const dim3 grid((unsigned)gemm_tiles(a.eng, a.Np, a.tile), 1, (unsigned)a.batch);
+  const int edge = gemm_tile_edge(a.eng, a.Np, a.variant, a.acc64);
+  const dim3 grid((unsigned)gemm_tiles(a.eng, a.Np, a.variant, a.acc64), 1, (unsigned)a.batch);
   switch (a.eng) {
     case Engine::F64:
-      hipLaunchKernelGGL((k_gemm_f64<kF64BK, kF64NW>), grid, dim3(kF64NW * 64), 0, s, a);
+      if (a.variant == 1) hipLaunchKernelGGL((k_gemm_f64<16, 8>), grid, dim3(8 * 64), 0, s, a);
+      else if (a.variant == 2) hipLaunchKernelGGL((k_gemm_f64<8, 4>), grid, dim3(4 * 64), 0, s, a);
+      else hipLaunchKernelGGL((k_gemm_f64<kF64BK, kF64NW>), grid, dim3(kF64NW * 64), 0, s, a);
       return hipGetLastError();
     case Engine::F32:
-      hipLaunchKernelGGL((k_gemm_f32<kF32BK, kF32NW>), grid, dim3(kF32NW * 64), 0, s, a);
+      if (a.variant == 1) hipLaunchKernelGGL((k_gemm_f32<16, 8>), grid, dim3(8 * 64), 0, s, a);
+      else if (a.variant == 2) hipLaunchKernelGGL((k_gemm_f32<32, 4>), grid, dim3(4 * 64), 0, s, a);
+      else hipLaunchKernelGGL((k_gemm_f32<kF32BK, kF32NW>), grid, dim3(kF32NW * 64), 0, s, a);
       return hipGetLastError();
     case Engine::BF16S2:
       return edge == 256 ? launch_bf16<2, 256, 16, kWaves256>(a, grid, s)
