@@ -118,6 +118,9 @@ typedef struct {
   int autotune;         /* 1: before the first products of a padded size, time every product-kernel
                            variant of the context's engines at that size and keep the fastest
                            (dmpt_autotune); the batched solve tunes every bucket size */
+  int grouped;          /* batched solve: 1 (default) = the launches of every recursion step are
+                           issued for all size buckets together, each product as one grouped launch
+                           over every bucket's (member, tile) blocks; 0 = bucket by bucket */
 } dmpt_options;
 
 #define DMPT_MAX_DIRS 8

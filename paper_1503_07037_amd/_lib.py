@@ -38,7 +38,7 @@ class Options(ctypes.Structure):
         ("max_newton", ctypes.c_int), ("max_cg", ctypes.c_int), ("refine", ctypes.c_int),
         ("ckpt_every", ctypes.c_int), ("check", ctypes.c_int), ("staged", ctypes.c_int),
         ("warm_traj", ctypes.c_int), ("schedule", ctypes.c_int), ("acc64", ctypes.c_int),
-        ("autotune", ctypes.c_int),
+        ("autotune", ctypes.c_int), ("grouped", ctypes.c_int),
     ]
 
 

@@ -49,7 +49,7 @@ def _torch():
 
 def options(prec="fp64", solver="cg", guess="prev", tol_occ=0.0, tol_cg=0.0, max_newton=50,
             max_cg=60, refine=0, ckpt_every=5, check=0, staged=1, warm_traj=1, schedule=1,
-            acc64=1, autotune=0):
+            acc64=1, autotune=0, grouped=1):
     """Build an options struct; 0 tolerances select the precision's defaults."""
     lib = L.load()
     o = L.Options()
@@ -64,6 +64,7 @@ def options(prec="fp64", solver="cg", guess="prev", tol_occ=0.0, tol_cg=0.0, max
     o.schedule = int(schedule)
     o.acc64 = int(acc64)
     o.autotune = int(autotune)
+    o.grouped = int(grouped)
     return o
 
 

@@ -20,6 +20,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -253,6 +254,14 @@ int planes_needed(const dmpt_options& o) {
 // modes differ in the products only.
 size_t esize_needed(const dmpt_options&) { return 8; }
 
+// A launch of the recursion step code kept for a grouped replay: a product
+// (its arguments) or any other launch (a closure that issues it).
+struct Op {
+  bool gemm = false;
+  GemmArgs ga{};
+  std::function<hipError_t()> fn;
+};
+
 // ------------------------------------------------------------------ views
 struct Call {
   dmpt_ctx c;
@@ -271,7 +280,22 @@ struct Call {
   int cs = 0;                    // members per step in c->st
   int cj = 0;                    // member of the J jet's solution in c->st (1 + d)
   const double* cmu = nullptr;   // chain loads: mu1[d], mu2[d]; D^(k) = D^(k)(mu = 0) - mu D_J
+  double* part = nullptr;        // partial sums of this call's products and reductions
+  size_t part_count = 0;         // ... and their capacity
+  std::vector<Op>* rec = nullptr;  // when set, launches are recorded here instead of issued
 };
+
+// Issue a launch of the recursion step code now, or record it (k.rec).
+#define EMIT(k, expr)                                                          \
+  do {                                                                         \
+    if ((k).rec) {                                                             \
+      Op op_;                                                                  \
+      op_.fn = [=]() { return (expr); };                                      \
+      (k).rec->push_back(op_);                                                 \
+    } else {                                                                   \
+      HIPCHK((k).c, (expr));                                                   \
+    }                                                                          \
+  } while (0)
 
 // Chain flags of a pass (linear schedule): save or load the order-0/1
 // solutions, save or load the order-2 solutions.
@@ -405,7 +429,7 @@ dmpt_status run_gemm(const Call& k, const G& g) {
   a.C1 = g.C1; a.sC1 = g.sC1; a.beta1 = g.beta1;
   a.C2 = g.C2; a.sC2 = g.sC2; a.beta2 = g.beta2;
   a.W = g.W; a.sW = g.sW;
-  a.partials = k.c->d_part;
+  a.partials = k.part;
   a.active = g.active;
   a.variant = variant_for(k.c, k.eng, k.Np);
   a.acc64 = acc64_of(k.c, k.eng);
@@ -427,7 +451,7 @@ dmpt_status run_gemm(const Call& k, const G& g) {
     if (ok && a.C1) ok = reg_ok(c, a.C1, span(a.sC1, 1) * es);
     if (ok && a.C2) ok = reg_ok(c, a.C2, span(a.sC2, 1) * es);
     if (ok && a.W) ok = reg_ok(c, a.W, span(a.sW, 1) * es) &&
-                        (size_t)b * gemm_tiles(k.eng, k.Np, a.variant, a.acc64) <= c->part_count;
+                        (size_t)b * gemm_tiles(k.eng, k.Np, a.variant, a.acc64) <= k.part_count;
     if (ok && b > 1) ok = a.sC != 0;
     if (!ok) return fail(c, DMPT_ERR_ARG, "internal: a product would leave its workspace");
   }
@@ -453,6 +477,15 @@ dmpt_status run_gemm(const Call& k, const G& g) {
     for (int p = 0; p < 3; ++p)
       if (a.Cpl[p]) bytes += members * nn * 2.0;
   }
+  if (k.rec) {
+    Op o;
+    o.gemm = true;
+    o.ga = a;
+    k.rec->push_back(o);
+    c->mfma_flops += mf;
+    c->useful_flops += uf;
+    return DMPT_OK;
+  }
   hipEvent_t ea = nullptr, eb = nullptr;
   if (c->prof_on) {
     if (c->prof_pending.size() >= 2048) STCHK(prof_resolve(c));
@@ -472,8 +505,10 @@ dmpt_status run_gemm(const Call& k, const G& g) {
 
 // Sum the GEMM per-tile partials into out[z*ostride + oidx].
 dmpt_status sum_gemm_partials(const Call& k, int batch, double* out, int ostride, int oidx) {
-  HIPCHK(k.c, sum_partials(k.c->d_part, gemm_tiles(k.eng, k.Np, variant_for(k.c, k.eng, k.Np), acc64_of(k.c, k.eng)), batch, out,
-                           ostride, oidx, k.c->stream));
+  const int tiles = gemm_tiles(k.eng, k.Np, variant_for(k.c, k.eng, k.Np), acc64_of(k.c, k.eng));
+  hipStream_t s = k.c->stream;
+  double* part = k.part;
+  EMIT(k, sum_partials(part, tiles, batch, out, ostride, oidx, s));
   return DMPT_OK;
 }
 
@@ -484,8 +519,9 @@ dmpt_status sym_inplace(const Call& k, const Group& g, int z0, int batch, double
   uint16_t* pl[3];
   planes_of(k, g, z0, pl);
   T* m = (T*)mptr(k, g, z0);
-  HIPCHK(k.c, (sym_combine<T, T>(m, k.Np, k.stride, k.N, k.Np, a, nullptr, 0, m, k.Np, k.stride,
-                                 pl, k.np, batch, k.c->stream)));
+  hipStream_t s = k.c->stream;
+  EMIT(k, (sym_combine<T, T>(m, k.Np, k.stride, k.N, k.Np, a, nullptr, 0, m, k.Np, k.stride, pl, k.np, batch,
+                             s)));
   return DMPT_OK;
 }
 
@@ -495,9 +531,12 @@ dmpt_status sym_to(const Call& k, const Group& in, const Group& out, int batch, 
   if (batch > in.count || batch > out.count) return fail(k.c, DMPT_ERR_ARG, "internal: sym batch too large");
   uint16_t* pl[3];
   planes_of(k, out, 0, pl);
-  HIPCHK(k.c, (sym_combine<T, T>((const T*)mptr(k, in, 0), k.Np, k.stride, k.N, k.Np, 1.0, nullptr,
-                                 0, (T*)mptr(k, out, 0), k.Np, k.stride, pl, planes ? k.np : 0,
-                                 batch, k.c->stream)));
+  const T* src = (const T*)mptr(k, in, 0);
+  T* dst = (T*)mptr(k, out, 0);
+  const int npl = planes ? k.np : 0;
+  hipStream_t s = k.c->stream;
+  EMIT(k, (sym_combine<T, T>(src, k.Np, k.stride, k.N, k.Np, 1.0, nullptr, 0, dst, k.Np, k.stride, pl, npl,
+                             batch, s)));
   return DMPT_OK;
 }
 
@@ -520,23 +559,33 @@ dmpt_status cg_solve(const Call& k, const Group& u, int batch, int ydiv, const i
   const WS* w = k.w;
   if (batch < 1 || ydiv < 1 || u.count < batch || w->R.count < batch || w->P.count < batch ||
       w->Q.count < batch || w->S0.count < (batch - 1) / ydiv + 1 || batch > kIterSlot ||
-      (size_t)batch * reduce_blocks(k.nn) > c->part_count)
+      (size_t)batch * reduce_blocks(k.nn) > k.part_count)
     return fail(c, DMPT_ERR_ARG, "internal: solve batch exceeds its workspace");
+  if (k.rec && !k.graph) return fail(c, DMPT_ERR_ARG, "internal: recorded solves need fixed counts");
   hipStream_t s = c->stream;
   const int hs = c->hstride;
   const double tol = k.tol_cg;
   const int64_t n = k.nn;
+  const int64_t st = k.stride;
+  const int np = k.np;
+  double* part = k.part;
+  int* act = w->active;
+  int* its = w->iters;
+  double* rr = w->rr;
+  double* pq = w->pq;
+  const double* ref = w->ref;
+  T* U = (T*)mptr(k, u, 0);
+  T* R = (T*)mptr(k, w->R, 0);
+  T* P = (T*)mptr(k, w->P, 0);
+  const T* Q = (const T*)mptr(k, w->Q, 0);
+  uint16_t* ppl[3];
+  planes_of(k, w->P, 0, ppl);
   // P = R (with planes)
-  {
-    uint16_t* pl[3];
-    planes_of(k, w->P, 0, pl);
-    HIPCHK(c, axpby<T>((const T*)mptr(k, w->R, 0), k.stride, (T*)mptr(k, w->P, 0), k.stride, n,
-                       batch, 1.0, 0.0, pl, k.stride, k.np, s));
-  }
-  if (mask) HIPCHK(c, expand_mask(mask, 1, w->active, batch, s));
-  else HIPCHK(c, set_values(w->active, 1, batch, nullptr, 0.0, 0, s));
-  HIPCHK(c, set_values(w->iters, 0, batch, nullptr, 0.0, 0, s));
-  HIPCHK(c, cg_check(w->rr, w->rr, w->ref, hs, batch, tol * tol, kEta * kEta, w->active, w->iters, s));
+  EMIT(k, axpby<T>(R, st, P, st, n, batch, 1.0, 0.0, ppl, st, np, s));
+  if (mask) EMIT(k, expand_mask(mask, 1, act, batch, s));
+  else EMIT(k, set_values(act, 1, batch, nullptr, 0.0, 0, s));
+  EMIT(k, set_values(its, 0, batch, nullptr, 0.0, 0, s));
+  EMIT(k, cg_check(rr, rr, ref, hs, batch, tol * tol, kEta * kEta, act, its, s));
   const int red_nb = reduce_blocks(n);
   const int cap = k.graph ? std::min(k.cg_iters, c->opt.max_cg) : c->opt.max_cg;
   for (int it = 0; it < cap && it + 1 < hs; ++it) {
@@ -563,22 +612,15 @@ dmpt_status cg_solve(const Call& k, const Group& u, int batch, int ydiv, const i
     g.counted = live;
     STCHK(run_gemm(k, g));
     STCHK(sum_gemm_partials(k, batch, w->pq + it, hs, 0));
-    HIPCHK(c, cg_update_xr<T>((T*)mptr(k, u, 0), (T*)mptr(k, w->R, 0), (const T*)mptr(k, w->P, 0),
-                              (const T*)mptr(k, w->Q, 0), n, k.stride, batch, w->rr + it,
-                              w->pq + it, hs, w->active, c->d_part, s));
-    HIPCHK(c, sum_partials(c->d_part, red_nb, batch, w->rr + it + 1, hs, 0, s));
-    {
-      uint16_t* pl[3];
-      planes_of(k, w->P, 0, pl);
-      HIPCHK(c, cg_update_p<T>((T*)mptr(k, w->P, 0), (const T*)mptr(k, w->R, 0), n, k.stride, batch,
-                               w->rr + it + 1, w->rr + it, hs, w->active, pl, k.np, s));
-    }
-    HIPCHK(c, cg_check(w->rr + it + 1, w->rr, w->ref, hs, batch, tol * tol, kEta * kEta, w->active,
-                       w->iters, s));
+    EMIT(k, cg_update_xr<T>(U, R, P, Q, n, st, batch, rr + it, pq + it, hs, act, part, s));
+    EMIT(k, sum_partials(part, red_nb, batch, rr + it + 1, hs, 0, s));
+    EMIT(k, cg_update_p<T>(P, R, n, st, batch, rr + it + 1, rr + it, hs, act, ppl, np, s));
+    EMIT(k, cg_check(rr + it + 1, rr, ref, hs, batch, tol * tol, kEta * kEta, act, its, s));
   }
   if (k.graph) {
     // fixed-count solve: its statistics accumulate on the device (read after the replays)
-    HIPCHK(c, cg_account(w->active, w->iters, batch, c->d_cgstat, s));
+    int* stat = c->d_cgstat;
+    EMIT(k, cg_account(act, its, batch, stat, s));
     return DMPT_OK;
   }
   HIPCHK(c, hipMemcpyAsync(c->h_int, w->active, batch * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -788,11 +830,16 @@ dmpt_status solve_order0(const Call& k, int step) {
   const int hs = c->hstride;
   uint16_t* pl[3] = {nullptr, nullptr, nullptr};
   // ||rhs||^2 = 4 ||D0||^2
-  HIPCHK(c, dot_partials<T>((const T*)mptr(k, w->D0, 0), k.stride, (const T*)mptr(k, w->D0, 0),
-                            k.stride, k.nn, k.m, c->d_part, s));
-  HIPCHK(c, sum_partials(c->d_part, reduce_blocks(k.nn), k.m, w->ref, 1, 0, s));
-  HIPCHK(c, axpby<double>(w->ref, 0, w->ref, 0, k.m, 1, 0.0, 4.0, pl, 0, 0, s));
+  {
+    const T* d0 = (const T*)mptr(k, w->D0, 0);
+    double* part = k.part;
+    double* ref = w->ref;
+    EMIT(k, dot_partials<T>(d0, k.stride, d0, k.stride, k.nn, k.m, part, s));
+    EMIT(k, sum_partials(part, reduce_blocks(k.nn), k.m, ref, 1, 0, s));
+    EMIT(k, axpby<double>(ref, 0, ref, 0, k.m, 1, 0.0, 4.0, pl, 0, 0, s));
+  }
   const bool guess_tj = k.traj && c->tj_valid >= 0 && step >= 0;
+  if (guess_tj && k.rec) return fail(c, DMPT_ERR_ARG, "internal: recorded passes keep no trajectory");
   if (guess_tj) {
     // U = this step's solution of the previous pass; R = 2 D0 - U - 4 U S0
     STCHK(tj_load<T>(k, c->U0, 0, step, 0));
@@ -824,8 +871,11 @@ dmpt_status solve_order0(const Call& k, int step) {
     STCHK(run_gemm(k, q));
     uint16_t* pd[3];
     planes_of(k, w->D0, 0, pd);
-    HIPCHK(c, axpby<T>((const T*)mptr(k, w->P, 0), k.stride, (T*)mptr(k, w->D0, 0), k.stride, k.nn,
-                       k.m, -8.0, 2.0, pd, k.stride, k.np, s));
+    {
+      const T* pp = (const T*)mptr(k, w->P, 0);
+      T* d0 = (T*)mptr(k, w->D0, 0);
+      EMIT(k, axpby<T>(pp, k.stride, d0, k.stride, k.nn, k.m, -8.0, 2.0, pd, k.stride, k.np, s));
+    }
     G g;
     g.X = op(k, w->D0, 0, true);
     g.Y = op(k, w->S0, 0, true);
@@ -1334,6 +1384,8 @@ Call make_call(dmpt_ctx c, int64_t N, bool refined) {
   k.nn = k.Np * k.Np;
   k.stride = c->np_max * c->np_max;
   k.tol_cg = c->opt.tol_cg;
+  k.part = c->d_part;
+  k.part_count = c->part_count;
   return k;
 }
 
@@ -1664,6 +1716,34 @@ double kappa_bound(double x, int step) {
   return 1.0 + t * t;
 }
 
+// The recursion steps of one batched pass, recorded before graph capture:
+// every bucket runs the same sequence of launches (the same code path with a
+// common CG count per step), so launch i of every bucket can be issued
+// together.  Where launch i is a product in every bucket, one grouped launch
+// covers all buckets' (member, tile) blocks; other launches are issued bucket
+// by bucket.  Each bucket has its own slice of the partial-sum buffer.
+struct BatchedPlan {
+  std::vector<std::vector<Op>> ops;     // per bucket
+  struct Group {
+    int op;                             // launch index
+    Engine eng;
+    int variant, acc64, edge;
+    int list_off, start_off, nprob, blocks;
+  };
+  std::vector<Group> groups;            // grouped products, in launch order
+  std::vector<int> first_group;         // per launch index: first group, or -1 (issue per bucket)
+  GemmArgs* d_list = nullptr;           // device copies of the grouped products' arguments
+  int* d_start = nullptr;
+};
+
+// Per-bucket slices of the partial sums: the most a product's tiles or a
+// reduction's blocks need over the bucket's members.
+size_t bucket_part_need(const Bucket& b, int members, Engine eng, int variant, int acc64) {
+  const size_t mem = (size_t)std::max(members, b.m);
+  const size_t nn = (size_t)b.Np * b.Np;
+  return std::max((size_t)gemm_tiles(eng, b.Np, variant, acc64), (size_t)reduce_blocks((int64_t)nn)) * mem;
+}
+
 // lin = 1: order 1 with the linear schedule; the response P_J to H1 = I runs
 // as an extra direction (its D_0 is c I: no input, no mu shift), is written to
 // PJs[slot], and each system's P1 is then corrected to Tr P1 = 0 exactly
@@ -1677,11 +1757,12 @@ dmpt_status batched_pass(dmpt_ctx c, std::vector<Bucket>& bk, int wsi, int ord, 
                          double* const* P2s, const int64_t* Ns, const std::vector<double>& cs,
                          double* d_mu_shift, double* d_tr, int rs, double* d_half, int lin,
                          const double* d_par, double* d_mu, double* const* PJs, int rs0,
-                         double* d_delta) {
+                         double* d_delta, BatchedPlan* plan, bool record) {
   hipStream_t s = c->stream;
   const int J = 1 + 2 * d;
   const int dd = d + (lin == 1 ? 1 : 0);  // directions the recursion carries
   std::vector<Call> ks(bk.size());
+  size_t part_off = 0;
   for (size_t b = 0; b < bk.size(); ++b) {
     Call& k = ks[b];
     k = make_call(c, bk[b].Np, false);
@@ -1694,7 +1775,33 @@ dmpt_status batched_pass(dmpt_ctx c, std::vector<Bucket>& bk, int wsi, int ord, 
     k.stride = k.nn;
     k.m = bk[b].m;
     k.graph = true;
+    if (plan) {
+      // this bucket's slice of the partial sums
+      const size_t need = bucket_part_need(bk[b], k.m * std::max(dd, 1), eng, variant_for(c, eng, k.Np),
+                                           acc64_of(c, eng));
+      k.part = c->d_part + part_off;
+      k.part_count = need;
+      part_off += need;
+      if (part_off > c->part_count) return fail(c, DMPT_ERR_ARG, "internal: batched partials exceed their buffer");
+    }
+    if (record) continue;
     if (dd > 0) HIPCHK(c, expand_mask(k.w->mask0, dd, k.w->mask1, k.m * dd, s));
+  }
+  if (record) {
+    // the steps only, every bucket with the same CG count per step
+    plan->ops.assign(bk.size(), {});
+    for (int step = 0; step < n; ++step) {
+      int iters = 1;
+      for (size_t b = 0; b < bk.size(); ++b)
+        iters = std::max(iters, cg_bound(kappa_bound(bk[b].xmax, step), ks[b].tol_cg, c->opt.max_cg));
+      for (size_t b = 0; b < bk.size(); ++b) {
+        ks[b].cg_iters = iters;
+        ks[b].rec = &plan->ops[b];
+        STCHK(recursion_step<T>(ks[b], ord, dd, -1));
+        ks[b].rec = nullptr;
+      }
+    }
+    return DMPT_OK;
   }
   // D_0 of every system and direction from the caller inputs; the shifts
   // -c mu live on the device so the graph picks up each Newton update.
@@ -1734,12 +1841,32 @@ dmpt_status batched_pass(dmpt_ctx c, std::vector<Bucket>& bk, int wsi, int ord, 
       }
     }
   }
-  for (int step = 0; step < n; ++step)
-    for (size_t b = 0; b < bk.size(); ++b) {
-      Call& k = ks[b];
-      k.cg_iters = cg_bound(kappa_bound(bk[b].xmax, step), k.tol_cg, c->opt.max_cg);
-      STCHK(recursion_step<T>(k, ord, dd, -1));
+  if (plan) {
+    // the recorded steps: launch i of every bucket together, products grouped
+    const size_t nops = plan->ops.empty() ? 0 : plan->ops[0].size();
+    for (size_t i = 0; i < nops; ++i) {
+      const int g0 = plan->first_group[i];
+      if (g0 >= 0) {
+        for (size_t g = (size_t)g0; g < plan->groups.size() && plan->groups[g].op == (int)i; ++g) {
+          const BatchedPlan::Group& G = plan->groups[g];
+          HIPCHK(c, gemm_grouped(G.eng, G.variant, G.acc64, G.edge, plan->d_list + G.list_off,
+                                 plan->d_start + G.start_off, G.nprob, G.blocks, s));
+        }
+      } else {
+        for (size_t b = 0; b < bk.size(); ++b) {
+          const Op& o = plan->ops[b][i];
+          HIPCHK(c, o.gemm ? gemm(o.ga, s) : o.fn());
+        }
+      }
     }
+  } else {
+    for (int step = 0; step < n; ++step)
+      for (size_t b = 0; b < bk.size(); ++b) {
+        Call& k = ks[b];
+        k.cg_iters = cg_bound(kappa_bound(bk[b].xmax, step), k.tol_cg, c->opt.max_cg);
+        STCHK(recursion_step<T>(k, ord, dd, -1));
+      }
+  }
   // outputs and traces, per system
   for (size_t b = 0; b < bk.size(); ++b) {
     const Call& k = ks[b];
@@ -1787,6 +1914,66 @@ dmpt_status batched_pass(dmpt_ctx c, std::vector<Bucket>& bk, int wsi, int ord, 
       }
     }
   }
+  return DMPT_OK;
+}
+
+// Group the recorded launches: launch i is grouped when it is a product in
+// every bucket; products with the same variant and tile edge share one
+// grouped launch.  The arguments and block offsets are copied to the device
+// (before capture; they stay there for every replay).
+dmpt_status build_plan(dmpt_ctx c, BatchedPlan& plan, std::vector<void*>& owned) {
+  const size_t nb = plan.ops.size();
+  if (nb == 0) return DMPT_OK;
+  const size_t nops = plan.ops[0].size();
+  for (auto& o : plan.ops)
+    if (o.size() != nops) return fail(c, DMPT_ERR_ARG, "internal: buckets recorded different launch sequences");
+  std::vector<GemmArgs> list;
+  std::vector<int> starts;
+  plan.first_group.assign(nops, -1);
+  for (size_t i = 0; i < nops; ++i) {
+    bool all = true;
+    for (size_t b = 0; b < nb && all; ++b) all = plan.ops[b][i].gemm;
+    if (!all) continue;
+    std::vector<bool> used(nb, false);
+    for (size_t b0 = 0; b0 < nb; ++b0) {
+      if (used[b0]) continue;
+      const GemmArgs& a0 = plan.ops[b0][i].ga;
+      const int edge = gemm_tile_edge(a0.eng, a0.Np, a0.variant, a0.acc64);
+      BatchedPlan::Group G;
+      G.op = (int)i;
+      G.eng = a0.eng;
+      G.variant = a0.variant;
+      G.acc64 = a0.acc64;
+      G.edge = edge;
+      G.list_off = (int)list.size();
+      G.start_off = (int)starts.size();
+      G.nprob = 0;
+      int blocks = 0;
+      for (size_t b = b0; b < nb; ++b) {
+        const GemmArgs& a = plan.ops[b][i].ga;
+        if (used[b] || a.eng != a0.eng || a.variant != a0.variant || a.acc64 != a0.acc64 ||
+            gemm_tile_edge(a.eng, a.Np, a.variant, a.acc64) != edge)
+          continue;
+        used[b] = true;
+        list.push_back(a);
+        starts.push_back(blocks);
+        blocks += a.batch * gemm_tiles(a.eng, a.Np, a.variant, a.acc64);
+        ++G.nprob;
+      }
+      starts.push_back(blocks);
+      G.blocks = blocks;
+      if (plan.first_group[i] < 0) plan.first_group[i] = (int)plan.groups.size();
+      plan.groups.push_back(G);
+    }
+  }
+  if (list.empty()) return DMPT_OK;
+  plan.d_list = (GemmArgs*)dev_alloc(c, list.size() * sizeof(GemmArgs));
+  plan.d_start = (int*)dev_alloc(c, starts.size() * sizeof(int));
+  if (!plan.d_list || !plan.d_start) return fail(c, DMPT_ERR_NOMEM, "batched plan allocation failed");
+  owned.push_back(plan.d_list);
+  owned.push_back(plan.d_start);
+  HIPCHK(c, hipMemcpy(plan.d_list, list.data(), list.size() * sizeof(GemmArgs), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(plan.d_start, starts.data(), starts.size() * sizeof(int), hipMemcpyHostToDevice));
   return DMPT_OK;
 }
 
@@ -2273,6 +2460,7 @@ void dmpt_default_options(dmpt_options* o) {
   o->schedule = 1;
   o->acc64 = 1;
   o->autotune = 0;
+  o->grouped = 1;
 }
 
 static dmpt_status normalise_options(dmpt_ctx c, const dmpt_options* in, dmpt_options* out) {
@@ -2286,6 +2474,7 @@ static dmpt_status normalise_options(dmpt_ctx c, const dmpt_options* in, dmpt_op
   if (o.schedule < 0 || o.schedule > 2) return fail(c, DMPT_ERR_ARG, "schedule must be 0, 1 or 2");
   if (o.acc64 != 0 && o.acc64 != 1) return fail(c, DMPT_ERR_ARG, "acc64 must be 0 or 1");
   if (o.autotune != 0 && o.autotune != 1) return fail(c, DMPT_ERR_ARG, "autotune must be 0 or 1");
+  if (o.grouped != 0 && o.grouped != 1) return fail(c, DMPT_ERR_ARG, "grouped must be 0 or 1");
   if (o.tol_occ <= 0) o.tol_occ = default_tol_occ(o.prec, o.refine);
   if (o.tol_cg <= 0) o.tol_cg = default_tol_cg(o.prec, o.refine);
   if (o.max_newton <= 0) o.max_newton = 50;
@@ -3314,6 +3503,12 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
     part_need = std::max(part_need, (size_t)(b.Np / 128) * (b.Np / 128) * b.m * dmem);
     part_need = std::max(part_need, (size_t)reduce_blocks((int64_t)nn) * b.m * dmem);
   }
+  if (c->opt.grouped) {
+    // grouped launches: every bucket its own slice of the partial sums
+    size_t sum = 0;
+    for (auto& b : bk) sum += bucket_part_need(b, b.m * dmem, eng, variant_for(c, eng, b.Np), acc64_of(c, eng));
+    part_need = std::max(part_need, sum);
+  }
   const int hs = c->hstride;
   (void)need;
   if (part_need > c->part_count) {
@@ -3498,6 +3693,19 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
         break;
       }
     }
+    // grouped launches: record this stage's steps and build the grouped products first
+    BatchedPlan plan;
+    BatchedPlan* pplan = c->opt.grouped ? &plan : nullptr;
+    if (pplan) {
+      dmpt_status pr = batched_pass<double>(c, bk, SG.wsi, ord, d, n, eng, slot_sys, H0s, H1s, P0s, P1s, P2s,
+                                            Ns, cs, d_shift, d_tr, rs, c->d_res + RES_HALF, SG.lin, d_par,
+                                            d_mu, pjs.data(), rs0, d_delta, pplan, true);
+      if (pr == DMPT_OK) pr = build_plan(c, plan, local);
+      if (pr != DMPT_OK) {
+        rc = pr;
+        break;
+      }
+    }
     // capture one pass of this stage
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
       rc = fail(c, DMPT_ERR_HIP, "hipStreamBeginCapture failed");
@@ -3505,7 +3713,7 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
     }
     dmpt_status cr = batched_pass<double>(c, bk, SG.wsi, ord, d, n, eng, slot_sys, H0s, H1s, P0s,
                                           P1s, P2s, Ns, cs, d_shift, d_tr, rs, c->d_res + RES_HALF,
-                                          SG.lin, d_par, d_mu, pjs.data(), rs0, d_delta);
+                                          SG.lin, d_par, d_mu, pjs.data(), rs0, d_delta, pplan, false);
     if (cr == DMPT_OK) {
       // with the linear schedule the later stages run one pass each and no
       // longer move mu0: the first stage settles it a hundred times tighter

@@ -90,6 +90,11 @@ const char* gemm_variant_name(Engine eng, int acc64, int variant);
 int gemm_tile_edge(Engine eng, int64_t Np, int variant, int acc64);
 int gemm_tiles(Engine eng, int64_t Np, int variant, int acc64);
 hipError_t gemm(const GemmArgs& a, hipStream_t s);
+// One grouped launch over nprob products of the same engine, variant and tile
+// edge (list, start: device arrays; problem p owns the blocks start[p] ..
+// start[p + 1] - 1, members x tiles in order; blocks = start[nprob]).
+hipError_t gemm_grouped(Engine eng, int variant, int acc64, int edge, const GemmArgs* list, const int* start,
+                        int nprob, int blocks, hipStream_t s);
 // Set the launch attributes of the product kernels (once per process and device).
 hipError_t gemm_prepare();
 

@@ -116,8 +116,8 @@ __device__ inline void epi(const GemmArgs& a, int z, int64_t row, int64_t col, d
 }
 
 // One thread per running member adds the member's work to the tally.
-__device__ inline void count_member(const GemmArgs& a) {
-  if (a.tally && blockIdx.x == 0 && threadIdx.x == 0) {
+__device__ inline void count_member(const GemmArgs& a, int bx) {
+  if (a.tally && bx == 0 && threadIdx.x == 0) {
     atomicAdd(a.tally, a.tally_m);
     atomicAdd(a.tally + 1, a.tally_u);
   }
@@ -136,19 +136,18 @@ __device__ inline void count_member(const GemmArgs& a) {
 constexpr int kF64BK = DMPT_F64_BK, kF64NW = DMPT_F64_NW;
 
 template <int BK, int NW>
-__global__ __launch_bounds__(NW * 64) void k_gemm_f64(GemmArgs a) {
+__device__ __forceinline__ void gemm_f64_tile(const GemmArgs& a, int z, int bx, int nbx) {
   constexpr int LD = BK + 1;
   constexpr int FN = 16 / NW;                  // 16-wide MFMA tiles per wave along n
   constexpr int THREADS = NW * 64;
   constexpr int Q = BK / 2;                    // double2 per row and stage
   constexpr int L = BM * Q / THREADS;          // double2 loads per thread, operand and stage
   static_assert(L >= 1 && FN >= 1, "tile split");
-  const int z = blockIdx.z;
   if (a.active && !a.active[z]) return;
-  count_member(a);
+  count_member(a, bx);
   const int64_t Np = a.Np;
   int tm, tn;
-  tile_coords(blockIdx.x, (int)(Np / BM), (int)(Np / BN), tm, tn);
+  tile_coords(bx, (int)(Np / BM), (int)(Np / BN), tm, tn);
   const double* X = (const double*)a.X.m + (z / a.X.div) * a.X.stride + (int64_t)tm * BM * Np;
   const double* Y = (const double*)a.Y.m + (z / a.Y.div) * a.Y.stride + (int64_t)tn * BN * Np;
   __shared__ double sX[2][BM][LD];
@@ -217,8 +216,27 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_f64(GemmArgs a) {
       }
   if (a.W) {
     const double s = block_sum(dsum, red);
-    if (tid == 0) a.partials[(int64_t)z * gridDim.x + blockIdx.x] = s;
+    if (tid == 0) a.partials[(int64_t)z * nbx + bx] = s;
   }
+}
+
+template <int BK, int NW>
+__global__ __launch_bounds__(NW * 64) void k_gemm_f64(GemmArgs a) {
+  gemm_f64_tile<BK, NW>(a, blockIdx.z, blockIdx.x, gridDim.x);
+}
+
+// Grouped launch: the blocks of nprob products (members x tiles each, in
+// order) in one grid; block b belongs to the problem p with start[p] <= b < start[p + 1].
+template <int BK, int NW>
+__global__ __launch_bounds__(NW * 64) void k_gemm_f64_grouped(const GemmArgs* __restrict__ list,
+                                                               const int* __restrict__ start, int nprob) {
+  int p = 0;
+  const int b = blockIdx.x;
+  while (p + 1 < nprob && b >= start[p + 1]) ++p;
+  const GemmArgs& a = list[p];
+  const int tiles = (int)((a.Np / BM) * (a.Np / BN));
+  const int local = b - start[p];
+  gemm_f64_tile<BK, NW>(a, local / tiles, local % tiles, tiles);
 }
 
 // ------------------------------------------------------------------ FP32
@@ -241,19 +259,18 @@ constexpr int kF32BK = DMPT_F32_BK, kF32NW = DMPT_F32_NW;
 constexpr int kF32Slice = 16;  // k extent of one FP32 partial sum
 
 template <int BK, int NW>
-__global__ __launch_bounds__(NW * 64) void k_gemm_f32(GemmArgs a) {
+__device__ __forceinline__ void gemm_f32_tile(const GemmArgs& a, int z, int bx, int nbx) {
   constexpr int LD = BK + 1;
   constexpr int FN = 8 / NW;                      // MFMA tiles per wave along n: 2 (NW 4), 1 (NW 8)
   constexpr int THREADS = NW * 64;
   constexpr int L = BM * BK / 2 / THREADS;        // double2 loads per thread, operand and stage
   constexpr int SL = BK / kF32Slice;              // FP32 slices per stage
   static_assert(FN >= 1 && L >= 1 && SL >= 1 && BK % kF32Slice == 0, "tile split");
-  const int z = blockIdx.z;
   if (a.active && !a.active[z]) return;
-  count_member(a);
+  count_member(a, bx);
   const int64_t Np = a.Np;
   int tm, tn;
-  tile_coords(blockIdx.x, (int)(Np / BM), (int)(Np / BN), tm, tn);
+  tile_coords(bx, (int)(Np / BM), (int)(Np / BN), tm, tn);
   const double* X = (const double*)a.X.m + (z / a.X.div) * a.X.stride + (int64_t)tm * BM * Np;
   const double* Y = (const double*)a.Y.m + (z / a.Y.div) * a.Y.stride + (int64_t)tn * BN * Np;
   __shared__ float sX[2][BM][LD];
@@ -367,8 +384,25 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_f32(GemmArgs a) {
       }
   if (a.W) {
     const double s = block_sum(dsum, red);
-    if (tid == 0) a.partials[(int64_t)z * gridDim.x + blockIdx.x] = s;
+    if (tid == 0) a.partials[(int64_t)z * nbx + bx] = s;
   }
+}
+
+template <int BK, int NW>
+__global__ __launch_bounds__(NW * 64) void k_gemm_f32(GemmArgs a) {
+  gemm_f32_tile<BK, NW>(a, blockIdx.z, blockIdx.x, gridDim.x);
+}
+
+template <int BK, int NW>
+__global__ __launch_bounds__(NW * 64) void k_gemm_f32_grouped(const GemmArgs* __restrict__ list,
+                                                               const int* __restrict__ start, int nprob) {
+  int p = 0;
+  const int b = blockIdx.x;
+  while (p + 1 < nprob && b >= start[p + 1]) ++p;
+  const GemmArgs& a = list[p];
+  const int tiles = (int)((a.Np / BM) * (a.Np / BN));
+  const int local = b - start[p];
+  gemm_f32_tile<BK, NW>(a, local / tiles, local % tiles, tiles);
 }
 
 // ------------------------------------------------------------------ split BF16
@@ -395,7 +429,7 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_f32(GemmArgs a) {
 //     first k block, so the conversions and FP64 adds run beside the matrix
 //     core instead of after it.  0: one FP32 accumulator over all of k.
 template <int S, int TM, int BK, int NW, int FL>
-__global__ __launch_bounds__(NW * 64) void k_gemm_bf16(GemmArgs a) {
+__device__ __forceinline__ void gemm_bf16_tile(const GemmArgs& a, int z, int bx, int nbx) {
   constexpr int WN = NW / 2;           // waves along n (two along m)
   constexpr int FM = TM / 64;          // MFMA tiles per wave along m
   constexpr int FN = TM / (32 * WN);   // MFMA tiles per wave along n
@@ -409,13 +443,12 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_bf16(GemmArgs a) {
   static_assert(FN >= 1, "at least one MFMA tile per wave along n");
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   __shared__ double red[NW];
-  const int z = blockIdx.z;
   if (a.active && !a.active[z]) return;
-  count_member(a);
+  count_member(a, bx);
   const int64_t Np = a.Np;
   const int64_t kbr = Np >> 4;         // blocks per 32-row block row of a plane
   int tm, tn;
-  tile_coords(blockIdx.x, (int)(Np / TM), (int)(Np / TM), tm, tn);
+  tile_coords(bx, (int)(Np / TM), (int)(Np / TM), tm, tn);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
   // the blocks this wave copies: stage block q = wave + NW j
@@ -558,8 +591,25 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_bf16(GemmArgs a) {
       }
   if (a.W) {
     const double s = block_sum(dsum, red);
-    if (tid == 0) a.partials[(int64_t)z * gridDim.x + blockIdx.x] = s;
+    if (tid == 0) a.partials[(int64_t)z * nbx + bx] = s;
   }
+}
+
+template <int S, int TM, int BK, int NW, int FL>
+__global__ __launch_bounds__(NW * 64) void k_gemm_bf16(GemmArgs a) {
+  gemm_bf16_tile<S, TM, BK, NW, FL>(a, blockIdx.z, blockIdx.x, gridDim.x);
+}
+
+template <int S, int TM, int BK, int NW, int FL>
+__global__ __launch_bounds__(NW * 64) void k_gemm_bf16_grouped(const GemmArgs* __restrict__ list,
+                                                                const int* __restrict__ start, int nprob) {
+  int p = 0;
+  const int b = blockIdx.x;
+  while (p + 1 < nprob && b >= start[p + 1]) ++p;
+  const GemmArgs& a = list[p];
+  const int tiles = (int)((a.Np / TM) * (a.Np / TM));
+  const int local = b - start[p];
+  gemm_bf16_tile<S, TM, BK, NW, FL>(a, local / tiles, local % tiles, tiles);
 }
 
 template <int S, int TM, int BK>
@@ -574,8 +624,19 @@ hipError_t launch_bf16(const GemmArgs& a, dim3 grid, hipStream_t s) {
 
 template <int S, int TM, int BK, int NW, int FL = 0>
 hipError_t prepare_bf16() {
-  return hipFuncSetAttribute((const void*)k_gemm_bf16<S, TM, BK, NW, FL>,
+  hipError_t e = hipFuncSetAttribute((const void*)k_gemm_bf16<S, TM, BK, NW, FL>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bf16_lds<S, TM, BK>());
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_gemm_bf16_grouped<S, TM, BK, NW, FL>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bf16_lds<S, TM, BK>());
+}
+
+template <int S, int TM, int BK, int NW, int FL = 0>
+hipError_t launch_bf16_grouped(const GemmArgs* list, const int* start, int nprob, int blocks, hipStream_t s) {
+  const size_t lds = bf16_lds<S, TM, BK>();
+  hipLaunchKernelGGL((k_gemm_bf16_grouped<S, TM, BK, NW, FL>), dim3(blocks), dim3(NW * 64), lds, s, list, start,
+                     nprob);
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -658,6 +719,31 @@ hipError_t gemm(const GemmArgs& a, hipStream_t s) {
       }
       return edge == 256 ? launch_bf16<3, 256, 16, kWaves256>(a, grid, s)
                          : launch_bf16<3, 128, 32, 4>(a, grid, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t gemm_grouped(Engine eng, int variant, int acc64, int edge, const GemmArgs* list, const int* start,
+                        int nprob, int blocks, hipStream_t s) {
+  if (nprob < 1 || blocks < 1 || variant < 0 || variant >= gemm_variants(eng, acc64)) return hipErrorInvalidValue;
+  switch (eng) {
+    case Engine::F64:
+      if (variant == 1) hipLaunchKernelGGL((k_gemm_f64_grouped<16, 8>), dim3(blocks), dim3(8 * 64), 0, s, list, start, nprob);
+      else if (variant == 2) hipLaunchKernelGGL((k_gemm_f64_grouped<8, 4>), dim3(blocks), dim3(4 * 64), 0, s, list, start, nprob);
+      else hipLaunchKernelGGL((k_gemm_f64_grouped<kF64BK, kF64NW>), dim3(blocks), dim3(kF64NW * 64), 0, s, list, start, nprob);
+      return hipGetLastError();
+    case Engine::F32:
+      if (variant == 1) hipLaunchKernelGGL((k_gemm_f32_grouped<16, 8>), dim3(blocks), dim3(8 * 64), 0, s, list, start, nprob);
+      else if (variant == 2) hipLaunchKernelGGL((k_gemm_f32_grouped<32, 4>), dim3(blocks), dim3(4 * 64), 0, s, list, start, nprob);
+      else hipLaunchKernelGGL((k_gemm_f32_grouped<kF32BK, kF32NW>), dim3(blocks), dim3(kF32NW * 64), 0, s, list, start, nprob);
+      return hipGetLastError();
+    case Engine::BF16S2:
+      return edge == 256 ? launch_bf16_grouped<2, 256, 16, kWaves256>(list, start, nprob, blocks, s)
+                         : launch_bf16_grouped<2, 128, 32, 4>(list, start, nprob, blocks, s);
+    case Engine::BF16S3:
+      if (acc64) return launch_bf16_grouped<3, 128, 32, 8, 1>(list, start, nprob, blocks, s);
+      return edge == 256 ? launch_bf16_grouped<3, 256, 16, kWaves256>(list, start, nprob, blocks, s)
+                         : launch_bf16_grouped<3, 128, 32, 4>(list, start, nprob, blocks, s);
   }
   return hipErrorInvalidValue;
 }

@@ -175,3 +175,26 @@ def test_linear_and_joint_schedules_agree(dm, small_batch, d, order):
                 assert abs(mus[k][1 + z] - r["mu1"][z]) < 1e-9 * max(1.0, abs(r["mu1"][z]))
                 if order >= 2:
                     assert abs(mus[k][1 + d + z] - r["mu2"][z]) < 1e-9 * max(1.0, abs(r["mu2"][z]))
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-9)])
+def test_grouped_and_per_bucket_launches_agree(dm, small_batch, prec, tol):
+    """The grouped launches (every product of a step as one launch over all size buckets) give the
+    results of the bucket-by-bucket launches (orders 0-2, five buckets)."""
+    print(f"case batched grouped vs per-bucket {prec}", flush=True)
+    nmax = max(s["h0"].shape[0] for s in small_batch)
+    out = {}
+    for grouped in (1, 0):
+        with dm.Context(nmax, dirs_max=3, prec=prec, grouped=grouped) as ctx:
+            P0, P1, P2, mus, st = ctx.mu_newton_batched(
+                [T(s["h0"]) for s in small_batch], [[T(h) for h in s["h1"]] for s in small_batch],
+                [s["beta"] for s in small_batch], [s["Ne"] for s in small_batch], n=25, order=2)
+        out[grouped] = (P0, P1, P2)
+        print(f"  grouped={grouped}: passes={st['newton_iters']} seconds={st['seconds']:.2f}")
+    for k in range(len(small_batch)):
+        a, b = out[1], out[0]
+        assert np.abs(a[0][k].cpu().numpy() - b[0][k].cpu().numpy()).max() < tol
+        for z in range(3):
+            for o in (1, 2):
+                x, y = a[o][k][z].cpu().numpy(), b[o][k][z].cpu().numpy()
+                assert np.abs(x - y).max() < tol * max(1.0, np.abs(y).max())
