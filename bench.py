@@ -5,17 +5,20 @@ Workload (default): the dense random-banded Hamiltonian, N = 8192 (bandwidth
 256, entries 0.3 g exp(-|i-j|/32), diagonal U(-2, 2)), Ne = 4096, beta = 40,
 n = 30 recursion steps, three diagonal dipole perturbations (x, y, z of a
 32 x 16 x 16 grid), orders 0-2 (polarisability and hyperpolarisability), the
-canonical Newton loop of Algorithm 1, split-BF16 (3-product) matrix products
-with FP32 accumulation.  Inputs are synthetic, seeded, already resident in
-HBM when the timed region starts.
+canonical Newton loop of Algorithm 1: split-BF16 (3-product) matrix products
+with FP32 accumulation until mu0 is close, then the final passes (order 0
+and the linear schedule's order-1 and order-2 passes) with int8-slice
+products (four signed int8 digits per operand, thirteen digit products
+summed exactly in int32).  Inputs are synthetic, seeded, already resident in HBM
+when the timed region starts.
 
 One step = one complete canonical solve (dmpt_mu_newton): every Newton pass,
 every recursion step, every order and direction.  value = response solves
 per second = directions / seconds per step.
 
 Printed: one JSON line with the metric, the roofline of the dominant kernel
-(the split-BF16 MFMA product kernel, timed with HIP events on the library's
-stream over the timed region), accuracy on the oracle's sampled entries, and
+(the product kernel with the most device time, timed with HIP events on
+the library's stream over the timed region), accuracy on the oracle's sampled entries, and
 the FP64 CPU oracle timed on a bounded sample on this host.  The roofline's
 "traffic" (HBM bytes per launch of that kernel) comes from the hardware
 counter summary profiles/traffic_<engine>.json when it was taken on the
@@ -47,8 +50,10 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAKS_TFLOPS = {"bf16x3": 2500.0, "bf16x6": 2500.0, "fp32": 157.3, "fp64": 78.6}
-DTYPE = {"bf16x3": "bf16", "bf16x6": "bf16", "fp32": "f32", "fp64": "f64"}
+# dense matrix-core peaks of an MI355X per engine (int8: TOP/s)
+PEAKS_TFLOPS = {"bf16x3": 2500.0, "bf16x6": 2500.0, "int8x13": 5000.0, "fp32": 157.3, "fp64": 78.6}
+DTYPE = {"bf16x3": "bf16", "bf16x6": "bf16", "int8x13": "i8", "fp32": "f32", "fp64": "f64"}
+REFINE_NAME = {1: "bf16x6", 2: "int8x13"}
 
 
 def parse():
@@ -64,8 +69,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tol-cg", type=float, default=0.0)
     ap.add_argument("--tol-occ", type=float, default=0.0)
-    ap.add_argument("--refine", type=int, default=-1,
-                    help="bf16x3: finish with the 6-product refinement passes (default on)")
+    ap.add_argument("--refine", type=int, default=-1, choices=[-1, 0, 1, 2],
+                    help="bf16x3: finish with the int8-slice passes (2, default), the 6-product "
+                         "split-BF16 passes (1) or not at all (0)")
     ap.add_argument("--acc64", type=int, default=1,
                     help="6-product products: FP32 per 32-wide k slice, FP64 across slices (default 1)")
     ap.add_argument("--solver", default="cg", choices=["cg", "ns"],
@@ -412,7 +418,7 @@ def main():
     H0 = torch.tensor(c["H0"], device=dev)
     H1 = [torch.tensor(h, device=dev) for h in c["H1"]]
     torch.cuda.synchronize()
-    refine = (1 if args.prec == "bf16x3" else 0) if args.refine < 0 else args.refine
+    refine = (2 if args.prec == "bf16x3" else 0) if args.refine < 0 else args.refine
     ctx = dm.Context(N, dirs_max=d, prec=args.prec, tol_cg=args.tol_cg, tol_occ=args.tol_occ,
                      refine=refine, acc64=args.acc64, solver=args.solver)
 
@@ -454,20 +460,23 @@ def main():
         "metric": "response solves/sec (P0+P1+P2) and MFMA TFLOP/s at N=8192, err <=1e-6 vs FP64",
         "value": value, "unit": "responses/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[args.prec], "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[dom], "data": "synthetic",
         "config": {"workload": f"{args.workload}: banded N={N}, d={d}, orders 0-{order}, "
                                f"beta={c['beta']}, n={c['n']}, Ne={c['Ne']}" if args.workload == "banded8192"
                    else args.workload,
                    "N": N, "dirs": d, "order": order, "beta": c["beta"], "n": c["n"],
                    "solver": args.solver,
-                   "precision": args.prec + ("+refine(bf16x6)" if refine else "")
+                   "precision": args.prec + (f"+refine({REFINE_NAME[refine]})" if refine else "")
                    + (", 6-product sums FP64 across 32-wide k slices" if args.acc64 and
-                      (refine or args.prec == "bf16x6") else ""),
+                      (refine == 1 or args.prec == "bf16x6") else "")
+                   + (", int8 digit products summed exactly in int32" if
+                      (refine == 2 or args.prec == "int8x13") else ""),
                    "parallelism": "single GPU"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
                      "achieved_measure": "algorithmic: 2 N^3 per logical product and member over "
-                                         "the kernel's device time",
+                                         "the kernel's device time; peak is the dense matrix-core "
+                                         f"rate of the kernel's own type ({DTYPE[dom]})",
                      "mfma_executed": executed, "mfma_util": executed / peak,
                      "algorithmic_flops_per_launch": pe["useful_flops"] / max(pe["launches"], 1),
                      "traffic": traffic["bytes_per_launch"] if traffic else None,

@@ -150,13 +150,13 @@ class Context:
         """Totals since the last reset: launches, ms, mfma_flops, useful_flops, and per engine."""
         d = L.ProfileData()
         self._raise(self.lib.dmpt_profile_get(self.h, ctypes.byref(d)))
-        names = ["fp64", "fp32", "bf16x3", "bf16x6"]
+        names = ["fp64", "fp32", "bf16x3", "bf16x6", "int8x13"]
         return dict(launches=d.launches, ms=d.ms, mfma_flops=d.mfma_flops,
                     useful_flops=d.useful_flops,
                     engines={names[i]: dict(launches=d.eng_launches[i], ms=d.eng_ms[i],
                                             mfma_flops=d.eng_mfma_flops[i], bytes=d.eng_bytes[i],
                                             useful_flops=d.eng_useful_flops[i])
-                         for i in range(4)})
+                         for i in range(len(names))})
 
     def bench_product(self, N, prec=None, variant=0, reps=10):
         """Mean device ms and TFLOP/s of the product kernel (a variant) alone at size N."""

@@ -40,8 +40,25 @@ constexpr int kIterSlot = 512;
 struct Group {
   void* m = nullptr;             // master base, members at m + z * stride elements
   uint16_t* pl[3] = {nullptr, nullptr, nullptr};
+  int8_t* q8 = nullptr;          // int8 slices (I8S4), members 4 stride bytes apart
+  double* qs = nullptr;          // their q, one per member
   int count = 0;
 };
+
+// Slicing state of a group with int8 slices: a member is re-sliced before a
+// product reads it when a plane writer touched its group since (plane
+// writers mark every member from the first they write to the end).
+struct Q8Reg {
+  const char* m = nullptr;
+  int64_t stride = 0;            // member stride (elements)
+  int count = 0;
+  int8_t* q8 = nullptr;
+  double* qs = nullptr;
+  std::vector<char> dirty;
+};
+// Members sliced by one launch pair at most (the block maxima of a launch
+// fill kQ8Chunk * 1024 doubles of the context's buffer).
+constexpr int kQ8Chunk = 64;
 
 // The matrices and solver scalars one recursion pass works on.  Members of
 // the per-direction groups are laid out [system][direction]; the single
@@ -74,6 +91,9 @@ struct dmpt_ctx_s {
   dmpt_options opt{};
   size_t esize = 8;              // master element size of the workspace
   int planes = 0;                // BF16 planes per operand allocated
+  bool q8 = false;               // operand groups carry int8 slices (I8S4)
+  std::vector<Q8Reg> q8reg;
+  double* d_qpart = nullptr;     // block maxima of the slicing launches
   std::vector<void*> allocs;
   // matrix groups and solver scalars of the single-system entry points
   WS ws;
@@ -183,6 +203,8 @@ dmpt_status fail(dmpt_ctx c, dmpt_status s, const std::string& msg) {
 // stands in for the null stream: order it after the work already queued on
 // the null stream before any device work of a call ...
 dmpt_status enter_call(dmpt_ctx c) {
+  // the caller may have changed anything since the last call
+  for (auto& r : c->q8reg) std::fill(r.dirty.begin(), r.dirty.end(), 1);
   if (c->sync_null) {
     HIPCHK(c, hipEventRecord(c->ev_in, nullptr));
     HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_in, 0));
@@ -212,17 +234,26 @@ Engine engine_of(dmpt_prec p) {
     case DMPT_FP32: return Engine::F32;
     case DMPT_BF16X3: return Engine::BF16S2;
     case DMPT_BF16X6: return Engine::BF16S3;
+    case DMPT_INT8X13: return Engine::I8S4;
   }
   return Engine::F64;
 }
 
+// The engine and precision of BF16X3's final passes (options.refine 1 or 2).
+Engine refine_engine(const dmpt_options& o) { return o.refine == 2 ? Engine::I8S4 : Engine::BF16S3; }
+dmpt_prec final_prec(dmpt_prec p, int refine) {
+  if (p == DMPT_BF16X3 && refine) return refine == 2 ? DMPT_INT8X13 : DMPT_BF16X6;
+  return p;
+}
+
 double default_tol_cg(dmpt_prec p, int refine) {
-  if (p == DMPT_BF16X3 && refine) p = DMPT_BF16X6;
+  p = final_prec(p, refine);
   switch (p) {
     case DMPT_FP64: return 1e-14;
     case DMPT_FP32: return 1e-9;
     case DMPT_BF16X3: return 1e-5;
     case DMPT_BF16X6: return 1e-9;
+    case DMPT_INT8X13: return 1e-9;
   }
   return 1e-14;
 }
@@ -234,20 +265,25 @@ constexpr double kPhaseATolCg = 1e-5;
 constexpr double kPhaseATolOcc = 1e-5;
 
 double default_tol_occ(dmpt_prec p, int refine) {
-  if (p == DMPT_BF16X3 && refine) p = DMPT_BF16X6;
+  p = final_prec(p, refine);
   switch (p) {
     case DMPT_FP64: return 1e-12;
     case DMPT_FP32: return 1e-7;
     case DMPT_BF16X3: return 1e-6;
     case DMPT_BF16X6: return 1e-7;
+    case DMPT_INT8X13: return 1e-7;
   }
   return 1e-12;
 }
 
 int planes_needed(const dmpt_options& o) {
   int p = engine_planes(engine_of(o.prec));
-  if (o.prec == DMPT_BF16X3 && o.refine) p = 3;
+  if (o.prec == DMPT_BF16X3 && o.refine == 1) p = 3;
   return p;
+}
+
+bool q8_needed(const dmpt_options& o) {
+  return o.prec == DMPT_INT8X13 || (o.prec == DMPT_BF16X3 && o.refine == 2);
 }
 
 // Master copies (iterates, solver vectors) are FP64 in every mode; the
@@ -312,12 +348,22 @@ BOp op(const Call& k, const Group& g, int z, bool batched) {
   o.stride = batched ? k.stride : 0;
   return o;
 }
+
+// A writer is about to change members z.. of g: their int8 slices go stale.
+void q8_touch(dmpt_ctx c, const Group& g, int z) {
+  for (auto& r : c->q8reg)
+    if (r.m == (const char*)g.m) {
+      for (int i = std::max(z, 0); i < r.count; ++i) r.dirty[i] = 1;
+      return;
+    }
+}
 void* mptr(const Call& k, const Group& g, int z) {
   return (char*)g.m + (size_t)z * k.stride * k.c->esize;
 }
 void planes_of(const Call& k, const Group& g, int z, uint16_t** out) {
   for (int p = 0; p < 3; ++p)
     out[p] = (g.pl[p] && p < k.np) ? g.pl[p] + (size_t)z * k.stride : nullptr;
+  q8_touch(k.c, g, z);
 }
 
 // C(batch members z0..z0+batch) = alpha X Y^T + beta1 C1 + beta2 C2
@@ -415,6 +461,55 @@ int variant_for(dmpt_ctx c, Engine eng, int64_t Np) {
 
 int acc64_of(dmpt_ctx c, Engine eng) { return eng == Engine::BF16S3 && c->opt.acc64 ? 1 : 0; }
 
+// Int8 slices of a product operand (I8S4): the members the launch reads are
+// sliced again where a writer touched them since their last slicing.
+// Host-side bounds of the int8 operands of a launch.
+bool ok_q8_bounds(const Call& k, const GemmArgs& a, int batch) {
+  if (k.eng != Engine::I8S4) return true;
+  auto span = [&](const BOp& o) -> size_t {
+    return ((o.stride ? (size_t)((batch - 1) / o.div) * (size_t)o.stride : 0) + (size_t)k.nn) * kQ8Slices;
+  };
+  auto nq = [&](const BOp& o) -> size_t { return (o.stride ? (size_t)((batch - 1) / o.div) : 0) + 1; };
+  return a.X.q8 && a.Y.q8 && reg_ok(k.c, a.X.q8, span(a.X)) && reg_ok(k.c, a.Y.q8, span(a.Y)) &&
+         reg_ok(k.c, a.X.qs, nq(a.X) * sizeof(double)) && reg_ok(k.c, a.Y.qs, nq(a.Y) * sizeof(double));
+}
+
+dmpt_status q8_operand(const Call& k, BOp& o, int batch) {
+  dmpt_ctx c = k.c;
+  const char* p = (const char*)o.m;
+  for (auto& r : c->q8reg) {
+    const size_t mb = (size_t)r.stride * c->esize;
+    if (p < r.m || p >= r.m + mb * r.count) continue;
+    const size_t off = (size_t)(p - r.m);
+    const int n = o.stride ? (batch - 1) / o.div + 1 : 1;
+    const int z0 = (int)(off / mb);
+    if (off % mb || r.stride != k.stride || z0 + n > r.count)
+      return fail(c, DMPT_ERR_ARG, "internal: an int8 operand does not match its group's members");
+    for (int z = z0; z < z0 + n;) {
+      if (!r.dirty[z]) {
+        ++z;
+        continue;
+      }
+      int e = z;
+      while (e < z0 + n && r.dirty[e] && e - z < kQ8Chunk) ++e;
+      const double* src = (const double*)(r.m + (size_t)z * mb);
+      int8_t* dst = r.q8 + (size_t)z * r.stride * kQ8Slices;
+      double* qd = r.qs + z;
+      const int cnt = e - z;
+      const int64_t st = r.stride, Np = k.Np;
+      double* part = c->d_qpart;
+      hipStream_t s = c->stream;
+      EMIT(k, quantize_q8(src, st, Np, cnt, part, dst, st * kQ8Slices, qd, nullptr, s));
+      for (int i = z; i < e; ++i) r.dirty[i] = 0;
+      z = e;
+    }
+    o.q8 = r.q8 + (size_t)z0 * r.stride * kQ8Slices;
+    o.qs = r.qs + z0;
+    return DMPT_OK;
+  }
+  return fail(c, DMPT_ERR_ARG, "internal: an int8 product operand lies outside the sliced workspace");
+}
+
 dmpt_status run_gemm(const Call& k, const G& g) {
   GemmArgs a{};
   a.eng = k.eng;
@@ -433,6 +528,18 @@ dmpt_status run_gemm(const Call& k, const G& g) {
   a.active = g.active;
   a.variant = variant_for(k.c, k.eng, k.Np);
   a.acc64 = acc64_of(k.c, k.eng);
+  if (k.eng == Engine::I8S4) {
+    if (k.Np > kQ8MaxK) return fail(k.c, DMPT_ERR_UNSUPPORTED, "int8 products need N <= 32768");
+    STCHK(q8_operand(k, a.X, g.batch));
+    STCHK(q8_operand(k, a.Y, g.batch));
+    // the output's slices go stale too (C may be an operand group)
+    for (auto& r : k.c->q8reg) {
+      const size_t mb = (size_t)r.stride * k.c->esize;
+      const char* p = (const char*)a.C;
+      if (p >= r.m && p < r.m + mb * r.count)
+        for (int i = (int)((size_t)(p - r.m) / mb); i < r.count; ++i) r.dirty[i] = 1;
+    }
+  }
   // every member the launch touches must lie inside a workspace allocation
   {
     dmpt_ctx c = k.c;
@@ -455,6 +562,8 @@ dmpt_status run_gemm(const Call& k, const G& g) {
     if (ok && b > 1) ok = a.sC != 0;
     if (!ok) return fail(c, DMPT_ERR_ARG, "internal: a product would leave its workspace");
   }
+  if (ok_q8_bounds(k, a, g.batch) == false)
+    return fail(k.c, DMPT_ERR_ARG, "internal: an int8 operand would leave its workspace");
   const double n3 = 2.0 * (double)k.Np * k.Np * k.Np;
   if (k.graph) {
     // replays skip converged members on the device: count there
@@ -470,7 +579,8 @@ dmpt_status run_gemm(const Call& k, const G& g) {
   double bytes = 0.0;
   {
     const double nn = (double)k.nn, es = (double)c->esize;
-    const double opb = k.np ? 2.0 * k.np : es;  // bytes per element of an operand as the kernel reads it
+    // bytes per element of an operand as the kernel reads it
+    const double opb = k.eng == Engine::I8S4 ? (double)kQ8Slices : (k.np ? 2.0 * k.np : es);
     auto distinct = [&](const BOp& o) { return o.stride ? (double)((members - 1) / o.div + 1) : 1.0; };
     bytes += (distinct(a.X) + distinct(a.Y)) * nn * opb;
     bytes += members * nn * es * (1.0 + (a.C1 ? 1.0 : 0.0) + (a.C2 ? 1.0 : 0.0) + (a.W ? 1.0 : 0.0));
@@ -615,6 +725,7 @@ dmpt_status cg_solve(const Call& k, const Group& u, int batch, int ydiv, const i
     EMIT(k, cg_update_xr<T>(U, R, P, Q, n, st, batch, rr + it, pq + it, hs, act, part, s));
     EMIT(k, sum_partials(part, red_nb, batch, rr + it + 1, hs, 0, s));
     EMIT(k, cg_update_p<T>(P, R, n, st, batch, rr + it + 1, rr + it, hs, act, ppl, np, s));
+    q8_touch(c, w->P, 0);  // ppl was fetched once: mark P's int8 slices stale on every write
     EMIT(k, cg_check(rr + it + 1, rr, ref, hs, batch, tol * tol, kEta * kEta, act, its, s));
   }
   if (k.graph) {
@@ -950,6 +1061,7 @@ dmpt_status ns_inverse(const Call& k) {
     STCHK(run_gemm(k, h));
     HIPCHK(c, (sym_combine<T, T>((const T*)mptr(k, w->R, 0), k.Np, 0, k.N, k.Np, 0.5, nullptr, 0,
                                  (T*)mptr(k, w->Zi, 0), k.Np, 0, pz, k.np, 1, s)));
+    q8_touch(c, w->Zi, 0);  // pz was fetched once: mark Zi's int8 slices stale on every write
   }
   return DMPT_OK;
 }
@@ -1377,7 +1489,7 @@ Call make_call(dmpt_ctx c, int64_t N, bool refined) {
   k.c = c;
   k.w = &c->ws;
   k.eng = engine_of(c->opt.prec);
-  if (refined && c->opt.prec == DMPT_BF16X3 && c->opt.refine) k.eng = Engine::BF16S3;
+  if (refined && c->opt.prec == DMPT_BF16X3 && c->opt.refine) k.eng = refine_engine(c->opt);
   k.np = engine_planes(k.eng);
   k.N = N;
   k.Np = padded(N);
@@ -2466,7 +2578,8 @@ void dmpt_default_options(dmpt_options* o) {
 static dmpt_status normalise_options(dmpt_ctx c, const dmpt_options* in, dmpt_options* out) {
   dmpt_options o;
   if (in) o = *in; else dmpt_default_options(&o);
-  if (o.prec < DMPT_FP64 || o.prec > DMPT_BF16X6) return fail(c, DMPT_ERR_ARG, "unknown precision");
+  if (o.prec < DMPT_FP64 || o.prec > DMPT_INT8X13) return fail(c, DMPT_ERR_ARG, "unknown precision");
+  if (o.refine < 0 || o.refine > 2) return fail(c, DMPT_ERR_ARG, "refine must be 0, 1 or 2");
   if (o.solver != DMPT_SOLVER_CG && o.solver != DMPT_SOLVER_NS)
     return fail(c, DMPT_ERR_ARG, "unknown solver");
   if (o.guess != DMPT_GUESS_PREV && o.guess != DMPT_GUESS_TAYLOR)
@@ -2538,6 +2651,7 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
   c->dirs_max = dirs_max;
   c->esize = esize_needed(c->opt);
   c->planes = planes_needed(c->opt);
+  c->q8 = q8_needed(c->opt);
   // two members at least (the adjoint solves its two seeds together) and one
   // more than dirs_max (the response to the identity of the linear schedule)
   const int dm = std::max(2, dirs_max + 1);
@@ -2556,6 +2670,19 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
         g.pl[p] = (uint16_t*)alloc(nn * 2 * count);
         if (!g.pl[p]) return false;
       }
+    if (planes && c->q8 && count > 0) {
+      g.q8 = (int8_t*)alloc(nn * kQ8Slices * count);
+      g.qs = (double*)alloc(sizeof(double) * count);
+      if (!g.q8 || !g.qs) return false;
+      Q8Reg r;
+      r.m = (const char*)g.m;
+      r.stride = (int64_t)nn;
+      r.count = count;
+      r.q8 = g.q8;
+      r.qs = g.qs;
+      r.dirty.assign(count, 1);
+      c->q8reg.push_back(r);
+    }
     return true;
   };
   const int dd = dirs_max > 0 ? dirs_max + 1 : 0;  // groups for perturbations may be empty
@@ -2580,6 +2707,10 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
   const size_t tiles = (size_t)(c->np_max / 128) * (c->np_max / 128);
   c->part_count = std::max<size_t>(tiles, 1024) * dm;
   c->d_part = (double*)alloc(sizeof(double) * c->part_count);
+  if (c->q8) {
+    c->d_qpart = (double*)alloc(sizeof(double) * (size_t)q8_blocks(c->np_max) * kQ8Chunk);
+    if (!c->d_qpart) return bail(DMPT_ERR_NOMEM, "device scalar allocation failed");
+  }
   c->d_gersh = (double*)alloc(sizeof(double) * (2 + 2 * (size_t)n_max));
   if (dirs_max > 0) {
     c->jout = (double*)alloc(sizeof(double) * (size_t)n_max * n_max);
@@ -2691,14 +2822,14 @@ dmpt_status dmpt_bench_product(dmpt_ctx c, int64_t N, dmpt_prec prec, int varian
   if (!c || !ms) return DMPT_ERR_ARG;
   if (N < 1 || N > c->n_max) return fail(c, DMPT_ERR_ARG, "N must lie in [1, n_max]");
   if (reps < 1 || reps > 100000) return fail(c, DMPT_ERR_ARG, "reps must lie in [1, 100000]");
-  if (prec < DMPT_FP64 || prec > DMPT_BF16X6) return fail(c, DMPT_ERR_ARG, "unknown precision");
+  if (prec < DMPT_FP64 || prec > DMPT_INT8X13) return fail(c, DMPT_ERR_ARG, "unknown precision");
   const Engine eng = engine_of(prec);
   if (variant < 0 || variant >= gemm_variants(eng, acc64_of(c, eng)))
     return fail(c, DMPT_ERR_ARG, "no such kernel variant for this precision");
   dmpt_options o = c->opt;
   o.prec = prec;
   o.refine = 0;
-  if (esize_needed(o) != c->esize || planes_needed(o) > c->planes)
+  if (esize_needed(o) != c->esize || planes_needed(o) > c->planes || (q8_needed(o) && !c->q8))
     return fail(c, DMPT_ERR_NOMEM, "precision needs a different workspace than the context holds");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, DMPT_ERR_HIP, "hipSetDevice failed");
   ENTER(c);
@@ -2723,6 +2854,11 @@ dmpt_status dmpt_bench_product(dmpt_ctx c, int64_t N, dmpt_prec prec, int varian
   a.partials = c->d_part;
   a.acc64 = acc64_of(c, k.eng);
   a.variant = variant;
+  if (k.eng == Engine::I8S4) {
+    if (k.Np > kQ8MaxK) return fail(c, DMPT_ERR_UNSUPPORTED, "int8 products need N <= 32768");
+    STCHK(q8_operand(k, a.X, 1));
+    STCHK(q8_operand(k, a.Y, 1));
+  }
   hipEvent_t e0, e1;
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
@@ -2766,6 +2902,7 @@ dmpt_prec prec_of(Engine e) {
     case Engine::F32: return DMPT_FP32;
     case Engine::BF16S2: return DMPT_BF16X3;
     case Engine::BF16S3: return DMPT_BF16X6;
+    case Engine::I8S4: return DMPT_INT8X13;
   }
   return DMPT_FP64;
 }
@@ -2835,7 +2972,7 @@ dmpt_status tune_engine(dmpt_ctx c, Engine eng, int64_t N, int* chosen) {
 int context_engines(dmpt_ctx c, Engine* out) {
   int n = 0;
   out[n++] = engine_of(c->opt.prec);
-  if (c->opt.prec == DMPT_BF16X3 && c->opt.refine) out[n++] = Engine::BF16S3;
+  if (c->opt.prec == DMPT_BF16X3 && c->opt.refine) out[n++] = refine_engine(c->opt);
   return n;
 }
 
@@ -2867,7 +3004,7 @@ dmpt_status dmpt_autotune(dmpt_ctx c, int64_t N, int* variant) {
 dmpt_status dmpt_set_variant(dmpt_ctx c, int64_t N, dmpt_prec prec, int variant) {
   if (!c) return DMPT_ERR_ARG;
   if (N < 1 || N > c->n_max) return fail(c, DMPT_ERR_ARG, "N must lie in [1, n_max]");
-  if (prec < DMPT_FP64 || prec > DMPT_BF16X6) return fail(c, DMPT_ERR_ARG, "unknown precision");
+  if (prec < DMPT_FP64 || prec > DMPT_INT8X13) return fail(c, DMPT_ERR_ARG, "unknown precision");
   const Engine eng = engine_of(prec);
   if (variant < 0 || variant >= gemm_variants(eng, acc64_of(c, eng)))
     return fail(c, DMPT_ERR_ARG, "no such kernel variant for this precision");
@@ -2879,7 +3016,7 @@ dmpt_status dmpt_get_variant(dmpt_ctx c, int64_t N, dmpt_prec prec, int* variant
                              int name_len) {
   if (!c || !variant) return DMPT_ERR_ARG;
   if (N < 1) return fail(c, DMPT_ERR_ARG, "N must be >= 1");
-  if (prec < DMPT_FP64 || prec > DMPT_BF16X6) return fail(c, DMPT_ERR_ARG, "unknown precision");
+  if (prec < DMPT_FP64 || prec > DMPT_INT8X13) return fail(c, DMPT_ERR_ARG, "unknown precision");
   const Engine eng = engine_of(prec);
   *variant = variant_for(c, eng, padded(N));
   if (tuned) *tuned = is_tuned(c, eng, padded(N)) ? 1 : 0;
@@ -3307,7 +3444,7 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
   int nph = 0;
   if (two_phase)
     phases[nph++] = {Engine::BF16S2, kPhaseATolCg, kPhaseATolOcc};
-  phases[nph++] = {two_phase ? Engine::BF16S3 : k.eng, c->opt.tol_cg, c->opt.tol_occ};
+  phases[nph++] = {two_phase ? refine_engine(c->opt) : k.eng, c->opt.tol_cg, c->opt.tol_occ};
   int ph = 0;
   double occ = 0;
   int it = 0;
@@ -3487,8 +3624,9 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
     bk.back().xmax = std::max(bk.back().xmax, xs[slot_sys[i]]);
   }
   // the batch's product engine; with options.autotune every bucket size is tuned first
-  const Engine eng = (c->opt.prec == DMPT_BF16X3 && c->opt.refine) ? Engine::BF16S3
+  const Engine eng = (c->opt.prec == DMPT_BF16X3 && c->opt.refine) ? refine_engine(c->opt)
                                                                     : engine_of(c->opt.prec);
+  if (eng == Engine::I8S4) return fail(c, DMPT_ERR_UNSUPPORTED, "the batched solve has no int8 products");
   if (c->opt.autotune)
     for (auto& b : bk)
       if (!is_tuned(c, eng, b.Np)) STCHK(tune_engine(c, eng, std::min<int64_t>(b.Np, c->n_max), nullptr));
@@ -3879,6 +4017,7 @@ dmpt_status dmpt_backward(dmpt_ctx c, int64_t N, const double* H0, double beta, 
   }
   reset_stats(c);
   Call k = make_call(c, N, true);
+  if (k.eng == Engine::I8S4) return fail(c, DMPT_ERR_UNSUPPORTED, "the adjoint has no int8 products");
   const int ck = std::max(1, std::min(c->opt.ckpt_every, n));
   dmpt_status r = adjoint_impl<double>(k, H0, beta, mu, n, Abar, G, ck);
   if (r != DMPT_OK) return r;

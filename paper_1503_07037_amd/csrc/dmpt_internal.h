@@ -20,14 +20,42 @@ constexpr int kPad = 128;
 inline int64_t padded(int64_t n) { return (n + kPad - 1) / kPad * kPad; }
 
 // Product engines (see gemm.hip).
-enum class Engine : int { F64 = 0, F32 = 1, BF16S2 = 2, BF16S3 = 3 };
+enum class Engine : int { F64 = 0, F32 = 1, BF16S2 = 2, BF16S3 = 3, I8S4 = 4 };
+constexpr int kEngines = 5;
 
+// BF16 planes per operand (the int8 engine keeps its slices apart, see q8_off).
 inline int engine_planes(Engine e) {
   return e == Engine::BF16S2 ? 2 : (e == Engine::BF16S3 ? 3 : 0);
 }
+// Matrix-core products per logical product.
 inline int engine_terms(Engine e) {
-  return e == Engine::BF16S2 ? 3 : (e == Engine::BF16S3 ? 6 : 1);
+  return e == Engine::BF16S2 ? 3 : (e == Engine::BF16S3 ? 6 : (e == Engine::I8S4 ? 13 : 1));
 }
+
+// Int8 slices of the I8S4 engine.  A member x (Np x Np, FP64 master) with
+// m = max |x| is stored as x = q (d0 + d1 / 254 + d2 / 254^2 + d3 / 254^3),
+// q = m / 127, every digit a signed int8 in [-127, 127] (each digit rounds
+// the scaled remainder of the ones before it to the nearest integer, so the
+// remainder stays within 1/2 and 254 times it fits the next digit).  Slice
+// s of the 32 x 32 block (row / 32, col / 32) is 1 KB at
+// ((row / 32) * (Np / 32) + col / 32) * 4 + s KB; inside it element (r, c)
+// sits at ((c / 16) * 32 + r) * 16 + c % 16: the operand order of
+// v_mfma_i32_32x32x32_i8 (lane l holds row l % 32 and 16 consecutive k of
+// half l / 32), so a wave moves a slice block as 64 consecutive 16-byte
+// pieces.  A member takes 4 Np^2 bytes; its q sits in a separate FP64 array.
+constexpr int kQ8Slices = 4;
+constexpr double kQ8Base = 254.0;
+__host__ __device__ inline int64_t q8_off(int64_t row, int64_t col, int64_t Np, int s) {
+  return ((((row >> 5) * (Np >> 5) + (col >> 5)) * kQ8Slices + s) << 10) + ((((col >> 4) & 1) << 5) + (row & 31)) * 16 +
+         (col & 15);
+}
+// Largest inner dimension whose int32 sums stay exact: four digit products
+// of weight 3, each at most 127^2 per term.  The products kept are the
+// thirteen of weight p + q <= 4: without (2, 2) the square of the third digit
+// would be missing from every diagonal entry of a product of a matrix with
+// itself (a one-signed error that traces add up), and (1, 3), (3, 1) bring the
+// remaining truncation to 254^-5 of the operands' scales.
+constexpr int64_t kQ8MaxK = 32768;
 
 // BF16 plane layout of an Np x Np member (Np a multiple of 32): blocks of
 // 32 rows x 16 columns, 512 elements (1 KB) each; block (row / 32, col / 16)
@@ -55,6 +83,8 @@ inline int64_t plane_np(int64_t n) {
 struct BOp {
   const void* m = nullptr;
   const uint16_t* pl[3] = {nullptr, nullptr, nullptr};
+  const int8_t* q8 = nullptr;  // I8S4: int8 slices of the member (4 stride bytes apart)
+  const double* qs = nullptr;  // I8S4: q of the member (one double apart)
   int64_t stride = 0;
   int div = 1;
 };
@@ -115,6 +145,14 @@ hipError_t sym_combine(const Tin* in, int64_t ldi, int64_t si, int64_t N, int64_
 template <class T>
 hipError_t transpose(const T* in, int64_t Np, int64_t stride, T* out, uint16_t* const* planes,
                      int nplanes, int batch, hipStream_t s);
+
+// Int8 slices (I8S4) of `batch` FP64 members x + z sx (Np x Np): block maxima
+// of |x| into part[z * nb ..] (nb = q8_blocks(Np)), then every block of the
+// slicing kernel reduces them to the member's max, writes q to qs[z] and its
+// share of the slices to q8 + z sq (bytes).
+int q8_blocks(int64_t Np);
+hipError_t quantize_q8(const double* x, int64_t sx, int64_t Np, int batch, double* part, int8_t* q8, int64_t sq,
+                       double* qs, const int* active, hipStream_t s);
 
 // Split a master matrix into BF16 planes (batched).
 hipError_t split_planes(const double* x, int64_t n_elems, int64_t sx, uint16_t* const* planes,

@@ -701,6 +701,98 @@ __global__ __launch_bounds__(kT) void k_lin_axpy(double* P1, const double* PJ, i
     P1[i] -= dl * PJ[i];
 }
 
+// ---------------------------------------------------------------- int8 slices (I8S4)
+// Largest |x| of a block; any NaN or infinity makes it infinite, so the
+// member's q becomes infinite and its products non-finite.
+__device__ inline double block_max(double v) {
+  __shared__ double red[kT / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double m = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) m = fmax(m, red[i]);
+  return m;
+}
+
+__global__ __launch_bounds__(kT) void k_amax(const double* __restrict__ x, int64_t sx, int64_t n,
+                                             double* __restrict__ part, int nb, const int* active) {
+  const int z = blockIdx.y;
+  if (active && !active[z]) return;
+  const double* xm = x + (int64_t)z * sx;
+  double m = 0.0;
+  bool bad = false;
+  for (int64_t i = ((int64_t)blockIdx.x * kT + threadIdx.x) * 2; i < n; i += (int64_t)gridDim.x * kT * 2) {
+    const d2v v = *(const d2v*)(xm + i);
+    const double a0 = fabs(v.x), a1 = fabs(v.y);
+    bad |= !(a0 <= 1.0e308) || !(a1 <= 1.0e308);
+    m = fmax(m, fmax(a0, a1));
+  }
+  m = block_max(bad ? INFINITY : m);
+  if (threadIdx.x == 0) part[(int64_t)z * nb + blockIdx.x] = m;
+}
+
+// Pack the low byte of eight digits into two words (byte e of word e / 4).
+__device__ inline uint32_t pack4(const int* d) {
+  return (uint32_t)(d[0] & 0xff) | ((uint32_t)(d[1] & 0xff) << 8) | ((uint32_t)(d[2] & 0xff) << 16) |
+         ((uint32_t)(d[3] & 0xff) << 24);
+}
+
+// One 16-element piece per thread and pass: piece u of a member is lane
+// u % 64 of 32 x 32 block u / 64 (block row major), i.e. row
+// 32 (block row) + l % 32, columns 32 (block col) + 16 (l / 32) .. + 15, and
+// its four slices go to the four 1 KB slice blocks of that block at byte 16 l.
+__global__ __launch_bounds__(kT) void k_quant(const double* __restrict__ x, int64_t sx, int64_t Np,
+                                              const double* __restrict__ part, int nb, int8_t* __restrict__ q8,
+                                              int64_t sq, double* __restrict__ qs, const int* active) {
+  const int z = blockIdx.y;
+  if (active && !active[z]) return;
+  __shared__ double sm;
+  double m = 0.0;
+  for (int i = threadIdx.x; i < nb; i += kT) m = fmax(m, part[(int64_t)z * nb + i]);
+  m = block_max(m);
+  if (threadIdx.x == 0) sm = m;
+  __syncthreads();
+  m = sm;
+  const double inv = (m > 0.0 && m <= 1.0e308) ? 127.0 / m : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) qs[z] = m / 127.0;
+  const double* xm = x + (int64_t)z * sx;
+  int8_t* qm = q8 + (int64_t)z * sq;
+  const int64_t kbr = Np >> 5;
+  const int64_t pieces = kbr * kbr * 64;
+  for (int64_t u = (int64_t)blockIdx.x * kT + threadIdx.x; u < pieces; u += (int64_t)gridDim.x * kT) {
+    const int64_t blk = u >> 6;
+    const int l = (int)(u & 63);
+    const int64_t rb = blk / kbr, cb = blk - rb * kbr;
+    const double* src = xm + (rb * 32 + (l & 31)) * Np + cb * 32 + (l >> 5) * 16;
+    int d[kQ8Slices][16];
+#pragma unroll
+    for (int e = 0; e < 16; e += 2) {
+      const d2v v = *(const d2v*)(src + e);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        double r = (h ? v.y : v.x) * inv;
+#pragma unroll
+        for (int sl = 0; sl < kQ8Slices; ++sl) {
+          const double t = rint(r);
+          d[sl][e + h] = (int)t;
+          r = (r - t) * kQ8Base;
+        }
+      }
+    }
+#pragma unroll
+    for (int sl = 0; sl < kQ8Slices; ++sl) {
+      uint32_t w[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) w[q] = pack4(&d[sl][4 * q]);
+      uint32_t* dst = (uint32_t*)(qm + ((blk * kQ8Slices + sl) << 10) + l * 16);
+      *(uint4*)dst = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+  }
+}
+
 inline unsigned red_grid(int64_t n) {
   int64_t b = (n + kT * 8 - 1) / (kT * 8);
   if (b < 1) b = 1;
@@ -762,6 +854,22 @@ DMPT_SYM_INST(double, float)
 DMPT_SYM_INST(float, float)
 DMPT_SYM_INST(float, double)
 #undef DMPT_SYM_INST
+
+int q8_blocks(int64_t Np) { return (int)red_grid(Np * Np); }
+
+hipError_t quantize_q8(const double* x, int64_t sx, int64_t Np, int batch, double* part, int8_t* q8, int64_t sq,
+                       double* qs, const int* active, hipStream_t s) {
+  if (Np <= 0 || Np % 32 != 0 || batch < 1 || !x || !part || !q8 || !qs) return hipErrorInvalidValue;
+  const int64_t n = Np * Np;
+  const unsigned nb = red_grid(n);
+  hipLaunchKernelGGL(k_amax, dim3(nb, batch), dim3(kT), 0, s, x, sx, n, part, (int)nb, active);
+  const int64_t pieces = n / 16;
+  int64_t g = (pieces + 2 * kT - 1) / (2 * kT);
+  if (g > 65535) g = 65535;
+  hipLaunchKernelGGL(k_quant, dim3((unsigned)g, batch), dim3(kT), 0, s, x, sx, Np, part, (int)nb, q8, sq, qs,
+                     active);
+  return hipGetLastError();
+}
 
 hipError_t split_planes(const double* x, int64_t n, int64_t sx, uint16_t* const* planes, int64_t sp,
                         int nplanes, int batch, hipStream_t s) {

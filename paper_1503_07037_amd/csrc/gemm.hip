@@ -19,6 +19,11 @@
 //   BF16S2  x = x_hi + x_lo (BF16 splits): x_hi y_hi + x_hi y_lo + x_lo y_hi
 //   BF16S3  x = x_0 + x_1 + x_2: the six products x_p y_q with p + q <= 2
 //           (both BF16 engines use v_mfma_f32_32x32x16_bf16, FP32 accumulation)
+//   I8S4    x = q_x (d_0 + d_1 / 254 + d_2 / 254^2 + d_3 / 254^3), one q per
+//           matrix, int8 digits (q8_off): the thirteen products d_p e_q
+//           with p + q <= 4 on v_mfma_i32_32x32x32_i8, summed exactly in
+//           int32 (one accumulator per weight p + q), combined in FP64 at the
+//           end
 // Master copies (the operands of the FP64 and FP32 engines, C1, C2, W and C)
 // are FP64 for every engine.
 //
@@ -639,6 +644,185 @@ hipError_t launch_bf16_grouped(const GemmArgs* list, const int* start, int nprob
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ int8 slices
+// 128 x 128 output tile, NW waves (WM along m, NW / WM along n; wave (wm, wn)
+// owns (128 / WM) x (128 WM / NW) as 32 x 32 MFMA tiles), one int32
+// accumulator tile per weight w = p + q (0 .. 4) of the digit products.  The operands move as 1 KB slice
+// blocks in MFMA operand order (q8_off), through the same pipeline as the
+// split-BF16 kernel: two LDS stages of BK of k and one register stage.  The
+// int32 sums are exact over the whole inner dimension, so nothing is folded
+// during the k loop; the epilogue evaluates
+//   q_x q_y (A_0 + (A_1 + (A_2 + (A_3 + A_4 / 254) / 254) / 254) / 254)
+// in FP64 (A_w: the weight-w accumulator).
+typedef int i4v __attribute__((ext_vector_type(4)));
+typedef int i16v __attribute__((ext_vector_type(16)));
+
+template <int BK, int NW, int WM>
+__device__ __forceinline__ void gemm_i8_tile(const GemmArgs& a, int z, int bx, int nbx) {
+  constexpr int TM = 128;
+  constexpr int S = kQ8Slices;
+  constexpr int W = S + 1;            // weights 0 .. 4
+  constexpr int WN = NW / WM;         // waves along n
+  constexpr int FM = TM / (32 * WM);  // MFMA tiles per wave along m
+  constexpr int FN = TM / (32 * WN);  // MFMA tiles per wave along n
+  constexpr int RB = TM / 32;         // 32-row blocks of an operand tile
+  constexpr int KB = BK / 32;         // 32-wide k blocks of a stage
+  constexpr int NBLK = RB * KB;       // slice blocks per operand slice and stage
+  constexpr int SBLK = 2 * S * NBLK;  // per stage: [operand][slice][row block][k block]
+  constexpr int LOADS = SBLK / NW;
+  constexpr int SBYTES = SBLK * 1024;
+  static_assert(SBLK % NW == 0, "a stage must split evenly over the waves");
+  static_assert(FN >= 1, "at least one MFMA tile per wave along n");
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  __shared__ double red[NW];
+  if (a.active && !a.active[z]) return;
+  count_member(a, bx);
+  const int64_t Np = a.Np;
+  const int64_t kbr = Np >> 5;  // 32-wide blocks per block row
+  int tm, tn;
+  tile_coords(bx, (int)(Np / TM), (int)(Np / TM), tm, tn);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int zx = z / a.X.div, zy = z / a.Y.div;
+  const int8_t* xq = a.X.q8 + (int64_t)zx * a.X.stride * S;
+  const int8_t* yq = a.Y.q8 + (int64_t)zy * a.Y.stride * S;
+  const double scale = a.X.qs[a.X.stride ? zx : 0] * a.Y.qs[a.Y.stride ? zy : 0];
+  const int8_t* src[LOADS];
+  int dst[LOADS];
+#pragma unroll
+  for (int j = 0; j < LOADS; ++j) {
+    const int q = wave + NW * j;
+    const int op = q / (S * NBLK), sl = (q / NBLK) % S, b = q % NBLK;
+    const int rb = b / KB, kb = b % KB;
+    const int64_t brow = (int64_t)(op ? tn : tm) * RB + rb;
+    src[j] = (op ? yq : xq) + (((brow * kbr + kb) * S + sl) << 10) + lane * 16;
+    dst[j] = q * 1024 + lane * 16;
+  }
+  u4v stg[LOADS];
+  auto gload = [&](int kt) {
+    const int64_t koff = (int64_t)kt * KB * S * 1024;
+#pragma unroll
+    for (int j = 0; j < LOADS; ++j) stg[j] = *(const u4v*)(src[j] + koff);
+  };
+  auto swrite = [&](int st) {
+#pragma unroll
+    for (int j = 0; j < LOADS; ++j) *(u4v*)(smem + st * SBYTES + dst[j]) = stg[j];
+  };
+  i16v acc[W][FM][FN];
+#pragma unroll
+  for (int w = 0; w < W; ++w)
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[w][i][j][r] = 0;
+  const int nk = (int)(Np / BK);
+  gload(0);
+  swrite(0);
+  if (nk > 1) gload(1);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const unsigned char* sb = smem + (kt & 1) * SBYTES + lane * 16;
+#pragma unroll
+    for (int kk = 0; kk < KB; ++kk) {
+      // fragments in consumption order: X digit 0 and every Y digit first
+      i4v xa[S][FM], yb[S][FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+        xa[0][i] = __builtin_bit_cast(i4v, *(const u4v*)(sb + (((0 * NBLK) + (wm * FM + i) * KB + kk) << 10)));
+#pragma unroll
+      for (int q = 0; q < S; ++q)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          yb[q][j] = __builtin_bit_cast(
+              i4v, *(const u4v*)(sb + ((((S + q) * NBLK) + (wn * FN + j) * KB + kk) << 10)));
+#pragma unroll
+      for (int p = 1; p < S; ++p)
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+          xa[p][i] = __builtin_bit_cast(i4v, *(const u4v*)(sb + (((p * NBLK) + (wm * FM + i) * KB + kk) << 10)));
+      if (kk == 0 && kt + 1 < nk) {
+        swrite((kt + 1) & 1);
+        if (kt + 2 < nk) gload(kt + 2);
+      }
+      // X digit p against Y digits q = 0 .. 4 - p: consecutive products go to
+      // different accumulators
+#pragma unroll
+      for (int p = 0; p < S; ++p)
+#pragma unroll
+        for (int q = 0; q < S && p + q < W; ++q)
+#pragma unroll
+          for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+              acc[p + q][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[p][i], yb[q][j], acc[p + q][i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  const double rb = 1.0 / kQ8Base;
+  double dsum = 0.0;
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t row = (int64_t)tm * TM + wm * (TM / WM) + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int64_t col = (int64_t)tn * TM + wn * (TM / WN) + j * 32 + (lane & 31);
+        double v = (double)acc[W - 1][i][j][r];
+#pragma unroll
+        for (int w = W - 2; w >= 0; --w) v = v * rb + (double)acc[w][i][j][r];
+        epi<double>(a, z, row, col, v * scale, dsum);
+      }
+  if (a.W) {
+    const double s = block_sum(dsum, red);
+    if (tid == 0) a.partials[(int64_t)z * nbx + bx] = s;
+  }
+}
+
+template <int BK, int NW, int WM>
+__global__ __launch_bounds__(NW * 64) void k_gemm_i8(GemmArgs a) {
+  gemm_i8_tile<BK, NW, WM>(a, blockIdx.z, blockIdx.x, gridDim.x);
+}
+
+template <int BK, int NW, int WM>
+__global__ __launch_bounds__(NW * 64) void k_gemm_i8_grouped(const GemmArgs* __restrict__ list,
+                                                              const int* __restrict__ start, int nprob) {
+  int p = 0;
+  const int b = blockIdx.x;
+  while (p + 1 < nprob && b >= start[p + 1]) ++p;
+  const GemmArgs& a = list[p];
+  const int tiles = (int)((a.Np / 128) * (a.Np / 128));
+  const int local = b - start[p];
+  gemm_i8_tile<BK, NW, WM>(a, local / tiles, local % tiles, tiles);
+}
+
+template <int BK>
+constexpr size_t i8_lds() { return (size_t)2 * 2 * kQ8Slices * 4 * (BK / 32) * 1024; }
+
+template <int BK, int NW, int WM>
+hipError_t prepare_i8() {
+  hipError_t e = hipFuncSetAttribute((const void*)k_gemm_i8<BK, NW, WM>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)i8_lds<BK>());
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_gemm_i8_grouped<BK, NW, WM>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)i8_lds<BK>());
+}
+
+template <int BK, int NW, int WM>
+hipError_t launch_i8(const GemmArgs& a, dim3 grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_gemm_i8<BK, NW, WM>), grid, dim3(NW * 64), i8_lds<BK>(), s, a);
+  return hipGetLastError();
+}
+
+template <int BK, int NW, int WM>
+hipError_t launch_i8_grouped(const GemmArgs* list, const int* start, int nprob, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL((k_gemm_i8_grouped<BK, NW, WM>), dim3(blocks), dim3(NW * 64), i8_lds<BK>(), s, list, start,
+                     nprob);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 // Kernel variants of each engine, chosen per padded size by the autotuner
@@ -647,12 +831,14 @@ hipError_t launch_bf16_grouped(const GemmArgs* list, const int* start, int nprob
 //   FP32  0: BK 32, 8 waves  1: BK 16, 8 waves   2: BK 32, 4 waves
 //   split BF16  0: 256 x 256 tiles where Np allows (else 128)   1: 128 x 128 tiles
 //   (the 6-product kernel with FP64 slice sums has 128 x 128 tiles only)
+//   int8  0: BK 32, 8 waves of 32 x 64   1: BK 32, 8 waves of 64 x 32
 int gemm_variants(Engine eng, int acc64) {
   switch (eng) {
     case Engine::F64: return 3;
     case Engine::F32: return 3;
     case Engine::BF16S2: return 2;
     case Engine::BF16S3: return acc64 ? 1 : 2;
+    case Engine::I8S4: return 2;
   }
   return 1;
 }
@@ -661,7 +847,9 @@ const char* gemm_variant_name(Engine eng, int acc64, int v) {
   static const char* f64[3] = {"FP64 BK 8, 8 waves", "FP64 BK 16, 8 waves", "FP64 BK 8, 4 waves"};
   static const char* f32[3] = {"FP32 BK 32, 8 waves", "FP32 BK 16, 8 waves", "FP32 BK 32, 4 waves"};
   static const char* bf[2] = {"BF16 256 x 256 tiles", "BF16 128 x 128 tiles"};
+  static const char* i8[2] = {"int8 BK 32, 8 waves of 32 x 64", "int8 BK 32, 8 waves of 64 x 32"};
   if (v < 0 || v >= gemm_variants(eng, acc64)) return "invalid";
+  if (eng == Engine::I8S4) return i8[v];
   if (eng == Engine::F64) return f64[v];
   if (eng == Engine::F32) return f32[v];
   if (eng == Engine::BF16S3 && acc64) return "BF16 128 x 128 tiles, FP64 slice sums";
@@ -684,6 +872,8 @@ hipError_t gemm_prepare() {
   if ((e = prepare_bf16<3, 128, 32, 4>())) return e;
   if ((e = prepare_bf16<3, 128, 32, 8, 1>())) return e;
   if ((e = prepare_bf16<2, 256, 16, kWaves256>())) return e;
+  if ((e = prepare_i8<32, 8, 2>())) return e;
+  if ((e = prepare_i8<32, 8, 4>())) return e;
   return prepare_bf16<3, 256, 16, kWaves256>();
 }
 
@@ -699,6 +889,10 @@ hipError_t gemm(const GemmArgs& a, hipStream_t s) {
   const int edge = gemm_tile_edge(a.eng, a.Np, a.variant, a.acc64);
   const dim3 grid((unsigned)gemm_tiles(a.eng, a.Np, a.variant, a.acc64), 1, (unsigned)a.batch);
   switch (a.eng) {
+    case Engine::I8S4:
+      if (a.Np > kQ8MaxK || !a.X.q8 || !a.Y.q8 || !a.X.qs || !a.Y.qs) return hipErrorInvalidValue;
+      if (a.variant == 1) return launch_i8<32, 8, 2>(a, grid, s);
+      return launch_i8<32, 8, 4>(a, grid, s);
     case Engine::F64:
       if (a.variant == 1) hipLaunchKernelGGL((k_gemm_f64<16, 8>), grid, dim3(8 * 64), 0, s, a);
       else if (a.variant == 2) hipLaunchKernelGGL((k_gemm_f64<8, 4>), grid, dim3(4 * 64), 0, s, a);
@@ -727,6 +921,9 @@ hipError_t gemm_grouped(Engine eng, int variant, int acc64, int edge, const Gemm
                         int nprob, int blocks, hipStream_t s) {
   if (nprob < 1 || blocks < 1 || variant < 0 || variant >= gemm_variants(eng, acc64)) return hipErrorInvalidValue;
   switch (eng) {
+    case Engine::I8S4:
+      if (variant == 1) return launch_i8_grouped<32, 8, 2>(list, start, nprob, blocks, s);
+      return launch_i8_grouped<32, 8, 4>(list, start, nprob, blocks, s);
     case Engine::F64:
       if (variant == 1) hipLaunchKernelGGL((k_gemm_f64_grouped<16, 8>), dim3(blocks), dim3(8 * 64), 0, s, list, start, nprob);
       else if (variant == 2) hipLaunchKernelGGL((k_gemm_f64_grouped<8, 4>), dim3(blocks), dim3(4 * 64), 0, s, list, start, nprob);

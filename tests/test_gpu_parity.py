@@ -132,13 +132,15 @@ def test_third_order_canonical_fp64(dm, schedule):
             assert abs(st[key][z] - ref[key][z]) < 1e-9 * max(1.0, abs(ref[key][z])), (key, z)
 
 
-def test_third_order_canonical_bf16x6(dm):
-    """Third order through the 6-product split with FP64 slice sums: <= 1e-6 (normalised)."""
-    print("case canonical bf16x6 order=3", flush=True)
+@pytest.mark.parametrize("prec", ["bf16x6", "int8x13"])
+def test_third_order_canonical_low_precision(dm, prec):
+    """Third order through the 6-product split with FP64 slice sums and through the 13-product int8
+    slices: <= 1e-6 (normalised)."""
+    print(f"case canonical {prec} order=3", flush=True)
     c = workloads.config("chain128")
     h3 = [_sym(np.random.default_rng(33), c["N"], 0.02)]
     ref = oracle.canonical_response(c["H0"], c["H1"], None, c["beta"], c["Ne"], c["n"], order=3, h3s=h3)
-    with dm.Context(c["N"], dirs_max=1, prec="bf16x6") as ctx:
+    with dm.Context(c["N"], dirs_max=1, prec=prec) as ctx:
         r = ctx.mu_newton(T(c["H0"]), [T(h) for h in c["H1"]], None, beta=c["beta"], Ne=c["Ne"],
                           n=c["n"], order=3, H3=[T(h3[0])])
     P0, P1, P2, mu, st = r
@@ -197,6 +199,8 @@ def test_chain128_taylor_guess_fp64(dm, chain128_ref):
     ("bf16x6", {}, 1e-6),              # 6-product split, FP64 iterates
     ("bf16x3", {}, 5e-5),              # 3-product split alone
     ("bf16x3", {"refine": 1}, 1e-6),   # 3-product passes, then the 6-product refinement
+    ("int8x13", {}, 1e-6),             # int8 slices, exact int32 sums
+    ("bf16x3", {"refine": 2}, 1e-6),   # 3-product passes, then int8 slices
 ])
 def test_chain128_canonical_low_precision(dm, chain128_ref, prec, extra, tol):
     print(f"case chain128 canonical {prec} {extra}", flush=True)
@@ -235,6 +239,27 @@ def test_ragged_multi_direction_fp64(dm, N, d, schedule):
         # Eq. Resp_0 observables: Tr(H2 P1), Omega^(1..3)
         for key in ("tr_h1p0", "tr_h2p1", "omega1", "omega2", "omega3"):
             assert abs(st[key][z] - ref[key][z]) < 1e-10 * max(1, abs(ref[key][z])), (key, z)
+
+
+@pytest.mark.parametrize("N,d", [(250, 3), (1000, 2)])
+def test_ragged_multi_direction_int8(dm, N, d):
+    """Int8 slices with N not a multiple of the tile (ragged last tile and zero padding inside the
+    slices), several directions, non-zero H2: every element against the oracle at 1e-6."""
+    print(f"case ragged canonical int8x13 N={N} d={d}", flush=True)
+    rng = np.random.default_rng(N)
+    h0 = workloads.banded(N, 9, bandwidth=24, decay=8.0)
+    grid = [np.arange(N) % 7 - 3.0, (np.arange(N) // 7) % 5 - 2.0, np.sin(np.arange(N))]
+    h1 = [np.diag(g) for g in grid][:d]
+    h2 = [_sym(rng, N, 0.02) if i == 0 else None for i in range(d)]
+    beta, n, Ne = 12.0, 22, N / 2.0 - 3.0
+    ref = oracle.canonical_response(h0, h1, h2, beta, Ne, n, order=2)
+    with dm.Context(N, dirs_max=d, prec="int8x13") as ctx:
+        P0, P1, P2, mu, st = ctx.mu_newton(T(h0), [T(h) for h in h1],
+                                           [T(h) if h is not None else None for h in h2],
+                                           beta=beta, Ne=Ne, n=n, order=2)
+    e0, e1, e2 = errs(P0, P1, P2, ref)
+    print(f"  errs {e0:.2e} {e1:.2e} {e2:.2e} newton={st['newton_iters']} flags={st['flags']}")
+    assert e0 < 1e-6 and e1 < 1e-6 and e2 < 1e-6
 
 
 def test_single_site(dm):
@@ -324,7 +349,7 @@ def test_nonorthogonal_canonical(dm, prec, tol):
 
 # ------------------------------------------------------------------ Newton-Schulz shared inverse
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("bf16x6", 1e-6), ("fp32", 1e-6)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("bf16x6", 1e-6), ("fp32", 1e-6), ("int8x13", 1e-6)])
 def test_newton_schulz_solver_canonical(dm, chain128_ref, prec, tol):
     """The shared-inverse solver (one inverse of T' per step for all orders) reaches the oracle."""
     print(f"case newton-schulz {prec}", flush=True)
@@ -369,7 +394,7 @@ def cubic2048_ref():
 
 @pytest.mark.timeout(300)
 @pytest.mark.parametrize("prec,refine,tol", [("fp64", 0, 1e-10), ("fp32", 0, 1e-6), ("bf16x6", 0, 1e-6),
-                                             ("bf16x3", 1, 1e-6)])
+                                             ("bf16x3", 1, 1e-6), ("int8x13", 0, 1e-6), ("bf16x3", 2, 1e-6)])
 def test_cubic2048_all_forms(dm, cubic2048_ref, prec, refine, tol):
     """16 x 16 x 8 simple-cubic lattice, beta 20, n 25, orders 0-2: every element of P0, P1 and P2
     against the oracle (P0 absolute, P1 and P2 relative to max |P^(k)|), every form."""
@@ -389,13 +414,15 @@ def test_cubic2048_all_forms(dm, cubic2048_ref, prec, refine, tol):
 # ------------------------------------------------------------------ N = 8192 banded (the benchmark)
 
 @pytest.mark.timeout(600)
-def test_banded8192_benchmark_configuration(dm):
-    """The benchmark's workload and launch configuration (bf16x3 passes, bf16x6 refinement with
-    FP64 slice accumulation, orders 0-2, 3 directions) against the oracle's stored samples."""
-    print("case banded8192 mixed", flush=True)
+@pytest.mark.parametrize("refine", [2, 1])
+def test_banded8192_benchmark_configuration(dm, refine):
+    """The benchmark's workload and launch configuration (bf16x3 passes, then the int8-slice
+    refinement (2) or the bf16x6 refinement with FP64 slice accumulation (1); orders 0-2,
+    3 directions) against the oracle's stored samples and whole row blocks."""
+    print(f"case banded8192 mixed refine={refine}", flush=True)
     c = workloads.config("banded8192")
     g = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "banded8192_samples.npz"))
-    with dm.Context(c["N"], dirs_max=len(c["H1"]), prec="bf16x3", refine=1, acc64=1) as ctx:
+    with dm.Context(c["N"], dirs_max=len(c["H1"]), prec="bf16x3", refine=refine, acc64=1) as ctx:
         P0, P1, P2, mu, st = ctx.mu_newton(T(c["H0"]), [T(h) for h in c["H1"]], None, beta=c["beta"],
                                            Ne=c["Ne"], n=c["n"], order=2)
     ii = torch.as_tensor(g["i"], device=P0.device)
@@ -425,7 +452,7 @@ def test_banded8192_benchmark_configuration(dm):
 
 # ------------------------------------------------------------------ checks (check = 1)
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("bf16x6", 1e-6)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("bf16x6", 1e-6), ("int8x13", 1e-6)])
 def test_final_checks_against_oracle(dm, chain128_ref, prec, tol):
     """check = 1: the commutator ||H0 P0 - P0 H0||_F, the idempotency Tr[P0 (I - P0)] and the output
     asymmetry of the returned P0, against the same quantities of the oracle's P0."""
@@ -474,3 +501,19 @@ def test_inputs_written_on_the_callers_stream_are_read_in_order(dm):
                 err = float(np.abs(P0.cpu().numpy() - ref).max())
         print(f"  side stream {side}: err {err:.2e}")
         assert err < 1e-12
+
+
+def test_int8_paths_without_int8_products_say_so(dm):
+    """The batched solve and the adjoint have no int8 products: they return DMPT_ERR_UNSUPPORTED
+    instead of computing with another engine."""
+    print("case int8 unsupported paths", flush=True)
+    from paper_1503_07037_amd import _lib as L
+    N, beta, n = 128, 10.0, 20
+    h0 = workloads.chain_1d(N, 3)
+    with dm.Context(N, dirs_max=1, prec="int8x13") as ctx:
+        with pytest.raises(dm.DMPTError) as e:
+            ctx.mu_newton_batched([T(h0)], [[T(np.diag(np.arange(N) - N / 2.0))]], [beta], [N / 2.0], n=n, order=1)
+        assert e.value.status == L.DMPT_ERR_UNSUPPORTED
+        with pytest.raises(dm.DMPTError) as e:
+            ctx.backward(T(h0), beta=beta, Ne=N / 2.0, n=n, Abar=T(np.eye(N)))
+        assert e.value.status == L.DMPT_ERR_UNSUPPORTED
