@@ -6,10 +6,10 @@ Workload (default): the dense random-banded Hamiltonian, N = 8192 (bandwidth
 n = 30 recursion steps, three diagonal dipole perturbations (x, y, z of a
 32 x 16 x 16 grid), orders 0-2 (polarisability and hyperpolarisability), the
 canonical Newton loop of Algorithm 1: split-BF16 (3-product) matrix products
-with FP32 accumulation until mu0 is close, then the final passes (order 0
-and the linear schedule's order-1 and order-2 passes) with int8-slice
-products (four signed int8 digits per operand, thirteen digit products
-summed exactly in int32).  Inputs are synthetic, seeded, already resident in HBM
+with FP32 accumulation until mu0 is close, then the final passes (one order-0
+pass and the linear schedule's order-1 and order-2 passes) with int8-slice
+products (each operand as one scale per matrix times four signed int8 digits,
+the thirteen digit products of weight <= 4 summed exactly in int32).  Inputs are synthetic, seeded, already resident in HBM
 when the timed region starts.
 
 One step = one complete canonical solve (dmpt_mu_newton): every Newton pass,
@@ -51,8 +51,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # dense matrix-core peaks of an MI355X per engine (int8: TOP/s)
-PEAKS_TFLOPS = {"bf16x3": 2500.0, "bf16x6": 2500.0, "int8x13": 5000.0, "fp32": 157.3, "fp64": 78.6}
-DTYPE = {"bf16x3": "bf16", "bf16x6": "bf16", "int8x13": "i8", "fp32": "f32", "fp64": "f64"}
+PEAKS_TFLOPS = {"bf16x3": 2500.0, "bf16x6": 2500.0, "int8x13": 5000.0, "int8x6": 5000.0, "fp32": 157.3,
+                "fp64": 78.6}
+DTYPE = {"bf16x3": "bf16", "bf16x6": "bf16", "int8x13": "i8", "int8x6": "i8", "fp32": "f32", "fp64": "f64"}
 REFINE_NAME = {1: "bf16x6", 2: "int8x13"}
 
 
@@ -70,8 +71,8 @@ def parse():
     ap.add_argument("--tol-cg", type=float, default=0.0)
     ap.add_argument("--tol-occ", type=float, default=0.0)
     ap.add_argument("--refine", type=int, default=-1, choices=[-1, 0, 1, 2],
-                    help="bf16x3: finish with the int8-slice passes (2, default), the 6-product "
-                         "split-BF16 passes (1) or not at all (0)")
+                    help="int8x6 / bf16x3: finish with the int8 13-product passes (2, default), the "
+                         "6-product split-BF16 passes (1) or not at all (0)")
     ap.add_argument("--acc64", type=int, default=1,
                     help="6-product products: FP32 per 32-wide k slice, FP64 across slices (default 1)")
     ap.add_argument("--solver", default="cg", choices=["cg", "ns"],
@@ -418,7 +419,7 @@ def main():
     H0 = torch.tensor(c["H0"], device=dev)
     H1 = [torch.tensor(h, device=dev) for h in c["H1"]]
     torch.cuda.synchronize()
-    refine = (2 if args.prec == "bf16x3" else 0) if args.refine < 0 else args.refine
+    refine = (2 if args.prec in ("bf16x3", "int8x6") else 0) if args.refine < 0 else args.refine
     ctx = dm.Context(N, dirs_max=d, prec=args.prec, tol_cg=args.tol_cg, tol_occ=args.tol_occ,
                      refine=refine, acc64=args.acc64, solver=args.solver)
 
@@ -470,7 +471,7 @@ def main():
                    + (", 6-product sums FP64 across 32-wide k slices" if args.acc64 and
                       (refine == 1 or args.prec == "bf16x6") else "")
                    + (", int8 digit products summed exactly in int32" if
-                      (refine == 2 or args.prec == "int8x13") else ""),
+                      (refine == 2 or args.prec.startswith("int8")) else ""),
                    "parallelism": "single GPU"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,

@@ -70,10 +70,12 @@ typedef enum {
   DMPT_BF16X6 = 3,  /* three-way BF16 split, the six cross products with p + q <= 2; with
                        options.acc64 each 32-wide slice of the inner index is summed in FP32
                        and the slices in FP64 */
-  DMPT_INT8X13 = 4  /* each operand as q (d0 + d1/254 + d2/254^2 + d3/254^3) with one FP64 q per
+  DMPT_INT8X13 = 4, /* each operand as q (d0 + d1/254 + d2/254^2 + d3/254^3) with one FP64 q per
                        matrix (its largest |entry| / 127) and signed int8 digits; the thirteen
                        digit products with p + q <= 4 on int8 MFMA, summed exactly in int32 over
                        the whole inner index (N <= 32768) and combined in FP64 */
+  DMPT_INT8X6 = 5   /* the same int8 digits, the first three only: the six products with p + q <= 2
+                       (exact int32 sums, no accumulation bias in traces; ~1e-6) */
 } dmpt_prec;
 
 /* Per-step linear solver for T' Y = R, T' = I + 4 D^2 (2 T of Algorithm 1). */
@@ -102,8 +104,8 @@ typedef struct {
   double tol_cg;        /* relative residual of each solve; <= 0: default for prec */
   int max_newton;       /* Newton passes (default 50) */
   int max_cg;           /* CG iterations per solve (default 60) */
-  int refine;           /* BF16X3 only: after convergence, redo the last passes in BF16X6 (1), in
-                           INT8X13 (2) or not (0) */
+  int refine;           /* BF16X3 and INT8X6: after convergence, redo the last passes in BF16X6 (1),
+                           in INT8X13 (2) or not (0) */
   int ckpt_every;       /* adjoint: keep every ckpt_every-th iterate, recompute the rest (default 5) */
   int check;            /* 1: compute the commutator and idempotency checks at the end of a call */
   int staged;           /* 1: converge mu0 with order-0 passes first, then run full passes (same fixed point) */
@@ -344,16 +346,16 @@ typedef struct {
   double mfma_flops;     /* matrix-core flops of those launches (every split product counted) */
   double useful_flops;   /* 2 N^3 per logical product and batch member */
   /* the same, per product engine: [0] FP64, [1] FP32, [2] BF16 3-product, [3] BF16 6-product,
-     [4] int8 13-product (its mfma_flops are int8 operations) */
-  int64_t eng_launches[5];
-  double eng_ms[5];
-  double eng_mfma_flops[5];
+     [4] int8 13-product, [5] int8 6-product (their mfma_flops are int8 operations) */
+  int64_t eng_launches[6];
+  double eng_ms[6];
+  double eng_mfma_flops[6];
   /* algorithmic HBM bytes of those launches: every operand member read once
      (BF16 planes or int8 slices for the split engines, masters otherwise; C1, C2 and W
      masters), C's master and planes written once */
-  double eng_bytes[5];
+  double eng_bytes[6];
   /* algorithmic flops of those launches: 2 N^3 per logical product and member */
-  double eng_useful_flops[5];
+  double eng_useful_flops[6];
 } dmpt_profile_data;
 
 dmpt_status dmpt_profile(dmpt_ctx ctx, int enable);
@@ -380,7 +382,7 @@ dmpt_status dmpt_congruence(dmpt_ctx ctx, int64_t N, const double* Z, const doub
  *   DMPT_BF16X3, DMPT_BF16X6 (options.acc64 = 0)
  *                0: 256 x 256 output tiles where the padded size allows   1: 128 x 128 tiles
  *   DMPT_BF16X6 with options.acc64 = 1: 0 only (128 x 128 tiles, FP64 slice sums)
- *   DMPT_INT8X13 0: 128 x 128 tiles, 8 waves of 32 x 64   1: 8 waves of 64 x 32
+ *   DMPT_INT8X13, DMPT_INT8X6  0: 128 x 128 tiles, 8 waves of 32 x 64   1: 8 waves of 64 x 32
  * Every variant computes the same products; they differ in speed. */
 
 /* Time the matrix-product kernel alone: `reps` products C = X Y^T of size N

@@ -25,7 +25,7 @@ STATUS_NAMES = {
     DMPT_ERR_UNSUPPORTED: "DMPT_ERR_UNSUPPORTED",
 }
 
-PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3, "int8x13": 4}
+PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3, "int8x13": 4, "int8x6": 5}
 SOLVER = {"cg": 0, "ns": 1}
 GUESS = {"prev": 0, "taylor": 1}
 MAX_DIRS = 8
@@ -100,9 +100,9 @@ class SparseStats(ctypes.Structure):
 class ProfileData(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double),
                 ("mfma_flops", ctypes.c_double), ("useful_flops", ctypes.c_double),
-                ("eng_launches", ctypes.c_int64 * 5), ("eng_ms", ctypes.c_double * 5),
-                ("eng_mfma_flops", ctypes.c_double * 5), ("eng_bytes", ctypes.c_double * 5),
-                ("eng_useful_flops", ctypes.c_double * 5)]
+                ("eng_launches", ctypes.c_int64 * 6), ("eng_ms", ctypes.c_double * 6),
+                ("eng_mfma_flops", ctypes.c_double * 6), ("eng_bytes", ctypes.c_double * 6),
+                ("eng_useful_flops", ctypes.c_double * 6)]
 
 
 EXPORTS = [

@@ -150,7 +150,7 @@ class Context:
         """Totals since the last reset: launches, ms, mfma_flops, useful_flops, and per engine."""
         d = L.ProfileData()
         self._raise(self.lib.dmpt_profile_get(self.h, ctypes.byref(d)))
-        names = ["fp64", "fp32", "bf16x3", "bf16x6", "int8x13"]
+        names = ["fp64", "fp32", "bf16x3", "bf16x6", "int8x13", "int8x6"]
         return dict(launches=d.launches, ms=d.ms, mfma_flops=d.mfma_flops,
                     useful_flops=d.useful_flops,
                     engines={names[i]: dict(launches=d.eng_launches[i], ms=d.eng_ms[i],

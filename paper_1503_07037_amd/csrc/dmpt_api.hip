@@ -40,7 +40,7 @@ constexpr int kIterSlot = 512;
 struct Group {
   void* m = nullptr;             // master base, members at m + z * stride elements
   uint16_t* pl[3] = {nullptr, nullptr, nullptr};
-  int8_t* q8 = nullptr;          // int8 slices (I8S4), members 4 stride bytes apart
+  int8_t* q8 = nullptr;          // int8 slices (I8S4, I8S3), members 4 stride bytes apart
   double* qs = nullptr;          // their q, one per member
   int count = 0;
 };
@@ -91,7 +91,7 @@ struct dmpt_ctx_s {
   dmpt_options opt{};
   size_t esize = 8;              // master element size of the workspace
   int planes = 0;                // BF16 planes per operand allocated
-  bool q8 = false;               // operand groups carry int8 slices (I8S4)
+  bool q8 = false;               // operand groups carry int8 slices (I8S4, I8S3)
   std::vector<Q8Reg> q8reg;
   double* d_qpart = nullptr;     // block maxima of the slicing launches
   std::vector<void*> allocs;
@@ -235,14 +235,17 @@ Engine engine_of(dmpt_prec p) {
     case DMPT_BF16X3: return Engine::BF16S2;
     case DMPT_BF16X6: return Engine::BF16S3;
     case DMPT_INT8X13: return Engine::I8S4;
+    case DMPT_INT8X6: return Engine::I8S3;
   }
   return Engine::F64;
 }
 
-// The engine and precision of BF16X3's final passes (options.refine 1 or 2).
+// Modes whose converged passes options.refine can finish in a finer engine.
+bool refinable(dmpt_prec p) { return p == DMPT_BF16X3 || p == DMPT_INT8X6; }
+// The engine and precision of those final passes (options.refine 1 or 2).
 Engine refine_engine(const dmpt_options& o) { return o.refine == 2 ? Engine::I8S4 : Engine::BF16S3; }
 dmpt_prec final_prec(dmpt_prec p, int refine) {
-  if (p == DMPT_BF16X3 && refine) return refine == 2 ? DMPT_INT8X13 : DMPT_BF16X6;
+  if (refinable(p) && refine) return refine == 2 ? DMPT_INT8X13 : DMPT_BF16X6;
   return p;
 }
 
@@ -254,6 +257,7 @@ double default_tol_cg(dmpt_prec p, int refine) {
     case DMPT_BF16X3: return 1e-5;
     case DMPT_BF16X6: return 1e-9;
     case DMPT_INT8X13: return 1e-9;
+    case DMPT_INT8X6: return 1e-7;
   }
   return 1e-14;
 }
@@ -272,18 +276,19 @@ double default_tol_occ(dmpt_prec p, int refine) {
     case DMPT_BF16X3: return 1e-6;
     case DMPT_BF16X6: return 1e-7;
     case DMPT_INT8X13: return 1e-7;
+    case DMPT_INT8X6: return 1e-6;
   }
   return 1e-12;
 }
 
 int planes_needed(const dmpt_options& o) {
   int p = engine_planes(engine_of(o.prec));
-  if (o.prec == DMPT_BF16X3 && o.refine == 1) p = 3;
+  if (refinable(o.prec) && o.refine == 1) p = 3;
   return p;
 }
 
 bool q8_needed(const dmpt_options& o) {
-  return o.prec == DMPT_INT8X13 || (o.prec == DMPT_BF16X3 && o.refine == 2);
+  return o.prec == DMPT_INT8X13 || o.prec == DMPT_INT8X6 || (refinable(o.prec) && o.refine == 2);
 }
 
 // Master copies (iterates, solver vectors) are FP64 in every mode; the
@@ -465,7 +470,7 @@ int acc64_of(dmpt_ctx c, Engine eng) { return eng == Engine::BF16S3 && c->opt.ac
 // sliced again where a writer touched them since their last slicing.
 // Host-side bounds of the int8 operands of a launch.
 bool ok_q8_bounds(const Call& k, const GemmArgs& a, int batch) {
-  if (k.eng != Engine::I8S4) return true;
+  if (!engine_int8(k.eng)) return true;
   auto span = [&](const BOp& o) -> size_t {
     return ((o.stride ? (size_t)((batch - 1) / o.div) * (size_t)o.stride : 0) + (size_t)k.nn) * kQ8Slices;
   };
@@ -528,7 +533,7 @@ dmpt_status run_gemm(const Call& k, const G& g) {
   a.active = g.active;
   a.variant = variant_for(k.c, k.eng, k.Np);
   a.acc64 = acc64_of(k.c, k.eng);
-  if (k.eng == Engine::I8S4) {
+  if (engine_int8(k.eng)) {
     if (k.Np > kQ8MaxK) return fail(k.c, DMPT_ERR_UNSUPPORTED, "int8 products need N <= 32768");
     STCHK(q8_operand(k, a.X, g.batch));
     STCHK(q8_operand(k, a.Y, g.batch));
@@ -580,7 +585,7 @@ dmpt_status run_gemm(const Call& k, const G& g) {
   {
     const double nn = (double)k.nn, es = (double)c->esize;
     // bytes per element of an operand as the kernel reads it
-    const double opb = k.eng == Engine::I8S4 ? (double)kQ8Slices : (k.np ? 2.0 * k.np : es);
+    const double opb = k.eng == Engine::I8S4 ? 4.0 : (k.eng == Engine::I8S3 ? 3.0 : (k.np ? 2.0 * k.np : es));
     auto distinct = [&](const BOp& o) { return o.stride ? (double)((members - 1) / o.div + 1) : 1.0; };
     bytes += (distinct(a.X) + distinct(a.Y)) * nn * opb;
     bytes += members * nn * es * (1.0 + (a.C1 ? 1.0 : 0.0) + (a.C2 ? 1.0 : 0.0) + (a.W ? 1.0 : 0.0));
@@ -1489,7 +1494,7 @@ Call make_call(dmpt_ctx c, int64_t N, bool refined) {
   k.c = c;
   k.w = &c->ws;
   k.eng = engine_of(c->opt.prec);
-  if (refined && c->opt.prec == DMPT_BF16X3 && c->opt.refine) k.eng = refine_engine(c->opt);
+  if (refined && refinable(c->opt.prec) && c->opt.refine) k.eng = refine_engine(c->opt);
   k.np = engine_planes(k.eng);
   k.N = N;
   k.Np = padded(N);
@@ -2578,7 +2583,7 @@ void dmpt_default_options(dmpt_options* o) {
 static dmpt_status normalise_options(dmpt_ctx c, const dmpt_options* in, dmpt_options* out) {
   dmpt_options o;
   if (in) o = *in; else dmpt_default_options(&o);
-  if (o.prec < DMPT_FP64 || o.prec > DMPT_INT8X13) return fail(c, DMPT_ERR_ARG, "unknown precision");
+  if (o.prec < DMPT_FP64 || o.prec > DMPT_INT8X6) return fail(c, DMPT_ERR_ARG, "unknown precision");
   if (o.refine < 0 || o.refine > 2) return fail(c, DMPT_ERR_ARG, "refine must be 0, 1 or 2");
   if (o.solver != DMPT_SOLVER_CG && o.solver != DMPT_SOLVER_NS)
     return fail(c, DMPT_ERR_ARG, "unknown solver");
@@ -2822,7 +2827,7 @@ dmpt_status dmpt_bench_product(dmpt_ctx c, int64_t N, dmpt_prec prec, int varian
   if (!c || !ms) return DMPT_ERR_ARG;
   if (N < 1 || N > c->n_max) return fail(c, DMPT_ERR_ARG, "N must lie in [1, n_max]");
   if (reps < 1 || reps > 100000) return fail(c, DMPT_ERR_ARG, "reps must lie in [1, 100000]");
-  if (prec < DMPT_FP64 || prec > DMPT_INT8X13) return fail(c, DMPT_ERR_ARG, "unknown precision");
+  if (prec < DMPT_FP64 || prec > DMPT_INT8X6) return fail(c, DMPT_ERR_ARG, "unknown precision");
   const Engine eng = engine_of(prec);
   if (variant < 0 || variant >= gemm_variants(eng, acc64_of(c, eng)))
     return fail(c, DMPT_ERR_ARG, "no such kernel variant for this precision");
@@ -2854,7 +2859,7 @@ dmpt_status dmpt_bench_product(dmpt_ctx c, int64_t N, dmpt_prec prec, int varian
   a.partials = c->d_part;
   a.acc64 = acc64_of(c, k.eng);
   a.variant = variant;
-  if (k.eng == Engine::I8S4) {
+  if (engine_int8(k.eng)) {
     if (k.Np > kQ8MaxK) return fail(c, DMPT_ERR_UNSUPPORTED, "int8 products need N <= 32768");
     STCHK(q8_operand(k, a.X, 1));
     STCHK(q8_operand(k, a.Y, 1));
@@ -2903,6 +2908,7 @@ dmpt_prec prec_of(Engine e) {
     case Engine::BF16S2: return DMPT_BF16X3;
     case Engine::BF16S3: return DMPT_BF16X6;
     case Engine::I8S4: return DMPT_INT8X13;
+    case Engine::I8S3: return DMPT_INT8X6;
   }
   return DMPT_FP64;
 }
@@ -2972,7 +2978,7 @@ dmpt_status tune_engine(dmpt_ctx c, Engine eng, int64_t N, int* chosen) {
 int context_engines(dmpt_ctx c, Engine* out) {
   int n = 0;
   out[n++] = engine_of(c->opt.prec);
-  if (c->opt.prec == DMPT_BF16X3 && c->opt.refine) out[n++] = refine_engine(c->opt);
+  if (refinable(c->opt.prec) && c->opt.refine) out[n++] = refine_engine(c->opt);
   return n;
 }
 
@@ -3004,7 +3010,7 @@ dmpt_status dmpt_autotune(dmpt_ctx c, int64_t N, int* variant) {
 dmpt_status dmpt_set_variant(dmpt_ctx c, int64_t N, dmpt_prec prec, int variant) {
   if (!c) return DMPT_ERR_ARG;
   if (N < 1 || N > c->n_max) return fail(c, DMPT_ERR_ARG, "N must lie in [1, n_max]");
-  if (prec < DMPT_FP64 || prec > DMPT_INT8X13) return fail(c, DMPT_ERR_ARG, "unknown precision");
+  if (prec < DMPT_FP64 || prec > DMPT_INT8X6) return fail(c, DMPT_ERR_ARG, "unknown precision");
   const Engine eng = engine_of(prec);
   if (variant < 0 || variant >= gemm_variants(eng, acc64_of(c, eng)))
     return fail(c, DMPT_ERR_ARG, "no such kernel variant for this precision");
@@ -3016,7 +3022,7 @@ dmpt_status dmpt_get_variant(dmpt_ctx c, int64_t N, dmpt_prec prec, int* variant
                              int name_len) {
   if (!c || !variant) return DMPT_ERR_ARG;
   if (N < 1) return fail(c, DMPT_ERR_ARG, "N must be >= 1");
-  if (prec < DMPT_FP64 || prec > DMPT_INT8X13) return fail(c, DMPT_ERR_ARG, "unknown precision");
+  if (prec < DMPT_FP64 || prec > DMPT_INT8X6) return fail(c, DMPT_ERR_ARG, "unknown precision");
   const Engine eng = engine_of(prec);
   *variant = variant_for(c, eng, padded(N));
   if (tuned) *tuned = is_tuned(c, eng, padded(N)) ? 1 : 0;
@@ -3424,7 +3430,7 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
   // tolerances) brings the mu jet close, then the 6-product engine with the
   // final tolerances finishes; otherwise a single phase.
   Call k = make_call(c, N, false);
-  const bool two_phase = c->opt.prec == DMPT_BF16X3 && c->opt.refine;
+  const bool two_phase = refinable(c->opt.prec) && c->opt.refine;
   struct Phase {
     Engine eng;
     double tol_cg, tol_occ;
@@ -3440,11 +3446,15 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
     k.traj = true;
     k.jets = jets;
   }
+  // the passes of the linear schedule run in the final engine.  An order-0
+  // pass of the final engine always precedes them: its Newton step settles
+  // mu0 far below the occupation tolerance, which P2 needs (its sensitivity
+  // to mu0 is much larger than Tr P0's)
+  const Phase lin_phase{two_phase ? refine_engine(c->opt) : k.eng, c->opt.tol_cg, c->opt.tol_occ};
   Phase phases[2];
   int nph = 0;
-  if (two_phase)
-    phases[nph++] = {Engine::BF16S2, kPhaseATolCg, kPhaseATolOcc};
-  phases[nph++] = {two_phase ? refine_engine(c->opt) : k.eng, c->opt.tol_cg, c->opt.tol_occ};
+  if (two_phase) phases[nph++] = {engine_of(c->opt.prec), kPhaseATolCg, kPhaseATolOcc};
+  phases[nph++] = lin_phase;
   int ph = 0;
   double occ = 0;
   int it = 0;
@@ -3483,6 +3493,16 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
     if (floor_ok) ok = true;
     if (ok && last) {
       if (floor_ok) c->flags |= DMPT_FLAG_NOISE_FLOOR;
+      // linear schedule: the order-1 pass recomputes every order at mu0 (and
+      // checks it with the exact slope), so the Newton step from these traces
+      // is free and takes mu0 from within tol_occ to its quadratic error; P2's
+      // sensitivity to mu0 needs that (an occupation error of 1e-7 N moved P2
+      // by a few 1e-6)
+      const double trpmu_f = beta * (r[RES_TR] - r[RES_FRO]);
+      if (linear && !floor_ok && trpmu_f > 0.0) {
+        const double mu_n = mu[0] + (Ne - r[RES_TR]) / trpmu_f;
+        if (mu_n >= br_lo && mu_n <= br_hi) mu[0] = mu_n;
+      }
       done = true;
       break;
     }
@@ -3522,7 +3542,7 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
   }
   if (it > c->opt.max_newton) it = c->opt.max_newton;
   if (done && linear) {
-    const Phase& P = phases[nph - 1];
+    const Phase& P = lin_phase;
     k.eng = P.eng;
     k.np = engine_planes(P.eng);
     k.tol_cg = P.tol_cg;
@@ -3624,9 +3644,9 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
     bk.back().xmax = std::max(bk.back().xmax, xs[slot_sys[i]]);
   }
   // the batch's product engine; with options.autotune every bucket size is tuned first
-  const Engine eng = (c->opt.prec == DMPT_BF16X3 && c->opt.refine) ? refine_engine(c->opt)
-                                                                    : engine_of(c->opt.prec);
-  if (eng == Engine::I8S4) return fail(c, DMPT_ERR_UNSUPPORTED, "the batched solve has no int8 products");
+  const Engine eng = (refinable(c->opt.prec) && c->opt.refine) ? refine_engine(c->opt)
+                                                                 : engine_of(c->opt.prec);
+  if (engine_int8(eng)) return fail(c, DMPT_ERR_UNSUPPORTED, "the batched solve has no int8 products");
   if (c->opt.autotune)
     for (auto& b : bk)
       if (!is_tuned(c, eng, b.Np)) STCHK(tune_engine(c, eng, std::min<int64_t>(b.Np, c->n_max), nullptr));
@@ -4017,7 +4037,7 @@ dmpt_status dmpt_backward(dmpt_ctx c, int64_t N, const double* H0, double beta, 
   }
   reset_stats(c);
   Call k = make_call(c, N, true);
-  if (k.eng == Engine::I8S4) return fail(c, DMPT_ERR_UNSUPPORTED, "the adjoint has no int8 products");
+  if (engine_int8(k.eng)) return fail(c, DMPT_ERR_UNSUPPORTED, "the adjoint has no int8 products");
   const int ck = std::max(1, std::min(c->opt.ckpt_every, n));
   dmpt_status r = adjoint_impl<double>(k, H0, beta, mu, n, Abar, G, ck);
   if (r != DMPT_OK) return r;

@@ -20,8 +20,9 @@ constexpr int kPad = 128;
 inline int64_t padded(int64_t n) { return (n + kPad - 1) / kPad * kPad; }
 
 // Product engines (see gemm.hip).
-enum class Engine : int { F64 = 0, F32 = 1, BF16S2 = 2, BF16S3 = 3, I8S4 = 4 };
-constexpr int kEngines = 5;
+enum class Engine : int { F64 = 0, F32 = 1, BF16S2 = 2, BF16S3 = 3, I8S4 = 4, I8S3 = 5 };
+constexpr int kEngines = 6;
+inline bool engine_int8(Engine e) { return e == Engine::I8S4 || e == Engine::I8S3; }
 
 // BF16 planes per operand (the int8 engine keeps its slices apart, see q8_off).
 inline int engine_planes(Engine e) {
@@ -29,7 +30,13 @@ inline int engine_planes(Engine e) {
 }
 // Matrix-core products per logical product.
 inline int engine_terms(Engine e) {
-  return e == Engine::BF16S2 ? 3 : (e == Engine::BF16S3 ? 6 : (e == Engine::I8S4 ? 13 : 1));
+  switch (e) {
+    case Engine::BF16S2: return 3;
+    case Engine::BF16S3: return 6;
+    case Engine::I8S4: return 13;
+    case Engine::I8S3: return 6;
+    default: return 1;
+  }
 }
 
 // Int8 slices of the I8S4 engine.  A member x (Np x Np, FP64 master) with

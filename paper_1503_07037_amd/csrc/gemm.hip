@@ -24,6 +24,7 @@
 //           with p + q <= 4 on v_mfma_i32_32x32x32_i8, summed exactly in
 //           int32 (one accumulator per weight p + q), combined in FP64 at the
 //           end
+//   I8S3    the same slices, digits 0-2 only: the six products with p + q <= 2
 // Master copies (the operands of the FP64 and FP32 engines, C1, C2, W and C)
 // are FP64 for every engine.
 //
@@ -647,21 +648,22 @@ hipError_t launch_bf16_grouped(const GemmArgs* list, const int* start, int nprob
 // ------------------------------------------------------------------ int8 slices
 // 128 x 128 output tile, NW waves (WM along m, NW / WM along n; wave (wm, wn)
 // owns (128 / WM) x (128 WM / NW) as 32 x 32 MFMA tiles), one int32
-// accumulator tile per weight w = p + q (0 .. 4) of the digit products.  The operands move as 1 KB slice
+// accumulator tile per weight w = p + q of the digit products: SD = 4 digits
+// read and weights 0 .. 4 (I8S4), or SD = 3 and weights 0 .. 2 (I8S3).  The operands move as 1 KB slice
 // blocks in MFMA operand order (q8_off), through the same pipeline as the
 // split-BF16 kernel: two LDS stages of BK of k and one register stage.  The
 // int32 sums are exact over the whole inner dimension, so nothing is folded
 // during the k loop; the epilogue evaluates
 //   q_x q_y (A_0 + (A_1 + (A_2 + (A_3 + A_4 / 254) / 254) / 254) / 254)
-// in FP64 (A_w: the weight-w accumulator).
+// (or its first three terms) in FP64 (A_w: the weight-w accumulator).
 typedef int i4v __attribute__((ext_vector_type(4)));
 typedef int i16v __attribute__((ext_vector_type(16)));
 
-template <int BK, int NW, int WM>
+template <int BK, int NW, int WM, int SD>
 __device__ __forceinline__ void gemm_i8_tile(const GemmArgs& a, int z, int bx, int nbx) {
   constexpr int TM = 128;
-  constexpr int S = kQ8Slices;
-  constexpr int W = S + 1;            // weights 0 .. 4
+  constexpr int S = SD;               // digits read (of the kQ8Slices stored)
+  constexpr int W = SD == 4 ? 5 : 3;  // weights kept: 0 .. 4 or 0 .. 2
   constexpr int WN = NW / WM;         // waves along n
   constexpr int FM = TM / (32 * WM);  // MFMA tiles per wave along m
   constexpr int FN = TM / (32 * WN);  // MFMA tiles per wave along n
@@ -684,8 +686,8 @@ __device__ __forceinline__ void gemm_i8_tile(const GemmArgs& a, int z, int bx, i
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
   const int zx = z / a.X.div, zy = z / a.Y.div;
-  const int8_t* xq = a.X.q8 + (int64_t)zx * a.X.stride * S;
-  const int8_t* yq = a.Y.q8 + (int64_t)zy * a.Y.stride * S;
+  const int8_t* xq = a.X.q8 + (int64_t)zx * a.X.stride * kQ8Slices;
+  const int8_t* yq = a.Y.q8 + (int64_t)zy * a.Y.stride * kQ8Slices;
   const double scale = a.X.qs[a.X.stride ? zx : 0] * a.Y.qs[a.Y.stride ? zy : 0];
   const int8_t* src[LOADS];
   int dst[LOADS];
@@ -695,12 +697,12 @@ __device__ __forceinline__ void gemm_i8_tile(const GemmArgs& a, int z, int bx, i
     const int op = q / (S * NBLK), sl = (q / NBLK) % S, b = q % NBLK;
     const int rb = b / KB, kb = b % KB;
     const int64_t brow = (int64_t)(op ? tn : tm) * RB + rb;
-    src[j] = (op ? yq : xq) + (((brow * kbr + kb) * S + sl) << 10) + lane * 16;
+    src[j] = (op ? yq : xq) + (((brow * kbr + kb) * kQ8Slices + sl) << 10) + lane * 16;
     dst[j] = q * 1024 + lane * 16;
   }
   u4v stg[LOADS];
   auto gload = [&](int kt) {
-    const int64_t koff = (int64_t)kt * KB * S * 1024;
+    const int64_t koff = (int64_t)kt * KB * kQ8Slices * 1024;
 #pragma unroll
     for (int j = 0; j < LOADS; ++j) stg[j] = *(const u4v*)(src[j] + koff);
   };
@@ -781,12 +783,12 @@ __device__ __forceinline__ void gemm_i8_tile(const GemmArgs& a, int z, int bx, i
   }
 }
 
-template <int BK, int NW, int WM>
+template <int BK, int NW, int WM, int SD>
 __global__ __launch_bounds__(NW * 64) void k_gemm_i8(GemmArgs a) {
-  gemm_i8_tile<BK, NW, WM>(a, blockIdx.z, blockIdx.x, gridDim.x);
+  gemm_i8_tile<BK, NW, WM, SD>(a, blockIdx.z, blockIdx.x, gridDim.x);
 }
 
-template <int BK, int NW, int WM>
+template <int BK, int NW, int WM, int SD>
 __global__ __launch_bounds__(NW * 64) void k_gemm_i8_grouped(const GemmArgs* __restrict__ list,
                                                               const int* __restrict__ start, int nprob) {
   int p = 0;
@@ -795,31 +797,31 @@ __global__ __launch_bounds__(NW * 64) void k_gemm_i8_grouped(const GemmArgs* __r
   const GemmArgs& a = list[p];
   const int tiles = (int)((a.Np / 128) * (a.Np / 128));
   const int local = b - start[p];
-  gemm_i8_tile<BK, NW, WM>(a, local / tiles, local % tiles, tiles);
+  gemm_i8_tile<BK, NW, WM, SD>(a, local / tiles, local % tiles, tiles);
 }
 
-template <int BK>
-constexpr size_t i8_lds() { return (size_t)2 * 2 * kQ8Slices * 4 * (BK / 32) * 1024; }
+template <int BK, int SD>
+constexpr size_t i8_lds() { return (size_t)2 * 2 * SD * 4 * (BK / 32) * 1024; }
 
-template <int BK, int NW, int WM>
+template <int BK, int NW, int WM, int SD>
 hipError_t prepare_i8() {
-  hipError_t e = hipFuncSetAttribute((const void*)k_gemm_i8<BK, NW, WM>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)i8_lds<BK>());
+  hipError_t e = hipFuncSetAttribute((const void*)k_gemm_i8<BK, NW, WM, SD>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)i8_lds<BK, SD>());
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_gemm_i8_grouped<BK, NW, WM>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)i8_lds<BK>());
+  return hipFuncSetAttribute((const void*)k_gemm_i8_grouped<BK, NW, WM, SD>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)i8_lds<BK, SD>());
 }
 
-template <int BK, int NW, int WM>
+template <int BK, int NW, int WM, int SD>
 hipError_t launch_i8(const GemmArgs& a, dim3 grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_gemm_i8<BK, NW, WM>), grid, dim3(NW * 64), i8_lds<BK>(), s, a);
+  hipLaunchKernelGGL((k_gemm_i8<BK, NW, WM, SD>), grid, dim3(NW * 64), (i8_lds<BK, SD>()), s, a);
   return hipGetLastError();
 }
 
-template <int BK, int NW, int WM>
+template <int BK, int NW, int WM, int SD>
 hipError_t launch_i8_grouped(const GemmArgs* list, const int* start, int nprob, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_gemm_i8_grouped<BK, NW, WM>), dim3(blocks), dim3(NW * 64), i8_lds<BK>(), s, list, start,
-                     nprob);
+  hipLaunchKernelGGL((k_gemm_i8_grouped<BK, NW, WM, SD>), dim3(blocks), dim3(NW * 64), (i8_lds<BK, SD>()), s, list,
+                     start, nprob);
   return hipGetLastError();
 }
 
@@ -831,7 +833,7 @@ hipError_t launch_i8_grouped(const GemmArgs* list, const int* start, int nprob, 
 //   FP32  0: BK 32, 8 waves  1: BK 16, 8 waves   2: BK 32, 4 waves
 //   split BF16  0: 256 x 256 tiles where Np allows (else 128)   1: 128 x 128 tiles
 //   (the 6-product kernel with FP64 slice sums has 128 x 128 tiles only)
-//   int8  0: BK 32, 8 waves of 32 x 64   1: BK 32, 8 waves of 64 x 32
+//   int8 (both digit counts)  0: BK 32, 8 waves of 32 x 64   1: BK 32, 8 waves of 64 x 32
 int gemm_variants(Engine eng, int acc64) {
   switch (eng) {
     case Engine::F64: return 3;
@@ -839,6 +841,7 @@ int gemm_variants(Engine eng, int acc64) {
     case Engine::BF16S2: return 2;
     case Engine::BF16S3: return acc64 ? 1 : 2;
     case Engine::I8S4: return 2;
+    case Engine::I8S3: return 2;
   }
   return 1;
 }
@@ -849,7 +852,7 @@ const char* gemm_variant_name(Engine eng, int acc64, int v) {
   static const char* bf[2] = {"BF16 256 x 256 tiles", "BF16 128 x 128 tiles"};
   static const char* i8[2] = {"int8 BK 32, 8 waves of 32 x 64", "int8 BK 32, 8 waves of 64 x 32"};
   if (v < 0 || v >= gemm_variants(eng, acc64)) return "invalid";
-  if (eng == Engine::I8S4) return i8[v];
+  if (eng == Engine::I8S4 || eng == Engine::I8S3) return i8[v];
   if (eng == Engine::F64) return f64[v];
   if (eng == Engine::F32) return f32[v];
   if (eng == Engine::BF16S3 && acc64) return "BF16 128 x 128 tiles, FP64 slice sums";
@@ -872,8 +875,10 @@ hipError_t gemm_prepare() {
   if ((e = prepare_bf16<3, 128, 32, 4>())) return e;
   if ((e = prepare_bf16<3, 128, 32, 8, 1>())) return e;
   if ((e = prepare_bf16<2, 256, 16, kWaves256>())) return e;
-  if ((e = prepare_i8<32, 8, 2>())) return e;
-  if ((e = prepare_i8<32, 8, 4>())) return e;
+  if ((e = prepare_i8<32, 8, 2, 4>())) return e;
+  if ((e = prepare_i8<32, 8, 4, 4>())) return e;
+  if ((e = prepare_i8<32, 8, 2, 3>())) return e;
+  if ((e = prepare_i8<32, 8, 4, 3>())) return e;
   return prepare_bf16<3, 256, 16, kWaves256>();
 }
 
@@ -890,9 +895,11 @@ hipError_t gemm(const GemmArgs& a, hipStream_t s) {
   const dim3 grid((unsigned)gemm_tiles(a.eng, a.Np, a.variant, a.acc64), 1, (unsigned)a.batch);
   switch (a.eng) {
     case Engine::I8S4:
+    case Engine::I8S3:
       if (a.Np > kQ8MaxK || !a.X.q8 || !a.Y.q8 || !a.X.qs || !a.Y.qs) return hipErrorInvalidValue;
-      if (a.variant == 1) return launch_i8<32, 8, 2>(a, grid, s);
-      return launch_i8<32, 8, 4>(a, grid, s);
+      if (a.eng == Engine::I8S3)
+        return a.variant == 1 ? launch_i8<32, 8, 2, 3>(a, grid, s) : launch_i8<32, 8, 4, 3>(a, grid, s);
+      return a.variant == 1 ? launch_i8<32, 8, 2, 4>(a, grid, s) : launch_i8<32, 8, 4, 4>(a, grid, s);
     case Engine::F64:
       if (a.variant == 1) hipLaunchKernelGGL((k_gemm_f64<16, 8>), grid, dim3(8 * 64), 0, s, a);
       else if (a.variant == 2) hipLaunchKernelGGL((k_gemm_f64<8, 4>), grid, dim3(4 * 64), 0, s, a);
@@ -922,8 +929,11 @@ hipError_t gemm_grouped(Engine eng, int variant, int acc64, int edge, const Gemm
   if (nprob < 1 || blocks < 1 || variant < 0 || variant >= gemm_variants(eng, acc64)) return hipErrorInvalidValue;
   switch (eng) {
     case Engine::I8S4:
-      if (variant == 1) return launch_i8_grouped<32, 8, 2>(list, start, nprob, blocks, s);
-      return launch_i8_grouped<32, 8, 4>(list, start, nprob, blocks, s);
+      if (variant == 1) return launch_i8_grouped<32, 8, 2, 4>(list, start, nprob, blocks, s);
+      return launch_i8_grouped<32, 8, 4, 4>(list, start, nprob, blocks, s);
+    case Engine::I8S3:
+      if (variant == 1) return launch_i8_grouped<32, 8, 2, 3>(list, start, nprob, blocks, s);
+      return launch_i8_grouped<32, 8, 4, 3>(list, start, nprob, blocks, s);
     case Engine::F64:
       if (variant == 1) hipLaunchKernelGGL((k_gemm_f64_grouped<16, 8>), dim3(blocks), dim3(8 * 64), 0, s, list, start, nprob);
       else if (variant == 2) hipLaunchKernelGGL((k_gemm_f64_grouped<8, 4>), dim3(blocks), dim3(4 * 64), 0, s, list, start, nprob);

@@ -201,6 +201,9 @@ def test_chain128_taylor_guess_fp64(dm, chain128_ref):
     ("bf16x3", {"refine": 1}, 1e-6),   # 3-product passes, then the 6-product refinement
     ("int8x13", {}, 1e-6),             # int8 slices, exact int32 sums
     ("bf16x3", {"refine": 2}, 1e-6),   # 3-product passes, then int8 slices
+    ("int8x6", {}, 1e-5),              # the first three int8 digits alone
+    ("int8x6", {"refine": 2}, 1e-6),   # int8 6-product passes, then the 13-product order-1/2 passes
+    ("int8x6", {"refine": 2, "schedule": 0}, 1e-6),  # the same with Algorithm 1's joint Newton
 ])
 def test_chain128_canonical_low_precision(dm, chain128_ref, prec, extra, tol):
     print(f"case chain128 canonical {prec} {extra}", flush=True)
@@ -394,7 +397,8 @@ def cubic2048_ref():
 
 @pytest.mark.timeout(300)
 @pytest.mark.parametrize("prec,refine,tol", [("fp64", 0, 1e-10), ("fp32", 0, 1e-6), ("bf16x6", 0, 1e-6),
-                                             ("bf16x3", 1, 1e-6), ("int8x13", 0, 1e-6), ("bf16x3", 2, 1e-6)])
+                                             ("bf16x3", 1, 1e-6), ("int8x13", 0, 1e-6), ("bf16x3", 2, 1e-6),
+                                             ("int8x6", 2, 1e-6)])
 def test_cubic2048_all_forms(dm, cubic2048_ref, prec, refine, tol):
     """16 x 16 x 8 simple-cubic lattice, beta 20, n 25, orders 0-2: every element of P0, P1 and P2
     against the oracle (P0 absolute, P1 and P2 relative to max |P^(k)|), every form."""
@@ -414,15 +418,16 @@ def test_cubic2048_all_forms(dm, cubic2048_ref, prec, refine, tol):
 # ------------------------------------------------------------------ N = 8192 banded (the benchmark)
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("refine", [2, 1])
-def test_banded8192_benchmark_configuration(dm, refine):
-    """The benchmark's workload and launch configuration (bf16x3 passes, then the int8-slice
-    refinement (2) or the bf16x6 refinement with FP64 slice accumulation (1); orders 0-2,
-    3 directions) against the oracle's stored samples and whole row blocks."""
-    print(f"case banded8192 mixed refine={refine}", flush=True)
+@pytest.mark.parametrize("prec,refine", [("int8x6", 2), ("bf16x3", 2), ("bf16x3", 1)])
+def test_banded8192_benchmark_configuration(dm, prec, refine):
+    """The benchmark's workload and launch configuration (int8 6-product passes, then the int8
+    13-product order-1 and order-2 passes; and the bf16x3 passes followed by the int8 (2) or the
+    bf16x6 refinement with FP64 slice accumulation (1); orders 0-2, 3 directions) against the
+    oracle's stored samples and whole row blocks."""
+    print(f"case banded8192 {prec} refine={refine}", flush=True)
     c = workloads.config("banded8192")
     g = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "banded8192_samples.npz"))
-    with dm.Context(c["N"], dirs_max=len(c["H1"]), prec="bf16x3", refine=refine, acc64=1) as ctx:
+    with dm.Context(c["N"], dirs_max=len(c["H1"]), prec=prec, refine=refine, acc64=1) as ctx:
         P0, P1, P2, mu, st = ctx.mu_newton(T(c["H0"]), [T(h) for h in c["H1"]], None, beta=c["beta"],
                                            Ne=c["Ne"], n=c["n"], order=2)
     ii = torch.as_tensor(g["i"], device=P0.device)
