@@ -19,13 +19,18 @@ SOURCES = ["gemm.hip", "elementwise.hip", "sparse.hip", "dmpt_api.hip"]
 ARCH = os.environ.get("DMPT_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
-    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-Werror",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # unroll the MFMA loops completely so the accumulator tiles stay in registers
     "-mllvm", "-unroll-threshold=100000",
     "-I" + INCLUDE, "-I" + CSRC,
 ]
+
+
+# roctx ranges (Newton passes, recursion steps, graph replays) for rocprofv3 --marker-trace
+ROCM_LIB = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
+LINK = ["-L" + ROCM_LIB, "-lrocprofiler-sdk-roctx", "-Wl,-rpath," + ROCM_LIB]
 
 
 def _hipcc():
@@ -61,7 +66,7 @@ def build(verbose=False):
             if o.strip():
                 print(o)
     tmp = LIB + ".tmp"
-    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp])
+    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, *LINK, "-o", tmp])
     os.replace(tmp, LIB)
     return LIB
 

@@ -16,6 +16,7 @@
 // steps P^(0) = I/2 - D^(0), P^(k) = -D^(k).
 #include <algorithm>
 #include <chrono>
+#include <cstdarg>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -24,6 +25,8 @@
 #include <mutex>
 #include <string>
 #include <vector>
+
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include "dmpt_internal.h"
 
@@ -107,6 +110,11 @@ struct dmpt_ctx_s {
   std::vector<std::pair<const char*, size_t>> regions;
   double* d_tally = nullptr;     // [executed MFMA flops, useful flops] of graph-replayed products
   bool log = false;              // DMPT_LOG set: one line per Newton pass on stderr
+  // DMPT_DEBUG_CHECKS set: every product's output is scanned for non-finite
+  // values and, after every recursion step, every iterate for non-finite values
+  // and exact symmetry (host-synchronising; passes recorded for a graph skip it)
+  bool debug = false;
+  double* d_dbg = nullptr;       // per-block maxima of the asymmetry scans
   // product-kernel variant per (engine, padded size): chosen by the autotuner or pinned
   struct Tuned {
     int eng;
@@ -227,6 +235,22 @@ struct CallScope {
   scope_.c = (ctx)
 
 dmpt_status autotune_if_asked(dmpt_ctx c, int64_t N);
+
+// A roctx range over a scope (Newton passes, recursion steps, graph replays):
+// `rocprofv3 --marker-trace` shows them on the host timeline.
+struct Range {
+  explicit Range(const char* fmt, ...) __attribute__((format(printf, 2, 3))) {
+    char buf[96];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    roctxRangePushA(buf);
+  }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 Engine engine_of(dmpt_prec p) {
   switch (p) {
@@ -615,6 +639,20 @@ dmpt_status run_gemm(const Call& k, const G& g) {
   }
   c->mfma_flops += mf;
   c->useful_flops += uf;
+  if (c->debug && !k.graph) {
+    HIPCHK(c, set_values(c->d_flag + 1, 0, 1, nullptr, 0.0, 0, c->stream));
+    for (int z = 0; z < g.batch; ++z)
+      HIPCHK(c, nonfinite_scan((const double*)((const char*)a.C + (size_t)z * a.sC * c->esize), k.Np, k.Np,
+                               c->d_flag + 1, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->h_int, c->d_flag + 1, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->h_int[0]) {
+      char msg[128];
+      std::snprintf(msg, sizeof msg, "debug check: a product (engine %d, Np %lld) wrote a non-finite value",
+                    (int)k.eng, (long long)k.Np);
+      return fail(c, DMPT_ERR_NONFINITE, msg);
+    }
+  }
   return DMPT_OK;
 }
 
@@ -1360,12 +1398,62 @@ dmpt_status recursion_step(const Call& k, int order, int d, int step) {
   return DMPT_OK;
 }
 
+// DMPT_DEBUG_CHECKS, after recursion step `step`: S0 and the iterates of every
+// order finite, and the iterates exactly symmetric (each is symmetrised after
+// its solve).  The message names the step, the matrix and the member.
+dmpt_status debug_step(const Call& k, int order, int d, int step) {
+  dmpt_ctx c = k.c;
+  if (!c->debug || k.rec) return DMPT_OK;
+  hipStream_t s = c->stream;
+  const WS* w = k.w;
+  const int md = k.m * d;
+  struct Item {
+    const Group* g;
+    int count;
+    const char* name;
+    bool sym;
+  };
+  const Item items[] = {{&w->D0, k.m, "D0", true},
+                        {&w->S0, k.m, "S0", false},
+                        {&w->D1, order >= 1 ? md : 0, "D1", true},
+                        {&w->D2, order >= 2 ? md : 0, "D2", true},
+                        {&w->D3, order >= 3 ? md : 0, "D3", true}};
+  const int nb = reduce_blocks(k.Np * k.Np);
+  std::vector<double> hm((size_t)nb);
+  for (const Item& it : items)
+    for (int z = 0; z < it.count; ++z) {
+      const double* x = (const double*)mptr(k, *it.g, z);
+      HIPCHK(c, set_values(c->d_flag + 1, 0, 1, nullptr, 0.0, 0, s));
+      HIPCHK(c, nonfinite_scan(x, k.Np, k.Np, c->d_flag + 1, s));
+      HIPCHK(c, hipMemcpyAsync(c->h_int, c->d_flag + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+      double asym = 0.0;
+      if (it.sym) {
+        HIPCHK(c, asym_max(x, k.Np, c->d_dbg, s));
+        HIPCHK(c, hipMemcpyAsync(hm.data(), c->d_dbg, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+      }
+      HIPCHK(c, hipStreamSynchronize(s));
+      if (it.sym)
+        for (double v : hm) asym = std::max(asym, v);
+      if (c->h_int[0] || asym > 0.0) {
+        char msg[160];
+        std::snprintf(msg, sizeof msg, "debug check after recursion step %d: %s member %d is %s", step, it.name, z,
+                      c->h_int[0] ? "not finite" : "not symmetric");
+        return fail(c, c->h_int[0] ? DMPT_ERR_NONFINITE : DMPT_ERR_ARG, msg);
+      }
+    }
+  return DMPT_OK;
+}
+
 // One full pass of the recursion for orders 0..order (single system).
 template <class T>
 dmpt_status recursion_pass(const Call& k, const PassIn& in) {
   const double cscale = std::ldexp(in.beta, -(in.n + 2));
   STCHK(init_d<T>(k, in, cscale));
-  for (int step = 0; step < in.n; ++step) STCHK(recursion_step<T>(k, in.order, in.d, step));
+  for (int step = 0; step < in.n; ++step) {
+    Range r("dmpt recursion step %d", step);
+    STCHK(recursion_step<T>(k, in.order, in.d, step));
+    STCHK(debug_step(k, in.order, in.d, step));
+  }
   if (k.traj) k.c->tj_valid = in.order;
   return DMPT_OK;
 }
@@ -1566,6 +1654,7 @@ dmpt_status one_pass(const Call& k, const PassIn& in, double* P0, double* const*
 dmpt_status pass_dispatch(const Call& k, const PassIn& in, double* P0, double* const* P1,
                           double* const* P2, double* const* P3 = nullptr) {
   if (in.order >= 3 && !P3) return fail(k.c, DMPT_ERR_ARG, "internal: P3 missing");
+  Range r("dmpt pass: order %d, %d directions, engine %d", in.order, in.d, (int)k.eng);
   return one_pass<double>(k, in, P0, P1, P2, P3);
 }
 
@@ -2422,7 +2511,7 @@ struct SparseJets {
 // each solved as Y = Z R (Z a polynomial in D0, so Y0 = 2 Z D0 as well).
 // d1 order-1 jets start from c (sym H1[z] - mu1[z] I) (H1[z] null: c (-mu1[z]) I),
 // d2 order-2 jets from -c mu2[z] I (no H2).
-dmpt_status sparse_pass(Sparse& w, SparseJets& J, const double* H0, int d1, const double* const* H1,
+dmpt_status sparse_pass_impl(Sparse& w, SparseJets& J, const double* H0, int d1, const double* const* H1,
                         const double* mu1, int d2, const double* mu2, double mu0, double beta, int n) {
   const double cs = std::ldexp(beta, -(n + 2));
   STCHK(sp_from_dense(w, H0, cs, -cs * mu0, J.D0));
@@ -2473,6 +2562,12 @@ dmpt_status sparse_pass(Sparse& w, SparseJets& J, const double* H0, int d1, cons
     for (int z = 0; z < d2; ++z) std::swap(J.D2[z], J.Y2[z]);
   }
   return DMPT_OK;
+}
+
+dmpt_status sparse_pass(Sparse& w, SparseJets& J, const double* H0, int d1, const double* const* H1,
+                        const double* mu1, int d2, const double* mu2, double mu0, double beta, int n) {
+  Range r("dmpt sparse pass: %d first-order and %d second-order jets", d1, d2);
+  return sparse_pass_impl(w, J, H0, d1, H1, mu1, d2, mu2, mu0, beta, n);
 }
 
 // ---------------------------------------------------------------- no-allocation path
@@ -2651,6 +2746,7 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
   }
   if (gemm_prepare() != hipSuccess) return bail(DMPT_ERR_HIP, "product kernel attributes");
   c->log = std::getenv("DMPT_LOG") != nullptr;
+  c->debug = std::getenv("DMPT_DEBUG_CHECKS") != nullptr;
   c->n_max = n_max;
   c->np_max = padded(n_max);
   c->dirs_max = dirs_max;
@@ -2712,6 +2808,10 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
   const size_t tiles = (size_t)(c->np_max / 128) * (c->np_max / 128);
   c->part_count = std::max<size_t>(tiles, 1024) * dm;
   c->d_part = (double*)alloc(sizeof(double) * c->part_count);
+  if (c->debug) {
+    c->d_dbg = (double*)alloc(sizeof(double) * (size_t)reduce_blocks(c->np_max * c->np_max));
+    if (!c->d_dbg) return bail(DMPT_ERR_NOMEM, "device scalar allocation failed");
+  }
   if (c->q8) {
     c->d_qpart = (double*)alloc(sizeof(double) * (size_t)q8_blocks(c->np_max) * kQ8Chunk);
     if (!c->d_qpart) return bail(DMPT_ERR_NOMEM, "device scalar allocation failed");
@@ -3900,6 +4000,7 @@ dmpt_status dmpt_mu_newton_batched(dmpt_ctx c, int nsys, const int64_t* Ns, cons
     const int passes0 = total_passes;
     const auto ts = std::chrono::steady_clock::now();
     for (int pass = 0; pass < c->opt.max_newton; ++pass) {
+      Range r("dmpt batched replay: stage %d, pass %d", stage, pass);
       if (hipGraphLaunch(gx[stage], s) != hipSuccess) {
         rc = fail(c, DMPT_ERR_HIP, "hipGraphLaunch failed");
         break;
@@ -4039,7 +4140,11 @@ dmpt_status dmpt_backward(dmpt_ctx c, int64_t N, const double* H0, double beta, 
   Call k = make_call(c, N, true);
   if (engine_int8(k.eng)) return fail(c, DMPT_ERR_UNSUPPORTED, "the adjoint has no int8 products");
   const int ck = std::max(1, std::min(c->opt.ckpt_every, n));
-  dmpt_status r = adjoint_impl<double>(k, H0, beta, mu, n, Abar, G, ck);
+  dmpt_status r;
+  {
+    Range rr("dmpt adjoint: N %lld, %d steps, checkpoints every %d", (long long)N, n, ck);
+    r = adjoint_impl<double>(k, H0, beta, mu, n, Abar, G, ck);
+  }
   if (r != DMPT_OK) return r;
   if (st) {
     std::memset(st, 0, sizeof(*st));

@@ -522,3 +522,25 @@ def test_int8_paths_without_int8_products_say_so(dm):
         with pytest.raises(dm.DMPTError) as e:
             ctx.backward(T(h0), beta=beta, Ne=N / 2.0, n=n, Abar=T(np.eye(N)))
         assert e.value.status == L.DMPT_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("prec,extra", [("fp64", {}), ("bf16x3", {"refine": 2}), ("int8x13", {})])
+def test_debug_checks_leave_results_unchanged(dm, chain128_ref, prec, extra, monkeypatch):
+    """DMPT_DEBUG_CHECKS (every product output scanned for non-finite values, every iterate checked
+    for non-finite values and exact symmetry after every recursion step) passes on a canonical
+    solve and changes no bit of the results."""
+    print(f"case debug checks {prec} {extra}", flush=True)
+    c, ref = chain128_ref
+    out = {}
+    for dbg in (0, 1):
+        if dbg:
+            monkeypatch.setenv("DMPT_DEBUG_CHECKS", "1")
+        else:
+            monkeypatch.delenv("DMPT_DEBUG_CHECKS", raising=False)
+        with dm.Context(c["N"], dirs_max=1, prec=prec, **extra) as ctx:
+            P0, P1, P2, mu, st = ctx.mu_newton(T(c["H0"]), [T(h) for h in c["H1"]], None,
+                                               beta=c["beta"], Ne=c["Ne"], n=c["n"], order=2)
+        out[dbg] = (P0.cpu().numpy(), P1[0].cpu().numpy(), P2[0].cpu().numpy(), list(mu))
+    for a, b in zip(out[0][:3], out[1][:3]):
+        assert np.array_equal(a, b)
+    assert out[0][3] == out[1][3]
