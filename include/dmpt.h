@@ -383,6 +383,7 @@ dmpt_status dmpt_congruence(dmpt_ctx ctx, int64_t N, const double* Z, const doub
  *                0: 256 x 256 output tiles where the padded size allows   1: 128 x 128 tiles
  *   DMPT_BF16X6 with options.acc64 = 1: 0 only (128 x 128 tiles, FP64 slice sums)
  *   DMPT_INT8X13, DMPT_INT8X6  0: 128 x 128 tiles, 8 waves of 32 x 64   1: 8 waves of 64 x 32
+ *                2, 3: the same with operand stages copied by LDS DMA, 64 deep
  * Every variant computes the same products; they differ in speed. */
 
 /* Time the matrix-product kernel alone: `reps` products C = X Y^T of size N

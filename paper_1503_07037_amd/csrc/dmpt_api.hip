@@ -24,6 +24,7 @@
 #include <functional>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include <rocprofiler-sdk-roctx/roctx.h>
@@ -71,6 +72,7 @@ struct WS {
   Group Zi;                      // T'^-1 of the current step (Newton-Schulz solver)
   double* rr = nullptr;          // CG <r,r> history [member][hstride]
   double* pq = nullptr;          // CG <p,Tp> history [member][hstride]
+  double* pb = nullptr;          // CG bounds of max |P| for its int8 slices [member][hstride]
   double* ref = nullptr;         // ||rhs||^2 [member]
   int* active = nullptr;         // CG masks [member]
   int* iters = nullptr;          // CG iteration counters [member]
@@ -740,6 +742,15 @@ dmpt_status cg_solve(const Call& k, const Group& u, int batch, int ydiv, const i
   EMIT(k, set_values(its, 0, batch, nullptr, 0.0, 0, s));
   EMIT(k, cg_check(rr, rr, ref, hs, batch, tol * tol, kEta * kEta, act, its, s));
   const int red_nb = reduce_blocks(n);
+  // int8 products: from the second iteration on, the direction update writes
+  // P's slices itself (its scale from a bound on max |P|), so P is not sliced
+  // again before the next product
+  Q8Reg* preg = nullptr;
+  if constexpr (std::is_same<T, double>::value) {
+    if (engine_int8(k.eng) && !k.rec && w->pb && c->d_qpart && batch <= kQ8Chunk)
+      for (auto& r : c->q8reg)
+        if (r.m == (const char*)w->P.m && r.stride == k.stride && r.count >= batch) preg = &r;
+  }
   const int cap = k.graph ? std::min(k.cg_iters, c->opt.max_cg) : c->opt.max_cg;
   for (int it = 0; it < cap && it + 1 < hs; ++it) {
     int live = -1;  // members still iterating (known on the host without a graph)
@@ -765,10 +776,20 @@ dmpt_status cg_solve(const Call& k, const Group& u, int batch, int ydiv, const i
     g.counted = live;
     STCHK(run_gemm(k, g));
     STCHK(sum_gemm_partials(k, batch, w->pq + it, hs, 0));
-    EMIT(k, cg_update_xr<T>(U, R, P, Q, n, st, batch, rr + it, pq + it, hs, act, part, s));
+    if (preg && it == 0) EMIT(k, q8_bound_init(preg->qs, w->pb, hs, batch, s));  // P sliced exactly above
+    EMIT(k, cg_update_xr<T>(U, R, P, Q, n, st, batch, rr + it, pq + it, hs, act, part, s,
+                            preg ? c->d_qpart : nullptr));
     EMIT(k, sum_partials(part, red_nb, batch, rr + it + 1, hs, 0, s));
-    EMIT(k, cg_update_p<T>(P, R, n, st, batch, rr + it + 1, rr + it, hs, act, ppl, np, s));
-    q8_touch(c, w->P, 0);  // ppl was fetched once: mark P's int8 slices stale on every write
+    if (preg) {
+      if constexpr (std::is_same<T, double>::value) {
+        EMIT(k, cg_update_p_q8(P, R, k.Np, st, batch, rr + it + 1, rr + it, hs, act, c->d_qpart, w->pb + it,
+                               w->pb + it + 1, preg->q8, st * kQ8Slices, preg->qs, s));
+      }
+      for (int z = 0; z < batch; ++z) preg->dirty[z] = 0;
+    } else {
+      EMIT(k, cg_update_p<T>(P, R, n, st, batch, rr + it + 1, rr + it, hs, act, ppl, np, s));
+      q8_touch(c, w->P, 0);  // ppl was fetched once: mark P's int8 slices stale on every write
+    }
     EMIT(k, cg_check(rr + it + 1, rr, ref, hs, batch, tol * tol, kEta * kEta, act, its, s));
   }
   if (k.graph) {
@@ -2798,6 +2819,10 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
   c->hstride = c->opt.max_cg + 2;
   c->ws.rr = (double*)alloc(sizeof(double) * dm * 512);
   c->ws.pq = (double*)alloc(sizeof(double) * dm * 512);
+  if (c->q8) {
+    c->ws.pb = (double*)alloc(sizeof(double) * dm * 512);
+    if (!c->ws.pb) return bail(DMPT_ERR_NOMEM, "device scalar allocation failed");
+  }
   c->ws.ref = (double*)alloc(sizeof(double) * dm);
   c->ws.active = (int*)alloc(sizeof(int) * dm);
   c->ws.iters = (int*)alloc(sizeof(int) * dm);

@@ -183,10 +183,21 @@ hipError_t trace(const T* x, int64_t ld, int64_t sx, int64_t N, int batch, doubl
 
 // CG updates (batched over right-hand sides z).
 //   update_xr: alpha = rr[z]/pq[z]; U += alpha P; R -= alpha Q; partials of <R,R>
+//   (and, when rmax is not null, block maxima of |R| at rmax[z * blocks + b])
 template <class T>
 hipError_t cg_update_xr(T* U, T* R, const T* P, const T* Q, int64_t n, int64_t stride, int batch,
                         const double* rr, const double* pq, int hstride, const int* active,
-                        double* partials, hipStream_t s);
+                        double* partials, hipStream_t s, double* rmax = nullptr);
+//   update_p with int8 slices (FP64, Np x Np members): P = R + beta P, and the
+//   slices of the new P (q8 + z sq bytes, q at qs[z]) from the scale bound
+//   max |R| (rmax from update_xr) + |beta| pb_old[z hstride], written to
+//   pb_new[z hstride]
+hipError_t cg_update_p_q8(double* P, const double* R, int64_t Np, int64_t stride, int batch, const double* rr_new,
+                          const double* rr_old, int hstride, const int* active, const double* rmax,
+                          const double* pb_old, double* pb_new, int8_t* q8, int64_t sq, double* qs,
+                          hipStream_t s);
+//   pb[z hstride] = 127 qs[z] (the bound of the first sliced P)
+hipError_t q8_bound_init(const double* qs, double* pb, int hstride, int batch, hipStream_t s);
 //   update_p: beta = rr_new[z]/rr_old[z]; P = R + beta P (+ planes)
 template <class T>
 hipError_t cg_update_p(T* P, const T* R, int64_t n, int64_t stride, int batch,

@@ -71,6 +71,21 @@ struct Planes {
 typedef double d2v __attribute__((ext_vector_type(2)));
 typedef float f2v __attribute__((ext_vector_type(2)));
 
+// Largest |x| of a block; any NaN or infinity makes it infinite, so the
+// member's q becomes infinite and its products non-finite.
+__device__ inline double block_max(double v) {
+  __shared__ double red[kT / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double m = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) m = fmax(m, red[i]);
+  return m;
+}
+
 template <class T>
 __device__ inline void ld2(const T* __restrict__ p, T (&v)[2]) {
   if constexpr (sizeof(T) == 8) {
@@ -254,7 +269,7 @@ __global__ __launch_bounds__(kT) void k_cg_xr(T* __restrict__ U, T* __restrict__
                                               const T* __restrict__ P, const T* __restrict__ Q,
                                               int64_t n, int64_t stride, const double* rr,
                                               const double* pq, int hstride, const int* active,
-                                              double* partials) {
+                                              double* partials, double* rmax) {
   const int z = blockIdx.y;
   if (active && !active[z]) {
     if (threadIdx.x == 0) partials[(int64_t)z * gridDim.x + blockIdx.x] = 0.0;
@@ -267,15 +282,23 @@ __global__ __launch_bounds__(kT) void k_cg_xr(T* __restrict__ U, T* __restrict__
   R += z * stride;
   P += z * stride;
   Q += z * stride;
-  double s = 0.0;
+  double s = 0.0, m = 0.0;
+  bool bad = false;
   for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
     U[i] += al * P[i];
     const T r = R[i] - al * Q[i];
     R[i] = r;
     s += (double)r * (double)r;
+    const double ar = fabs((double)r);
+    bad |= !(ar <= 1.0e308);  // NaN or infinity: the slicing scale becomes infinite
+    m = fmax(m, ar);
   }
   s = block_sum(s);
   if (threadIdx.x == 0) partials[(int64_t)z * gridDim.x + blockIdx.x] = s;
+  if (rmax) {
+    m = block_max(bad ? INFINITY : m);
+    if (threadIdx.x == 0) rmax[(int64_t)z * gridDim.x + blockIdx.x] = m;
+  }
 }
 
 template <class T>
@@ -702,21 +725,6 @@ __global__ __launch_bounds__(kT) void k_lin_axpy(double* P1, const double* PJ, i
 }
 
 // ---------------------------------------------------------------- int8 slices (I8S4)
-// Largest |x| of a block; any NaN or infinity makes it infinite, so the
-// member's q becomes infinite and its products non-finite.
-__device__ inline double block_max(double v) {
-  __shared__ double red[kT / 64];
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double m = 0.0;
-  if (threadIdx.x == 0)
-    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) m = fmax(m, red[i]);
-  return m;
-}
-
 __global__ __launch_bounds__(kT) void k_amax(const double* __restrict__ x, int64_t sx, int64_t n,
                                              double* __restrict__ part, int nb, const int* active) {
   const int z = blockIdx.y;
@@ -791,6 +799,80 @@ __global__ __launch_bounds__(kT) void k_quant(const double* __restrict__ x, int6
       *(uint4*)dst = make_uint4(w[0], w[1], w[2], w[3]);
     }
   }
+}
+
+// CG direction update P = R + beta P with the int8 slices of the new P
+// written in the same pass (I8S4 / I8S3 operands).  The slicing scale needs a
+// bound on max |P| before P exists: max |R| (block maxima from the residual
+// update) + |beta| times the previous bound, from the per-iteration bound
+// history pb (pb_old read, pb_new and the member's q written by block 0, so
+// no block reads what another block of this launch writes).  The bound is at
+// least the true maximum, so every digit fits; it can exceed it by at most
+// the previous bound's slack times beta (< 1 in practice), a fraction of a bit.
+__global__ __launch_bounds__(kT) void k_cg_p_q8(double* __restrict__ P, const double* __restrict__ R, int64_t Np,
+                                                int64_t stride, const double* rr_new, const double* rr_old,
+                                                int hstride, const int* active, const double* __restrict__ rmax,
+                                                int nb, const double* pb_old, double* pb_new, int8_t* __restrict__ q8,
+                                                int64_t sq, double* __restrict__ qs) {
+  const int z = blockIdx.y;
+  if (active && !active[z]) return;
+  __shared__ double sm;
+  double m = 0.0;
+  for (int i = threadIdx.x; i < nb; i += kT) m = fmax(m, rmax[(int64_t)z * nb + i]);
+  m = block_max(m);
+  if (threadIdx.x == 0) sm = m;
+  __syncthreads();
+  const double ro = rr_old[z * hstride];
+  const double beta = ro != 0.0 ? rr_new[z * hstride] / ro : 0.0;
+  const double bound = (sm + fabs(beta) * pb_old[z * hstride]) * (1.0 + 1.0e-12);
+  const double inv = (bound > 0.0 && bound <= 1.0e308) ? 127.0 / bound : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    pb_new[z * hstride] = bound;
+    qs[z] = bound / 127.0;
+  }
+  double* pm = P + (int64_t)z * stride;
+  const double* rm = R + (int64_t)z * stride;
+  int8_t* qm = q8 + (int64_t)z * sq;
+  const int64_t kbr = Np >> 5;
+  const int64_t pieces = kbr * kbr * 64;
+  for (int64_t u = (int64_t)blockIdx.x * kT + threadIdx.x; u < pieces; u += (int64_t)gridDim.x * kT) {
+    const int64_t blk = u >> 6;
+    const int l = (int)(u & 63);
+    const int64_t rb = blk / kbr, cb = blk - rb * kbr;
+    const int64_t off = (rb * 32 + (l & 31)) * Np + cb * 32 + (l >> 5) * 16;
+    int d[kQ8Slices][16];
+#pragma unroll
+    for (int e = 0; e < 16; e += 2) {
+      const d2v rv = *(const d2v*)(rm + off + e);
+      d2v pv = *(const d2v*)(pm + off + e);
+      pv.x = rv.x + beta * pv.x;
+      pv.y = rv.y + beta * pv.y;
+      *(d2v*)(pm + off + e) = pv;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        double r = (h ? pv.y : pv.x) * inv;
+#pragma unroll
+        for (int sl = 0; sl < kQ8Slices; ++sl) {
+          const double t = rint(r);
+          d[sl][e + h] = (int)t;
+          r = (r - t) * kQ8Base;
+        }
+      }
+    }
+#pragma unroll
+    for (int sl = 0; sl < kQ8Slices; ++sl) {
+      uint32_t w[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) w[q] = pack4(&d[sl][4 * q]);
+      *(uint4*)(qm + ((blk * kQ8Slices + sl) << 10) + l * 16) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+  }
+}
+
+// pb[z * hstride] = 127 q[z]: the bound history starts at the sliced maximum of the first P.
+__global__ void k_q8_bound_init(const double* qs, double* pb, int hstride, int batch) {
+  const int z = blockIdx.x * blockDim.x + threadIdx.x;
+  if (z < batch) pb[z * hstride] = 127.0 * qs[z];
 }
 
 inline unsigned red_grid(int64_t n) {
@@ -914,18 +996,37 @@ template hipError_t trace<float>(const float*, int64_t, int64_t, int64_t, int, d
 template <class T>
 hipError_t cg_update_xr(T* U, T* R, const T* P, const T* Q, int64_t n, int64_t stride, int batch,
                         const double* rr, const double* pq, int hstride, const int* active,
-                        double* partials, hipStream_t s) {
+                        double* partials, hipStream_t s, double* rmax) {
   // (element pairs per thread measured 4 % slower here than one element)
   hipLaunchKernelGGL(k_cg_xr<T>, dim3(red_grid(n), batch), dim3(kT), 0, s, U, R, P, Q, n, stride,
-                     rr, pq, hstride, active, partials);
+                     rr, pq, hstride, active, partials, rmax);
   return hipGetLastError();
 }
 template hipError_t cg_update_xr<double>(double*, double*, const double*, const double*, int64_t,
                                          int64_t, int, const double*, const double*, int,
-                                         const int*, double*, hipStream_t);
+                                         const int*, double*, hipStream_t, double*);
 template hipError_t cg_update_xr<float>(float*, float*, const float*, const float*, int64_t,
                                         int64_t, int, const double*, const double*, int, const int*,
-                                        double*, hipStream_t);
+                                        double*, hipStream_t, double*);
+
+hipError_t cg_update_p_q8(double* P, const double* R, int64_t Np, int64_t stride, int batch, const double* rr_new,
+                          const double* rr_old, int hstride, const int* active, const double* rmax,
+                          const double* pb_old, double* pb_new, int8_t* q8, int64_t sq, double* qs,
+                          hipStream_t s) {
+  if (Np <= 0 || Np % 32 != 0 || batch < 1) return hipErrorInvalidValue;
+  const int64_t n = Np * Np;
+  const int64_t pieces = n / 16;
+  int64_t g = (pieces + 2 * kT - 1) / (2 * kT);
+  if (g > 65535) g = 65535;
+  hipLaunchKernelGGL(k_cg_p_q8, dim3((unsigned)g, batch), dim3(kT), 0, s, P, R, Np, stride, rr_new, rr_old, hstride,
+                     active, rmax, (int)red_grid(n), pb_old, pb_new, q8, sq, qs);
+  return hipGetLastError();
+}
+
+hipError_t q8_bound_init(const double* qs, double* pb, int hstride, int batch, hipStream_t s) {
+  hipLaunchKernelGGL(k_q8_bound_init, dim3((batch + 63) / 64), dim3(64), 0, s, qs, pb, hstride, batch);
+  return hipGetLastError();
+}
 
 template <class T>
 hipError_t cg_update_p(T* P, const T* R, int64_t n, int64_t stride, int batch, const double* rr_new,

@@ -683,7 +683,8 @@ __device__ __forceinline__ void gemm_i8_tile(const GemmArgs& a, int z, int bx, i
   const int64_t kbr = Np >> 5;  // 32-wide blocks per block row
   int tm, tn;
   tile_coords(bx, (int)(Np / TM), (int)(Np / TM), tm, tn);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // the wave index is uniform: block addresses live in scalar registers
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / WN, wn = wave % WN;
   const int zx = z / a.X.div, zy = z / a.Y.div;
   const int8_t* xq = a.X.q8 + (int64_t)zx * a.X.stride * kQ8Slices;
@@ -783,6 +784,146 @@ __device__ __forceinline__ void gemm_i8_tile(const GemmArgs& a, int z, int bx, i
   }
 }
 
+// The same product with the operand stages copied by the LDS DMA path
+// (global_load_lds_dwordx4: each lane's 16 bytes go straight to LDS at
+// base + 16 lane, the 1 KB slice-block order): no staging registers and no
+// LDS write instructions, so a stage can hold 64 of k (two k blocks) in two
+// 64 KB LDS buffers, one barrier per 64 of k.  Per stage: wait for this
+// wave's copies of the stage, barrier (everyone's copies landed, everyone is
+// done with the other buffer), read the first k block's fragments, start the
+// copies of the next stage into the other buffer, multiply.
+template <int NW, int WM, int SD>
+__device__ __forceinline__ void gemm_i8_dma_tile(const GemmArgs& a, int z, int bx, int nbx) {
+  constexpr int TM = 128, BK = 64;
+  constexpr int S = SD;
+  constexpr int W = SD == 4 ? 5 : 3;
+  constexpr int WN = NW / WM;
+  constexpr int FM = TM / (32 * WM);
+  constexpr int FN = TM / (32 * WN);
+  constexpr int RB = TM / 32;
+  constexpr int KB = BK / 32;
+  constexpr int NBLK = RB * KB;
+  constexpr int SBLK = 2 * S * NBLK;
+  constexpr int LOADS = SBLK / NW;
+  constexpr int SBYTES = SBLK * 1024;
+  static_assert(SBLK % NW == 0, "a stage must split evenly over the waves");
+  static_assert(FN >= 1 && FM >= 1, "at least one MFMA tile per wave");
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  __shared__ double red[NW];
+  if (a.active && !a.active[z]) return;
+  count_member(a, bx);
+  const int64_t Np = a.Np;
+  const int64_t kbr = Np >> 5;
+  int tm, tn;
+  tile_coords(bx, (int)(Np / TM), (int)(Np / TM), tm, tn);
+  // the wave index is uniform: block addresses live in scalar registers
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave / WN, wn = wave % WN;
+  const int zx = z / a.X.div, zy = z / a.Y.div;
+  const int8_t* xq = a.X.q8 + (int64_t)zx * a.X.stride * kQ8Slices;
+  const int8_t* yq = a.Y.q8 + (int64_t)zy * a.Y.stride * kQ8Slices;
+  const double scale = a.X.qs[a.X.stride ? zx : 0] * a.Y.qs[a.Y.stride ? zy : 0];
+  const int8_t* src[LOADS];
+  int dst[LOADS];
+#pragma unroll
+  for (int j = 0; j < LOADS; ++j) {
+    const int q = wave + NW * j;
+    const int op = q / (S * NBLK), sl = (q / NBLK) % S, b = q % NBLK;
+    const int rb = b / KB, kb = b % KB;
+    const int64_t brow = (int64_t)(op ? tn : tm) * RB + rb;
+    src[j] = (op ? yq : xq) + (((brow * kbr + kb) * kQ8Slices + sl) << 10);  // uniform
+    dst[j] = q * 1024;  // uniform: the DMA adds 16 lane itself
+  }
+  auto issue = [&](int kt) {
+    const int64_t koff = (int64_t)kt * KB * kQ8Slices * 1024 + lane * 16;
+    unsigned char* base = smem + (kt & 1) * SBYTES;
+#pragma unroll
+    for (int j = 0; j < LOADS; ++j)
+      __builtin_amdgcn_global_load_lds((const void*)(src[j] + koff),
+                                       (__attribute__((address_space(3))) void*)(base + dst[j]), 16, 0, 0);
+  };
+  i16v acc[W][FM][FN];
+#pragma unroll
+  for (int w = 0; w < W; ++w)
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[w][i][j][r] = 0;
+  const int nk = (int)(Np / BK);
+  issue(0);
+  for (int kt = 0; kt < nk; ++kt) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's copies of stage kt
+    __syncthreads();
+    const unsigned char* sb = smem + (kt & 1) * SBYTES + lane * 16;
+#pragma unroll
+    for (int kk = 0; kk < KB; ++kk) {
+      i4v xa[S][FM], yb[S][FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+        xa[0][i] = __builtin_bit_cast(i4v, *(const u4v*)(sb + (((0 * NBLK) + (wm * FM + i) * KB + kk) << 10)));
+#pragma unroll
+      for (int q = 0; q < S; ++q)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          yb[q][j] = __builtin_bit_cast(
+              i4v, *(const u4v*)(sb + ((((S + q) * NBLK) + (wn * FN + j) * KB + kk) << 10)));
+#pragma unroll
+      for (int p = 1; p < S; ++p)
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+          xa[p][i] = __builtin_bit_cast(i4v, *(const u4v*)(sb + (((p * NBLK) + (wm * FM + i) * KB + kk) << 10)));
+      if (kk == 0 && kt + 1 < nk) issue(kt + 1);
+#pragma unroll
+      for (int p = 0; p < S; ++p)
+#pragma unroll
+        for (int q = 0; q < S && p + q < W; ++q)
+#pragma unroll
+          for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+              acc[p + q][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(xa[p][i], yb[q][j], acc[p + q][i][j], 0, 0, 0);
+    }
+  }
+  const double rb = 1.0 / kQ8Base;
+  double dsum = 0.0;
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t row = (int64_t)tm * TM + wm * (TM / WM) + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int64_t col = (int64_t)tn * TM + wn * (TM / WN) + j * 32 + (lane & 31);
+        double v = (double)acc[W - 1][i][j][r];
+#pragma unroll
+        for (int w = W - 2; w >= 0; --w) v = v * rb + (double)acc[w][i][j][r];
+        epi<double>(a, z, row, col, v * scale, dsum);
+      }
+  if (a.W) {
+    const double s = block_sum(dsum, red);
+    if (tid == 0) a.partials[(int64_t)z * nbx + bx] = s;
+  }
+}
+
+template <int NW, int WM, int SD>
+__global__ __launch_bounds__(NW * 64) void k_gemm_i8_dma(GemmArgs a) {
+  gemm_i8_dma_tile<NW, WM, SD>(a, blockIdx.z, blockIdx.x, gridDim.x);
+}
+
+template <int NW, int WM, int SD>
+__global__ __launch_bounds__(NW * 64) void k_gemm_i8_dma_grouped(const GemmArgs* __restrict__ list,
+                                                                  const int* __restrict__ start, int nprob) {
+  int p = 0;
+  const int b = blockIdx.x;
+  while (p + 1 < nprob && b >= start[p + 1]) ++p;
+  const GemmArgs& a = list[p];
+  const int tiles = (int)((a.Np / 128) * (a.Np / 128));
+  const int local = b - start[p];
+  gemm_i8_dma_tile<NW, WM, SD>(a, local / tiles, local % tiles, tiles);
+}
+
 template <int BK, int NW, int WM, int SD>
 __global__ __launch_bounds__(NW * 64) void k_gemm_i8(GemmArgs a) {
   gemm_i8_tile<BK, NW, WM, SD>(a, blockIdx.z, blockIdx.x, gridDim.x);
@@ -825,6 +966,54 @@ hipError_t launch_i8_grouped(const GemmArgs* list, const int* start, int nprob, 
   return hipGetLastError();
 }
 
+template <int SD>
+constexpr size_t i8_dma_lds() { return (size_t)2 * 2 * SD * 4 * 2 * 1024; }
+
+template <int NW, int WM, int SD>
+hipError_t prepare_i8_dma() {
+  hipError_t e = hipFuncSetAttribute((const void*)k_gemm_i8_dma<NW, WM, SD>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)i8_dma_lds<SD>());
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_gemm_i8_dma_grouped<NW, WM, SD>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)i8_dma_lds<SD>());
+}
+
+template <int NW, int WM, int SD>
+hipError_t launch_i8_dma(const GemmArgs& a, dim3 grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_gemm_i8_dma<NW, WM, SD>), grid, dim3(NW * 64), (i8_dma_lds<SD>()), s, a);
+  return hipGetLastError();
+}
+
+template <int NW, int WM, int SD>
+hipError_t launch_i8_dma_grouped(const GemmArgs* list, const int* start, int nprob, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL((k_gemm_i8_dma_grouped<NW, WM, SD>), dim3(blocks), dim3(NW * 64), (i8_dma_lds<SD>()), s, list,
+                     start, nprob);
+  return hipGetLastError();
+}
+
+// Int8 launch by variant: 0, 1 register-staged (32 x 64 / 64 x 32 wave tiles),
+// 2, 3 LDS DMA with 64-deep stages (same wave tiles).
+template <int SD>
+hipError_t launch_i8_variant(const GemmArgs& a, dim3 grid, hipStream_t s) {
+  switch (a.variant) {
+    case 1: return launch_i8<32, 8, 2, SD>(a, grid, s);
+    case 2: return launch_i8_dma<8, 4, SD>(a, grid, s);
+    case 3: return launch_i8_dma<8, 2, SD>(a, grid, s);
+    default: return launch_i8<32, 8, 4, SD>(a, grid, s);
+  }
+}
+
+template <int SD>
+hipError_t launch_i8_variant_grouped(int variant, const GemmArgs* list, const int* start, int nprob, int blocks,
+                                     hipStream_t s) {
+  switch (variant) {
+    case 1: return launch_i8_grouped<32, 8, 2, SD>(list, start, nprob, blocks, s);
+    case 2: return launch_i8_dma_grouped<8, 4, SD>(list, start, nprob, blocks, s);
+    case 3: return launch_i8_dma_grouped<8, 2, SD>(list, start, nprob, blocks, s);
+    default: return launch_i8_grouped<32, 8, 4, SD>(list, start, nprob, blocks, s);
+  }
+}
+
 }  // namespace
 
 // Kernel variants of each engine, chosen per padded size by the autotuner
@@ -834,14 +1023,15 @@ hipError_t launch_i8_grouped(const GemmArgs* list, const int* start, int nprob, 
 //   split BF16  0: 256 x 256 tiles where Np allows (else 128)   1: 128 x 128 tiles
 //   (the 6-product kernel with FP64 slice sums has 128 x 128 tiles only)
 //   int8 (both digit counts)  0: BK 32, 8 waves of 32 x 64   1: BK 32, 8 waves of 64 x 32
+//                             2, 3: the same wave tiles, LDS DMA copies, BK 64
 int gemm_variants(Engine eng, int acc64) {
   switch (eng) {
     case Engine::F64: return 3;
     case Engine::F32: return 3;
     case Engine::BF16S2: return 2;
     case Engine::BF16S3: return acc64 ? 1 : 2;
-    case Engine::I8S4: return 2;
-    case Engine::I8S3: return 2;
+    case Engine::I8S4: return 4;
+    case Engine::I8S3: return 4;
   }
   return 1;
 }
@@ -850,7 +1040,8 @@ const char* gemm_variant_name(Engine eng, int acc64, int v) {
   static const char* f64[3] = {"FP64 BK 8, 8 waves", "FP64 BK 16, 8 waves", "FP64 BK 8, 4 waves"};
   static const char* f32[3] = {"FP32 BK 32, 8 waves", "FP32 BK 16, 8 waves", "FP32 BK 32, 4 waves"};
   static const char* bf[2] = {"BF16 256 x 256 tiles", "BF16 128 x 128 tiles"};
-  static const char* i8[2] = {"int8 BK 32, 8 waves of 32 x 64", "int8 BK 32, 8 waves of 64 x 32"};
+  static const char* i8[4] = {"int8 BK 32, 8 waves of 32 x 64", "int8 BK 32, 8 waves of 64 x 32",
+                              "int8 LDS DMA, BK 64, 8 waves of 32 x 64", "int8 LDS DMA, BK 64, 8 waves of 64 x 32"};
   if (v < 0 || v >= gemm_variants(eng, acc64)) return "invalid";
   if (eng == Engine::I8S4 || eng == Engine::I8S3) return i8[v];
   if (eng == Engine::F64) return f64[v];
@@ -879,6 +1070,10 @@ hipError_t gemm_prepare() {
   if ((e = prepare_i8<32, 8, 4, 4>())) return e;
   if ((e = prepare_i8<32, 8, 2, 3>())) return e;
   if ((e = prepare_i8<32, 8, 4, 3>())) return e;
+  if ((e = prepare_i8_dma<8, 4, 4>())) return e;
+  if ((e = prepare_i8_dma<8, 2, 4>())) return e;
+  if ((e = prepare_i8_dma<8, 4, 3>())) return e;
+  if ((e = prepare_i8_dma<8, 2, 3>())) return e;
   return prepare_bf16<3, 256, 16, kWaves256>();
 }
 
@@ -897,9 +1092,7 @@ hipError_t gemm(const GemmArgs& a, hipStream_t s) {
     case Engine::I8S4:
     case Engine::I8S3:
       if (a.Np > kQ8MaxK || !a.X.q8 || !a.Y.q8 || !a.X.qs || !a.Y.qs) return hipErrorInvalidValue;
-      if (a.eng == Engine::I8S3)
-        return a.variant == 1 ? launch_i8<32, 8, 2, 3>(a, grid, s) : launch_i8<32, 8, 4, 3>(a, grid, s);
-      return a.variant == 1 ? launch_i8<32, 8, 2, 4>(a, grid, s) : launch_i8<32, 8, 4, 4>(a, grid, s);
+      return a.eng == Engine::I8S3 ? launch_i8_variant<3>(a, grid, s) : launch_i8_variant<4>(a, grid, s);
     case Engine::F64:
       if (a.variant == 1) hipLaunchKernelGGL((k_gemm_f64<16, 8>), grid, dim3(8 * 64), 0, s, a);
       else if (a.variant == 2) hipLaunchKernelGGL((k_gemm_f64<8, 4>), grid, dim3(4 * 64), 0, s, a);
@@ -928,12 +1121,8 @@ hipError_t gemm_grouped(Engine eng, int variant, int acc64, int edge, const Gemm
                         int nprob, int blocks, hipStream_t s) {
   if (nprob < 1 || blocks < 1 || variant < 0 || variant >= gemm_variants(eng, acc64)) return hipErrorInvalidValue;
   switch (eng) {
-    case Engine::I8S4:
-      if (variant == 1) return launch_i8_grouped<32, 8, 2, 4>(list, start, nprob, blocks, s);
-      return launch_i8_grouped<32, 8, 4, 4>(list, start, nprob, blocks, s);
-    case Engine::I8S3:
-      if (variant == 1) return launch_i8_grouped<32, 8, 2, 3>(list, start, nprob, blocks, s);
-      return launch_i8_grouped<32, 8, 4, 3>(list, start, nprob, blocks, s);
+    case Engine::I8S4: return launch_i8_variant_grouped<4>(variant, list, start, nprob, blocks, s);
+    case Engine::I8S3: return launch_i8_variant_grouped<3>(variant, list, start, nprob, blocks, s);
     case Engine::F64:
       if (variant == 1) hipLaunchKernelGGL((k_gemm_f64_grouped<16, 8>), dim3(blocks), dim3(8 * 64), 0, s, list, start, nprob);
       else if (variant == 2) hipLaunchKernelGGL((k_gemm_f64_grouped<8, 4>), dim3(blocks), dim3(4 * 64), 0, s, list, start, nprob);
