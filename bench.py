@@ -9,8 +9,11 @@ canonical Newton loop of Algorithm 1: split-BF16 (3-product) matrix products
 with FP32 accumulation until mu0 is close, then the final passes (one order-0
 pass and the linear schedule's order-1 and order-2 passes) with int8-slice
 products (each operand as one scale per matrix times four signed int8 digits,
-the thirteen digit products of weight <= 4 summed exactly in int32).  Inputs are synthetic, seeded, already resident in HBM
-when the timed region starts.
+the thirteen digit products of weight <= 4 summed exactly in int32).  Per-step
+solves: CG in the order-0 passes; in the order-1 and order-2 passes the shared
+inverse of T' by Newton-Schulz (built once per step in the order-1 pass, kept,
+and applied with one product per right-hand side).  Inputs are synthetic,
+seeded, already resident in HBM when the timed region starts.
 
 One step = one complete canonical solve (dmpt_mu_newton): every Newton pass,
 every recursion step, every order and direction.  value = response solves
@@ -24,8 +27,8 @@ the FP64 CPU oracle timed on a bounded sample on this host.  The roofline's
 counter summary profiles/traffic_<engine>.json when it was taken on the
 current product-kernel source, else null.
 
-The accuracy-matched FP64 form (the same library in DMPT_FP64, Newton-Schulz
-solver) is timed on the same workload after the timed region (one solve;
+The accuracy-matched FP64 form (the same library in DMPT_FP64, same solvers)
+is timed on the same workload after the timed region (one solve;
 --no-fp64-compare skips it).  roofline.achieved is the algorithmic rate of
 the dominant kernel: 2 N^3 flops per logical matrix product (every split
 product of the same logical product counts once) over the kernel's device
@@ -75,8 +78,9 @@ def parse():
                          "6-product split-BF16 passes (1) or not at all (0)")
     ap.add_argument("--acc64", type=int, default=1,
                     help="6-product products: FP32 per 32-wide k slice, FP64 across slices (default 1)")
-    ap.add_argument("--solver", default="cg", choices=["cg", "ns"],
-                    help="per-step solver: conjugate gradients or the Newton-Schulz shared inverse")
+    ap.add_argument("--solver", default="hybrid", choices=["cg", "ns", "hybrid"],
+                    help="per-step solver: conjugate gradients, the Newton-Schulz shared inverse, or CG "
+                         "in order-0 passes and the shared inverse in passes with jets")
     ap.add_argument("--no-fp64-compare", action="store_true",
                     help="skip the FP64 solve of the same workload on the GPU")
     ap.add_argument("--order", type=int, default=-1,
@@ -93,15 +97,20 @@ def kernel_source_sha():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def measured_traffic(engine):
-    """HBM bytes per launch of the product kernel from the committed counter summary, or None."""
+def measured_traffic(engine, alg_bytes_per_launch):
+    """HBM bytes per launch of the product kernel from the committed counter summary, or None
+    when the kernel source changed since the counters were taken or the summary covers another
+    launch mix (its algorithmic bytes per launch differ from this run's by more than 1 %)."""
     path = os.path.join(ROOT, "profiles", f"traffic_{engine}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
     if t.get("kernel_source_sha256") != kernel_source_sha():
-        return None  # the kernel changed since the counters were taken
+        return None
+    ref = t.get("algorithmic_bytes_per_launch", 0.0)
+    if not ref or abs(ref - alg_bytes_per_launch) > 0.01 * ref:
+        return None
     return t
 
 
@@ -188,11 +197,12 @@ def accuracy(name, P0, P1, P2, mu, st=None):
 
 
 def fp64_gpu(dm, c, H0, H1, d, order):
-    """One FP64 canonical solve of the same workload on the GPU, with the faster FP64 solver
-    (the Newton-Schulz shared inverse: one product per right-hand side, no refinement needed)."""
+    """One FP64 canonical solve of the same workload on the GPU, with the same solvers as the
+    timed form (CG in the order-0 passes, the shared inverse in the passes with jets; its fastest
+    FP64 form)."""
     import torch
     N = c["N"]
-    ctx = dm.Context(N, dirs_max=d, prec="fp64", solver="ns")
+    ctx = dm.Context(N, dirs_max=d, prec="fp64", solver="hybrid")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     out = ctx.mu_newton(H0, H1, None, beta=c["beta"], Ne=c["Ne"], n=c["n"], order=order)
@@ -200,7 +210,7 @@ def fp64_gpu(dm, c, H0, H1, d, order):
     secs = time.perf_counter() - t0
     st = out[4]
     ctx.close()
-    return out, {"seconds": secs, "value": d / secs, "unit": "responses/s", "solver": "ns",
+    return out, {"seconds": secs, "value": d / secs, "unit": "responses/s", "solver": "hybrid",
                  "newton_iters": st["newton_iters"], "cg_iters_total": st["cg_iters_total"],
                  "mfma_tflops": st["mfma_flops"] / secs / 1e12}
 
@@ -456,7 +466,7 @@ def main():
     peak = PEAKS_TFLOPS[dom]
     name = args.workload if not args.n else None
     acc = accuracy(name, P0, P1, P2, mu, st) if name else None
-    traffic = measured_traffic(dom)
+    traffic = measured_traffic(dom, pe["bytes"] / max(pe["launches"], 1))
     res = {
         "metric": "response solves/sec (P0+P1+P2) and MFMA TFLOP/s at N=8192, err <=1e-6 vs FP64",
         "value": value, "unit": "responses/s", "n_gpus": 1, "steps": args.steps,

@@ -81,10 +81,21 @@ typedef enum {
 /* Per-step linear solver for T' Y = R, T' = I + 4 D^2 (2 T of Algorithm 1). */
 typedef enum {
   DMPT_SOLVER_CG = 0,  /* conjugate gradients, one product per iteration and right-hand side (Sec. II) */
-  DMPT_SOLVER_NS = 1   /* shared inverse Z of T' by Newton-Schulz (four steps from the minimax linear
-                          start), reused for every order and direction (Sec. II remark): one product
-                          per right-hand side, plus one refinement step below FP64; single-system
-                          paths (the batched and adjoint paths keep CG) */
+  DMPT_SOLVER_NS = 1,  /* shared inverse Z of T' by Newton-Schulz from the minimax linear start on
+                          the step's spectral interval [1, 1 + 4 b^2], b = min(1/2, 2^step ||D_0||)
+                          with ||D_0|| from the Gershgorin interval of H0 (four steps once
+                          ||D|| ~ 1/2, none while ||D|| < ~1e-5), reused for every order and
+                          direction (Sec. II remark): one product per right-hand side, plus one
+                          refinement step with FP32, BF16 and INT8X6 products; single-system paths
+                          (the batched and adjoint paths keep CG).  In the environment,
+                          DMPT_NS_ITERS=k forces k steps everywhere and DMPT_NS_REFINE=0|1 the
+                          refinement step off or on (debugging) */
+  DMPT_SOLVER_HYBRID = 2 /* CG in passes of order 0 (one right-hand side per step, warm-started), the
+                            shared inverse in passes that carry jets when the products are FP64 or
+                            INT8X13 (other products keep CG there: the inverse's rounding biases
+                            the jets' traces); under the linear schedule the order-1 pass keeps Z
+                            of every step (n N^2 master elements, when the memory is there) and
+                            the later passes reuse it */
 } dmpt_solver;
 
 /* Initial guess of the conjugate-gradient solve. */

@@ -26,7 +26,7 @@ STATUS_NAMES = {
 }
 
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3, "int8x13": 4, "int8x6": 5}
-SOLVER = {"cg": 0, "ns": 1}
+SOLVER = {"cg": 0, "ns": 1, "hybrid": 2}
 GUESS = {"prev": 0, "taylor": 1}
 MAX_DIRS = 8
 

@@ -136,6 +136,12 @@ struct dmpt_ctx_s {
   // loaded by the order-2 pass instead of forming them again (optional)
   void* ss = nullptr;
   size_t ss_bytes = 0;
+  // per step the shared inverse Z of T' (Newton-Schulz passes of the linear
+  // schedule: the order-1 pass saves it, the order-2 and -3 passes load it)
+  void* zs = nullptr;
+  size_t zs_bytes = 0;
+  int ns_iters_env = 0;          // DMPT_NS_ITERS (experiments: Newton-Schulz steps)
+  int ns_refine_env = -1;        // DMPT_NS_REFINE (experiments: 0/1 refinement step)
   int64_t tj_np = 0;
   int tj_valid = -1;
   Group U0;                      // order-0 CG unknown when the guess comes from tj
@@ -189,6 +195,13 @@ enum : int {
 };
 
 inline int res_hp(int k, int j, int z) { return RES_HP + ((k - 1) * 4 + j) * DMPT_MAX_DIRS + z; }
+
+// DMPT_LOG lines: seconds on the host's steady clock (differences time the
+// passes, each of which ends with a stream synchronisation) and the executed
+// matrix-core work so far.
+double log_clock() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
 
 dmpt_status fail(dmpt_ctx c, dmpt_status s, const std::string& msg) {
   if (c) c->err = msg;
@@ -350,6 +363,8 @@ struct Call {
   double* part = nullptr;        // partial sums of this call's products and reductions
   size_t part_count = 0;         // ... and their capacity
   std::vector<Op>* rec = nullptr;  // when set, launches are recorded here instead of issued
+  double glo = NAN, ghi = NAN;   // Gershgorin interval of sym(H0), when the caller scanned it
+  double d0b = -1.0;             // this pass: a bound on ||D_0||_2 (< 0: none known)
 };
 
 // Issue a launch of the recursion step code now, or record it (k.rec).
@@ -369,6 +384,8 @@ struct Call {
 constexpr int kSave01 = 1, kLoad01 = 2, kSave2 = 4, kLoad2 = 8;
 // ... and save or load the square terms S0, S1 of every step (c->ss, see ss_ptr)
 constexpr int kSaveS = 16, kLoadS = 32;
+// ... and save or load the shared inverse Z of every step (c->zs)
+constexpr int kSaveZ = 64, kLoadZ = 128;
 
 // Member z of a group as an operand.
 BOp op(const Call& k, const Group& g, int z, bool batched) {
@@ -1095,19 +1112,79 @@ dmpt_status solve_order0(const Call& k, int step) {
 // Z <- Z (2 I - T' Z): the error squares each time, 17^-16 after four
 // iterations.  Z is a polynomial in S0, so it commutes with T' and stays
 // symmetric; it is re-symmetrised after every iteration.  Single system only.
+//
+// Early steps need far less: |f(d)| <= 2 |d| for the map f(d) = 2d / (1 + 4d^2),
+// so ||D_s|| <= b_s = min(1/2, 2^s ||D_0||), with ||D_0|| <= c max|eps - mu0|
+// from the Gershgorin interval of H0.  T' then has its eigenvalues in
+// [1, 1 + delta], delta = 4 b_s^2, where the minimax linear start (the
+// degree-2 Chebyshev residual on that interval) has error
+// e0 = delta^2 / (8 + 8 delta + delta^2) -- 1/17 at delta = 1, ~ delta^2 / 8
+// for small delta -- and the iteration count is the smallest k with
+// e0^(2^k) <= 2^-60: four at delta = 1, none while ||D_s|| is below ~1e-5.
 constexpr int kNsIters = 4;
 
+struct NsStart {
+  double a, b;  // Z0 = a I + b S0
+  int iters;
+};
+
+NsStart ns_start(const Call& k, int step) {
+  double delta = 1.0;
+  if (k.d0b >= 0.0 && step >= 0) {
+    const double bs = std::min(0.5, std::ldexp(k.d0b, std::min(step, 1000)) * (1.0 + 1e-3));
+    delta = std::min(1.0, 4.0 * bs * bs);
+  }
+  const double den = 8.0 + 8.0 * delta + delta * delta;
+  NsStart z{(8.0 + 8.0 * delta) / den, -32.0 / den, 0};
+  const double e0 = delta * delta / den;
+  double e = e0;
+  while (e > 0x1p-60 && z.iters < kNsIters) {
+    e = e * e;
+    ++z.iters;
+  }
+  if (k.c->ns_iters_env > 0) z.iters = k.c->ns_iters_env;
+  return z;
+}
+
+// Whether a solve with Z is followed by one refinement step: with FP32 and
+// split-BF16 products Z and R Z carry the products' rounding (1e-7 .. 1e-5),
+// and one residual correction recovers it.  FP64 products need none, and
+// neither do the 13-product int8 ones: their only error is the dropped digit
+// products (~1e-10 relative), the same as in a CG solve with those products
+// (at N = 8192 the solve without the step matched or beat the CG form).
+bool ns_refines(const Call& k) {
+  if (k.c->ns_refine_env >= 0) return k.c->ns_refine_env != 0;
+  return k.eng != Engine::F64 && k.eng != Engine::I8S4;
+}
+
+// Whether the steps of a pass of this order solve with the shared inverse:
+// always with DMPT_SOLVER_NS; with DMPT_SOLVER_HYBRID only in passes that
+// carry jets (one inverse then serves 1 + d or more right-hand sides, while
+// an order-0 pass has one, where CG from a warm start needs fewer products),
+// and only with FP64 or 13-product int8 products.  With split-BF16 products
+// the inverse's own rounding biases the traces of the jets (Tr(H1 P2) 1.8e-6
+// with BF16X6 at N = 8192, against 5e-7 with CG), so those passes keep CG.
+bool ns_pass(const Call& k, int order) {
+  const dmpt_solver sv = k.c->opt.solver;
+  const bool hybrid_ns = sv == DMPT_SOLVER_HYBRID && order >= 1 &&
+                         (k.eng == Engine::F64 || k.eng == Engine::I8S4);
+  return (sv == DMPT_SOLVER_NS || hybrid_ns) && k.m == 1 && !k.graph;
+}
+
 template <class T>
-dmpt_status ns_inverse(const Call& k) {
+dmpt_status ns_inverse(const Call& k, int step) {
   dmpt_ctx c = k.c;
   const WS* w = k.w;
   hipStream_t s = c->stream;
   if (k.m != 1) return fail(c, DMPT_ERR_ARG, "internal: Newton-Schulz runs on one system");
   uint16_t* pz[3];
   planes_of(k, w->Zi, 0, pz);
-  HIPCHK(c, scaled_plus_identity<T>((const T*)mptr(k, w->S0, 0), (T*)mptr(k, w->Zi, 0), k.N, k.Np,
-                                    16.0 / 17.0, -32.0 / 17.0, pz, k.np, s));
-  for (int it = 0; it < kNsIters; ++it) {
+  const NsStart z0 = ns_start(k, step);
+  HIPCHK(c, scaled_plus_identity<T>((const T*)mptr(k, w->S0, 0), (T*)mptr(k, w->Zi, 0), k.N, k.Np, z0.a,
+                                    z0.b, pz, k.np, s));
+  q8_touch(c, w->Zi, 0);
+  const int iters = z0.iters;
+  for (int it = 0; it < iters; ++it) {
     G g;  // M = T' Z = Z + 4 S0 Z  -> P[0] (with planes)
     g.X = op(k, w->S0, 0, false);
     g.Y = op(k, w->Zi, 0, false);
@@ -1152,7 +1229,7 @@ dmpt_status ns_solve(const Call& k, const Group& g, int md) {
   planes_of(k, g, 0, a.Cpl);
   a.batch = md;
   STCHK(run_gemm(k, a));
-  if (k.eng != Engine::F64) {
+  if (ns_refines(k)) {
     G r;  // R -= U + 4 U S0
     r.X = op(k, g, 0, true);
     r.Y = op(k, w->S0, 0, true);
@@ -1204,6 +1281,30 @@ dmpt_status solve_jet(const Call& k, const Group& g, int md, int d) {
   return DMPT_OK;
 }
 
+// Inverse store (c->zs, masters): per step the shared inverse Z of T'.
+bool zs_fits(const Call& k, int step) {
+  return step >= 0 && ((size_t)step + 1) * (size_t)k.nn * k.c->esize <= k.c->zs_bytes;
+}
+
+template <class T>
+dmpt_status zs_save(const Call& k, int step) {
+  if (!zs_fits(k, step)) return fail(k.c, DMPT_ERR_ARG, "internal: inverse-store index");
+  uint16_t* none[3] = {nullptr, nullptr, nullptr};
+  HIPCHK(k.c, (convert<T, T>((const T*)mptr(k, k.w->Zi, 0), 0, (T*)k.c->zs + (size_t)step * k.nn, 0, k.nn,
+                             1, none, 0, 0, k.c->stream)));
+  return DMPT_OK;
+}
+
+template <class T>
+dmpt_status zs_load(const Call& k, int step) {
+  if (!zs_fits(k, step)) return fail(k.c, DMPT_ERR_ARG, "internal: inverse-store index");
+  uint16_t* pl[3];
+  planes_of(k, k.w->Zi, 0, pl);
+  HIPCHK(k.c, (convert<T, T>((const T*)k.c->zs + (size_t)step * k.nn, 0, (T*)mptr(k, k.w->Zi, 0), 0, k.nn,
+                             1, pl, 0, k.w->Zi.pl[0] ? k.np : 0, k.c->stream)));
+  return DMPT_OK;
+}
+
 // One recursion step for orders 0..order, d directions per system, on the
 // iterates held in k.w (Algorithm 1's inner loop body, in D form).
 template <class T>
@@ -1214,8 +1315,12 @@ dmpt_status recursion_step(const Call& k, int order, int d, int step) {
   if (k.chain & kLoadS) STCHK(ss_load<T>(k, w->S0, 0, step, 0, 0.0, 0));
   else STCHK(square0<T>(k));
   if (k.chain & kSaveS) STCHK(ss_save<T>(k, w->S0, 0, step, 0));
-  const bool ns = c->opt.solver == DMPT_SOLVER_NS && k.m == 1 && !k.graph;
-  if (ns) STCHK(ns_inverse<T>(k));
+  const bool ns = ns_pass(k, order);
+  if (ns) {
+    if (k.chain & kLoadZ) STCHK(zs_load<T>(k, step));
+    else STCHK(ns_inverse<T>(k, step));
+    if (k.chain & kSaveZ) STCHK(zs_save<T>(k, step));
+  }
   if (order >= 1 && (k.chain & kLoadS)) {
     // the order-1 pass stored S1 at mu1 = 0; S1 is linear in mu1: S1 = S1(0) - mu1 S1_J
     for (int z = 0; z < md; ++z) STCHK(ss_load<T>(k, w->S1, z, step, 1 + z, k.cmu[z], k.cj));
@@ -1467,8 +1572,11 @@ dmpt_status debug_step(const Call& k, int order, int d, int step) {
 
 // One full pass of the recursion for orders 0..order (single system).
 template <class T>
-dmpt_status recursion_pass(const Call& k, const PassIn& in) {
+dmpt_status recursion_pass(const Call& k0, const PassIn& in) {
   const double cscale = std::ldexp(in.beta, -(in.n + 2));
+  Call k = k0;
+  if (std::isfinite(k0.glo) && std::isfinite(k0.ghi) && in.mu)
+    k.d0b = cscale * std::max(std::fabs(k0.glo - in.mu[0]), std::fabs(k0.ghi - in.mu[0]));
   STCHK(init_d<T>(k, in, cscale));
   for (int step = 0; step < in.n; ++step) {
     Range r("dmpt recursion step %d", step);
@@ -2263,6 +2371,24 @@ bool ensure_squares(dmpt_ctx c, int n, int members, int64_t Np) {
   return true;
 }
 
+// Inverse store for n steps of one Np x Np master; false when the memory is
+// not there (the later passes then build Z again).
+bool ensure_inverses(dmpt_ctx c, int n, int64_t Np) {
+  const size_t need = (size_t)n * (size_t)Np * Np * c->esize;
+  if (c->zs && c->zs_bytes >= need) return true;
+  if (c->zs) {
+    (void)hipStreamSynchronize(c->stream);
+    dev_free(c, c->zs);
+    c->zs = nullptr;
+    c->zs_bytes = 0;
+  }
+  void* p = dev_alloc(c, need);
+  if (!p) return false;
+  c->zs = p;
+  c->zs_bytes = need;
+  return true;
+}
+
 // Occupation error of Algorithm 1 (*occ_err, absolute) and its normalised
 // form (*rel): max(|Tr P0 - Ne| / N, max_k |Tr P^(k)| / sum_i |P^(k)_ii|).
 void occupation_error(const double* res, int d, int order, double Ne, int64_t N, double* occ_err,
@@ -2317,13 +2443,15 @@ dmpt_status linear_orders(Call& k, const PassIn& base, int64_t N, int order, dou
   const bool keep = order >= 2 && c->opt.schedule == 1 && ensure_chain(c, base.n, cs, k.Np);
   // and the square terms S0, S1 (d directions and J) for the order-2 pass
   const bool keep_s = keep && ensure_squares(c, base.n, 2 + d, k.Np);
+  // and, when these passes solve with the shared inverse, Z of every step
+  const bool keep_z = keep_s && ns_pass(k, 1) && ns_pass(k, 2) && ensure_inverses(c, base.n, k.Np);
   k.cs = cs;
   k.cj = 1 + d;
   double trJ = 0.0, prev = INFINITY;
   constexpr int kMaxPasses = 4;
   for (int a = 0; a < kMaxPasses; ++a) {
     m1[0] = mu[0];
-    k.chain = keep ? (kSave01 | (keep_s ? kSaveS : 0)) : 0;
+    k.chain = keep ? (kSave01 | (keep_s ? kSaveS : 0) | (keep_z ? kSaveZ : 0)) : 0;
     STCHK(pass_dispatch(k, in1, P0, p1x.data(), nullptr));
     k.chain = 0;
     *passes += 1;
@@ -2332,8 +2460,10 @@ dmpt_status linear_orders(Call& k, const PassIn& base, int64_t N, int order, dou
       return fail(c, DMPT_ERR_NOCONV, "Tr J vanished: the occupation does not respond to mu");
     const double rel = std::fabs(c->h_res[RES_TR] - Ne) / (double)N;
     if (c->log)
-      std::fprintf(stderr, "[dmpt] order-1 pass: mu0 %.15g TrP0-Ne %.3e rel %.3e TrJ %.6e cg_total %ld\n",
-                   mu[0], c->h_res[RES_TR] - Ne, rel, trJ, c->cg_total);
+      std::fprintf(stderr,
+                   "[dmpt] order-1 pass: mu0 %.15g TrP0-Ne %.3e rel %.3e TrJ %.6e cg_total %ld t %.4f "
+                   "mfma %.4e\n",
+                   mu[0], c->h_res[RES_TR] - Ne, rel, trJ, c->cg_total, log_clock(), c->mfma_flops);
     if (rel <= tol || (rel > 0.5 * prev && rel <= 1e3 * tol)) {
       if (rel > tol) c->flags |= DMPT_FLAG_NOISE_FLOOR;
       *settled = true;
@@ -2351,13 +2481,15 @@ dmpt_status linear_orders(Call& k, const PassIn& base, int64_t N, int order, dou
     std::vector<double> m2(1 + 3 * DMPT_MAX_DIRS, 0.0);
     for (int i = 0; i <= d; ++i) m2[i] = mu[i];
     PassIn in2{base.H0, d, base.H1, base.H2, base.beta, base.n, 2, m2.data()};
-    k.chain = keep ? (kLoad01 | (keep_s ? kLoadS : 0) | (order >= 3 ? kSave2 : 0)) : 0;
+    k.chain = keep ? (kLoad01 | (keep_s ? kLoadS : 0) | (keep_z ? kLoadZ : 0) | (order >= 3 ? kSave2 : 0)) : 0;
     k.cmu = mu + 1;
     STCHK(pass_dispatch(k, in2, P0, P1, P2));
     k.chain = 0;
     k.cmu = nullptr;
     *passes += 1;
-    if (c->log) std::fprintf(stderr, "[dmpt] order-2 pass: cg_total %ld\n", c->cg_total);
+    if (c->log)
+      std::fprintf(stderr, "[dmpt] order-2 pass: cg_total %ld t %.4f mfma %.4e\n", c->cg_total, log_clock(),
+                   c->mfma_flops);
     for (int z = 0; z < d; ++z) {
       mu[1 + d + z] = c->h_res[RES_TR + 1 + d + z] / trJ;
       HIPCHK(c, axpby<double>(c->jout, 0, P2[z], 0, nn, 1, -mu[1 + d + z], 1.0, none, 0, 0, s));
@@ -2370,7 +2502,7 @@ dmpt_status linear_orders(Call& k, const PassIn& base, int64_t N, int order, dou
     for (int i = 0; i <= 2 * d; ++i) m3[i] = mu[i];
     PassIn in3{base.H0, d, base.H1, base.H2, base.beta, base.n, 3, m3.data()};
     in3.H3 = base.H3;
-    k.chain = keep ? (kLoad01 | kLoad2) : 0;
+    k.chain = keep ? (kLoad01 | kLoad2 | (keep_z ? kLoadZ : 0)) : 0;
     k.cmu = mu + 1;
     STCHK(pass_dispatch(k, in3, P0, P1, P2, P3));
     k.chain = 0;
@@ -2701,7 +2833,7 @@ static dmpt_status normalise_options(dmpt_ctx c, const dmpt_options* in, dmpt_op
   if (in) o = *in; else dmpt_default_options(&o);
   if (o.prec < DMPT_FP64 || o.prec > DMPT_INT8X6) return fail(c, DMPT_ERR_ARG, "unknown precision");
   if (o.refine < 0 || o.refine > 2) return fail(c, DMPT_ERR_ARG, "refine must be 0, 1 or 2");
-  if (o.solver != DMPT_SOLVER_CG && o.solver != DMPT_SOLVER_NS)
+  if (o.solver != DMPT_SOLVER_CG && o.solver != DMPT_SOLVER_NS && o.solver != DMPT_SOLVER_HYBRID)
     return fail(c, DMPT_ERR_ARG, "unknown solver");
   if (o.guess != DMPT_GUESS_PREV && o.guess != DMPT_GUESS_TAYLOR)
     return fail(c, DMPT_ERR_ARG, "unknown initial guess");
@@ -2768,6 +2900,8 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
   if (gemm_prepare() != hipSuccess) return bail(DMPT_ERR_HIP, "product kernel attributes");
   c->log = std::getenv("DMPT_LOG") != nullptr;
   c->debug = std::getenv("DMPT_DEBUG_CHECKS") != nullptr;
+  if (const char* e = std::getenv("DMPT_NS_ITERS")) c->ns_iters_env = std::atoi(e);
+  if (const char* e = std::getenv("DMPT_NS_REFINE")) c->ns_refine_env = std::atoi(e);
   c->n_max = n_max;
   c->np_max = padded(n_max);
   c->dirs_max = dirs_max;
@@ -3176,6 +3310,7 @@ dmpt_status dmpt_finalize(dmpt_ctx c) {
   if (c->tj) dev_free(c, c->tj);
   if (c->st) dev_free(c, c->st);
   if (c->ss) dev_free(c, c->ss);
+  if (c->zs) dev_free(c, c->zs);
   if (c->ev_in) (void)hipEventDestroy(c->ev_in);
   if (c->ev_out) (void)hipEventDestroy(c->ev_out);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -3497,6 +3632,8 @@ dmpt_status dmpt_response(dmpt_ctx c, int64_t N, const double* H0, int d, const 
   if (beta * emax >= std::ldexp(1.0, n + 1))
     return fail(c, DMPT_ERR_RANGE, "beta * max|eps - mu| >= 2^(n+1): the recursion's start leaves [0, 1]");
   Call k = make_call(c, N, true);
+  k.glo = glo;
+  k.ghi = ghi;
   STCHK(pass_dispatch(k, in, P0, P1, P2, P3));
   double occ = 0;
   for (int i = 1; i < nmu; ++i) occ += std::fabs(c->h_res[RES_TR + i]);
@@ -3523,6 +3660,7 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
   ENTER(c);
   const auto t0 = std::chrono::steady_clock::now();
   reset_stats(c);
+  if (c->log) std::fprintf(stderr, "[dmpt] mu_newton N %lld d %d order %d t %.4f\n", (long long)N, d, order, log_clock());
   const int dd = order >= 1 ? d : 0;
   const int nmu = 1 + order * dd;
   std::vector<double> mu(1 + 3 * DMPT_MAX_DIRS, 0.0);
@@ -3555,6 +3693,8 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
   // tolerances) brings the mu jet close, then the 6-product engine with the
   // final tolerances finishes; otherwise a single phase.
   Call k = make_call(c, N, false);
+  k.glo = glo;
+  k.ghi = ghi;
   const bool two_phase = refinable(c->opt.prec) && c->opt.refine;
   struct Phase {
     Engine eng;
@@ -3609,8 +3749,9 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
     if (c->log)
       std::fprintf(stderr,
                    "[dmpt] pass %d phase %d engine %d order %d mu0 %.15g TrP0-Ne %.3e occ_err %.3e "
-                   "rel %.3e cg_total %ld\n",
-                   it, ph, (int)P.eng, stage_order, mu[0], r[RES_TR] - Ne, occ, rel, c->cg_total);
+                   "rel %.3e cg_total %ld t %.4f mfma %.4e\n",
+                   it, ph, (int)P.eng, stage_order, mu[0], r[RES_TR] - Ne, occ, rel, c->cg_total, log_clock(),
+                   c->mfma_flops);
     // noise floor: a normalised error that stopped shrinking and is within
     // 1000 tol_occ counts as converged (the traces carry the products'
     // rounding); before the final phase and stage this only moves on

@@ -366,6 +366,55 @@ def test_newton_schulz_solver_canonical(dm, chain128_ref, prec, tol):
     assert st["cg_iters_total"] == 0
 
 
+@pytest.mark.parametrize("prec,refine,tol,schedule", [
+    ("fp64", 0, 1e-10, 1), ("fp64", 0, 1e-10, 0), ("fp64", 0, 1e-10, 2), ("int8x13", 0, 1e-6, 1),
+    ("bf16x3", 2, 1e-6, 1), ("bf16x6", 0, 1e-6, 1), ("fp32", 0, 1e-6, 1)])
+def test_hybrid_solver_canonical(dm, chain128_ref, prec, refine, tol, schedule):
+    """CG in the order-0 passes, the shared inverse in the passes with jets (schedule 1: the order-1
+    pass stores Z of every step and the order-2 pass reuses it; 2: the order-2 pass solves again;
+    0: Algorithm 1's joint Newton, every pass with jets) reaches the oracle; with BF16 and FP32
+    products every pass keeps CG."""
+    print(f"case hybrid {prec} refine={refine} schedule={schedule}", flush=True)
+    c, ref = chain128_ref
+    with dm.Context(c["N"], dirs_max=1, prec=prec, refine=refine, solver="hybrid", schedule=schedule) as ctx:
+        P0, P1, P2, mu, st = ctx.mu_newton(T(c["H0"]), [T(h) for h in c["H1"]], None,
+                                           beta=c["beta"], Ne=c["Ne"], n=c["n"], order=2)
+    e0, e1, e2 = errs(P0, P1, P2, ref)
+    print(f"  errs {e0:.2e} {e1:.2e} {e2:.2e} newton={st['newton_iters']} cg={st['cg_iters_total']}")
+    assert e0 < tol and e1 < tol and e2 < tol
+    assert abs(mu[0] - ref["mu0"]) < 10 * tol
+    if schedule != 0:
+        assert st["cg_iters_total"] > 0  # the order-0 passes ran CG
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("int8x13", 5e-8)])
+def test_newton_schulz_short_start_matches_full_iterations(dm, chain128_ref, prec, tol, monkeypatch):
+    """The step-dependent start (fewer Newton-Schulz iterations while ||D_s|| is small) gives the
+    results of four iterations in every step (DMPT_NS_ITERS=4 forces them): to rounding in FP64;
+    with int8x13 products, whose dropped digit products leave ~1e-8 on P2, within a few times
+    that (the two forms round different products)."""
+    print(f"case newton-schulz short start {prec}", flush=True)
+    c, _ = chain128_ref
+    out = []
+    for force in (None, "4"):
+        if force:
+            monkeypatch.setenv("DMPT_NS_ITERS", force)
+        else:
+            monkeypatch.delenv("DMPT_NS_ITERS", raising=False)
+        with dm.Context(c["N"], dirs_max=1, prec=prec, solver="ns") as ctx:
+            P0, P1, P2, mu, st = ctx.mu_newton(T(c["H0"]), [T(h) for h in c["H1"]], None,
+                                               beta=c["beta"], Ne=c["Ne"], n=c["n"], order=2)
+        out.append((P0.cpu().numpy(), P1[0].cpu().numpy(), P2[0].cpu().numpy(), st["mfma_flops"]))
+    monkeypatch.delenv("DMPT_NS_ITERS", raising=False)
+    (a0, a1, a2, fa), (b0, b1, b2, fb) = out
+    d0 = np.abs(a0 - b0).max()
+    d1 = np.abs(a1 - b1).max() / np.abs(b1).max()
+    d2 = np.abs(a2 - b2).max() / np.abs(b2).max()
+    print(f"  differences {d0:.2e} {d1:.2e} {d2:.2e}; products {fa:.3e} vs {fb:.3e}")
+    assert d0 < tol and d1 < tol and d2 < tol
+    assert fa < fb  # the short start did fewer products
+
+
 def test_newton_schulz_third_order_ragged(dm):
     print("case newton-schulz order 3 ragged", flush=True)
     N, n, beta, Ne = 200, 20, 10.0, 97.0
@@ -396,15 +445,18 @@ def cubic2048_ref():
 
 
 @pytest.mark.timeout(300)
-@pytest.mark.parametrize("prec,refine,tol", [("fp64", 0, 1e-10), ("fp32", 0, 1e-6), ("bf16x6", 0, 1e-6),
-                                             ("bf16x3", 1, 1e-6), ("int8x13", 0, 1e-6), ("bf16x3", 2, 1e-6),
-                                             ("int8x6", 2, 1e-6)])
-def test_cubic2048_all_forms(dm, cubic2048_ref, prec, refine, tol):
+@pytest.mark.parametrize("prec,refine,tol,solver", [
+    ("fp64", 0, 1e-10, "cg"), ("fp32", 0, 1e-6, "cg"), ("bf16x6", 0, 1e-6, "cg"), ("bf16x3", 1, 1e-6, "cg"),
+    ("int8x13", 0, 1e-6, "cg"), ("bf16x3", 2, 1e-6, "cg"), ("int8x6", 2, 1e-6, "cg"),
+    ("fp64", 0, 1e-10, "hybrid"), ("int8x13", 0, 1e-6, "hybrid"), ("bf16x3", 2, 1e-6, "hybrid"),
+    ("int8x6", 2, 1e-6, "hybrid")])
+def test_cubic2048_all_forms(dm, cubic2048_ref, prec, refine, tol, solver):
     """16 x 16 x 8 simple-cubic lattice, beta 20, n 25, orders 0-2: every element of P0, P1 and P2
-    against the oracle (P0 absolute, P1 and P2 relative to max |P^(k)|), every form."""
-    print(f"case cubic2048 {prec} refine={refine}", flush=True)
+    against the oracle (P0 absolute, P1 and P2 relative to max |P^(k)|), every form, with CG in
+    every pass or with the shared inverse in the passes that carry jets."""
+    print(f"case cubic2048 {prec} refine={refine} solver={solver}", flush=True)
     c, ref = cubic2048_ref
-    with dm.Context(c["N"], dirs_max=len(c["H1"]), prec=prec, refine=refine) as ctx:
+    with dm.Context(c["N"], dirs_max=len(c["H1"]), prec=prec, refine=refine, solver=solver) as ctx:
         P0, P1, P2, mu, st = ctx.mu_newton(T(c["H0"]), [T(h) for h in c["H1"]], None, beta=c["beta"],
                                            Ne=c["Ne"], n=c["n"], order=2)
     e0, e1, e2 = errs(P0, P1, P2, ref)
@@ -418,16 +470,18 @@ def test_cubic2048_all_forms(dm, cubic2048_ref, prec, refine, tol):
 # ------------------------------------------------------------------ N = 8192 banded (the benchmark)
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("prec,refine", [("int8x6", 2), ("bf16x3", 2), ("bf16x3", 1)])
-def test_banded8192_benchmark_configuration(dm, prec, refine):
-    """The benchmark's workload and launch configuration (int8 6-product passes, then the int8
-    13-product order-1 and order-2 passes; and the bf16x3 passes followed by the int8 (2) or the
-    bf16x6 refinement with FP64 slice accumulation (1); orders 0-2, 3 directions) against the
-    oracle's stored samples and whole row blocks."""
-    print(f"case banded8192 {prec} refine={refine}", flush=True)
+@pytest.mark.parametrize("prec,refine,solver", [("bf16x3", 2, "hybrid"), ("int8x6", 2, "cg"), ("bf16x3", 2, "cg"),
+                                                ("bf16x3", 1, "cg")])
+def test_banded8192_benchmark_configuration(dm, prec, refine, solver):
+    """The benchmark's workload and launch configuration (bf16x3 passes, then the int8 13-product
+    passes, CG in order-0 passes and the shared inverse in the order-1 and order-2 passes), and the
+    other forms: int8 6-product first passes, CG everywhere, the bf16x6 refinement with FP64 slice
+    accumulation (1); orders 0-2, 3 directions; against the oracle's stored samples and whole row
+    blocks."""
+    print(f"case banded8192 {prec} refine={refine} solver={solver}", flush=True)
     c = workloads.config("banded8192")
     g = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "banded8192_samples.npz"))
-    with dm.Context(c["N"], dirs_max=len(c["H1"]), prec=prec, refine=refine, acc64=1) as ctx:
+    with dm.Context(c["N"], dirs_max=len(c["H1"]), prec=prec, refine=refine, acc64=1, solver=solver) as ctx:
         P0, P1, P2, mu, st = ctx.mu_newton(T(c["H0"]), [T(h) for h in c["H1"]], None, beta=c["beta"],
                                            Ne=c["Ne"], n=c["n"], order=2)
     ii = torch.as_tensor(g["i"], device=P0.device)
