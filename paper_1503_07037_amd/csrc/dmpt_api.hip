@@ -306,6 +306,12 @@ double default_tol_cg(dmpt_prec p, int refine) {
 // near 1e-6 of the occupation).
 constexpr double kPhaseATolCg = 1e-5;
 constexpr double kPhaseATolOcc = 1e-5;
+// When the first phase meets its tolerance with an occupation error below
+// this, its Newton step is not taken: the error is then within that phase's
+// own trace bias (the 3-product split's rounding), and a step on it moves mu0
+// away (banded N = 8192: from 1.3e-7 to 6e-6 of the occupation, measured by
+// the int8 pass that follows).
+constexpr double kPhaseABias = 3e-5;
 
 double default_tol_occ(dmpt_prec p, int refine) {
   p = final_prec(p, refine);
@@ -2420,7 +2426,7 @@ void occupation_error(const double* res, int d, int order, double Ne, int64_t N,
 // Y1 = Y1(mu1 = 0) - mu1 Y_J.
 // *settled: whether mu0 met the tolerance (or its noise floor).
 dmpt_status linear_orders(Call& k, const PassIn& base, int64_t N, int order, double* mu,
-                          double mu_lo, double mu_hi, double Ne, double tol, double* P0,
+                          double mu_lo, double mu_hi, double Ne, double tol, double prev_rel, double* P0,
                           double* const* P1, double* const* P2, double* const* P3, bool* settled,
                           int* passes) {
   dmpt_ctx c = k.c;
@@ -2464,7 +2470,12 @@ dmpt_status linear_orders(Call& k, const PassIn& base, int64_t N, int order, dou
                    "[dmpt] order-1 pass: mu0 %.15g TrP0-Ne %.3e rel %.3e TrJ %.6e cg_total %ld t %.4f "
                    "mfma %.4e\n",
                    mu[0], c->h_res[RES_TR] - Ne, rel, trJ, c->cg_total, log_clock(), c->mfma_flops);
-    if (rel <= tol || (rel > 0.5 * prev && rel <= 1e3 * tol)) {
+    // noise floor: the error stopped shrinking (within 1000 tol), or, on the
+    // first pass, the Newton step that set mu0 came from the quadratic regime
+    // (100 prev_rel^2 <= tol: it should have left ~prev_rel^2) and the error
+    // is still within 10 tol -- the floor of this engine's traces
+    const bool quad_floor = a == 0 && 100.0 * prev_rel * prev_rel <= tol && rel <= 10.0 * tol;
+    if (rel <= tol || quad_floor || (rel > 0.5 * prev && rel <= 1e3 * tol)) {
       if (rel > tol) c->flags |= DMPT_FLAG_NOISE_FLOOR;
       *settled = true;
       break;
@@ -2902,6 +2913,7 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
   c->debug = std::getenv("DMPT_DEBUG_CHECKS") != nullptr;
   if (const char* e = std::getenv("DMPT_NS_ITERS")) c->ns_iters_env = std::atoi(e);
   if (const char* e = std::getenv("DMPT_NS_REFINE")) c->ns_refine_env = std::atoi(e);
+
   c->n_max = n_max;
   c->np_max = padded(n_max);
   c->dirs_max = dirs_max;
@@ -3732,6 +3744,7 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
   // with mu0); a Newton step that leaves it, or a vanishing Tr P_mu, is
   // replaced by bisection
   double br_lo = mu_lo, br_hi = mu_hi;
+  double last_rel = INFINITY;  // normalised error of the last pass of the loop
   for (it = 1; it <= c->opt.max_newton; ++it) {
     const Phase& P = phases[ph];
     k.eng = P.eng;
@@ -3744,6 +3757,7 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
       return fail(c, DMPT_ERR_NONFINITE, "non-finite trace in the Newton loop");
     double rel = 0.0;
     occupation_error(r, dd, stage_order, Ne, N, &occ, &rel);
+    last_rel = rel;
     bool ok = rel <= P.tol_occ;
     const bool last = ph == nph - 1 && stage_order == loop_order;
     if (c->log)
@@ -3781,7 +3795,10 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
     // taken: the bracket's ends then carry the traces' rounding
     const bool occ_met = std::fabs(r[RES_TR] - Ne) <= P.tol_occ * (double)N;
     const bool newton_step = trpmu > 0.0 && (occ_met || (mu_n >= br_lo && mu_n <= br_hi));
-    if (newton_step) {
+    const bool switching = ok && stage_order == loop_order && ph < nph - 1;
+    if (switching && rel <= kPhaseABias) {
+      if (c->log) std::fprintf(stderr, "[dmpt] phase switch keeps mu0\n");
+    } else if (newton_step) {
       mu[0] = mu_n;
       for (int i = 1; i < 1 + stage_order * dd; ++i) mu[i] -= r[RES_TR + i] / trpmu;
     } else {
@@ -3814,7 +3831,7 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
     k.tol_cg = P.tol_cg;
     bool settled = false;
     int passes = 0;
-    STCHK(linear_orders(k, in, N, order, mu.data(), mu_lo, mu_hi, Ne, P.tol_occ, P0, P1, P2, P3,
+    STCHK(linear_orders(k, in, N, order, mu.data(), mu_lo, mu_hi, Ne, P.tol_occ, last_rel, P0, P1, P2, P3,
                         &settled, &passes));
     it += passes;
     done = settled;
