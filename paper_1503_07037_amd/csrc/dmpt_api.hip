@@ -142,6 +142,7 @@ struct dmpt_ctx_s {
   size_t zs_bytes = 0;
   int ns_iters_env = 0;          // DMPT_NS_ITERS (experiments: Newton-Schulz steps)
   int ns_refine_env = -1;        // DMPT_NS_REFINE (experiments: 0/1 refinement step)
+  bool full_tiles = false;       // DMPT_FULL_TILES set: symmetric products compute every tile
   int64_t tj_np = 0;
   int tj_valid = -1;
   Group U0;                      // order-0 CG unknown when the guess comes from tj
@@ -433,6 +434,7 @@ struct G {
   int batch = 1;
   const int* active = nullptr;
   int counted = -1;  // members whose flops are tallied (-1: all; the host knows the others are skipped)
+  bool sym = false;  // C = X Y^T is symmetric (and so are C1, C2): compute the lower triangle, mirror it
 };
 
 // ------------------------------------------------------------------ host-side bounds
@@ -582,6 +584,8 @@ dmpt_status run_gemm(const Call& k, const G& g) {
   a.active = g.active;
   a.variant = variant_for(k.c, k.eng, k.Np);
   a.acc64 = acc64_of(k.c, k.eng);
+  // recorded launches (graph replays, grouped launches) keep every tile
+  a.sym = g.sym && !k.rec && !g.W && !k.c->full_tiles ? 1 : 0;
   if (engine_int8(k.eng)) {
     if (k.Np > kQ8MaxK) return fail(k.c, DMPT_ERR_UNSUPPORTED, "int8 products need N <= 32768");
     STCHK(q8_operand(k, a.X, g.batch));
@@ -618,7 +622,9 @@ dmpt_status run_gemm(const Call& k, const G& g) {
   }
   if (ok_q8_bounds(k, a, g.batch) == false)
     return fail(k.c, DMPT_ERR_ARG, "internal: an int8 operand would leave its workspace");
-  const double n3 = 2.0 * (double)k.Np * k.Np * k.Np;
+  // the share of the output tiles computed (below 1 for symmetric outputs)
+  const double tf = (double)gemm_launch_tiles(a) / (double)gemm_tiles(k.eng, k.Np, a.variant, a.acc64);
+  const double n3 = 2.0 * (double)k.Np * k.Np * k.Np * tf;
   if (k.graph) {
     // replays skip converged members on the device: count there
     a.tally = k.c->d_tally;
@@ -627,7 +633,7 @@ dmpt_status run_gemm(const Call& k, const G& g) {
   }
   const int members = g.counted >= 0 ? g.counted : g.batch;
   const double mf = n3 * engine_terms(k.eng) * members;
-  const double uf = 2.0 * (double)k.N * k.N * k.N * members;
+  const double uf = 2.0 * (double)k.N * k.N * k.N * tf * members;
   dmpt_ctx c = k.c;
   // algorithmic bytes: distinct operand members read once, C written once
   double bytes = 0.0;
@@ -898,6 +904,7 @@ dmpt_status square0(const Call& k) {
   planes_of(k, w->S0, 0, g.Cpl);
   g.batch = k.m;
   g.active = w->mask0;
+  g.sym = true;  // S0 = D0 D0
   return run_gemm(k, g);
 }
 
@@ -1066,6 +1073,7 @@ dmpt_status solve_order0(const Call& k, int step) {
     q.sC = k.stride;
     q.batch = k.m;
     q.active = w->mask0;
+    q.sym = true;  // D0 S0
     STCHK(run_gemm(k, q));
     uint16_t* pd[3];
     planes_of(k, w->D0, 0, pd);
@@ -1198,6 +1206,7 @@ dmpt_status ns_inverse(const Call& k, int step) {
     planes_of(k, w->P, 0, g.Cpl);
     g.alpha = 4.0;
     g.C1 = mptr(k, w->Zi, 0); g.beta1 = 1.0;
+    g.sym = true;  // S0 and Z commute (Z is a polynomial in S0)
     STCHK(run_gemm(k, g));
     G h;  // R[0] = 2 Z - Z M
     h.X = op(k, w->Zi, 0, false);
@@ -1205,6 +1214,7 @@ dmpt_status ns_inverse(const Call& k, int step) {
     h.C = mptr(k, w->R, 0);
     h.alpha = -1.0;
     h.C1 = mptr(k, w->Zi, 0); h.beta1 = 2.0;
+    h.sym = true;
     STCHK(run_gemm(k, h));
     HIPCHK(c, (sym_combine<T, T>((const T*)mptr(k, w->R, 0), k.Np, 0, k.N, k.Np, 0.5, nullptr, 0,
                                  (T*)mptr(k, w->Zi, 0), k.Np, 0, pz, k.np, 1, s)));
@@ -1234,6 +1244,7 @@ dmpt_status ns_solve(const Call& k, const Group& g, int md) {
   a.sC = k.stride;
   planes_of(k, g, 0, a.Cpl);
   a.batch = md;
+  a.sym = &g == &w->D0;  // order 0: R = 2 D0 commutes with Z
   STCHK(run_gemm(k, a));
   if (ns_refines(k)) {
     G r;  // R -= U + 4 U S0
@@ -1366,6 +1377,7 @@ dmpt_status recursion_step(const Call& k, int order, int d, int step) {
     h.C1 = mptr(k, w->S2, 0); h.sC1 = k.stride; h.beta1 = 1.0;
     h.batch = md;
     h.active = w->mask1;
+    h.sym = true;  // D1 D1, added to the symmetric D2 D0 + D0 D2
     STCHK(run_gemm(k, h));
   }
   if (order >= 3) {
@@ -2913,6 +2925,7 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
   c->debug = std::getenv("DMPT_DEBUG_CHECKS") != nullptr;
   if (const char* e = std::getenv("DMPT_NS_ITERS")) c->ns_iters_env = std::atoi(e);
   if (const char* e = std::getenv("DMPT_NS_REFINE")) c->ns_refine_env = std::atoi(e);
+  c->full_tiles = std::getenv("DMPT_FULL_TILES") != nullptr;
 
   c->n_max = n_max;
   c->np_max = padded(n_max);

@@ -112,6 +112,9 @@ struct GemmArgs {
   const int* active;           // optional per-batch mask; 0 = skip the member
   int variant;                 // kernel variant of the engine (gemm_variants; 0 = default)
   int acc64;                   // BF16S3 only: FP32 per stage, FP64 across stages (128-wide tiles)
+  int sym;                     // C is symmetric: only the tiles on and below the diagonal are
+                               // computed (when the tile count per side is even and W is unset),
+                               // then the upper triangle is mirrored from the lower one
   // optional executed-work tally (graph replays, where the host cannot see
   // which members are skipped): every member that runs adds tally_m and
   // tally_u to tally[0] and tally[1]
@@ -126,6 +129,8 @@ int gemm_variants(Engine eng, int acc64);
 const char* gemm_variant_name(Engine eng, int acc64, int variant);
 int gemm_tile_edge(Engine eng, int64_t Np, int variant, int acc64);
 int gemm_tiles(Engine eng, int64_t Np, int variant, int acc64);
+// Output tiles per member that gemm() computes (fewer than gemm_tiles with sym).
+int gemm_launch_tiles(const GemmArgs& a);
 hipError_t gemm(const GemmArgs& a, hipStream_t s);
 // One grouped launch over nprob products of the same engine, variant and tile
 // edge (list, start: device arrays; problem p owns the blocks start[p] ..

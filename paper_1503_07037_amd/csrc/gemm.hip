@@ -52,7 +52,7 @@ constexpr int kGroupM = 8;   // tile rows per raster group
 constexpr int kXcd = 8;      // XCDs of an MI355X
 
 // Tile coordinates of a (possibly remapped) linear block index.
-__device__ inline void tile_coords(int b, int tiles_m, int tiles_n, int& tm, int& tn) {
+__device__ inline void raster(int b, int tiles_m, int tiles_n, int& tm, int& tn) {
   const int T = tiles_m * tiles_n;
   if (T % kXcd == 0) b = (b % kXcd) * (T / kXcd) + b / kXcd;
   const int per_group = kGroupM * tiles_n;
@@ -62,6 +62,27 @@ __device__ inline void tile_coords(int b, int tiles_m, int tiles_n, int& tm, int
   const int r = b % per_group;
   tm = first + r % gsz;
   tn = r / gsz;
+}
+
+// With sym, only the tiles on and below the diagonal of the square T x T
+// tile grid (T even): rows p and T - 1 - p hold p + 1 and T - p of them,
+// T + 1 together, so the triangle is the (T / 2) x (T + 1) grid folded at
+// q = p (gemm_launch_tiles gives the launch size).
+__device__ inline void tile_coords(int b, int tiles_m, int tiles_n, int& tm, int& tn, int sym = 0) {
+  if (!sym) {
+    raster(b, tiles_m, tiles_n, tm, tn);
+    return;
+  }
+  const int T = tiles_m;
+  int p, q;
+  raster(b, T / 2, T + 1, p, q);
+  if (q <= p) {
+    tm = p;
+    tn = q;
+  } else {
+    tm = T - 1 - p;
+    tn = q - p - 1;
+  }
 }
 
 __device__ inline double block_sum(double v, double* red) {
@@ -153,7 +174,7 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmArgs& a, int z, int bx, 
   count_member(a, bx);
   const int64_t Np = a.Np;
   int tm, tn;
-  tile_coords(bx, (int)(Np / BM), (int)(Np / BN), tm, tn);
+  tile_coords(bx, (int)(Np / BM), (int)(Np / BN), tm, tn, a.sym);
   const double* X = (const double*)a.X.m + (z / a.X.div) * a.X.stride + (int64_t)tm * BM * Np;
   const double* Y = (const double*)a.Y.m + (z / a.Y.div) * a.Y.stride + (int64_t)tn * BN * Np;
   __shared__ double sX[2][BM][LD];
@@ -276,7 +297,7 @@ __device__ __forceinline__ void gemm_f32_tile(const GemmArgs& a, int z, int bx, 
   count_member(a, bx);
   const int64_t Np = a.Np;
   int tm, tn;
-  tile_coords(bx, (int)(Np / BM), (int)(Np / BN), tm, tn);
+  tile_coords(bx, (int)(Np / BM), (int)(Np / BN), tm, tn, a.sym);
   const double* X = (const double*)a.X.m + (z / a.X.div) * a.X.stride + (int64_t)tm * BM * Np;
   const double* Y = (const double*)a.Y.m + (z / a.Y.div) * a.Y.stride + (int64_t)tn * BN * Np;
   __shared__ float sX[2][BM][LD];
@@ -454,7 +475,7 @@ __device__ __forceinline__ void gemm_bf16_tile(const GemmArgs& a, int z, int bx,
   const int64_t Np = a.Np;
   const int64_t kbr = Np >> 4;         // blocks per 32-row block row of a plane
   int tm, tn;
-  tile_coords(bx, (int)(Np / TM), (int)(Np / TM), tm, tn);
+  tile_coords(bx, (int)(Np / TM), (int)(Np / TM), tm, tn, a.sym);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
   // the blocks this wave copies: stage block q = wave + NW j
@@ -682,7 +703,7 @@ __device__ __forceinline__ void gemm_i8_tile(const GemmArgs& a, int z, int bx, i
   const int64_t Np = a.Np;
   const int64_t kbr = Np >> 5;  // 32-wide blocks per block row
   int tm, tn;
-  tile_coords(bx, (int)(Np / TM), (int)(Np / TM), tm, tn);
+  tile_coords(bx, (int)(Np / TM), (int)(Np / TM), tm, tn, a.sym);
   // the wave index is uniform: block addresses live in scalar registers
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / WN, wn = wave % WN;
@@ -815,7 +836,7 @@ __device__ __forceinline__ void gemm_i8_dma_tile(const GemmArgs& a, int z, int b
   const int64_t Np = a.Np;
   const int64_t kbr = Np >> 5;
   int tm, tn;
-  tile_coords(bx, (int)(Np / TM), (int)(Np / TM), tm, tn);
+  tile_coords(bx, (int)(Np / TM), (int)(Np / TM), tm, tn, a.sym);
   // the wave index is uniform: block addresses live in scalar registers
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / WN, wn = wave % WN;
@@ -1082,12 +1103,71 @@ int gemm_tiles(Engine eng, int64_t Np, int variant, int acc64) {
   return (int)((Np / e) * (Np / e));
 }
 
-hipError_t gemm(const GemmArgs& a, hipStream_t s) {
-  if (a.Np <= 0 || a.Np % BM != 0 || a.batch <= 0 || a.X.div < 1 || a.Y.div < 1 || a.variant < 0 ||
-      a.variant >= gemm_variants(a.eng, a.acc64))
+int gemm_launch_tiles(const GemmArgs& a) {
+  const int T = (int)(a.Np / gemm_tile_edge(a.eng, a.Np, a.variant, a.acc64));
+  if (a.sym && !a.W && T % 2 == 0) return T / 2 * (T + 1);
+  return T * T;
+}
+
+namespace {
+
+struct Planes3 {
+  uint16_t* p[3];
+};
+
+// Upper triangle of each symmetric product output from its lower triangle
+// (master and, when requested, split planes): 32 x 32 blocks (bi, bj) with
+// bi >= bj go through LDS and are written transposed at (bj, bi); diagonal
+// blocks copy their strictly lower part only.
+__global__ __launch_bounds__(256) void k_mirror(double* __restrict__ C, int64_t Np, int64_t sC, Planes3 pl, int np,
+                                                const int* active) {
+  const int z = blockIdx.z;
+  if (active && !active[z]) return;
+  const int64_t nb = Np / 32;
+  const int64_t bi = blockIdx.x / nb, bj = blockIdx.x % nb;
+  if (bi < bj) return;
+  __shared__ double t[32][33];
+  double* c = C + (int64_t)z * sC;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) t[r][tx] = c[(bi * 32 + r) * Np + bj * 32 + tx];
+  __syncthreads();
+  uint16_t* p[3] = {nullptr, nullptr, nullptr};
+  for (int i = 0; i < np; ++i) p[i] = pl.p[i] + (int64_t)z * sC;
+  // destination row bj*32 + r2 (source column), column bi*32 + tx (source row)
+  for (int r2 = ty; r2 < 32; r2 += 8) {
+    if (bi == bj && tx <= r2) continue;  // diagonal block: source (tx, r2) must lie below the diagonal
+    const double v = t[tx][r2];
+    const int64_t row = bj * 32 + r2, col = bi * 32 + tx;
+    c[row * Np + col] = v;
+    if (np) write_split(v, p, np, plane_off(row, col, Np));
+  }
+}
+
+}  // namespace
+
+hipError_t gemm_launch(const GemmArgs& a, int tiles, hipStream_t s);
+
+hipError_t gemm(const GemmArgs& a0, hipStream_t s) {
+  if (a0.Np <= 0 || a0.Np % BM != 0 || a0.batch <= 0 || a0.X.div < 1 || a0.Y.div < 1 || a0.variant < 0 ||
+      a0.variant >= gemm_variants(a0.eng, a0.acc64))
     return hipErrorInvalidValue;
+  GemmArgs a = a0;
+  const int full = gemm_tiles(a.eng, a.Np, a.variant, a.acc64);
+  const int tiles = gemm_launch_tiles(a);
+  a.sym = tiles < full ? 1 : 0;
+  hipError_t e = gemm_launch(a, tiles, s);
+  if (e != hipSuccess || !a.sym) return e;
+  Planes3 pl{{a.Cpl[0], a.Cpl[1], a.Cpl[2]}};
+  const int np = a.Cpl[2] ? 3 : (a.Cpl[1] ? 2 : (a.Cpl[0] ? 1 : 0));
+  const int64_t nb = a.Np / 32;
+  hipLaunchKernelGGL(k_mirror, dim3((unsigned)(nb * nb), 1, (unsigned)a.batch), dim3(256), 0, s, (double*)a.C,
+                     a.Np, a.sC, pl, np, a.active);
+  return hipGetLastError();
+}
+
+hipError_t gemm_launch(const GemmArgs& a, int tiles, hipStream_t s) {
   const int edge = gemm_tile_edge(a.eng, a.Np, a.variant, a.acc64);
-  const dim3 grid((unsigned)gemm_tiles(a.eng, a.Np, a.variant, a.acc64), 1, (unsigned)a.batch);
+  const dim3 grid((unsigned)tiles, 1, (unsigned)a.batch);
   switch (a.eng) {
     case Engine::I8S4:
     case Engine::I8S3:

@@ -415,6 +415,44 @@ def test_newton_schulz_short_start_matches_full_iterations(dm, chain128_ref, pre
     assert fa < fb  # the short start did fewer products
 
 
+@pytest.mark.parametrize("prec,solver,tol", [("fp64", "hybrid", 1e-12), ("fp64", "cg", 1e-12),
+                                              ("int8x13", "hybrid", 5e-8), ("bf16x3", "cg", 3e-5)])
+def test_symmetric_products_match_full_tiles(dm, prec, solver, tol, monkeypatch):
+    """Products with a symmetric result (D0 D0, the Newton-Schulz products, D1 D1, R Z at order 0)
+    compute the tiles on and below the diagonal and mirror them; DMPT_FULL_TILES=1 computes every
+    tile.  Ragged N = 1000 (Np = 1024: eight 128-wide tile rows, four 256-wide ones) and
+    N = 640 (five 128-wide rows: odd, so every tile is computed), orders 0-2: the two agree to
+    rounding (int8x13: within the engine's own error; bf16x3 without refinement: within its ~1e-5)."""
+    rng = np.random.default_rng(5)
+    for N in (1000, 640):
+        print(f"case symmetric products {prec} {solver} N={N}", flush=True)
+        h0 = workloads.banded(N, 11, bandwidth=24, decay=8.0)
+        h1 = [np.diag(np.linspace(-1.0, 1.0, N)), _sym(rng, N, 0.05)]
+        out = []
+        for full in (False, True):
+            if full:
+                monkeypatch.setenv("DMPT_FULL_TILES", "1")
+            else:
+                monkeypatch.delenv("DMPT_FULL_TILES", raising=False)
+            with dm.Context(N, dirs_max=2, prec=prec, solver=solver) as ctx:
+                P0, P1, P2, mu, st = ctx.mu_newton(T(h0), [T(h) for h in h1], None, beta=12.0,
+                                                   Ne=N / 2.0, n=22, order=2)
+            out.append((P0.cpu().numpy(), [p.cpu().numpy() for p in P1], [p.cpu().numpy() for p in P2],
+                        st["mfma_flops"]))
+        monkeypatch.delenv("DMPT_FULL_TILES", raising=False)
+        (a0, a1, a2, fa), (b0, b1, b2, fb) = out
+        d0 = np.abs(a0 - b0).max()
+        d1 = max(np.abs(x - y).max() / np.abs(y).max() for x, y in zip(a1, b1))
+        d2 = max(np.abs(x - y).max() / np.abs(y).max() for x, y in zip(a2, b2))
+        print(f"  differences {d0:.2e} {d1:.2e} {d2:.2e}; executed {fa:.3e} vs {fb:.3e}")
+        assert d0 < tol and d1 < tol and d2 < tol
+        assert np.abs(a0 - a0.T).max() == 0.0
+        if N == 1000:
+            assert fa < fb
+        else:
+            assert fa == fb
+
+
 def test_newton_schulz_third_order_ragged(dm):
     print("case newton-schulz order 3 ragged", flush=True)
     N, n, beta, Ne = 200, 20, 10.0, 97.0
