@@ -372,6 +372,7 @@ struct Call {
   std::vector<Op>* rec = nullptr;  // when set, launches are recorded here instead of issued
   double glo = NAN, ghi = NAN;   // Gershgorin interval of sym(H0), when the caller scanned it
   double d0b = -1.0;             // this pass: a bound on ||D_0||_2 (< 0: none known)
+  int jdir = -1;                 // order-1 member that is the response J to H1 = I (linear schedule)
 };
 
 // Issue a launch of the recursion step code now, or record it (k.rec).
@@ -1333,6 +1334,12 @@ dmpt_status recursion_step(const Call& k, int order, int d, int step) {
   else STCHK(square0<T>(k));
   if (k.chain & kSaveS) STCHK(ss_save<T>(k, w->S0, 0, step, 0));
   const bool ns = ns_pass(k, order);
+  // the identity direction of an order-1 pass solved with the shared inverse:
+  // with S1_J = 2 D0 D1_J, Y0 = 2 D0 Z and 4 S0 Z = I - Z, the order-1 step
+  // (2 D1_J - 4 Y0 S1_J) Z is D1_J (4 Z^2 - 2 Z), two symmetric products
+  // (used where Z is as accurate as the products: no refinement step)
+  const bool jt = ns && !ns_refines(k) && order == 1 && k.m == 1 && k.jdir >= 0 && k.jdir == k.m * d - 1 &&
+                  !(k.chain & kLoad01) && !(k.chain & kLoadS);
   if (ns) {
     if (k.chain & kLoadZ) STCHK(zs_load<T>(k, step));
     else STCHK(ns_inverse<T>(k, step));
@@ -1342,16 +1349,29 @@ dmpt_status recursion_step(const Call& k, int order, int d, int step) {
     // the order-1 pass stored S1 at mu1 = 0; S1 is linear in mu1: S1 = S1(0) - mu1 S1_J
     for (int z = 0; z < md; ++z) STCHK(ss_load<T>(k, w->S1, z, step, 1 + z, k.cmu[z], k.cj));
   } else if (order >= 1) {
-    // Q = D1 D0 -> S1 = Q + Q^T
-    G g;
-    g.X = op(k, w->D1, 0, true);
-    g.Y = op(k, w->D0, 0, true);
-    g.Y.div = d;
-    g.C = mptr(k, w->Q, 0);
-    g.sC = k.stride;
-    g.batch = md;
-    g.active = w->mask1;
-    STCHK(run_gemm(k, g));
+    // Q = D1 D0 -> S1 = Q + Q^T (for J, a polynomial in D0 that commutes
+    // with it, Q is symmetric: S1_J = 2 D1_J D0)
+    const int mr = jt ? md - 1 : md;
+    if (mr > 0) {
+      G g;
+      g.X = op(k, w->D1, 0, true);
+      g.Y = op(k, w->D0, 0, true);
+      g.Y.div = d;
+      g.C = mptr(k, w->Q, 0);
+      g.sC = k.stride;
+      g.batch = mr;
+      g.active = w->mask1;
+      STCHK(run_gemm(k, g));
+    }
+    if (jt) {
+      G g;
+      g.X = op(k, w->D1, mr, false);
+      g.Y = op(k, w->D0, 0, false);
+      g.C = mptr(k, w->Q, mr);
+      g.active = w->mask1 ? w->mask1 + mr : nullptr;
+      g.sym = true;
+      STCHK(run_gemm(k, g));
+    }
     STCHK(sym_to<T>(k, w->Q, w->S1, md, true));
     if (k.chain & kSaveS)
       for (int z = 0; z < md; ++z) STCHK(ss_save<T>(k, w->S1, z, step, 1 + z));
@@ -1429,20 +1449,44 @@ dmpt_status recursion_step(const Call& k, int order, int d, int step) {
     // the order-1 solutions are linear in mu1: Y1 = Y1(mu1 = 0) - mu1 Y_J
     for (int z = 0; z < md; ++z) STCHK(st_load<T>(k, w->D1, z, step, 1 + z, k.cmu[z], k.cj));
   } else if (order >= 1) {
-    G g;  // R = 2 D1 - 4 Y0 S1   (Y0 = new D0), ||rhs||^2 -> ref
-    g.X = op(k, w->D0, 0, true);
-    g.X.div = d;
-    g.Y = op(k, w->S1, 0, true);
-    g.C = mptr(k, w->R, 0);
-    g.sC = k.stride;
-    g.alpha = -4.0;
-    g.C1 = mptr(k, w->D1, 0); g.sC1 = k.stride; g.beta1 = 2.0;
-    g.W = mptr(k, w->R, 0); g.sW = k.stride;
-    g.batch = md;
-    g.active = w->mask1;
-    STCHK(run_gemm(k, g));
-    STCHK(sum_gemm_partials(k, md, w->ref, 1, 0));
-    if (ns) {
+    const int mr = jt ? md - 1 : md;
+    if (mr > 0) {
+      G g;  // R = 2 D1 - 4 Y0 S1   (Y0 = new D0), ||rhs||^2 -> ref
+      g.X = op(k, w->D0, 0, true);
+      g.X.div = d;
+      g.Y = op(k, w->S1, 0, true);
+      g.C = mptr(k, w->R, 0);
+      g.sC = k.stride;
+      g.alpha = -4.0;
+      g.C1 = mptr(k, w->D1, 0); g.sC1 = k.stride; g.beta1 = 2.0;
+      g.W = mptr(k, w->R, 0); g.sW = k.stride;
+      g.batch = mr;
+      g.active = w->mask1;
+      STCHK(run_gemm(k, g));
+      STCHK(sum_gemm_partials(k, mr, w->ref, 1, 0));
+    }
+    if (jt) {
+      if (mr > 0) STCHK(ns_solve<T>(k, w->D1, mr));
+      G m;  // M = 4 Z Z - 2 Z -> P[J]
+      m.X = op(k, w->Zi, 0, false);
+      m.Y = op(k, w->Zi, 0, false);
+      m.C = mptr(k, w->P, mr);
+      planes_of(k, w->P, mr, m.Cpl);
+      m.alpha = 4.0;
+      m.C1 = mptr(k, w->Zi, 0); m.beta1 = -2.0;
+      m.sym = true;
+      STCHK(run_gemm(k, m));
+      G u;  // R[J] = D1_J M, then D1_J = R[J]
+      u.X = op(k, w->D1, mr, false);
+      u.Y = op(k, w->P, mr, false);
+      u.C = mptr(k, w->R, mr);
+      u.sym = true;
+      STCHK(run_gemm(k, u));
+      uint16_t* pj[3];
+      planes_of(k, w->D1, mr, pj);
+      HIPCHK(c, (convert<T, T>((const T*)mptr(k, w->R, mr), 0, (T*)mptr(k, w->D1, mr), 0, k.nn, 1, pj, 0,
+                               w->D1.pl[0] ? k.np : 0, c->stream)));
+    } else if (ns) {
       STCHK(ns_solve<T>(k, w->D1, md));
     } else {
       if (k.traj && c->tj_valid >= 1)  // guess: this step's solution of the previous pass
@@ -2470,8 +2514,11 @@ dmpt_status linear_orders(Call& k, const PassIn& base, int64_t N, int order, dou
   for (int a = 0; a < kMaxPasses; ++a) {
     m1[0] = mu[0];
     k.chain = keep ? (kSave01 | (keep_s ? kSaveS : 0) | (keep_z ? kSaveZ : 0)) : 0;
-    STCHK(pass_dispatch(k, in1, P0, p1x.data(), nullptr));
+    k.jdir = d;
+    const dmpt_status e1 = pass_dispatch(k, in1, P0, p1x.data(), nullptr);
+    k.jdir = -1;
     k.chain = 0;
+    STCHK(e1);
     *passes += 1;
     trJ = c->h_res[RES_TR + 1 + d];
     if (!(std::fabs(trJ) > 0.0) || !std::isfinite(trJ))
