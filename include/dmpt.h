@@ -90,12 +90,11 @@ typedef enum {
                           (the batched and adjoint paths keep CG).  In the environment,
                           DMPT_NS_ITERS=k forces k steps everywhere and DMPT_NS_REFINE=0|1 the
                           refinement step off or on (debugging) */
-  DMPT_SOLVER_HYBRID = 2 /* CG in passes of order 0 (one right-hand side per step, warm-started), the
-                            shared inverse in passes that carry jets when the products are FP64 or
-                            INT8X13 (other products keep CG there: the inverse's rounding biases
-                            the jets' traces); under the linear schedule the order-1 pass keeps Z
-                            of every step (n N^2 master elements, when the memory is there) and
-                            the later passes reuse it */
+  DMPT_SOLVER_HYBRID = 2 /* the shared inverse in the passes whose products are FP64 or INT8X13 (no
+                            refinement step needed), CG in the others (FP32, BF16 and INT8X6
+                            products: the inverse's rounding biases the jets' traces); under the
+                            linear schedule the order-1 pass keeps Z of every step (n N^2 master
+                            elements, when the memory is there) and the later passes reuse it */
 } dmpt_solver;
 
 /* Initial guess of the conjugate-gradient solve. */

@@ -1172,17 +1172,19 @@ bool ns_refines(const Call& k) {
   return k.eng != Engine::F64 && k.eng != Engine::I8S4;
 }
 
-// Whether the steps of a pass of this order solve with the shared inverse:
-// always with DMPT_SOLVER_NS; with DMPT_SOLVER_HYBRID only in passes that
-// carry jets (one inverse then serves 1 + d or more right-hand sides, while
-// an order-0 pass has one, where CG from a warm start needs fewer products),
-// and only with FP64 or 13-product int8 products.  With split-BF16 products
-// the inverse's own rounding biases the traces of the jets (Tr(H1 P2) 1.8e-6
-// with BF16X6 at N = 8192, against 5e-7 with CG), so those passes keep CG.
+// Whether the steps of a pass solve with the shared inverse: always with
+// DMPT_SOLVER_NS; with DMPT_SOLVER_HYBRID when the products are FP64 or
+// 13-product int8 (the inverse then needs no refinement step, and with the
+// step-fitted start and symmetric products it costs fewer products than CG
+// even for the single right-hand side of an order-0 pass; its traces are
+// also cleaner: at N = 8192 the int8 occupation error after the Newton step
+// fell from 6e-10 to 3e-11).  With FP32 and split-BF16 products the passes
+// keep CG: the inverse's own rounding biases the traces of the jets
+// (Tr(H1 P2) 1.8e-6 with BF16X6 at N = 8192, against 5e-7 with CG).
 bool ns_pass(const Call& k, int order) {
+  (void)order;
   const dmpt_solver sv = k.c->opt.solver;
-  const bool hybrid_ns = sv == DMPT_SOLVER_HYBRID && order >= 1 &&
-                         (k.eng == Engine::F64 || k.eng == Engine::I8S4);
+  const bool hybrid_ns = sv == DMPT_SOLVER_HYBRID && (k.eng == Engine::F64 || k.eng == Engine::I8S4);
   return (sv == DMPT_SOLVER_NS || hybrid_ns) && k.m == 1 && !k.graph;
 }
 
@@ -2973,6 +2975,7 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
   if (const char* e = std::getenv("DMPT_NS_ITERS")) c->ns_iters_env = std::atoi(e);
   if (const char* e = std::getenv("DMPT_NS_REFINE")) c->ns_refine_env = std::atoi(e);
   c->full_tiles = std::getenv("DMPT_FULL_TILES") != nullptr;
+
 
   c->n_max = n_max;
   c->np_max = padded(n_max);
