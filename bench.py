@@ -5,15 +5,15 @@ Workload (default): the dense random-banded Hamiltonian, N = 8192 (bandwidth
 256, entries 0.3 g exp(-|i-j|/32), diagonal U(-2, 2)), Ne = 4096, beta = 40,
 n = 30 recursion steps, three diagonal dipole perturbations (x, y, z of a
 32 x 16 x 16 grid), orders 0-2 (polarisability and hyperpolarisability), the
-canonical Newton loop of Algorithm 1: split-BF16 (3-product) matrix products
-with FP32 accumulation until mu0 is close, then the final passes (one order-0
-pass and the linear schedule's order-1 and order-2 passes) with int8-slice
-products (each operand as one scale per matrix times four signed int8 digits,
-the thirteen digit products of weight <= 4 summed exactly in int32).  Per-step
-solves: CG in the order-0 passes; in the order-1 and order-2 passes the shared
-inverse of T' by Newton-Schulz (built once per step in the order-1 pass, kept,
-and applied with one product per right-hand side).  Inputs are synthetic,
-seeded, already resident in HBM when the timed region starts.
+canonical Newton loop of Algorithm 1 (order-0 passes until mu0 is settled,
+then the linear schedule's order-1 and order-2 passes), every product with
+int8 slices (each operand as one scale per matrix times four signed int8
+digits, the thirteen digit products of weight <= 4 summed exactly in int32).
+Per-step solves: the shared inverse of T' by Newton-Schulz (its start fitted
+to the step's spectral interval; built once per step in the order-1 pass,
+kept for the order-2 pass, applied with one product per right-hand side).
+Inputs are synthetic, seeded, already resident in HBM when the timed region
+starts.
 
 One step = one complete canonical solve (dmpt_mu_newton): every Newton pass,
 every recursion step, every order and direction.  value = response solves
@@ -67,7 +67,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="banded8192",
                     choices=["banded8192", "cubic2048", "chain128", "batch64", "adjoint4096"])
-    ap.add_argument("--prec", default="bf16x3", choices=list(PEAKS_TFLOPS))
+    ap.add_argument("--prec", default="int8x13", choices=list(PEAKS_TFLOPS))
     ap.add_argument("--n", type=int, default=0, help="shrink the banded workload to this N (testing)")
     ap.add_argument("--cpu-sample-n", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -79,8 +79,8 @@ def parse():
     ap.add_argument("--acc64", type=int, default=1,
                     help="6-product products: FP32 per 32-wide k slice, FP64 across slices (default 1)")
     ap.add_argument("--solver", default="hybrid", choices=["cg", "ns", "hybrid"],
-                    help="per-step solver: conjugate gradients, the Newton-Schulz shared inverse, or CG "
-                         "in order-0 passes and the shared inverse in passes with jets")
+                    help="per-step solver: conjugate gradients, the Newton-Schulz shared inverse, or the "
+                         "shared inverse with FP64 and int8x13 products and CG with the others")
     ap.add_argument("--no-fp64-compare", action="store_true",
                     help="skip the FP64 solve of the same workload on the GPU")
     ap.add_argument("--order", type=int, default=-1,

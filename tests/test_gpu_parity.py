@@ -510,14 +510,13 @@ def test_cubic2048_all_forms(dm, cubic2048_ref, prec, refine, tol, solver):
 # ------------------------------------------------------------------ N = 8192 banded (the benchmark)
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("prec,refine,solver", [("bf16x3", 2, "hybrid"), ("int8x6", 2, "cg"), ("bf16x3", 2, "cg"),
-                                                ("bf16x3", 1, "cg")])
+@pytest.mark.parametrize("prec,refine,solver", [("int8x13", 0, "hybrid"), ("bf16x3", 2, "hybrid"), ("int8x6", 2, "cg"),
+                                                ("bf16x3", 2, "cg"), ("bf16x3", 1, "cg")])
 def test_banded8192_benchmark_configuration(dm, prec, refine, solver):
-    """The benchmark's workload and launch configuration (bf16x3 passes, then the int8 13-product
-    passes, CG in order-0 passes and the shared inverse in the order-1 and order-2 passes), and the
-    other forms: int8 6-product first passes, CG everywhere, the bf16x6 refinement with FP64 slice
-    accumulation (1); orders 0-2, 3 directions; against the oracle's stored samples and whole row
-    blocks."""
+    """The benchmark's workload and launch configuration (int8 13-product passes with the shared
+    inverse), and the other forms: bf16x3 first passes, int8 6-product first passes, CG everywhere,
+    the bf16x6 refinement with FP64 slice accumulation (1); orders 0-2, 3 directions; against the
+    oracle's stored samples and whole row blocks."""
     print(f"case banded8192 {prec} refine={refine} solver={solver}", flush=True)
     c = workloads.config("banded8192")
     g = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "banded8192_samples.npz"))
