@@ -59,6 +59,11 @@ struct Q8Reg {
   int8_t* q8 = nullptr;
   double* qs = nullptr;
   std::vector<char> dirty;
+  // max |x| of the tiles of each member as the int8 product that last wrote
+  // it left them (mx + z * mx_cap; mx_n[z] of them, 0: unknown, scan again)
+  double* mx = nullptr;
+  int64_t mx_cap = 0;
+  std::vector<int> mx_n;
 };
 // Members sliced by one launch pair at most (the block maxima of a launch
 // fill kQ8Chunk * 1024 doubles of the context's buffer).
@@ -69,7 +74,8 @@ constexpr int kQ8Chunk = 64;
 // system entry points use one system.
 struct WS {
   Group D0, D1, D2, D3, S0, S1, S2, S3, R, P, Q;
-  Group Zi;                      // T'^-1 of the current step (Newton-Schulz solver)
+  Group Zi;                      // T'^-1 of the current step (Newton-Schulz solver): two members,
+                                 // the iteration alternates them (ctx zcur: the current one)
   double* rr = nullptr;          // CG <r,r> history [member][hstride]
   double* pq = nullptr;          // CG <p,Tp> history [member][hstride]
   double* pb = nullptr;          // CG bounds of max |P| for its int8 slices [member][hstride]
@@ -140,6 +146,7 @@ struct dmpt_ctx_s {
   // schedule: the order-1 pass saves it, the order-2 and -3 passes load it)
   void* zs = nullptr;
   size_t zs_bytes = 0;
+  int zcur = 0;                  // member of ws.Zi that holds the current step's inverse
   int ns_iters_env = 0;          // DMPT_NS_ITERS (experiments: Newton-Schulz steps)
   int ns_refine_env = -1;        // DMPT_NS_REFINE (experiments: 0/1 refinement step)
   bool full_tiles = false;       // DMPT_FULL_TILES set: symmetric products compute every tile
@@ -409,7 +416,10 @@ BOp op(const Call& k, const Group& g, int z, bool batched) {
 void q8_touch(dmpt_ctx c, const Group& g, int z) {
   for (auto& r : c->q8reg)
     if (r.m == (const char*)g.m) {
-      for (int i = std::max(z, 0); i < r.count; ++i) r.dirty[i] = 1;
+      for (int i = std::max(z, 0); i < r.count; ++i) {
+        r.dirty[i] = 1;
+        r.mx_n[i] = 0;
+      }
       return;
     }
 }
@@ -547,8 +557,11 @@ dmpt_status q8_operand(const Call& k, BOp& o, int batch) {
         ++z;
         continue;
       }
+      // a run of dirty members with the same kind of maxima (known from the
+      // product that wrote them, with the same tile count, or unknown)
+      const int kn = r.mx_n[z];
       int e = z;
-      while (e < z0 + n && r.dirty[e] && e - z < kQ8Chunk) ++e;
+      while (e < z0 + n && r.dirty[e] && r.mx_n[e] == kn && e - z < kQ8Chunk) ++e;
       const double* src = (const double*)(r.m + (size_t)z * mb);
       int8_t* dst = r.q8 + (size_t)z * r.stride * kQ8Slices;
       double* qd = r.qs + z;
@@ -556,7 +569,13 @@ dmpt_status q8_operand(const Call& k, BOp& o, int batch) {
       const int64_t st = r.stride, Np = k.Np;
       double* part = c->d_qpart;
       hipStream_t s = c->stream;
-      EMIT(k, quantize_q8(src, st, Np, cnt, part, dst, st * kQ8Slices, qd, nullptr, s));
+      if (kn > 0) {
+        const double* known = r.mx + (size_t)z * r.mx_cap;
+        const int64_t cap = r.mx_cap;
+        EMIT(k, quantize_q8_known(src, st, Np, cnt, known, cap, kn, dst, st * kQ8Slices, qd, s));
+      } else {
+        EMIT(k, quantize_q8(src, st, Np, cnt, part, dst, st * kQ8Slices, qd, nullptr, s));
+      }
       for (int i = z; i < e; ++i) r.dirty[i] = 0;
       z = e;
     }
@@ -591,12 +610,26 @@ dmpt_status run_gemm(const Call& k, const G& g) {
     if (k.Np > kQ8MaxK) return fail(k.c, DMPT_ERR_UNSUPPORTED, "int8 products need N <= 32768");
     STCHK(q8_operand(k, a.X, g.batch));
     STCHK(q8_operand(k, a.Y, g.batch));
-    // the output's slices go stale too (C may be an operand group)
+    // the output's slices go stale too (C may be an operand group); when C
+    // is whole members of a sliced group, the kernel leaves their tile
+    // maxima for the next slicing
     for (auto& r : k.c->q8reg) {
       const size_t mb = (size_t)r.stride * k.c->esize;
       const char* p = (const char*)a.C;
-      if (p >= r.m && p < r.m + mb * r.count)
-        for (int i = (int)((size_t)(p - r.m) / mb); i < r.count; ++i) r.dirty[i] = 1;
+      if (p >= r.m && p < r.m + mb * r.count) {
+        const int z0 = (int)((size_t)(p - r.m) / mb);
+        for (int i = z0; i < r.count; ++i) {
+          r.dirty[i] = 1;
+          r.mx_n[i] = 0;
+        }
+        const int64_t tiles = gemm_launch_tiles(a);
+        if (!k.rec && !g.active && (size_t)(p - r.m) % mb == 0 && (g.batch == 1 || a.sC == r.stride) &&
+            z0 + g.batch <= r.count && tiles <= r.mx_cap) {
+          a.cmax = r.mx + (size_t)z0 * r.mx_cap;
+          a.cmax_stride = r.mx_cap;
+          for (int i = z0; i < z0 + g.batch; ++i) r.mx_n[i] = (int)tiles;
+        }
+      }
     }
   }
   // every member the launch touches must lie inside a workspace allocation
@@ -1188,6 +1221,14 @@ bool ns_pass(const Call& k, int order) {
   return (sv == DMPT_SOLVER_NS || hybrid_ns) && k.m == 1 && !k.graph;
 }
 
+// Whether a product marked symmetric computes only the lower triangle of
+// tiles (the tile count per side is even; DMPT_FULL_TILES unset; not recorded):
+// then its output is exactly symmetric.
+bool sym_tiles(const Call& k) {
+  const int edge = gemm_tile_edge(k.eng, k.Np, variant_for(k.c, k.eng, k.Np), acc64_of(k.c, k.eng));
+  return !k.rec && !k.c->full_tiles && (k.Np / edge) % 2 == 0;
+}
+
 template <class T>
 dmpt_status ns_inverse(const Call& k, int step) {
   dmpt_ctx c = k.c;
@@ -1199,30 +1240,37 @@ dmpt_status ns_inverse(const Call& k, int step) {
   const NsStart z0 = ns_start(k, step);
   HIPCHK(c, scaled_plus_identity<T>((const T*)mptr(k, w->S0, 0), (T*)mptr(k, w->Zi, 0), k.N, k.Np, z0.a,
                                     z0.b, pz, k.np, s));
-  q8_touch(c, w->Zi, 0);
-  const int iters = z0.iters;
-  for (int it = 0; it < iters; ++it) {
+  int cur = 0;
+  const bool exact = sym_tiles(k);  // symmetric products leave Z exactly symmetric
+  for (int it = 0; it < z0.iters; ++it) {
+    const int nxt = 1 - cur;
     G g;  // M = T' Z = Z + 4 S0 Z  -> P[0] (with planes)
     g.X = op(k, w->S0, 0, false);
-    g.Y = op(k, w->Zi, 0, false);
+    g.Y = op(k, w->Zi, cur, false);
     g.C = mptr(k, w->P, 0);
     planes_of(k, w->P, 0, g.Cpl);
     g.alpha = 4.0;
-    g.C1 = mptr(k, w->Zi, 0); g.beta1 = 1.0;
+    g.C1 = mptr(k, w->Zi, cur); g.beta1 = 1.0;
     g.sym = true;  // S0 and Z commute (Z is a polynomial in S0)
     STCHK(run_gemm(k, g));
-    G h;  // R[0] = 2 Z - Z M
-    h.X = op(k, w->Zi, 0, false);
+    G h;  // Z' = 2 Z - Z M: straight into the other member, or via R[0] and a symmetrisation
+    h.X = op(k, w->Zi, cur, false);
     h.Y = op(k, w->P, 0, false);
-    h.C = mptr(k, w->R, 0);
+    h.C = exact ? mptr(k, w->Zi, nxt) : mptr(k, w->R, 0);
+    if (exact) planes_of(k, w->Zi, nxt, h.Cpl);
     h.alpha = -1.0;
-    h.C1 = mptr(k, w->Zi, 0); h.beta1 = 2.0;
+    h.C1 = mptr(k, w->Zi, cur); h.beta1 = 2.0;
     h.sym = true;
     STCHK(run_gemm(k, h));
-    HIPCHK(c, (sym_combine<T, T>((const T*)mptr(k, w->R, 0), k.Np, 0, k.N, k.Np, 0.5, nullptr, 0,
-                                 (T*)mptr(k, w->Zi, 0), k.Np, 0, pz, k.np, 1, s)));
-    q8_touch(c, w->Zi, 0);  // pz was fetched once: mark Zi's int8 slices stale on every write
+    if (!exact) {
+      uint16_t* pn[3];
+      planes_of(k, w->Zi, nxt, pn);
+      HIPCHK(c, (sym_combine<T, T>((const T*)mptr(k, w->R, 0), k.Np, 0, k.N, k.Np, 0.5, nullptr, 0,
+                                   (T*)mptr(k, w->Zi, nxt), k.Np, 0, pn, k.np, 1, s)));
+    }
+    cur = nxt;
   }
+  c->zcur = cur;
   return DMPT_OK;
 }
 
@@ -1239,9 +1287,10 @@ dmpt_status ns_solve(const Call& k, const Group& g, int md) {
     HIPCHK(k.c, split_planes((const double*)mptr(k, w->R, 0), k.nn, k.stride, pr, k.stride, k.np, md,
                              k.c->stream));
   }
+  const int zc = k.c->zcur;
   G a;
   a.X = op(k, w->R, 0, true);
-  a.Y = op(k, w->Zi, 0, true);
+  a.Y = op(k, w->Zi, zc, true);
   a.Y.div = md;
   a.C = mptr(k, g, 0);
   a.sC = k.stride;
@@ -1249,6 +1298,8 @@ dmpt_status ns_solve(const Call& k, const Group& g, int md) {
   a.batch = md;
   a.sym = &g == &w->D0;  // order 0: R = 2 D0 commutes with Z
   STCHK(run_gemm(k, a));
+  // an order-0 solution from symmetric tiles is symmetric already
+  if (a.sym && sym_tiles(k) && !ns_refines(k)) return DMPT_OK;
   if (ns_refines(k)) {
     G r;  // R -= U + 4 U S0
     r.X = op(k, g, 0, true);
@@ -1264,7 +1315,7 @@ dmpt_status ns_solve(const Call& k, const Group& g, int md) {
     STCHK(run_gemm(k, r));
     G u;  // U += R Z
     u.X = op(k, w->R, 0, true);
-    u.Y = op(k, w->Zi, 0, true);
+    u.Y = op(k, w->Zi, zc, true);
     u.Y.div = md;
     u.C = mptr(k, g, 0);
     u.sC = k.stride;
@@ -1310,7 +1361,7 @@ template <class T>
 dmpt_status zs_save(const Call& k, int step) {
   if (!zs_fits(k, step)) return fail(k.c, DMPT_ERR_ARG, "internal: inverse-store index");
   uint16_t* none[3] = {nullptr, nullptr, nullptr};
-  HIPCHK(k.c, (convert<T, T>((const T*)mptr(k, k.w->Zi, 0), 0, (T*)k.c->zs + (size_t)step * k.nn, 0, k.nn,
+  HIPCHK(k.c, (convert<T, T>((const T*)mptr(k, k.w->Zi, k.c->zcur), 0, (T*)k.c->zs + (size_t)step * k.nn, 0, k.nn,
                              1, none, 0, 0, k.c->stream)));
   return DMPT_OK;
 }
@@ -1322,6 +1373,7 @@ dmpt_status zs_load(const Call& k, int step) {
   planes_of(k, k.w->Zi, 0, pl);
   HIPCHK(k.c, (convert<T, T>((const T*)k.c->zs + (size_t)step * k.nn, 0, (T*)mptr(k, k.w->Zi, 0), 0, k.nn,
                              1, pl, 0, k.w->Zi.pl[0] ? k.np : 0, k.c->stream)));
+  k.c->zcur = 0;
   return DMPT_OK;
 }
 
@@ -1470,12 +1522,13 @@ dmpt_status recursion_step(const Call& k, int order, int d, int step) {
     if (jt) {
       if (mr > 0) STCHK(ns_solve<T>(k, w->D1, mr));
       G m;  // M = 4 Z Z - 2 Z -> P[J]
-      m.X = op(k, w->Zi, 0, false);
-      m.Y = op(k, w->Zi, 0, false);
+      const int zc = c->zcur;
+      m.X = op(k, w->Zi, zc, false);
+      m.Y = op(k, w->Zi, zc, false);
       m.C = mptr(k, w->P, mr);
       planes_of(k, w->P, mr, m.Cpl);
       m.alpha = 4.0;
-      m.C1 = mptr(k, w->Zi, 0); m.beta1 = -2.0;
+      m.C1 = mptr(k, w->Zi, zc); m.beta1 = -2.0;
       m.sym = true;
       STCHK(run_gemm(k, m));
       G u;  // R[J] = D1_J M, then D1_J = R[J]
@@ -1495,7 +1548,7 @@ dmpt_status recursion_step(const Call& k, int order, int d, int step) {
         for (int z = 0; z < md; ++z) STCHK(tj_load<T>(k, w->D1, z, step, 1 + z));
       STCHK(solve_jet<T>(k, w->D1, md, d));
     }
-    if (k.traj)
+    if (k.traj && !ns)  // CG guesses only
       for (int z = 0; z < md; ++z) STCHK(tj_save<T>(k, w->D1, z, step, 1 + z));
     if (k.chain & kSave01)
       for (int z = 0; z < md; ++z) STCHK(st_save<T>(k, w->D1, z, step, 1 + z));
@@ -1535,7 +1588,7 @@ dmpt_status recursion_step(const Call& k, int order, int d, int step) {
         for (int z = 0; z < md; ++z) STCHK(tj_load<T>(k, w->D2, z, step, 1 + d + z));
       STCHK(solve_jet<T>(k, w->D2, md, d));
     }
-    if (k.traj)
+    if (k.traj && !ns)  // CG guesses only
       for (int z = 0; z < md; ++z) STCHK(tj_save<T>(k, w->D2, z, step, 1 + d + z));
     if (k.chain & kSave2)
       for (int z = 0; z < md; ++z) STCHK(st_save<T>(k, w->D2, z, step, 2 + d + z));
@@ -1582,7 +1635,7 @@ dmpt_status recursion_step(const Call& k, int order, int d, int step) {
         for (int z = 0; z < md; ++z) STCHK(tj_load<T>(k, w->D3, z, step, 1 + 2 * d + z));
       STCHK(solve_jet<T>(k, w->D3, md, d));
     }
-    if (k.traj)
+    if (k.traj && !ns)  // CG guesses only
       for (int z = 0; z < md; ++z) STCHK(tj_save<T>(k, w->D3, z, step, 1 + 2 * d + z));
   }
   return DMPT_OK;
@@ -1647,7 +1700,8 @@ dmpt_status recursion_pass(const Call& k0, const PassIn& in) {
     STCHK(recursion_step<T>(k, in.order, in.d, step));
     STCHK(debug_step(k, in.order, in.d, step));
   }
-  if (k.traj) k.c->tj_valid = in.order;
+  // passes with the shared inverse keep no trajectory (only CG reads it)
+  if (k.traj) k.c->tj_valid = ns_pass(k, in.order) ? -1 : in.order;
   return DMPT_OK;
 }
 
@@ -1747,8 +1801,14 @@ dmpt_status check_dirs(dmpt_ctx c, int d, int order, const double* const* H1, co
 }
 
 // Non-finite scan of the inputs and the Gershgorin interval of sym(H0).
-dmpt_status scan_inputs(dmpt_ctx c, int64_t N, const PassIn& in, double* glo, double* ghi) {
+// gscratch: 2 + 2 N doubles for the Gershgorin row bounds (null: the
+// context's, which holds n_max rows).
+dmpt_status scan_inputs(dmpt_ctx c, int64_t N, const PassIn& in, double* glo, double* ghi,
+                        double* gscratch = nullptr) {
   hipStream_t s = c->stream;
+  double* gs = gscratch ? gscratch : c->d_gersh;
+  if (!gscratch && N > c->n_max)
+    return fail(c, DMPT_ERR_ARG, "internal: the context's Gershgorin scratch holds n_max rows");
   HIPCHK(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), s));
   HIPCHK(c, nonfinite_scan(in.H0, N, N, c->d_flag, s));
   for (int o = 1; o <= in.order; ++o)
@@ -1757,9 +1817,9 @@ dmpt_status scan_inputs(dmpt_ctx c, int64_t N, const PassIn& in, double* glo, do
                                : (o == 2 ? (in.H2 ? in.H2[z] : nullptr) : (in.H3 ? in.H3[z] : nullptr));
       if (h) HIPCHK(c, nonfinite_scan(h, N, N, c->d_flag, s));
     }
-  HIPCHK(c, gershgorin(in.H0, N, c->d_gersh, s));
+  HIPCHK(c, gershgorin(in.H0, N, gs, s));
   double g[2];
-  HIPCHK(c, hipMemcpyAsync(g, c->d_gersh, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(g, gs, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipMemcpyAsync(c->h_int, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
   if (c->h_int[0]) return fail(c, DMPT_ERR_NONFINITE, "non-finite value in an input matrix");
@@ -3004,7 +3064,9 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
     if (planes && c->q8 && count > 0) {
       g.q8 = (int8_t*)alloc(nn * kQ8Slices * count);
       g.qs = (double*)alloc(sizeof(double) * count);
-      if (!g.q8 || !g.qs) return false;
+      const int64_t cap = (c->np_max / 128) * (c->np_max / 128);
+      double* mx = (double*)alloc(sizeof(double) * (size_t)cap * count);
+      if (!g.q8 || !g.qs || !mx) return false;
       Q8Reg r;
       r.m = (const char*)g.m;
       r.stride = (int64_t)nn;
@@ -3012,6 +3074,9 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
       r.q8 = g.q8;
       r.qs = g.qs;
       r.dirty.assign(count, 1);
+      r.mx = mx;
+      r.mx_cap = cap;
+      r.mx_n.assign(count, 0);
       c->q8reg.push_back(r);
     }
     return true;
@@ -3020,7 +3085,7 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
   // R carries planes: the Newton-Schulz solve reads the right-hand sides as an operand
   bool ok = group(c->ws.D0, 1, true) && group(c->ws.S0, 1, true) && group(c->ws.R, dm, true) &&
             group(c->ws.P, dm, true) && group(c->ws.Q, dm, false) && group(c->U0, 1, true) &&
-            group(c->ws.Zi, 1, true);
+            group(c->ws.Zi, 2, true);
   if (ok && dd > 0)
     ok = group(c->ws.D1, dd, true) && group(c->ws.D2, dd, true) && group(c->ws.D3, dd, true) &&
          group(c->ws.S1, dd, true) && group(c->ws.S2, dd, true) && group(c->ws.S3, dd, true);
@@ -3445,7 +3510,14 @@ dmpt_status dmpt_sparse_response(dmpt_ctx c, int64_t N, const double* H0, int d,
   // inputs: non-finite values, range of the recursion
   PassIn pin{H0, dd, H1, nullptr, beta, n, order >= 1 ? 1 : 0, nullptr};
   double glo, ghi;
-  STCHK(scan_inputs(c, N, pin, &glo, &ghi));
+  {
+    // N is not bounded by the context's n_max here: a scratch of its own
+    double* gs = (double*)dev_alloc(c, sizeof(double) * (2 + 2 * (size_t)N));
+    if (!gs) return fail(c, DMPT_ERR_NOMEM, "sparse path: Gershgorin scratch allocation failed");
+    const dmpt_status r = scan_inputs(c, N, pin, &glo, &ghi, gs);  // ends with a stream synchronisation
+    dev_free(c, gs);
+    STCHK(r);
+  }
   if (beta * (ghi - glo) >= std::ldexp(1.0, n + 1))
     return fail(c, DMPT_ERR_RANGE, "beta * spread(H0) >= 2^(n+1): the recursion's start leaves [0, 1]");
   double mu0 = mu_inout[0];

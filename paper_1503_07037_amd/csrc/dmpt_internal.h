@@ -112,6 +112,8 @@ struct GemmArgs {
   const int* active;           // optional per-batch mask; 0 = skip the member
   int variant;                 // kernel variant of the engine (gemm_variants; 0 = default)
   int acc64;                   // BF16S3 only: FP32 per stage, FP64 across stages (128-wide tiles)
+  double* cmax;                // int8 kernels, optional: max |C| of every launched tile at
+  int64_t cmax_stride;         //   cmax[z * cmax_stride + tile] (the int8 slicing of C then skips its scan)
   int sym;                     // C is symmetric: only the tiles on and below the diagonal are
                                // computed (when the tile count per side is even and W is unset),
                                // then the upper triangle is mirrored from the lower one
@@ -165,6 +167,10 @@ hipError_t transpose(const T* in, int64_t Np, int64_t stride, T* out, uint16_t* 
 int q8_blocks(int64_t Np);
 hipError_t quantize_q8(const double* x, int64_t sx, int64_t Np, int batch, double* part, int8_t* q8, int64_t sq,
                        double* qs, const int* active, hipStream_t s);
+// The same with the maxima already known: nb partial maxima per member at
+// part[z * pstride ..] (e.g. the tile maxima a product kernel wrote).
+hipError_t quantize_q8_known(const double* x, int64_t sx, int64_t Np, int batch, const double* part,
+                             int64_t pstride, int nb, int8_t* q8, int64_t sq, double* qs, hipStream_t s);
 
 // Split a master matrix into BF16 planes (batched).
 hipError_t split_planes(const double* x, int64_t n_elems, int64_t sx, uint16_t* const* planes,

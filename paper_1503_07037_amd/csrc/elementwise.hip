@@ -753,13 +753,14 @@ __device__ inline uint32_t pack4(const int* d) {
 // 32 (block row) + l % 32, columns 32 (block col) + 16 (l / 32) .. + 15, and
 // its four slices go to the four 1 KB slice blocks of that block at byte 16 l.
 __global__ __launch_bounds__(kT) void k_quant(const double* __restrict__ x, int64_t sx, int64_t Np,
-                                              const double* __restrict__ part, int nb, int8_t* __restrict__ q8,
-                                              int64_t sq, double* __restrict__ qs, const int* active) {
+                                              const double* __restrict__ part, int64_t pstride, int nb,
+                                              int8_t* __restrict__ q8, int64_t sq, double* __restrict__ qs,
+                                              const int* active) {
   const int z = blockIdx.y;
   if (active && !active[z]) return;
   __shared__ double sm;
   double m = 0.0;
-  for (int i = threadIdx.x; i < nb; i += kT) m = fmax(m, part[(int64_t)z * nb + i]);
+  for (int i = threadIdx.x; i < nb; i += kT) m = fmax(m, part[(int64_t)z * pstride + i]);
   m = block_max(m);
   if (threadIdx.x == 0) sm = m;
   __syncthreads();
@@ -948,8 +949,20 @@ hipError_t quantize_q8(const double* x, int64_t sx, int64_t Np, int batch, doubl
   const int64_t pieces = n / 16;
   int64_t g = (pieces + 2 * kT - 1) / (2 * kT);
   if (g > 65535) g = 65535;
-  hipLaunchKernelGGL(k_quant, dim3((unsigned)g, batch), dim3(kT), 0, s, x, sx, Np, part, (int)nb, q8, sq, qs,
-                     active);
+  hipLaunchKernelGGL(k_quant, dim3((unsigned)g, batch), dim3(kT), 0, s, x, sx, Np, part, (int64_t)nb, (int)nb, q8,
+                     sq, qs, active);
+  return hipGetLastError();
+}
+
+hipError_t quantize_q8_known(const double* x, int64_t sx, int64_t Np, int batch, const double* part,
+                             int64_t pstride, int nb, int8_t* q8, int64_t sq, double* qs, hipStream_t s) {
+  if (Np <= 0 || Np % 32 != 0 || batch < 1 || !x || !part || nb < 1 || pstride < nb || !q8 || !qs)
+    return hipErrorInvalidValue;
+  const int64_t pieces = Np * Np / 16;
+  int64_t g = (pieces + 2 * kT - 1) / (2 * kT);
+  if (g > 65535) g = 65535;
+  hipLaunchKernelGGL(k_quant, dim3((unsigned)g, batch), dim3(kT), 0, s, x, sx, Np, part, pstride, nb, q8, sq, qs,
+                     (const int*)nullptr);
   return hipGetLastError();
 }
 

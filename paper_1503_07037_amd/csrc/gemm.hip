@@ -125,8 +125,8 @@ __device__ inline void write_split(double v, uint16_t* const* pl, int np, int64_
 // Epilogue for output element (row, col): master at row * Np + col, BF16
 // planes (when requested) in the plane layout.
 template <class T>
-__device__ inline void epi(const GemmArgs& a, int z, int64_t row, int64_t col, double acc,
-                           double& dsum) {
+__device__ inline double epi(const GemmArgs& a, int z, int64_t row, int64_t col, double acc,
+                             double& dsum) {
   const int64_t off = row * a.Np + col;
   double v = a.alpha * acc;
   if (a.C1) v += a.beta1 * (double)((const T*)a.C1)[z * a.sC1 + off];
@@ -140,6 +140,25 @@ __device__ inline void epi(const GemmArgs& a, int z, int64_t row, int64_t col, d
     write_split((double)out, pl, a.Cpl[2] ? 3 : (a.Cpl[1] ? 2 : 1), plane_off(row, col, a.Np));
   }
   if (a.W) dsum += (double)((const T*)a.W)[z * a.sW + off] * (double)out;
+  return (double)out;
+}
+
+// Running max |v| of a thread's outputs; a NaN makes it infinite (the int8
+// slicing then fails loudly instead of dropping it).
+__device__ inline double max_abs(double m, double v) { return v == v ? fmax(m, fabs(v)) : INFINITY; }
+
+__device__ inline double block_max(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s = fmax(s, red[i]);
+  }
+  return s;
 }
 
 // One thread per running member adds the member's work to the tally.
@@ -785,7 +804,7 @@ __device__ __forceinline__ void gemm_i8_tile(const GemmArgs& a, int z, int bx, i
     __syncthreads();
   }
   const double rb = 1.0 / kQ8Base;
-  double dsum = 0.0;
+  double dsum = 0.0, dmax = 0.0;
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -797,11 +816,15 @@ __device__ __forceinline__ void gemm_i8_tile(const GemmArgs& a, int z, int bx, i
         double v = (double)acc[W - 1][i][j][r];
 #pragma unroll
         for (int w = W - 2; w >= 0; --w) v = v * rb + (double)acc[w][i][j][r];
-        epi<double>(a, z, row, col, v * scale, dsum);
+        dmax = max_abs(dmax, epi<double>(a, z, row, col, v * scale, dsum));
       }
   if (a.W) {
     const double s = block_sum(dsum, red);
     if (tid == 0) a.partials[(int64_t)z * nbx + bx] = s;
+  }
+  if (a.cmax) {
+    const double m = block_max(dmax, red);
+    if (tid == 0) a.cmax[(int64_t)z * a.cmax_stride + bx] = m;
   }
 }
 
@@ -908,7 +931,7 @@ __device__ __forceinline__ void gemm_i8_dma_tile(const GemmArgs& a, int z, int b
     }
   }
   const double rb = 1.0 / kQ8Base;
-  double dsum = 0.0;
+  double dsum = 0.0, dmax = 0.0;
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -920,11 +943,15 @@ __device__ __forceinline__ void gemm_i8_dma_tile(const GemmArgs& a, int z, int b
         double v = (double)acc[W - 1][i][j][r];
 #pragma unroll
         for (int w = W - 2; w >= 0; --w) v = v * rb + (double)acc[w][i][j][r];
-        epi<double>(a, z, row, col, v * scale, dsum);
+        dmax = max_abs(dmax, epi<double>(a, z, row, col, v * scale, dsum));
       }
   if (a.W) {
     const double s = block_sum(dsum, red);
     if (tid == 0) a.partials[(int64_t)z * nbx + bx] = s;
+  }
+  if (a.cmax) {
+    const double m = block_max(dmax, red);
+    if (tid == 0) a.cmax[(int64_t)z * a.cmax_stride + bx] = m;
   }
 }
 
