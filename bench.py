@@ -5,10 +5,11 @@ Workload (default): the dense random-banded Hamiltonian, N = 8192 (bandwidth
 256, entries 0.3 g exp(-|i-j|/32), diagonal U(-2, 2)), Ne = 4096, beta = 40,
 n = 30 recursion steps, three diagonal dipole perturbations (x, y, z of a
 32 x 16 x 16 grid), orders 0-2 (polarisability and hyperpolarisability), the
-canonical Newton loop of Algorithm 1 (order-0 passes until mu0 is settled,
-then the linear schedule's order-1 and order-2 passes), every product with
-int8 slices (each operand as one scale per matrix times four signed int8
-digits, the thirteen digit products of weight <= 4 summed exactly in int32).
+canonical Newton loop of Algorithm 1: one order-0 pass with the six int8
+digit products of weight <= 2 (three digits) brings mu0 close, then an
+order-0 pass and the linear schedule's order-1 and order-2 passes with all
+thirteen digit products of weight <= 4 (each operand as one scale per matrix
+times four signed int8 digits; products summed exactly in int32).
 Per-step solves: the shared inverse of T' by Newton-Schulz (its start fitted
 to the step's spectral interval; built once per step in the order-1 pass,
 kept for the order-2 pass, applied with one product per right-hand side).
@@ -67,7 +68,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="banded8192",
                     choices=["banded8192", "cubic2048", "chain128", "batch64", "adjoint4096"])
-    ap.add_argument("--prec", default="int8x13", choices=list(PEAKS_TFLOPS))
+    ap.add_argument("--prec", default="int8x6", choices=list(PEAKS_TFLOPS))
     ap.add_argument("--n", type=int, default=0, help="shrink the banded workload to this N (testing)")
     ap.add_argument("--cpu-sample-n", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")

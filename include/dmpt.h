@@ -91,10 +91,13 @@ typedef enum {
                           DMPT_NS_ITERS=k forces k steps everywhere and DMPT_NS_REFINE=0|1 the
                           refinement step off or on (debugging) */
   DMPT_SOLVER_HYBRID = 2 /* the shared inverse in the passes whose products are FP64 or INT8X13 (no
-                            refinement step needed), CG in the others (FP32, BF16 and INT8X6
-                            products: the inverse's rounding biases the jets' traces); under the
-                            linear schedule the order-1 pass keeps Z of every step (n N^2 master
-                            elements, when the memory is there) and the later passes reuse it */
+                            refinement step needed) and in the first-phase passes of INT8X6 with
+                            refine = 2 (loose tolerance: no refinement step; that phase then ends
+                            at an occupation error of 5e-4), CG in the others (FP32, BF16 and
+                            final INT8X6 products: the inverse's rounding biases the jets' traces);
+                            under the linear schedule the order-1 pass keeps Z of every step
+                            (n N^2 master elements, when the memory is there) and the later
+                            passes reuse it */
 } dmpt_solver;
 
 /* Initial guess of the conjugate-gradient solve. */

@@ -314,6 +314,12 @@ double default_tol_cg(dmpt_prec p, int refine) {
 // near 1e-6 of the occupation).
 constexpr double kPhaseATolCg = 1e-5;
 constexpr double kPhaseATolOcc = 1e-5;
+// With 6-product int8 products and the shared inverse the first phase's
+// traces are within ~1e-8 of the final engine's, so its one Newton step from
+// an occupation error below this lands in the final engine's quadratic
+// regime (banded N = 8192: 3.6e-4 -> 2.2e-7) and one pass of the first phase
+// suffices.
+constexpr double kPhaseATolOccI8 = 5e-4;
 // When the first phase meets its tolerance with an occupation error below
 // this, its Newton step is not taken: the error is then within that phase's
 // own trace bias (the 3-product split's rounding), and a step on it moves mu0
@@ -380,6 +386,7 @@ struct Call {
   double glo = NAN, ghi = NAN;   // Gershgorin interval of sym(H0), when the caller scanned it
   double d0b = -1.0;             // this pass: a bound on ||D_0||_2 (< 0: none known)
   int jdir = -1;                 // order-1 member that is the response J to H1 = I (linear schedule)
+  bool first_phase = false;      // a pass of the loose first phase before the final engine's passes
 };
 
 // Issue a launch of the recursion step code now, or record it (k.rec).
@@ -1202,6 +1209,7 @@ NsStart ns_start(const Call& k, int step) {
 // (at N = 8192 the solve without the step matched or beat the CG form).
 bool ns_refines(const Call& k) {
   if (k.c->ns_refine_env >= 0) return k.c->ns_refine_env != 0;
+  if (k.first_phase && k.eng == Engine::I8S3) return false;  // its loose tolerance needs no refinement
   return k.eng != Engine::F64 && k.eng != Engine::I8S4;
 }
 
@@ -1217,7 +1225,8 @@ bool ns_refines(const Call& k) {
 bool ns_pass(const Call& k, int order) {
   (void)order;
   const dmpt_solver sv = k.c->opt.solver;
-  const bool hybrid_ns = sv == DMPT_SOLVER_HYBRID && (k.eng == Engine::F64 || k.eng == Engine::I8S4);
+  const bool hybrid_ns = sv == DMPT_SOLVER_HYBRID && (k.eng == Engine::F64 || k.eng == Engine::I8S4 ||
+                                                      (k.eng == Engine::I8S3 && k.first_phase));
   return (sv == DMPT_SOLVER_NS || hybrid_ns) && k.m == 1 && !k.graph;
 }
 
@@ -3865,7 +3874,11 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
   const Phase lin_phase{two_phase ? refine_engine(c->opt) : k.eng, c->opt.tol_cg, c->opt.tol_occ};
   Phase phases[2];
   int nph = 0;
-  if (two_phase) phases[nph++] = {engine_of(c->opt.prec), kPhaseATolCg, kPhaseATolOcc};
+  if (two_phase) {
+    const Engine ea = engine_of(c->opt.prec);
+    const bool i8a = ea == Engine::I8S3 && c->opt.solver == DMPT_SOLVER_HYBRID;
+    phases[nph++] = {ea, kPhaseATolCg, i8a ? kPhaseATolOccI8 : kPhaseATolOcc};
+  }
   phases[nph++] = lin_phase;
   int ph = 0;
   double occ = 0;
@@ -3885,6 +3898,7 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
     k.eng = P.eng;
     k.np = engine_planes(P.eng);
     k.tol_cg = P.tol_cg;
+    k.first_phase = ph < nph - 1;
     in.order = stage_order;
     STCHK(pass_dispatch(k, in, P0, P1, P2, P3));
     const double* r = c->h_res;
@@ -3964,6 +3978,7 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
     k.eng = P.eng;
     k.np = engine_planes(P.eng);
     k.tol_cg = P.tol_cg;
+    k.first_phase = false;
     bool settled = false;
     int passes = 0;
     STCHK(linear_orders(k, in, N, order, mu.data(), mu_lo, mu_hi, Ne, P.tol_occ, last_rel, P0, P1, P2, P3,
