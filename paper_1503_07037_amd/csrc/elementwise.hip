@@ -759,6 +759,9 @@ __global__ __launch_bounds__(kT) void k_quant(const double* __restrict__ x, int6
   const int z = blockIdx.y;
   if (active && !active[z]) return;
   __shared__ double sm;
+  // one 32 x 32 block per wave and round, staged through LDS: read with whole
+  // 256-byte rows, then each lane takes 16 consecutive elements of one row
+  __shared__ double tile[kT / 64][32][33];
   double m = 0.0;
   for (int i = threadIdx.x; i < nb; i += kT) m = fmax(m, part[(int64_t)z * pstride + i]);
   m = block_max(m);
@@ -769,36 +772,49 @@ __global__ __launch_bounds__(kT) void k_quant(const double* __restrict__ x, int6
   if (blockIdx.x == 0 && threadIdx.x == 0) qs[z] = m / 127.0;
   const double* xm = x + (int64_t)z * sx;
   int8_t* qm = q8 + (int64_t)z * sq;
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+  double(*t)[33] = tile[wave];
   const int64_t kbr = Np >> 5;
-  const int64_t pieces = kbr * kbr * 64;
-  for (int64_t u = (int64_t)blockIdx.x * kT + threadIdx.x; u < pieces; u += (int64_t)gridDim.x * kT) {
-    const int64_t blk = u >> 6;
-    const int l = (int)(u & 63);
-    const int64_t rb = blk / kbr, cb = blk - rb * kbr;
-    const double* src = xm + (rb * 32 + (l & 31)) * Np + cb * 32 + (l >> 5) * 16;
-    int d[kQ8Slices][16];
+  const int64_t nblk = kbr * kbr;
+  // every wave of the block takes the same number of rounds (the barriers)
+  for (int64_t g = blockIdx.x; g * (kT / 64) < nblk; g += gridDim.x) {
+    const int64_t blk = g * (kT / 64) + wave;
+    const bool live = blk < nblk;
+    const int64_t rb = live ? blk / kbr : 0, cb = live ? blk - rb * kbr : 0;
+    if (live) {
+      const double* base = xm + rb * 32 * Np + cb * 32;
 #pragma unroll
-    for (int e = 0; e < 16; e += 2) {
-      const d2v v = *(const d2v*)(src + e);
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        double r = (h ? v.y : v.x) * inv;
-#pragma unroll
-        for (int sl = 0; sl < kQ8Slices; ++sl) {
-          const double t = rint(r);
-          d[sl][e + h] = (int)t;
-          r = (r - t) * kQ8Base;
-        }
+      for (int i = 0; i < 8; ++i) {
+        const int r = i * 4 + (l >> 4), c = (l & 15) * 2;
+        const d2v v = *(const d2v*)(base + (int64_t)r * Np + c);
+        t[r][c] = v.x;
+        t[r][c + 1] = v.y;
       }
     }
+    __syncthreads();
+    if (live) {
+      const int row = l & 31, c0 = (l >> 5) * 16;
+      int d[kQ8Slices][16];
 #pragma unroll
-    for (int sl = 0; sl < kQ8Slices; ++sl) {
-      uint32_t w[4];
+      for (int e = 0; e < 16; ++e) {
+        double r = t[row][c0 + e] * inv;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) w[q] = pack4(&d[sl][4 * q]);
-      uint32_t* dst = (uint32_t*)(qm + ((blk * kQ8Slices + sl) << 10) + l * 16);
-      *(uint4*)dst = make_uint4(w[0], w[1], w[2], w[3]);
+        for (int sl = 0; sl < kQ8Slices; ++sl) {
+          const double q = rint(r);
+          d[sl][e] = (int)q;
+          r = (r - q) * kQ8Base;
+        }
+      }
+#pragma unroll
+      for (int sl = 0; sl < kQ8Slices; ++sl) {
+        uint32_t w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[q] = pack4(&d[sl][4 * q]);
+        uint32_t* dst = (uint32_t*)(qm + ((blk * kQ8Slices + sl) << 10) + l * 16);
+        *(uint4*)dst = make_uint4(w[0], w[1], w[2], w[3]);
+      }
     }
+    __syncthreads();
   }
 }
 
@@ -946,8 +962,8 @@ hipError_t quantize_q8(const double* x, int64_t sx, int64_t Np, int batch, doubl
   const int64_t n = Np * Np;
   const unsigned nb = red_grid(n);
   hipLaunchKernelGGL(k_amax, dim3(nb, batch), dim3(kT), 0, s, x, sx, n, part, (int)nb, active);
-  const int64_t pieces = n / 16;
-  int64_t g = (pieces + 2 * kT - 1) / (2 * kT);
+  const int64_t nblk = (Np / 32) * (Np / 32);
+  int64_t g = (nblk + 2 * (kT / 64) - 1) / (2 * (kT / 64));
   if (g > 65535) g = 65535;
   hipLaunchKernelGGL(k_quant, dim3((unsigned)g, batch), dim3(kT), 0, s, x, sx, Np, part, (int64_t)nb, (int)nb, q8,
                      sq, qs, active);
@@ -958,8 +974,8 @@ hipError_t quantize_q8_known(const double* x, int64_t sx, int64_t Np, int batch,
                              int64_t pstride, int nb, int8_t* q8, int64_t sq, double* qs, hipStream_t s) {
   if (Np <= 0 || Np % 32 != 0 || batch < 1 || !x || !part || nb < 1 || pstride < nb || !q8 || !qs)
     return hipErrorInvalidValue;
-  const int64_t pieces = Np * Np / 16;
-  int64_t g = (pieces + 2 * kT - 1) / (2 * kT);
+  const int64_t nblk = (Np / 32) * (Np / 32);
+  int64_t g = (nblk + 2 * (kT / 64) - 1) / (2 * (kT / 64));
   if (g > 65535) g = 65535;
   hipLaunchKernelGGL(k_quant, dim3((unsigned)g, batch), dim3(kT), 0, s, x, sx, Np, part, pstride, nb, q8, sq, qs,
                      (const int*)nullptr);
