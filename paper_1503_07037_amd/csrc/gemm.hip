@@ -143,10 +143,6 @@ __device__ inline double epi(const GemmArgs& a, int z, int64_t row, int64_t col,
   return (double)out;
 }
 
-// Running max |v| of a thread's outputs; a NaN makes it infinite (the int8
-// slicing then fails loudly instead of dropping it).
-__device__ inline double max_abs(double m, double v) { return v == v ? fmax(m, fabs(v)) : INFINITY; }
-
 __device__ inline double block_max(double v, double* red) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
@@ -804,7 +800,12 @@ __device__ __forceinline__ void gemm_i8_tile(const GemmArgs& a, int z, int bx, i
     __syncthreads();
   }
   const double rb = 1.0 / kQ8Base;
-  double dsum = 0.0, dmax = 0.0;
+  double dsum = 0.0;
+  // largest |C| of the tile, rounded up to FP32: an upper bound, so the
+  // digits of the slicing still fit (their scale is at most 2^-24 larger than
+  // the exact maximum's), and one register instead of two keeps the epilogue
+  // within the register budget
+  float fmx = 0.0f;
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -816,14 +817,17 @@ __device__ __forceinline__ void gemm_i8_tile(const GemmArgs& a, int z, int bx, i
         double v = (double)acc[W - 1][i][j][r];
 #pragma unroll
         for (int w = W - 2; w >= 0; --w) v = v * rb + (double)acc[w][i][j][r];
-        dmax = max_abs(dmax, epi<double>(a, z, row, col, v * scale, dsum));
+        {
+          const double o = epi<double>(a, z, row, col, v * scale, dsum);
+          fmx = o == o ? fmaxf(fmx, __double2float_ru(fabs(o))) : INFINITY;
+        }
       }
   if (a.W) {
     const double s = block_sum(dsum, red);
     if (tid == 0) a.partials[(int64_t)z * nbx + bx] = s;
   }
   if (a.cmax) {
-    const double m = block_max(dmax, red);
+    const double m = block_max((double)fmx, red);
     if (tid == 0) a.cmax[(int64_t)z * a.cmax_stride + bx] = m;
   }
 }
@@ -931,7 +935,12 @@ __device__ __forceinline__ void gemm_i8_dma_tile(const GemmArgs& a, int z, int b
     }
   }
   const double rb = 1.0 / kQ8Base;
-  double dsum = 0.0, dmax = 0.0;
+  double dsum = 0.0;
+  // largest |C| of the tile, rounded up to FP32: an upper bound, so the
+  // digits of the slicing still fit (their scale is at most 2^-24 larger than
+  // the exact maximum's), and one register instead of two keeps the epilogue
+  // within the register budget
+  float fmx = 0.0f;
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -943,14 +952,17 @@ __device__ __forceinline__ void gemm_i8_dma_tile(const GemmArgs& a, int z, int b
         double v = (double)acc[W - 1][i][j][r];
 #pragma unroll
         for (int w = W - 2; w >= 0; --w) v = v * rb + (double)acc[w][i][j][r];
-        dmax = max_abs(dmax, epi<double>(a, z, row, col, v * scale, dsum));
+        {
+          const double o = epi<double>(a, z, row, col, v * scale, dsum);
+          fmx = o == o ? fmaxf(fmx, __double2float_ru(fabs(o))) : INFINITY;
+        }
       }
   if (a.W) {
     const double s = block_sum(dsum, red);
     if (tid == 0) a.partials[(int64_t)z * nbx + bx] = s;
   }
   if (a.cmax) {
-    const double m = block_max(dmax, red);
+    const double m = block_max((double)fmx, red);
     if (tid == 0) a.cmax[(int64_t)z * a.cmax_stride + bx] = m;
   }
 }
