@@ -752,24 +752,28 @@ __device__ inline uint32_t pack4(const int* d) {
 // u % 64 of 32 x 32 block u / 64 (block row major), i.e. row
 // 32 (block row) + l % 32, columns 32 (block col) + 16 (l / 32) .. + 15, and
 // its four slices go to the four 1 KB slice blocks of that block at byte 16 l.
-__global__ __launch_bounds__(kT) void k_quant(const double* __restrict__ x, int64_t sx, int64_t Np,
-                                              const double* __restrict__ part, int64_t pstride, int nb,
-                                              int8_t* __restrict__ q8, int64_t sq, double* __restrict__ qs,
-                                              const int* active) {
-  const int z = blockIdx.y;
+// qs[z] = (the largest of member z's nb partial maxima) / 127, one block per member.
+__global__ __launch_bounds__(kT) void k_qscale(const double* __restrict__ part, int64_t pstride, int nb,
+                                               double* __restrict__ qs, const int* active) {
+  const int z = blockIdx.x;
   if (active && !active[z]) return;
-  __shared__ double sm;
-  // one 32 x 32 block per wave and round, staged through LDS: read with whole
-  // 256-byte rows, then each lane takes 16 consecutive elements of one row
-  __shared__ double tile[kT / 64][32][33];
   double m = 0.0;
   for (int i = threadIdx.x; i < nb; i += kT) m = fmax(m, part[(int64_t)z * pstride + i]);
   m = block_max(m);
-  if (threadIdx.x == 0) sm = m;
-  __syncthreads();
-  m = sm;
-  const double inv = (m > 0.0 && m <= 1.0e308) ? 127.0 / m : 0.0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) qs[z] = m / 127.0;
+  if (threadIdx.x == 0) qs[z] = m / 127.0;
+}
+
+__global__ __launch_bounds__(kT) void k_quant(const double* __restrict__ x, int64_t sx, int64_t Np,
+                                              int8_t* __restrict__ q8, int64_t sq, const double* __restrict__ qs,
+                                              const int* active) {
+  const int z = blockIdx.y;
+  if (active && !active[z]) return;
+  // one 32 x 32 block per wave and round, staged through LDS: read with whole
+  // 256-byte rows, then each lane takes 16 consecutive elements of one row
+  __shared__ double tile[kT / 64][32][33];
+  // digits of x / q, q = qs[z] = max |x| / 127 (the scale the products apply)
+  const double q = qs[z];
+  const double inv = (q > 0.0 && q <= 1.0e306) ? 1.0 / q : 0.0;
   const double* xm = x + (int64_t)z * sx;
   int8_t* qm = q8 + (int64_t)z * sq;
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -962,11 +966,12 @@ hipError_t quantize_q8(const double* x, int64_t sx, int64_t Np, int batch, doubl
   const int64_t n = Np * Np;
   const unsigned nb = red_grid(n);
   hipLaunchKernelGGL(k_amax, dim3(nb, batch), dim3(kT), 0, s, x, sx, n, part, (int)nb, active);
+  hipLaunchKernelGGL(k_qscale, dim3(batch), dim3(kT), 0, s, part, (int64_t)nb, (int)nb, qs, active);
   const int64_t nblk = (Np / 32) * (Np / 32);
   int64_t g = (nblk + 2 * (kT / 64) - 1) / (2 * (kT / 64));
   if (g > 65535) g = 65535;
-  hipLaunchKernelGGL(k_quant, dim3((unsigned)g, batch), dim3(kT), 0, s, x, sx, Np, part, (int64_t)nb, (int)nb, q8,
-                     sq, qs, active);
+  hipLaunchKernelGGL(k_quant, dim3((unsigned)g, batch), dim3(kT), 0, s, x, sx, Np, q8, sq, (const double*)qs,
+                     active);
   return hipGetLastError();
 }
 
@@ -974,10 +979,11 @@ hipError_t quantize_q8_known(const double* x, int64_t sx, int64_t Np, int batch,
                              int64_t pstride, int nb, int8_t* q8, int64_t sq, double* qs, hipStream_t s) {
   if (Np <= 0 || Np % 32 != 0 || batch < 1 || !x || !part || nb < 1 || pstride < nb || !q8 || !qs)
     return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_qscale, dim3(batch), dim3(kT), 0, s, part, pstride, nb, qs, (const int*)nullptr);
   const int64_t nblk = (Np / 32) * (Np / 32);
   int64_t g = (nblk + 2 * (kT / 64) - 1) / (2 * (kT / 64));
   if (g > 65535) g = 65535;
-  hipLaunchKernelGGL(k_quant, dim3((unsigned)g, batch), dim3(kT), 0, s, x, sx, Np, part, pstride, nb, q8, sq, qs,
+  hipLaunchKernelGGL(k_quant, dim3((unsigned)g, batch), dim3(kT), 0, s, x, sx, Np, q8, sq, (const double*)qs,
                      (const int*)nullptr);
   return hipGetLastError();
 }
