@@ -107,3 +107,45 @@ def test_struct_layouts_match_the_header(struct, pyname):
     assert lay["size"] == ctypes.sizeof(cls)
     for n in names:
         assert lay[n] == getattr(cls, n).offset, n
+
+
+def _c_values(names):
+    """Values of header enumerators, from a C program compiled with gcc."""
+    import json
+    import shutil
+    import subprocess
+    import tempfile
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if not cc:
+        pytest.skip("no C compiler")
+    body = ",".join(f'\\"{n}\\":%d' for n in names)
+    args = ", ".join(f"(int){n}" for n in names)
+    src = f"""#include <stdio.h>
+#include "dmpt.h"
+int main(void) {{ printf("{{{body}}}", {args}); return 0; }}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "values.c")
+        exe = os.path.join(d, "values")
+        open(c, "w").write(src)
+        subprocess.run([cc, "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        return json.loads(subprocess.run([exe], check=True, stdout=subprocess.PIPE, text=True).stdout)
+
+
+def test_binding_enum_values_match_the_header():
+    """The binding's names for precision modes, solvers and guesses map to the header's values, and every
+    enumerator of those enums has a name in the binding."""
+    from paper_1503_07037_amd import _lib as L
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    groups = {"dmpt_prec": (L.PREC, {"fp64": "DMPT_FP64", "fp32": "DMPT_FP32", "bf16x3": "DMPT_BF16X3",
+                                      "bf16x6": "DMPT_BF16X6", "int8x13": "DMPT_INT8X13", "int8x6": "DMPT_INT8X6"}),
+              "dmpt_solver": (L.SOLVER, {"cg": "DMPT_SOLVER_CG", "ns": "DMPT_SOLVER_NS",
+                                         "hybrid": "DMPT_SOLVER_HYBRID"}),
+              "dmpt_guess": (L.GUESS, {"prev": "DMPT_GUESS_PREV", "taylor": "DMPT_GUESS_TAYLOR"})}
+    for enum, (pymap, cnames) in groups.items():
+        body = re.search(r"typedef enum \{([^}]*)\}\s*" + enum + r"\s*;", text).group(1)
+        declared = re.findall(r"\b(DMPT_[A-Z0-9_]+)\s*=", body)
+        assert sorted(declared) == sorted(cnames.values()), (enum, declared)
+        vals = _c_values(list(cnames.values()))
+        for py, cn in cnames.items():
+            assert pymap[py] == vals[cn], (enum, py, cn)
