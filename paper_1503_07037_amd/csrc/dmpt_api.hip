@@ -3863,7 +3863,12 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
   // trajectory members: order 0, order 1 (plus the identity direction of the
   // linear schedule), orders 2 and 3
   const int jets = linear ? std::max(2 + dd, 1 + order * dd) : 1 + order * dd;
-  if (c->opt.warm_traj && ensure_traj(c, n, jets, k.Np)) {
+  // only CG reads the trajectory: none when every pass solves with the shared inverse
+  const Engine e_final = refinable(c->opt.prec) && c->opt.refine ? refine_engine(c->opt) : engine_of(c->opt.prec);
+  const bool all_ns = c->opt.solver == DMPT_SOLVER_NS ||
+                      (c->opt.solver == DMPT_SOLVER_HYBRID && (e_final == Engine::F64 || e_final == Engine::I8S4) &&
+                       (!(refinable(c->opt.prec) && c->opt.refine) || engine_of(c->opt.prec) == Engine::I8S3));
+  if (c->opt.warm_traj && !all_ns && ensure_traj(c, n, jets, k.Np)) {
     k.traj = true;
     k.jets = jets;
   }
