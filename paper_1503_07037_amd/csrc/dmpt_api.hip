@@ -147,8 +147,8 @@ struct dmpt_ctx_s {
   void* zs = nullptr;
   size_t zs_bytes = 0;
   int zcur = 0;                  // member of ws.Zi that holds the current step's inverse
-  int ns_iters_env = 0;          // DMPT_NS_ITERS (experiments: Newton-Schulz steps)
-  int ns_refine_env = -1;        // DMPT_NS_REFINE (experiments: 0/1 refinement step)
+  int ns_iters_env = 0;          // DMPT_NS_ITERS (debugging): Newton-Schulz steps in every step
+  int ns_refine_env = -1;        // DMPT_NS_REFINE (debugging): refinement step off (0) or on (1)
   bool full_tiles = false;       // DMPT_FULL_TILES set: symmetric products compute every tile
   int64_t tj_np = 0;
   int tj_valid = -1;
