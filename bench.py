@@ -64,7 +64,7 @@ REFINE_NAME = {1: "bf16x6", 2: "int8x13"}
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="banded8192",
                     choices=["banded8192", "cubic2048", "chain128", "batch64", "adjoint4096"])
