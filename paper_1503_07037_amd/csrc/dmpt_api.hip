@@ -147,9 +147,12 @@ struct dmpt_ctx_s {
   void* zs = nullptr;
   size_t zs_bytes = 0;
   int zcur = 0;                  // member of ws.Zi that holds the current step's inverse
+  bool zs_valid = false;         // zs holds this call's inverses of a pass at mu0 = zs_mu0
+  double zs_mu0 = 0.0;
   int ns_iters_env = 0;          // DMPT_NS_ITERS (debugging): Newton-Schulz steps in every step
   int ns_refine_env = -1;        // DMPT_NS_REFINE (debugging): refinement step off (0) or on (1)
   bool full_tiles = false;       // DMPT_FULL_TILES set: symmetric products compute every tile
+  bool ns_cold = false;          // DMPT_NS_COLD set: no Newton-Schulz start from stored inverses
   int64_t tj_np = 0;
   int tj_valid = -1;
   Group U0;                      // order-0 CG unknown when the guess comes from tj
@@ -387,6 +390,8 @@ struct Call {
   double d0b = -1.0;             // this pass: a bound on ||D_0||_2 (< 0: none known)
   int jdir = -1;                 // order-1 member that is the response J to H1 = I (linear schedule)
   bool first_phase = false;      // a pass of the loose first phase before the final engine's passes
+  double cscale = 0.0;           // this pass: c = beta 2^-(n+2)
+  double z_dmu = -1.0;           // |mu0 - mu0 of the stored inverses| (kWarmZ; < 0: none)
 };
 
 // Issue a launch of the recursion step code now, or record it (k.rec).
@@ -408,6 +413,9 @@ constexpr int kSave01 = 1, kLoad01 = 2, kSave2 = 4, kLoad2 = 8;
 constexpr int kSaveS = 16, kLoadS = 32;
 // ... and save or load the shared inverse Z of every step (c->zs)
 constexpr int kSaveZ = 64, kLoadZ = 128;
+// ... or start each step's Newton-Schulz iteration from the stored Z of a
+// pass at a nearby mu0 when that needs fewer steps (see ns_warm_iters)
+constexpr int kWarmZ = 256;
 
 // Member z of a group as an operand.
 BOp op(const Call& k, const Group& g, int z, bool batched) {
@@ -1238,20 +1246,61 @@ bool sym_tiles(const Call& k) {
   return !k.rec && !k.c->full_tiles && (k.Np / edge) % 2 == 0;
 }
 
+// Steps of the iteration from a stored inverse Z_old of T'_old (a pass at
+// mu0 - dmu): the perturbation enters D_0 = c (H - mu0 I) as c dmu I, which
+// commutes with H, so ||D_s - D_s,old|| <= min(2^s c |dmu|, 2 b_s) (|f'| <= 2)
+// and ||I - T' Z_old|| <= 4 ||D_s^2 - D_s,old^2|| <= 8 b_s ||D_s - D_s,old||,
+// floored at the stored inverse's own rounding (1e-10).  Returns the step
+// count to 2^-60 when it is below the count from the minimax start, else -1.
+int ns_warm_iters(const Call& k, int step, int scratch) {
+  if (!(k.z_dmu >= 0.0) || k.d0b < 0.0 || !(k.cscale > 0.0) || step < 0 || k.c->ns_iters_env > 0) return -1;
+  const double bs = std::min(0.5, std::ldexp(k.d0b, std::min(step, 1000)) * (1.0 + 1e-3));
+  const double dd = std::min(2.0 * bs, std::ldexp(k.cscale * k.z_dmu, std::min(step, 1000)) * (1.0 + 1e-3));
+  double e = std::max(8.0 * bs * dd, 1e-10);
+  if (!(e < 1.0)) return -1;
+  int it = 0;
+  do {
+    e = e * e;
+    ++it;
+  } while (e > 0x1p-60 && it < kNsIters);
+  return e <= 0x1p-60 && it < scratch ? it : -1;
+}
+
+template <class T>
+dmpt_status ns_iterate(const Call& k, int iters);
+template <class T>
+dmpt_status zs_load(const Call& k, int step);
+
 template <class T>
 dmpt_status ns_inverse(const Call& k, int step) {
   dmpt_ctx c = k.c;
   const WS* w = k.w;
   hipStream_t s = c->stream;
   if (k.m != 1) return fail(c, DMPT_ERR_ARG, "internal: Newton-Schulz runs on one system");
+  const NsStart z0 = ns_start(k, step);
+  if (k.chain & kWarmZ) {
+    const int wi = ns_warm_iters(k, step, z0.iters);
+    if (wi > 0) {
+      STCHK(zs_load<T>(k, step));  // Z_old into member 0
+      return ns_iterate<T>(k, wi);
+    }
+  }
   uint16_t* pz[3];
   planes_of(k, w->Zi, 0, pz);
-  const NsStart z0 = ns_start(k, step);
   HIPCHK(c, scaled_plus_identity<T>((const T*)mptr(k, w->S0, 0), (T*)mptr(k, w->Zi, 0), k.N, k.Np, z0.a,
                                     z0.b, pz, k.np, s));
+  return ns_iterate<T>(k, z0.iters);
+}
+
+// Newton-Schulz steps Z <- Z (2 I - T' Z) from the start in member 0 of Zi.
+template <class T>
+dmpt_status ns_iterate(const Call& k, int iters) {
+  dmpt_ctx c = k.c;
+  const WS* w = k.w;
+  hipStream_t s = c->stream;
   int cur = 0;
   const bool exact = sym_tiles(k);  // symmetric products leave Z exactly symmetric
-  for (int it = 0; it < z0.iters; ++it) {
+  for (int it = 0; it < iters; ++it) {
     const int nxt = 1 - cur;
     G g;  // M = T' Z = Z + 4 S0 Z  -> P[0] (with planes)
     g.X = op(k, w->S0, 0, false);
@@ -1701,6 +1750,7 @@ template <class T>
 dmpt_status recursion_pass(const Call& k0, const PassIn& in) {
   const double cscale = std::ldexp(in.beta, -(in.n + 2));
   Call k = k0;
+  k.cscale = cscale;
   if (std::isfinite(k0.glo) && std::isfinite(k0.ghi) && in.mu)
     k.d0b = cscale * std::max(std::fabs(k0.glo - in.mu[0]), std::fabs(k0.ghi - in.mu[0]));
   STCHK(init_d<T>(k, in, cscale));
@@ -2585,11 +2635,21 @@ dmpt_status linear_orders(Call& k, const PassIn& base, int64_t N, int order, dou
   for (int a = 0; a < kMaxPasses; ++a) {
     m1[0] = mu[0];
     k.chain = keep ? (kSave01 | (keep_s ? kSaveS : 0) | (keep_z ? kSaveZ : 0)) : 0;
+    // the final order-0 pass (or the previous order-1 pass) left its inverses
+    // at a nearby mu0: start from them where that saves steps
+    const bool warm = keep_z && c->zs_valid && !c->ns_cold;
+    if (warm) {
+      k.chain |= kWarmZ;
+      k.z_dmu = std::fabs(mu[0] - c->zs_mu0);
+    }
     k.jdir = d;
     const dmpt_status e1 = pass_dispatch(k, in1, P0, p1x.data(), nullptr);
     k.jdir = -1;
     k.chain = 0;
+    k.z_dmu = -1.0;
     STCHK(e1);
+    c->zs_valid = keep_z;
+    c->zs_mu0 = mu[0];
     *passes += 1;
     trJ = c->h_res[RES_TR + 1 + d];
     if (!(std::fabs(trJ) > 0.0) || !std::isfinite(trJ))
@@ -3044,6 +3104,7 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
   if (const char* e = std::getenv("DMPT_NS_ITERS")) c->ns_iters_env = std::atoi(e);
   if (const char* e = std::getenv("DMPT_NS_REFINE")) c->ns_refine_env = std::atoi(e);
   c->full_tiles = std::getenv("DMPT_FULL_TILES") != nullptr;
+  c->ns_cold = std::getenv("DMPT_NS_COLD") != nullptr;
 
 
   c->n_max = n_max;
@@ -3816,6 +3877,7 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
   ENTER(c);
   const auto t0 = std::chrono::steady_clock::now();
   reset_stats(c);
+  c->zs_valid = false;  // stored inverses belong to one call's Hamiltonian
   if (c->log) std::fprintf(stderr, "[dmpt] mu_newton N %lld d %d order %d t %.4f\n", (long long)N, d, order, log_clock());
   const int dd = order >= 1 ? d : 0;
   const int nmu = 1 + order * dd;
@@ -3905,7 +3967,19 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
     k.tol_cg = P.tol_cg;
     k.first_phase = ph < nph - 1;
     in.order = stage_order;
-    STCHK(pass_dispatch(k, in, P0, P1, P2, P3));
+    // the final engine's order-0 passes keep their inverses: the order-1
+    // pass starts from them (one mu0 Newton step away)
+    const bool save_z = linear && ph == nph - 1 && stage_order == 0 && ns_pass(k, 0) &&
+                        ensure_inverses(c, n, k.Np);
+    const double pass_mu0 = mu[0];
+    k.chain = save_z ? kSaveZ : 0;
+    const dmpt_status ep = pass_dispatch(k, in, P0, P1, P2, P3);
+    k.chain = 0;
+    STCHK(ep);
+    if (save_z) {
+      c->zs_valid = true;
+      c->zs_mu0 = pass_mu0;
+    }
     const double* r = c->h_res;
     if (!std::isfinite(r[RES_TR]) || !std::isfinite(r[RES_FRO]))
       return fail(c, DMPT_ERR_NONFINITE, "non-finite trace in the Newton loop");
