@@ -3907,8 +3907,9 @@ dmpt_status dmpt_mu_newton(dmpt_ctx c, int64_t N, const double* H0, int d, const
   const double mu_lo = std::max(ghi - lrange, glo - 50.0 / beta);
   const double mu_hi = std::min(glo + lrange, ghi + 50.0 / beta);
   mu[0] = std::min(std::max(mu[0], mu_lo), mu_hi);
-  // Phases: with refinement, the split-BF16 3-product engine (loose
-  // tolerances) brings the mu jet close, then the 6-product engine with the
+  // Phases: with refinement, the cheaper engine of prec (3-product split
+  // BF16 or 6-product int8; loose tolerances) brings mu0 close, then the
+  // refinement engine (6-product split BF16 or 13-product int8) with the
   // final tolerances finishes; otherwise a single phase.
   Call k = make_call(c, N, false);
   k.glo = glo;
