@@ -87,9 +87,11 @@ typedef enum {
                           ||D|| ~ 1/2, none while ||D|| < ~1e-5), reused for every order and
                           direction (Sec. II remark): one product per right-hand side, plus one
                           refinement step with FP32, BF16 and INT8X6 products; single-system paths
-                          (the batched and adjoint paths keep CG).  In the environment,
-                          DMPT_NS_ITERS=k forces k steps everywhere and DMPT_NS_REFINE=0|1 the
-                          refinement step off or on (debugging) */
+                          (the batched and adjoint paths keep CG).  Under the linear schedule the
+                          order-1 pass starts each step from the final order-0 pass's inverse
+                          where a bound on the mu0 shift allows fewer steps.  In the environment,
+                          DMPT_NS_ITERS=k forces k steps everywhere, DMPT_NS_REFINE=0|1 the
+                          refinement step off or on and DMPT_NS_COLD the fresh start (debugging) */
   DMPT_SOLVER_HYBRID = 2 /* the shared inverse in the passes whose products are FP64 or INT8X13 (no
                             refinement step needed) and in the first-phase passes of INT8X6 with
                             refine = 2 (loose tolerance: no refinement step; that phase then ends
@@ -124,7 +126,8 @@ typedef struct {
   int staged;           /* 1: converge mu0 with order-0 passes first, then run full passes (same fixed point) */
   int warm_traj;        /* 1: keep every step's iterates (FP32 copies) and start each CG of the next
                            Newton pass from the same step's previous solution instead of the
-                           previous recursion step's iterate; falls back when memory is short */
+                           previous recursion step's iterate; falls back when memory is short, and
+                           is not allocated when every pass solves with the shared inverse */
   int schedule;         /* canonical loop for orders >= 1: 0 = Algorithm 1's Newton update of every
                            mu^(k) with Tr P_mu; 1 = after mu0 has converged, one pass per order with
                            the extra response J to H1 = I: P^(k) is affine in mu^(k) with slope -J,
