@@ -1019,15 +1019,13 @@ dmpt_status st_load(const Call& k, const Group& g, int z, int step, int j, doubl
     return fail(k.c, DMPT_ERR_ARG, "internal: chain index");
   uint16_t* pl[3];
   planes_of(k, g, z, pl);
-  uint16_t* none[3] = {nullptr, nullptr, nullptr};
   T* dst = (T*)mptr(k, g, z);
   if (a == 0.0) {
     HIPCHK(k.c, (convert<T, T>(st_ptr<T>(k, step, j), 0, dst, 0, k.nn, 1, pl, 0,
                                g.pl[0] ? k.np : 0, k.c->stream)));
   } else {
-    HIPCHK(k.c, (convert<T, T>(st_ptr<T>(k, step, j), 0, dst, 0, k.nn, 1, none, 0, 0, k.c->stream)));
-    HIPCHK(k.c, axpby<T>(st_ptr<T>(k, step, jb), 0, dst, 0, k.nn, 1, -a, 1.0, pl, 0,
-                         g.pl[0] ? k.np : 0, k.c->stream));
+    HIPCHK(k.c, axpbyz<T>(st_ptr<T>(k, step, jb), st_ptr<T>(k, step, j), dst, k.nn, -a, 1.0, pl,
+                          g.pl[0] ? k.np : 0, k.c->stream));
   }
   return DMPT_OK;
 }
@@ -1060,15 +1058,13 @@ dmpt_status ss_load(const Call& k, const Group& g, int z, int step, int j, doubl
     return fail(k.c, DMPT_ERR_ARG, "internal: square-term index");
   uint16_t* pl[3];
   planes_of(k, g, z, pl);
-  uint16_t* none[3] = {nullptr, nullptr, nullptr};
   T* dst = (T*)mptr(k, g, z);
   if (a == 0.0) {
     HIPCHK(k.c, (convert<T, T>(ss_ptr<T>(k, step, j), 0, dst, 0, k.nn, 1, pl, 0, g.pl[0] ? k.np : 0,
                                k.c->stream)));
   } else {
-    HIPCHK(k.c, (convert<T, T>(ss_ptr<T>(k, step, j), 0, dst, 0, k.nn, 1, none, 0, 0, k.c->stream)));
-    HIPCHK(k.c, axpby<T>(ss_ptr<T>(k, step, jb), 0, dst, 0, k.nn, 1, -a, 1.0, pl, 0, g.pl[0] ? k.np : 0,
-                         k.c->stream));
+    HIPCHK(k.c, axpbyz<T>(ss_ptr<T>(k, step, jb), ss_ptr<T>(k, step, j), dst, k.nn, -a, 1.0, pl,
+                          g.pl[0] ? k.np : 0, k.c->stream));
   }
   return DMPT_OK;
 }
@@ -1442,10 +1438,17 @@ dmpt_status recursion_step(const Call& k, int order, int d, int step) {
   dmpt_ctx c = k.c;
   const WS* w = k.w;
   const int md = k.m * d;
-  if (k.chain & kLoadS) STCHK(ss_load<T>(k, w->S0, 0, step, 0, 0.0, 0));
-  else STCHK(square0<T>(k));
-  if (k.chain & kSaveS) STCHK(ss_save<T>(k, w->S0, 0, step, 0));
   const bool ns = ns_pass(k, order);
+  // S0 serves only the solves (T' in CG, the inverse's iteration and its
+  // refinement): a pass that loads the order-0/1 chains and the inverse and
+  // refines nothing does not read it
+  const bool s0_unread = ns && (k.chain & kLoad01) && (k.chain & kLoadZ) && !ns_refines(k);
+  if (k.chain & kLoadS) {
+    if (!s0_unread) STCHK(ss_load<T>(k, w->S0, 0, step, 0, 0.0, 0));
+  } else {
+    STCHK(square0<T>(k));
+  }
+  if (k.chain & kSaveS) STCHK(ss_save<T>(k, w->S0, 0, step, 0));
   // the identity direction of an order-1 pass solved with the shared inverse:
   // with S1_J = 2 D0 D1_J, Y0 = 2 D0 Z and 4 S0 Z = I - Z, the order-1 step
   // (2 D1_J - 4 Y0 S1_J) Z is D1_J (4 Z^2 - 2 Z), two symmetric products
@@ -1544,7 +1547,18 @@ dmpt_status recursion_step(const Call& k, int order, int d, int step) {
     // the order-0 chain of this mu0 is stored: Y0 = its solution at this step
     STCHK(st_load<T>(k, w->D0, 0, step, 0, 0.0, 0));
   } else {
-    if (ns) {
+    if (ns && engine_int8(k.eng) && !ns_refines(k)) {
+      // D0 = 2 D0 Z in place: the int8 product reads D0's slices (made before
+      // it starts), never its master, and 2 D0 commutes with Z
+      G a;
+      a.X = op(k, w->D0, 0, false);
+      a.Y = op(k, w->Zi, c->zcur, false);
+      a.C = mptr(k, w->D0, 0);
+      a.alpha = 2.0;
+      a.sym = true;
+      STCHK(run_gemm(k, a));
+      if (!sym_tiles(k)) STCHK(sym_inplace<T>(k, w->D0, 0, 1, 0.5));
+    } else if (ns) {
       // R = 2 D0 (with planes), D0 = R Z
       uint16_t* pr[3];
       planes_of(k, w->R, 0, pr);

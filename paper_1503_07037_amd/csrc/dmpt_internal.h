@@ -233,6 +233,12 @@ template <class T>
 hipError_t axpby(const T* x, int64_t sx, T* y, int64_t sy, int64_t n, int batch, double a,
                  double b, uint16_t* const* planes, int64_t sp, int nplanes, hipStream_t s);
 
+// Element-wise linear combination into a third array: out = a x + b y
+// (one member, master) + planes of out
+template <class T>
+hipError_t axpbyz(const T* x, const T* y, T* out, int64_t n, double a, double b, uint16_t* const* planes,
+                  int nplanes, hipStream_t s);
+
 // out = (Tout) in for n elements per member (batched) + planes of out
 template <class Tin, class Tout>
 hipError_t convert(const Tin* in, int64_t si, Tout* out, int64_t so, int64_t n, int batch,

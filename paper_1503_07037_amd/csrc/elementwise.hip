@@ -406,6 +406,34 @@ __global__ __launch_bounds__(kT) void k_axpby(const T* __restrict__ x, int64_t s
   }
 }
 
+// out = a x + b y (one member), with planes of out: the same arithmetic as
+// k_axpby with y read from a third array
+template <class T>
+__global__ __launch_bounds__(kT) void k_axpbyz(const T* __restrict__ x, const T* __restrict__ y,
+                                               T* __restrict__ out, int64_t n, double a, double b, Planes pl,
+                                               int np, int64_t Np, int v2) {
+  uint16_t* p3[3] = {pl.p[0], pl.p[1], pl.p[2]};
+  const T ta = (T)a, tb = (T)b;
+  if (v2) {
+    for (int64_t c = (int64_t)blockIdx.x * kT + threadIdx.x; c < (n >> 1); c += (int64_t)gridDim.x * kT) {
+      const int64_t i = c << 1;
+      T xv[2], yv[2];
+      ld2(x + i, xv);
+      ld2(y + i, yv);
+#pragma unroll
+      for (int e = 0; e < 2; ++e) yv[e] = ta * xv[e] + tb * yv[e];
+      st2(out + i, yv);
+      if (np) split_store2(yv, p3, np, plane_off_lin(i, Np));
+    }
+    return;
+  }
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+    const T v = ta * x[i] + tb * y[i];
+    out[i] = v;
+    if (np) split_store((double)v, p3, np, plane_off_lin(i, Np));
+  }
+}
+
 // out = (Tout) in, batched, with planes of out
 template <class Tin, class Tout>
 __global__ __launch_bounds__(kT) void k_convert(const Tin* __restrict__ in, int64_t si,
@@ -1119,6 +1147,24 @@ template hipError_t axpby<double>(const double*, int64_t, double*, int64_t, int6
                                   double, uint16_t* const*, int64_t, int, hipStream_t);
 template hipError_t axpby<float>(const float*, int64_t, float*, int64_t, int64_t, int, double,
                                  double, uint16_t* const*, int64_t, int, hipStream_t);
+
+template <class T>
+hipError_t axpbyz(const T* x, const T* y, T* out, int64_t n, double a, double b, uint16_t* const* planes,
+                  int nplanes, hipStream_t s) {
+  Planes pl{{nullptr, nullptr, nullptr}};
+  for (int p = 0; p < nplanes; ++p) pl.p[p] = planes[p];
+  const int64_t Np = nplanes ? plane_np(n) : 0;
+  if (nplanes && !Np) return hipErrorInvalidValue;
+  bool ok = pair_ok(x, 0, n) && pair_ok(y, 0, n) && pair_ok(out, 0, n);
+  for (int p = 0; p < nplanes; ++p) ok = ok && pair_ok(pl.p[p], 0, n);
+  hipLaunchKernelGGL(k_axpbyz<T>, dim3(ew_grid(n)), dim3(kT), 0, s, x, y, out, n, a, b, pl, nplanes, Np,
+                     ok ? 1 : 0);
+  return hipGetLastError();
+}
+template hipError_t axpbyz<double>(const double*, const double*, double*, int64_t, double, double,
+                                   uint16_t* const*, int, hipStream_t);
+template hipError_t axpbyz<float>(const float*, const float*, float*, int64_t, double, double,
+                                  uint16_t* const*, int, hipStream_t);
 
 template <class Tin, class Tout>
 hipError_t convert(const Tin* in, int64_t si, Tout* out, int64_t so, int64_t n, int batch,
