@@ -438,6 +438,37 @@ void q8_touch(dmpt_ctx c, const Group& g, int z) {
       return;
     }
 }
+// Maxima sink of an element-wise writer of members z0 .. z0 + batch - 1 of g
+// (called after planes_of, which marks them stale): the writer leaves
+// `entries` partial maxima of |x| per member at the returned address (member
+// stride *stride), and the next slicing of these members reads them instead
+// of scanning.  Null when g has no int8 slices or the maxima do not fit.
+double* q8_sink(const Call& k, const Group& g, int z0, int batch, int64_t entries, int64_t* stride) {
+  if (k.rec || !engine_int8(k.eng)) return nullptr;
+  for (auto& r : k.c->q8reg)
+    if (r.m == (const char*)g.m) {
+      if (z0 < 0 || batch < 1 || z0 + batch > r.count || entries < 1 || entries > r.mx_cap ||
+          r.stride != k.stride)
+        return nullptr;
+      for (int i = z0; i < z0 + batch; ++i) r.mx_n[i] = (int)entries;
+      *stride = r.mx_cap;
+      return r.mx + (size_t)z0 * r.mx_cap;
+    }
+  return nullptr;
+}
+// The maxima sink of a grid-stride element-wise writer of member z of g: the
+// block count it must run with in *blocks (0 without a sink).
+double* ew_sink(const Call& k, const Group& g, int z, int64_t* stride, int64_t* blocks) {
+  *blocks = 0;
+  for (auto& r : k.c->q8reg)
+    if (r.m == (const char*)g.m) {
+      const int64_t e = ew_sink_blocks(k.nn, r.mx_cap);
+      double* mx = q8_sink(k, g, z, 1, e, stride);
+      if (mx) *blocks = e;
+      return mx;
+    }
+  return nullptr;
+}
 void* mptr(const Call& k, const Group& g, int z) {
   return (char*)g.m + (size_t)z * k.stride * k.c->esize;
 }
@@ -753,8 +784,10 @@ dmpt_status sym_inplace(const Call& k, const Group& g, int z0, int batch, double
   planes_of(k, g, z0, pl);
   T* m = (T*)mptr(k, g, z0);
   hipStream_t s = k.c->stream;
+  int64_t ms = 0;
+  double* mx = q8_sink(k, g, z0, batch, sym_pair_blocks(k.Np), &ms);
   EMIT(k, (sym_combine<T, T>(m, k.Np, k.stride, k.N, k.Np, a, nullptr, 0, m, k.Np, k.stride, pl, k.np, batch,
-                             s)));
+                             s, nullptr, 0.0, nullptr, mx, ms)));
   return DMPT_OK;
 }
 
@@ -768,8 +801,10 @@ dmpt_status sym_to(const Call& k, const Group& in, const Group& out, int batch, 
   T* dst = (T*)mptr(k, out, 0);
   const int npl = planes ? k.np : 0;
   hipStream_t s = k.c->stream;
+  int64_t ms = 0;
+  double* mx = q8_sink(k, out, 0, batch, sym_pair_blocks(k.Np), &ms);
   EMIT(k, (sym_combine<T, T>(src, k.Np, k.stride, k.N, k.Np, 1.0, nullptr, 0, dst, k.Np, k.stride, pl, npl,
-                             batch, s)));
+                             batch, s, nullptr, 0.0, nullptr, mx, ms)));
   return DMPT_OK;
 }
 
@@ -1020,12 +1055,14 @@ dmpt_status st_load(const Call& k, const Group& g, int z, int step, int j, doubl
   uint16_t* pl[3];
   planes_of(k, g, z, pl);
   T* dst = (T*)mptr(k, g, z);
+  int64_t ms = 0, mb = 0;
+  double* mx = ew_sink(k, g, z, &ms, &mb);
   if (a == 0.0) {
     HIPCHK(k.c, (convert<T, T>(st_ptr<T>(k, step, j), 0, dst, 0, k.nn, 1, pl, 0,
-                               g.pl[0] ? k.np : 0, k.c->stream)));
+                               g.pl[0] ? k.np : 0, k.c->stream, mx, ms, mb)));
   } else {
     HIPCHK(k.c, axpbyz<T>(st_ptr<T>(k, step, jb), st_ptr<T>(k, step, j), dst, k.nn, -a, 1.0, pl,
-                          g.pl[0] ? k.np : 0, k.c->stream));
+                          g.pl[0] ? k.np : 0, k.c->stream, mx, mb));
   }
   return DMPT_OK;
 }
@@ -1059,12 +1096,14 @@ dmpt_status ss_load(const Call& k, const Group& g, int z, int step, int j, doubl
   uint16_t* pl[3];
   planes_of(k, g, z, pl);
   T* dst = (T*)mptr(k, g, z);
+  int64_t ms = 0, mb = 0;
+  double* mx = ew_sink(k, g, z, &ms, &mb);
   if (a == 0.0) {
     HIPCHK(k.c, (convert<T, T>(ss_ptr<T>(k, step, j), 0, dst, 0, k.nn, 1, pl, 0, g.pl[0] ? k.np : 0,
-                               k.c->stream)));
+                               k.c->stream, mx, ms, mb)));
   } else {
     HIPCHK(k.c, axpbyz<T>(ss_ptr<T>(k, step, jb), ss_ptr<T>(k, step, j), dst, k.nn, -a, 1.0, pl,
-                          g.pl[0] ? k.np : 0, k.c->stream));
+                          g.pl[0] ? k.np : 0, k.c->stream, mx, mb));
   }
   return DMPT_OK;
 }
@@ -1283,8 +1322,10 @@ dmpt_status ns_inverse(const Call& k, int step) {
   }
   uint16_t* pz[3];
   planes_of(k, w->Zi, 0, pz);
+  int64_t ms = 0, mb = 0;
+  double* mx = ew_sink(k, w->Zi, 0, &ms, &mb);
   HIPCHK(c, scaled_plus_identity<T>((const T*)mptr(k, w->S0, 0), (T*)mptr(k, w->Zi, 0), k.N, k.Np, z0.a,
-                                    z0.b, pz, k.np, s));
+                                    z0.b, pz, k.np, s, mx, mb));
   return ns_iterate<T>(k, z0.iters);
 }
 
@@ -1425,8 +1466,10 @@ dmpt_status zs_load(const Call& k, int step) {
   if (!zs_fits(k, step)) return fail(k.c, DMPT_ERR_ARG, "internal: inverse-store index");
   uint16_t* pl[3];
   planes_of(k, k.w->Zi, 0, pl);
+  int64_t ms = 0, mb = 0;
+  double* mx = ew_sink(k, k.w->Zi, 0, &ms, &mb);
   HIPCHK(k.c, (convert<T, T>((const T*)k.c->zs + (size_t)step * k.nn, 0, (T*)mptr(k, k.w->Zi, 0), 0, k.nn,
-                             1, pl, 0, k.w->Zi.pl[0] ? k.np : 0, k.c->stream)));
+                             1, pl, 0, k.w->Zi.pl[0] ? k.np : 0, k.c->stream, mx, ms, mb)));
   k.c->zcur = 0;
   return DMPT_OK;
 }
@@ -1603,16 +1646,21 @@ dmpt_status recursion_step(const Call& k, int order, int d, int step) {
       m.C1 = mptr(k, w->Zi, zc); m.beta1 = -2.0;
       m.sym = true;
       STCHK(run_gemm(k, m));
-      G u;  // R[J] = D1_J M, then D1_J = R[J]
+      // D1_J = D1_J M: in place with int8 products (they read D1_J's slices,
+      // not its master), else through R[J]
+      const bool inplace = engine_int8(k.eng);
+      G u;
       u.X = op(k, w->D1, mr, false);
       u.Y = op(k, w->P, mr, false);
-      u.C = mptr(k, w->R, mr);
+      u.C = mptr(k, inplace ? w->D1 : w->R, mr);
       u.sym = true;
       STCHK(run_gemm(k, u));
-      uint16_t* pj[3];
-      planes_of(k, w->D1, mr, pj);
-      HIPCHK(c, (convert<T, T>((const T*)mptr(k, w->R, mr), 0, (T*)mptr(k, w->D1, mr), 0, k.nn, 1, pj, 0,
-                               w->D1.pl[0] ? k.np : 0, c->stream)));
+      if (!inplace) {
+        uint16_t* pj[3];
+        planes_of(k, w->D1, mr, pj);
+        HIPCHK(c, (convert<T, T>((const T*)mptr(k, w->R, mr), 0, (T*)mptr(k, w->D1, mr), 0, k.nn, 1, pj, 0,
+                                 w->D1.pl[0] ? k.np : 0, c->stream)));
+      }
     } else if (ns) {
       STCHK(ns_solve<T>(k, w->D1, md));
     } else {

@@ -149,11 +149,17 @@ hipError_t gemm_prepare();
 // in: Tin with leading dim ldi; out: Tout with leading dim ldo (+ split planes).
 // Batched over `batch` members with element strides.
 // The tile pair (i, j) / (j, i) is handled by one block, so in == out is allowed.
+// With mx (and no gate), member z also leaves sym_pair_blocks(span) partial
+// maxima of |out| at mx + z mstride (their max is the member's max |out|).
 template <class Tin, class Tout>
 hipError_t sym_combine(const Tin* in, int64_t ldi, int64_t si, int64_t N, int64_t Np, double a,
                        const double* dshift, int dstride, Tout* out, int64_t ldo, int64_t so,
                        uint16_t* const* planes, int nplanes, int batch, hipStream_t s,
-                       const Tin* in2 = nullptr, double a2 = 0.0, const int* gate = nullptr);
+                       const Tin* in2 = nullptr, double a2 = 0.0, const int* gate = nullptr,
+                       double* mx = nullptr, int64_t mstride = 0);
+// Blocks per member of sym_combine over span rows: one per 128 x 128 tile
+// pair on and above the diagonal (with mx, the maxima each member leaves).
+int64_t sym_pair_blocks(int64_t span);
 
 // out = in^T (Np x Np members, batched, with planes); in != out.
 template <class T>
@@ -237,17 +243,24 @@ hipError_t axpby(const T* x, int64_t sx, T* y, int64_t sy, int64_t n, int batch,
 // (one member, master) + planes of out
 template <class T>
 hipError_t axpbyz(const T* x, const T* y, T* out, int64_t n, double a, double b, uint16_t* const* planes,
-                  int nplanes, hipStream_t s);
+                  int nplanes, hipStream_t s, double* mx = nullptr, int64_t mblocks = 0);
+// With mx, axpbyz, convert and scaled_plus_identity run mblocks blocks per
+// member, and block b of member z leaves max |out| over its elements at
+// mx[z * mstride + b] (their max is the member's max |out|).  The block
+// count for n elements and at most cap maxima:
+int64_t ew_sink_blocks(int64_t n, int64_t cap);
 
 // out = (Tout) in for n elements per member (batched) + planes of out
 template <class Tin, class Tout>
 hipError_t convert(const Tin* in, int64_t si, Tout* out, int64_t so, int64_t n, int batch,
-                   uint16_t* const* planes, int64_t sp, int nplanes, hipStream_t s);
+                   uint16_t* const* planes, int64_t sp, int nplanes, hipStream_t s, double* mx = nullptr,
+                   int64_t mstride = 0, int64_t mblocks = 0);
 
 // Fill identity-plus-scaled matrix: out = a I + b x (Np x Np, zero padding kept)
 template <class T>
 hipError_t scaled_plus_identity(const T* x, T* out, int64_t N, int64_t Np, double a, double b,
-                                uint16_t* const* planes, int nplanes, hipStream_t s);
+                                uint16_t* const* planes, int nplanes, hipStream_t s, double* mx = nullptr,
+                                int64_t mblocks = 0);
 
 // p[0..n) = v and q[0..nq) = qv; either pointer may be null with count 0
 hipError_t set_values(int* p, int v, int n, double* q, double qv, int nq, hipStream_t s);

@@ -125,56 +125,77 @@ inline bool pair_ok(const T* p, int64_t stride, int64_t n) {
 }
 
 // ------------------------------------------------------------ symmetrise
-// One block owns the tile pair (bi, bj) and (bj, bi), bi <= bj: both input
-// tiles are staged in LDS before either output tile is written, so the
-// kernel may run in place.  Reads and writes stay row-contiguous.
+// Block t owns the 128 x 128 tile pair (BI, BJ) and (BJ, BI), BI <= BJ,
+// t = BJ (BJ + 1) / 2 + BI, and walks its 32 x 32 pairs (bi, bj), bi <= bj:
+// both input tiles of a pair are staged in LDS before either output tile is
+// written, so the kernel may run in place.  Reads and writes stay
+// row-contiguous.  With mx, the block leaves max |out| over its pair (an
+// infinite one for a non-finite value) at mx[z * mstride + t].
 template <class Tin, class Tout>
 __global__ __launch_bounds__(kT) void k_sym(const Tin* in, int64_t ldi, int64_t si, int64_t N,
                                             int64_t Np, double a, const double* dshift,
                                             int dstride, Tout* out, int64_t ldo, int64_t so,
                                             Planes pl, int np, int64_t out_rows, const Tin* in2,
-                                            double a2, const int* gate) {
+                                            double a2, const int* gate, int64_t nb, double* mx,
+                                            int64_t mstride) {
   __shared__ double ta[32][33], tb[32][33];
-  const int64_t bi = blockIdx.y, bj = blockIdx.x;
-  if (bi > bj) return;
   if (gate && !*gate) return;  // a converged system of a batch keeps its outputs
-  const int z = blockIdx.z;
+  const int64_t t = blockIdx.x;
+  int64_t BJ = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while (BJ > 0 && BJ * (BJ + 1) / 2 > t) --BJ;
+  while ((BJ + 1) * (BJ + 2) / 2 <= t) ++BJ;
+  const int64_t BI = t - BJ * (BJ + 1) / 2;
+  const int z = blockIdx.y;
   in += z * si;
   if (in2) in2 += z * si;
   out += z * so;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
-  // ta = a in(bi,bj) + a2 in2(bi,bj), tb likewise for (bj,bi)
-  for (int r = ty; r < 32; r += 8) {
-    int64_t gi = bi * 32 + r, gj = bj * 32 + tx;
-    bool ok = gi < N && gj < N;
-    ta[r][tx] = ok ? a * (double)in[gi * ldi + gj] + (in2 ? a2 * (double)in2[gi * ldi + gj] : 0.0)
-                   : 0.0;
-    gi = bj * 32 + r;
-    gj = bi * 32 + tx;
-    ok = gi < N && gj < N;
-    tb[r][tx] = ok ? a * (double)in[gi * ldi + gj] + (in2 ? a2 * (double)in2[gi * ldi + gj] : 0.0)
-                   : 0.0;
-  }
-  __syncthreads();
   const double ds = dshift ? dshift[z * dstride] : 0.0;
   uint16_t* p3[3] = {pl.p[0] ? pl.p[0] + z * so : nullptr, pl.p[1] ? pl.p[1] + z * so : nullptr,
                      pl.p[2] ? pl.p[2] + z * so : nullptr};
-  for (int pass = 0; pass < 2; ++pass) {
-    if (pass == 1 && bi == bj) break;
-    const int64_t ti = pass ? bj : bi, tj = pass ? bi : bj;
+  double m = 0.0;
+  bool bad = false;
+  for (int q = 0; q < 16; ++q) {
+    const int64_t bi = BI * 4 + (q >> 2), bj = BJ * 4 + (q & 3);
+    if (bi > bj || bj >= nb) continue;  // the same for every thread of the block
+    __syncthreads();                    // the previous pair is written: ta, tb are free
+    // ta = a in(bi,bj) + a2 in2(bi,bj), tb likewise for (bj,bi)
     for (int r = ty; r < 32; r += 8) {
-      const int64_t gi = ti * 32 + r, gj = tj * 32 + tx;
-      if (gi >= out_rows || gj >= out_rows) continue;
-      double v = 0.0;
-      if (gi < N && gj < N) {
-        // out(ti,tj)[r][tx] = ta(ti,tj)[r][tx] + ta(tj,ti)[tx][r] (scales already applied)
-        v = pass ? (tb[r][tx] + ta[tx][r]) : (ta[r][tx] + tb[tx][r]);
-        if (gi == gj) v += ds;
-      }
-      const Tout o = (Tout)v;
-      out[gi * ldo + gj] = o;
-      if (np) split_store((double)o, p3, np, plane_off(gi, gj, ldo));
+      int64_t gi = bi * 32 + r, gj = bj * 32 + tx;
+      bool ok = gi < N && gj < N;
+      ta[r][tx] = ok ? a * (double)in[gi * ldi + gj] + (in2 ? a2 * (double)in2[gi * ldi + gj] : 0.0)
+                     : 0.0;
+      gi = bj * 32 + r;
+      gj = bi * 32 + tx;
+      ok = gi < N && gj < N;
+      tb[r][tx] = ok ? a * (double)in[gi * ldi + gj] + (in2 ? a2 * (double)in2[gi * ldi + gj] : 0.0)
+                     : 0.0;
     }
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+      if (pass == 1 && bi == bj) break;
+      const int64_t ti = pass ? bj : bi, tj = pass ? bi : bj;
+      for (int r = ty; r < 32; r += 8) {
+        const int64_t gi = ti * 32 + r, gj = tj * 32 + tx;
+        if (gi >= out_rows || gj >= out_rows) continue;
+        double v = 0.0;
+        if (gi < N && gj < N) {
+          // out(ti,tj)[r][tx] = ta(ti,tj)[r][tx] + ta(tj,ti)[tx][r] (scales already applied)
+          v = pass ? (tb[r][tx] + ta[tx][r]) : (ta[r][tx] + tb[tx][r]);
+          if (gi == gj) v += ds;
+        }
+        const Tout o = (Tout)v;
+        out[gi * ldo + gj] = o;
+        if (np) split_store((double)o, p3, np, plane_off(gi, gj, ldo));
+        const double ao = fabs((double)o);
+        bad |= !(ao <= 1.0e308);
+        m = fmax(m, ao);
+      }
+    }
+  }
+  if (mx) {
+    const double bm = block_max(bad ? INFINITY : m);
+    if (threadIdx.x == 0) mx[z * mstride + t] = bm;
   }
 }
 
@@ -407,13 +428,16 @@ __global__ __launch_bounds__(kT) void k_axpby(const T* __restrict__ x, int64_t s
 }
 
 // out = a x + b y (one member), with planes of out: the same arithmetic as
-// k_axpby with y read from a third array
+// k_axpby with y read from a third array.  With mx, block b leaves max |out|
+// over its elements (infinite for a non-finite one) at mx[b].
 template <class T>
 __global__ __launch_bounds__(kT) void k_axpbyz(const T* __restrict__ x, const T* __restrict__ y,
                                                T* __restrict__ out, int64_t n, double a, double b, Planes pl,
-                                               int np, int64_t Np, int v2) {
+                                               int np, int64_t Np, int v2, double* __restrict__ mx) {
   uint16_t* p3[3] = {pl.p[0], pl.p[1], pl.p[2]};
   const T ta = (T)a, tb = (T)b;
+  double m = 0.0;
+  bool bad = false;
   if (v2) {
     for (int64_t c = (int64_t)blockIdx.x * kT + threadIdx.x; c < (n >> 1); c += (int64_t)gridDim.x * kT) {
       const int64_t i = c << 1;
@@ -424,26 +448,44 @@ __global__ __launch_bounds__(kT) void k_axpbyz(const T* __restrict__ x, const T*
       for (int e = 0; e < 2; ++e) yv[e] = ta * xv[e] + tb * yv[e];
       st2(out + i, yv);
       if (np) split_store2(yv, p3, np, plane_off_lin(i, Np));
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const double av = fabs((double)yv[e]);
+        bad |= !(av <= 1.0e308);
+        m = fmax(m, av);
+      }
     }
-    return;
+  } else {
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+      const T v = ta * x[i] + tb * y[i];
+      out[i] = v;
+      if (np) split_store((double)v, p3, np, plane_off_lin(i, Np));
+      const double av = fabs((double)v);
+      bad |= !(av <= 1.0e308);
+      m = fmax(m, av);
+    }
   }
-  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
-    const T v = ta * x[i] + tb * y[i];
-    out[i] = v;
-    if (np) split_store((double)v, p3, np, plane_off_lin(i, Np));
+  if (mx) {
+    const double bm = block_max(bad ? INFINITY : m);
+    if (threadIdx.x == 0) mx[blockIdx.x] = bm;
   }
 }
 
-// out = (Tout) in, batched, with planes of out
+// out = (Tout) in, batched, with planes of out.  With mx, block b of member z
+// leaves max |out| over its elements (infinite for a non-finite one) at
+// mx[z * mstride + b].
 template <class Tin, class Tout>
 __global__ __launch_bounds__(kT) void k_convert(const Tin* __restrict__ in, int64_t si,
                                                 Tout* __restrict__ out, int64_t so, int64_t n,
-                                                Planes pl, int64_t sp, int np, int64_t Np, int v2) {
+                                                Planes pl, int64_t sp, int np, int64_t Np, int v2,
+                                                double* __restrict__ mx, int64_t mstride) {
   const int z = blockIdx.y;
   in += z * si;
   out += z * so;
   uint16_t* p3[3] = {pl.p[0] ? pl.p[0] + z * sp : nullptr, pl.p[1] ? pl.p[1] + z * sp : nullptr,
                      pl.p[2] ? pl.p[2] + z * sp : nullptr};
+  double m = 0.0;
+  bool bad = false;
   if (v2) {
     for (int64_t c = (int64_t)blockIdx.x * kT + threadIdx.x; c < (n >> 1); c += (int64_t)gridDim.x * kT) {
       const int64_t i = c << 1;
@@ -454,20 +496,36 @@ __global__ __launch_bounds__(kT) void k_convert(const Tin* __restrict__ in, int6
       o2[1] = (Tout)a2[1];
       st2(out + i, o2);
       if (np) split_store2(o2, p3, np, plane_off_lin(i, Np));
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const double av = fabs((double)o2[e]);
+        bad |= !(av <= 1.0e308);
+        m = fmax(m, av);
+      }
     }
-    return;
+  } else {
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+      const Tout v = (Tout)in[i];
+      out[i] = v;
+      if (np) split_store((double)v, p3, np, plane_off_lin(i, Np));
+      const double av = fabs((double)v);
+      bad |= !(av <= 1.0e308);
+      m = fmax(m, av);
+    }
   }
-  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
-    const Tout v = (Tout)in[i];
-    out[i] = v;
-    if (np) split_store((double)v, p3, np, plane_off_lin(i, Np));
+  if (mx) {
+    const double bm = block_max(bad ? INFINITY : m);
+    if (threadIdx.x == 0) mx[z * mstride + blockIdx.x] = bm;
   }
 }
 
 template <class T>
 __global__ __launch_bounds__(kT) void k_spi(const T* __restrict__ x, T* __restrict__ out, int64_t N,
-                                            int64_t Np, double a, double b, Planes pl, int np) {
+                                            int64_t Np, double a, double b, Planes pl, int np,
+                                            double* __restrict__ mx) {
   const int64_t n = Np * Np;
+  double m = 0.0;
+  bool bad = false;
   for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
     const int64_t r = i / Np, c = i % Np;
     double v = (b != 0.0) ? b * (double)x[i] : 0.0;
@@ -475,6 +533,13 @@ __global__ __launch_bounds__(kT) void k_spi(const T* __restrict__ x, T* __restri
     const T o = (T)v;
     out[i] = o;
     if (np) split_store((double)o, pl.p, np, plane_off(r, c, Np));
+    const double ao = fabs((double)o);
+    bad |= !(ao <= 1.0e308);
+    m = fmax(m, ao);
+  }
+  if (mx) {  // block b: max |out| over its elements at mx[b]
+    const double bm = block_max(bad ? INFINITY : m);
+    if (threadIdx.x == 0) mx[blockIdx.x] = bm;
   }
 }
 
@@ -962,24 +1027,31 @@ template <class Tin, class Tout>
 hipError_t sym_combine(const Tin* in, int64_t ldi, int64_t si, int64_t N, int64_t Np, double a,
                        const double* dshift, int dstride, Tout* out, int64_t ldo, int64_t so,
                        uint16_t* const* planes, int nplanes, int batch, hipStream_t s,
-                       const Tin* in2, double a2, const int* gate) {
+                       const Tin* in2, double a2, const int* gate, double* mx, int64_t mstride) {
   Planes pl{{nullptr, nullptr, nullptr}};
   for (int p = 0; p < nplanes; ++p) pl.p[p] = planes[p];
   // planes exist only for workspace members: Np x Np with ld = Np
   if (nplanes && (ldo != Np || Np % 32 != 0)) return hipErrorInvalidValue;
   const int64_t rows = (ldo == N && ldo != Np) ? N : ldo;  // caller buffer: only N x N
   const int64_t span = rows > N ? rows : N;
-  const unsigned nb = (unsigned)((span + 31) / 32);
-  hipLaunchKernelGGL((k_sym<Tin, Tout>), dim3(nb, nb, batch), dim3(kT), 0, s, in, ldi, si, N, Np, a,
-                     dshift, dstride, out, ldo, so, pl, nplanes, rows, in2, a2, gate);
+  const int64_t nb = (span + 31) / 32;
+  const int64_t pairs = sym_pair_blocks(span);
+  if (mx && (mstride < pairs || gate)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_sym<Tin, Tout>), dim3((unsigned)pairs, batch), dim3(kT), 0, s, in, ldi, si, N, Np, a,
+                     dshift, dstride, out, ldo, so, pl, nplanes, rows, in2, a2, gate, nb, mx, mstride);
   return hipGetLastError();
+}
+
+int64_t sym_pair_blocks(int64_t span) {
+  const int64_t nb128 = (span + 127) / 128;
+  return nb128 * (nb128 + 1) / 2;
 }
 
 #define DMPT_SYM_INST(TI, TO)                                                                   \
   template hipError_t sym_combine<TI, TO>(const TI*, int64_t, int64_t, int64_t, int64_t, double,  \
                                           const double*, int, TO*, int64_t, int64_t,             \
                                           uint16_t* const*, int, int, hipStream_t, const TI*,    \
-                                          double, const int*);
+                                          double, const int*, double*, int64_t);
 DMPT_SYM_INST(double, double)
 DMPT_SYM_INST(double, float)
 DMPT_SYM_INST(float, float)
@@ -1150,38 +1222,48 @@ template hipError_t axpby<float>(const float*, int64_t, float*, int64_t, int64_t
 
 template <class T>
 hipError_t axpbyz(const T* x, const T* y, T* out, int64_t n, double a, double b, uint16_t* const* planes,
-                  int nplanes, hipStream_t s) {
+                  int nplanes, hipStream_t s, double* mx, int64_t mblocks) {
   Planes pl{{nullptr, nullptr, nullptr}};
   for (int p = 0; p < nplanes; ++p) pl.p[p] = planes[p];
   const int64_t Np = nplanes ? plane_np(n) : 0;
   if (nplanes && !Np) return hipErrorInvalidValue;
+  if (mx && (mblocks < 1 || mblocks > 65535)) return hipErrorInvalidValue;
   bool ok = pair_ok(x, 0, n) && pair_ok(y, 0, n) && pair_ok(out, 0, n);
   for (int p = 0; p < nplanes; ++p) ok = ok && pair_ok(pl.p[p], 0, n);
-  hipLaunchKernelGGL(k_axpbyz<T>, dim3(ew_grid(n)), dim3(kT), 0, s, x, y, out, n, a, b, pl, nplanes, Np,
-                     ok ? 1 : 0);
+  const unsigned g = mx ? (unsigned)mblocks : ew_grid(n);
+  hipLaunchKernelGGL(k_axpbyz<T>, dim3(g), dim3(kT), 0, s, x, y, out, n, a, b, pl, nplanes, Np, ok ? 1 : 0, mx);
   return hipGetLastError();
 }
 template hipError_t axpbyz<double>(const double*, const double*, double*, int64_t, double, double,
-                                   uint16_t* const*, int, hipStream_t);
+                                   uint16_t* const*, int, hipStream_t, double*, int64_t);
 template hipError_t axpbyz<float>(const float*, const float*, float*, int64_t, double, double,
-                                  uint16_t* const*, int, hipStream_t);
+                                  uint16_t* const*, int, hipStream_t, double*, int64_t);
+
+int64_t ew_sink_blocks(int64_t n, int64_t cap) {
+  const int64_t g = (int64_t)ew_grid(n);
+  return g < cap ? g : cap;
+}
 
 template <class Tin, class Tout>
 hipError_t convert(const Tin* in, int64_t si, Tout* out, int64_t so, int64_t n, int batch,
-                   uint16_t* const* planes, int64_t sp, int nplanes, hipStream_t s) {
+                   uint16_t* const* planes, int64_t sp, int nplanes, hipStream_t s, double* mx,
+                   int64_t mstride, int64_t mblocks) {
   Planes pl{{nullptr, nullptr, nullptr}};
   for (int p = 0; p < nplanes; ++p) pl.p[p] = planes[p];
   const int64_t Np = nplanes ? plane_np(n) : 0;
   if (nplanes && !Np) return hipErrorInvalidValue;
+  if (mx && (mblocks < 1 || mblocks > 65535 || (batch > 1 && mstride < mblocks))) return hipErrorInvalidValue;
   bool ok = pair_ok(in, si, n) && pair_ok(out, so, n);
   for (int p = 0; p < nplanes; ++p) ok = ok && pair_ok(pl.p[p], sp, n);
-  hipLaunchKernelGGL((k_convert<Tin, Tout>), dim3(ew_grid(n), batch), dim3(kT), 0, s, in, si, out, so,
-                     n, pl, sp, nplanes, Np, ok ? 1 : 0);
+  const unsigned g = mx ? (unsigned)mblocks : ew_grid(n);
+  hipLaunchKernelGGL((k_convert<Tin, Tout>), dim3(g, batch), dim3(kT), 0, s, in, si, out, so, n, pl, sp,
+                     nplanes, Np, ok ? 1 : 0, mx, mstride);
   return hipGetLastError();
 }
 #define DMPT_CONV_INST(TI, TO)                                                                \
   template hipError_t convert<TI, TO>(const TI*, int64_t, TO*, int64_t, int64_t, int,         \
-                                      uint16_t* const*, int64_t, int, hipStream_t);
+                                      uint16_t* const*, int64_t, int, hipStream_t, double*,   \
+                                      int64_t, int64_t);
 DMPT_CONV_INST(double, float)
 DMPT_CONV_INST(float, double)
 DMPT_CONV_INST(float, float)
@@ -1190,17 +1272,21 @@ DMPT_CONV_INST(double, double)
 
 template <class T>
 hipError_t scaled_plus_identity(const T* x, T* out, int64_t N, int64_t Np, double a, double b,
-                                uint16_t* const* planes, int nplanes, hipStream_t s) {
+                                uint16_t* const* planes, int nplanes, hipStream_t s, double* mx,
+                                int64_t mblocks) {
   Planes pl{{nullptr, nullptr, nullptr}};
   for (int p = 0; p < nplanes; ++p) pl.p[p] = planes[p];
-  hipLaunchKernelGGL(k_spi<T>, dim3(ew_grid(Np * Np)), dim3(kT), 0, s, x, out, N, Np, a, b, pl,
-                     nplanes);
+  if (mx && (mblocks < 1 || mblocks > 65535)) return hipErrorInvalidValue;
+  const unsigned g = mx ? (unsigned)mblocks : ew_grid(Np * Np);
+  hipLaunchKernelGGL(k_spi<T>, dim3(g), dim3(kT), 0, s, x, out, N, Np, a, b, pl, nplanes, mx);
   return hipGetLastError();
 }
 template hipError_t scaled_plus_identity<double>(const double*, double*, int64_t, int64_t, double,
-                                                 double, uint16_t* const*, int, hipStream_t);
+                                                 double, uint16_t* const*, int, hipStream_t, double*,
+                                                 int64_t);
 template hipError_t scaled_plus_identity<float>(const float*, float*, int64_t, int64_t, double,
-                                                double, uint16_t* const*, int, hipStream_t);
+                                                double, uint16_t* const*, int, hipStream_t, double*,
+                                                int64_t);
 
 hipError_t set_values(int* p, int v, int n, double* q, double qv, int nq, hipStream_t s) {
   const int m = n > nq ? n : nq;
