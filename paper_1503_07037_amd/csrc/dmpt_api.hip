@@ -1491,7 +1491,9 @@ dmpt_status recursion_step(const Call& k, int order, int d, int step) {
   } else {
     STCHK(square0<T>(k));
   }
-  if (k.chain & kSaveS) STCHK(ss_save<T>(k, w->S0, 0, step, 0));
+  // the pass that loads these chains then does not read S0 either
+  const bool s0_unread_later = ns && (k.chain & kSave01) && (k.chain & kSaveZ) && !ns_refines(k);
+  if ((k.chain & kSaveS) && !s0_unread_later) STCHK(ss_save<T>(k, w->S0, 0, step, 0));
   // the identity direction of an order-1 pass solved with the shared inverse:
   // with S1_J = 2 D0 D1_J, Y0 = 2 D0 Z and 4 S0 Z = I - Z, the order-1 step
   // (2 D1_J - 4 Y0 S1_J) Z is D1_J (4 Z^2 - 2 Z), two symmetric products

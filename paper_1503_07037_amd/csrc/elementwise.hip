@@ -127,9 +127,10 @@ inline bool pair_ok(const T* p, int64_t stride, int64_t n) {
 // ------------------------------------------------------------ symmetrise
 // Block t owns the 128 x 128 tile pair (BI, BJ) and (BJ, BI), BI <= BJ,
 // t = BJ (BJ + 1) / 2 + BI, and walks its 32 x 32 pairs (bi, bj), bi <= bj:
-// both input tiles of a pair are staged in LDS before either output tile is
-// written, so the kernel may run in place.  Reads and writes stay
-// row-contiguous.  With mx, the block leaves max |out| over its pair (an
+// both input tiles of a pair are read before either output tile is written,
+// and the pairs are disjoint (reading the next pair while writing this one
+// touches other elements), so the kernel may run in place.  Reads and writes
+// stay row-contiguous.  With mx, the block leaves max |out| over its pair (an
 // infinite one for a non-finite value) at mx[z * mstride + t].
 template <class Tin, class Tout>
 __global__ __launch_bounds__(kT) void k_sym(const Tin* in, int64_t ldi, int64_t si, int64_t N,
@@ -153,25 +154,49 @@ __global__ __launch_bounds__(kT) void k_sym(const Tin* in, int64_t ldi, int64_t 
   const double ds = dshift ? dshift[z * dstride] : 0.0;
   uint16_t* p3[3] = {pl.p[0] ? pl.p[0] + z * so : nullptr, pl.p[1] ? pl.p[1] + z * so : nullptr,
                      pl.p[2] ? pl.p[2] + z * so : nullptr};
-  double m = 0.0;
-  bool bad = false;
-  for (int q = 0; q < 16; ++q) {
+  // the block's pairs (bi, bj) = (4 BI + q / 4, 4 BJ + q % 4), bi <= bj, in
+  // order of q; the next pair's inputs are loaded into registers while the
+  // current pair is written
+  auto valid = [&](int q) {
     const int64_t bi = BI * 4 + (q >> 2), bj = BJ * 4 + (q & 3);
-    if (bi > bj || bj >= nb) continue;  // the same for every thread of the block
-    __syncthreads();                    // the previous pair is written: ta, tb are free
-    // ta = a in(bi,bj) + a2 in2(bi,bj), tb likewise for (bj,bi)
-    for (int r = ty; r < 32; r += 8) {
+    return bi <= bj && bj < nb;
+  };
+  auto next = [&](int q) {
+    do ++q;
+    while (q < 16 && !valid(q));
+    return q;
+  };
+  auto load = [&](int q, double (&ra)[4], double (&rb)[4]) {
+    const int64_t bi = BI * 4 + (q >> 2), bj = BJ * 4 + (q & 3);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = ty + 8 * u;
+      // ra = a in(bi,bj) + a2 in2(bi,bj), rb likewise for (bj,bi)
       int64_t gi = bi * 32 + r, gj = bj * 32 + tx;
       bool ok = gi < N && gj < N;
-      ta[r][tx] = ok ? a * (double)in[gi * ldi + gj] + (in2 ? a2 * (double)in2[gi * ldi + gj] : 0.0)
-                     : 0.0;
+      ra[u] = ok ? a * (double)in[gi * ldi + gj] + (in2 ? a2 * (double)in2[gi * ldi + gj] : 0.0) : 0.0;
       gi = bj * 32 + r;
       gj = bi * 32 + tx;
       ok = gi < N && gj < N;
-      tb[r][tx] = ok ? a * (double)in[gi * ldi + gj] + (in2 ? a2 * (double)in2[gi * ldi + gj] : 0.0)
-                     : 0.0;
+      rb[u] = ok ? a * (double)in[gi * ldi + gj] + (in2 ? a2 * (double)in2[gi * ldi + gj] : 0.0) : 0.0;
+    }
+  };
+  double m = 0.0;
+  bool bad = false;
+  double ra[4], rb[4];
+  int q = valid(0) ? 0 : next(0);
+  if (q < 16) load(q, ra, rb);
+  while (q < 16) {  // the same pairs for every thread of the block
+    const int qn = next(q);
+    const int64_t bi = BI * 4 + (q >> 2), bj = BJ * 4 + (q & 3);
+    __syncthreads();  // the previous pair is written: ta, tb are free
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      ta[ty + 8 * u][tx] = ra[u];
+      tb[ty + 8 * u][tx] = rb[u];
     }
     __syncthreads();
+    if (qn < 16) load(qn, ra, rb);
     for (int pass = 0; pass < 2; ++pass) {
       if (pass == 1 && bi == bj) break;
       const int64_t ti = pass ? bj : bi, tj = pass ? bi : bj;
@@ -192,6 +217,7 @@ __global__ __launch_bounds__(kT) void k_sym(const Tin* in, int64_t ldi, int64_t 
         m = fmax(m, ao);
       }
     }
+    q = qn;
   }
   if (mx) {
     const double bm = block_max(bad ? INFINITY : m);
