@@ -105,6 +105,9 @@ struct dmpt_ctx_s {
   bool q8 = false;               // operand groups carry int8 slices (I8S4, I8S3)
   std::vector<Q8Reg> q8reg;
   double* d_qpart = nullptr;     // block maxima of the slicing launches
+  double* d_dpart = nullptr;     // partial diagonal tiles of split symmetric int8 products
+  int dpart_members = 0;
+  int diag_split = 4;            // parts per diagonal tile (DMPT_DIAG_SPLIT; 0: no split)
   std::vector<void*> allocs;
   // matrix groups and solver scalars of the single-system entry points
   WS ws;
@@ -652,6 +655,11 @@ dmpt_status run_gemm(const Call& k, const G& g) {
   a.acc64 = acc64_of(k.c, k.eng);
   // recorded launches (graph replays, grouped launches) keep every tile
   a.sym = g.sym && !k.rec && !g.W && !k.c->full_tiles ? 1 : 0;
+  if (a.sym && engine_int8(k.eng) && k.c->d_dpart) {
+    a.dpart = k.c->d_dpart;
+    a.dsplit = k.c->diag_split;
+    a.dpart_members = k.c->dpart_members;
+  }
   if (engine_int8(k.eng)) {
     if (k.Np > kQ8MaxK) return fail(k.c, DMPT_ERR_UNSUPPORTED, "int8 products need N <= 32768");
     STCHK(q8_operand(k, a.X, g.batch));
@@ -668,7 +676,7 @@ dmpt_status run_gemm(const Call& k, const G& g) {
           r.dirty[i] = 1;
           r.mx_n[i] = 0;
         }
-        const int64_t tiles = gemm_launch_tiles(a);
+        const int64_t tiles = gemm_cmax_entries(a);
         if (!k.rec && !g.active && (size_t)(p - r.m) % mb == 0 && (g.batch == 1 || a.sC == r.stride) &&
             z0 + g.batch <= r.count && tiles <= r.mx_cap) {
           a.cmax = r.mx + (size_t)z0 * r.mx_cap;
@@ -3168,6 +3176,7 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
   if (const char* e = std::getenv("DMPT_NS_ITERS")) c->ns_iters_env = std::atoi(e);
   if (const char* e = std::getenv("DMPT_NS_REFINE")) c->ns_refine_env = std::atoi(e);
   c->full_tiles = std::getenv("DMPT_FULL_TILES") != nullptr;
+  if (const char* e = std::getenv("DMPT_DIAG_SPLIT")) c->diag_split = std::max(0, std::min(8, std::atoi(e)));
   c->ns_cold = std::getenv("DMPT_NS_COLD") != nullptr;
 
 
@@ -3198,7 +3207,9 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
     if (planes && c->q8 && count > 0) {
       g.q8 = (int8_t*)alloc(nn * kQ8Slices * count);
       g.qs = (double*)alloc(sizeof(double) * count);
-      const int64_t cap = (c->np_max / 128) * (c->np_max / 128);
+      // room for one maximum per product tile, and for the blocks of the
+      // element-wise writers (up to 16384 per member keeps them streaming)
+      const int64_t cap = std::max<int64_t>((c->np_max / 128) * (c->np_max / 128), 16384);
       double* mx = (double*)alloc(sizeof(double) * (size_t)cap * count);
       if (!g.q8 || !g.qs || !mx) return false;
       Q8Reg r;
@@ -3248,6 +3259,12 @@ dmpt_status dmpt_init(dmpt_ctx* out, int device, int64_t n_max, int dirs_max, co
   if (c->q8) {
     c->d_qpart = (double*)alloc(sizeof(double) * (size_t)q8_blocks(c->np_max) * kQ8Chunk);
     if (!c->d_qpart) return bail(DMPT_ERR_NOMEM, "device scalar allocation failed");
+    if (c->diag_split >= 2) {
+      // the largest symmetric product batch: the order-2 square terms of every direction
+      c->dpart_members = dm;
+      c->d_dpart = (double*)alloc(sizeof(double) * (size_t)(c->np_max / 128) * c->diag_split * 128 * 128 * dm);
+      if (!c->d_dpart) return bail(DMPT_ERR_NOMEM, "device workspace allocation failed");
+    }
   }
   c->d_gersh = (double*)alloc(sizeof(double) * (2 + 2 * (size_t)n_max));
   if (dirs_max > 0) {

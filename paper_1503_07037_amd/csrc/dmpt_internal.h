@@ -117,6 +117,13 @@ struct GemmArgs {
   int sym;                     // C is symmetric: only the tiles on and below the diagonal are
                                // computed (when the tile count per side is even and W is unset),
                                // then the upper triangle is mirrored from the lower one
+  // int8 kernels with sym, optional: each diagonal tile is computed as dsplit
+  // blocks over consecutive ranges of the inner index that leave their FP64
+  // partial tiles in dpart (room for dpart_members members), then summed in a
+  // fixed order by a second kernel; the off-diagonal tiles keep one block each
+  double* dpart;
+  int dsplit;
+  int dpart_members;
   // optional executed-work tally (graph replays, where the host cannot see
   // which members are skipped): every member that runs adds tally_m and
   // tally_u to tally[0] and tally[1]
@@ -133,6 +140,8 @@ int gemm_tile_edge(Engine eng, int64_t Np, int variant, int acc64);
 int gemm_tiles(Engine eng, int64_t Np, int variant, int acc64);
 // Output tiles per member that gemm() computes (fewer than gemm_tiles with sym).
 int gemm_launch_tiles(const GemmArgs& a);
+// Tile maxima per member that an int8 product with cmax leaves.
+int gemm_cmax_entries(const GemmArgs& a);
 hipError_t gemm(const GemmArgs& a, hipStream_t s);
 // One grouped launch over nprob products of the same engine, variant and tile
 // edge (list, start: device arrays; problem p owns the blocks start[p] ..

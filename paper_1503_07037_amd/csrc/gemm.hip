@@ -50,6 +50,7 @@ constexpr int BM = 128, BN = 128;
 constexpr int kWaves256 = 8;  // waves of the 256 x 256 split-BF16 kernel (two per SIMD)
 constexpr int kGroupM = 8;   // tile rows per raster group
 constexpr int kXcd = 8;      // XCDs of an MI355X
+constexpr int kDiagParts = 4;  // row parts per diagonal tile in the summing kernel of split products
 
 // Tile coordinates of a (possibly remapped) linear block index.
 __device__ inline void raster(int b, int tiles_m, int tiles_n, int& tm, int& tn) {
@@ -717,8 +718,44 @@ __device__ __forceinline__ void gemm_i8_tile(const GemmArgs& a, int z, int bx, i
   count_member(a, bx);
   const int64_t Np = a.Np;
   const int64_t kbr = Np >> 5;  // 32-wide blocks per block row
-  int tm, tn;
-  tile_coords(bx, (int)(Np / TM), (int)(Np / TM), tm, tn, a.sym);
+  const int T = (int)(Np / TM);
+  int nk = (int)(Np / BK);
+  int tm, tn, split = -1, kfirst = 0, cslot = bx;
+  if (a.sym == 2) {
+    // the T dsplit blocks of the diagonal tiles first (diagonal tile tm,
+    // k stages [split nk / dsplit, (split + 1) nk / dsplit)), then the strictly
+    // lower triangle folded into (T / 2) x (T - 1); the maxima of the
+    // diagonal tiles come from the summing kernel (kDiagParts per tile, slots
+    // 0 .. T kDiagParts - 1)
+    const int nd = T * a.dsplit;
+    if (bx < nd) {
+      tm = tn = bx / a.dsplit;
+      split = bx % a.dsplit;
+      kfirst = split * nk / a.dsplit;
+      nk = (split + 1) * nk / a.dsplit - kfirst;
+    } else {
+      int p, q;
+      raster(bx - nd, T / 2, T - 1, p, q);
+      if (q < p) {
+        tm = p;
+        tn = q;
+      } else {
+        tm = T - 1 - p;
+        tn = q - p;
+      }
+      cslot = T * kDiagParts + (bx - nd);
+    }
+  } else {
+    tile_coords(bx, T, T, tm, tn, a.sym);
+  }
+  // all of these are the same for the whole block: keep them in scalar
+  // registers (the vector registers hold the accumulators)
+  tm = __builtin_amdgcn_readfirstlane(tm);
+  tn = __builtin_amdgcn_readfirstlane(tn);
+  split = __builtin_amdgcn_readfirstlane(split);
+  kfirst = __builtin_amdgcn_readfirstlane(kfirst);
+  nk = __builtin_amdgcn_readfirstlane(nk);
+  cslot = __builtin_amdgcn_readfirstlane(cslot);
   // the wave index is uniform: block addresses live in scalar registers
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / WN, wn = wave % WN;
@@ -734,7 +771,7 @@ __device__ __forceinline__ void gemm_i8_tile(const GemmArgs& a, int z, int bx, i
     const int op = q / (S * NBLK), sl = (q / NBLK) % S, b = q % NBLK;
     const int rb = b / KB, kb = b % KB;
     const int64_t brow = (int64_t)(op ? tn : tm) * RB + rb;
-    src[j] = (op ? yq : xq) + (((brow * kbr + kb) * kQ8Slices + sl) << 10) + lane * 16;
+    src[j] = (op ? yq : xq) + (((brow * kbr + (int64_t)kfirst * KB + kb) * kQ8Slices + sl) << 10) + lane * 16;
     dst[j] = q * 1024 + lane * 16;
   }
   u4v stg[LOADS];
@@ -756,7 +793,6 @@ __device__ __forceinline__ void gemm_i8_tile(const GemmArgs& a, int z, int bx, i
       for (int j = 0; j < FN; ++j)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[w][i][j][r] = 0;
-  const int nk = (int)(Np / BK);
   gload(0);
   swrite(0);
   if (nk > 1) gload(1);
@@ -800,6 +836,20 @@ __device__ __forceinline__ void gemm_i8_tile(const GemmArgs& a, int z, int bx, i
     __syncthreads();
   }
   const double rb = 1.0 / kQ8Base;
+  // the epilogue's view of the arguments: a partial diagonal tile goes as it
+  // is (alpha = 1, nothing added, no maxima) to rows 0 .. 127 of the strip
+  // [member][split] of 128 x Np values in dpart, at its own columns
+  GemmArgs e = a;
+  if (split >= 0) {
+    e.C = (void*)((uintptr_t)a.dpart + (uintptr_t)(((int64_t)split - (int64_t)tm) * TM * Np * (int64_t)sizeof(double)));
+    e.sC = (int64_t)a.dsplit * TM * Np;
+    e.alpha = 1.0;
+    e.C1 = nullptr;
+    e.C2 = nullptr;
+    e.W = nullptr;
+    e.cmax = nullptr;
+    e.Cpl[0] = e.Cpl[1] = e.Cpl[2] = nullptr;
+  }
   double dsum = 0.0;
   // largest |C| of the tile, rounded up to FP32: an upper bound, so the
   // digits of the slicing still fit (their scale is at most 2^-24 larger than
@@ -818,17 +868,17 @@ __device__ __forceinline__ void gemm_i8_tile(const GemmArgs& a, int z, int bx, i
 #pragma unroll
         for (int w = W - 2; w >= 0; --w) v = v * rb + (double)acc[w][i][j][r];
         {
-          const double o = epi<double>(a, z, row, col, v * scale, dsum);
+          const double o = epi<double>(e, z, row, col, v * scale, dsum);
           fmx = o == o ? fmaxf(fmx, __double2float_ru(fabs(o))) : INFINITY;
         }
       }
-  if (a.W) {
+  if (e.W) {
     const double s = block_sum(dsum, red);
     if (tid == 0) a.partials[(int64_t)z * nbx + bx] = s;
   }
-  if (a.cmax) {
+  if (e.cmax) {
     const double m = block_max((double)fmx, red);
-    if (tid == 0) a.cmax[(int64_t)z * a.cmax_stride + bx] = m;
+    if (tid == 0) a.cmax[(int64_t)z * a.cmax_stride + cslot] = m;
   }
 }
 
@@ -1148,6 +1198,22 @@ int gemm_launch_tiles(const GemmArgs& a) {
   return T * T;
 }
 
+// Whether gemm() computes the diagonal tiles of a symmetric product in parts:
+// int8 register-staged kernels with at least 8 tile rows (more, shorter
+// blocks fill the last round of the launch).
+static bool diag_split(const GemmArgs& a) {
+  const int T = (int)(a.Np / 128);
+  return (a.eng == Engine::I8S4 || a.eng == Engine::I8S3) && a.variant <= 1 && a.dpart && a.dsplit >= 2 &&
+         a.dsplit <= 8 && a.batch <= a.dpart_members && T >= 8 && a.Np / 32 >= a.dsplit &&
+         gemm_launch_tiles(a) < T * T;
+}
+
+int gemm_cmax_entries(const GemmArgs& a) {
+  if (!diag_split(a)) return gemm_launch_tiles(a);
+  const int T = (int)(a.Np / 128);
+  return T * kDiagParts + T * (T - 1) / 2;
+}
+
 namespace {
 
 struct Planes3 {
@@ -1182,6 +1248,51 @@ __global__ __launch_bounds__(256) void k_mirror(double* __restrict__ C, int64_t 
   }
 }
 
+// The diagonal tiles of a split symmetric int8 product: block (d, part, z)
+// sums the dsplit partial tiles of rows 32 part .. 32 part + 31 of diagonal
+// tile d in order, applies the epilogue of the product kernels and leaves
+// their max |C| in slot d kDiagParts + part.
+__global__ __launch_bounds__(256) void k_diag_sum(GemmArgs a) {
+  constexpr int TM = 128, RP = TM / kDiagParts, PER = RP * TM / 256;
+  const int z = blockIdx.z, d = blockIdx.x, part = blockIdx.y;
+  if (a.active && !a.active[z]) return;
+  __shared__ double red[4];
+  // partial s of member z: rows 0 .. 127 of the strip (z, s) of 128 x Np
+  // values, diagonal tile d at columns 128 d ..
+  const int64_t strip = (int64_t)TM * a.Np;
+  const double* dp = a.dpart + (int64_t)z * a.dsplit * strip + (int64_t)d * TM;
+  double dsum = 0.0, m = 0.0;
+  bool bad = false;
+  double v[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    const int64_t lr = part * RP + e / TM, lc = e % TM;
+    v[u] = dp[lr * a.Np + lc];
+  }
+  for (int sp = 1; sp < a.dsplit; ++sp)
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      const int64_t lr = part * RP + e / TM, lc = e % TM;
+      v[u] += dp[sp * strip + lr * a.Np + lc];
+    }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    const int64_t row = (int64_t)d * TM + part * RP + e / TM, col = (int64_t)d * TM + e % TM;
+    const double o = epi<double>(a, z, row, col, v[u], dsum);
+    const double ao = fabs(o);
+    bad |= !(ao <= 1.0e308);
+    m = fmax(m, ao);
+  }
+  if (a.cmax) {
+    // an FP32 value rounded up, as the product kernels leave it
+    const double bm = block_max(bad ? (double)INFINITY : (double)__double2float_ru(m), red);
+    if (threadIdx.x == 0) a.cmax[(int64_t)z * a.cmax_stride + d * kDiagParts + part] = bm;
+  }
+}
+
 }  // namespace
 
 hipError_t gemm_launch(const GemmArgs& a, int tiles, hipStream_t s);
@@ -1192,10 +1303,20 @@ hipError_t gemm(const GemmArgs& a0, hipStream_t s) {
     return hipErrorInvalidValue;
   GemmArgs a = a0;
   const int full = gemm_tiles(a.eng, a.Np, a.variant, a.acc64);
-  const int tiles = gemm_launch_tiles(a);
+  int tiles = gemm_launch_tiles(a);
   a.sym = tiles < full ? 1 : 0;
+  const int T = (int)(a.Np / 128);
+  if (a.sym && diag_split(a)) {
+    a.sym = 2;
+    tiles = T * a.dsplit + T * (T - 1) / 2;
+  }
   hipError_t e = gemm_launch(a, tiles, s);
   if (e != hipSuccess || !a.sym) return e;
+  if (a.sym == 2) {
+    hipLaunchKernelGGL(k_diag_sum, dim3((unsigned)T, kDiagParts, (unsigned)a.batch), dim3(256), 0, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   Planes3 pl{{a.Cpl[0], a.Cpl[1], a.Cpl[2]}};
   const int np = a.Cpl[2] ? 3 : (a.Cpl[1] ? 2 : (a.Cpl[0] ? 1 : 0));
   const int64_t nb = a.Np / 32;

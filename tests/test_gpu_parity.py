@@ -455,6 +455,45 @@ def test_symmetric_products_match_full_tiles(dm, prec, solver, tol, monkeypatch)
             assert fa == fb
 
 
+@pytest.mark.parametrize("prec,refine", [("int8x13", 0), ("int8x6", 2)])
+def test_split_diagonal_tiles_match_whole_tiles(dm, prec, refine, monkeypatch):
+    """Symmetric int8 products with at least eight 128-wide tile rows compute each diagonal tile as
+    four blocks over quarters of the inner index plus a summing kernel (DMPT_DIAG_SPLIT=0: one
+    block per diagonal tile).  The int32 sums of a quarter are exact, so only the FP64 addition of
+    the four partial tiles rounds differently: N = 1000 (8 tile rows) and N = 2000 (16), orders 0-2,
+    agree far below the engine's own error, and against the oracle."""
+    rng = np.random.default_rng(8)
+    for N in (1000, 2000):
+        print(f"case split diagonal {prec} N={N}", flush=True)
+        h0 = workloads.banded(N, 13, bandwidth=24, decay=8.0)
+        h1 = [np.diag(np.linspace(-1.0, 1.0, N)), _sym(rng, N, 0.05)]
+        out = []
+        for split in (True, False):
+            if split:
+                monkeypatch.delenv("DMPT_DIAG_SPLIT", raising=False)
+            else:
+                monkeypatch.setenv("DMPT_DIAG_SPLIT", "0")
+            with dm.Context(N, dirs_max=2, prec=prec, refine=refine, solver="hybrid") as ctx:
+                P0, P1, P2, mu, st = ctx.mu_newton(T(h0), [T(h) for h in h1], None, beta=12.0,
+                                                   Ne=N / 2.0, n=22, order=2)
+            out.append((P0.cpu().numpy(), [p.cpu().numpy() for p in P1], [p.cpu().numpy() for p in P2]))
+        monkeypatch.delenv("DMPT_DIAG_SPLIT", raising=False)
+        (a0, a1, a2), (b0, b1, b2) = out
+        d0 = np.abs(a0 - b0).max()
+        d1 = max(np.abs(x - y).max() / np.abs(y).max() for x, y in zip(a1, b1))
+        d2 = max(np.abs(x - y).max() / np.abs(y).max() for x, y in zip(a2, b2))
+        print(f"  split vs whole: {d0:.2e} {d1:.2e} {d2:.2e}", flush=True)
+        assert d0 < 1e-9 and d1 < 1e-9 and d2 < 1e-9
+        assert np.abs(a0 - a0.T).max() == 0.0
+        if N == 1000:
+            ref = oracle.canonical_response(h0, h1, None, 12.0, N / 2.0, 22, order=2)
+            e0 = np.abs(a0 - ref["P0"]).max()
+            e1 = max(np.abs(x - y).max() / np.abs(y).max() for x, y in zip(a1, ref["P1"]))
+            e2 = max(np.abs(x - y).max() / np.abs(y).max() for x, y in zip(a2, ref["P2"]))
+            print(f"  against the oracle: {e0:.2e} {e1:.2e} {e2:.2e}", flush=True)
+            assert e0 < 1e-6 and e1 < 1e-6 and e2 < 1e-6
+
+
 def test_newton_schulz_third_order_ragged(dm):
     print("case newton-schulz order 3 ragged", flush=True)
     N, n, beta, Ne = 200, 20, 10.0, 97.0
