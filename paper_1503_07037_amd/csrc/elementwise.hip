@@ -125,8 +125,9 @@ inline bool pair_ok(const T* p, int64_t stride, int64_t n) {
 }
 
 // ------------------------------------------------------------ symmetrise
-// Block t owns the 128 x 128 tile pair (BI, BJ) and (BJ, BI), BI <= BJ,
-// t = BJ (BJ + 1) / 2 + BI, and walks its 32 x 32 pairs (bi, bj), bi <= bj:
+// Block t owns the 32 g x 32 g tile pair (BI, BJ) and (BJ, BI), BI <= BJ,
+// t = BJ (BJ + 1) / 2 + BI, and walks its 32 x 32 pairs (bi, bj), bi <= bj
+// (g = 4 when the block leaves a maximum, else 1: one pair per block):
 // both input tiles of a pair are read before either output tile is written,
 // and the pairs are disjoint (reading the next pair while writing this one
 // touches other elements), so the kernel may run in place.  Reads and writes
@@ -137,7 +138,7 @@ __global__ __launch_bounds__(kT) void k_sym(const Tin* in, int64_t ldi, int64_t 
                                             int64_t Np, double a, const double* dshift,
                                             int dstride, Tout* out, int64_t ldo, int64_t so,
                                             Planes pl, int np, int64_t out_rows, const Tin* in2,
-                                            double a2, const int* gate, int64_t nb, double* mx,
+                                            double a2, const int* gate, int64_t nb, int g, double* mx,
                                             int64_t mstride) {
   __shared__ double ta[32][33], tb[32][33];
   if (gate && !*gate) return;  // a converged system of a batch keeps its outputs
@@ -158,16 +159,16 @@ __global__ __launch_bounds__(kT) void k_sym(const Tin* in, int64_t ldi, int64_t 
   // order of q; the next pair's inputs are loaded into registers while the
   // current pair is written
   auto valid = [&](int q) {
-    const int64_t bi = BI * 4 + (q >> 2), bj = BJ * 4 + (q & 3);
+    const int64_t bi = BI * g + q / g, bj = BJ * g + q % g;
     return bi <= bj && bj < nb;
   };
   auto next = [&](int q) {
     do ++q;
-    while (q < 16 && !valid(q));
+    while (q < g * g && !valid(q));
     return q;
   };
   auto load = [&](int q, double (&ra)[4], double (&rb)[4]) {
-    const int64_t bi = BI * 4 + (q >> 2), bj = BJ * 4 + (q & 3);
+    const int64_t bi = BI * g + q / g, bj = BJ * g + q % g;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int r = ty + 8 * u;
@@ -185,10 +186,10 @@ __global__ __launch_bounds__(kT) void k_sym(const Tin* in, int64_t ldi, int64_t 
   bool bad = false;
   double ra[4], rb[4];
   int q = valid(0) ? 0 : next(0);
-  if (q < 16) load(q, ra, rb);
-  while (q < 16) {  // the same pairs for every thread of the block
+  if (q < g * g) load(q, ra, rb);
+  while (q < g * g) {  // the same pairs for every thread of the block
     const int qn = next(q);
-    const int64_t bi = BI * 4 + (q >> 2), bj = BJ * 4 + (q & 3);
+    const int64_t bi = BI * g + q / g, bj = BJ * g + q % g;
     __syncthreads();  // the previous pair is written: ta, tb are free
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -196,7 +197,7 @@ __global__ __launch_bounds__(kT) void k_sym(const Tin* in, int64_t ldi, int64_t 
       tb[ty + 8 * u][tx] = rb[u];
     }
     __syncthreads();
-    if (qn < 16) load(qn, ra, rb);
+    if (qn < g * g) load(qn, ra, rb);
     for (int pass = 0; pass < 2; ++pass) {
       if (pass == 1 && bi == bj) break;
       const int64_t ti = pass ? bj : bi, tj = pass ? bi : bj;
@@ -1061,10 +1062,13 @@ hipError_t sym_combine(const Tin* in, int64_t ldi, int64_t si, int64_t N, int64_
   const int64_t rows = (ldo == N && ldo != Np) ? N : ldo;  // caller buffer: only N x N
   const int64_t span = rows > N ? rows : N;
   const int64_t nb = (span + 31) / 32;
-  const int64_t pairs = sym_pair_blocks(span);
-  if (mx && (mstride < pairs || gate)) return hipErrorInvalidValue;
+  // with maxima: one block per 128 x 128 pair (few maxima); else one per 32 x 32 pair
+  const int g = mx ? 4 : 1;
+  const int64_t nbg = (nb + g - 1) / g;
+  const int64_t pairs = nbg * (nbg + 1) / 2;
+  if (mx && (mstride < pairs || gate || pairs != sym_pair_blocks(span))) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_sym<Tin, Tout>), dim3((unsigned)pairs, batch), dim3(kT), 0, s, in, ldi, si, N, Np, a,
-                     dshift, dstride, out, ldo, so, pl, nplanes, rows, in2, a2, gate, nb, mx, mstride);
+                     dshift, dstride, out, ldo, so, pl, nplanes, rows, in2, a2, gate, nb, g, mx, mstride);
   return hipGetLastError();
 }
 
