@@ -394,6 +394,7 @@ struct Call {
   int jdir = -1;                 // order-1 member that is the response J to H1 = I (linear schedule)
   bool first_phase = false;      // a pass of the loose first phase before the final engine's passes
   double cscale = 0.0;           // this pass: c = beta 2^-(n+2)
+  int nsteps = 0;                // this pass: recursion steps n
   double z_dmu = -1.0;           // |mu0 - mu0 of the stored inverses| (kWarmZ; < 0: none)
 };
 
@@ -1226,13 +1227,30 @@ dmpt_status solve_order0(const Call& k, int step) {
 // degree-2 Chebyshev residual on that interval) has error
 // e0 = delta^2 / (8 + 8 delta + delta^2) -- 1/17 at delta = 1, ~ delta^2 / 8
 // for small delta -- and the iteration count is the smallest k with
-// e0^(2^k) <= 2^-60: four at delta = 1, none while ||D_s|| is below ~1e-5.
+// e0^(2^k) <= the products' resolution (ns_target; FP64: 2^-60, four at
+// delta = 1, none while ||D_s|| is below ~1e-5).
 constexpr int kNsIters = 4;
 
 struct NsStart {
   double a, b;  // Z0 = a I + b S0
   int iters;
 };
+
+bool ns_refines(const Call& k);
+
+// Residual bound ||I - T' Z|| at which the iteration of step `step` stops:
+// 2^-60, except in the 6-product int8 first phase (three base-254 digits
+// resolve 2^-24, and that phase only brackets mu0): there 2^-26 divided by
+// the growth of an error from this step to the last one (|f'| <= 2 per
+// step), so the inverse's share of the final error stays below the
+// products' resolution.  (The start's error is the same for every element
+// and does not average out in the traces: with 2^-44 in every step of the
+// 13-product passes, Tr(H1 P2) at N = 8192 moved from 6e-7 to 1.1e-6.)
+double ns_target(const Call& k, int step) {
+  if (k.eng == Engine::I8S3 && k.first_phase && !ns_refines(k) && k.nsteps > 0 && step >= 0 && step < k.nsteps)
+    return std::max(0x1p-60, std::ldexp(1.0, -26 - (k.nsteps - step)));
+  return 0x1p-60;
+}
 
 NsStart ns_start(const Call& k, int step) {
   double delta = 1.0;
@@ -1243,8 +1261,9 @@ NsStart ns_start(const Call& k, int step) {
   const double den = 8.0 + 8.0 * delta + delta * delta;
   NsStart z{(8.0 + 8.0 * delta) / den, -32.0 / den, 0};
   const double e0 = delta * delta / den;
+  const double target = ns_target(k, step);
   double e = e0;
-  while (e > 0x1p-60 && z.iters < kNsIters) {
+  while (e > target && z.iters < kNsIters) {
     e = e * e;
     ++z.iters;
   }
@@ -1294,19 +1313,20 @@ bool sym_tiles(const Call& k) {
 // commutes with H, so ||D_s - D_s,old|| <= min(2^s c |dmu|, 2 b_s) (|f'| <= 2)
 // and ||I - T' Z_old|| <= 4 ||D_s^2 - D_s,old^2|| <= 8 b_s ||D_s - D_s,old||,
 // floored at the stored inverse's own rounding (1e-10).  Returns the step
-// count to 2^-60 when it is below the count from the minimax start, else -1.
+// count to ns_target when it is below the count from the minimax start, else -1.
 int ns_warm_iters(const Call& k, int step, int scratch) {
   if (!(k.z_dmu >= 0.0) || k.d0b < 0.0 || !(k.cscale > 0.0) || step < 0 || k.c->ns_iters_env > 0) return -1;
   const double bs = std::min(0.5, std::ldexp(k.d0b, std::min(step, 1000)) * (1.0 + 1e-3));
   const double dd = std::min(2.0 * bs, std::ldexp(k.cscale * k.z_dmu, std::min(step, 1000)) * (1.0 + 1e-3));
   double e = std::max(8.0 * bs * dd, 1e-10);
   if (!(e < 1.0)) return -1;
+  const double target = ns_target(k, step);
   int it = 0;
   do {
     e = e * e;
     ++it;
-  } while (e > 0x1p-60 && it < kNsIters);
-  return e <= 0x1p-60 && it < scratch ? it : -1;
+  } while (e > target && it < kNsIters);
+  return e <= target && it < scratch ? it : -1;
 }
 
 template <class T>
@@ -1823,6 +1843,7 @@ dmpt_status recursion_pass(const Call& k0, const PassIn& in) {
   const double cscale = std::ldexp(in.beta, -(in.n + 2));
   Call k = k0;
   k.cscale = cscale;
+  k.nsteps = in.n;
   if (std::isfinite(k0.glo) && std::isfinite(k0.ghi) && in.mu)
     k.d0b = cscale * std::max(std::fabs(k0.glo - in.mu[0]), std::fabs(k0.ghi - in.mu[0]));
   STCHK(init_d<T>(k, in, cscale));

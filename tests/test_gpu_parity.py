@@ -461,7 +461,10 @@ def test_split_diagonal_tiles_match_whole_tiles(dm, prec, refine, monkeypatch):
     four blocks over quarters of the inner index plus a summing kernel (DMPT_DIAG_SPLIT=0: one
     block per diagonal tile).  The int32 sums of a quarter are exact, so only the FP64 addition of
     the four partial tiles rounds differently: N = 1000 (8 tile rows) and N = 2000 (16), orders 0-2,
-    agree far below the engine's own error, and against the oracle."""
+    agree far below the engine's own error (int8x13: 1e-9; int8x6 with refine = 2: 5e-8, the
+    13-product engine's error, since the loose first phase's different rounding moves the mu0 its
+    Newton step hands on, and the final passes end anywhere within their tolerance), and against
+    the oracle."""
     rng = np.random.default_rng(8)
     for N in (1000, 2000):
         print(f"case split diagonal {prec} N={N}", flush=True)
@@ -483,7 +486,8 @@ def test_split_diagonal_tiles_match_whole_tiles(dm, prec, refine, monkeypatch):
         d1 = max(np.abs(x - y).max() / np.abs(y).max() for x, y in zip(a1, b1))
         d2 = max(np.abs(x - y).max() / np.abs(y).max() for x, y in zip(a2, b2))
         print(f"  split vs whole: {d0:.2e} {d1:.2e} {d2:.2e}", flush=True)
-        assert d0 < 1e-9 and d1 < 1e-9 and d2 < 1e-9
+        tol = 1e-9 if refine == 0 else 5e-8
+        assert d0 < tol and d1 < tol and d2 < tol
         assert np.abs(a0 - a0.T).max() == 0.0
         if N == 1000:
             ref = oracle.canonical_response(h0, h1, None, 12.0, N / 2.0, 22, order=2)
