@@ -432,10 +432,12 @@ BOp op(const Call& k, const Group& g, int z, bool batched) {
 }
 
 // A writer is about to change members z.. of g: their int8 slices go stale.
-void q8_touch(dmpt_ctx c, const Group& g, int z) {
+void q8_touch(dmpt_ctx c, const Group& g, int z, int n = -1) {
   for (auto& r : c->q8reg)
     if (r.m == (const char*)g.m) {
-      for (int i = std::max(z, 0); i < r.count; ++i) {
+      // n members from z (n < 0: every member from z on)
+      const int e = n < 0 ? r.count : std::min(r.count, z + n);
+      for (int i = std::max(z, 0); i < e; ++i) {
         r.dirty[i] = 1;
         r.mx_n[i] = 0;
       }
@@ -476,10 +478,12 @@ double* ew_sink(const Call& k, const Group& g, int z, int64_t* stride, int64_t* 
 void* mptr(const Call& k, const Group& g, int z) {
   return (char*)g.m + (size_t)z * k.stride * k.c->esize;
 }
-void planes_of(const Call& k, const Group& g, int z, uint16_t** out) {
+// The planes of member z of g for a writer of n members from z (n < 0: the
+// writer may cover every member from z on); their int8 slices go stale.
+void planes_of(const Call& k, const Group& g, int z, uint16_t** out, int n = -1) {
   for (int p = 0; p < 3; ++p)
     out[p] = (g.pl[p] && p < k.np) ? g.pl[p] + (size_t)z * k.stride : nullptr;
-  q8_touch(k.c, g, z);
+  q8_touch(k.c, g, z, n);
 }
 
 // C(batch members z0..z0+batch) = alpha X Y^T + beta1 C1 + beta2 C2
@@ -673,13 +677,16 @@ dmpt_status run_gemm(const Call& k, const G& g) {
       const char* p = (const char*)a.C;
       if (p >= r.m && p < r.m + mb * r.count) {
         const int z0 = (int)((size_t)(p - r.m) / mb);
-        for (int i = z0; i < r.count; ++i) {
+        // C as whole members z0 .. z0 + batch - 1: exactly those go stale (an
+        // operand member beside them keeps its slices), else every member from z0
+        const bool whole = (size_t)(p - r.m) % mb == 0 && (g.batch == 1 || a.sC == r.stride) &&
+                           z0 + g.batch <= r.count;
+        for (int i = z0; i < (whole ? z0 + g.batch : r.count); ++i) {
           r.dirty[i] = 1;
           r.mx_n[i] = 0;
         }
         const int64_t tiles = gemm_cmax_entries(a);
-        if (!k.rec && !g.active && (size_t)(p - r.m) % mb == 0 && (g.batch == 1 || a.sC == r.stride) &&
-            z0 + g.batch <= r.count && tiles <= r.mx_cap) {
+        if (!k.rec && !g.active && whole && tiles <= r.mx_cap) {
           a.cmax = r.mx + (size_t)z0 * r.mx_cap;
           a.cmax_stride = r.mx_cap;
           for (int i = z0; i < z0 + g.batch; ++i) r.mx_n[i] = (int)tiles;
@@ -1380,7 +1387,7 @@ dmpt_status ns_iterate(const Call& k, int iters) {
     h.X = op(k, w->Zi, cur, false);
     h.Y = op(k, w->P, 0, false);
     h.C = exact ? mptr(k, w->Zi, nxt) : mptr(k, w->R, 0);
-    if (exact) planes_of(k, w->Zi, nxt, h.Cpl);
+    if (exact) planes_of(k, w->Zi, nxt, h.Cpl, 1);  // Zi[cur], this product's X, keeps its slices
     h.alpha = -1.0;
     h.C1 = mptr(k, w->Zi, cur); h.beta1 = 2.0;
     h.sym = true;
