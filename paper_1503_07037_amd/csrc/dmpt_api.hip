@@ -1246,17 +1246,23 @@ struct NsStart {
 bool ns_refines(const Call& k);
 
 // Residual bound ||I - T' Z|| at which the iteration of step `step` stops:
-// 2^-60, except in the 6-product int8 first phase (three base-254 digits
-// resolve 2^-24, and that phase only brackets mu0): there 2^-26 divided by
-// the growth of an error from this step to the last one (|f'| <= 2 per
-// step), so the inverse's share of the final error stays below the
-// products' resolution.  (The start's error is the same for every element
-// and does not average out in the traces: with 2^-44 in every step of the
-// 13-product passes, Tr(H1 P2) at N = 8192 moved from 6e-7 to 1.1e-6.)
+// the resolution of the products, divided by the growth of an error from
+// this step to the last one (|f'| <= 2 per step), so the inverse's share of
+// the final error stays below that resolution, and never below 2^-60 (FP64
+// and the forms with a refinement step stop there): 2^-34 for the
+// 13-product int8 engine (its dropped digit products leave ~1e-10), 2^-26
+// for the 6-product int8 first phase (three base-254 digits resolve 2^-24,
+// and that phase only brackets mu0).  The growth factor matters: the
+// start's error is the same polynomial for every element and does not
+// average out in the traces (2^-44 in every step of the 13-product passes
+// moved Tr(H1 P2) at N = 8192 from 6e-7 to 1.1e-6).
 double ns_target(const Call& k, int step) {
-  if (k.eng == Engine::I8S3 && k.first_phase && !ns_refines(k) && k.nsteps > 0 && step >= 0 && step < k.nsteps)
-    return std::max(0x1p-60, std::ldexp(1.0, -26 - (k.nsteps - step)));
-  return 0x1p-60;
+  if (ns_refines(k) || k.nsteps <= 0 || step < 0 || step >= k.nsteps) return 0x1p-60;
+  int res = 0;
+  if (k.eng == Engine::I8S4) res = 34;
+  else if (k.eng == Engine::I8S3 && k.first_phase) res = 26;
+  if (!res) return 0x1p-60;
+  return std::max(0x1p-60, std::ldexp(1.0, -res - (k.nsteps - step)));
 }
 
 NsStart ns_start(const Call& k, int step) {
