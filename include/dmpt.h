@@ -84,8 +84,9 @@ typedef enum {
   DMPT_SOLVER_NS = 1,  /* shared inverse Z of T' by Newton-Schulz from the minimax linear start on
                           the step's spectral interval [1, 1 + 4 b^2], b = min(1/2, 2^step ||D_0||)
                           with ||D_0|| from the Gershgorin interval of H0, iterated to a residual
-                          of 2^-60 (four steps once ||D|| ~ 1/2, none while ||D|| < ~1e-5; in the
-                          INT8X6 first phase of refine = 2, 2^-26 2^-(n - step)), reused for every order and
+                          of 2^-60 (four steps once ||D|| ~ 1/2, none while ||D|| < ~1e-5; with
+                          INT8X13 products 2^-34 2^-(n - step), in the INT8X6 first phase of
+                          refine = 2 2^-26 2^-(n - step), never below 2^-60), reused for every order and
                           direction (Sec. II remark): one product per right-hand side, plus one
                           refinement step with FP32, BF16 and INT8X6 products; single-system paths
                           (the batched and adjoint paths keep CG).  Under the linear schedule the
